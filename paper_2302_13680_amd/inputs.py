@@ -1,0 +1,210 @@
+"""Seeded synthetic problem instances for the linear-quadratic OCPUU.
+
+This module only builds problem data: the random diffusion coefficients at
+the cell faces, the block scalars and the right-hand side of the discrete
+optimality system (Section 2, eq. full_space_optimality_system, rescaled to
+its symmetric form).  It holds none of the multigrid method's arithmetic and
+is shared by the GPU path and by the CPU oracle.
+
+Discretization (5-point finite differences on the unit square, Dirichlet):
+  * ``n`` interior nodes per direction, ``h = 1/(n+1)``; node ``(x, k)``
+    (0-based) sits at ``((x+1) h, (k+1) h)``.
+  * ``kx[j, k, f]`` (``f = 0..n``) is kappa_j at the x-face between nodes
+    ``f-1`` and ``f`` of row ``k``, i.e. at ``((f+1/2) h, (k+1) h)``;
+    ``ky[j, g, x]`` (``g = 0..n``) is kappa_j at ``((x+1) h, (g+1/2) h)``.
+  * The stiffness matrix A_j is the h^2-scaled 5-point stencil built from
+    those faces, the mass matrix is lumped, ``M = h^2 I``.
+
+Blocks of S (eq. (2) notation): C_j = zeta_j h^2 I, G = nu h^2 I,
+D_j = E_j = -h^2 I, with Monte Carlo weights zeta_j = 1/N.  Right-hand side:
+f_Y,j = zeta_j h^2 y_d, f_U = 0, f_P,j = h^2 f.  This is the paper's system
+with B = M after the adjoint is rescaled by zeta (the symmetrization remarked
+on at the end of Section 2).
+
+Coefficient model (Section 3.2, eq. log_normal, replaced by an analytic
+Karhunen-Loeve-type expansion on the square):
+  log kappa_j(x, y) = sum_{m=1..M} a_m xi_{j,m} sin(m pi x) sin(m pi y),
+with xi drawn from ``numpy.random.default_rng(seed).standard_normal((N, M))``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    n: int
+    N: int
+    nu: float
+    kx: np.ndarray          # (N, n, n+1) float64
+    ky: np.ndarray          # (N, n+1, n) float64
+    c: np.ndarray           # (N,) C_j diagonal value
+    d: np.ndarray           # (N,) D_j diagonal value
+    e: np.ndarray           # (N,) E_j diagonal value
+    g: float                # G diagonal value
+    fY: np.ndarray          # (N, n, n)
+    fU: np.ndarray          # (n, n)
+    fP: np.ndarray          # (N, n, n)
+    xi: np.ndarray = field(default=None, repr=False)
+    yd: np.ndarray = field(default=None, repr=False)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def h(self) -> float:
+        return 1.0 / (self.n + 1)
+
+    @property
+    def dof(self) -> int:
+        return (2 * self.N + 1) * self.n * self.n
+
+    # --- layouts -----------------------------------------------------------
+    # "paper" layout: x = [y_1..y_N | u | p_1..p_N], every block [n][n] (eq. (2)).
+    # "node" layout (GPU): Y block [n][n][N], U block [n][n], P block [n][n][N]
+    # (samples innermost), faces kx [n][n+1][N], ky [n+1][n][N].
+    def rhs_paper(self) -> np.ndarray:
+        return np.concatenate([self.fY.ravel(), self.fU.ravel(), self.fP.ravel()])
+
+    def rhs_node(self) -> np.ndarray:
+        return paper_to_node(self.rhs_paper(), self.n, self.N)
+
+    def faces_node(self):
+        return (np.ascontiguousarray(self.kx.transpose(1, 2, 0)),
+                np.ascontiguousarray(self.ky.transpose(1, 2, 0)))
+
+
+def paper_to_node(v: np.ndarray, n: int, N: int) -> np.ndarray:
+    """Permute a vector from eq. (2) order to the node layout (samples innermost)."""
+    nn = n * n
+    v = np.asarray(v)
+    Y = v[:N * nn].reshape(N, n, n).transpose(1, 2, 0)
+    U = v[N * nn:(N + 1) * nn]
+    P = v[(N + 1) * nn:].reshape(N, n, n).transpose(1, 2, 0)
+    return np.concatenate([Y.ravel(), U.ravel(), P.ravel()])
+
+
+def node_to_paper(v: np.ndarray, n: int, N: int) -> np.ndarray:
+    nn = n * n
+    v = np.asarray(v)
+    Y = v[:N * nn].reshape(n, n, N).transpose(2, 0, 1)
+    U = v[N * nn:(N + 1) * nn]
+    P = v[(N + 1) * nn:].reshape(n, n, N).transpose(2, 0, 1)
+    return np.concatenate([Y.ravel(), U.ravel(), P.ravel()])
+
+
+def kl_amplitudes(M: int, sigma: float, decay: bool) -> np.ndarray:
+    m = np.arange(1, M + 1, dtype=np.float64)
+    return sigma / m if decay else np.full(M, sigma)
+
+
+def log_kappa(xi: np.ndarray, amps: np.ndarray, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """log kappa_j at points (X, Y) for every sample j; returns (N,) + X.shape."""
+    M = amps.shape[0]
+    out = np.zeros((xi.shape[0],) + X.shape)
+    for m in range(1, M + 1):
+        mode = np.sin(m * math.pi * X) * np.sin(m * math.pi * Y)
+        out += (amps[m - 1] * xi[:, m - 1])[:, None, None] * mode[None]
+    return out
+
+
+def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float = 0.5,
+                 decay: bool = False, seed: int = 0, yd: str | np.ndarray = "sin",
+                 f: float = 1.0, xi: np.ndarray | None = None,
+                 kappa_const: float | None = None) -> Problem:
+    """Build one seeded instance.
+
+    ``decay=False`` gives amplitudes a_m = sigma (the 31x31, N=8 case, four modes
+    of amplitude 0.5); ``decay=True`` gives a_m = sigma/m.  ``kappa_const`` replaces
+    the random field by a constant (used by closed-form checks).
+    """
+    h = 1.0 / (n + 1)
+    if xi is None:
+        xi = np.random.default_rng(seed).standard_normal((N, M))
+    xi = np.asarray(xi, dtype=np.float64)
+    amps = kl_amplitudes(xi.shape[1], sigma, decay)
+    nodes = (np.arange(n) + 1.0) * h
+    faces = (np.arange(n + 1) + 0.5) * h
+    if kappa_const is not None:
+        kx = np.full((N, n, n + 1), float(kappa_const))
+        ky = np.full((N, n + 1, n), float(kappa_const))
+    else:
+        FX, KY_ = np.meshgrid(faces, nodes)          # kx: rows k (y = nodes), faces f (x = faces)
+        kx = np.exp(log_kappa(xi, amps, FX, KY_))
+        XN, GF = np.meshgrid(nodes, faces)           # ky: rows g (y = faces), columns x (x = nodes)
+        ky = np.exp(log_kappa(xi, amps, XN, GF))
+    XX, YY = np.meshgrid(nodes, nodes)
+    if isinstance(yd, str):
+        if yd == "sin":
+            ydv = np.sin(math.pi * XX) * np.sin(math.pi * YY)
+        elif yd == "zero":
+            ydv = np.zeros((n, n))
+        else:
+            raise ValueError(yd)
+    else:
+        ydv = np.asarray(yd, dtype=np.float64).reshape(n, n)
+    zeta = np.full(N, 1.0 / N)
+    c = zeta * h * h
+    d = np.full(N, -h * h)
+    e = np.full(N, -h * h)
+    g = nu * h * h
+    fY = (zeta * h * h)[:, None, None] * ydv[None]
+    fU = np.zeros((n, n))
+    fP = np.full((N, n, n), h * h * f)
+    return Problem(n=n, N=N, nu=nu, kx=np.ascontiguousarray(kx), ky=np.ascontiguousarray(ky),
+                   c=c, d=d, e=e, g=g, fY=fY, fU=fU, fP=fP, xi=xi, yd=ydv,
+                   meta=dict(M=xi.shape[1], sigma=sigma, decay=decay, seed=seed, f=f))
+
+
+def random_yd(n: int, rng: np.random.Generator, terms: int = 3, kmax: int = 4) -> np.ndarray:
+    """Target state drawn as a random sum of ``terms`` sine products
+    sum_t c_t sin(k_t pi x) sin(l_t pi y), c_t ~ U[-1, 1], k_t, l_t ~ U{1..kmax}."""
+    h = 1.0 / (n + 1)
+    nodes = (np.arange(n) + 1.0) * h
+    XX, YY = np.meshgrid(nodes, nodes)
+    out = np.zeros((n, n))
+    for _ in range(terms):
+        ct = rng.uniform(-1.0, 1.0)
+        kk = int(rng.integers(1, kmax + 1))
+        ll = int(rng.integers(1, kmax + 1))
+        out += ct * np.sin(kk * math.pi * XX) * np.sin(ll * math.pi * YY)
+    return out
+
+
+# Named workloads of the evaluation (sizes from the experiment plan).
+def small_fp64(seed: int = 0) -> Problem:
+    """31x31 interior grid, N=8, four modes of amplitude 0.5, nu=1e-4."""
+    return make_problem(31, 8, 1e-4, M=4, sigma=0.5, decay=False, seed=seed)
+
+
+def medium_fp64(seed: int = 1) -> Problem:
+    """255x255 interior grid, N=64, six modes of amplitude 0.5/m, nu=1e-4."""
+    return make_problem(255, 64, 1e-4, M=6, sigma=0.5, decay=True, seed=seed)
+
+
+def large_mixed(seed: int = 2) -> Problem:
+    """511x511 interior grid, N=256, six modes of amplitude 1.0/m, nu=1e-4."""
+    return make_problem(511, 256, 1e-4, M=6, sigma=1.0, decay=True, seed=seed)
+
+
+def batch_instances(count: int = 64, draw_seed: int = 999, first_seed: int = 1000):
+    """Uneven batch: n ~ U{63,127,255}, N ~ U{16,32,64,128}, log10 nu ~ U[-6,-2]."""
+    rng = np.random.default_rng(draw_seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice([63, 127, 255]))
+        N = int(rng.choice([16, 32, 64, 128]))
+        nu = float(10.0 ** rng.uniform(-6.0, -2.0))
+        out.append(dict(n=n, N=N, nu=nu, seed=first_seed + i))
+    return out
+
+
+def learned_instance(seed: int, n: int = 127, N: int = 128) -> Problem:
+    """Warm-start workload: nu log-uniform in [1e-5, 1e-3], y_d a random sum of
+    three sine products, f = 1, six modes of amplitude 0.5/m."""
+    rng = np.random.default_rng(seed)
+    nu = float(10.0 ** rng.uniform(-5.0, -3.0))
+    yd = random_yd(n, rng)
+    xi = rng.standard_normal((N, 6))
+    return make_problem(n, N, nu, M=6, sigma=0.5, decay=True, seed=seed, yd=yd, xi=xi)
