@@ -1,0 +1,181 @@
+"""Benchmark of the collective multigrid solver on one MI355X.
+
+One step = one full solve of the 255x255, N = 64 linear-quadratic OCPUU
+(FP64, six KL modes of amplitude 0.5/m, nu = 1e-4) from a zero initial guess
+to a relative residual of 1e-8 with GMRES(30) preconditioned by one V(2,2)
+cycle, inputs resident in HBM.  Prints one JSON line.
+
+value  = whole-job DoF-sweeps/s: (2N+1) n^2 unknowns x fine-level smoothing
+         sweeps performed in the solve (4 per V-cycle) / solve wall time.
+roofline: the dominant kernel (the collective Gauss-Seidel half-sweep on the
+         finest level) timed with HIP events on the library's stream, its
+         algorithmic bytes per launch against the 8 TB/s HBM peak.
+cpu_baseline: the CPU oracle solving the same instance with the same method
+         on the host's cores (rank 0 only).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("time to rel. residual 1e-8 & DoF-sweeps/s; % HBM roofline; vs plain FP64 V-cycle")
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.h", "smg.hip"):
+        with open(os.path.join(ROOT, "paper_2302_13680_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def halfsweep_bytes(n: int, N: int, word: int) -> float:
+    """Algorithmic bytes of one half-sweep launch (red colour): the 4 faces of
+    every updated node, y and p of every node of the other colour, the three
+    right-hand-side rows of the updated nodes, and y, p, u written back."""
+    nact = ((n - 1) // 2) * n + (n + 1) // 2
+    nin = n * n - nact
+    words = N * (4 * nact + 2 * nin + 2 * nact + 2 * nact) + 2 * nact
+    return float(words * word)
+
+
+def load_traffic(kind: str):
+    path = os.path.join(ROOT, "profiles", f"traffic_{kind}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != kernel_source_hash():
+        return None     # the kernel changed since the counters were taken
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sweeps", type=int, default=200, help="half-sweep launches timed for the roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
+                                   "note, not an implemented path", "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2302_13680_amd import binding, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = inputs.medium_fp64()
+    n, N = prob.n, prob.N
+    dof = prob.dof
+    ctx, f = binding.context_from_problem(prob, device=dev, gmres_restart=30)
+    x = torch.zeros(dof, dtype=torch.float64, device=dev)
+    stream = ctx.stream
+
+    def solve(method, rtol):
+        x.zero_()
+        rc, st = ctx.solve(x, f, method, rtol=rtol, maxit=200, history=0)
+        if rc != binding.SMG_OK:
+            raise RuntimeError(f"solve did not converge: {st}")
+        return st
+
+    # ---------------- headline: GMRES(30) + V(2,2) to 1e-8, K timed steps
+    for _ in range(args.warmup):
+        solve(binding.SMG_GMRES, args.rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles = 0
+    for _ in range(args.steps):
+        st = solve(binding.SMG_GMRES, args.rtol)
+        cycles += st["inner_iterations"]
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    ms_per_step = 1e3 * t_total / args.steps
+    gmres_its = st["iterations"]
+    sweeps_per_cycle = 4
+    value = dof * sweeps_per_cycle * cycles / t_total
+
+    # ---------------- plain FP64 stationary V-cycle (the comparison baseline)
+    solve(binding.SMG_VCYCLE, args.rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stv = solve(binding.SMG_VCYCLE, args.rtol)
+    torch.cuda.synchronize()
+    t_vcycle_ms = 1e3 * (time.perf_counter() - t0)
+    # tolerance of the workload definition
+    t0 = time.perf_counter()
+    st10 = solve(binding.SMG_GMRES, 1e-10)
+    torch.cuda.synchronize()
+    t_gmres10_ms = 1e3 * (time.perf_counter() - t0)
+
+    # ---------------- roofline of the dominant kernel: finest-level half-sweep
+    xs = torch.zeros(dof, dtype=torch.float64, device=dev)
+    for _ in range(10):
+        ctx.smooth(0, 0, xs, f)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for i in range(args.sweeps):
+        ctx.smooth(0, i & 1, xs, f)
+    ev1.record(stream)
+    ev1.synchronize()
+    t_launch_us = 1e3 * ev0.elapsed_time(ev1) / args.sweeps
+    bytes_launch = halfsweep_bytes(n, N, 8)
+    achieved = bytes_launch / (t_launch_us * 1e-6) / 1e9
+    traffic = load_traffic("halfsweep_f64_medium")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_halfsweep<double,64,1> (finest level)", "avg_launch_us": round(t_launch_us, 2),
+                "algorithmic_bytes_per_launch": bytes_launch}
+
+    # ---------------- CPU oracle on the host cores (same instance, same method)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        o = orc.Oracle(prob)
+        fp = prob.rhs_paper()
+        t0 = time.perf_counter()
+        _, its_o, _ = o.gmres(fp, m=30, tol=args.rtol, maxit=200)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": round(dof * sweeps_per_cycle * its_o / t_cpu, 1), "unit": "DoF-sweeps/s",
+               "cores": orc.num_threads(), "kind": "oracle",
+               "sample": f"one full GMRES(30)+V(2,2) solve to {args.rtol:g} of the same instance "
+                         f"({its_o} iterations, {t_cpu:.2f} s)",
+               "time_to_tol_s": round(t_cpu, 3)}
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "DoF-sweeps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "LQ-OCPUU 255x255 interior grid, N=64 samples, 6 KL modes a_m=0.5/m, "
+                               "nu=1e-4, FP64, GMRES(30)+V(2,2) to rel. residual 1e-8",
+                   "n": n, "N": N, "dof": dof, "levels": ctx.levels_n},
+        "time_to_1e-8_ms": round(ms_per_step, 3),
+        "gmres_iterations": gmres_its,
+        "fp64_vcycle_time_to_1e-8_ms": round(t_vcycle_ms, 3),
+        "fp64_vcycle_cycles": stv["iterations"],
+        "gmres_time_to_1e-10_ms": round(t_gmres10_ms, 3),
+        "gmres_iterations_1e-10": st10["iterations"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

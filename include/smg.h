@@ -1,0 +1,190 @@
+/* smg.h -- C ABI of the MI355X collective multigrid library (libsmg.so).
+ *
+ * Solves the block saddle-point system S x = f of a linear-quadratic optimal
+ * control problem under uncertainty (Ciaramella, Nobile, Vanzan, arXiv
+ * 2302.13680, eq. (2) and eq. full_space_optimality_system):
+ *
+ *     [ C_1            A_1^T          ] [ y_1 ]   [ f_Y,1 ]
+ *     [     ...             ...       ] [ ... ]   [  ...  ]
+ *     [         C_N             A_N^T ] [ y_N ]   [ f_Y,N ]
+ *     [             G   D_1 ...  D_N  ] [  u  ] = [  f_U  ]
+ *     [ A_1         E_1               ] [ p_1 ]   [ f_P,1 ]
+ *     [     ...     ...               ] [ ... ]   [  ...  ]
+ *     [         A_N E_N               ] [ p_N ]   [ f_P,N ]
+ *
+ * on an n x n interior grid of the unit square (homogeneous Dirichlet), with
+ *   - A_j the symmetric 5-point stencil built from face coefficients
+ *     (finite differences scaled by h^2; A_j^T = A_j): for node (x, k)
+ *       (A_j v)(x,k) = (kW+kE+kS+kN) v(x,k) - kW v(x-1,k) - kE v(x+1,k)
+ *                                           - kS v(x,k-1) - kN v(x,k+1),
+ *     kW = kx(k, x), kE = kx(k, x+1), kS = ky(k, x), kN = ky(k+1, x);
+ *   - C_j = c_j I, D_j = d_j I, E_j = e_j I, G = g I (diagonal blocks with one
+ *     value per sample, e.g. c_j = zeta_j h^2, d_j = e_j = -h^2, g = nu h^2).
+ *
+ * The solver is the collective multigrid V-cycle (Alg. 1) with the
+ * red-black collective Gauss-Seidel smoother whose node solve is
+ * eq. solution_reduced_system, used stationary, as the right preconditioner
+ * of GMRES(m), or in FP32 inside FP64 iterative refinement.
+ *
+ * LAYOUTS (all device memory; samples innermost):
+ *   vector x or f, length (2N+1) n^2 elements:
+ *       [ Y block: [n][n][N] | U block: [n][n] | P block: [n][n][N] ]
+ *       i.e. Y(j, x, k) at  (k*n + x)*N + j,  U(x, k) at N*n*n + k*n + x,
+ *            P(j, x, k) at  (N+1)*n*n + (k*n + x)*N + j.
+ *   kx: [n][n+1][N]  kx(k, f, j) = coefficient of sample j on the x-face
+ *       between columns f-1 and f of row k (f = 0 and f = n touch the boundary)
+ *   ky: [n+1][n][N]  ky(g, x, j) = coefficient on the y-face between rows
+ *       g-1 and g of column x.
+ *   This is eq. (2)'s ordering with every block transposed to node-major,
+ *   sample-minor order, so that one wavefront holds the samples of a node.
+ *
+ * OWNERSHIP: all device buffers (blocks, x, f, workspace) belong to the
+ * caller and must outlive the context; the library never frees them.  The
+ * finest-level kx/ky are referenced, not copied.  The context struct itself
+ * is allocated by smg_setup and freed by smg_destroy.  Work is enqueued on the
+ * caller's HIP stream; calls that report iteration counts or norms
+ * synchronize that stream.  A context is not thread-safe: one context per
+ * stream.
+ *
+ * ERRORS: every int-returning call returns SMG_OK (0), SMG_NOT_CONVERGED (1,
+ * stats are filled) or a negative code; smg_strerror maps codes to text and
+ * smg_last_error(ctx) gives detail.  Arguments are validated on the host
+ * before any launch.
+ */
+#ifndef SMG_H
+#define SMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMG_OK 0
+#define SMG_NOT_CONVERGED 1
+#define SMG_EINVAL (-1)       /* bad size, pointer or option */
+#define SMG_ESINGULAR (-2)    /* non-positive diagonal or node denominator, singular coarsest block */
+#define SMG_EHIP (-3)         /* a HIP runtime call failed */
+#define SMG_ENONFINITE (-4)   /* a residual norm became NaN or Inf */
+#define SMG_EWORKSPACE (-5)   /* workspace missing or too small */
+
+/* arithmetic of the V-cycle */
+#define SMG_F64 0             /* everything in FP64 */
+#define SMG_F32 1             /* smoother, residual and transfers in FP32, coarsest solve,
+                                 outer residual and Krylov updates in FP64 */
+
+/* solver choice for smg_solve */
+#define SMG_VCYCLE 0          /* stationary V-cycles (FP32 mode: FP64 refinement, one FP32 cycle per step) */
+#define SMG_GMRES 1           /* right-preconditioned GMRES(m) (FP32 mode: FP64 refinement
+                                 around flexible GMRES(m) with the FP32 cycle) */
+
+typedef struct smg_ctx smg_ctx;
+
+typedef struct {
+  int n;              /* interior nodes per direction: (coarsest_n+1) 2^k - 1 */
+  int nsamples;       /* N >= 1 (at most 512) */
+  int coarsest_n;     /* odd, 1..7; grid of the direct solve (0 selects 7) */
+  int pre, post;      /* smoothing sweeps n1, n2 per level (red + black half-sweeps each) */
+  double theta;       /* relaxation of the node update (1 = Gauss-Seidel; 0 selects 1) */
+  int precision;      /* SMG_F64 or SMG_F32 */
+  int gmres_restart;  /* basis size m reserved for GMRES (0 = no Krylov storage) */
+} smg_desc;
+
+typedef struct {
+  const double *kx;   /* device, [n][n+1][N] */
+  const double *ky;   /* device, [n+1][n][N] */
+  const double *c;    /* host, [N]: C_j = c_j I (> 0) */
+  const double *d;    /* host, [N]: D_j = d_j I */
+  const double *e;    /* host, [N]: E_j = e_j I */
+  double g;           /* G = g I (> 0) */
+} smg_blocks;
+
+typedef struct {
+  int iterations;       /* V-cycles (stationary), GMRES iterations, or refinement steps */
+  int inner_iterations; /* preconditioner applications (V-cycles) in total */
+  int restarts;         /* GMRES restarts */
+  double relres;        /* final ||f - S x||_2 / ||f||_2 in FP64 */
+  double relres_y, relres_u, relres_p; /* per block row, each relative to ||f||_2 */
+  double time_ms;       /* wall time of the call, host clock */
+  double *history;      /* optional caller buffer: relative residual per iteration */
+  int history_cap;      /* its length (0 = none) */
+  int history_len;      /* entries written */
+} smg_stats;
+
+/* Bytes of device workspace smg_setup needs for this descriptor.  Pure host
+ * computation; returns 0 for an invalid descriptor. */
+size_t smg_workspace_bytes(const smg_desc *desc);
+
+/* Build the level hierarchy (Section 3: nested grids n -> (n-1)/2 with coarse
+ * operators by rediscretization: face coefficients averaged pairwise, the
+ * diagonal blocks scaled by 4 per level), check a > 0 and the node
+ * denominators of eq. solution_reduced_system (c, d e with the sign that makes
+ * G + sum_j d_j c_j e_j / a_j^2 > 0), and factor the coarsest level (its A_j
+ * and the control Schur complement inverted in FP64).  workspace: device
+ * buffer of at least smg_workspace_bytes(desc) bytes, 256-byte aligned.
+ * stream: hipStream_t (NULL = default stream).  On success *out is a new
+ * context. */
+int smg_setup(const smg_desc *desc, const smg_blocks *blocks, void *workspace,
+              size_t workspace_bytes, void *stream, smg_ctx **out);
+
+void smg_destroy(smg_ctx *ctx);
+
+const char *smg_strerror(int code);
+const char *smg_last_error(const smg_ctx *ctx);
+
+int smg_num_levels(const smg_ctx *ctx);
+int smg_level_n(const smg_ctx *ctx, int level);
+
+/* Sx = S x on the finest level, FP64 (eq. (2)).  x and Sx: device vectors. */
+int smg_apply(smg_ctx *ctx, const double *x, double *Sx);
+
+/* r = f - S x on the finest level, FP64; if norms != NULL it receives (host)
+ * { ||r||, ||r_Y||, ||r_U||, ||r_P|| } (2-norms). */
+int smg_residual(smg_ctx *ctx, const double *x, const double *f, double *r, double *norms);
+
+/* One half-sweep of the collective Gauss-Seidel smoother on level `level`
+ * (eq. collective_smoothing, node solve eq. solution_reduced_system): every
+ * node with (x + k) % 2 == colour gets (1-theta) x_i + theta S~_i^{-1} b_i.
+ * x, f: FP64 device vectors of that level's size. */
+int smg_smooth(smg_ctx *ctx, int level, int colour, double *x, const double *f);
+
+/* coarse = R fine (R = P^T, full weighting with weights 1, 1/2, 1/4), fine of
+ * level `level`, coarse of level + 1, all 2N+1 fields.  FP64 device vectors. */
+int smg_restrict(smg_ctx *ctx, int level, const double *fine, double *coarse);
+
+/* fine += P coarse (bilinear interpolation; Alg. 1 coarse correction). */
+int smg_prolong_add(smg_ctx *ctx, int level, const double *coarse, double *fine);
+
+/* X = S^{-1} F on the coarsest level (Alg. 1 direct solver), FP64. */
+int smg_coarse_solve(smg_ctx *ctx, const double *F, double *X);
+
+/* Copy the face coefficients the hierarchy holds for `level` into device
+ * buffers kx [n_l][n_l+1][N] and ky [n_l+1][n_l][N] (FP64). */
+int smg_level_faces(smg_ctx *ctx, int level, double *kx, double *ky);
+
+/* ncycles V-cycles (Alg. 1) in place on the finest level: x <- Vcycle(x, f).
+ * In SMG_F32 mode x and f are rounded to FP32 on entry and x is widened on
+ * exit. */
+int smg_vcycle(smg_ctx *ctx, double *x, const double *f, int ncycles);
+
+/* GMRES(restart) preconditioned on the right by one V-cycle from a zero guess,
+ * on the initial guess in x (Section 3.2 experiments; the monitored residual
+ * is the unpreconditioned one).  Stops when ||f - S x|| <= rtol ||f|| or after
+ * maxit iterations.  restart <= desc.gmres_restart.  In SMG_F32 mode the
+ * basis stays FP64 and the preconditioner is the FP32 cycle (flexible GMRES). */
+int smg_gmres_precond(smg_ctx *ctx, double *x, const double *f, int restart, double rtol,
+                      int maxit, smg_stats *stats);
+
+/* Solve S x = f to ||f - S x||_2 <= rtol ||f||_2 starting from the x given.
+ * method SMG_VCYCLE or SMG_GMRES (see above); in SMG_F32 mode both run as FP64
+ * iterative refinement around the FP32 cycle (maxit bounds the refinement
+ * steps; each GMRES-based step stops at inner_rtol = 1e-5 relative to the
+ * current residual). */
+int smg_solve(smg_ctx *ctx, double *x, const double *f, int method, double rtol, int maxit,
+              smg_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMG_H */

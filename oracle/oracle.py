@@ -69,6 +69,7 @@ def _load():
     L.or_solve_ir.restype = C.c_int
     L.or_solve_ir.argtypes = [vp, _dp, _dp, C.c_double, C.c_double, C.c_int, C.c_int, _dp,
                               C.POINTER(C.c_int)]
+    L.or_num_threads.restype = C.c_int
     L.or_norm.restype = C.c_double
     L.or_norm.argtypes = [_dp, C.c_size_t]
     _lib = L
@@ -110,6 +111,10 @@ def coarsen_faces(nf: int, N: int, kx, ky):
     kyc = np.zeros((N, nc + 1, nc))
     _load().or_coarsen_faces(nf, N, _f64(kx), _f64(ky), kxc, kyc)
     return kxc, kyc
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
 
 
 def norm(v) -> float:

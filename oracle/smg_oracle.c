@@ -23,6 +23,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define REAL double
 #define SFX(name) name##_f64
@@ -368,6 +371,15 @@ void or_vcycle32(or_ctx *C, double *x, const double *f, int ncycles) {
   for (int i = 0; i < ncycles; ++i) vcycle_f32(C, 0, x32, f32);
   for (size_t i = 0; i < len; ++i) x[i] = (double)x32[i];
   free(x32); free(f32);
+}
+
+/* threads the node loops run on (the CPU baseline reports it) */
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 /* 2-norm with a fixed summation order. */

@@ -1,0 +1,233 @@
+"""Thin ctypes binding of libsmg.so (the C ABI of include/smg.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Device memory and the stream come from PyTorch (ROCm build); vectors and
+faces are torch tensors in the library's node layout (samples innermost).
+The binding refuses to run without the compiled library: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmg.so")
+
+SMG_OK, SMG_NOT_CONVERGED = 0, 1
+SMG_F64, SMG_F32 = 0, 1
+SMG_VCYCLE, SMG_GMRES = 0, 1
+
+EXPORTED = [
+    "smg_workspace_bytes", "smg_setup", "smg_destroy", "smg_strerror", "smg_last_error",
+    "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_smooth", "smg_restrict",
+    "smg_prolong_add", "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond",
+    "smg_solve",
+]
+
+
+class Desc(C.Structure):
+    _fields_ = [("n", C.c_int), ("nsamples", C.c_int), ("coarsest_n", C.c_int), ("pre", C.c_int),
+                ("post", C.c_int), ("theta", C.c_double), ("precision", C.c_int),
+                ("gmres_restart", C.c_int)]
+
+
+class Blocks(C.Structure):
+    _fields_ = [("kx", C.c_void_p), ("ky", C.c_void_p), ("c", C.POINTER(C.c_double)),
+                ("d", C.POINTER(C.c_double)), ("e", C.POINTER(C.c_double)), ("g", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("inner_iterations", C.c_int), ("restarts", C.c_int),
+                ("relres", C.c_double), ("relres_y", C.c_double), ("relres_u", C.c_double),
+                ("relres_p", C.c_double), ("time_ms", C.c_double),
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int),
+                ("history_len", C.c_int)]
+
+
+class SmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"smg error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsmg.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2302_13680_amd.build.build()")
+    L = C.CDLL(path)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    L.smg_workspace_bytes.restype = C.c_size_t
+    L.smg_workspace_bytes.argtypes = [C.POINTER(Desc)]
+    L.smg_setup.restype = i
+    L.smg_setup.argtypes = [C.POINTER(Desc), C.POINTER(Blocks), vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.smg_destroy.argtypes = [vp]
+    L.smg_strerror.restype = C.c_char_p
+    L.smg_strerror.argtypes = [i]
+    L.smg_last_error.restype = C.c_char_p
+    L.smg_last_error.argtypes = [vp]
+    L.smg_num_levels.argtypes = [vp]
+    L.smg_level_n.argtypes = [vp, i]
+    L.smg_apply.argtypes = [vp, vp, vp]
+    L.smg_residual.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
+    L.smg_smooth.argtypes = [vp, i, i, vp, vp]
+    L.smg_restrict.argtypes = [vp, i, vp, vp]
+    L.smg_prolong_add.argtypes = [vp, i, vp, vp]
+    L.smg_coarse_solve.argtypes = [vp, vp, vp]
+    L.smg_level_faces.argtypes = [vp, i, vp, vp]
+    L.smg_vcycle.argtypes = [vp, vp, vp, i]
+    L.smg_gmres_precond.argtypes = [vp, vp, vp, i, d, i, C.POINTER(Stats)]
+    L.smg_solve.argtypes = [vp, vp, vp, i, d, i, C.POINTER(Stats)]
+    for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_restrict", "smg_prolong_add",
+                 "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond", "smg_solve",
+                 "smg_num_levels", "smg_level_n"]:
+        getattr(L, name).restype = i
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return C.c_void_p(t.data_ptr())
+
+
+def workspace_bytes(n, N, coarsest_n=7, pre=2, post=2, theta=1.0, precision=SMG_F64, gmres_restart=30):
+    L = load()
+    desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart)
+    return int(L.smg_workspace_bytes(C.byref(desc)))
+
+
+class Context:
+    """One smg_ctx: hierarchy + coarsest factorization for one instance.
+
+    kx, ky: float64 device tensors in the node layout ([n][n+1][N], [n+1][n][N]);
+    c, d, e: per-sample diagonal values (host sequences), g: scalar.
+    """
+
+    def __init__(self, n, N, kx, ky, c, d, e, g, *, coarsest_n=7, pre=2, post=2, theta=1.0,
+                 precision=SMG_F64, gmres_restart=30, stream=None):
+        import torch
+        L = load()
+        self.L = L
+        self.n, self.N = n, N
+        self.precision = precision
+        self.device = kx.device
+        self.desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart)
+        nbytes = int(L.smg_workspace_bytes(C.byref(self.desc)))
+        if nbytes == 0:
+            raise SmgError(-1, "invalid descriptor")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.kx, self.ky = kx, ky     # referenced by the library: keep alive
+        self._c = np.ascontiguousarray(c, dtype=np.float64)
+        self._d = np.ascontiguousarray(d, dtype=np.float64)
+        self._e = np.ascontiguousarray(e, dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        blocks = Blocks(_ptr(kx), _ptr(ky), self._c.ctypes.data_as(dp), self._d.ctypes.data_as(dp),
+                        self._e.ctypes.data_as(dp), float(g))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        rc = L.smg_setup(C.byref(self.desc), C.byref(blocks), _ptr(self.workspace), nbytes,
+                         C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if rc != SMG_OK:
+            raise SmgError(rc, L.smg_strerror(rc).decode())
+        self.ctx = ctx
+        self.nlev = L.smg_num_levels(ctx)
+        self.levels_n = [L.smg_level_n(ctx, l) for l in range(self.nlev)]
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.smg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_nc=False):
+        if rc == SMG_OK or (allow_nc and rc == SMG_NOT_CONVERGED):
+            return rc
+        detail = self.L.smg_last_error(self.ctx).decode() if self.ctx else ""
+        raise SmgError(rc, self.L.smg_strerror(rc).decode() + (": " + detail if detail else ""))
+
+    def vlen(self, level=0):
+        n = self.levels_n[level]
+        return (2 * self.N + 1) * n * n
+
+    # --- steps ------------------------------------------------------------
+    def apply(self, x, out):
+        return self._check(self.L.smg_apply(self.ctx, _ptr(x), _ptr(out)))
+
+    def residual(self, x, f, r, norms=False):
+        if norms:
+            buf = (C.c_double * 4)()
+            self._check(self.L.smg_residual(self.ctx, _ptr(x), _ptr(f), _ptr(r), buf))
+            return list(buf)
+        self._check(self.L.smg_residual(self.ctx, _ptr(x), _ptr(f), _ptr(r), None))
+        return None
+
+    def smooth(self, level, colour, x, f):
+        return self._check(self.L.smg_smooth(self.ctx, level, colour, _ptr(x), _ptr(f)))
+
+    def restrict(self, level, fine, coarse):
+        return self._check(self.L.smg_restrict(self.ctx, level, _ptr(fine), _ptr(coarse)))
+
+    def prolong_add(self, level, coarse, fine):
+        return self._check(self.L.smg_prolong_add(self.ctx, level, _ptr(coarse), _ptr(fine)))
+
+    def coarse_solve(self, F, X):
+        return self._check(self.L.smg_coarse_solve(self.ctx, _ptr(F), _ptr(X)))
+
+    def level_faces(self, level, kx, ky):
+        return self._check(self.L.smg_level_faces(self.ctx, level, _ptr(kx), _ptr(ky)))
+
+    def vcycle(self, x, f, ncycles=1):
+        return self._check(self.L.smg_vcycle(self.ctx, _ptr(x), _ptr(f), ncycles))
+
+    def _stats(self, history):
+        st = Stats()
+        if history:
+            self._hist = (C.c_double * history)()
+            st.history = self._hist
+            st.history_cap = history
+        return st
+
+    def gmres(self, x, f, restart=30, rtol=1e-10, maxit=200, history=256):
+        st = self._stats(history)
+        rc = self._check(self.L.smg_gmres_precond(self.ctx, _ptr(x), _ptr(f), restart, rtol, maxit,
+                                                  C.byref(st)), allow_nc=True)
+        return rc, _stats_dict(st)
+
+    def solve(self, x, f, method=SMG_VCYCLE, rtol=1e-10, maxit=200, history=256):
+        st = self._stats(history)
+        rc = self._check(self.L.smg_solve(self.ctx, _ptr(x), _ptr(f), method, rtol, maxit, C.byref(st)),
+                         allow_nc=True)
+        return rc, _stats_dict(st)
+
+
+def _stats_dict(st):
+    hist = [st.history[i] for i in range(st.history_len)] if st.history_len else []
+    return dict(iterations=st.iterations, inner_iterations=st.inner_iterations, restarts=st.restarts,
+                relres=st.relres, relres_y=st.relres_y, relres_u=st.relres_u, relres_p=st.relres_p,
+                time_ms=st.time_ms, history=hist)
+
+
+def context_from_problem(prob, device="cuda", **kw):
+    """Upload a problem's faces (node layout) and build a Context; returns (ctx, f)."""
+    import torch
+    kxn, kyn = prob.faces_node()
+    kx = torch.from_numpy(kxn).to(device)
+    ky = torch.from_numpy(kyn).to(device)
+    ctx = Context(prob.n, prob.N, kx, ky, prob.c, prob.d, prob.e, prob.g, **kw)
+    f = torch.from_numpy(prob.rhs_node()).to(device)
+    return ctx, f

@@ -1,0 +1,773 @@
+// smg.hip -- runtime and C ABI of the collective multigrid library (see include/smg.h).
+//
+// Host side of the method: the level hierarchy (nested grids n -> (n-1)/2,
+// rediscretized coarse operators), the V-cycle of Alg. 1 as a sequence of
+// kernel launches on the caller's stream, the coarsest direct solve, the
+// stationary and GMRES drivers and FP64 iterative refinement around an FP32
+// V-cycle.  All device memory comes from the caller's workspace, carved here.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/smg.h"
+#include "kernels.h"
+
+using namespace smg;
+
+namespace {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxSamples = 512;
+
+template <typename T>
+struct Level {
+  int n = 0;
+  T* kx = nullptr;   // [n][n+1][N]
+  T* ky = nullptr;   // [n+1][n][N]
+  T* c = nullptr;    // [N]
+  T* d = nullptr;
+  T* e = nullptr;
+  T g = 0;
+  T* x = nullptr;    // level iterate (levels >= 1, and level 0 of the FP32 cycle)
+  T* f = nullptr;    // level right-hand side
+};
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// lanes per node W and samples per lane JM for N samples
+template <typename F>
+void seg_dispatch(int N, F&& fn) {
+  if (N <= 1) fn(IC<1>{}, IC<1>{});
+  else if (N <= 2) fn(IC<2>{}, IC<1>{});
+  else if (N <= 4) fn(IC<4>{}, IC<1>{});
+  else if (N <= 8) fn(IC<8>{}, IC<1>{});
+  else if (N <= 16) fn(IC<16>{}, IC<1>{});
+  else if (N <= 32) fn(IC<32>{}, IC<1>{});
+  else if (N <= 64) fn(IC<64>{}, IC<1>{});
+  else if (N <= 128) fn(IC<64>{}, IC<2>{});
+  else if (N <= 256) fn(IC<64>{}, IC<4>{});
+  else fn(IC<64>{}, IC<8>{});
+}
+
+int count_levels(int n, int nc) {
+  int nl = 1, t = n;
+  while (t > nc) {
+    if ((t & 1) == 0) return -1;
+    t = (t - 1) / 2;
+    if (++nl > kMaxLevels) return -1;
+  }
+  return t == nc ? nl : -1;
+}
+
+size_t vlen(int n, int N) { return (size_t)(2 * N + 1) * n * n; }
+
+}  // namespace
+
+struct smg_ctx {
+  smg_desc desc{};
+  int nlev = 0, N = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  Level<double> L64[kMaxLevels];
+  Level<float> L32[kMaxLevels];
+  double* r64 = nullptr;       // level-0 sized residual scratch of the FP64 cycle
+  float* r32 = nullptr;        // same for the FP32 cycle
+  int m = 0;                   // coarsest unknowns per field
+  double* Ainv = nullptr;      // [N][m][m]
+  double* Sinv = nullptr;      // [m][m]
+  double* ds = nullptr;        // [N][m]
+  double* terms = nullptr;     // [N][m][m], setup only
+  double* partials = nullptr;  // [npart][3] per-block squared norms of a residual
+  size_t npart = 0;
+  double* norms = nullptr;     // [4]
+  double* mdp = nullptr;       // [kPartials][kMaxBasis+1]
+  double* hdev = nullptr;      // [3][kMaxBasis+1]
+  int* flag = nullptr;
+  double* V = nullptr;         // [(m+1)][len0] Krylov basis
+  double* Z64 = nullptr;       // [m][len0] preconditioned basis (FP64 cycle)
+  float* Z32 = nullptr;        // [m][len0] preconditioned basis (FP32 cycle)
+  double* w = nullptr;         // [len0]
+  double* rr = nullptr;        // [len0]
+  size_t len0 = 0;
+  double* host = nullptr;      // pinned host staging
+  size_t used_bytes = 0;
+};
+
+namespace {
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+bool desc_valid(const smg_desc& d, std::string* why) {
+  auto fail = [&](const char* m) { if (why) *why = m; return false; };
+  if (d.nsamples < 1 || d.nsamples > kMaxSamples) return fail("nsamples must be in [1, 512]");
+  if (d.coarsest_n < 1 || d.coarsest_n > 7 || (d.coarsest_n & 1) == 0) return fail("coarsest_n must be odd and <= 7");
+  if (d.n < 1 || count_levels(d.n, d.coarsest_n) < 1) return fail("n must be (coarsest_n+1)*2^k - 1");
+  if (d.pre < 0 || d.post < 0 || d.pre > 64 || d.post > 64) return fail("pre/post out of range");
+  if (!(d.theta > 0.0 && d.theta < 2.0)) return fail("theta must lie in (0, 2)");
+  if (d.precision != SMG_F64 && d.precision != SMG_F32) return fail("precision must be SMG_F64 or SMG_F32");
+  if (d.gmres_restart < 0 || d.gmres_restart > kMaxBasis - 1) return fail("gmres_restart must be in [0, 31]");
+  return true;
+}
+
+smg_desc normalized(const smg_desc& in) {
+  smg_desc d = in;
+  if (d.coarsest_n == 0) d.coarsest_n = 7;
+  if (d.theta == 0.0) d.theta = 1.0;
+  return d;
+}
+
+// Lay out (base == null: only size) every device buffer of a context.
+size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
+  Carver cv(base);
+  const int N = d.nsamples, nl = count_levels(d.n, d.coarsest_n);
+  const bool f32 = d.precision == SMG_F32;
+  int n = d.n;
+  for (int l = 0; l < nl; ++l) {
+    Level<double>& L = C->L64[l];
+    L.n = n;
+    const size_t fx = (size_t)n * (n + 1) * N, len = vlen(n, N);
+    if (l > 0) { L.kx = cv.take<double>(fx); L.ky = cv.take<double>(fx); }
+    L.c = cv.take<double>(N); L.d = cv.take<double>(N); L.e = cv.take<double>(N);
+    if (l > 0 && !f32) { L.x = cv.take<double>(len); L.f = cv.take<double>(len); }
+    if (f32) {
+      Level<float>& M = C->L32[l];
+      M.n = n;
+      M.kx = cv.take<float>(fx); M.ky = cv.take<float>(fx);
+      M.c = cv.take<float>(N); M.d = cv.take<float>(N); M.e = cv.take<float>(N);
+      M.x = cv.take<float>(len); M.f = cv.take<float>(len);
+    }
+    n = (n - 1) / 2;
+  }
+  const size_t len0 = vlen(d.n, N);
+  C->len0 = len0;
+  if (f32) C->r32 = cv.take<float>(len0); else C->r64 = cv.take<double>(len0);
+  const int m = d.coarsest_n * d.coarsest_n;
+  C->m = m;
+  C->Ainv = cv.take<double>((size_t)N * m * m);
+  C->Sinv = cv.take<double>((size_t)m * m);
+  C->ds = cv.take<double>((size_t)N * m);
+  C->terms = cv.take<double>((size_t)N * m * m);
+  C->npart = ((size_t)d.n * d.n + 3) / 4 + 1;   // residual blocks hold >= 4 nodes
+  C->partials = cv.take<double>(C->npart * 3);
+  C->norms = cv.take<double>(4);
+  C->mdp = cv.take<double>((size_t)kPartials * (kMaxBasis + 1));
+  C->hdev = cv.take<double>(3 * (kMaxBasis + 1));
+  C->flag = cv.take<int>(1);
+  C->w = cv.take<double>(len0);
+  C->rr = cv.take<double>(len0);
+  const int mr = d.gmres_restart;
+  if (mr > 0) {
+    C->V = cv.take<double>(len0 * (mr + 1));
+    if (f32) C->Z32 = cv.take<float>(len0 * mr); else C->Z64 = cv.take<double>(len0 * mr);
+  }
+  return cv.off + 256;
+}
+
+int hip_fail(smg_ctx* C, hipError_t e, const char* where) {
+  C->err = std::string(where) + ": " + hipGetErrorString(e);
+  return SMG_EHIP;
+}
+
+#define HIP_TRY(call)                                      \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hip_fail(C, e_, #call);   \
+  } while (0)
+
+#define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+int grid_for(size_t len) {
+  size_t b = (len + kBlock - 1) / kBlock;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename T>
+LevelArgs<T> args(const Level<T>& L, int N) {
+  LevelArgs<T> a;
+  a.n = L.n; a.N = N; a.kx = L.kx; a.ky = L.ky; a.c = L.c; a.d = L.d; a.e = L.e; a.g = L.g;
+  return a;
+}
+
+template <typename T>
+int fill(smg_ctx* C, T* p, size_t len, T v) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, p, v);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+template <typename TI, typename TO>
+int convert(smg_ctx* C, const TI* in, TO* out, size_t len) {
+  hipLaunchKernelGGL((k_convert<TI, TO>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, in, out);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+template <typename T>
+int halfsweep(smg_ctx* C, const Level<T>& L, T* x, const T* f, int colour) {
+  const int nact = colour_count(L.n, colour);
+  const T theta = (T)C->desc.theta;
+  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    const int per = kBlock / W, nb = (nact + per - 1) / per;
+    hipLaunchKernelGGL((k_halfsweep<T, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N), x, f,
+                       colour, theta, nact);
+  });
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+// out = f - S x (mode 0) or S x (mode 1); norms into C->norms when want_norm.
+template <typename T, typename TX, typename TO>
+int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, int mode, bool want_norm) {
+  const size_t nn = (size_t)L.n * L.n;
+  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    const int per = kBlock / W;
+    const int nb = (int)((nn + per - 1) / per);
+    hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N), x, f,
+                       out, mode, want_norm ? C->partials : (double*)nullptr);
+    if (want_norm)
+      hipLaunchKernelGGL(k_finalize_norms3, dim3(1), dim3(kBlock), 0, C->stream, C->partials, nb, C->norms);
+  });
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+template <typename T>
+int restrict_to(smg_ctx* C, int nf, const T* fine, T* coarse) {
+  const int nc = (nf - 1) / 2;
+  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    const int per = kBlock / W, nb = (nc * nc + per - 1) / per;
+    hipLaunchKernelGGL((k_restrict<T, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, nf, C->N, fine, coarse);
+  });
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+template <typename T>
+int prolong_add(smg_ctx* C, int nc, const T* coarse, T* fine) {
+  const int nf = 2 * nc + 1;
+  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    const int per = kBlock / W, nb = (nf * nf + per - 1) / per;
+    hipLaunchKernelGGL((k_prolong_add<T, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, nc, C->N, coarse, fine);
+  });
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+template <typename TV>
+int coarse_solve(smg_ctx* C, const TV* F, TV* X) {
+  const Level<double>& L = C->L64[C->nlev - 1];
+  hipLaunchKernelGGL((k_coarse_phase1<TV>), dim3(C->N), dim3(64), 0, C->stream, C->m, C->N, C->Ainv, L.c, L.d,
+                     F, C->ds);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_coarse_phase2<TV>), dim3(C->N), dim3(64), 0, C->stream, C->m, C->N, C->Ainv, C->Sinv,
+                     L.c, L.e, F, C->ds, X);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+#define TRY(expr)                  \
+  do {                             \
+    int rc_ = (expr);              \
+    if (rc_ != SMG_OK) return rc_; \
+  } while (0)
+
+// Alg. 1 on level l (Levels Ls of type T), x and f of that level.
+template <typename T>
+int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f) {
+  if (l == C->nlev - 1) return coarse_solve<T>(C, f, x);
+  const Level<T>& L = Ls[l];
+  for (int s = 0; s < C->desc.pre; ++s) {
+    TRY(halfsweep<T>(C, L, x, f, 0));
+    TRY(halfsweep<T>(C, L, x, f, 1));
+  }
+  TRY((residual<T, T, T>(C, L, x, f, r, 0, false)));
+  Level<T>& Lc = Ls[l + 1];
+  TRY(restrict_to<T>(C, L.n, r, Lc.f));
+  TRY(fill<T>(C, Lc.x, vlen(Lc.n, C->N), T(0)));
+  TRY(vcycle_level<T>(C, Ls, r, l + 1, Lc.x, Lc.f));
+  TRY(prolong_add<T>(C, Lc.n, Lc.x, x));
+  for (int s = 0; s < C->desc.post; ++s) {
+    TRY(halfsweep<T>(C, L, x, f, 0));
+    TRY(halfsweep<T>(C, L, x, f, 1));
+  }
+  return SMG_OK;
+}
+
+int vcycle64(smg_ctx* C, double* x, const double* f) { return vcycle_level<double>(C, C->L64, C->r64, 0, x, f); }
+int vcycle32(smg_ctx* C, float* x, const float* f) { return vcycle_level<float>(C, C->L32, C->r32, 0, x, f); }
+
+int sync(smg_ctx* C) {
+  HIP_TRY(hipStreamSynchronize(C->stream));
+  return SMG_OK;
+}
+
+// FP64 residual of the finest level into out (may be null), norms to host h[0..3].
+int residual_norms64(smg_ctx* C, const double* x, const double* f, double* out, double* h) {
+  TRY((residual<double, double, double>(C, C->L64[0], x, f, out, 0, true)));
+  HIP_TRY(hipMemcpyAsync(C->host, C->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, C->stream));
+  TRY(sync(C));
+  for (int i = 0; i < 4; ++i) h[i] = C->host[i];
+  return SMG_OK;
+}
+
+// ||f||_2 via the residual kernel's norm path (x = 0 gives r = f): reuse mdot on f.
+int vec_norm(smg_ctx* C, const double* v, size_t len, double* out) {
+  hipLaunchKernelGGL((k_mdot<double>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, v, (const double*)nullptr,
+                     (size_t)0, 0, 1, C->mdp);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_mdot_finalize, dim3(1), dim3(kBlock), 0, C->stream, C->mdp, kPartials, 0, 1, C->hdev, 0);
+  LAUNCH_CHECK();
+  HIP_TRY(hipMemcpyAsync(C->host, C->hdev + kMaxBasis, sizeof(double), hipMemcpyDeviceToHost, C->stream));
+  TRY(sync(C));
+  *out = std::sqrt(C->host[0]);
+  return SMG_OK;
+}
+
+void stats_begin(smg_stats* st) {
+  if (!st) return;
+  st->iterations = 0; st->inner_iterations = 0; st->restarts = 0;
+  st->relres = st->relres_y = st->relres_u = st->relres_p = NAN;
+  st->history_len = 0;
+}
+
+void stats_push(smg_stats* st, double v) {
+  if (st && st->history && st->history_len < st->history_cap) st->history[st->history_len++] = v;
+}
+
+void stats_norms(smg_stats* st, const double* h, double fn) {
+  if (!st) return;
+  st->relres = h[0] / fn; st->relres_y = h[1] / fn; st->relres_u = h[2] / fn; st->relres_p = h[3] / fn;
+}
+
+// Apply the preconditioner to V_k and the operator to the result:
+//   Z_k = Vcycle(0, V_k);  w = S Z_k.
+int precond_and_apply(smg_ctx* C, int k) {
+  const size_t len = C->len0;
+  double* vk = C->V + (size_t)k * len;
+  if (C->desc.precision == SMG_F64) {
+    double* zk = C->Z64 + (size_t)k * len;
+    TRY(fill<double>(C, zk, len, 0.0));
+    TRY(vcycle64(C, zk, vk));
+    TRY((residual<double, double, double>(C, C->L64[0], zk, (const double*)nullptr, C->w, 1, false)));
+  } else {
+    float* zk = C->Z32 + (size_t)k * len;
+    TRY((convert<double, float>(C, vk, C->L32[0].f, len)));
+    TRY(fill<float>(C, zk, len, 0.0f));
+    TRY(vcycle32(C, zk, C->L32[0].f));
+    TRY((residual<double, float, double>(C, C->L64[0], zk, (const float*)nullptr, C->w, 1, false)));
+  }
+  return SMG_OK;
+}
+
+template <typename TV>
+int mdot(smg_ctx* C, const double* w, const TV* V, int nv, int with_norm, double* out) {
+  const size_t len = C->len0;
+  hipLaunchKernelGGL((k_mdot<TV>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, w, V, len, nv, with_norm,
+                     C->mdp);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_mdot_finalize, dim3(1), dim3(kBlock), 0, C->stream, C->mdp, kPartials, nv, with_norm, out, 0);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+// One restart cycle of right-preconditioned (flexible) GMRES with classical
+// Gram-Schmidt applied twice.  On entry C->w holds r0 = f - S x with norm beta.
+// Iterates until the recurrence residual <= target, m steps, or *budget runs
+// out; x += Z y at the end.  Returns its in *its_done and the last recurrence
+// residual in *est.
+int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int budget, int* its_done,
+                double* est, smg_stats* st, double fn) {
+  const size_t len = C->len0;
+  const int K1 = kMaxBasis + 1;
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), y(m);
+  g[0] = beta;
+  // V_0 = r0 / beta
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, (const double*)C->w, C->V,
+                     1.0 / beta);
+  LAUNCH_CHECK();
+  int k = 0, done = 0;
+  double res = beta;
+  for (; k < m && done < budget; ++k) {
+    TRY(precond_and_apply(C, k));
+    // h1 = V^T w ; w -= V h1 ; h2 = V^T w (+ ||w||^2) ; w -= V h2
+    TRY(mdot<double>(C, C->w, C->V, k + 1, 0, C->hdev));
+    hipLaunchKernelGGL((k_gs_update<double>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, C->w, C->V, len,
+                       k + 1, C->hdev);
+    LAUNCH_CHECK();
+    TRY(mdot<double>(C, C->w, C->V, k + 1, 1, C->hdev + K1));
+    hipLaunchKernelGGL((k_gs_update<double>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, C->w, C->V, len,
+                       k + 1, C->hdev + K1);
+    LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(C->host, C->hdev, sizeof(double) * 2 * K1, hipMemcpyDeviceToHost, C->stream));
+    TRY(sync(C));
+    double h2sq = 0.0;
+    for (int i = 0; i <= k; ++i) {
+      H[(size_t)i * m + k] = C->host[i] + C->host[K1 + i];
+      h2sq += C->host[K1 + i] * C->host[K1 + i];
+    }
+    double wsq = C->host[K1 + kMaxBasis] - h2sq;   // ||w - V h2||^2 = ||w||^2 - ||h2||^2
+    if (!(wsq > 0.0)) wsq = 0.0;
+    const double hn = std::sqrt(wsq);
+    if (!std::isfinite(hn)) { C->err = "non-finite Arnoldi norm"; return SMG_ENONFINITE; }
+    H[(size_t)(k + 1) * m + k] = hn;
+    if (hn > 0.0) {
+      hipLaunchKernelGGL(k_scale, dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, (const double*)C->w,
+                         C->V + (size_t)(k + 1) * len, 1.0 / hn);
+      LAUNCH_CHECK();
+    }
+    for (int i = 0; i < k; ++i) {
+      const double a = H[(size_t)i * m + k], b = H[(size_t)(i + 1) * m + k];
+      H[(size_t)i * m + k] = cs[i] * a + sn[i] * b;
+      H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = H[(size_t)k * m + k], b = H[(size_t)(k + 1) * m + k];
+    const double rr = std::sqrt(a * a + b * b);
+    cs[k] = a / rr; sn[k] = b / rr;
+    H[(size_t)k * m + k] = rr; H[(size_t)(k + 1) * m + k] = 0.0;
+    g[k + 1] = -sn[k] * g[k];
+    g[k] = cs[k] * g[k];
+    res = std::fabs(g[k + 1]);
+    ++done;
+    stats_push(st, res / fn);
+    if (res <= target || hn == 0.0) { ++k; break; }
+  }
+  const int kend = k;
+  for (int i = kend - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int q = i + 1; q < kend; ++q) s -= H[(size_t)i * m + q] * y[q];
+    y[i] = s / H[(size_t)i * m + i];
+  }
+  if (kend > 0) {
+    for (int i = 0; i < kend; ++i) C->host[i] = y[i];
+    HIP_TRY(hipMemcpyAsync(C->hdev, C->host, sizeof(double) * kend, hipMemcpyHostToDevice, C->stream));
+    if (C->desc.precision == SMG_F64)
+      hipLaunchKernelGGL((k_basis_axpy<double>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x, C->Z64, len,
+                         kend, C->hdev);
+    else
+      hipLaunchKernelGGL((k_basis_axpy<float>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x, C->Z32, len,
+                         kend, C->hdev);
+    LAUNCH_CHECK();
+  }
+  *its_done = done;
+  *est = res;
+  return SMG_OK;
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int check_level(const smg_ctx* C, int level, int need_coarser) {
+  if (level < 0 || level >= C->nlev) return SMG_EINVAL;
+  if (need_coarser && level + 1 >= C->nlev) return SMG_EINVAL;
+  return SMG_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+size_t smg_workspace_bytes(const smg_desc* desc) {
+  if (!desc) return 0;
+  const smg_desc d = normalized(*desc);
+  if (!desc_valid(d, nullptr)) return 0;
+  smg_ctx tmp;
+  return plan(d, &tmp, nullptr);
+}
+
+const char* smg_strerror(int code) {
+  switch (code) {
+    case SMG_OK: return "ok";
+    case SMG_NOT_CONVERGED: return "not converged within the iteration limit";
+    case SMG_EINVAL: return "invalid argument";
+    case SMG_ESINGULAR: return "singular or non-positive block";
+    case SMG_EHIP: return "HIP runtime error";
+    case SMG_ENONFINITE: return "non-finite residual";
+    case SMG_EWORKSPACE: return "workspace missing or too small";
+    default: return "unknown error";
+  }
+}
+
+const char* smg_last_error(const smg_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+int smg_num_levels(const smg_ctx* ctx) { return ctx ? ctx->nlev : 0; }
+int smg_level_n(const smg_ctx* ctx, int level) {
+  return (ctx && level >= 0 && level < ctx->nlev) ? ctx->L64[level].n : 0;
+}
+
+void smg_destroy(smg_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->host) (void)hipHostFree(ctx->host);
+  delete ctx;
+}
+
+int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, size_t workspace_bytes,
+              void* stream, smg_ctx** out) {
+  if (!out) return SMG_EINVAL;
+  *out = nullptr;
+  if (!desc_in || !B || !B->kx || !B->ky || !B->c || !B->d || !B->e) return SMG_EINVAL;
+  const smg_desc d = normalized(*desc_in);
+  std::string why;
+  if (!desc_valid(d, &why)) return SMG_EINVAL;
+  const int N = d.nsamples;
+  // node denominators g + sum_j d_j c_j e_j / a_j^2 stay positive for every a_j > 0
+  if (!(B->g > 0.0) || !std::isfinite(B->g)) return SMG_ESINGULAR;
+  for (int j = 0; j < N; ++j) {
+    if (!(B->c[j] > 0.0) || !std::isfinite(B->c[j]) || !std::isfinite(B->d[j]) || !std::isfinite(B->e[j]))
+      return SMG_ESINGULAR;
+    if (B->d[j] * B->c[j] * B->e[j] < 0.0) return SMG_ESINGULAR;
+  }
+  smg_ctx* C = new smg_ctx();
+  C->desc = d;
+  C->N = N;
+  C->nlev = count_levels(d.n, d.coarsest_n);
+  C->stream = (hipStream_t)stream;
+  const size_t need = plan(d, C, workspace);
+  if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255) != 0) {
+    delete C;
+    return SMG_EWORKSPACE;
+  }
+  C->used_bytes = need;
+  auto fail = [&](int rc) { smg_destroy(C); return rc; };
+  if (hipHostMalloc((void**)&C->host, sizeof(double) * 4 * (kMaxBasis + 1), hipHostMallocDefault) != hipSuccess)
+    return fail(SMG_EHIP);
+  // level 0 references the caller's faces; coarse faces by rediscretization
+  C->L64[0].kx = const_cast<double*>(B->kx);
+  C->L64[0].ky = const_cast<double*>(B->ky);
+  std::vector<double> cc(B->c, B->c + N), dd(B->d, B->d + N), ee(B->e, B->e + N);
+  double g = B->g;
+  std::vector<float> cf(N), df(N), ef(N);
+  for (int l = 0; l < C->nlev; ++l) {
+    Level<double>& L = C->L64[l];
+    L.g = g;
+    if (hipMemcpy(L.c, cc.data(), sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L.d, dd.data(), sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L.e, ee.data(), sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(SMG_EHIP);
+    if (d.precision == SMG_F32) {
+      Level<float>& M = C->L32[l];
+      M.g = (float)g;
+      for (int j = 0; j < N; ++j) { cf[j] = (float)cc[j]; df[j] = (float)dd[j]; ef[j] = (float)ee[j]; }
+      if (hipMemcpy(M.c, cf.data(), sizeof(float) * N, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(M.d, df.data(), sizeof(float) * N, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(M.e, ef.data(), sizeof(float) * N, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(SMG_EHIP);
+    }
+    // mass-type blocks carry h^2: x4 per coarsening
+    for (int j = 0; j < N; ++j) { cc[j] *= 4.0; dd[j] *= 4.0; ee[j] *= 4.0; }
+    g *= 4.0;
+  }
+  const size_t fx0 = (size_t)d.n * (d.n + 1) * N;
+  if (hipMemsetAsync(C->flag, 0, sizeof(int), C->stream) != hipSuccess) return fail(SMG_EHIP);
+  hipLaunchKernelGGL(k_check_faces, dim3(grid_for(fx0)), dim3(kBlock), 0, C->stream, fx0, B->kx, B->ky, C->flag);
+  if (hipGetLastError() != hipSuccess) return fail(SMG_EHIP);
+  for (int l = 1; l < C->nlev; ++l) {
+    const Level<double>& F = C->L64[l - 1];
+    Level<double>& L = C->L64[l];
+    const size_t tot = (size_t)L.n * (L.n + 1) * N;
+    hipLaunchKernelGGL((k_coarsen_faces<double>), dim3(grid_for(tot)), dim3(kBlock), 0, C->stream, F.n, N, F.kx,
+                       F.ky, L.kx, L.ky);
+    if (hipGetLastError() != hipSuccess) return fail(SMG_EHIP);
+  }
+  if (d.precision == SMG_F32) {
+    for (int l = 0; l < C->nlev; ++l) {
+      const size_t fx = (size_t)C->L64[l].n * (C->L64[l].n + 1) * N;
+      if (convert<double, float>(C, C->L64[l].kx, C->L32[l].kx, fx) != SMG_OK ||
+          convert<double, float>(C, C->L64[l].ky, C->L32[l].ky, fx) != SMG_OK)
+        return fail(SMG_EHIP);
+    }
+  }
+  // coarsest factorization (FP64): A_j^{-1} and the control Schur complement inverse
+  const Level<double>& Lc = C->L64[C->nlev - 1];
+  hipLaunchKernelGGL(k_coarse_invert_A, dim3(N), dim3(kBlock), 0, C->stream, Lc.n, N, Lc.kx, Lc.ky, C->Ainv);
+  hipLaunchKernelGGL(k_coarse_schur_terms, dim3(N), dim3(kBlock), 0, C->stream, C->m, C->Ainv, Lc.c, Lc.d, Lc.e,
+                     C->terms);
+  hipLaunchKernelGGL(k_coarse_schur_invert, dim3(1), dim3(kBlock), 0, C->stream, C->m, N, C->terms, Lc.g, C->Sinv);
+  if (hipGetLastError() != hipSuccess) return fail(SMG_EHIP);
+  int flag = 0;
+  if (hipMemcpyAsync(&flag, C->flag, sizeof(int), hipMemcpyDeviceToHost, C->stream) != hipSuccess) return fail(SMG_EHIP);
+  if (hipStreamSynchronize(C->stream) != hipSuccess) return fail(SMG_EHIP);
+  if (flag) return fail(SMG_ESINGULAR);
+  *out = C;
+  return SMG_OK;
+}
+
+int smg_apply(smg_ctx* C, const double* x, double* Sx) {
+  if (!C || !x || !Sx) return SMG_EINVAL;
+  return residual<double, double, double>(C, C->L64[0], x, (const double*)nullptr, Sx, 1, false);
+}
+
+int smg_residual(smg_ctx* C, const double* x, const double* f, double* r, double* norms) {
+  if (!C || !x || !f || !r) return SMG_EINVAL;
+  if (norms) return residual_norms64(C, x, f, r, norms);
+  return residual<double, double, double>(C, C->L64[0], x, f, r, 0, false);
+}
+
+int smg_smooth(smg_ctx* C, int level, int colour, double* x, const double* f) {
+  if (!C || !x || !f || (colour != 0 && colour != 1)) return SMG_EINVAL;
+  TRY(check_level(C, level, 0));
+  return halfsweep<double>(C, C->L64[level], x, f, colour);
+}
+
+int smg_restrict(smg_ctx* C, int level, const double* fine, double* coarse) {
+  if (!C || !fine || !coarse) return SMG_EINVAL;
+  TRY(check_level(C, level, 1));
+  return restrict_to<double>(C, C->L64[level].n, fine, coarse);
+}
+
+int smg_prolong_add(smg_ctx* C, int level, const double* coarse, double* fine) {
+  if (!C || !fine || !coarse) return SMG_EINVAL;
+  TRY(check_level(C, level, 1));
+  return prolong_add<double>(C, C->L64[level + 1].n, coarse, fine);
+}
+
+int smg_coarse_solve(smg_ctx* C, const double* F, double* X) {
+  if (!C || !F || !X) return SMG_EINVAL;
+  return coarse_solve<double>(C, F, X);
+}
+
+int smg_level_faces(smg_ctx* C, int level, double* kx, double* ky) {
+  if (!C || !kx || !ky) return SMG_EINVAL;
+  TRY(check_level(C, level, 0));
+  const int n = C->L64[level].n;
+  const size_t bytes = (size_t)n * (n + 1) * C->N * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(kx, C->L64[level].kx, bytes, hipMemcpyDeviceToDevice, C->stream));
+  HIP_TRY(hipMemcpyAsync(ky, C->L64[level].ky, bytes, hipMemcpyDeviceToDevice, C->stream));
+  return SMG_OK;
+}
+
+int smg_vcycle(smg_ctx* C, double* x, const double* f, int ncycles) {
+  if (!C || !x || !f || ncycles < 0) return SMG_EINVAL;
+  if (C->desc.precision == SMG_F64) {
+    for (int i = 0; i < ncycles; ++i) TRY(vcycle64(C, x, f));
+    return SMG_OK;
+  }
+  Level<float>& L = C->L32[0];
+  TRY((convert<double, float>(C, x, L.x, C->len0)));
+  TRY((convert<double, float>(C, f, L.f, C->len0)));
+  for (int i = 0; i < ncycles; ++i) TRY(vcycle32(C, L.x, L.f));
+  TRY((convert<float, double>(C, L.x, x, C->len0)));
+  return SMG_OK;
+}
+
+int smg_gmres_precond(smg_ctx* C, double* x, const double* f, int restart, double rtol, int maxit,
+                      smg_stats* st) {
+  if (!C || !x || !f || restart < 1 || restart > C->desc.gmres_restart || !(rtol > 0) || maxit < 1)
+    return SMG_EINVAL;
+  const double t0 = now_ms();
+  stats_begin(st);
+  double fn;
+  TRY(vec_norm(C, f, C->len0, &fn));
+  if (!(fn > 0.0)) fn = 1.0;
+  double h[4];
+  TRY(residual_norms64(C, x, f, C->w, h));
+  stats_push(st, h[0] / fn);
+  int its = 0, restarts = 0, rc = SMG_NOT_CONVERGED;
+  while (true) {
+    if (!std::isfinite(h[0])) { rc = SMG_ENONFINITE; break; }
+    if (h[0] <= rtol * fn) { rc = SMG_OK; break; }
+    if (its >= maxit) break;
+    int done = 0;
+    double est = 0;
+    TRY(gmres_cycle(C, x, h[0], restart, rtol * fn, maxit - its, &done, &est, st, fn));
+    its += done;
+    TRY(residual_norms64(C, x, f, C->w, h));
+    if (h[0] > rtol * fn && its < maxit) ++restarts;
+  }
+  if (st) {
+    stats_norms(st, h, fn);
+    st->iterations = its;
+    st->inner_iterations = its;
+    st->restarts = restarts;
+    st->time_ms = now_ms() - t0;
+  }
+  return rc;
+}
+
+int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, int maxit, smg_stats* st) {
+  if (!C || !x || !f || !(rtol > 0) || maxit < 1) return SMG_EINVAL;
+  if (method != SMG_VCYCLE && method != SMG_GMRES) return SMG_EINVAL;
+  const double t0 = now_ms();
+  const bool f32 = C->desc.precision == SMG_F32;
+  if (method == SMG_GMRES && !f32) {
+    const int m = C->desc.gmres_restart;
+    if (m < 1) return SMG_EINVAL;
+    return smg_gmres_precond(C, x, f, m, rtol, maxit, st);
+  }
+  if (method == SMG_GMRES && C->desc.gmres_restart < 1) return SMG_EINVAL;
+  stats_begin(st);
+  double fn;
+  TRY(vec_norm(C, f, C->len0, &fn));
+  if (!(fn > 0.0)) fn = 1.0;
+  double h[4];
+  int its = 0, inner = 0, rc = SMG_NOT_CONVERGED;
+  while (true) {
+    if (!f32) {
+      TRY(residual_norms64(C, x, f, nullptr, h));
+    } else if (method == SMG_VCYCLE) {
+      // FP64 residual rounded straight into the FP32 cycle's right-hand side
+      TRY((residual<double, double, float>(C, C->L64[0], x, f, C->L32[0].f, 0, true)));
+      HIP_TRY(hipMemcpyAsync(C->host, C->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, C->stream));
+      TRY(sync(C));
+      for (int i = 0; i < 4; ++i) h[i] = C->host[i];
+    } else {
+      TRY(residual_norms64(C, x, f, C->w, h));
+    }
+    stats_push(st, h[0] / fn);
+    if (!std::isfinite(h[0])) { rc = SMG_ENONFINITE; break; }
+    if (h[0] <= rtol * fn) { rc = SMG_OK; break; }
+    if (its >= maxit) break;
+    if (!f32) {
+      TRY(vcycle64(C, x, f));
+      ++inner;
+    } else if (method == SMG_VCYCLE) {
+      TRY(fill<float>(C, C->L32[0].x, C->len0, 0.0f));
+      TRY(vcycle32(C, C->L32[0].x, C->L32[0].f));
+      hipLaunchKernelGGL((k_add<float>), dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, x,
+                         (const float*)C->L32[0].x);
+      LAUNCH_CHECK();
+      ++inner;
+    } else {
+      int done = 0;
+      double est = 0;
+      const double inner_rtol = 1e-5;
+      TRY(gmres_cycle(C, x, h[0], C->desc.gmres_restart, inner_rtol * h[0], C->desc.gmres_restart, &done, &est,
+                      nullptr, fn));
+      inner += done;
+    }
+    ++its;
+  }
+  if (st) {
+    stats_norms(st, h, fn);
+    st->iterations = its;
+    st->inner_iterations = inner;
+    st->time_ms = now_ms() - t0;
+  }
+  return rc;
+}
+
+}  // extern "C"

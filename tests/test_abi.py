@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/smg.h declares, and sizes/validates descriptors."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "smg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(smg_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2302_13680_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2302_13680_amd import build
+        build.build()
+    return binding.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_2302_13680_amd import binding
+    assert sorted(binding.EXPORTED) == names
+
+
+def test_workspace_bytes_validation(lib):
+    from paper_2302_13680_amd.binding import Desc
+    ok = Desc(255, 64, 7, 2, 2, 1.0, 0, 30)
+    nb = lib.smg_workspace_bytes(C.byref(ok))
+    # at least the Krylov basis: 61 vectors of (2N+1) n^2 doubles
+    assert nb >= 61 * (2 * 64 + 1) * 255 * 255 * 8
+    f32 = Desc(255, 64, 7, 2, 2, 1.0, 1, 30)
+    assert lib.smg_workspace_bytes(C.byref(f32)) > 0
+    for bad in [Desc(254, 64, 7, 2, 2, 1.0, 0, 30),   # n not (nc+1)2^k - 1
+                Desc(255, 0, 7, 2, 2, 1.0, 0, 30),    # no samples
+                Desc(255, 513, 7, 2, 2, 1.0, 0, 30),  # too many samples
+                Desc(255, 64, 6, 2, 2, 1.0, 0, 30),   # even coarsest grid
+                Desc(255, 64, 7, 2, 2, 2.5, 0, 30),   # theta out of range
+                Desc(255, 64, 7, 2, 2, 1.0, 2, 30),   # unknown precision
+                Desc(255, 64, 7, 2, 2, 1.0, 0, 40)]:  # restart too long
+        assert lib.smg_workspace_bytes(C.byref(bad)) == 0
+    # defaults: coarsest_n 0 -> 7, theta 0 -> 1
+    assert lib.smg_workspace_bytes(C.byref(Desc(31, 8, 0, 2, 2, 0.0, 0, 0))) > 0
+
+
+def test_strerror_covers_codes(lib):
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert lib.smg_strerror(code).decode() != "unknown error"
+
+
+def test_setup_rejects_bad_arguments_before_any_launch(lib):
+    from paper_2302_13680_amd.binding import Blocks, Desc
+    out = C.c_void_p()
+    d = Desc(31, 8, 7, 2, 2, 1.0, 0, 0)
+    assert lib.smg_setup(C.byref(d), None, None, 0, None, C.byref(out)) == -1
+    c = (C.c_double * 8)(*([1.0] * 8))
+    dd = (C.c_double * 8)(*([-1.0] * 8))
+    b = Blocks(C.c_void_p(256), C.c_void_p(256), c, dd, dd, -1.0)   # g < 0: rejected on the host
+    assert lib.smg_setup(C.byref(d), C.byref(b), C.c_void_p(256), 1 << 30, None, C.byref(out)) == -2
+    b = Blocks(C.c_void_p(256), C.c_void_p(256), c, dd, dd, 1.0)
+    assert lib.smg_setup(C.byref(d), C.byref(b), None, 0, None, C.byref(out)) == -5
