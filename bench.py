@@ -30,8 +30,9 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources the finest-level half-sweep kernel is built from."""
     h = hashlib.sha256()
-    for f in ("kernels.h", "smg.hip"):
+    for f in ("common.h", "smoother.h"):
         with open(os.path.join(ROOT, "paper_2302_13680_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -66,6 +67,9 @@ def main():
     ap.add_argument("--sweeps", type=int, default=200, help="half-sweep launches timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--counters", action="store_true",
+                    help="launch only the finest-level half-sweep (20x) and a 1 GiB device copy (5x), "
+                         "for hardware-counter passes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
@@ -85,6 +89,19 @@ def main():
     ctx, f = binding.context_from_problem(prob, device=dev, gmres_restart=30)
     x = torch.zeros(dof, dtype=torch.float64, device=dev)
     stream = ctx.stream
+
+    if args.counters:
+        for i in range(20):
+            ctx.smooth(0, i & 1, x, f)
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters": "done", "halfsweep_launches": 20,
+                          "halfsweep_algorithmic_bytes": halfsweep_bytes(n, N, 8),
+                          "copy_bytes_each_way": a.numel() * 8, "copy_launches": 5}), flush=True)
+        return
 
     def solve(method, rtol):
         x.zero_()

@@ -88,7 +88,16 @@ typedef struct {
   double theta;       /* relaxation of the node update (1 = Gauss-Seidel; 0 selects 1) */
   int precision;      /* SMG_F64 or SMG_F32 */
   int gmres_restart;  /* basis size m reserved for GMRES (0 = no Krylov storage) */
+  int flags;          /* SMG_FLAG_* bits */
 } smg_desc;
+
+/* flags */
+#define SMG_FLAG_EAGER 1      /* launch every V-cycle kernel by kernel instead of replaying a
+                                 captured hipGraph (the default captures one graph per distinct
+                                 (x, f) buffer pair on first use and replays it afterwards) */
+#define SMG_FLAG_UNFUSED 2    /* separate residual, restriction, prolongation and zero-fill
+                                 kernels (the default fuses them into neighbouring kernels when
+                                 theta = 1; both compute the same iteration) */
 
 typedef struct {
   const double *kx;   /* device, [n][n+1][N] */

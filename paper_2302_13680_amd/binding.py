@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libsmg.so")
 SMG_OK, SMG_NOT_CONVERGED = 0, 1
 SMG_F64, SMG_F32 = 0, 1
 SMG_VCYCLE, SMG_GMRES = 0, 1
+SMG_FLAG_EAGER = 1
+SMG_FLAG_UNFUSED = 2
 
 EXPORTED = [
     "smg_workspace_bytes", "smg_setup", "smg_destroy", "smg_strerror", "smg_last_error",
@@ -31,7 +33,7 @@ EXPORTED = [
 class Desc(C.Structure):
     _fields_ = [("n", C.c_int), ("nsamples", C.c_int), ("coarsest_n", C.c_int), ("pre", C.c_int),
                 ("post", C.c_int), ("theta", C.c_double), ("precision", C.c_int),
-                ("gmres_restart", C.c_int)]
+                ("gmres_restart", C.c_int), ("flags", C.c_int)]
 
 
 class Blocks(C.Structure):
@@ -100,9 +102,10 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-def workspace_bytes(n, N, coarsest_n=7, pre=2, post=2, theta=1.0, precision=SMG_F64, gmres_restart=30):
+def workspace_bytes(n, N, coarsest_n=7, pre=2, post=2, theta=1.0, precision=SMG_F64, gmres_restart=30,
+                    flags=0):
     L = load()
-    desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart)
+    desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart, flags)
     return int(L.smg_workspace_bytes(C.byref(desc)))
 
 
@@ -114,14 +117,14 @@ class Context:
     """
 
     def __init__(self, n, N, kx, ky, c, d, e, g, *, coarsest_n=7, pre=2, post=2, theta=1.0,
-                 precision=SMG_F64, gmres_restart=30, stream=None):
+                 precision=SMG_F64, gmres_restart=30, flags=0, stream=None):
         import torch
         L = load()
         self.L = L
         self.n, self.N = n, N
         self.precision = precision
         self.device = kx.device
-        self.desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart)
+        self.desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart, flags)
         nbytes = int(L.smg_workspace_bytes(C.byref(self.desc)))
         if nbytes == 0:
             raise SmgError(-1, "invalid descriptor")

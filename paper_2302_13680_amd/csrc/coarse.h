@@ -1,0 +1,188 @@
+// coarse.h -- hierarchy setup and the coarsest-level direct solve (gfx950).
+#pragma once
+#include "common.h"
+
+namespace smg {
+
+// ------------------------------------------------------------------- setup
+// Coarse faces by rediscretization: mean of the two fine faces under a coarse face.
+template <typename T>
+__global__ void k_coarsen_faces(int nf, int N, const T* __restrict__ kxf, const T* __restrict__ kyf,
+                                T* __restrict__ kxc, T* __restrict__ kyc) {
+  const int nc = (nf - 1) / 2;
+  const size_t tot = (size_t)nc * (nc + 1) * N;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < tot; i += (size_t)gridDim.x * kBlock) {
+    const int j = (int)(i % N);
+    const size_t r = i / N;
+    {  // kx: (K, F)
+      const int F = (int)(r % (nc + 1)), K = (int)(r / (nc + 1));
+      const size_t fb = ((size_t)(2 * K + 1) * (nf + 1) + 2 * F) * N + j;
+      kxc[i] = T(0.5) * (kxf[fb] + kxf[fb + N]);
+    }
+    {  // ky: (G, X)
+      const int X = (int)(r % nc), G = (int)(r / nc);
+      const size_t fb = ((size_t)(2 * G) * nf + 2 * X + 1) * N + j;
+      kyc[i] = T(0.5) * (kyf[fb] + kyf[fb + (size_t)nf * N]);
+    }
+  }
+}
+
+// flags[0] = 1 if any face is not finite or <= 0 (A_j would lose its positive diagonal).
+__global__ void k_check_faces(size_t len, const double* __restrict__ a, const double* __restrict__ b,
+                              int* __restrict__ flag) {
+  int bad = 0;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < len; i += (size_t)gridDim.x * kBlock) {
+    const double u = a[i], v = b[i];
+    if (!(u > 0.0) || !(v > 0.0) || !isfinite(u) || !isfinite(v)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+// In-place Gauss-Jordan inversion of an m x m matrix held in LDS (no pivoting:
+// used on symmetric positive definite matrices only).  All threads call it.
+__device__ void lds_invert_spd(double* A, double* col, int m) {
+  for (int p = 0; p < m; ++p) {
+    __syncthreads();
+    const double piv = A[p * m + p];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) col[i] = A[i * m + p];
+    __syncthreads();
+    const double ip = 1.0 / piv;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) A[p * m + j] = (j == p) ? ip : A[p * m + j] * ip;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      const int i = idx / m, j = idx - i * m;
+      if (i == p) continue;
+      const double fct = col[i];
+      A[idx] = (j == p) ? -fct * ip : A[idx] - fct * A[p * m + j];
+    }
+  }
+  __syncthreads();
+}
+
+// One block per sample: assemble the coarsest A_j (m = n^2) from its faces and invert it.
+__global__ __launch_bounds__(kBlock) void k_coarse_invert_A(int n, int N, const double* __restrict__ kx,
+                                                            const double* __restrict__ ky,
+                                                            double* __restrict__ Ainv) {
+  __shared__ double A[kMaxCoarse * kMaxCoarse];
+  __shared__ double col[kMaxCoarse];
+  const int j = blockIdx.x, m = n * n;
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) A[idx] = 0.0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+    const int k = r / n, x = r - k * n;
+    const double kw = kx[((size_t)k * (n + 1) + x) * N + j], ke = kx[((size_t)k * (n + 1) + x + 1) * N + j];
+    const double ks = ky[((size_t)k * n + x) * N + j], kn = ky[((size_t)(k + 1) * n + x) * N + j];
+    A[r * m + r] = (kw + ke) + (ks + kn);
+    if (x > 0) A[r * m + r - 1] = -kw;
+    if (x < n - 1) A[r * m + r + 1] = -ke;
+    if (k > 0) A[r * m + r - n] = -ks;
+    if (k < n - 1) A[r * m + r + n] = -kn;
+  }
+  lds_invert_spd(A, col, m);
+  // stored transposed: AinvT[c][r] = Ainv[r][c], so that a thread per row reads coalesced
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+    const int r = idx / m, q = idx - r * m;
+    Ainv[(size_t)j * m * m + (size_t)q * m + r] = A[idx];
+  }
+}
+
+// terms[j] = (d_j c_j e_j Ainv_j Ainv_j)^T from the transposed inverses (one block per sample)
+__global__ __launch_bounds__(kBlock) void k_coarse_schur_terms(int m, const double* __restrict__ Ainv,
+                                                               const double* __restrict__ c,
+                                                               const double* __restrict__ d,
+                                                               const double* __restrict__ e,
+                                                               double* __restrict__ terms) {
+  __shared__ double A[kMaxCoarse * kMaxCoarse];
+  const int j = blockIdx.x;
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) A[idx] = Ainv[(size_t)j * m * m + idx];
+  __syncthreads();
+  const double s = d[j] * c[j] * e[j];
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+    const int i = idx / m, q = idx - i * m;
+    double t = 0.0;
+    for (int r = 0; r < m; ++r) t += A[i * m + r] * A[r * m + q];
+    terms[(size_t)j * m * m + idx] = s * t;
+  }
+}
+
+// Transposed Schur complement (g I + sum_j terms[j])^T (fixed order over j) inverted in
+// place; the result is the transposed storage of its inverse.  One block.
+__global__ __launch_bounds__(kBlock) void k_coarse_schur_invert(int m, int N, const double* __restrict__ terms,
+                                                                double g, double* __restrict__ Sinv) {
+  __shared__ double A[kMaxCoarse * kMaxCoarse];
+  __shared__ double col[kMaxCoarse];
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+    double s = (idx / m == idx % m) ? g : 0.0;
+    for (int j = 0; j < N; ++j) s += terms[(size_t)j * m * m + idx];
+    A[idx] = s;
+  }
+  lds_invert_spd(A, col, m);
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) Sinv[idx] = A[idx];
+}
+
+// ------------------------------------------------------------ coarsest solve
+// Block elimination of eq. (2) on the coarsest grid, one block per sample j:
+//   phase 1: ds_j = d_j A_j^{-1} (F_Y,j - c_j A_j^{-1} F_P,j)
+//   phase 2: u = Sinv (F_U - sum_j ds_j);  y_j = A_j^{-1}(F_P,j - e_j u);
+//            p_j = A_j^{-1}(F_Y,j - c_j y_j)
+// Vectors in the level layout (type TV), arithmetic in FP64.
+// (M v)_i with M stored transposed (MT[c][i] = M[i][c]): coalesced across threads i.
+__device__ __forceinline__ double row_dot(const double* __restrict__ MT, int m, int i, const double* v) {
+  double s = 0.0;
+#pragma unroll 7
+  for (int c = 0; c < m; ++c) s += MT[(size_t)c * m + i] * v[c];
+  return s;
+}
+
+template <typename TV>
+__global__ __launch_bounds__(64) void k_coarse_phase1(int m, int N, const double* __restrict__ Ainv,
+                                                      const double* __restrict__ c, const double* __restrict__ d,
+                                                      const TV* __restrict__ F, double* __restrict__ ds) {
+  __shared__ double sF[kMaxCoarse], sT[kMaxCoarse];
+  const int j = blockIdx.x, i = threadIdx.x;
+  const double* Aj = Ainv + (size_t)j * m * m;
+  const TV* FY = F;
+  const TV* FP = F + (size_t)(N + 1) * m;
+  if (i < m) sF[i] = (double)FP[(size_t)i * N + j];
+  __syncthreads();
+  if (i < m) sT[i] = (double)FY[(size_t)i * N + j] - c[j] * row_dot(Aj, m, i, sF);
+  __syncthreads();
+  if (i < m) ds[(size_t)j * m + i] = d[j] * row_dot(Aj, m, i, sT);
+}
+
+template <typename TV>
+__global__ __launch_bounds__(64) void k_coarse_phase2(int m, int N, const double* __restrict__ Ainv,
+                                                      const double* __restrict__ Sinv,
+                                                      const double* __restrict__ c, const double* __restrict__ e,
+                                                      const TV* __restrict__ F, const double* __restrict__ ds,
+                                                      TV* __restrict__ X) {
+  __shared__ double sR[kMaxCoarse], sU[kMaxCoarse], sT[kMaxCoarse], sY[kMaxCoarse];
+  const int j = blockIdx.x, i = threadIdx.x;
+  const double* Aj = Ainv + (size_t)j * m * m;
+  const TV* FY = F;
+  const TV* FU = F + (size_t)N * m;
+  const TV* FP = F + (size_t)(N + 1) * m;
+  if (i < m) {
+    double s = (double)FU[i];
+#pragma unroll 8
+    for (int q = 0; q < N; ++q) s -= ds[(size_t)q * m + i];
+    sR[i] = s;
+  }
+  __syncthreads();
+  if (i < m) sU[i] = row_dot(Sinv, m, i, sR);
+  __syncthreads();
+  if (i < m) sT[i] = (double)FP[(size_t)i * N + j] - e[j] * sU[i];
+  __syncthreads();
+  if (i < m) sY[i] = row_dot(Aj, m, i, sT);
+  __syncthreads();
+  if (i < m) sT[i] = (double)FY[(size_t)i * N + j] - c[j] * sY[i];
+  __syncthreads();
+  if (i < m) {
+    const double p = row_dot(Aj, m, i, sT);
+    X[(size_t)i * N + j] = (TV)sY[i];
+    X[(size_t)(N + 1) * m + (size_t)i * N + j] = (TV)p;
+    if (j == 0) X[(size_t)N * m + i] = (TV)sU[i];
+  }
+}
+
+}  // namespace smg

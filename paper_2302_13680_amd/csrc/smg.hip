@@ -42,6 +42,15 @@ template <int V>
 using IC = std::integral_constant<int, V>;
 
 // lanes per node W and samples per lane JM for N samples
+// compile-time width KM >= nv of the Krylov multi-vector kernels
+template <typename F>
+void km_dispatch(int nv, F&& fn) {
+  if (nv <= 4) fn(IC<4>{});
+  else if (nv <= 8) fn(IC<8>{});
+  else if (nv <= 16) fn(IC<16>{});
+  else fn(IC<32>{});
+}
+
 template <typename F>
 void seg_dispatch(int N, F&& fn) {
   if (N <= 1) fn(IC<1>{}, IC<1>{});
@@ -98,6 +107,15 @@ struct smg_ctx {
   size_t len0 = 0;
   double* host = nullptr;      // pinned host staging
   size_t used_bytes = 0;
+  // captured V-cycles, one per (x, f, kind); kind = precision * 2 + zero_first
+  struct Graph {
+    const void* x;
+    const void* f;
+    int kind;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  hipStream_t cap_stream = nullptr;  // private stream used only while capturing
 };
 
 namespace {
@@ -124,6 +142,7 @@ bool desc_valid(const smg_desc& d, std::string* why) {
   if (!(d.theta > 0.0 && d.theta < 2.0)) return fail("theta must lie in (0, 2)");
   if (d.precision != SMG_F64 && d.precision != SMG_F32) return fail("precision must be SMG_F64 or SMG_F32");
   if (d.gmres_restart < 0 || d.gmres_restart > kMaxBasis - 1) return fail("gmres_restart must be in [0, 31]");
+  if (d.flags & ~(SMG_FLAG_EAGER | SMG_FLAG_UNFUSED)) return fail("unknown flag bits");
   return true;
 }
 
@@ -222,15 +241,24 @@ int convert(smg_ctx* C, const TI* in, TO* out, size_t len) {
   return SMG_OK;
 }
 
+// src: kPlain (neighbours from x), kZero (x is zero), kProlong (x + P ec).
 template <typename T>
-int halfsweep(smg_ctx* C, const Level<T>& L, T* x, const T* f, int colour) {
+int halfsweep(smg_ctx* C, const Level<T>& L, T* x, const T* f, int colour, int src = kPlain,
+              const T* ec = nullptr) {
   const int nact = colour_count(L.n, colour);
   const T theta = (T)C->desc.theta;
   seg_dispatch(C->N, [&](auto Wc, auto Jc) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     const int per = kBlock / W, nb = (nact + per - 1) / per;
-    hipLaunchKernelGGL((k_halfsweep<T, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N), x, f,
-                       colour, theta, nact);
+    if (src == kZero)
+      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kZero>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N), x,
+                         f, colour, theta, nact, ec);
+    else if (src == kProlong)
+      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kProlong>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N),
+                         x, f, colour, theta, nact, ec);
+    else
+      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kPlain>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N), x,
+                         f, colour, theta, nact, ec);
   });
   LAUNCH_CHECK();
   return SMG_OK;
@@ -247,7 +275,7 @@ int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, i
     hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N), x, f,
                        out, mode, want_norm ? C->partials : (double*)nullptr);
     if (want_norm)
-      hipLaunchKernelGGL(k_finalize_norms3, dim3(1), dim3(kBlock), 0, C->stream, C->partials, nb, C->norms);
+      hipLaunchKernelGGL(k_finalize_norms3, dim3(1), dim3(1024), 0, C->stream, C->partials, nb, C->norms);
   });
   LAUNCH_CHECK();
   return SMG_OK;
@@ -295,30 +323,99 @@ int coarse_solve(smg_ctx* C, const TV* F, TV* X) {
     if (rc_ != SMG_OK) return rc_; \
   } while (0)
 
-// Alg. 1 on level l (Levels Ls of type T), x and f of that level.
+// Alg. 1 on level l (Levels Ls of type T), x and f of that level; x_zero: x
+// holds (or is to be taken as) zero on entry.
+//
+// With theta = 1 the launch sequence is fused without changing the iteration:
+//  - from a zero guess the first red half-sweep reads no neighbours (kZero) and
+//    no zero fill is written;
+//  - the coarse correction x += P e_c is folded into the first post-smoothing red
+//    half-sweep (kProlong): red nodes read their black neighbours corrected on
+//    the fly, and the black half-sweep that follows overwrites every black node.
 template <typename T>
-int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f) {
+int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f, bool x_zero) {
   if (l == C->nlev - 1) return coarse_solve<T>(C, f, x);
   const Level<T>& L = Ls[l];
-  for (int s = 0; s < C->desc.pre; ++s) {
+  const bool fused = C->desc.theta == 1.0 && !(C->desc.flags & SMG_FLAG_UNFUSED);
+  int s0 = 0;
+  if (x_zero) {
+    if (fused && C->desc.pre > 0) {
+      TRY(halfsweep<T>(C, L, x, f, 0, kZero));
+      TRY(halfsweep<T>(C, L, x, f, 1));
+      s0 = 1;
+    } else {
+      TRY(fill<T>(C, x, vlen(L.n, C->N), T(0)));
+    }
+  }
+  for (int s = s0; s < C->desc.pre; ++s) {
     TRY(halfsweep<T>(C, L, x, f, 0));
     TRY(halfsweep<T>(C, L, x, f, 1));
   }
-  TRY((residual<T, T, T>(C, L, x, f, r, 0, false)));
   Level<T>& Lc = Ls[l + 1];
+  TRY((residual<T, T, T>(C, L, x, f, r, 0, false)));
   TRY(restrict_to<T>(C, L.n, r, Lc.f));
-  TRY(fill<T>(C, Lc.x, vlen(Lc.n, C->N), T(0)));
-  TRY(vcycle_level<T>(C, Ls, r, l + 1, Lc.x, Lc.f));
-  TRY(prolong_add<T>(C, Lc.n, Lc.x, x));
-  for (int s = 0; s < C->desc.post; ++s) {
+  TRY(vcycle_level<T>(C, Ls, r, l + 1, Lc.x, Lc.f, true));
+  int p0 = 0;
+  if (fused && C->desc.post > 0) {
+    TRY(halfsweep<T>(C, L, x, f, 0, kProlong, Lc.x));
+    TRY(halfsweep<T>(C, L, x, f, 1));
+    p0 = 1;
+  } else {
+    TRY(prolong_add<T>(C, Lc.n, Lc.x, x));
+  }
+  for (int s = p0; s < C->desc.post; ++s) {
     TRY(halfsweep<T>(C, L, x, f, 0));
     TRY(halfsweep<T>(C, L, x, f, 1));
   }
   return SMG_OK;
 }
 
-int vcycle64(smg_ctx* C, double* x, const double* f) { return vcycle_level<double>(C, C->L64, C->r64, 0, x, f); }
-int vcycle32(smg_ctx* C, float* x, const float* f) { return vcycle_level<float>(C, C->L32, C->r32, 0, x, f); }
+template <typename T>
+int cycle_eager(smg_ctx* C, T* x, const T* f, bool zero_first) {
+  Level<T>* Ls;
+  T* r;
+  if constexpr (std::is_same<T, double>::value) { Ls = C->L64; r = C->r64; }
+  else { Ls = C->L32; r = C->r32; }
+  return vcycle_level<T>(C, Ls, r, 0, x, f, zero_first);
+}
+
+constexpr size_t kMaxGraphs = 128;
+
+// One V-cycle on the finest level (x <- Vcycle(x, f), or from zero when
+// zero_first).  Unless the context is eager, the launch sequence is captured
+// once per (x, f) pair into a hipGraph on a private stream and replayed on the
+// caller's stream; graphs hold no memset nodes.
+template <typename T>
+int run_cycle(smg_ctx* C, T* x, const T* f, bool zero_first) {
+  if ((C->desc.flags & SMG_FLAG_EAGER) || !C->cap_stream) return cycle_eager<T>(C, x, f, zero_first);
+  const int kind = (std::is_same<T, double>::value ? 0 : 2) + (zero_first ? 1 : 0);
+  for (auto& g : C->graphs)
+    if (g.x == x && g.f == f && g.kind == kind) {
+      HIP_TRY(hipGraphLaunch(g.exec, C->stream));
+      return SMG_OK;
+    }
+  if (C->graphs.size() >= kMaxGraphs) return cycle_eager<T>(C, x, f, zero_first);
+  hipStream_t user = C->stream;
+  C->stream = C->cap_stream;
+  hipError_t e = hipStreamBeginCapture(C->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) { C->stream = user; return hip_fail(C, e, "hipStreamBeginCapture"); }
+  const int rc = cycle_eager<T>(C, x, f, zero_first);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(C->cap_stream, &graph);
+  C->stream = user;
+  if (rc != SMG_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+  if (e != hipSuccess) return hip_fail(C, e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(C, e, "hipGraphInstantiate");
+  C->graphs.push_back({x, f, kind, exec});
+  HIP_TRY(hipGraphLaunch(exec, C->stream));
+  return SMG_OK;
+}
+
+int vcycle64(smg_ctx* C, double* x, const double* f) { return run_cycle<double>(C, x, f, false); }
+int vcycle32(smg_ctx* C, float* x, const float* f) { return run_cycle<float>(C, x, f, false); }
 
 int sync(smg_ctx* C) {
   HIP_TRY(hipStreamSynchronize(C->stream));
@@ -336,10 +433,10 @@ int residual_norms64(smg_ctx* C, const double* x, const double* f, double* out, 
 
 // ||f||_2 via the residual kernel's norm path (x = 0 gives r = f): reuse mdot on f.
 int vec_norm(smg_ctx* C, const double* v, size_t len, double* out) {
-  hipLaunchKernelGGL((k_mdot<double>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, v, (const double*)nullptr,
-                     (size_t)0, 0, 1, C->mdp);
+  hipLaunchKernelGGL((k_mdot<double, 4>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, v,
+                     (const double*)nullptr, (size_t)0, 0, 1, C->mdp);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_mdot_finalize, dim3(1), dim3(kBlock), 0, C->stream, C->mdp, kPartials, 0, 1, C->hdev, 0);
+  hipLaunchKernelGGL(k_mdot_finalize, dim3(kMaxBasis + 1), dim3(kBlock), 0, C->stream, C->mdp, kPartials, 0, 1, C->hdev, 0);
   LAUNCH_CHECK();
   HIP_TRY(hipMemcpyAsync(C->host, C->hdev + kMaxBasis, sizeof(double), hipMemcpyDeviceToHost, C->stream));
   TRY(sync(C));
@@ -370,14 +467,12 @@ int precond_and_apply(smg_ctx* C, int k) {
   double* vk = C->V + (size_t)k * len;
   if (C->desc.precision == SMG_F64) {
     double* zk = C->Z64 + (size_t)k * len;
-    TRY(fill<double>(C, zk, len, 0.0));
-    TRY(vcycle64(C, zk, vk));
+    TRY(run_cycle<double>(C, zk, vk, true));
     TRY((residual<double, double, double>(C, C->L64[0], zk, (const double*)nullptr, C->w, 1, false)));
   } else {
     float* zk = C->Z32 + (size_t)k * len;
     TRY((convert<double, float>(C, vk, C->L32[0].f, len)));
-    TRY(fill<float>(C, zk, len, 0.0f));
-    TRY(vcycle32(C, zk, C->L32[0].f));
+    TRY(run_cycle<float>(C, zk, C->L32[0].f, true));
     TRY((residual<double, float, double>(C, C->L64[0], zk, (const float*)nullptr, C->w, 1, false)));
   }
   return SMG_OK;
@@ -386,10 +481,13 @@ int precond_and_apply(smg_ctx* C, int k) {
 template <typename TV>
 int mdot(smg_ctx* C, const double* w, const TV* V, int nv, int with_norm, double* out) {
   const size_t len = C->len0;
-  hipLaunchKernelGGL((k_mdot<TV>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, w, V, len, nv, with_norm,
-                     C->mdp);
+  km_dispatch(nv, [&](auto Kc) {
+    constexpr int KM = decltype(Kc)::value;
+    hipLaunchKernelGGL((k_mdot<TV, KM>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, w, V, len, nv, with_norm,
+                       C->mdp);
+  });
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_mdot_finalize, dim3(1), dim3(kBlock), 0, C->stream, C->mdp, kPartials, nv, with_norm, out, 0);
+  hipLaunchKernelGGL(k_mdot_finalize, dim3(kMaxBasis + 1), dim3(kBlock), 0, C->stream, C->mdp, kPartials, nv, with_norm, out, 0);
   LAUNCH_CHECK();
   return SMG_OK;
 }
@@ -413,30 +511,58 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
   double res = beta;
   for (; k < m && done < budget; ++k) {
     TRY(precond_and_apply(C, k));
-    // h1 = V^T w ; w -= V h1 ; h2 = V^T w (+ ||w||^2) ; w -= V h2
-    TRY(mdot<double>(C, C->w, C->V, k + 1, 0, C->hdev));
-    hipLaunchKernelGGL((k_gs_update<double>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, C->w, C->V, len,
-                       k + 1, C->hdev);
-    LAUNCH_CHECK();
-    TRY(mdot<double>(C, C->w, C->V, k + 1, 1, C->hdev + K1));
-    hipLaunchKernelGGL((k_gs_update<double>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, C->w, C->V, len,
-                       k + 1, C->hdev + K1);
-    LAUNCH_CHECK();
-    HIP_TRY(hipMemcpyAsync(C->host, C->hdev, sizeof(double) * 2 * K1, hipMemcpyDeviceToHost, C->stream));
+    // Classical Gram-Schmidt with selective reorthogonalization (Daniel, Gragg,
+    // Kaufman, Stewart 1976, "twice is enough"):
+    //   A: h1 = V^T w and ||w||^2                                  (one pass)
+    //   if ||w - V h1|| > ||w|| / sqrt(2): accept h1
+    //   else B: w <- w - V h1 with h2 = V^T w and ||w||^2           (one pass)
+    //   C: v_{k+1} = (w - V h) / h_{k+1,k}                         (one pass)
+    // where h_{k+1,k}^2 = ||w||^2 - ||h||^2 for the last projection h.
+    TRY(mdot<double>(C, C->w, C->V, k + 1, 1, C->hdev));
+    HIP_TRY(hipMemcpyAsync(C->host, C->hdev, sizeof(double) * K1, hipMemcpyDeviceToHost, C->stream));
     TRY(sync(C));
-    double h2sq = 0.0;
+    double h1sq = 0.0;
     for (int i = 0; i <= k; ++i) {
-      H[(size_t)i * m + k] = C->host[i] + C->host[K1 + i];
-      h2sq += C->host[K1 + i] * C->host[K1 + i];
+      H[(size_t)i * m + k] = C->host[i];
+      h1sq += C->host[i] * C->host[i];
     }
-    double wsq = C->host[K1 + kMaxBasis] - h2sq;   // ||w - V h2||^2 = ||w||^2 - ||h2||^2
+    const double w0sq = C->host[kMaxBasis];
+    double wsq = w0sq - h1sq;
+    const double* hlast = C->hdev;
+    if (!(wsq > 0.5 * w0sq)) {
+      km_dispatch(k + 1, [&](auto Kc) {
+        constexpr int KM = decltype(Kc)::value;
+        hipLaunchKernelGGL((k_gs_update_mdot<double, KM>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, C->w,
+                           (const double*)C->V, len, k + 1, (const double*)C->hdev, C->mdp);
+      });
+      LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_mdot_finalize, dim3(kMaxBasis + 1), dim3(kBlock), 0, C->stream, (const double*)C->mdp,
+                         kPartials, k + 1, 1, C->hdev + K1, 0);
+      LAUNCH_CHECK();
+      HIP_TRY(hipMemcpyAsync(C->host + K1, C->hdev + K1, sizeof(double) * K1, hipMemcpyDeviceToHost, C->stream));
+      TRY(sync(C));
+      double h2sq = 0.0;
+      for (int i = 0; i <= k; ++i) {
+        H[(size_t)i * m + k] += C->host[K1 + i];
+        h2sq += C->host[K1 + i] * C->host[K1 + i];
+      }
+      wsq = C->host[K1 + kMaxBasis] - h2sq;
+      hlast = C->hdev + K1;
+    }
     if (!(wsq > 0.0)) wsq = 0.0;
     const double hn = std::sqrt(wsq);
-    if (!std::isfinite(hn)) { C->err = "non-finite Arnoldi norm"; return SMG_ENONFINITE; }
+    if (!std::isfinite(hn) || !std::isfinite(H[(size_t)k * m + k])) {
+      C->err = "non-finite Arnoldi coefficients";
+      return SMG_ENONFINITE;
+    }
     H[(size_t)(k + 1) * m + k] = hn;
     if (hn > 0.0) {
-      hipLaunchKernelGGL(k_scale, dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, (const double*)C->w,
-                         C->V + (size_t)(k + 1) * len, 1.0 / hn);
+      km_dispatch(k + 1, [&](auto Kc) {
+        constexpr int KM = decltype(Kc)::value;
+        hipLaunchKernelGGL((k_gs_final<double, KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len,
+                           (const double*)C->w, (const double*)C->V, len, k + 1, hlast,
+                           C->V + (size_t)(k + 1) * len, 1.0 / hn);
+      });
       LAUNCH_CHECK();
     }
     for (int i = 0; i < k; ++i) {
@@ -464,12 +590,15 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
   if (kend > 0) {
     for (int i = 0; i < kend; ++i) C->host[i] = y[i];
     HIP_TRY(hipMemcpyAsync(C->hdev, C->host, sizeof(double) * kend, hipMemcpyHostToDevice, C->stream));
-    if (C->desc.precision == SMG_F64)
-      hipLaunchKernelGGL((k_basis_axpy<double>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x, C->Z64, len,
-                         kend, C->hdev);
-    else
-      hipLaunchKernelGGL((k_basis_axpy<float>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x, C->Z32, len,
-                         kend, C->hdev);
+    km_dispatch(kend, [&](auto Kc) {
+      constexpr int KM = decltype(Kc)::value;
+      if (C->desc.precision == SMG_F64)
+        hipLaunchKernelGGL((k_basis_axpy<double, KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x,
+                           (const double*)C->Z64, len, kend, (const double*)C->hdev);
+      else
+        hipLaunchKernelGGL((k_basis_axpy<float, KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x,
+                           (const float*)C->Z32, len, kend, (const double*)C->hdev);
+    });
     LAUNCH_CHECK();
   }
   *its_done = done;
@@ -521,6 +650,9 @@ int smg_level_n(const smg_ctx* ctx, int level) {
 
 void smg_destroy(smg_ctx* ctx) {
   if (!ctx) return;
+  for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+  ctx->graphs.clear();
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->host) (void)hipHostFree(ctx->host);
   delete ctx;
 }
@@ -554,6 +686,9 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
   C->used_bytes = need;
   auto fail = [&](int rc) { smg_destroy(C); return rc; };
   if (hipHostMalloc((void**)&C->host, sizeof(double) * 4 * (kMaxBasis + 1), hipHostMallocDefault) != hipSuccess)
+    return fail(SMG_EHIP);
+  if (!(d.flags & SMG_FLAG_EAGER) &&
+      hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(SMG_EHIP);
   // level 0 references the caller's faces; coarse faces by rediscretization
   C->L64[0].kx = const_cast<double*>(B->kx);
@@ -745,8 +880,7 @@ int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, i
       TRY(vcycle64(C, x, f));
       ++inner;
     } else if (method == SMG_VCYCLE) {
-      TRY(fill<float>(C, C->L32[0].x, C->len0, 0.0f));
-      TRY(vcycle32(C, C->L32[0].x, C->L32[0].f));
+      TRY(run_cycle<float>(C, C->L32[0].x, C->L32[0].f, true));
       hipLaunchKernelGGL((k_add<float>), dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, x,
                          (const float*)C->L32[0].x);
       LAUNCH_CHECK();

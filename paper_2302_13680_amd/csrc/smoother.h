@@ -1,0 +1,136 @@
+// smoother.h -- collective Gauss-Seidel half-sweep kernels (gfx950).
+#pragma once
+#include "common.h"
+
+namespace smg {
+
+// Neighbour values the half-sweep reads, by source:
+//   kPlain   : the level iterate x (the other colour)
+//   kZero    : a zero iterate (first red half-sweep of a cycle started from 0)
+//   kProlong : x + P e_c, the iterate after the coarse correction of Alg. 1,
+//              interpolated on the fly from the coarse correction e_c (the other
+//              colour is overwritten by the following half-sweep, so the
+//              corrected values never need to be stored)
+enum NbSource { kPlain = 0, kZero = 1, kProlong = 2 };
+
+// Coarse corrections (P e)(nb) of the four neighbours W, E, S, N of a fine node
+// with x + k even (the red colour), for one sample field of the coarse vector e
+// (nc x nc coarse grid, stride N between nodes).  Such a node either coincides
+// with coarse node (X, K) (x, k odd) or is the centre of a coarse cell (x, k
+// even); every neighbour lies on a coarse edge, so bilinear interpolation there
+// averages two coarse values.  Coarse nodes outside the grid are zero.
+template <typename T>
+__device__ __forceinline__ void prolong_nb(const T* __restrict__ e, int nc, int N, int j, int x, int k,
+                                           T& cw, T& ce, T& cs, T& cn) {
+  auto at = [&](int X, int K) -> T {
+    return (X >= 0 && X < nc && K >= 0 && K < nc) ? e[((size_t)K * nc + X) * N + j] : T(0);
+  };
+  if (x & 1) {
+    const int X = (x - 1) >> 1, K = (k - 1) >> 1;
+    const T c0 = at(X, K);
+    cw = T(0.5) * (at(X - 1, K) + c0);
+    ce = T(0.5) * (c0 + at(X + 1, K));
+    cs = T(0.5) * (at(X, K - 1) + c0);
+    cn = T(0.5) * (c0 + at(X, K + 1));
+  } else {
+    const int X = x >> 1, K = k >> 1;
+    const T a = at(X - 1, K - 1), b = at(X, K - 1), c = at(X - 1, K), d = at(X, K);
+    cw = T(0.5) * (a + c);
+    ce = T(0.5) * (b + d);
+    cs = T(0.5) * (a + b);
+    cn = T(0.5) * (c + d);
+  }
+}
+
+// One half-sweep of collective Gauss-Seidel: each node of `colour` is replaced
+// by the solution of its (2N+1)x(2N+1) system (eq. solution_reduced_system)
+// with the opposite-colour neighbours fixed:
+//   bP_j = fY_j + sum_nb k_nb p_j,nb      (rhs of the C_j / A_j^T row)
+//   bY_j = fP_j + sum_nb k_nb y_j,nb      (rhs of the A_j / E_j row)
+//   u    = (fU + sum_j d_j (c_j bY_j / a_j^2 - bP_j / a_j)) / (g + sum_j d_j c_j e_j / a_j^2)
+//   y_j  = (bY_j - e_j u) / a_j,   p_j = (bP_j - c_j y_j) / a_j
+// theta != 1 (relaxation) is supported for SRC == kPlain only.
+template <typename T, int W, int JM, int SRC>
+__global__ __launch_bounds__(kBlock) void k_halfsweep(LevelArgs<T> L, T* __restrict__ x,
+                                                      const T* __restrict__ f, int colour,
+                                                      T theta, int nactive,
+                                                      const T* __restrict__ ec) {
+  const int n = L.n, N = L.N;
+  const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & (W - 1);
+  const int slot = b * (kBlock / W) + threadIdx.x / W;
+  if (slot >= nactive) return;  // whole W-lane groups leave together
+  int xx, k;
+  colour_node(slot, n, colour, xx, k);
+  const size_t node = (size_t)k * n + xx;
+  T* __restrict__ Y = x;
+  T* __restrict__ U = x + (size_t)N * nn;
+  T* __restrict__ P = x + (size_t)(N + 1) * nn;
+  const T* __restrict__ fY = f;
+  const T* __restrict__ fU = f + (size_t)N * nn;
+  const T* __restrict__ fP = f + (size_t)(N + 1) * nn;
+  const size_t kxb = ((size_t)k * (n + 1) + xx) * N;
+  const size_t kyb = node * N;
+  const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
+  const int nc = (n - 1) / 2;
+  const size_t nnc = (size_t)nc * nc;
+  const T* eY = ec;
+  const T* eP = ec + (size_t)(N + 1) * nnc;
+  T bP[JM], bY[JM], ia[JM];
+  T num = 0, den = 0;
+#pragma unroll
+  for (int q = 0; q < JM; ++q) {
+    const int j = lane + q * W;
+    bP[q] = 0; bY[q] = 0; ia[q] = 0;
+    if (j < N) {
+      const T kw = L.kx[kxb + j], ke = L.kx[kxb + N + j];
+      const T ks = L.ky[kyb + j], kn = L.ky[kyb + rowN + j];
+      const size_t base = node * N + j;
+      T sy = 0, sp = 0;
+      if constexpr (SRC != kZero) {
+        if (hw) { sy += kw * Y[base - N]; sp += kw * P[base - N]; }
+        if (he) { sy += ke * Y[base + N]; sp += ke * P[base + N]; }
+        if (hs) { sy += ks * Y[base - rowN]; sp += ks * P[base - rowN]; }
+        if (hn) { sy += kn * Y[base + rowN]; sp += kn * P[base + rowN]; }
+      }
+      if constexpr (SRC == kProlong) {   // colour 0 only: x + k even
+        T cw, ce, cs, cn;
+        prolong_nb(eY, nc, N, j, xx, k, cw, ce, cs, cn);
+        sy += (hw ? kw * cw : T(0)) + (he ? ke * ce : T(0)) + (hs ? ks * cs : T(0)) + (hn ? kn * cn : T(0));
+        prolong_nb(eP, nc, N, j, xx, k, cw, ce, cs, cn);
+        sp += (hw ? kw * cw : T(0)) + (he ? ke * ce : T(0)) + (hs ? ks * cs : T(0)) + (hn ? kn * cn : T(0));
+      }
+      const T a = (kw + ke) + (ks + kn);
+      const T ai = T(1) / a;
+      const T cj = L.c[j], dj = L.d[j], ej = L.e[j];
+      const T bp = fY[base] + sp, by = fP[base] + sy;
+      const T t = cj * ai * ai;
+      num += dj * (t * by - ai * bp);
+      den += dj * t * ej;
+      bP[q] = bp; bY[q] = by; ia[q] = ai;
+    }
+  }
+  num = group_sum<W>(num);
+  den = group_sum<W>(den);
+  const T un = (fU[node] + num) / (L.g + den);
+  const bool relax = SRC == kPlain && theta != T(1);
+#pragma unroll
+  for (int q = 0; q < JM; ++q) {
+    const int j = lane + q * W;
+    if (j < N) {
+      const size_t base = node * N + j;
+      T yn = ia[q] * (bY[q] - L.e[j] * un);
+      T pn = ia[q] * (bP[q] - L.c[j] * yn);
+      if (relax) {
+        yn = (T(1) - theta) * Y[base] + theta * yn;
+        pn = (T(1) - theta) * P[base] + theta * pn;
+      }
+      Y[base] = yn;
+      P[base] = pn;
+    }
+  }
+  if (lane == 0) U[node] = relax ? (T(1) - theta) * U[node] + theta * un : un;
+}
+
+}  // namespace smg

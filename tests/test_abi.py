@@ -35,22 +35,23 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_workspace_bytes_validation(lib):
     from paper_2302_13680_amd.binding import Desc
-    ok = Desc(255, 64, 7, 2, 2, 1.0, 0, 30)
+    ok = Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 0)
     nb = lib.smg_workspace_bytes(C.byref(ok))
     # at least the Krylov basis: 61 vectors of (2N+1) n^2 doubles
     assert nb >= 61 * (2 * 64 + 1) * 255 * 255 * 8
-    f32 = Desc(255, 64, 7, 2, 2, 1.0, 1, 30)
+    f32 = Desc(255, 64, 7, 2, 2, 1.0, 1, 30, 0)
     assert lib.smg_workspace_bytes(C.byref(f32)) > 0
-    for bad in [Desc(254, 64, 7, 2, 2, 1.0, 0, 30),   # n not (nc+1)2^k - 1
-                Desc(255, 0, 7, 2, 2, 1.0, 0, 30),    # no samples
-                Desc(255, 513, 7, 2, 2, 1.0, 0, 30),  # too many samples
-                Desc(255, 64, 6, 2, 2, 1.0, 0, 30),   # even coarsest grid
-                Desc(255, 64, 7, 2, 2, 2.5, 0, 30),   # theta out of range
-                Desc(255, 64, 7, 2, 2, 1.0, 2, 30),   # unknown precision
-                Desc(255, 64, 7, 2, 2, 1.0, 0, 40)]:  # restart too long
+    for bad in [Desc(254, 64, 7, 2, 2, 1.0, 0, 30, 0),   # n not (nc+1)2^k - 1
+                Desc(255, 0, 7, 2, 2, 1.0, 0, 30, 0),    # no samples
+                Desc(255, 513, 7, 2, 2, 1.0, 0, 30, 0),  # too many samples
+                Desc(255, 64, 6, 2, 2, 1.0, 0, 30, 0),   # even coarsest grid
+                Desc(255, 64, 7, 2, 2, 2.5, 0, 30, 0),   # theta out of range
+                Desc(255, 64, 7, 2, 2, 1.0, 2, 30, 0),   # unknown precision
+                Desc(255, 64, 7, 2, 2, 1.0, 0, 40, 0),   # restart too long
+                Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 4)]:  # unknown flags
         assert lib.smg_workspace_bytes(C.byref(bad)) == 0
     # defaults: coarsest_n 0 -> 7, theta 0 -> 1
-    assert lib.smg_workspace_bytes(C.byref(Desc(31, 8, 0, 2, 2, 0.0, 0, 0))) > 0
+    assert lib.smg_workspace_bytes(C.byref(Desc(31, 8, 0, 2, 2, 0.0, 0, 0, 0))) > 0
 
 
 def test_strerror_covers_codes(lib):
@@ -61,7 +62,7 @@ def test_strerror_covers_codes(lib):
 def test_setup_rejects_bad_arguments_before_any_launch(lib):
     from paper_2302_13680_amd.binding import Blocks, Desc
     out = C.c_void_p()
-    d = Desc(31, 8, 7, 2, 2, 1.0, 0, 0)
+    d = Desc(31, 8, 7, 2, 2, 1.0, 0, 0, 0)
     assert lib.smg_setup(C.byref(d), None, None, 0, None, C.byref(out)) == -1
     c = (C.c_double * 8)(*([1.0] * 8))
     dd = (C.c_double * 8)(*([-1.0] * 8))
