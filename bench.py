@@ -59,6 +59,140 @@ def load_traffic(kind: str):
     return t.get("bytes_per_launch")
 
 
+def time_halfsweep(ctx, x, f, stream, launches):
+    """Average duration (us) of `launches` finest-level half-sweeps, HIP events on
+    the library's stream."""
+    import torch
+    for _ in range(5):
+        ctx.smooth(0, 0, x, f)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(launches):
+        ctx.smooth(0, i & 1, x, f)
+    e1.record(stream)
+    e1.synchronize()
+    return 1e3 * e0.elapsed_time(e1) / launches
+
+
+def timed_solve(ctx, x, f, method, rtol, maxit=200):
+    import torch
+    from paper_2302_13680_amd import binding
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = ctx.solve(x, f, method, rtol=rtol, maxit=maxit, history=0)
+    torch.cuda.synchronize()
+    if rc != binding.SMG_OK:
+        raise RuntimeError(f"solve did not converge: {st}")
+    return 1e3 * (time.perf_counter() - t0), st
+
+
+def large_mixed_section(dev):
+    """511x511, N=256, six modes of amplitude 1.0/m: FP32 V-cycle inside FP64
+    refinement against the plain FP64 V-cycle on the same GPU."""
+    import torch
+    from paper_2302_13680_amd import binding, inputs
+    prob = inputs.large_mixed()
+    n, N, dof = prob.n, prob.N, prob.dof
+    kxn, kyn = prob.faces_node()
+    kx = torch.from_numpy(kxn).to(dev)
+    ky = torch.from_numpy(kyn).to(dev)
+    f = torch.from_numpy(prob.rhs_node()).to(dev)
+    del kxn, kyn
+    c64 = binding.Context(n, N, kx, ky, prob.c, prob.d, prob.e, prob.g, gmres_restart=0)
+    c32 = binding.Context(n, N, kx, ky, prob.c, prob.d, prob.e, prob.g, gmres_restart=30,
+                          precision=binding.SMG_F32)
+    x = torch.zeros(dof, dtype=torch.float64, device=dev)
+    out = {"workload": "LQ-OCPUU 511x511 interior grid, N=256 samples, 6 KL modes a_m=1.0/m, nu=1e-4",
+           "dof": dof}
+    timed_solve(c64, x, f, binding.SMG_VCYCLE, 1e-8)          # warm-up (graph capture)
+    t64, s64 = timed_solve(c64, x, f, binding.SMG_VCYCLE, 1e-8)
+    out["fp64_vcycle_time_to_1e-8_ms"] = round(t64, 2)
+    out["fp64_vcycle_cycles"] = s64["iterations"]
+    for name, method in (("fp32_refinement_vcycle", binding.SMG_VCYCLE), ("fp32_refinement_fgmres30", binding.SMG_GMRES)):
+        timed_solve(c32, x, f, method, 1e-8)
+        t, st = timed_solve(c32, x, f, method, 1e-8)
+        out[name + "_time_to_1e-8_ms"] = round(t, 2)
+        out[name + "_outer_steps"] = st["iterations"]
+        out[name + "_fp32_cycles"] = st["inner_iterations"]
+        out[name + "_speedup_vs_fp64_vcycle"] = round(t64 / t, 3)
+    # errors at 1e-10: FP32 refinement against the FP64 V-cycle solution
+    t64b, _ = timed_solve(c64, x, f, binding.SMG_VCYCLE, 1e-10)
+    x64 = x.clone()
+    t32b, st32b = timed_solve(c32, x, f, binding.SMG_VCYCLE, 1e-10)
+    out["fp64_vcycle_time_to_1e-10_ms"] = round(t64b, 2)
+    out["fp32_refinement_vcycle_time_to_1e-10_ms"] = round(t32b, 2)
+    nn = n * n
+    blocks = {"y": slice(0, N * nn), "u": slice(N * nn, (N + 1) * nn), "p": slice((N + 1) * nn, None)}
+    out["fp32_refinement_rel_diff_vs_fp64_at_1e-10"] = {
+        k: float((torch.linalg.norm(x[sl] - x64[sl]) / torch.linalg.norm(x64[sl])).item()) for k, sl in blocks.items()}
+    # finest-level half-sweep rooflines in both precisions
+    xs = torch.zeros(dof, dtype=torch.float64, device=dev)
+    us64 = time_halfsweep(c64, xs, f, c64.stream, 50)
+    b64 = halfsweep_bytes(n, N, 8)
+    out["roofline_fp64_halfsweep"] = {"avg_launch_us": round(us64, 2), "achieved_GBs": round(b64 / us64 / 1e3, 1),
+                                      "frac": round(b64 / us64 / 1e3 / HBM_PEAK_GBS, 4)}
+    del x64, xs
+    return out, c32, f, x
+
+
+def batch_section(dev, cache_path):
+    """64 uneven instances (n in {63,127,255}, N in {16,32,64,128}, nu log-uniform
+    in [1e-6, 1e-2]) solved to 1e-8 by the batched FP32-refined solver with
+    autotuned lane widths, against sequential plain FP64 V-cycle solves."""
+    import torch
+    from paper_2302_13680_amd import autotune, binding, inputs
+    specs = inputs.batch_instances()
+    c32s, c64s, xs, fs = [], [], [], []
+    for sp in specs:
+        p = inputs.make_problem(sp["n"], sp["N"], sp["nu"], M=6, sigma=0.5, decay=True, seed=sp["seed"])
+        kxn, kyn = p.faces_node()
+        kx = torch.from_numpy(kxn).to(dev)
+        ky = torch.from_numpy(kyn).to(dev)
+        f = torch.from_numpy(p.rhs_node()).to(dev)
+        c32s.append(binding.Context(p.n, p.N, kx, ky, p.c, p.d, p.e, p.g, gmres_restart=0,
+                                    precision=binding.SMG_F32))
+        c64s.append(binding.Context(p.n, p.N, kx, ky, p.c, p.d, p.e, p.g, gmres_restart=0))
+        xs.append(torch.zeros(p.dof, dtype=torch.float64, device=dev))
+        fs.append(f)
+    t0 = time.perf_counter()
+    lanes, _ = autotune.tune(c32s, cache_path)
+    t_tune = time.perf_counter() - t0
+    bt = binding.Batch(c32s, xs, fs, lanes=lanes)
+    for x in xs:
+        x.zero_()
+    bt.solve(rtol=1e-8, maxit=60)                        # warm-up (graph capture)
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, stats, wall = bt.solve(rtol=1e-8, maxit=60)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    # sequential plain FP64 V-cycle solves of the same instances on the same GPU
+    for c, x, f in zip(c64s, xs, fs):
+        timed_solve(c, x, f, binding.SMG_VCYCLE, 1e-8)   # warm-up (graph capture)
+    t0 = time.perf_counter()
+    seq = []
+    for c, x, f in zip(c64s, xs, fs):
+        t, st = timed_solve(c, x, f, binding.SMG_VCYCLE, 1e-8)
+        seq.append(t)
+    t_seq = time.perf_counter() - t0
+    return {
+        "workload": "64 LQ-OCPUU instances, n in {63,127,255}, N in {16,32,64,128}, nu log-uniform [1e-6,1e-2], "
+                    "6 KL modes a_m=0.5/m, FP32 V(2,2) in FP64 refinement to 1e-8",
+        "converged": rc == 0, "instances": len(specs), "wall_ms": round(1e3 * t_batch, 2),
+        "aggregate_solves_per_s": round(len(specs) / t_batch, 2),
+        "sequential_fp64_vcycle_ms": round(1e3 * t_seq, 2),
+        "speedup_vs_sequential_fp64_vcycle": round(t_seq / t_batch, 3),
+        "autotune_s": round(t_tune, 2), "lanes": lanes,
+        "per_instance": [{"n": sp["n"], "N": sp["N"], "nu": sp["nu"], "cycles": st["iterations"],
+                          "time_to_1e-8_ms": round(st["time_ms"], 3), "fp64_vcycle_ms": round(t, 3)}
+                         for sp, st, t in zip(specs, stats, seq)],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +201,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=200, help="half-sweep launches timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune_lanes.json"))
     ap.add_argument("--counters", action="store_true",
                     help="launch only the finest-level half-sweep (20x) and a 1 GiB device copy (5x), "
                          "for hardware-counter passes")
@@ -89,6 +225,7 @@ def main():
     ctx, f = binding.context_from_problem(prob, device=dev, gmres_restart=30)
     x = torch.zeros(dof, dtype=torch.float64, device=dev)
     stream = ctx.stream
+    levels = list(ctx.levels_n)
 
     if args.counters:
         for i in range(20):
@@ -159,6 +296,17 @@ def main():
                 "kernel": "k_halfsweep<double,64,1> (finest level)", "avg_launch_us": round(t_launch_us, 2),
                 "algorithmic_bytes_per_launch": bytes_launch}
 
+    extra = {}
+    if not args.quick:
+        del ctx, x, xs
+        torch.cuda.empty_cache()
+        large, c32, fl, xl = large_mixed_section(dev)
+        extra["large_mixed"] = large
+        del c32, fl, xl
+        torch.cuda.empty_cache()
+        extra["batch"] = batch_section(dev, args.tune_cache)
+        torch.cuda.empty_cache()
+
     # ---------------- CPU oracle on the host cores (same instance, same method)
     cpu = None
     if not args.no_cpu_baseline:
@@ -181,7 +329,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "LQ-OCPUU 255x255 interior grid, N=64 samples, 6 KL modes a_m=0.5/m, "
                                "nu=1e-4, FP64, GMRES(30)+V(2,2) to rel. residual 1e-8",
-                   "n": n, "N": N, "dof": dof, "levels": ctx.levels_n},
+                   "n": n, "N": N, "dof": dof, "levels": levels},
         "time_to_1e-8_ms": round(ms_per_step, 3),
         "gmres_iterations": gmres_its,
         "fp64_vcycle_time_to_1e-8_ms": round(t_vcycle_ms, 3),
@@ -191,6 +339,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 

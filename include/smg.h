@@ -192,6 +192,51 @@ int smg_gmres_precond(smg_ctx *ctx, double *x, const double *f, int restart, dou
 int smg_solve(smg_ctx *ctx, double *x, const double *f, int method, double rtol, int maxit,
               smg_stats *stats);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent problem instances (different n, N and blocks) solved
+ * together: every refinement step of all unretired instances -- FP64 residual
+ * r_i = f_i - S_i x_i, convergence check, one correction V-cycle from zero in
+ * the contexts' precision (red-black collective Gauss-Seidel V(pre,post),
+ * Alg. 1), x_i += correction -- is one fixed sequence of batched launches,
+ * each covering one phase of all instances at the same hierarchy depth,
+ * captured once into a hipGraph and replayed.  An instance is retired on the
+ * device as soon as its relative residual meets the tolerance; its blocks then
+ * exit at once.  The instances' contexts must share precision, pre, post and
+ * stream and use theta = 1 (pre, post >= 1).  Calls that overlap on the same
+ * contexts race (the batch uses their scratch buffers). */
+typedef struct smg_batch smg_batch;
+
+/* Device workspace bytes a batch over these contexts needs (0 if invalid). */
+size_t smg_batch_workspace_bytes(smg_ctx *const *ctxs, int count);
+
+/* Bind the instances' FP64 device vectors x[i] (initial guess in, solution
+ * out) and f[i] to a batch.  lanes (host, may be NULL): lanes per grid node of
+ * each instance (power of two <= 64 with nsamples/lanes <= 8), e.g. from
+ * smg_tune_lanes; NULL picks min(64, pow2ceil(N)).  Computes ||f_i|| and
+ * copies the launch tables into the workspace (>= smg_batch_workspace_bytes,
+ * 256-byte aligned, caller-owned). */
+int smg_batch_setup(smg_ctx *const *ctxs, int count, double *const *x, const double *const *f,
+                    const int *lanes, void *workspace, size_t workspace_bytes, smg_batch **out);
+
+/* Run refinement steps until every instance has ||f_i - S_i x_i||_2 <=
+ * rtol ||f_i||_2 or has used maxit correction cycles.  stats (host, may be
+ * NULL): count entries; iterations = correction cycles, relres, time_ms =
+ * device time from the start of the call to the step that retired the
+ * instance.  wall_ms (may be NULL): host wall time of the call.  Returns
+ * SMG_NOT_CONVERGED if any instance hit maxit. */
+int smg_batch_solve(smg_batch *batch, double rtol, int maxit, smg_stats *stats, double *wall_ms);
+
+void smg_batch_destroy(smg_batch *batch);
+const char *smg_batch_last_error(const smg_batch *batch);
+
+/* Autotuner of the lanes-per-node width of the batched half-sweep for one
+ * context: times the finest-level red half-sweep for each width W in
+ * {64, 32, 16, 8} (W <= pow2ceil(N), N/W <= 8) with HIP events on the
+ * context's stream.  lanes/us (host, cap entries) receive the candidates and
+ * their average launch time in microseconds, *ncand their number, *best the
+ * fastest width.  Overwrites the context's scratch vectors. */
+int smg_tune_lanes(smg_ctx *ctx, int cap, int *lanes, double *us, int *ncand, int *best);
+
 #ifdef __cplusplus
 }
 #endif

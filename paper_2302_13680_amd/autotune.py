@@ -1,0 +1,39 @@
+"""Autotuner of the batched solver's lanes-per-node width, with a JSON cache.
+
+For every distinct (n, N, precision) among a batch's contexts the library's
+smg_tune_lanes times the finest-level half-sweep for each admissible width
+(64, 32, 16, 8 lanes per node) and the fastest is kept.  Results are cached by
+key "n x N : precision : device name" in a JSON file so that later runs reuse
+them without timing.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import binding
+
+
+def _key(ctx, device_name: str) -> str:
+    prec = "f32" if ctx.precision == binding.SMG_F32 else "f64"
+    return f"{ctx.n}x{ctx.N}:{prec}:{device_name}"
+
+
+def tune(contexts, cache_path: str | None = None, device_name: str = "gfx950"):
+    """Return one lane width per context (tuned or from the cache) and the table."""
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+    lanes = []
+    for ctx in contexts:
+        key = _key(ctx, device_name)
+        if key not in cache:
+            best, table = binding.tune_lanes(ctx)
+            cache[key] = {"best": best, "us": {str(k): v for k, v in table.items()}}
+        lanes.append(int(cache[key]["best"]))
+    if cache_path:
+        os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+        with open(cache_path, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+    return lanes, cache

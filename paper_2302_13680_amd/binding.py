@@ -26,7 +26,8 @@ EXPORTED = [
     "smg_workspace_bytes", "smg_setup", "smg_destroy", "smg_strerror", "smg_last_error",
     "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_smooth", "smg_restrict",
     "smg_prolong_add", "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond",
-    "smg_solve",
+    "smg_solve", "smg_batch_workspace_bytes", "smg_batch_setup", "smg_batch_solve", "smg_batch_destroy",
+    "smg_batch_last_error", "smg_tune_lanes",
 ]
 
 
@@ -88,6 +89,19 @@ def load(path: str = LIB_PATH):
     L.smg_vcycle.argtypes = [vp, vp, vp, i]
     L.smg_gmres_precond.argtypes = [vp, vp, vp, i, d, i, C.POINTER(Stats)]
     L.smg_solve.argtypes = [vp, vp, vp, i, d, i, C.POINTER(Stats)]
+    L.smg_batch_workspace_bytes.restype = C.c_size_t
+    L.smg_batch_workspace_bytes.argtypes = [C.POINTER(vp), i]
+    L.smg_batch_setup.restype = i
+    L.smg_batch_setup.argtypes = [C.POINTER(vp), i, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int), vp,
+                                  C.c_size_t, C.POINTER(vp)]
+    L.smg_batch_solve.restype = i
+    L.smg_batch_solve.argtypes = [vp, d, i, C.POINTER(Stats), C.POINTER(C.c_double)]
+    L.smg_batch_destroy.argtypes = [vp]
+    L.smg_batch_last_error.restype = C.c_char_p
+    L.smg_batch_last_error.argtypes = [vp]
+    L.smg_tune_lanes.restype = i
+    L.smg_tune_lanes.argtypes = [vp, i, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_int),
+                                 C.POINTER(C.c_int)]
     for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_restrict", "smg_prolong_add",
                  "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond", "smg_solve",
                  "smg_num_levels", "smg_level_n"]:
@@ -216,6 +230,67 @@ class Context:
         rc = self._check(self.L.smg_solve(self.ctx, _ptr(x), _ptr(f), method, rtol, maxit, C.byref(st)),
                          allow_nc=True)
         return rc, _stats_dict(st)
+
+
+class Batch:
+    """smg_batch over several Contexts with bound FP64 device vectors x[i], f[i]."""
+
+    def __init__(self, contexts, xs, fs, lanes=None):
+        import torch
+        L = load()
+        self.L = L
+        self.contexts = list(contexts)
+        self.xs, self.fs = list(xs), list(fs)
+        cnt = len(self.contexts)
+        ctxs = (C.c_void_p * cnt)(*[c.ctx for c in self.contexts])
+        nbytes = int(L.smg_batch_workspace_bytes(ctxs, cnt))
+        if nbytes == 0:
+            raise SmgError(-1, "invalid batch")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.contexts[0].device)
+        xp = (C.c_void_p * cnt)(*[_ptr(x).value for x in self.xs])
+        fp = (C.c_void_p * cnt)(*[_ptr(f).value for f in self.fs])
+        lp = (C.c_int * cnt)(*lanes) if lanes is not None else None
+        out = C.c_void_p()
+        rc = L.smg_batch_setup(ctxs, cnt, xp, fp, lp, _ptr(self.workspace), nbytes, C.byref(out))
+        if rc != SMG_OK:
+            raise SmgError(rc, L.smg_strerror(rc).decode())
+        self.batch = out
+        self.lanes = list(lanes) if lanes is not None else None
+
+    def solve(self, rtol=1e-8, maxit=100):
+        cnt = len(self.contexts)
+        st = (Stats * cnt)()
+        wall = C.c_double(0.0)
+        rc = self.L.smg_batch_solve(self.batch, rtol, maxit, st, C.byref(wall))
+        if rc not in (SMG_OK, SMG_NOT_CONVERGED):
+            raise SmgError(rc, self.L.smg_strerror(rc).decode() + ": " +
+                           self.L.smg_batch_last_error(self.batch).decode())
+        return rc, [_stats_dict(s) for s in st], wall.value
+
+    def close(self):
+        if getattr(self, "batch", None):
+            self.L.smg_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune_lanes(ctx):
+    """Time the batched half-sweep of one context for each lane width; returns
+    (best_width, {width: microseconds})."""
+    L = load()
+    lanes = (C.c_int * 8)()
+    us = (C.c_double * 8)()
+    nc = C.c_int(0)
+    best = C.c_int(0)
+    rc = L.smg_tune_lanes(ctx.ctx, 8, lanes, us, C.byref(nc), C.byref(best))
+    if rc != SMG_OK:
+        raise SmgError(rc, L.smg_strerror(rc).decode())
+    return best.value, {lanes[i]: us[i] for i in range(nc.value)}
 
 
 def _stats_dict(st):

@@ -1,0 +1,205 @@
+// batch.h -- batched kernels: one launch runs one phase of the refinement step
+// for many independent instances (different n, N, nu) at once.  A launch is a
+// list of tasks, one per instance, each owning a contiguous range of (logical)
+// blocks; a block finds its task by binary search over the task offsets.
+// Instances whose residual already met the tolerance are retired by a device
+// flag and their blocks exit at once.  The per-node arithmetic is the same
+// device code as the single-instance kernels.
+#pragma once
+#include "coarse.h"
+#include "common.h"
+#include "residual.h"
+#include "smoother.h"
+#include "transfer.h"
+
+namespace smg {
+
+template <typename T>
+struct BTask {
+  int inst;            // instance index (retire flag, statistics)
+  int W;               // lanes per node of this instance
+  int nitems;          // node groups (or samples, or elements) of this task
+  int block0;          // first logical block of the task
+  LevelArgs<T> L;      // level operator
+  T* x;                // level iterate / coarsest solution
+  const T* f;          // level right-hand side
+  T* a;                // phase output: fine residual, coarse right-hand side
+  const T* b;          // phase input: fine residual, coarse correction
+  int m;               // coarsest unknowns per field
+  const double* Ainv;  // coarsest factors (transposed storage) and scratch
+  const double* Sinv;
+  double* ds;
+  const double* c64;   // coarsest diagonal blocks in FP64
+  const double* d64;
+  const double* e64;
+};
+
+// FP64 outer residual of one instance, rounded into the reduced-precision
+// right-hand side of its correction cycle; the task also owns a range of
+// norm partials (one triple per block).
+template <typename TO>
+struct BOuterTask {
+  int inst, W, nitems, block0;
+  LevelArgs<double> L;
+  const double* x;
+  const double* f;
+  TO* out;
+};
+
+template <typename TD>
+struct BAddTask {
+  int inst, block0, nblk;
+  size_t len;
+  double* x;
+  const TD* d;
+};
+
+struct BCheck {
+  int pb0, pnb;        // partial-block range of the instance's outer residual
+  double fnorm;        // ||f|| of the instance
+};
+
+template <typename Task>
+__device__ __forceinline__ int find_task(const Task* __restrict__ tasks, int ntasks, int b) {
+  __shared__ int s_idx;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tasks[mid].block0 <= b) lo = mid; else hi = mid - 1;
+    }
+    s_idx = lo;
+  }
+  __syncthreads();
+  return s_idx;
+}
+
+template <typename T, int JM, int SRC>
+__global__ __launch_bounds__(kBlock) void kb_halfsweep(const BTask<T>* __restrict__ tasks, int ntasks, int colour,
+                                                       const int* __restrict__ done) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const BTask<T>& t = tasks[find_task(tasks, ntasks, b)];
+  if (done[t.inst]) return;
+  const int W = t.W;
+  const int lane = threadIdx.x & (W - 1);
+  const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
+  if (slot >= t.nitems) return;
+  halfsweep_node<T, JM, SRC>(t.L, t.x, t.f, colour, T(1), slot, lane, W, t.b);
+}
+
+// level residual r = f - S x into t.a
+template <typename T, int JM>
+__global__ __launch_bounds__(kBlock) void kb_residual(const BTask<T>* __restrict__ tasks, int ntasks,
+                                                      const int* __restrict__ done) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const BTask<T>& t = tasks[find_task(tasks, ntasks, b)];
+  if (done[t.inst]) return;
+  const int W = t.W;
+  const int lane = threadIdx.x & (W - 1);
+  const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
+  if (slot >= t.nitems) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+  residual_node<T, T, T, JM>(t.L, t.x, t.f, t.a, 0, slot, lane, W, acc);
+}
+
+// coarse right-hand side t.a = R t.b (t.b: fine residual of grid t.L.n)
+template <typename T, int JM>
+__global__ __launch_bounds__(kBlock) void kb_restrict(const BTask<T>* __restrict__ tasks, int ntasks,
+                                                      const int* __restrict__ done) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const BTask<T>& t = tasks[find_task(tasks, ntasks, b)];
+  if (done[t.inst]) return;
+  const int W = t.W;
+  const int lane = threadIdx.x & (W - 1);
+  const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
+  if (slot >= t.nitems) return;
+  restrict_node<T, JM>(t.L.n, t.L.N, t.b, t.a, slot, lane, W);
+}
+
+// coarsest direct solve, one block per (instance, sample)
+template <typename T>
+__global__ __launch_bounds__(64) void kb_coarse1(const BTask<T>* __restrict__ tasks, int ntasks,
+                                                 const int* __restrict__ done) {
+  const int b = blockIdx.x;
+  const BTask<T>& t = tasks[find_task(tasks, ntasks, b)];
+  if (done[t.inst]) return;
+  coarse_phase1_sample<T>(b - t.block0, t.m, t.L.N, t.Ainv, t.c64, t.d64, t.f, t.ds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void kb_coarse2(const BTask<T>* __restrict__ tasks, int ntasks,
+                                                 const int* __restrict__ done) {
+  const int b = blockIdx.x;
+  const BTask<T>& t = tasks[find_task(tasks, ntasks, b)];
+  if (done[t.inst]) return;
+  coarse_phase2_sample<T>(b - t.block0, t.m, t.L.N, t.Ainv, t.Sinv, t.c64, t.e64, t.f, t.ds, t.x);
+}
+
+// FP64 outer residual, rounded into t.out; per-block squared norms into partials.
+template <typename TO, int JM>
+__global__ __launch_bounds__(kBlock) void kb_outer_residual(const BOuterTask<TO>* __restrict__ tasks, int ntasks,
+                                                            const int* __restrict__ done,
+                                                            double* __restrict__ partials) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const BOuterTask<TO>& t = tasks[find_task(tasks, ntasks, b)];
+  if (done[t.inst]) return;
+  const int W = t.W;
+  const int lane = threadIdx.x & (W - 1);
+  const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (slot < t.nitems) residual_node<double, double, TO, JM>(t.L, t.x, t.f, t.out, 0, slot, lane, W, acc);
+  block_sum<3>(acc);
+  if (threadIdx.x == 0) {
+    partials[3 * (size_t)b + 0] = acc[0];
+    partials[3 * (size_t)b + 1] = acc[1];
+    partials[3 * (size_t)b + 2] = acc[2];
+  }
+}
+
+// One block per instance: relative residual from the partials; retire the
+// instance (flag, device wall-clock stamp) once it meets tol, otherwise count
+// the correction cycle this step is about to apply (at most maxit).
+__global__ __launch_bounds__(kBlock) void kb_check(const BCheck* __restrict__ chk, const double* __restrict__ partials,
+                                                   double tol, int maxit, int* __restrict__ done,
+                                                   int* __restrict__ iters, double* __restrict__ relres,
+                                                   long long* __restrict__ tdone) {
+  const int i = blockIdx.x;
+  if (done[i]) return;
+  double acc[1] = {0.0};
+  const BCheck c = chk[i];
+  for (int q = threadIdx.x; q < c.pnb; q += kBlock) {
+    const double* p = partials + 3 * (size_t)(c.pb0 + q);
+    acc[0] += (p[0] + p[1]) + p[2];
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) {
+    const double rel = sqrt(acc[0]) / c.fnorm;
+    relres[i] = rel;
+    if (!(rel > tol)) {            // converged (a NaN also retires: flagged by relres)
+      done[i] = 1;
+      tdone[i] = wall_clock64();
+    } else if (iters[i] >= maxit) {
+      done[i] = 2;                 // iteration limit
+      tdone[i] = wall_clock64();
+    } else {
+      iters[i] += 1;
+    }
+  }
+}
+
+template <typename TD>
+__global__ __launch_bounds__(kBlock) void kb_add(const BAddTask<TD>* __restrict__ tasks, int ntasks,
+                                                 const int* __restrict__ done) {
+  const int b = blockIdx.x;
+  const BAddTask<TD>& t = tasks[find_task(tasks, ntasks, b)];
+  if (done[t.inst]) return;
+  for (size_t i = (size_t)(b - t.block0) * kBlock + threadIdx.x; i < t.len; i += (size_t)t.nblk * kBlock)
+    t.x[i] += (double)t.d[i];
+}
+
+// device wall clock at the start of a batched solve
+__global__ void kb_stamp(long long* __restrict__ t0) {
+  if (threadIdx.x == 0) *t0 = wall_clock64();
+}
+
+}  // namespace smg

@@ -134,12 +134,13 @@ __device__ __forceinline__ double row_dot(const double* __restrict__ MT, int m, 
   return s;
 }
 
+// Phase 1 for sample j (one block of >= m threads).
 template <typename TV>
-__global__ __launch_bounds__(64) void k_coarse_phase1(int m, int N, const double* __restrict__ Ainv,
-                                                      const double* __restrict__ c, const double* __restrict__ d,
-                                                      const TV* __restrict__ F, double* __restrict__ ds) {
+__device__ __forceinline__ void coarse_phase1_sample(int j, int m, int N, const double* __restrict__ Ainv,
+                                                     const double* __restrict__ c, const double* __restrict__ d,
+                                                     const TV* __restrict__ F, double* __restrict__ ds) {
   __shared__ double sF[kMaxCoarse], sT[kMaxCoarse];
-  const int j = blockIdx.x, i = threadIdx.x;
+  const int i = threadIdx.x;
   const double* Aj = Ainv + (size_t)j * m * m;
   const TV* FY = F;
   const TV* FP = F + (size_t)(N + 1) * m;
@@ -150,14 +151,15 @@ __global__ __launch_bounds__(64) void k_coarse_phase1(int m, int N, const double
   if (i < m) ds[(size_t)j * m + i] = d[j] * row_dot(Aj, m, i, sT);
 }
 
+// Phase 2 for sample j (one block of >= m threads); block j = 0 also writes u.
 template <typename TV>
-__global__ __launch_bounds__(64) void k_coarse_phase2(int m, int N, const double* __restrict__ Ainv,
-                                                      const double* __restrict__ Sinv,
-                                                      const double* __restrict__ c, const double* __restrict__ e,
-                                                      const TV* __restrict__ F, const double* __restrict__ ds,
-                                                      TV* __restrict__ X) {
+__device__ __forceinline__ void coarse_phase2_sample(int j, int m, int N, const double* __restrict__ Ainv,
+                                                     const double* __restrict__ Sinv,
+                                                     const double* __restrict__ c, const double* __restrict__ e,
+                                                     const TV* __restrict__ F, const double* __restrict__ ds,
+                                                     TV* __restrict__ X) {
   __shared__ double sR[kMaxCoarse], sU[kMaxCoarse], sT[kMaxCoarse], sY[kMaxCoarse];
-  const int j = blockIdx.x, i = threadIdx.x;
+  const int i = threadIdx.x;
   const double* Aj = Ainv + (size_t)j * m * m;
   const TV* FY = F;
   const TV* FU = F + (size_t)N * m;
@@ -183,6 +185,22 @@ __global__ __launch_bounds__(64) void k_coarse_phase2(int m, int N, const double
     X[(size_t)(N + 1) * m + (size_t)i * N + j] = (TV)p;
     if (j == 0) X[(size_t)N * m + i] = (TV)sU[i];
   }
+}
+
+template <typename TV>
+__global__ __launch_bounds__(64) void k_coarse_phase1(int m, int N, const double* __restrict__ Ainv,
+                                                      const double* __restrict__ c, const double* __restrict__ d,
+                                                      const TV* __restrict__ F, double* __restrict__ ds) {
+  coarse_phase1_sample<TV>(blockIdx.x, m, N, Ainv, c, d, F, ds);
+}
+
+template <typename TV>
+__global__ __launch_bounds__(64) void k_coarse_phase2(int m, int N, const double* __restrict__ Ainv,
+                                                      const double* __restrict__ Sinv,
+                                                      const double* __restrict__ c, const double* __restrict__ e,
+                                                      const TV* __restrict__ F, const double* __restrict__ ds,
+                                                      TV* __restrict__ X) {
+  coarse_phase2_sample<TV>(blockIdx.x, m, N, Ainv, Sinv, c, e, F, ds, X);
 }
 
 }  // namespace smg

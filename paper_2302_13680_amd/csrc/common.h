@@ -47,6 +47,13 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Sum over a group of W lanes (W a power of two <= 64, runtime or constant).
+template <typename T>
+__device__ __forceinline__ T group_sum_w(T v, int W) {
+  for (int off = W >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+  return v;
+}
+
 // Block-wide sum of NV values over BS threads, deterministic order; result valid in thread 0.
 template <int NV, int BS = kBlock>
 __device__ __forceinline__ void block_sum(double (&v)[NV]) {

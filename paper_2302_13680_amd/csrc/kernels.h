@@ -6,3 +6,4 @@
 #include "transfer.h"
 #include "coarse.h"
 #include "krylov.h"
+#include "batch.h"

@@ -4,69 +4,76 @@
 
 namespace smg {
 
-// ---------------------------------------------------------------- residual
-// out = f - S x (mode 0) or out = S x (mode 1) over every node; the block rows
-// are those of eq. (2).  Faces and arithmetic in T, x and f in TX, out in TO.
-// out may be null (norms only).  partials (if not null) receives per block
-// { sum r_Y^2, sum r_U^2, sum r_P^2 }.
+// Residual rows of one node (slot = k n + x) by a group of W lanes:
+// out = f - S x (mode 0) or out = S x (mode 1), block rows of eq. (2):
+//   Y rows: C_j y_j + A_j^T p_j,  U row: G u + sum_j D_j p_j,  P rows: A_j y_j + E_j u.
+// Faces and arithmetic in T, x and f in TX, out in TO (out may be null).
+// acc[0..2] accumulate the squared Y, U (lane 0) and P residual entries.
+template <typename T, typename TX, typename TO, int JM>
+__device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* __restrict__ x,
+                                              const TX* __restrict__ f, TO* __restrict__ out, int mode,
+                                              int slot, int lane, int W, double (&acc)[3]) {
+  const int n = L.n, N = L.N;
+  const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
+  const int k = slot / n, xx = slot - k * n;
+  const size_t node = (size_t)slot;
+  const TX* Y = x;
+  const TX* P = x + (size_t)(N + 1) * nn;
+  const T u = (T)x[(size_t)N * nn + node];
+  const size_t kxb = ((size_t)k * (n + 1) + xx) * N;
+  const size_t kyb = node * N;
+  const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
+  T dsum = 0;
+#pragma unroll
+  for (int q = 0; q < JM; ++q) {
+    const int j = lane + q * W;
+    if (j < N) {
+      const T kw = L.kx[kxb + j], ke = L.kx[kxb + N + j];
+      const T ks = L.ky[kyb + j], kn = L.ky[kyb + rowN + j];
+      const size_t base = node * N + j;
+      const T y0 = (T)Y[base], p0 = (T)P[base];
+      T sy = 0, sp = 0;
+      if (hw) { sy += kw * (T)Y[base - N]; sp += kw * (T)P[base - N]; }
+      if (he) { sy += ke * (T)Y[base + N]; sp += ke * (T)P[base + N]; }
+      if (hs) { sy += ks * (T)Y[base - rowN]; sp += ks * (T)P[base - rowN]; }
+      if (hn) { sy += kn * (T)Y[base + rowN]; sp += kn * (T)P[base + rowN]; }
+      const T a = (kw + ke) + (ks + kn);
+      T rY = L.c[j] * y0 + (a * p0 - sp);     // C_j y_j + A_j^T p_j
+      T rP = (a * y0 - sy) + L.e[j] * u;      // A_j y_j + E_j u
+      dsum += L.d[j] * p0;
+      if (mode == 0) {
+        rY = (T)f[base] - rY;
+        rP = (T)f[(size_t)(N + 1) * nn + base] - rP;
+      }
+      if (out) {
+        out[base] = (TO)rY;
+        out[(size_t)(N + 1) * nn + base] = (TO)rP;
+      }
+      acc[0] += (double)rY * (double)rY;
+      acc[2] += (double)rP * (double)rP;
+    }
+  }
+  dsum = group_sum_w(dsum, W);
+  if (lane == 0) {
+    T rU = L.g * u + dsum;                    // G u + sum_j D_j p_j
+    if (mode == 0) rU = (T)f[(size_t)N * nn + node] - rU;
+    if (out) out[(size_t)N * nn + node] = (TO)rU;
+    acc[1] = (double)rU * (double)rU;
+  }
+}
+
+// out = f - S x (mode 0) or out = S x (mode 1) over every node.  partials (if not
+// null) receives per block { sum r_Y^2, sum r_U^2, sum r_P^2 }.
 template <typename T, typename TX, typename TO, int W, int JM>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelArgs<T> L, const TX* __restrict__ x,
                                                      const TX* __restrict__ f,
                                                      TO* __restrict__ out, int mode,
                                                      double* __restrict__ partials) {
-  const int n = L.n, N = L.N;
-  const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (W - 1);
   const int slot = b * (kBlock / W) + threadIdx.x / W;
   double acc[3] = {0.0, 0.0, 0.0};
-  if (slot < (int)nn) {
-    const int k = slot / n, xx = slot - k * n;
-    const size_t node = (size_t)slot;
-    const TX* Y = x;
-    const TX* P = x + (size_t)(N + 1) * nn;
-    const T u = (T)x[(size_t)N * nn + node];
-    const size_t kxb = ((size_t)k * (n + 1) + xx) * N;
-    const size_t kyb = node * N;
-    const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
-    T dsum = 0;
-#pragma unroll
-    for (int q = 0; q < JM; ++q) {
-      const int j = lane + q * W;
-      if (j < N) {
-        const T kw = L.kx[kxb + j], ke = L.kx[kxb + N + j];
-        const T ks = L.ky[kyb + j], kn = L.ky[kyb + rowN + j];
-        const size_t base = node * N + j;
-        const T y0 = (T)Y[base], p0 = (T)P[base];
-        T sy = 0, sp = 0;
-        if (hw) { sy += kw * (T)Y[base - N]; sp += kw * (T)P[base - N]; }
-        if (he) { sy += ke * (T)Y[base + N]; sp += ke * (T)P[base + N]; }
-        if (hs) { sy += ks * (T)Y[base - rowN]; sp += ks * (T)P[base - rowN]; }
-        if (hn) { sy += kn * (T)Y[base + rowN]; sp += kn * (T)P[base + rowN]; }
-        const T a = (kw + ke) + (ks + kn);
-        T rY = L.c[j] * y0 + (a * p0 - sp);     // C_j y_j + A_j^T p_j
-        T rP = (a * y0 - sy) + L.e[j] * u;      // A_j y_j + E_j u
-        dsum += L.d[j] * p0;
-        if (mode == 0) {
-          rY = (T)f[base] - rY;
-          rP = (T)f[(size_t)(N + 1) * nn + base] - rP;
-        }
-        if (out) {
-          out[base] = (TO)rY;
-          out[(size_t)(N + 1) * nn + base] = (TO)rP;
-        }
-        acc[0] += (double)rY * (double)rY;
-        acc[2] += (double)rP * (double)rP;
-      }
-    }
-    dsum = group_sum<W>(dsum);
-    if (lane == 0) {
-      T rU = L.g * u + dsum;                    // G u + sum_j D_j p_j
-      if (mode == 0) rU = (T)f[(size_t)N * nn + node] - rU;
-      if (out) out[(size_t)N * nn + node] = (TO)rU;
-      acc[1] = (double)rU * (double)rU;
-    }
-  }
+  if (slot < L.n * L.n) residual_node<T, TX, TO, JM>(L, x, f, out, mode, slot, lane, W, acc);
   if (partials) {
     block_sum<3>(acc);
     if (threadIdx.x == 0) {

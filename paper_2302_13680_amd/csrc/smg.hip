@@ -7,6 +7,7 @@
 // V-cycle.  All device memory comes from the caller's workspace, carved here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -618,6 +619,300 @@ int check_level(const smg_ctx* C, int level, int need_coarser) {
 
 }  // namespace
 
+// ============================================================ batched solves
+// Many independent instances advance together: one refinement step of every
+// unretired instance (FP64 outer residual, convergence check, one correction
+// V-cycle from zero, x += correction) is a fixed list of batched launches,
+// each covering one phase for all instances at the same hierarchy depth, and
+// the whole step is captured once into a hipGraph.
+struct smg_batch {
+  std::vector<smg_ctx*> ctx;
+  int count = 0, precision = SMG_F64, jm = 1;
+  hipStream_t stream = nullptr, cap_stream = nullptr;
+  std::string err;
+  std::vector<int> lanes;
+  std::vector<double> fnorm;
+  struct Phase {
+    int kind, colour, src;
+    size_t off;       // byte offset of the task table in the workspace
+    int ntasks, nblocks;
+  };
+  std::vector<Phase> phases;
+  char* base = nullptr;      // workspace
+  int* done = nullptr;
+  int* iters = nullptr;
+  double* relres = nullptr;
+  long long* tdone = nullptr;
+  long long* t0 = nullptr;
+  double* partials = nullptr;
+  BCheck* chk = nullptr;
+  hipGraphExec_t graph = nullptr;   // one refinement step, for (cap_tol, cap_maxit)
+  double cap_tol = -1.0;
+  int cap_maxit = -1;
+  void* host = nullptr;      // pinned staging
+  size_t bytes = 0;
+};
+
+namespace {
+
+enum BPhaseKind { kbOuter, kbCheck, kbSweep, kbResidual, kbRestrict, kbCoarse1, kbCoarse2, kbAdd };
+
+int default_lanes(int N) {
+  int W = 1;
+  while (W < N && W < 64) W <<= 1;
+  return W;
+}
+
+int pow2_ok(int W) { return W >= 1 && W <= 64 && (W & (W - 1)) == 0; }
+
+// Layout of the batch workspace: every task table and the per-instance state.
+// With base == null only sizes are computed.  T is the correction arithmetic.
+template <typename T>
+size_t batch_build(smg_batch* B, double* const* x, const double* const* f, std::vector<char>* blob) {
+  const int cnt = B->count;
+  Level<T>* (*levels)(smg_ctx*) = [](smg_ctx* C) -> Level<T>* {
+    if constexpr (std::is_same<T, double>::value) return C->L64; else return C->L32;
+  };
+  auto x0 = [](smg_ctx* C) -> T* {
+    if constexpr (std::is_same<T, double>::value) return C->w; else return C->L32[0].x;
+  };
+  auto f0 = [](smg_ctx* C) -> T* {
+    if constexpr (std::is_same<T, double>::value) return C->rr; else return C->L32[0].f;
+  };
+  auto r0 = [](smg_ctx* C) -> T* {
+    if constexpr (std::is_same<T, double>::value) return C->r64; else return C->r32;
+  };
+  // level d of instance i (d = 0 is the finest): x, f, operator
+  auto lvl_x = [&](int i, int d) -> T* { return d == 0 ? x0(B->ctx[i]) : levels(B->ctx[i])[d].x; };
+  auto lvl_f = [&](int i, int d) -> T* { return d == 0 ? f0(B->ctx[i]) : levels(B->ctx[i])[d].f; };
+  auto lvl_args = [&](int i, int d) -> LevelArgs<T> { return args(levels(B->ctx[i])[d], B->ctx[i]->N); };
+  int maxD = 0;
+  for (int i = 0; i < cnt; ++i) maxD = std::max(maxD, B->ctx[i]->nlev);
+  B->phases.clear();
+  blob->clear();
+  auto align = [&]() { while (blob->size() % 256) blob->push_back(0); };
+  auto add_phase = [&](int kind, int colour, int src, const void* tasks, size_t tbytes, int ntasks, int nblocks) {
+    align();
+    smg_batch::Phase p{kind, colour, src, blob->size(), ntasks, nblocks};
+    const char* c = (const char*)tasks;
+    blob->insert(blob->end(), c, c + tbytes);
+    B->phases.push_back(p);
+  };
+  auto groups = [&](int i, int items) {
+    const int per = kBlock / B->lanes[i];
+    return (items + per - 1) / per;
+  };
+  // --- outer FP64 residual into the correction right-hand side, with norm partials
+  std::vector<BOuterTask<T>> outer;
+  std::vector<BCheck> chk(cnt);
+  int nb = 0;
+  for (int i = 0; i < cnt; ++i) {
+    smg_ctx* C = B->ctx[i];
+    const int n = C->L64[0].n;
+    BOuterTask<T> t{};
+    t.inst = i; t.W = B->lanes[i]; t.nitems = n * n; t.block0 = nb;
+    t.L = args(C->L64[0], C->N); t.x = x ? x[i] : nullptr; t.f = f ? f[i] : nullptr; t.out = f0(C);
+    const int blocks = groups(i, n * n);
+    chk[i].pb0 = nb; chk[i].pnb = blocks; chk[i].fnorm = 1.0;
+    nb += blocks;
+    outer.push_back(t);
+  }
+  const int outer_blocks = nb;
+  add_phase(kbOuter, 0, 0, outer.data(), sizeof(BOuterTask<T>) * outer.size(), cnt, nb);
+  add_phase(kbCheck, 0, 0, nullptr, 0, cnt, cnt);
+  // --- correction V-cycle from zero, in lockstep by depth
+  auto sweep_phase = [&](int d, int colour, int src, bool down) {
+    std::vector<BTask<T>> ts;
+    int blocks = 0;
+    for (int i = 0; i < cnt; ++i) {
+      if (d >= B->ctx[i]->nlev - 1) continue;
+      BTask<T> t{};
+      t.inst = i; t.W = B->lanes[i]; t.L = lvl_args(i, d);
+      t.nitems = colour_count(t.L.n, colour); t.block0 = blocks;
+      t.x = lvl_x(i, d); t.f = lvl_f(i, d);
+      t.b = src == kProlong ? lvl_x(i, d + 1) : nullptr;
+      blocks += groups(i, t.nitems);
+      ts.push_back(t);
+    }
+    (void)down;
+    if (!ts.empty()) add_phase(kbSweep, colour, src, ts.data(), sizeof(BTask<T>) * ts.size(), (int)ts.size(), blocks);
+  };
+  for (int d = 0; d + 1 < maxD; ++d) {
+    const int pre = B->ctx[0]->desc.pre;
+    sweep_phase(d, 0, kZero, true);
+    sweep_phase(d, 1, kPlain, true);
+    for (int s = 1; s < pre; ++s) { sweep_phase(d, 0, kPlain, true); sweep_phase(d, 1, kPlain, true); }
+    std::vector<BTask<T>> rs, rr;
+    int brs = 0, brr = 0;
+    for (int i = 0; i < cnt; ++i) {
+      if (d >= B->ctx[i]->nlev - 1) continue;
+      BTask<T> t{};
+      t.inst = i; t.W = B->lanes[i]; t.L = lvl_args(i, d);
+      t.x = lvl_x(i, d); t.f = lvl_f(i, d); t.a = r0(B->ctx[i]);
+      t.nitems = t.L.n * t.L.n; t.block0 = brs;
+      brs += groups(i, t.nitems);
+      rs.push_back(t);
+      BTask<T> q{};
+      q.inst = i; q.W = B->lanes[i]; q.L = t.L; q.b = r0(B->ctx[i]); q.a = lvl_f(i, d + 1);
+      const int nc = (t.L.n - 1) / 2;
+      q.nitems = nc * nc; q.block0 = brr;
+      brr += groups(i, q.nitems);
+      rr.push_back(q);
+    }
+    if (!rs.empty()) {
+      add_phase(kbResidual, 0, 0, rs.data(), sizeof(BTask<T>) * rs.size(), (int)rs.size(), brs);
+      add_phase(kbRestrict, 0, 0, rr.data(), sizeof(BTask<T>) * rr.size(), (int)rr.size(), brr);
+    }
+  }
+  {
+    std::vector<BTask<T>> cs;
+    int blocks = 0;
+    for (int i = 0; i < cnt; ++i) {
+      smg_ctx* C = B->ctx[i];
+      const int d = C->nlev - 1;
+      BTask<T> t{};
+      t.inst = i; t.W = B->lanes[i]; t.L = lvl_args(i, d);
+      t.x = lvl_x(i, d); t.f = lvl_f(i, d);
+      t.m = C->m; t.Ainv = C->Ainv; t.Sinv = C->Sinv; t.ds = C->ds;
+      t.c64 = C->L64[d].c; t.d64 = C->L64[d].d; t.e64 = C->L64[d].e;
+      t.nitems = C->N; t.block0 = blocks;
+      blocks += C->N;
+      cs.push_back(t);
+    }
+    add_phase(kbCoarse1, 0, 0, cs.data(), sizeof(BTask<T>) * cs.size(), cnt, blocks);
+    add_phase(kbCoarse2, 0, 0, cs.data(), sizeof(BTask<T>) * cs.size(), cnt, blocks);
+  }
+  for (int d = maxD - 2; d >= 0; --d) {
+    const int post = B->ctx[0]->desc.post;
+    sweep_phase(d, 0, kProlong, false);
+    sweep_phase(d, 1, kPlain, false);
+    for (int s = 1; s < post; ++s) { sweep_phase(d, 0, kPlain, false); sweep_phase(d, 1, kPlain, false); }
+  }
+  {
+    std::vector<BAddTask<T>> as;
+    int blocks = 0;
+    for (int i = 0; i < cnt; ++i) {
+      smg_ctx* C = B->ctx[i];
+      BAddTask<T> t{};
+      t.inst = i; t.block0 = blocks; t.len = C->len0; t.x = x ? x[i] : nullptr; t.d = x0(C);
+      t.nblk = (int)std::min<size_t>((C->len0 + kBlock - 1) / kBlock, 1024);
+      blocks += t.nblk;
+      as.push_back(t);
+    }
+    add_phase(kbAdd, 0, 0, as.data(), sizeof(BAddTask<T>) * as.size(), cnt, blocks);
+  }
+  // per-instance state after the tables
+  align();
+  const size_t st = blob->size();
+  size_t off = st;
+  auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+  const size_t o_done = take(sizeof(int) * cnt), o_iters = take(sizeof(int) * cnt);
+  const size_t o_rel = take(sizeof(double) * cnt), o_td = take(sizeof(long long) * cnt);
+  const size_t o_t0 = take(sizeof(long long)), o_chk = take(sizeof(BCheck) * cnt);
+  // partials sized for the smallest lane width (most blocks)
+  size_t maxpb = 0;
+  for (int i = 0; i < cnt; ++i) maxpb += ((size_t)B->ctx[i]->L64[0].n * B->ctx[i]->L64[0].n + 3) / 4 + 1;
+  const size_t o_part = take(sizeof(double) * 3 * std::max<size_t>(maxpb, (size_t)outer_blocks));
+  if (B->base) {
+    B->done = (int*)(B->base + o_done); B->iters = (int*)(B->base + o_iters);
+    B->relres = (double*)(B->base + o_rel); B->tdone = (long long*)(B->base + o_td);
+    B->t0 = (long long*)(B->base + o_t0); B->chk = (BCheck*)(B->base + o_chk);
+    B->partials = (double*)(B->base + o_part);
+    for (int i = 0; i < cnt; ++i) chk[i].fnorm = B->fnorm[i];
+    // the check table travels with the blob
+    blob->resize(off, 0);
+    memcpy(blob->data() + o_chk, chk.data(), sizeof(BCheck) * cnt);
+  }
+  return off + 256;
+}
+
+template <typename F>
+void jm_dispatch(int jm, F&& fn) {
+  if (jm <= 1) fn(IC<1>{});
+  else if (jm <= 2) fn(IC<2>{});
+  else if (jm <= 4) fn(IC<4>{});
+  else fn(IC<8>{});
+}
+
+#define BHIP(call)                                                           \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      B->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+      return SMG_EHIP;                                                       \
+    }                                                                        \
+  } while (0)
+
+template <typename T>
+int batch_launch_step(smg_batch* B, hipStream_t s, double tol, int maxit) {
+  for (const auto& p : B->phases) {
+    const void* tasks = B->base + p.off;
+    const int nt = p.ntasks, nbk = p.nblocks;
+    switch (p.kind) {
+      case kbOuter:
+        jm_dispatch(B->jm, [&](auto Jc) {
+          constexpr int JM = decltype(Jc)::value;
+          hipLaunchKernelGGL((kb_outer_residual<T, JM>), dim3(nbk), dim3(kBlock), 0, s,
+                             (const BOuterTask<T>*)tasks, nt, (const int*)B->done, B->partials);
+        });
+        break;
+      case kbCheck:
+        hipLaunchKernelGGL(kb_check, dim3(B->count), dim3(kBlock), 0, s, (const BCheck*)B->chk,
+                           (const double*)B->partials, tol, maxit, B->done, B->iters, B->relres, B->tdone);
+        break;
+      case kbSweep:
+        jm_dispatch(B->jm, [&](auto Jc) {
+          constexpr int JM = decltype(Jc)::value;
+          if (p.src == kZero)
+            hipLaunchKernelGGL((kb_halfsweep<T, JM, kZero>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks,
+                               nt, p.colour, (const int*)B->done);
+          else if (p.src == kProlong)
+            hipLaunchKernelGGL((kb_halfsweep<T, JM, kProlong>), dim3(nbk), dim3(kBlock), 0, s,
+                               (const BTask<T>*)tasks, nt, p.colour, (const int*)B->done);
+          else
+            hipLaunchKernelGGL((kb_halfsweep<T, JM, kPlain>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks,
+                               nt, p.colour, (const int*)B->done);
+        });
+        break;
+      case kbResidual:
+        jm_dispatch(B->jm, [&](auto Jc) {
+          constexpr int JM = decltype(Jc)::value;
+          hipLaunchKernelGGL((kb_residual<T, JM>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks, nt,
+                             (const int*)B->done);
+        });
+        break;
+      case kbRestrict:
+        jm_dispatch(B->jm, [&](auto Jc) {
+          constexpr int JM = decltype(Jc)::value;
+          hipLaunchKernelGGL((kb_restrict<T, JM>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks, nt,
+                             (const int*)B->done);
+        });
+        break;
+      case kbCoarse1:
+        hipLaunchKernelGGL((kb_coarse1<T>), dim3(nbk), dim3(64), 0, s, (const BTask<T>*)tasks, nt,
+                           (const int*)B->done);
+        break;
+      case kbCoarse2:
+        hipLaunchKernelGGL((kb_coarse2<T>), dim3(nbk), dim3(64), 0, s, (const BTask<T>*)tasks, nt,
+                           (const int*)B->done);
+        break;
+      case kbAdd:
+        hipLaunchKernelGGL((kb_add<T>), dim3(nbk), dim3(kBlock), 0, s, (const BAddTask<T>*)tasks, nt,
+                           (const int*)B->done);
+        break;
+    }
+    BHIP(hipGetLastError());
+  }
+  return SMG_OK;
+}
+
+int batch_step(smg_batch* B, double tol, int maxit) {
+  if (B->precision == SMG_F32) return batch_launch_step<float>(B, B->stream, tol, maxit);
+  return batch_launch_step<double>(B, B->stream, tol, maxit);
+}
+
+}  // namespace
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -902,6 +1197,229 @@ int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, i
     st->time_ms = now_ms() - t0;
   }
   return rc;
+}
+
+}  // extern "C"
+
+// ================================================================ batch C ABI
+extern "C" {
+
+static int batch_validate(smg_ctx* const* ctxs, int count, const int* lanes, smg_batch* B) {
+  if (!ctxs || count < 1) return SMG_EINVAL;
+  B->count = count;
+  B->ctx.assign(ctxs, ctxs + count);
+  B->lanes.resize(count);
+  B->fnorm.assign(count, 1.0);
+  B->precision = ctxs[0] ? ctxs[0]->desc.precision : 0;
+  B->jm = 1;
+  for (int i = 0; i < count; ++i) {
+    smg_ctx* C = ctxs[i];
+    if (!C) return SMG_EINVAL;
+    if (C->desc.precision != B->precision || C->desc.theta != 1.0 || C->desc.pre < 1 || C->desc.post < 1 ||
+        C->desc.pre != ctxs[0]->desc.pre || C->desc.post != ctxs[0]->desc.post || C->stream != ctxs[0]->stream)
+      return SMG_EINVAL;
+    const int W = lanes ? lanes[i] : default_lanes(C->N);
+    if (!pow2_ok(W) || (C->N + W - 1) / W > 8) return SMG_EINVAL;
+    B->lanes[i] = W;
+    B->jm = std::max(B->jm, (C->N + W - 1) / W);
+  }
+  B->stream = ctxs[0]->stream;
+  return SMG_OK;
+}
+
+size_t smg_batch_workspace_bytes(smg_ctx* const* ctxs, int count) {
+  smg_batch B;
+  if (batch_validate(ctxs, count, nullptr, &B) != SMG_OK) return 0;
+  std::vector<char> blob;
+  return B.precision == SMG_F32 ? batch_build<float>(&B, nullptr, nullptr, &blob)
+                                : batch_build<double>(&B, nullptr, nullptr, &blob);
+}
+
+void smg_batch_destroy(smg_batch* B) {
+  if (!B) return;
+  if (B->graph) (void)hipGraphExecDestroy(B->graph);
+  if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+  if (B->host) (void)hipHostFree(B->host);
+  delete B;
+}
+
+const char* smg_batch_last_error(const smg_batch* B) { return B ? B->err.c_str() : ""; }
+
+int smg_batch_setup(smg_ctx* const* ctxs, int count, double* const* x, const double* const* f, const int* lanes,
+                    void* workspace, size_t workspace_bytes, smg_batch** out) {
+  if (!out) return SMG_EINVAL;
+  *out = nullptr;
+  if (!x || !f) return SMG_EINVAL;
+  smg_batch* B = new smg_batch();
+  int rc = batch_validate(ctxs, count, lanes, B);
+  if (rc != SMG_OK) { delete B; return rc; }
+  for (int i = 0; i < count; ++i)
+    if (!x[i] || !f[i]) { delete B; return SMG_EINVAL; }
+  for (int i = 0; i < count; ++i) {
+    double fn = 0.0;
+    rc = vec_norm(ctxs[i], f[i], ctxs[i]->len0, &fn);
+    if (rc != SMG_OK) { B->err = ctxs[i]->err; smg_batch_destroy(B); return rc; }
+    B->fnorm[i] = fn > 0.0 ? fn : 1.0;
+  }
+  std::vector<char> blob;
+  B->base = (char*)workspace;
+  const size_t need = B->precision == SMG_F32 ? batch_build<float>(B, x, f, &blob)
+                                              : batch_build<double>(B, x, f, &blob);
+  if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255) != 0) {
+    smg_batch_destroy(B);
+    return SMG_EWORKSPACE;
+  }
+  B->bytes = need;
+  if (hipMemcpyAsync(workspace, blob.data(), blob.size(), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+      hipStreamSynchronize(B->stream) != hipSuccess ||
+      hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipHostMalloc(&B->host, (sizeof(int) + sizeof(double) + 2 * sizeof(long long)) * (count + 2),
+                    hipHostMallocDefault) != hipSuccess) {
+    smg_batch_destroy(B);
+    return SMG_EHIP;
+  }
+  *out = B;
+  return SMG_OK;
+}
+
+// Solve every instance to ||f_i - S_i x_i|| <= rtol ||f_i|| (x_i: initial guess
+// in, solution out), at most maxit correction cycles each.  stats (may be null)
+// receives count entries: iterations = correction V-cycles, relres, time_ms =
+// device time from the start of the call to the step that retired the instance.
+// wall_ms (may be null) receives the host wall time of the whole batch.
+int smg_batch_solve(smg_batch* B, double rtol, int maxit, smg_stats* stats, double* wall_ms) {
+  if (!B || !(rtol > 0) || maxit < 1) return SMG_EINVAL;
+  const double t_start = now_ms();
+  const int cnt = B->count;
+  hipStream_t s = B->stream;
+  BHIP(hipMemsetAsync(B->done, 0, sizeof(int) * cnt, s));
+  BHIP(hipMemsetAsync(B->iters, 0, sizeof(int) * cnt, s));
+  hipLaunchKernelGGL(kb_stamp, dim3(1), dim3(64), 0, s, B->t0);
+  BHIP(hipGetLastError());
+  // one refinement step of the whole batch as a graph (captured per tolerance)
+  if (!B->graph || B->cap_tol != rtol || B->cap_maxit != maxit) {
+    if (B->graph) { (void)hipGraphExecDestroy(B->graph); B->graph = nullptr; }
+    BHIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+    const hipStream_t keep = B->stream;
+    B->stream = B->cap_stream;
+    const int rc = batch_step(B, rtol, maxit);
+    B->stream = keep;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
+    if (rc != SMG_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    BHIP(e);
+    const hipError_t ei = hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    BHIP(ei);
+    B->cap_tol = rtol;
+    B->cap_maxit = maxit;
+  }
+  int* hdone = (int*)B->host;
+  int steps = 0;
+  bool all = false;
+  while (!all && steps < maxit + 2) {
+    BHIP(hipGraphLaunch(B->graph, s));
+    ++steps;
+    if (steps % 2 == 0 || steps >= maxit + 2) {
+      BHIP(hipMemcpyAsync(hdone, B->done, sizeof(int) * cnt, hipMemcpyDeviceToHost, s));
+      BHIP(hipStreamSynchronize(s));
+      all = true;
+      for (int i = 0; i < cnt; ++i) all = all && hdone[i] != 0;
+    }
+  }
+  std::vector<int> its(cnt), dn(cnt);
+  std::vector<double> rel(cnt);
+  std::vector<long long> td(cnt);
+  long long t0 = 0;
+  BHIP(hipMemcpyAsync(dn.data(), B->done, sizeof(int) * cnt, hipMemcpyDeviceToHost, s));
+  BHIP(hipMemcpyAsync(its.data(), B->iters, sizeof(int) * cnt, hipMemcpyDeviceToHost, s));
+  BHIP(hipMemcpyAsync(rel.data(), B->relres, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+  BHIP(hipMemcpyAsync(td.data(), B->tdone, sizeof(long long) * cnt, hipMemcpyDeviceToHost, s));
+  BHIP(hipMemcpyAsync(&t0, B->t0, sizeof(long long), hipMemcpyDeviceToHost, s));
+  BHIP(hipStreamSynchronize(s));
+  int dev = 0, khz = 0;
+  BHIP(hipGetDevice(&dev));
+  BHIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  int rc = SMG_OK;
+  for (int i = 0; i < cnt; ++i) {
+    if (dn[i] != 1) rc = SMG_NOT_CONVERGED;
+    if (!std::isfinite(rel[i])) rc = SMG_ENONFINITE;
+    if (stats) {
+      smg_stats* st = &stats[i];
+      st->iterations = its[i];
+      st->inner_iterations = its[i];
+      st->restarts = 0;
+      st->relres = rel[i];
+      st->relres_y = st->relres_u = st->relres_p = NAN;
+      st->time_ms = dn[i] && khz > 0 ? (double)(td[i] - t0) / (double)khz : NAN;
+      st->history_len = 0;
+    }
+  }
+  if (wall_ms) *wall_ms = now_ms() - t_start;
+  return rc;
+}
+
+// Autotuner of the lanes-per-node width of one context's half-sweep: times the
+// finest-level red half-sweep (the batched kernel, one task) for every width
+// W in {64, 32, 16, 8} with W <= pow2ceil(N) and N/W <= 8 samples per lane.
+// lanes/us receive up to `cap` candidates, *ncand their number, *best the
+// fastest width.  Uses the context's correction buffers as scratch.
+int smg_tune_lanes(smg_ctx* C, int cap, int* lanes, double* us, int* ncand, int* best) {
+  if (!C || cap < 1 || !lanes || !us || !ncand || !best) return SMG_EINVAL;
+  const bool f32 = C->desc.precision == SMG_F32;
+  const int N = C->N, top = default_lanes(N);
+  int k = 0;
+  double best_us = 1e300;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipMemsetAsync(C->flag, 0, sizeof(int), C->stream));
+  auto run = [&](auto tag, int W) -> int {
+    using T = decltype(tag);
+    Level<T>* Lp;
+    T* xs;
+    T* fs;
+    if constexpr (std::is_same<T, float>::value) { Lp = &C->L32[0]; xs = C->L32[0].x; fs = C->L32[0].f; }
+    else { Lp = &C->L64[0]; xs = C->w; fs = C->rr; }
+    Level<T>& L = *Lp;
+    TRY(fill<T>(C, xs, C->len0, T(0)));
+    TRY(fill<T>(C, fs, C->len0, T(1)));
+    BTask<T> t{};
+    t.inst = 0; t.W = W; t.L = args(L, N); t.nitems = colour_count(L.n, 0); t.block0 = 0;
+    t.x = xs; t.f = fs;
+    const int per = kBlock / W, nbk = (t.nitems + per - 1) / per;
+    HIP_TRY(hipMemcpyAsync(C->mdp, &t, sizeof(t), hipMemcpyHostToDevice, C->stream));
+    const int jm = (N + W - 1) / W;
+    auto launch = [&]() {
+      jm_dispatch(jm, [&](auto Jc) {
+        constexpr int JM = decltype(Jc)::value;
+        hipLaunchKernelGGL((kb_halfsweep<T, JM, kPlain>), dim3(nbk), dim3(kBlock), 0, C->stream,
+                           (const BTask<T>*)C->mdp, 1, 0, (const int*)C->flag);
+      });
+    };
+    for (int r = 0; r < 3; ++r) launch();
+    HIP_TRY(hipEventRecord(e0, C->stream));
+    const int reps = 20;
+    for (int r = 0; r < reps; ++r) launch();
+    HIP_TRY(hipEventRecord(e1, C->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    LAUNCH_CHECK();
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    const double u = 1e3 * ms / reps;
+    lanes[k] = W; us[k] = u; ++k;
+    if (u < best_us) { best_us = u; *best = W; }
+    return SMG_OK;
+  };
+  for (int W = 64; W >= 8 && k < cap; W >>= 1) {
+    if (W > top || (N + W - 1) / W > 8) continue;
+    const int rc = f32 ? run(float(0), W) : run(double(0), W);
+    if (rc != SMG_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rc; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ncand = k;
+  return k > 0 ? SMG_OK : SMG_EINVAL;
 }
 
 }  // extern "C"

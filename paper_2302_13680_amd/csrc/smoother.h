@@ -1,4 +1,4 @@
-// smoother.h -- collective Gauss-Seidel half-sweep kernels (gfx950).
+// smoother.h -- collective Gauss-Seidel half-sweep (gfx950).
 #pragma once
 #include "common.h"
 
@@ -42,25 +42,23 @@ __device__ __forceinline__ void prolong_nb(const T* __restrict__ e, int nc, int 
   }
 }
 
-// One half-sweep of collective Gauss-Seidel: each node of `colour` is replaced
-// by the solution of its (2N+1)x(2N+1) system (eq. solution_reduced_system)
-// with the opposite-colour neighbours fixed:
+// Half-sweep update of the slot-th node of `colour` by one group of W lanes
+// (lane = index in the group, JM >= ceil(N/W) samples per lane).  The node is
+// replaced by the solution of its (2N+1)x(2N+1) system (eq.
+// solution_reduced_system) with the opposite-colour neighbours fixed:
 //   bP_j = fY_j + sum_nb k_nb p_j,nb      (rhs of the C_j / A_j^T row)
 //   bY_j = fP_j + sum_nb k_nb y_j,nb      (rhs of the A_j / E_j row)
 //   u    = (fU + sum_j d_j (c_j bY_j / a_j^2 - bP_j / a_j)) / (g + sum_j d_j c_j e_j / a_j^2)
 //   y_j  = (bY_j - e_j u) / a_j,   p_j = (bP_j - c_j y_j) / a_j
-// theta != 1 (relaxation) is supported for SRC == kPlain only.
-template <typename T, int W, int JM, int SRC>
-__global__ __launch_bounds__(kBlock) void k_halfsweep(LevelArgs<T> L, T* __restrict__ x,
-                                                      const T* __restrict__ f, int colour,
-                                                      T theta, int nactive,
-                                                      const T* __restrict__ ec) {
+// theta != 1 (relaxation) is supported for SRC == kPlain only; kProlong needs
+// colour 0.  W is a compile-time constant after inlining in the single-instance
+// kernel and a per-instance value in the batched one; the arithmetic is the same.
+template <typename T, int JM, int SRC>
+__device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restrict__ x,
+                                               const T* __restrict__ f, int colour, T theta, int slot,
+                                               int lane, int W, const T* __restrict__ ec) {
   const int n = L.n, N = L.N;
   const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int lane = threadIdx.x & (W - 1);
-  const int slot = b * (kBlock / W) + threadIdx.x / W;
-  if (slot >= nactive) return;  // whole W-lane groups leave together
   int xx, k;
   colour_node(slot, n, colour, xx, k);
   const size_t node = (size_t)k * n + xx;
@@ -94,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_halfsweep(LevelArgs<T> L, T* __restr
         if (hs) { sy += ks * Y[base - rowN]; sp += ks * P[base - rowN]; }
         if (hn) { sy += kn * Y[base + rowN]; sp += kn * P[base + rowN]; }
       }
-      if constexpr (SRC == kProlong) {   // colour 0 only: x + k even
+      if constexpr (SRC == kProlong) {
         T cw, ce, cs, cn;
         prolong_nb(eY, nc, N, j, xx, k, cw, ce, cs, cn);
         sy += (hw ? kw * cw : T(0)) + (he ? ke * ce : T(0)) + (hs ? ks * cs : T(0)) + (hn ? kn * cn : T(0));
@@ -111,8 +109,8 @@ __global__ __launch_bounds__(kBlock) void k_halfsweep(LevelArgs<T> L, T* __restr
       bP[q] = bp; bY[q] = by; ia[q] = ai;
     }
   }
-  num = group_sum<W>(num);
-  den = group_sum<W>(den);
+  num = group_sum_w(num, W);
+  den = group_sum_w(den, W);
   const T un = (fU[node] + num) / (L.g + den);
   const bool relax = SRC == kPlain && theta != T(1);
 #pragma unroll
@@ -131,6 +129,19 @@ __global__ __launch_bounds__(kBlock) void k_halfsweep(LevelArgs<T> L, T* __restr
     }
   }
   if (lane == 0) U[node] = relax ? (T(1) - theta) * U[node] + theta * un : un;
+}
+
+// One half-sweep of collective Gauss-Seidel over every node of `colour`.
+template <typename T, int W, int JM, int SRC>
+__global__ __launch_bounds__(kBlock) void k_halfsweep(LevelArgs<T> L, T* __restrict__ x,
+                                                      const T* __restrict__ f, int colour,
+                                                      T theta, int nactive,
+                                                      const T* __restrict__ ec) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & (W - 1);
+  const int slot = b * (kBlock / W) + threadIdx.x / W;
+  if (slot >= nactive) return;  // whole W-lane groups leave together
+  halfsweep_node<T, JM, SRC>(L, x, f, colour, theta, slot, lane, W, ec);
 }
 
 }  // namespace smg

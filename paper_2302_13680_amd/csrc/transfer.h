@@ -4,18 +4,14 @@
 
 namespace smg {
 
-// ----------------------------------------------------------------- transfers
-// coarse = R fine, R = P^T: coarse node (X, K) sits on fine node (2X+1, 2K+1)
-// and gathers its 3x3 fine neighbourhood with weights w(dx) w(dk).
-template <typename T, int W, int JM>
-__global__ __launch_bounds__(kBlock) void k_restrict(int nf, int N, const T* __restrict__ fine,
-                                                     T* __restrict__ coarse) {
+// coarse = R fine, R = P^T: coarse node (X, K) = slot sits on fine node
+// (2X+1, 2K+1) and gathers its 3x3 fine neighbourhood with weights w(dx) w(dk).
+// One group of W lanes per coarse node.
+template <typename T, int JM>
+__device__ __forceinline__ void restrict_node(int nf, int N, const T* __restrict__ fine,
+                                              T* __restrict__ coarse, int slot, int lane, int W) {
   const int nc = (nf - 1) / 2;
   const size_t nnf = (size_t)nf * nf, nnc = (size_t)nc * nc;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int lane = threadIdx.x & (W - 1);
-  const int slot = b * (kBlock / W) + threadIdx.x / W;
-  if (slot >= (int)nnc) return;
   const int K = slot / nc, X = slot - K * nc;
   const size_t c0 = (size_t)(2 * K + 1) * nf + (2 * X + 1);
   const T* fY = fine;
@@ -48,6 +44,17 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nf, int N, const T* __r
         sU += (T)(lin_w(dx) * lin_w(dk)) * fU[(long)c0 + (long)dk * nf + dx];
     coarse[(size_t)N * nnc + slot] = sU;
   }
+}
+
+template <typename T, int W, int JM>
+__global__ __launch_bounds__(kBlock) void k_restrict(int nf, int N, const T* __restrict__ fine,
+                                                     T* __restrict__ coarse) {
+  const int nc = (nf - 1) / 2;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & (W - 1);
+  const int slot = b * (kBlock / W) + threadIdx.x / W;
+  if (slot >= nc * nc) return;
+  restrict_node<T, JM>(nf, N, fine, coarse, slot, lane, W);
 }
 
 // fine += P coarse, bilinear interpolation gathered per fine node.
