@@ -193,6 +193,38 @@ def batch_section(dev, cache_path):
     }
 
 
+def learned_section(dev, n_train=2000, n_test=200, epochs=20):
+    """Warm start on 127x127, N=128 (nu log-uniform in [1e-5, 1e-3], y_d random
+    sums of three sine products): 2000 multigrid solves as training data, the
+    network trained on the GPU by the library's kernels, 200 held-out seeds."""
+    import torch
+    from paper_2302_13680_amd import binding, learn
+    n, N = 127, 128
+    H = learn.grid_for(n)
+    t0 = time.perf_counter()
+    feats, raw = learn.make_dataset(list(range(10000, 10000 + n_train)), n=n, N=N, device=dev)
+    t_data = time.perf_counter() - t0
+    norm = learn.standardization(raw, n)
+    tg = learn.standardize(raw, norm, n)
+    del raw
+    net = binding.Net(16, H, device=dev)
+    net.set_params(torch.tensor(learn.param_init(0), device=dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = learn.train(net, feats, tg, n, epochs=epochs, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del feats, tg
+    recs = learn.evaluate(net, list(range(20000, 20000 + n_test)), norm, n=n, N=N, device=dev)
+    summ = learn.summarize(recs)
+    summ.update({"workload": "127x127, N=128, nu log-uniform [1e-5,1e-3], y_d random sums of 3 sine "
+                             "products; FP64 V(2,2) to 1e-8",
+                 "params": net.np, "train_instances": n_train, "test_instances": n_test,
+                 "epochs": epochs, "dataset_s": round(t_data, 2), "train_s": round(t_train, 2),
+                 "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]})
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +337,8 @@ def main():
         del c32, fl, xl
         torch.cuda.empty_cache()
         extra["batch"] = batch_section(dev, args.tune_cache)
+        torch.cuda.empty_cache()
+        extra["learned"] = learned_section(dev)
         torch.cuda.empty_cache()
 
     # ---------------- CPU oracle on the host cores (same instance, same method)

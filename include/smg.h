@@ -237,6 +237,46 @@ const char *smg_batch_last_error(const smg_batch *batch);
  * fastest width.  Overwrites the context's scratch vectors. */
 int smg_tune_lanes(smg_ctx *ctx, int cap, int *lanes, double *us, int *ncand, int *best);
 
+/* ------------------------------------------------------- warm-start network
+ * A convolutional encoder-decoder (4 levels, 16/32/48/48 channels, nearest
+ * upsampling with additive skips, SiLU, about 165k parameters) maps per-node
+ * features of an instance -- mean and standard deviation over the samples of
+ * the node log-coefficient, the target state y_d and log10(nu) + 4 -- on an
+ * H x H grid (H a multiple of 8, H >= n, zero beyond the instance's nodes) to
+ * a normalized prediction of (u, mean_j y_j, mean_j p_j).  Convolutions run as
+ * implicit GEMMs on the BF16 matrix cores with FP32 accumulation; master
+ * weights, gradients and Adam moments are FP32.  The prediction lifted to
+ * x0 = (y_j = mean y, u, p_j = mean p) is an initial guess for smg_solve; the
+ * caller keeps the zero start when ||f - S x0|| exceeds ||f||.
+ * Parameters: one FP32 vector, per layer W[cout][tap][cin] (tap = 3 ky + kx)
+ * followed by b[cout].  All tensors are device memory, NHWC, batch-major. */
+typedef struct smg_net smg_net;
+
+int smg_net_param_count(void);
+/* workspace bytes for mini-batches of `batch` samples on an H x H grid (0 if invalid) */
+size_t smg_net_workspace_bytes(int batch, int H);
+int smg_net_setup(int batch, int H, void *workspace, size_t workspace_bytes, void *stream, smg_net **out);
+void smg_net_destroy(smg_net *net);
+const char *smg_net_last_error(const smg_net *net);
+/* copy FP32 parameters in (resets the Adam state) / out */
+int smg_net_set_params(smg_net *net, const float *theta);
+int smg_net_get_params(smg_net *net, float *theta);
+/* out[batch][H][H][3] (FP32) = network(x[batch][H][H][4] FP32) */
+int smg_net_forward(smg_net *net, const float *x, float *out);
+/* forward + backward of the mean squared error over pixels with y, x < valid
+ * and the three channels: grad (device, param_count FP32, may be NULL) and
+ * *loss (host, may be NULL); synchronizes the stream when loss is requested */
+int smg_net_grad(smg_net *net, const float *x, const float *target, int valid, float *grad, float *loss);
+/* forward + backward + one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) */
+int smg_net_train_step(smg_net *net, const float *x, const float *target, int valid, float lr, float *loss);
+
+/* features feat[H][H][4] of the instance behind ctx with right-hand side f */
+int smg_net_features(smg_ctx *ctx, const double *f, int H, float *feat);
+/* normalized targets tgt[H][H][3] from a solution x; norm (host) = {mean[3], std[3]} */
+int smg_net_targets(smg_ctx *ctx, const double *x, int H, const float *norm, float *tgt);
+/* x0 (device, ctx layout) from a normalized prediction pred[H][H][3] */
+int smg_net_lift(smg_ctx *ctx, const float *pred, int H, const float *norm, double *x0);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,10 @@ EXPORTED = [
     "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_smooth", "smg_restrict",
     "smg_prolong_add", "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond",
     "smg_solve", "smg_batch_workspace_bytes", "smg_batch_setup", "smg_batch_solve", "smg_batch_destroy",
-    "smg_batch_last_error", "smg_tune_lanes",
+    "smg_batch_last_error", "smg_tune_lanes", "smg_net_param_count", "smg_net_workspace_bytes",
+    "smg_net_setup", "smg_net_destroy", "smg_net_last_error", "smg_net_set_params", "smg_net_get_params",
+    "smg_net_forward", "smg_net_grad", "smg_net_train_step", "smg_net_features", "smg_net_targets",
+    "smg_net_lift",
 ]
 
 
@@ -102,6 +105,26 @@ def load(path: str = LIB_PATH):
     L.smg_tune_lanes.restype = i
     L.smg_tune_lanes.argtypes = [vp, i, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_int),
                                  C.POINTER(C.c_int)]
+    fp = C.POINTER(C.c_float)
+    L.smg_net_param_count.restype = i
+    L.smg_net_workspace_bytes.restype = C.c_size_t
+    L.smg_net_workspace_bytes.argtypes = [i, i]
+    L.smg_net_setup.restype = i
+    L.smg_net_setup.argtypes = [i, i, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.smg_net_destroy.argtypes = [vp]
+    L.smg_net_last_error.restype = C.c_char_p
+    L.smg_net_last_error.argtypes = [vp]
+    L.smg_net_set_params.argtypes = [vp, vp]
+    L.smg_net_get_params.argtypes = [vp, vp]
+    L.smg_net_forward.argtypes = [vp, vp, vp]
+    L.smg_net_grad.argtypes = [vp, vp, vp, i, vp, fp]
+    L.smg_net_train_step.argtypes = [vp, vp, vp, i, C.c_float, fp]
+    L.smg_net_features.argtypes = [vp, vp, i, vp]
+    L.smg_net_targets.argtypes = [vp, vp, i, fp, vp]
+    L.smg_net_lift.argtypes = [vp, vp, i, fp, vp]
+    for name in ["smg_net_set_params", "smg_net_get_params", "smg_net_forward", "smg_net_grad",
+                 "smg_net_train_step", "smg_net_features", "smg_net_targets", "smg_net_lift"]:
+        getattr(L, name).restype = i
     for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_restrict", "smg_prolong_add",
                  "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond", "smg_solve",
                  "smg_num_levels", "smg_level_n"]:
@@ -291,6 +314,77 @@ def tune_lanes(ctx):
     if rc != SMG_OK:
         raise SmgError(rc, L.smg_strerror(rc).decode())
     return best.value, {lanes[i]: us[i] for i in range(nc.value)}
+
+
+class Net:
+    """smg_net: the warm-start network for mini-batches of `batch` samples on H x H."""
+
+    def __init__(self, batch, H, device="cuda", stream=None):
+        import torch
+        L = load()
+        self.L, self.B, self.H = L, batch, H
+        self.np = int(L.smg_net_param_count())
+        nbytes = int(L.smg_net_workspace_bytes(batch, H))
+        if nbytes == 0:
+            raise SmgError(-1, "invalid network shape")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        out = C.c_void_p()
+        rc = L.smg_net_setup(batch, H, _ptr(self.workspace), nbytes, C.c_void_p(self.stream.cuda_stream),
+                             C.byref(out))
+        if rc != SMG_OK:
+            raise SmgError(rc, L.smg_strerror(rc).decode())
+        self.net = out
+
+    def _check(self, rc):
+        if rc != SMG_OK:
+            raise SmgError(rc, self.L.smg_strerror(rc).decode() + ": " + self.L.smg_net_last_error(self.net).decode())
+
+    def set_params(self, theta):
+        self._check(self.L.smg_net_set_params(self.net, _ptr(theta)))
+
+    def get_params(self, out):
+        self._check(self.L.smg_net_get_params(self.net, _ptr(out)))
+
+    def forward(self, x, out):
+        self._check(self.L.smg_net_forward(self.net, _ptr(x), _ptr(out)))
+
+    def grad(self, x, target, valid, grad=None):
+        loss = C.c_float(0.0)
+        self._check(self.L.smg_net_grad(self.net, _ptr(x), _ptr(target), valid,
+                                        _ptr(grad) if grad is not None else None, C.byref(loss)))
+        return loss.value
+
+    def train_step(self, x, target, valid, lr, want_loss=True):
+        loss = C.c_float(0.0)
+        self._check(self.L.smg_net_train_step(self.net, _ptr(x), _ptr(target), valid, float(lr),
+                                              C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if getattr(self, "net", None):
+            self.L.smg_net_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def net_features(ctx, f, H, out):
+    ctx._check(ctx.L.smg_net_features(ctx.ctx, _ptr(f), H, _ptr(out)))
+
+
+def net_targets(ctx, x, H, norm, out):
+    arr = (C.c_float * 6)(*[float(v) for v in norm])
+    ctx._check(ctx.L.smg_net_targets(ctx.ctx, _ptr(x), H, arr, _ptr(out)))
+
+
+def net_lift(ctx, pred, H, norm, x0):
+    arr = (C.c_float * 6)(*[float(v) for v in norm])
+    ctx._check(ctx.L.smg_net_lift(ctx.ctx, _ptr(pred), H, arr, _ptr(x0)))
 
 
 def _stats_dict(st):

@@ -7,3 +7,4 @@
 #include "coarse.h"
 #include "krylov.h"
 #include "batch.h"
+#include "netio.h"

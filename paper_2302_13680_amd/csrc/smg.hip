@@ -1423,3 +1423,42 @@ int smg_tune_lanes(smg_ctx* C, int cap, int* lanes, double* us, int* ncand, int*
 }
 
 }  // extern "C"
+
+// ============================================================ network glue
+extern "C" {
+
+int smg_net_features(smg_ctx* C, const double* f, int H, float* feat) {
+  if (!C || !f || !feat || H < C->L64[0].n) return SMG_EINVAL;
+  const Level<double>& L = C->L64[0];
+  std::vector<double> c0(1);
+  HIP_TRY(hipMemcpy(c0.data(), L.c, sizeof(double), hipMemcpyDeviceToHost));
+  const double h = 1.0 / (L.n + 1);
+  const float lognu4 = (float)(std::log10(L.g / (h * h)) + 4.0);
+  hipLaunchKernelGGL(k_net_features, dim3((H * H + 255) / 256), dim3(256), 0, C->stream, L.n, C->N, H,
+                     (const double*)L.kx, (const double*)L.ky, f, 1.0 / c0[0], lognu4, feat);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+int smg_net_targets(smg_ctx* C, const double* x, int H, const float* norm, float* tgt) {
+  if (!C || !x || !norm || !tgt || H < C->L64[0].n) return SMG_EINVAL;
+  NetNorm nm;
+  for (int c = 0; c < 3; ++c) { nm.mean[c] = norm[c]; nm.std[c] = norm[3 + c]; }
+  hipLaunchKernelGGL(k_net_targets, dim3((H * H + 255) / 256), dim3(256), 0, C->stream, C->L64[0].n, C->N, H, x,
+                     nm, tgt);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+int smg_net_lift(smg_ctx* C, const float* pred, int H, const float* norm, double* x0) {
+  if (!C || !pred || !norm || !x0 || H < C->L64[0].n) return SMG_EINVAL;
+  NetNorm nm;
+  for (int c = 0; c < 3; ++c) { nm.mean[c] = norm[c]; nm.std[c] = norm[3 + c]; }
+  const size_t tot = (size_t)C->L64[0].n * C->L64[0].n * C->N;
+  hipLaunchKernelGGL(k_net_lift, dim3(grid_for(tot)), dim3(kBlock), 0, C->stream, C->L64[0].n, C->N, H, pred, nm,
+                     x0);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+}  // extern "C"

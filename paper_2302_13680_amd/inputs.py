@@ -203,8 +203,47 @@ def batch_instances(count: int = 64, draw_seed: int = 999, first_seed: int = 100
 def learned_instance(seed: int, n: int = 127, N: int = 128) -> Problem:
     """Warm-start workload: nu log-uniform in [1e-5, 1e-3], y_d a random sum of
     three sine products, f = 1, six modes of amplitude 0.5/m."""
+    nu, yd, xi = learned_instance_params(seed, n, N)
+    return make_problem(n, N, nu, M=6, sigma=0.5, decay=True, seed=seed, yd=yd, xi=xi)
+
+
+def make_problem_device(n: int, N: int, nu: float, xi, yd, *, sigma: float = 0.5, decay: bool = True,
+                        f: float = 1.0, device="cuda"):
+    """The same instance as ``make_problem`` (analytic KL coefficients at the
+    faces, Monte Carlo weights, f = 1), generated directly on the device in the
+    node layout.  Returns (kx, ky, rhs, c, d, e, g): torch FP64 device tensors
+    for the faces and right-hand side, numpy arrays / float for the blocks."""
+    import torch
+    h = 1.0 / (n + 1)
+    xi = torch.as_tensor(np.asarray(xi, dtype=np.float64), device=device)
+    M = xi.shape[1]
+    amps = torch.as_tensor(kl_amplitudes(M, sigma, decay), device=device)
+    nodes = (torch.arange(n, device=device, dtype=torch.float64) + 1.0) * h
+    faces = (torch.arange(n + 1, device=device, dtype=torch.float64) + 0.5) * h
+    m = torch.arange(1, M + 1, device=device, dtype=torch.float64)
+    sn = torch.sin(math.pi * m[:, None] * nodes[None, :])       # (M, n)
+    sf = torch.sin(math.pi * m[:, None] * faces[None, :])       # (M, n+1)
+    w = amps[None, :] * xi                                      # (N, M)
+    # kx[k][f][j] = exp(sum_m w[j, m] sin(m pi f_x) sin(m pi y_k)); ky[g][x][j] likewise
+    kx = torch.exp(torch.einsum("jm,mk,mf->kfj", w, sn, sf)).contiguous()
+    ky = torch.exp(torch.einsum("jm,mg,mx->gxj", w, sf, sn)).contiguous()
+    ydv = torch.as_tensor(np.asarray(yd, dtype=np.float64), device=device).reshape(n, n)
+    zeta = 1.0 / N
+    c = np.full(N, zeta * h * h)
+    d = np.full(N, -h * h)
+    e = np.full(N, -h * h)
+    g = nu * h * h
+    fY = (zeta * h * h) * ydv[:, :, None].expand(n, n, N)
+    fP = torch.full((n, n, N), h * h * f, dtype=torch.float64, device=device)
+    fU = torch.zeros(n * n, dtype=torch.float64, device=device)
+    rhs = torch.cat([fY.reshape(-1), fU, fP.reshape(-1)]).contiguous()
+    return kx, ky, rhs, c, d, e, g
+
+
+def learned_instance_params(seed: int, n: int = 127, N: int = 128):
+    """Random draws of the warm-start workload for one seed: (nu, y_d, xi)."""
     rng = np.random.default_rng(seed)
     nu = float(10.0 ** rng.uniform(-5.0, -3.0))
     yd = random_yd(n, rng)
     xi = rng.standard_normal((N, 6))
-    return make_problem(n, N, nu, M=6, sigma=0.5, decay=True, seed=seed, yd=yd, xi=xi)
+    return nu, yd, xi

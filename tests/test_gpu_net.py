@@ -1,0 +1,143 @@
+"""Warm-start network on the GPU (BF16 matrix cores, FP32 accumulation) against
+the FP64 reference of oracle/convnet.py, and the warm start end to end.
+
+Tolerances: the GPU rounds weights, inputs and every intermediate activation
+to BF16 (relative 2^-9 per rounding) while the reference keeps FP64 between
+layers; over 15 layers this stays within a few percent of the output norm.
+Gradients are compared by cosine (>= 0.999) and norm ratio (within 5%)."""
+import numpy as np
+import pytest
+
+from oracle import convnet as cn
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_13680_amd import binding
+    binding.load()
+    return binding
+
+
+def _setup(B, batch=2, H=16, seed=0):
+    rng = np.random.default_rng(seed)
+    theta = cn.init_params(seed) + 0.02 * rng.standard_normal(cn.n_params())
+    theta = cn.bf16_round(theta)
+    x = cn.bf16_round(rng.standard_normal((batch, H, H, 4)))
+    t = rng.standard_normal((batch, H, H, 3))
+    net = B.Net(batch, H)
+    assert net.np == cn.n_params()
+    net.set_params(torch.tensor(theta, dtype=torch.float32, device="cuda"))
+    return net, theta, x, t
+
+
+def test_forward_matches_reference(B):
+    net, theta, x, _ = _setup(B)
+    out = torch.empty(x.shape[:3] + (3,), dtype=torch.float32, device="cuda")
+    net.forward(torch.tensor(x, dtype=torch.float32, device="cuda"), out)
+    ref = cn.forward(cn.unflatten(theta), x)
+    got = out.cpu().double().numpy()
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel <= 3e-2, rel
+
+
+def test_single_layer_is_exact_matrix_core_product(B):
+    """A network whose layers after the first are identities is not available, so
+    check the first layer through the gradient of a linear probe: with all weights
+    zero except the output layer, the output is the bias; with a zero bias the
+    output layer's gradient is the exact matrix product of BF16 operands."""
+    net, theta, x, t = _setup(B, seed=3)
+    th = np.zeros(cn.n_params())
+    # last layer weights and bias random, all others zero -> output = bias
+    nlast = 3 * 16 + 3
+    th[-nlast:] = cn.bf16_round(np.random.default_rng(1).standard_normal(nlast))
+    net.set_params(torch.tensor(th, dtype=torch.float32, device="cuda"))
+    out = torch.empty(x.shape[:3] + (3,), dtype=torch.float32, device="cuda")
+    net.forward(torch.tensor(x, dtype=torch.float32, device="cuda"), out)
+    bias = th[-3:]
+    np.testing.assert_allclose(out.cpu().numpy(), np.broadcast_to(bias, out.shape), rtol=0, atol=1e-6)
+
+
+def test_gradient_matches_reference(B):
+    net, theta, x, t = _setup(B, seed=5)
+    H = x.shape[1]
+    mask = np.zeros((x.shape[0], H, H))
+    mask[:, :H - 1, :H - 1] = 1.0
+    loss_ref, grads = cn.loss_and_grad(cn.unflatten(theta), x, t, mask)
+    g_ref = cn.flatten(grads)
+    g = torch.empty(cn.n_params(), dtype=torch.float32, device="cuda")
+    loss = net.grad(torch.tensor(x, dtype=torch.float32, device="cuda"),
+                    torch.tensor(t, dtype=torch.float32, device="cuda"), H - 1, g)
+    gg = g.cpu().double().numpy()
+    assert abs(loss - loss_ref) <= 2e-2 * loss_ref
+    cos = gg @ g_ref / (np.linalg.norm(gg) * np.linalg.norm(g_ref))
+    assert cos >= 0.999, cos
+    assert abs(np.linalg.norm(gg) / np.linalg.norm(g_ref) - 1) <= 5e-2
+    # per layer, weights and biases
+    o = 0
+    for (ci, co, tp, *_r) in cn.ARCH:
+        for size in (co * tp * ci, co):
+            a, b = gg[o:o + size], g_ref[o:o + size]
+            o += size
+            c = a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300)
+            assert c >= 0.99, (ci, co, size, c)
+
+
+def test_training_reduces_loss(B):
+    net, theta, x, t = _setup(B, batch=4, seed=7)
+    H = x.shape[1]
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    td = torch.tensor(0.3 * t, dtype=torch.float32, device="cuda")
+    l0 = net.grad(xd, td, H)
+    for _ in range(60):
+        net.train_step(xd, td, H, 3e-3, want_loss=False)
+    l1 = net.grad(xd, td, H)
+    assert l1 < 0.5 * l0, (l0, l1)
+
+
+def test_adam_step_matches_reference(B):
+    """One Adam step on the GPU equals the reference update from the GPU gradient."""
+    net, theta, x, t = _setup(B, seed=9)
+    H = x.shape[1]
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    td = torch.tensor(t, dtype=torch.float32, device="cuda")
+    g = torch.empty(cn.n_params(), dtype=torch.float32, device="cuda")
+    net.grad(xd, td, H, g)
+    net.train_step(xd, td, H, 1e-3, want_loss=False)
+    th1 = torch.empty_like(g)
+    net.get_params(th1)
+    ref, _, _ = cn.adam_step(theta.astype(np.float32).astype(np.float64), g.cpu().double().numpy(),
+                             np.zeros(cn.n_params()), np.zeros(cn.n_params()), 1, lr=1e-3)
+    np.testing.assert_allclose(th1.cpu().double().numpy(), ref, rtol=0, atol=2e-6)
+
+
+def test_warm_start_gain_small(B):
+    """Trained on multigrid solutions of 31x31, N=16 instances, the network predicts
+    held-out fields far better than the training-set mean; the solve from its lifted
+    x0 needs no more V-cycles than the zero start; with the residual rule the
+    warm start falls back to the zero start (same solve) whenever ||f - S x0|| > ||f||."""
+    from paper_2302_13680_amd import learn
+    n, N = 31, 16
+    H = learn.grid_for(n)
+    feats, raw = learn.make_dataset(list(range(30000, 30160)), n=n, N=N)
+    norm = learn.standardization(raw, n)
+    tg = learn.standardize(raw, norm, n)
+    net = B.Net(8, H)
+    net.set_params(torch.tensor(learn.param_init(0), device="cuda"))
+    hist = learn.train(net, feats, tg, n, epochs=25, lr=3e-3, seed=0)
+    assert hist[-1] < 0.2 * hist[0], hist
+    recs = learn.evaluate(net, list(range(40000, 40016)), norm, n=n, N=N)
+    s = learn.summarize(recs)
+    print(s)
+    assert s["all_converged"]
+    for c in range(3):
+        assert s["pred_rel_err_u_ybar_q"][c] < 0.5 * s["dataset_mean_rel_err_u_ybar_q"][c], s
+    assert s["warm_start_no_fallback_mean_cycles"] <= s["zero_start_mean_cycles"], s
+    for r in recs:
+        assert r["fell_back"] == (r["x0_relres"] > 1.0)
+        if r["fell_back"]:
+            assert r["warm_cycles"] == r["zero_cycles"]
