@@ -82,49 +82,105 @@ __global__ __launch_bounds__(kBlock) void k_mdot_finalize(const double* __restri
   if (threadIdx.x == 0) out[i] = accumulate ? out[i] + v[0] : v[0];
 }
 
-// Second Gram-Schmidt pass fused with the update of the first:
-//   w <- w - sum_i h_i V_i   (h = first-pass coefficients, on the device)
-//   partials[b][i] = block sum of V_i * w (new w), slot kMaxBasis = block sum of w^2
-template <typename TV, int KM>
-__global__ __launch_bounds__(kBlock) void k_gs_update_mdot(size_t len, double* __restrict__ w,
-                                                           const TV* __restrict__ V, size_t ldv, int nv,
-                                                           const double* __restrict__ h,
-                                                           double* __restrict__ partials) {
-  double acc[KM + 1], hh[KM];
+// ------------------------------------------- Arnoldi with delayed reorthogonalization
+// One Arnoldi step touches the basis in two passes.  On entry V_0..V_{k-1} are
+// orthonormal, V_k is the previous step's projected vector (scaled to about unit
+// norm, not yet reorthogonalized) and w = S z_k.
+//   dots:   s = V_{<k}^T V_k, b = V_{<k}^T w, c = V_k.V_k, d = V_k.w, e = w.w
+//   update: V_k <- (V_k - V_{<k} s) / alpha              (second projection of V_k)
+//           V_{k+1} <- (w - V_{<k} b - h_kk V_k) / rho    (first projection of w)
+// with alpha^2 = c - |s|^2, h_kk = (d - s.b) / alpha; the host derives alpha,
+// h_kk and rho from the dots between the two passes.
+constexpr int kArnSlots = 2 * kMaxBasis + 4;   // partial slots of the dots pass
+
+template <int KM>
+struct ArnSlots {
+  static constexpr int kC = 2 * KM, kD = 2 * KM + 1, kE = 2 * KM + 2, kCount = 2 * KM + 3;
+};
+
+// partials[b][slot], slots: [0,KM) s_i, [KM,2KM) b_i, then c, d, e (ArnSlots).
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_arnoldi_dots(size_t len, const double* __restrict__ V, size_t ldv,
+                                                         int k, const double* __restrict__ w,
+                                                         double* __restrict__ partials) {
+  using S = ArnSlots<KM>;
+  double acc[S::kCount];
 #pragma unroll
-  for (int i = 0; i <= KM; ++i) acc[i] = 0.0;
-#pragma unroll
-  for (int i = 0; i < KM; ++i) hh[i] = i < nv ? h[i] : 0.0;
+  for (int i = 0; i < S::kCount; ++i) acc[i] = 0.0;
+  const double* __restrict__ vk = V + (size_t)k * ldv;
   for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < len; t += (size_t)gridDim.x * kBlock) {
     double vv[KM];
 #pragma unroll
-    for (int i = 0; i < KM; ++i) vv[i] = i < nv ? (double)V[(size_t)i * ldv + t] : 0.0;
-    double s = w[t];
+    for (int i = 0; i < KM; ++i) vv[i] = i < k ? V[(size_t)i * ldv + t] : 0.0;
+    const double v = vk[t], wv = w[t];
 #pragma unroll
-    for (int i = 0; i < KM; ++i) s -= hh[i] * vv[i];
-    w[t] = s;
-#pragma unroll
-    for (int i = 0; i < KM; ++i) acc[i] += s * vv[i];
-    acc[KM] += s * s;
+    for (int i = 0; i < KM; ++i) {
+      acc[i] += vv[i] * v;
+      acc[KM + i] += vv[i] * wv;
+    }
+    acc[S::kC] += v * v;
+    acc[S::kD] += v * wv;
+    acc[S::kE] += wv * wv;
   }
-  store_block_partials<KM>(acc, nv, 1, partials);
+  __shared__ double red[kBlock / 64][S::kCount];
+  const int lane = threadIdx.x & 63, wvi = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < S::kCount; ++i) {
+    const double s = group_sum<64>(acc[i]);
+    if (lane == 0) red[wvi][i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < S::kCount; i += kBlock) {
+    double s = red[0][i];
+    for (int q = 1; q < kBlock / 64; ++q) s += red[q][i];
+    partials[(size_t)blockIdx.x * kArnSlots + i] = s;
+  }
 }
 
-// Last Gram-Schmidt update fused with the normalization: out = s (w - sum_i h_i V_i).
-template <typename TV, int KM>
-__global__ __launch_bounds__(kBlock) void k_gs_final(size_t len, const double* __restrict__ w,
-                                                     const TV* __restrict__ V, size_t ldv, int nv,
-                                                     const double* __restrict__ h, double* __restrict__ out,
-                                                     double s) {
-  double hh[KM];
-#pragma unroll
-  for (int i = 0; i < KM; ++i) hh[i] = i < nv ? h[i] : 0.0;
+// out[i] = sum_b partials[b][i], one block per slot, fixed order.
+__global__ __launch_bounds__(kBlock) void k_partials_finalize(const double* __restrict__ partials, int nb,
+                                                              int stride, double* __restrict__ out) {
+  const int i = blockIdx.x;
+  double v[1] = {0.0};
+  for (int b = threadIdx.x; b < nb; b += kBlock) v[0] += partials[(size_t)b * stride + i];
+  block_sum<1>(v);
+  if (threadIdx.x == 0) out[i] = v[0];
+}
+
+struct ArnCoef {
+  double s[kMaxBasis];
+  double b[kMaxBasis];
+  double inv_alpha, hkk, inv_rho;
+};
+
+// The update pass.  If norm_partials is not null, partials[b] = block sum of the
+// squared entries of the unscaled new vector (w - V_{<k} b - h_kk V_k).
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_arnoldi_update(size_t len, double* __restrict__ V, size_t ldv, int k,
+                                                           const double* __restrict__ w, ArnCoef cf,
+                                                           double* __restrict__ norm_partials) {
+  double* __restrict__ vk = V + (size_t)k * ldv;
+  double* __restrict__ vn = V + (size_t)(k + 1) * ldv;
+  double acc[1] = {0.0};
   for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < len; t += (size_t)gridDim.x * kBlock) {
-    double v = w[t];
+    double vv[KM];
 #pragma unroll
-    for (int i = 0; i < KM; ++i)
-      if (i < nv) v -= hh[i] * (double)V[(size_t)i * ldv + t];
-    out[t] = v * s;
+    for (int i = 0; i < KM; ++i) vv[i] = i < k ? V[(size_t)i * ldv + t] : 0.0;
+    double v = vk[t], ws = w[t];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {
+      v -= cf.s[i] * vv[i];
+      ws -= cf.b[i] * vv[i];
+    }
+    v *= cf.inv_alpha;
+    ws -= cf.hkk * v;
+    vk[t] = v;
+    vn[t] = ws * cf.inv_rho;
+    acc[0] += ws * ws;
+  }
+  if (norm_partials) {
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) norm_partials[blockIdx.x] = acc[0];
   }
 }
 
@@ -134,19 +190,19 @@ __global__ void k_scale(size_t len, const double* __restrict__ w, double* __rest
     v[t] = w[t] * s;
 }
 
-// x += sum_i y_i Z_i  (y on the device)
+struct BasisCoef {
+  double y[kMaxBasis];
+};
+
+// x += sum_i y_i Z_i
 template <typename TZ, int KM>
 __global__ __launch_bounds__(kBlock) void k_basis_axpy(size_t len, double* __restrict__ x,
-                                                       const TZ* __restrict__ Z, size_t ldz, int nz,
-                                                       const double* __restrict__ y) {
-  double yy[KM];
-#pragma unroll
-  for (int i = 0; i < KM; ++i) yy[i] = i < nz ? y[i] : 0.0;
+                                                       const TZ* __restrict__ Z, size_t ldz, int nz, BasisCoef cf) {
   for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < len; t += (size_t)gridDim.x * kBlock) {
     double s = x[t];
 #pragma unroll
     for (int i = 0; i < KM; ++i)
-      if (i < nz) s += yy[i] * (double)Z[(size_t)i * ldz + t];
+      if (i < nz) s += cf.y[i] * (double)Z[(size_t)i * ldz + t];
     x[t] = s;
   }
 }

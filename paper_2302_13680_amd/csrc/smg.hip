@@ -44,12 +44,17 @@ using IC = std::integral_constant<int, V>;
 
 // lanes per node W and samples per lane JM for N samples
 // compile-time width KM >= nv of the Krylov multi-vector kernels
+// Register width of the multi-vector kernels for nv basis vectors.
+int km_width(int nv) { return nv <= 4 ? 4 : nv <= 8 ? 8 : nv <= 16 ? 16 : 32; }
+
 template <typename F>
 void km_dispatch(int nv, F&& fn) {
-  if (nv <= 4) fn(IC<4>{});
-  else if (nv <= 8) fn(IC<8>{});
-  else if (nv <= 16) fn(IC<16>{});
-  else fn(IC<32>{});
+  switch (km_width(nv)) {
+    case 4: fn(IC<4>{}); break;
+    case 8: fn(IC<8>{}); break;
+    case 16: fn(IC<16>{}); break;
+    default: fn(IC<32>{}); break;
+  }
 }
 
 template <typename F>
@@ -97,7 +102,7 @@ struct smg_ctx {
   double* partials = nullptr;  // [npart][3] per-block squared norms of a residual
   size_t npart = 0;
   double* norms = nullptr;     // [4]
-  double* mdp = nullptr;       // [kPartials][kMaxBasis+1]
+  double* mdp = nullptr;       // [kPartials][kArnSlots] partials of the Krylov reductions
   double* hdev = nullptr;      // [3][kMaxBasis+1]
   int* flag = nullptr;
   double* V = nullptr;         // [(m+1)][len0] Krylov basis
@@ -188,7 +193,7 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
   C->npart = ((size_t)d.n * d.n + 3) / 4 + 1;   // residual blocks hold >= 4 nodes
   C->partials = cv.take<double>(C->npart * 3);
   C->norms = cv.take<double>(4);
-  C->mdp = cv.take<double>((size_t)kPartials * (kMaxBasis + 1));
+  C->mdp = cv.take<double>((size_t)kPartials * kArnSlots);
   C->hdev = cv.take<double>(3 * (kMaxBasis + 1));
   C->flag = cv.take<int>(1);
   C->w = cv.take<double>(len0);
@@ -479,126 +484,172 @@ int precond_and_apply(smg_ctx* C, int k) {
   return SMG_OK;
 }
 
-template <typename TV>
-int mdot(smg_ctx* C, const double* w, const TV* V, int nv, int with_norm, double* out) {
-  const size_t len = C->len0;
-  km_dispatch(nv, [&](auto Kc) {
-    constexpr int KM = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_mdot<TV, KM>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, w, V, len, nv, with_norm,
-                       C->mdp);
-  });
-  LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_mdot_finalize, dim3(kMaxBasis + 1), dim3(kBlock), 0, C->stream, C->mdp, kPartials, nv, with_norm, out, 0);
-  LAUNCH_CHECK();
-  return SMG_OK;
+// Least squares min |g0 e_1 - H y| over the first nc columns of the
+// (m+1) x m upper Hessenberg H (row-major, row stride m), by Givens rotations
+// from scratch.  Returns the residual norm; writes y[0..nc) if y is not null.
+double hessenberg_lsq(const std::vector<double>& H, int m, int nc, double g0, double* y) {
+  std::vector<double> R(H.begin(), H.begin() + (size_t)(nc + 1) * m), g(nc + 1, 0.0), cs(nc), sn(nc);
+  g[0] = g0;
+  for (int j = 0; j < nc; ++j) {
+    for (int i = 0; i < j; ++i) {
+      const double a = R[(size_t)i * m + j], b = R[(size_t)(i + 1) * m + j];
+      R[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+      R[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = R[(size_t)j * m + j], b = R[(size_t)(j + 1) * m + j];
+    const double rr = std::sqrt(a * a + b * b);
+    cs[j] = rr > 0.0 ? a / rr : 1.0;
+    sn[j] = rr > 0.0 ? b / rr : 0.0;
+    R[(size_t)j * m + j] = rr;
+    R[(size_t)(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+  }
+  if (y) {
+    for (int i = nc - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int q = i + 1; q < nc; ++q) s -= R[(size_t)i * m + q] * y[q];
+      y[i] = s / R[(size_t)i * m + i];
+    }
+  }
+  return std::fabs(g[nc]);
 }
 
-// One restart cycle of right-preconditioned (flexible) GMRES with classical
-// Gram-Schmidt applied twice.  On entry C->w holds r0 = f - S x with norm beta.
-// Iterates until the recurrence residual <= target, m steps, or *budget runs
-// out; x += Z y at the end.  Returns its in *its_done and the last recurrence
-// residual in *est.
+// One restart cycle of right-preconditioned (flexible) GMRES.  The Arnoldi
+// process is classical Gram-Schmidt applied twice, with the second projection
+// of each basis vector delayed to the next step, where it shares one pass over
+// the basis with the first projection of the new vector (Hernandez, Roman and
+// Tomas 2007; Bielich et al. 2022): per step one V-cycle, one operator apply,
+// one pass of dot products, one host synchronization and one update pass.  The
+// preconditioner sees each basis vector before its second projection, which
+// flexible GMRES allows (x += Z y with A Z = V H holds for any Z).  The
+// provisional subdiagonal |w'| of a step is replaced by the exact norm after the
+// second projection in the next step, and the least-squares problem is
+// re-solved from scratch each step.
+// On entry C->w holds r0 = f - S x with norm beta.  Iterates until the
+// recurrence residual <= target, m steps, or *budget runs out; x += Z y at the
+// end.  Returns its in *its_done and the last recurrence residual in *est.
 int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int budget, int* its_done,
                 double* est, smg_stats* st, double fn) {
   const size_t len = C->len0;
-  const int K1 = kMaxBasis + 1;
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), y(m);
-  g[0] = beta;
-  // V_0 = r0 / beta
+  std::vector<double> H((size_t)(m + 1) * m, 0.0);
+  // V_0 = r0 / beta; r0 = g0 V_0 after V_0's second projection (normalization)
   hipLaunchKernelGGL(k_scale, dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, (const double*)C->w, C->V,
                      1.0 / beta);
   LAUNCH_CHECK();
+  double g0 = beta, rho = 1.0;   // V_k as stored = (projected vector) / rho
   int k = 0, done = 0;
   double res = beta;
   for (; k < m && done < budget; ++k) {
     TRY(precond_and_apply(C, k));
-    // Classical Gram-Schmidt with selective reorthogonalization (Daniel, Gragg,
-    // Kaufman, Stewart 1976, "twice is enough"):
-    //   A: h1 = V^T w and ||w||^2                                  (one pass)
-    //   if ||w - V h1|| > ||w|| / sqrt(2): accept h1
-    //   else B: w <- w - V h1 with h2 = V^T w and ||w||^2           (one pass)
-    //   C: v_{k+1} = (w - V h) / h_{k+1,k}                         (one pass)
-    // where h_{k+1,k}^2 = ||w||^2 - ||h||^2 for the last projection h.
-    TRY(mdot<double>(C, C->w, C->V, k + 1, 1, C->hdev));
-    HIP_TRY(hipMemcpyAsync(C->host, C->hdev, sizeof(double) * K1, hipMemcpyDeviceToHost, C->stream));
+    const int KMv = km_width(k);
+    const int nslots = 2 * KMv + 3;
+    km_dispatch(k, [&](auto Kc) {
+      constexpr int KM = decltype(Kc)::value;
+      hipLaunchKernelGGL((k_arnoldi_dots<KM>), dim3(kPartials), dim3(kBlock), 0, C->stream, len,
+                         (const double*)C->V, len, k, (const double*)C->w, C->mdp);
+    });
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_partials_finalize, dim3(nslots), dim3(kBlock), 0, C->stream, (const double*)C->mdp,
+                       kPartials, kArnSlots, C->hdev);
+    LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(C->host, C->hdev, sizeof(double) * nslots, hipMemcpyDeviceToHost, C->stream));
     TRY(sync(C));
-    double h1sq = 0.0;
-    for (int i = 0; i <= k; ++i) {
-      H[(size_t)i * m + k] = C->host[i];
-      h1sq += C->host[i] * C->host[i];
+    const double* s = C->host;
+    const double* b = C->host + KMv;
+    const double c = C->host[2 * KMv], d = C->host[2 * KMv + 1], e = C->host[2 * KMv + 2];
+    double ss = 0.0, sb = 0.0, bb = 0.0;
+    for (int i = 0; i < k; ++i) {
+      ss += s[i] * s[i];
+      sb += s[i] * b[i];
+      bb += b[i] * b[i];
     }
-    const double w0sq = C->host[kMaxBasis];
-    double wsq = w0sq - h1sq;
-    const double* hlast = C->hdev;
-    if (!(wsq > 0.5 * w0sq)) {
-      km_dispatch(k + 1, [&](auto Kc) {
+    const double a2 = c - ss;
+    if (!std::isfinite(a2) || !std::isfinite(d) || !std::isfinite(e)) {
+      C->err = "non-finite Arnoldi coefficients";
+      return SMG_ENONFINITE;
+    }
+    if (!(a2 > 0.0)) {
+      // V_k lies in the span of V_{<k}: the Krylov space is invariant and the
+      // previous step's solution is exact.
+      if (k > 0) H[(size_t)k * m + k - 1] = 0.0;
+      break;
+    }
+    const double alpha = std::sqrt(a2);
+    if (k == 0) {
+      g0 = beta * alpha;
+    } else {
+      for (int i = 0; i < k; ++i) H[(size_t)i * m + k - 1] += rho * s[i];
+      H[(size_t)k * m + k - 1] = rho * alpha;
+    }
+    const double hkk = (d - sb) / alpha;
+    for (int i = 0; i < k; ++i) H[(size_t)i * m + k] = b[i];
+    H[(size_t)k * m + k] = hkk;
+    ArnCoef cf;
+    for (int i = 0; i < kMaxBasis; ++i) {
+      cf.s[i] = i < k ? s[i] : 0.0;
+      cf.b[i] = i < k ? b[i] : 0.0;
+    }
+    cf.inv_alpha = 1.0 / alpha;
+    cf.hkk = hkk;
+    // |w'|^2 from the dots; trusted unless cancellation takes more than four digits
+    const double wn2 = e - bb - hkk * hkk;
+    const bool estimated = wn2 > 1e-4 * e;
+    double hn;
+    bool updated = false;
+    if (estimated) {
+      hn = std::sqrt(wn2);
+    } else {
+      cf.inv_rho = 1.0;
+      km_dispatch(k, [&](auto Kc) {
         constexpr int KM = decltype(Kc)::value;
-        hipLaunchKernelGGL((k_gs_update_mdot<double, KM>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, C->w,
-                           (const double*)C->V, len, k + 1, (const double*)C->hdev, C->mdp);
+        hipLaunchKernelGGL((k_arnoldi_update<KM>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, C->V, len, k,
+                           (const double*)C->w, cf, C->mdp);
       });
       LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_mdot_finalize, dim3(kMaxBasis + 1), dim3(kBlock), 0, C->stream, (const double*)C->mdp,
-                         kPartials, k + 1, 1, C->hdev + K1, 0);
+      hipLaunchKernelGGL(k_partials_finalize, dim3(1), dim3(kBlock), 0, C->stream, (const double*)C->mdp, kPartials,
+                         1, C->hdev);
       LAUNCH_CHECK();
-      HIP_TRY(hipMemcpyAsync(C->host + K1, C->hdev + K1, sizeof(double) * K1, hipMemcpyDeviceToHost, C->stream));
+      HIP_TRY(hipMemcpyAsync(C->host, C->hdev, sizeof(double), hipMemcpyDeviceToHost, C->stream));
       TRY(sync(C));
-      double h2sq = 0.0;
-      for (int i = 0; i <= k; ++i) {
-        H[(size_t)i * m + k] += C->host[K1 + i];
-        h2sq += C->host[K1 + i] * C->host[K1 + i];
-      }
-      wsq = C->host[K1 + kMaxBasis] - h2sq;
-      hlast = C->hdev + K1;
+      hn = std::sqrt(std::max(C->host[0], 0.0));
+      updated = true;
     }
-    if (!(wsq > 0.0)) wsq = 0.0;
-    const double hn = std::sqrt(wsq);
-    if (!std::isfinite(hn) || !std::isfinite(H[(size_t)k * m + k])) {
+    if (!std::isfinite(hn) || !std::isfinite(hkk)) {
       C->err = "non-finite Arnoldi coefficients";
       return SMG_ENONFINITE;
     }
     H[(size_t)(k + 1) * m + k] = hn;
-    if (hn > 0.0) {
-      km_dispatch(k + 1, [&](auto Kc) {
-        constexpr int KM = decltype(Kc)::value;
-        hipLaunchKernelGGL((k_gs_final<double, KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len,
-                           (const double*)C->w, (const double*)C->V, len, k + 1, hlast,
-                           C->V + (size_t)(k + 1) * len, 1.0 / hn);
-      });
-      LAUNCH_CHECK();
-    }
-    for (int i = 0; i < k; ++i) {
-      const double a = H[(size_t)i * m + k], b = H[(size_t)(i + 1) * m + k];
-      H[(size_t)i * m + k] = cs[i] * a + sn[i] * b;
-      H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * b;
-    }
-    const double a = H[(size_t)k * m + k], b = H[(size_t)(k + 1) * m + k];
-    const double rr = std::sqrt(a * a + b * b);
-    cs[k] = a / rr; sn[k] = b / rr;
-    H[(size_t)k * m + k] = rr; H[(size_t)(k + 1) * m + k] = 0.0;
-    g[k + 1] = -sn[k] * g[k];
-    g[k] = cs[k] * g[k];
-    res = std::fabs(g[k + 1]);
+    res = hessenberg_lsq(H, m, k + 1, g0, nullptr);
     ++done;
     stats_push(st, res / fn);
-    if (res <= target || hn == 0.0) { ++k; break; }
+    if (res <= target || hn == 0.0 || k + 1 == m || done == budget) { ++k; break; }
+    if (!updated) {
+      cf.inv_rho = 1.0 / hn;
+      km_dispatch(k, [&](auto Kc) {
+        constexpr int KM = decltype(Kc)::value;
+        hipLaunchKernelGGL((k_arnoldi_update<KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, C->V, len,
+                           k, (const double*)C->w, cf, (double*)nullptr);
+      });
+      LAUNCH_CHECK();
+      rho = hn;
+    } else {
+      rho = 1.0;
+    }
   }
   const int kend = k;
-  for (int i = kend - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int q = i + 1; q < kend; ++q) s -= H[(size_t)i * m + q] * y[q];
-    y[i] = s / H[(size_t)i * m + i];
-  }
   if (kend > 0) {
-    for (int i = 0; i < kend; ++i) C->host[i] = y[i];
-    HIP_TRY(hipMemcpyAsync(C->hdev, C->host, sizeof(double) * kend, hipMemcpyHostToDevice, C->stream));
+    BasisCoef y;
+    for (int i = 0; i < kMaxBasis; ++i) y.y[i] = 0.0;
+    hessenberg_lsq(H, m, kend, g0, y.y);
     km_dispatch(kend, [&](auto Kc) {
       constexpr int KM = decltype(Kc)::value;
       if (C->desc.precision == SMG_F64)
         hipLaunchKernelGGL((k_basis_axpy<double, KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x,
-                           (const double*)C->Z64, len, kend, (const double*)C->hdev);
+                           (const double*)C->Z64, len, kend, y);
       else
         hipLaunchKernelGGL((k_basis_axpy<float, KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x,
-                           (const float*)C->Z32, len, kend, (const double*)C->hdev);
+                           (const float*)C->Z32, len, kend, y);
     });
     LAUNCH_CHECK();
   }
