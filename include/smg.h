@@ -89,6 +89,10 @@ typedef struct {
   int precision;      /* SMG_F64 or SMG_F32 */
   int gmres_restart;  /* basis size m reserved for GMRES (0 = no Krylov storage) */
   int flags;          /* SMG_FLAG_* bits */
+  int strip;          /* smoother traversal: vertical strips of this many columns (even), each
+                         visited row by row, so that values shared by neighbouring rows are
+                         reused from L2; 0 or >= n = row-major order.  Any value gives the
+                         same iterates (a half-sweep updates one colour from the other). */
 } smg_desc;
 
 /* flags */

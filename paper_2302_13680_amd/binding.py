@@ -37,7 +37,7 @@ EXPORTED = [
 class Desc(C.Structure):
     _fields_ = [("n", C.c_int), ("nsamples", C.c_int), ("coarsest_n", C.c_int), ("pre", C.c_int),
                 ("post", C.c_int), ("theta", C.c_double), ("precision", C.c_int),
-                ("gmres_restart", C.c_int), ("flags", C.c_int)]
+                ("gmres_restart", C.c_int), ("flags", C.c_int), ("strip", C.c_int)]
 
 
 class Blocks(C.Structure):
@@ -140,9 +140,9 @@ def _ptr(t):
 
 
 def workspace_bytes(n, N, coarsest_n=7, pre=2, post=2, theta=1.0, precision=SMG_F64, gmres_restart=30,
-                    flags=0):
+                    flags=0, strip=0):
     L = load()
-    desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart, flags)
+    desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart, flags, strip)
     return int(L.smg_workspace_bytes(C.byref(desc)))
 
 
@@ -154,14 +154,14 @@ class Context:
     """
 
     def __init__(self, n, N, kx, ky, c, d, e, g, *, coarsest_n=7, pre=2, post=2, theta=1.0,
-                 precision=SMG_F64, gmres_restart=30, flags=0, stream=None):
+                 precision=SMG_F64, gmres_restart=30, flags=0, strip=0, stream=None):
         import torch
         L = load()
         self.L = L
         self.n, self.N = n, N
         self.precision = precision
         self.device = kx.device
-        self.desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart, flags)
+        self.desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart, flags, strip)
         nbytes = int(L.smg_workspace_bytes(C.byref(self.desc)))
         if nbytes == 0:
             raise SmgError(-1, "invalid descriptor")

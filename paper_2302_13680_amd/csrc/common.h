@@ -29,6 +29,7 @@ struct LevelArgs {
   const T* __restrict__ d;
   const T* __restrict__ e;
   T g;
+  int strip;   // columns per strip of the colour traversal (colour_node)
 };
 
 // MI355X dispatches workgroup b to XCD b % 8.  Remap so that every XCD works on
@@ -77,12 +78,25 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
 }
 
 // Node (x, k) of the slot-th node of colour `colour` ((x + k) % 2 == colour),
-// n odd, row-major order.  A pair of rows holds n nodes of each colour.
-__device__ __forceinline__ void colour_node(int slot, int n, int colour, int& x, int& k) {
-  const int pr = slot / n, rem = slot - pr * n;
-  const int c0 = (n - colour + 1) >> 1;  // nodes of this colour on the even row of the pair
-  if (rem < c0) { k = 2 * pr; x = colour + 2 * rem; }
-  else { k = 2 * pr + 1; x = (1 - colour) + 2 * (rem - c0); }
+// n odd.  The grid is cut into vertical strips of S columns (S even; S >= n is
+// plain row-major order) and each strip is traversed row by row, strips one
+// after another.  Rows above and below a node are then visited soon after it
+// within a strip, so opposite-colour values shared between neighbouring rows are
+// read again while still in L2.  In a strip of width w a pair of rows (even k
+// first) holds w nodes of each colour.
+__host__ __device__ inline void colour_node(int slot, int n, int colour, int S, int& x, int& k) {
+  int x0 = 0, w = n, l = slot;
+  if (S < n) {
+    const int per = n * (S >> 1);   // nodes of either colour in a full strip
+    const int s = slot / per;
+    x0 = s * S;
+    w = n - x0 < S ? n - x0 : S;
+    l = slot - s * per;
+  }
+  const int pr = l / w, rem = l - pr * w;
+  const int c0 = (w - colour + 1) >> 1;  // nodes of this colour on the even row of the pair
+  if (rem < c0) { k = 2 * pr; x = x0 + colour + 2 * rem; }
+  else { k = 2 * pr + 1; x = x0 + (1 - colour) + 2 * (rem - c0); }
 }
 
 // Weights of 1D linear interpolation: 1 at the coinciding node, 1/2 next to it.

@@ -60,7 +60,7 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
   const int n = L.n, N = L.N;
   const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
   int xx, k;
-  colour_node(slot, n, colour, xx, k);
+  colour_node(slot, n, colour, L.strip, xx, k);
   const size_t node = (size_t)k * n + xx;
   T* __restrict__ Y = x;
   T* __restrict__ U = x + (size_t)N * nn;

@@ -90,6 +90,27 @@ def test_halfsweeps(B, O, n, N, theta):
         assert rel(node_to_paper(host(xd), n, N), x) <= 1e-13, colour
 
 
+@pytest.mark.parametrize("n,N", [(63, 16), (31, 100), (127, 64)])
+@pytest.mark.parametrize("strip", [2, 8, 30])
+def test_halfsweeps_strip_order(B, O, n, N, strip):
+    """The strip traversal visits the nodes of a colour in another order; a
+    half-sweep reads only the other colour, so the iterates are bitwise those of
+    row-major order, and match the oracle."""
+    p = mk(n, N, seed=n + strip)
+    o = O.Oracle(p, coarsest_n=7)
+    c_row, f = B.context_from_problem(p, gmres_restart=0, strip=n + 1)
+    c_str, _ = B.context_from_problem(p, gmres_restart=0, strip=strip)
+    x = np.random.default_rng(4).standard_normal(o.vlen())
+    fp = p.rhs_paper()
+    xa, xb = dev(paper_to_node(x, n, N)), dev(paper_to_node(x, n, N))
+    for colour in (0, 1, 0, 1):
+        x = o.halfsweep(x, fp, colour)
+        c_row.smooth(0, colour, xa, f)
+        c_str.smooth(0, colour, xb, f)
+        assert torch.equal(xa, xb), colour
+        assert rel(node_to_paper(host(xb), n, N), x) <= 1e-13, colour
+
+
 @pytest.mark.parametrize("n,N", [(31, 8), (63, 16), (31, 100)])
 def test_hierarchy_faces_bit_exact(B, O, n, N):
     p = mk(n, N, seed=5)
