@@ -5,9 +5,9 @@
 // A node's N samples are contiguous, so a group of W lanes of one wavefront
 // (W = 1..64, a power of two) holds one node and each lane handles JM samples
 // j = lane, lane + W, ...; the reductions over samples that the node solve and
-// the control row need are butterfly shuffles inside that group.  Every lane
-// of a group ends with the bitwise-same sum (IEEE addition is commutative), so
-// all lanes agree on u_i.
+// the control row need stay inside that group (DPP lane moves and reads of row
+// sums, group_sum).  Every lane of a group ends with the bitwise-same sum (IEEE
+// addition is commutative), so all lanes agree on u_i.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -41,18 +41,62 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Move a value between lanes of a row of 16 lanes with DPP (CTRL: 0xB1 = xor 1
+// and 0x4E = xor 2 inside quads, 0x141 = mirror inside 8 lanes, 0x140 = mirror
+// inside 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Sum over aligned groups of W lanes (W a power of two <= 64); every lane of a
+// group gets the bitwise-same sum (each step adds two values that the partner
+// lane adds in the other order).  Within a 16-lane row the partners come by DPP:
+// xor 1 and xor 2 inside quads, then the 8-lane and 16-lane mirrors, each of
+// which pairs a lane with one in the other half of its block.  Groups of 32 and
+// 64 lanes add the row sums read from lanes 0, 16, 32, 48.  Lanes of other
+// groups are never read into a group's sum, so groups of a wave may be inactive.
 template <int W, typename T>
 __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+  if constexpr (W >= 2) v += dpp_move<0xB1>(v);
+  if constexpr (W >= 4) v += dpp_move<0x4E>(v);
+  if constexpr (W >= 8) v += dpp_move<0x141>(v);
+  if constexpr (W >= 16) v += dpp_move<0x140>(v);
+  if constexpr (W == 32) {
+    const T r0 = lane_value(v, 0), r1 = lane_value(v, 16), r2 = lane_value(v, 32), r3 = lane_value(v, 48);
+    v = (__lane_id() & 32) ? r2 + r3 : r0 + r1;
+  } else if constexpr (W == 64) {
+    const T r0 = lane_value(v, 0), r1 = lane_value(v, 16), r2 = lane_value(v, 32), r3 = lane_value(v, 48);
+    v = (r0 + r1) + (r2 + r3);
+  }
   return v;
 }
 
-// Sum over a group of W lanes (W a power of two <= 64, runtime or constant).
+// group_sum for a group width known at run time (uniform across the wave).
 template <typename T>
 __device__ __forceinline__ T group_sum_w(T v, int W) {
-  for (int off = W >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
-  return v;
+  switch (W) {
+    case 1: return v;
+    case 2: return group_sum<2>(v);
+    case 4: return group_sum<4>(v);
+    case 8: return group_sum<8>(v);
+    case 16: return group_sum<16>(v);
+    case 32: return group_sum<32>(v);
+    default: return group_sum<64>(v);
+  }
 }
 
 // Block-wide sum of NV values over BS threads, deterministic order; result valid in thread 0.
