@@ -23,28 +23,34 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
   const size_t kxb = ((size_t)k * (n + 1) + xx) * N;
   const size_t kyb = node * N;
   const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
+  // Unconditional loads: a missing neighbour reads the node itself and a sample
+  // j >= N reads sample N-1; both are selected away (see halfsweep_node).
+  const ptrdiff_t ow = hw ? -(ptrdiff_t)N : 0, oe = he ? (ptrdiff_t)N : 0;
+  const ptrdiff_t os = hs ? -(ptrdiff_t)rowN : 0, on = hn ? (ptrdiff_t)rowN : 0;
   T dsum = 0;
 #pragma unroll
   for (int q = 0; q < JM; ++q) {
-    const int j = lane + q * W;
-    if (j < N) {
-      const T kw = L.kx[kxb + j], ke = L.kx[kxb + N + j];
-      const T ks = L.ky[kyb + j], kn = L.ky[kyb + rowN + j];
-      const size_t base = node * N + j;
-      const T y0 = (T)Y[base], p0 = (T)P[base];
-      T sy = 0, sp = 0;
-      if (hw) { sy += kw * (T)Y[base - N]; sp += kw * (T)P[base - N]; }
-      if (he) { sy += ke * (T)Y[base + N]; sp += ke * (T)P[base + N]; }
-      if (hs) { sy += ks * (T)Y[base - rowN]; sp += ks * (T)P[base - rowN]; }
-      if (hn) { sy += kn * (T)Y[base + rowN]; sp += kn * (T)P[base + rowN]; }
-      const T a = (kw + ke) + (ks + kn);
-      T rY = L.c[j] * y0 + (a * p0 - sp);     // C_j y_j + A_j^T p_j
-      T rP = (a * y0 - sy) + L.e[j] * u;      // A_j y_j + E_j u
-      dsum += L.d[j] * p0;
-      if (mode == 0) {
-        rY = (T)f[base] - rY;
-        rP = (T)f[(size_t)(N + 1) * nn + base] - rP;
-      }
+    const int j0 = lane + q * W;
+    const bool act = j0 < N;
+    const int j = act ? j0 : N - 1;
+    const T kw = L.kx[kxb + j], ke = L.kx[kxb + N + j];
+    const T ks = L.ky[kyb + j], kn = L.ky[kyb + rowN + j];
+    const size_t base = node * N + j;
+    const T y0 = (T)Y[base], p0 = (T)P[base];
+    auto nbsum = [&](T vw, T ve, T vs, T vn) -> T {
+      return ((hw ? kw * vw : T(0)) + (he ? ke * ve : T(0))) + ((hs ? ks * vs : T(0)) + (hn ? kn * vn : T(0)));
+    };
+    const T sy = nbsum((T)Y[base + ow], (T)Y[base + oe], (T)Y[base + os], (T)Y[base + on]);
+    const T sp = nbsum((T)P[base + ow], (T)P[base + oe], (T)P[base + os], (T)P[base + on]);
+    const T a = (kw + ke) + (ks + kn);
+    T rY = L.c[j] * y0 + (a * p0 - sp);     // C_j y_j + A_j^T p_j
+    T rP = (a * y0 - sy) + L.e[j] * u;      // A_j y_j + E_j u
+    dsum += act ? L.d[j] * p0 : T(0);
+    if (mode == 0) {
+      rY = (T)f[base] - rY;
+      rP = (T)f[(size_t)(N + 1) * nn + base] - rP;
+    }
+    if (act) {
       if (out) {
         out[base] = (TO)rY;
         out[(size_t)(N + 1) * nn + base] = (TO)rP;
@@ -65,7 +71,8 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
 // out = f - S x (mode 0) or out = S x (mode 1) over every node.  partials (if not
 // null) receives per block { sum r_Y^2, sum r_U^2, sum r_P^2 }.
 template <typename T, typename TX, typename TO, int W, int JM>
-__global__ __launch_bounds__(kBlock) void k_residual(LevelArgs<T> L, const TX* __restrict__ x,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, JM >= 4 ? 3 : 8)))
+void k_residual(LevelArgs<T> L, const TX* __restrict__ x,
                                                      const TX* __restrict__ f,
                                                      TO* __restrict__ out, int mode,
                                                      double* __restrict__ partials) {
@@ -81,6 +88,26 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelArgs<T> L, const TX* _
       partials[3 * (size_t)b + 1] = acc[1];
       partials[3 * (size_t)b + 2] = acc[2];
     }
+  }
+}
+
+// First stage of the norm reduction for many partials: block b sums the b-th
+// contiguous chunk of the nb block partials into out[b][0..2] (fixed order).
+__global__ __launch_bounds__(kBlock) void k_norms3_stage(const double* __restrict__ partials, int nb,
+                                                       double* __restrict__ out) {
+  const int chunk = (nb + gridDim.x - 1) / gridDim.x;
+  const int lo = blockIdx.x * chunk, hi = min(nb, lo + chunk);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int i = lo + threadIdx.x; i < hi; i += kBlock) {
+    acc[0] += partials[3 * (size_t)i + 0];
+    acc[1] += partials[3 * (size_t)i + 1];
+    acc[2] += partials[3 * (size_t)i + 2];
+  }
+  block_sum<3>(acc);
+  if (threadIdx.x == 0) {
+    out[3 * (size_t)blockIdx.x + 0] = acc[0];
+    out[3 * (size_t)blockIdx.x + 1] = acc[1];
+    out[3 * (size_t)blockIdx.x + 2] = acc[2];
   }
 }
 

@@ -44,6 +44,9 @@ using IC = std::integral_constant<int, V>;
 
 // lanes per node W and samples per lane JM for N samples
 // compile-time width KM >= nv of the Krylov multi-vector kernels
+constexpr int kNormStage = 128;       // blocks of the first norm-reduction stage
+constexpr int kNormStageMin = 4096;   // partials above which the two-stage reduction is used
+
 // Register width of the multi-vector kernels for nv basis vectors.
 int km_width(int nv) { return nv <= 4 ? 4 : nv <= 8 ? 8 : nv <= 16 ? 16 : 32; }
 
@@ -101,6 +104,7 @@ struct smg_ctx {
   double* terms = nullptr;     // [N][m][m], setup only
   double* partials = nullptr;  // [npart][3] per-block squared norms of a residual
   size_t npart = 0;
+  double* partials2 = nullptr; // [kNormStage][3] first-stage sums of many partials
   double* norms = nullptr;     // [4]
   double* mdp = nullptr;       // [kPartials][kArnSlots] partials of the Krylov reductions
   double* hdev = nullptr;      // [3][kMaxBasis+1]
@@ -193,6 +197,7 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
   C->terms = cv.take<double>((size_t)N * m * m);
   C->npart = ((size_t)d.n * d.n + 3) / 4 + 1;   // residual blocks hold >= 4 nodes
   C->partials = cv.take<double>(C->npart * 3);
+  C->partials2 = cv.take<double>((size_t)kNormStage * 3);
   C->norms = cv.take<double>(4);
   C->mdp = cv.take<double>((size_t)kPartials * kArnSlots);
   C->hdev = cv.take<double>(3 * (kMaxBasis + 1));
@@ -291,8 +296,16 @@ int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, i
     const int nb = (int)((nn + per - 1) / per);
     hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N), x, f,
                        out, mode, want_norm ? C->partials : (double*)nullptr);
-    if (want_norm)
-      hipLaunchKernelGGL(k_finalize_norms3, dim3(1), dim3(1024), 0, C->stream, C->partials, nb, C->norms);
+    if (want_norm) {
+      if (nb > kNormStageMin) {   // two stages: one block alone reads partials at ~50 GB/s
+        hipLaunchKernelGGL(k_norms3_stage, dim3(kNormStage), dim3(kBlock), 0, C->stream, C->partials, nb,
+                           C->partials2);
+        hipLaunchKernelGGL(k_finalize_norms3, dim3(1), dim3(1024), 0, C->stream, C->partials2, kNormStage,
+                           C->norms);
+      } else {
+        hipLaunchKernelGGL(k_finalize_norms3, dim3(1), dim3(1024), 0, C->stream, C->partials, nb, C->norms);
+      }
+    }
   });
   LAUNCH_CHECK();
   return SMG_OK;

@@ -18,18 +18,21 @@ __device__ __forceinline__ void restrict_node(int nf, int N, const T* __restrict
   const T* fP = fine + (size_t)(N + 1) * nnf;
 #pragma unroll
   for (int q = 0; q < JM; ++q) {
-    const int j = lane + q * W;
-    if (j < N) {
-      T sY = 0, sP = 0;
+    // loads for a ragged sample j >= N read sample N-1 (in bounds); only the
+    // stores are guarded, so all loads of the node can be in flight together
+    const int j0 = lane + q * W;
+    const int j = j0 < N ? j0 : N - 1;
+    T sY = 0, sP = 0;
 #pragma unroll
-      for (int dk = -1; dk <= 1; ++dk)
+    for (int dk = -1; dk <= 1; ++dk)
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const T w = (T)(lin_w(dx) * lin_w(dk));
-          const size_t fi = (size_t)((long)c0 + (long)dk * nf + dx) * N + j;
-          sY += w * fY[fi];
-          sP += w * fP[fi];
-        }
+      for (int dx = -1; dx <= 1; ++dx) {
+        const T w = (T)(lin_w(dx) * lin_w(dk));
+        const size_t fi = (size_t)((long)c0 + (long)dk * nf + dx) * N + j;
+        sY += w * fY[fi];
+        sP += w * fP[fi];
+      }
+    if (j0 < N) {
       coarse[(size_t)slot * N + j] = sY;
       coarse[(size_t)(N + 1) * nnc + (size_t)slot * N + j] = sP;
     }
