@@ -22,29 +22,28 @@ enum NbSource { kPlain = 0, kZero = 1, kProlong = 2 };
 template <typename T>
 __device__ __forceinline__ void prolong_nb(const T* __restrict__ e, int nc, int N, int j, int x, int k,
                                            T& cw, T& ce, T& cs, T& cn) {
-  // loads are unconditional (clamped into the grid) and masked afterwards, so
-  // that they can all be in flight together
+  // Five unconditional loads (clamped into the grid, outside values selected to
+  // zero) for both cases, so that they are in flight together with the node's
+  // other loads.  x odd: v0 = (X, K) and its W, E, S, N coarse neighbours
+  // v1..v4; x even: v1..v4 = the cell corners (X-1, K-1), (X, K-1), (X-1, K),
+  // (X, K) (v0 = v4 is read twice).
   auto at = [&](int X, int K) -> T {
     const bool in = X >= 0 && X < nc && K >= 0 && K < nc;
     const int Xc = X < 0 ? 0 : (X >= nc ? nc - 1 : X), Kc = K < 0 ? 0 : (K >= nc ? nc - 1 : K);
     const T v = e[((size_t)Kc * nc + Xc) * N + j];
     return in ? v : T(0);
   };
-  if (x & 1) {
-    const int X = (x - 1) >> 1, K = (k - 1) >> 1;
-    const T c0 = at(X, K);
-    cw = T(0.5) * (at(X - 1, K) + c0);
-    ce = T(0.5) * (c0 + at(X + 1, K));
-    cs = T(0.5) * (at(X, K - 1) + c0);
-    cn = T(0.5) * (c0 + at(X, K + 1));
-  } else {
-    const int X = x >> 1, K = k >> 1;
-    const T a = at(X - 1, K - 1), b = at(X, K - 1), c = at(X - 1, K), d = at(X, K);
-    cw = T(0.5) * (a + c);
-    ce = T(0.5) * (b + d);
-    cs = T(0.5) * (a + b);
-    cn = T(0.5) * (c + d);
-  }
+  const bool odd = x & 1;
+  const int X = odd ? (x - 1) >> 1 : x >> 1, K = odd ? (k - 1) >> 1 : k >> 1;
+  const T v0 = at(X, K);
+  const T v1 = at(X - 1, odd ? K : K - 1);
+  const T v2 = at(odd ? X + 1 : X, odd ? K : K - 1);
+  const T v3 = at(odd ? X : X - 1, odd ? K - 1 : K);
+  const T v4 = at(X, odd ? K + 1 : K);
+  cw = T(0.5) * (v1 + (odd ? v0 : v3));
+  ce = T(0.5) * ((odd ? v0 : v2) + (odd ? v2 : v4));
+  cs = T(0.5) * ((odd ? v3 : v1) + (odd ? v0 : v2));
+  cn = T(0.5) * ((odd ? v0 : v3) + v4);
 }
 
 // Half-sweep update of the slot-th node of `colour` by one group of W lanes
