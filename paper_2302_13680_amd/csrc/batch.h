@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void kb_residual(const BTask<T>* __restrict
   const int lane = threadIdx.x & (W - 1);
   const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
   if (slot >= t.nitems) return;
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   residual_node<T, T, T, JM>(t.L, t.x, t.f, t.a, 0, slot, lane, W, acc);
 }
 
@@ -146,13 +146,14 @@ __global__ __launch_bounds__(kBlock) void kb_outer_residual(const BOuterTask<TO>
   const int W = t.W;
   const int lane = threadIdx.x & (W - 1);
   const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (slot < t.nitems) residual_node<double, double, TO, JM>(t.L, t.x, t.f, t.out, 0, slot, lane, W, acc);
-  block_sum<3>(acc);
+  double r3[3] = {acc[0], acc[1], acc[2]};
+  block_sum<3>(r3);
   if (threadIdx.x == 0) {
-    partials[3 * (size_t)b + 0] = acc[0];
-    partials[3 * (size_t)b + 1] = acc[1];
-    partials[3 * (size_t)b + 2] = acc[2];
+    partials[3 * (size_t)b + 0] = r3[0];
+    partials[3 * (size_t)b + 1] = r3[1];
+    partials[3 * (size_t)b + 2] = r3[2];
   }
 }
 

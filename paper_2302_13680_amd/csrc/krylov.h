@@ -83,14 +83,16 @@ __global__ __launch_bounds__(kBlock) void k_mdot_finalize(const double* __restri
 }
 
 // ------------------------------------------- Arnoldi with delayed reorthogonalization
-// One Arnoldi step touches the basis in two passes.  On entry V_0..V_{k-1} are
-// orthonormal, V_k is the previous step's projected vector (scaled to about unit
-// norm, not yet reorthogonalized) and w = S z_k.
-//   dots:   s = V_{<k}^T V_k, b = V_{<k}^T w, c = V_k.V_k, d = V_k.w, e = w.w
-//   update: V_k <- (V_k - V_{<k} s) / alpha              (second projection of V_k)
-//           V_{k+1} <- (w - V_{<k} b - h_kk V_k) / rho    (first projection of w)
-// with alpha^2 = c - |s|^2, h_kk = (d - s.b) / alpha; the host derives alpha,
-// h_kk and rho from the dots between the two passes.
+// One Arnoldi step touches the basis in two passes.  The stored vectors V_i are
+// never rewritten: the orthonormal basis is V' = V T with an upper-triangular T
+// kept on the host (it holds the normalizations and the second projections).
+// On entry V_k is the previous step's projected vector (scaled to about unit
+// norm, not yet projected a second time) and w = S z_k.
+//   dots:   R = V_{<k}^T V_k, B = V_{<k}^T w, c = V_k.V_k, d = V_k.w, e = w.w
+//   update: V_{k+1} = (w - V_{<=k} g) / rho
+// where the host turns R, B into projections on V' (s = T^T R, b = T^T B),
+// derives alpha^2 = c - |s|^2, h_kk = (d - s.b) / alpha, the new column of T and
+// the combination g = T [b; h_kk].
 constexpr int kArnSlots = 2 * kMaxBasis + 4;   // partial slots of the dots pass
 
 template <int KM>
@@ -98,7 +100,7 @@ struct ArnSlots {
   static constexpr int kC = 2 * KM, kD = 2 * KM + 1, kE = 2 * KM + 2, kCount = 2 * KM + 3;
 };
 
-// partials[b][slot], slots: [0,KM) s_i, [KM,2KM) b_i, then c, d, e (ArnSlots).
+// partials[b][slot], slots: [0,KM) R_i, [KM,2KM) B_i, then c, d, e (ArnSlots).
 template <int KM>
 __global__ __launch_bounds__(kBlock) void k_arnoldi_dots(size_t len, const double* __restrict__ V, size_t ldv,
                                                          int k, const double* __restrict__ w,
@@ -148,33 +150,26 @@ __global__ __launch_bounds__(kBlock) void k_partials_finalize(const double* __re
 }
 
 struct ArnCoef {
-  double s[kMaxBasis];
-  double b[kMaxBasis];
-  double inv_alpha, hkk, inv_rho;
+  double g[kMaxBasis];   // coefficients of V_0..V_k
+  double inv_rho;
 };
 
-// The update pass.  If norm_partials is not null, partials[b] = block sum of the
-// squared entries of the unscaled new vector (w - V_{<k} b - h_kk V_k).
+// The update pass V_{k+1} = (w - sum_{i<=k} g_i V_i) * inv_rho (KM >= k + 1).  If
+// norm_partials is not null, partials[b] = block sum of the squared entries of
+// the unscaled vector.
 template <int KM>
 __global__ __launch_bounds__(kBlock) void k_arnoldi_update(size_t len, double* __restrict__ V, size_t ldv, int k,
                                                            const double* __restrict__ w, ArnCoef cf,
                                                            double* __restrict__ norm_partials) {
-  double* __restrict__ vk = V + (size_t)k * ldv;
   double* __restrict__ vn = V + (size_t)(k + 1) * ldv;
   double acc[1] = {0.0};
   for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < len; t += (size_t)gridDim.x * kBlock) {
     double vv[KM];
 #pragma unroll
-    for (int i = 0; i < KM; ++i) vv[i] = i < k ? V[(size_t)i * ldv + t] : 0.0;
-    double v = vk[t], ws = w[t];
+    for (int i = 0; i < KM; ++i) vv[i] = i <= k ? V[(size_t)i * ldv + t] : 0.0;
+    double ws = w[t];
 #pragma unroll
-    for (int i = 0; i < KM; ++i) {
-      v -= cf.s[i] * vv[i];
-      ws -= cf.b[i] * vv[i];
-    }
-    v *= cf.inv_alpha;
-    ws -= cf.hkk * v;
-    vk[t] = v;
+    for (int i = 0; i < KM; ++i) ws -= cf.g[i] * vv[i];
     vn[t] = ws * cf.inv_rho;
     acc[0] += ws * ws;
   }
@@ -182,12 +177,6 @@ __global__ __launch_bounds__(kBlock) void k_arnoldi_update(size_t len, double* _
     block_sum<1>(acc);
     if (threadIdx.x == 0) norm_partials[blockIdx.x] = acc[0];
   }
-}
-
-// v = s w
-__global__ void k_scale(size_t len, const double* __restrict__ w, double* __restrict__ v, double s) {
-  for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < len; t += (size_t)gridDim.x * kBlock)
-    v[t] = w[t] * s;
 }
 
 struct BasisCoef {

@@ -8,11 +8,12 @@ namespace smg {
 // out = f - S x (mode 0) or out = S x (mode 1), block rows of eq. (2):
 //   Y rows: C_j y_j + A_j^T p_j,  U row: G u + sum_j D_j p_j,  P rows: A_j y_j + E_j u.
 // Faces and arithmetic in T, x and f in TX, out in TO (out may be null).
-// acc[0..2] accumulate the squared Y, U (lane 0) and P residual entries.
+// acc[0..2] accumulate the squared Y, U (lane 0) and P residual entries, acc[3]
+// the squared entries of f (mode 0), which gives ||f|| in the same pass.
 template <typename T, typename TX, typename TO, int JM>
 __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* __restrict__ x,
                                               const TX* __restrict__ f, TO* __restrict__ out, int mode,
-                                              int slot, int lane, int W, double (&acc)[3]) {
+                                              int slot, int lane, int W, double (&acc)[4]) {
   const int n = L.n, N = L.N;
   const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
   const int k = slot / n, xx = slot - k * n;
@@ -46,9 +47,12 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
     T rY = L.c[j] * y0 + (a * p0 - sp);     // C_j y_j + A_j^T p_j
     T rP = (a * y0 - sy) + L.e[j] * u;      // A_j y_j + E_j u
     dsum += act ? L.d[j] * p0 : T(0);
+    double ff = 0.0;
     if (mode == 0) {
-      rY = (T)f[base] - rY;
-      rP = (T)f[(size_t)(N + 1) * nn + base] - rP;
+      const T fy = (T)f[base], fp = (T)f[(size_t)(N + 1) * nn + base];
+      rY = fy - rY;
+      rP = fp - rP;
+      ff = (double)fy * (double)fy + (double)fp * (double)fp;
     }
     if (act) {
       if (out) {
@@ -57,76 +61,76 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
       }
       acc[0] += (double)rY * (double)rY;
       acc[2] += (double)rP * (double)rP;
+      acc[3] += ff;
     }
   }
   dsum = group_sum_w(dsum, W);
   if (lane == 0) {
     T rU = L.g * u + dsum;                    // G u + sum_j D_j p_j
-    if (mode == 0) rU = (T)f[(size_t)N * nn + node] - rU;
+    if (mode == 0) {
+      const T fu = (T)f[(size_t)N * nn + node];
+      rU = fu - rU;
+      acc[3] += (double)fu * (double)fu;
+    }
     if (out) out[(size_t)N * nn + node] = (TO)rU;
     acc[1] = (double)rU * (double)rU;
   }
 }
 
 // out = f - S x (mode 0) or out = S x (mode 1) over every node.  partials (if not
-// null) receives per block { sum r_Y^2, sum r_U^2, sum r_P^2 }.
+// null) receives per block { sum r_Y^2, sum r_U^2, sum r_P^2, sum f^2 }.
 template <typename T, typename TX, typename TO, int W, int JM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, JM >= 4 ? 3 : 8)))
-void k_residual(LevelArgs<T> L, const TX* __restrict__ x,
-                                                     const TX* __restrict__ f,
-                                                     TO* __restrict__ out, int mode,
-                                                     double* __restrict__ partials) {
+void k_residual(LevelArgs<T> L, const TX* __restrict__ x, const TX* __restrict__ f, TO* __restrict__ out,
+                int mode, double* __restrict__ partials) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (W - 1);
   const int slot = b * (kBlock / W) + threadIdx.x / W;
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (slot < L.n * L.n) residual_node<T, TX, TO, JM>(L, x, f, out, mode, slot, lane, W, acc);
   if (partials) {
-    block_sum<3>(acc);
+    block_sum<4>(acc);
     if (threadIdx.x == 0) {
-      partials[3 * (size_t)b + 0] = acc[0];
-      partials[3 * (size_t)b + 1] = acc[1];
-      partials[3 * (size_t)b + 2] = acc[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) partials[4 * (size_t)b + i] = acc[i];
     }
   }
 }
 
 // First stage of the norm reduction for many partials: block b sums the b-th
-// contiguous chunk of the nb block partials into out[b][0..2] (fixed order).
-__global__ __launch_bounds__(kBlock) void k_norms3_stage(const double* __restrict__ partials, int nb,
-                                                       double* __restrict__ out) {
+// contiguous chunk of the nb block partials into out[b][0..3] (fixed order).
+__global__ __launch_bounds__(kBlock) void k_norms_stage(const double* __restrict__ partials, int nb,
+                                                      double* __restrict__ out) {
   const int chunk = (nb + gridDim.x - 1) / gridDim.x;
   const int lo = blockIdx.x * chunk, hi = min(nb, lo + chunk);
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = lo + threadIdx.x; i < hi; i += kBlock) {
-    acc[0] += partials[3 * (size_t)i + 0];
-    acc[1] += partials[3 * (size_t)i + 1];
-    acc[2] += partials[3 * (size_t)i + 2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] += partials[4 * (size_t)i + c];
   }
-  block_sum<3>(acc);
+  block_sum<4>(acc);
   if (threadIdx.x == 0) {
-    out[3 * (size_t)blockIdx.x + 0] = acc[0];
-    out[3 * (size_t)blockIdx.x + 1] = acc[1];
-    out[3 * (size_t)blockIdx.x + 2] = acc[2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[4 * (size_t)blockIdx.x + c] = acc[c];
   }
 }
 
-// norms[0..3] = { ||r||, ||r_Y||, ||r_U||, ||r_P|| } from nb block partials
-// (one block of 1024 threads, fixed summation order).
-__global__ __launch_bounds__(1024) void k_finalize_norms3(const double* __restrict__ partials,
-                                                          int nb, double* __restrict__ norms) {
-  double acc[3] = {0.0, 0.0, 0.0};
+// norms[0..4] = { ||r||, ||r_Y||, ||r_U||, ||r_P||, ||f|| } from nb block
+// partials (one block of 1024 threads, fixed summation order).
+__global__ __launch_bounds__(1024) void k_finalize_norms(const double* __restrict__ partials, int nb,
+                                                         double* __restrict__ norms) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < nb; i += 1024) {
-    acc[0] += partials[3 * (size_t)i + 0];
-    acc[1] += partials[3 * (size_t)i + 1];
-    acc[2] += partials[3 * (size_t)i + 2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] += partials[4 * (size_t)i + c];
   }
-  block_sum<3, 1024>(acc);
+  block_sum<4, 1024>(acc);
   if (threadIdx.x == 0) {
     norms[0] = sqrt(acc[0] + acc[1] + acc[2]);
     norms[1] = sqrt(acc[0]);
     norms[2] = sqrt(acc[1]);
     norms[3] = sqrt(acc[2]);
+    norms[4] = sqrt(acc[3]);
   }
 }
 

@@ -102,9 +102,9 @@ struct smg_ctx {
   double* Sinv = nullptr;      // [m][m]
   double* ds = nullptr;        // [N][m]
   double* terms = nullptr;     // [N][m][m], setup only
-  double* partials = nullptr;  // [npart][3] per-block squared norms of a residual
+  double* partials = nullptr;  // [npart][4] per-block squared norms of a residual and of f
   size_t npart = 0;
-  double* partials2 = nullptr; // [kNormStage][3] first-stage sums of many partials
+  double* partials2 = nullptr; // [kNormStage][4] first-stage sums of many partials
   double* norms = nullptr;     // [4]
   double* mdp = nullptr;       // [kPartials][kArnSlots] partials of the Krylov reductions
   double* hdev = nullptr;      // [3][kMaxBasis+1]
@@ -196,9 +196,9 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
   C->ds = cv.take<double>((size_t)N * m);
   C->terms = cv.take<double>((size_t)N * m * m);
   C->npart = ((size_t)d.n * d.n + 3) / 4 + 1;   // residual blocks hold >= 4 nodes
-  C->partials = cv.take<double>(C->npart * 3);
-  C->partials2 = cv.take<double>((size_t)kNormStage * 3);
-  C->norms = cv.take<double>(4);
+  C->partials = cv.take<double>(C->npart * 4);
+  C->partials2 = cv.take<double>((size_t)kNormStage * 4);
+  C->norms = cv.take<double>(5);
   C->mdp = cv.take<double>((size_t)kPartials * kArnSlots);
   C->hdev = cv.take<double>(3 * (kMaxBasis + 1));
   C->flag = cv.take<int>(1);
@@ -286,7 +286,8 @@ int halfsweep(smg_ctx* C, const Level<T>& L, T* x, const T* f, int colour, int s
   return SMG_OK;
 }
 
-// out = f - S x (mode 0) or S x (mode 1); norms into C->norms when want_norm.
+// out = f - S x (mode 0) or S x (mode 1); when want_norm, C->norms receives
+// { ||r||, ||r_Y||, ||r_U||, ||r_P||, ||f|| } (||f|| = 0 in mode 1).
 template <typename T, typename TX, typename TO>
 int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, int mode, bool want_norm) {
   const size_t nn = (size_t)L.n * L.n;
@@ -298,12 +299,12 @@ int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, i
                        out, mode, want_norm ? C->partials : (double*)nullptr);
     if (want_norm) {
       if (nb > kNormStageMin) {   // two stages: one block alone reads partials at ~50 GB/s
-        hipLaunchKernelGGL(k_norms3_stage, dim3(kNormStage), dim3(kBlock), 0, C->stream, C->partials, nb,
+        hipLaunchKernelGGL(k_norms_stage, dim3(kNormStage), dim3(kBlock), 0, C->stream, C->partials, nb,
                            C->partials2);
-        hipLaunchKernelGGL(k_finalize_norms3, dim3(1), dim3(1024), 0, C->stream, C->partials2, kNormStage,
+        hipLaunchKernelGGL(k_finalize_norms, dim3(1), dim3(1024), 0, C->stream, C->partials2, kNormStage,
                            C->norms);
       } else {
-        hipLaunchKernelGGL(k_finalize_norms3, dim3(1), dim3(1024), 0, C->stream, C->partials, nb, C->norms);
+        hipLaunchKernelGGL(k_finalize_norms, dim3(1), dim3(1024), 0, C->stream, C->partials, nb, C->norms);
       }
     }
   });
@@ -452,16 +453,17 @@ int sync(smg_ctx* C) {
   return SMG_OK;
 }
 
-// FP64 residual of the finest level into out (may be null), norms to host h[0..3].
+// FP64 residual of the finest level into out (may be null); norms to host
+// h[0..4] = { ||r||, ||r_Y||, ||r_U||, ||r_P||, ||f|| }.
 int residual_norms64(smg_ctx* C, const double* x, const double* f, double* out, double* h) {
   TRY((residual<double, double, double>(C, C->L64[0], x, f, out, 0, true)));
-  HIP_TRY(hipMemcpyAsync(C->host, C->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, C->stream));
+  HIP_TRY(hipMemcpyAsync(C->host, C->norms, 5 * sizeof(double), hipMemcpyDeviceToHost, C->stream));
   TRY(sync(C));
-  for (int i = 0; i < 4; ++i) h[i] = C->host[i];
+  for (int i = 0; i < 5; ++i) h[i] = C->host[i];
   return SMG_OK;
 }
 
-// ||f||_2 via the residual kernel's norm path (x = 0 gives r = f): reuse mdot on f.
+// ||v||_2 (one multi-dot pass with no basis vectors).
 int vec_norm(smg_ctx* C, const double* v, size_t len, double* out) {
   hipLaunchKernelGGL((k_mdot<double, 4>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, v,
                      (const double*)nullptr, (size_t)0, 0, 1, C->mdp);
@@ -544,23 +546,26 @@ double hessenberg_lsq(const std::vector<double>& H, int m, int nc, double g0, do
 // of each basis vector delayed to the next step, where it shares one pass over
 // the basis with the first projection of the new vector (Hernandez, Roman and
 // Tomas 2007; Bielich et al. 2022): per step one V-cycle, one operator apply,
-// one pass of dot products, one host synchronization and one update pass.  The
-// preconditioner sees each basis vector before its second projection, which
-// flexible GMRES allows (x += Z y with A Z = V H holds for any Z).  The
-// provisional subdiagonal |w'| of a step is replaced by the exact norm after the
-// second projection in the next step, and the least-squares problem is
-// re-solved from scratch each step.
-// On entry C->w holds r0 = f - S x with norm beta.  Iterates until the
-// recurrence residual <= target, m steps, or *budget runs out; x += Z y at the
-// end.  Returns its in *its_done and the last recurrence residual in *est.
+// one pass of dot products, one host synchronization and one update pass that
+// writes only the new vector (the second projections and normalizations live in
+// the triangular factor T of V' = V T on the host).  The preconditioner sees
+// each basis vector before its second projection, which flexible GMRES allows
+// (x += Z y with A Z = V' H holds for any Z).  The provisional subdiagonal |w'|
+// of a step is replaced by the exact norm after the second projection in the
+// next step, and the least-squares problem is re-solved from scratch each step.
+// On entry V_0 holds r0 = f - S x itself (norm beta), and r0 = g0 V'_0 with
+// g0 = |r0| from the first dots pass.  Iterates until the recurrence residual
+// <= target, m steps, or *budget runs out; x += Z y at the end.  Returns its in
+// *its_done and the last recurrence residual in *est.
 int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int budget, int* its_done,
                 double* est, smg_stats* st, double fn) {
   const size_t len = C->len0;
-  std::vector<double> H((size_t)(m + 1) * m, 0.0);
-  // V_0 = r0 / beta; r0 = g0 V_0 after V_0's second projection (normalization)
-  hipLaunchKernelGGL(k_scale, dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, (const double*)C->w, C->V,
-                     1.0 / beta);
-  LAUNCH_CHECK();
+  const int m1 = m + 1;
+  std::vector<double> H((size_t)m1 * m, 0.0);
+  // Orthonormal basis V' = V T (T upper triangular, T[l * m1 + i] = weight of
+  // stored V_l in V'_i); the stored vectors are never rewritten.
+  std::vector<double> T((size_t)m1 * m1, 0.0);
+  std::vector<double> s(m1), b(m1);
   double g0 = beta, rho = 1.0;   // V_k as stored = (projected vector) / rho
   int k = 0, done = 0;
   double res = beta;
@@ -579,14 +584,21 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
     LAUNCH_CHECK();
     HIP_TRY(hipMemcpyAsync(C->host, C->hdev, sizeof(double) * nslots, hipMemcpyDeviceToHost, C->stream));
     TRY(sync(C));
-    const double* s = C->host;
-    const double* b = C->host + KMv;
+    const double* R = C->host;          // stored V_l . V_k
+    const double* B = C->host + KMv;    // stored V_l . w
     const double c = C->host[2 * KMv], d = C->host[2 * KMv + 1], e = C->host[2 * KMv + 2];
+    // projections on the orthonormal basis: s = T^T R, b = T^T B
     double ss = 0.0, sb = 0.0, bb = 0.0;
     for (int i = 0; i < k; ++i) {
-      ss += s[i] * s[i];
-      sb += s[i] * b[i];
-      bb += b[i] * b[i];
+      double si = 0.0, bi = 0.0;
+      for (int l = 0; l <= i; ++l) {
+        si += T[(size_t)l * m1 + i] * R[l];
+        bi += T[(size_t)l * m1 + i] * B[l];
+      }
+      s[i] = si; b[i] = bi;
+      ss += si * si;
+      sb += si * bi;
+      bb += bi * bi;
     }
     const double a2 = c - ss;
     if (!std::isfinite(a2) || !std::isfinite(d) || !std::isfinite(e)) {
@@ -600,8 +612,14 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
       break;
     }
     const double alpha = std::sqrt(a2);
+    // V'_k = (V_k - sum_{i<k} s_i V'_i) / alpha
+    for (int l = 0; l <= k; ++l) {
+      double t = l == k ? 1.0 : 0.0;
+      for (int i = l; i < k; ++i) t -= s[i] * T[(size_t)l * m1 + i];
+      T[(size_t)l * m1 + k] = t / alpha;
+    }
     if (k == 0) {
-      g0 = beta * alpha;
+      g0 = alpha;
     } else {
       for (int i = 0; i < k; ++i) H[(size_t)i * m + k - 1] += rho * s[i];
       H[(size_t)k * m + k - 1] = rho * alpha;
@@ -609,13 +627,16 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
     const double hkk = (d - sb) / alpha;
     for (int i = 0; i < k; ++i) H[(size_t)i * m + k] = b[i];
     H[(size_t)k * m + k] = hkk;
+    // w' = w - sum_{i<k} b_i V'_i - hkk V'_k = w - sum_{l<=k} g_l V_l
     ArnCoef cf;
-    for (int i = 0; i < kMaxBasis; ++i) {
-      cf.s[i] = i < k ? s[i] : 0.0;
-      cf.b[i] = i < k ? b[i] : 0.0;
+    for (int l = 0; l < kMaxBasis; ++l) {
+      double g = 0.0;
+      if (l <= k) {
+        for (int i = l; i < k; ++i) g += T[(size_t)l * m1 + i] * b[i];
+        g += T[(size_t)l * m1 + k] * hkk;
+      }
+      cf.g[l] = g;
     }
-    cf.inv_alpha = 1.0 / alpha;
-    cf.hkk = hkk;
     // |w'|^2 from the dots; trusted unless cancellation takes more than four digits
     const double wn2 = e - bb - hkk * hkk;
     const bool estimated = wn2 > 1e-4 * e;
@@ -625,7 +646,7 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
       hn = std::sqrt(wn2);
     } else {
       cf.inv_rho = 1.0;
-      km_dispatch(k, [&](auto Kc) {
+      km_dispatch(k + 1, [&](auto Kc) {
         constexpr int KM = decltype(Kc)::value;
         hipLaunchKernelGGL((k_arnoldi_update<KM>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, C->V, len, k,
                            (const double*)C->w, cf, C->mdp);
@@ -650,7 +671,7 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
     if (res <= target || hn == 0.0 || k + 1 == m || done == budget) { ++k; break; }
     if (!updated) {
       cf.inv_rho = 1.0 / hn;
-      km_dispatch(k, [&](auto Kc) {
+      km_dispatch(k + 1, [&](auto Kc) {
         constexpr int KM = decltype(Kc)::value;
         hipLaunchKernelGGL((k_arnoldi_update<KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, C->V, len,
                            k, (const double*)C->w, cf, (double*)nullptr);
@@ -1130,7 +1151,12 @@ int smg_apply(smg_ctx* C, const double* x, double* Sx) {
 
 int smg_residual(smg_ctx* C, const double* x, const double* f, double* r, double* norms) {
   if (!C || !x || !f || !r) return SMG_EINVAL;
-  if (norms) return residual_norms64(C, x, f, r, norms);
+  if (norms) {
+    double h[5];
+    TRY(residual_norms64(C, x, f, r, h));
+    for (int i = 0; i < 4; ++i) norms[i] = h[i];
+    return SMG_OK;
+  }
   return residual<double, double, double>(C, C->L64[0], x, f, r, 0, false);
 }
 
@@ -1187,11 +1213,9 @@ int smg_gmres_precond(smg_ctx* C, double* x, const double* f, int restart, doubl
     return SMG_EINVAL;
   const double t0 = now_ms();
   stats_begin(st);
-  double fn;
-  TRY(vec_norm(C, f, C->len0, &fn));
-  if (!(fn > 0.0)) fn = 1.0;
-  double h[4];
-  TRY(residual_norms64(C, x, f, C->w, h));
+  double h[5];
+  TRY(residual_norms64(C, x, f, C->V, h));
+  const double fn = h[4] > 0.0 ? h[4] : 1.0;
   stats_push(st, h[0] / fn);
   int its = 0, restarts = 0, rc = SMG_NOT_CONVERGED;
   while (true) {
@@ -1202,7 +1226,7 @@ int smg_gmres_precond(smg_ctx* C, double* x, const double* f, int restart, doubl
     double est = 0;
     TRY(gmres_cycle(C, x, h[0], restart, rtol * fn, maxit - its, &done, &est, st, fn));
     its += done;
-    TRY(residual_norms64(C, x, f, C->w, h));
+    TRY(residual_norms64(C, x, f, C->V, h));
     if (h[0] > rtol * fn && its < maxit) ++restarts;
   }
   if (st) {
@@ -1227,10 +1251,8 @@ int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, i
   }
   if (method == SMG_GMRES && C->desc.gmres_restart < 1) return SMG_EINVAL;
   stats_begin(st);
-  double fn;
-  TRY(vec_norm(C, f, C->len0, &fn));
-  if (!(fn > 0.0)) fn = 1.0;
-  double h[4];
+  double fn = -1.0;   // ||f||, from the first residual pass
+  double h[5];
   int its = 0, inner = 0, rc = SMG_NOT_CONVERGED;
   while (true) {
     if (!f32) {
@@ -1238,12 +1260,13 @@ int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, i
     } else if (method == SMG_VCYCLE) {
       // FP64 residual rounded straight into the FP32 cycle's right-hand side
       TRY((residual<double, double, float>(C, C->L64[0], x, f, C->L32[0].f, 0, true)));
-      HIP_TRY(hipMemcpyAsync(C->host, C->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, C->stream));
+      HIP_TRY(hipMemcpyAsync(C->host, C->norms, 5 * sizeof(double), hipMemcpyDeviceToHost, C->stream));
       TRY(sync(C));
-      for (int i = 0; i < 4; ++i) h[i] = C->host[i];
+      for (int i = 0; i < 5; ++i) h[i] = C->host[i];
     } else {
-      TRY(residual_norms64(C, x, f, C->w, h));
+      TRY(residual_norms64(C, x, f, C->V, h));   // r0 straight into the Krylov basis
     }
+    if (fn < 0.0) fn = h[4] > 0.0 ? h[4] : 1.0;
     stats_push(st, h[0] / fn);
     if (!std::isfinite(h[0])) { rc = SMG_ENONFINITE; break; }
     if (h[0] <= rtol * fn) { rc = SMG_OK; break; }
