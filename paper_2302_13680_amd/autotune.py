@@ -2,9 +2,12 @@
 
 For every distinct (n, N, precision) among a batch's contexts the library's
 smg_tune_lanes times the finest-level half-sweep for each admissible width
-(64, 32, 16, 8 lanes per node) and the fastest is kept.  Results are cached by
-key "n x N : precision : device name" in a JSON file so that later runs reuse
-them without timing.
+(64, 32, 16, 8 lanes per node).  The batched kernels are compiled for one
+samples-per-lane count JM = max_i ceil(N_i / W_i) for all instances, so a
+narrow width for a large-N instance slows every instance; the choice for each
+instance is therefore the fastest width with ceil(N / W) <= ceil(max_i N_i / 64),
+the smallest JM the batch allows.  Timings are cached by key
+"n x N : precision : device name" in a JSON file so that later runs reuse them.
 """
 from __future__ import annotations
 
@@ -25,13 +28,15 @@ def tune(contexts, cache_path: str | None = None, device_name: str = "gfx950"):
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
             cache = json.load(fh)
+    jm_cap = max(-(-ctx.N // 64) for ctx in contexts)
     lanes = []
     for ctx in contexts:
         key = _key(ctx, device_name)
         if key not in cache:
             best, table = binding.tune_lanes(ctx)
             cache[key] = {"best": best, "us": {str(k): v for k, v in table.items()}}
-        lanes.append(int(cache[key]["best"]))
+        table = {int(w): us for w, us in cache[key]["us"].items() if -(-ctx.N // int(w)) <= jm_cap}
+        lanes.append(min(table, key=table.get) if table else int(cache[key]["best"]))
     if cache_path:
         os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
         with open(cache_path, "w") as fh:

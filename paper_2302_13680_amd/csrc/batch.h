@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void kb_restrict(const BTask<T>* __restrict
   const int lane = threadIdx.x & (W - 1);
   const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
   if (slot >= t.nitems) return;
-  restrict_node<T, JM>(t.L.n, t.L.N, t.b, t.a, slot, lane, W);
+  restrict_node<T, JM>(t.L.n, t.L.N, t.b, t.a, slot, lane, W, coarse_strip(t.L.strip));
 }
 
 // coarsest direct solve, one block per (instance, sample)

@@ -127,10 +127,19 @@ __global__ __launch_bounds__(kBlock) void k_coarse_schur_invert(int m, int N, co
 //            p_j = A_j^{-1}(F_Y,j - c_j y_j)
 // Vectors in the level layout (type TV), arithmetic in FP64.
 // (M v)_i with M stored transposed (MT[c][i] = M[i][c]): coalesced across threads i.
-__device__ __forceinline__ double row_dot(const double* __restrict__ MT, int m, int i, const double* v) {
+// Row i of M stored transposed (MT[c][i] = M[i][c]; coalesced across threads i)
+// into registers: all kMaxCoarse loads are issued before the first use (indices
+// past m are clamped into the matrix), so a row costs one memory round trip and
+// is reused for every product with M.
+__device__ __forceinline__ void load_row(const double* __restrict__ MT, int m, int i, double (&a)[kMaxCoarse]) {
+#pragma unroll
+  for (int c = 0; c < kMaxCoarse; ++c) a[c] = MT[(size_t)(c < m ? c : m - 1) * m + i];
+}
+// (M v)_i from the row in registers, summed over c = 0..m-1 in order.
+__device__ __forceinline__ double dot_row(const double (&a)[kMaxCoarse], int m, const double* v) {
   double s = 0.0;
-#pragma unroll 7
-  for (int c = 0; c < m; ++c) s += MT[(size_t)c * m + i] * v[c];
+#pragma unroll
+  for (int c = 0; c < kMaxCoarse; ++c) s += c < m ? a[c] * v[c] : 0.0;
   return s;
 }
 
@@ -144,11 +153,15 @@ __device__ __forceinline__ void coarse_phase1_sample(int j, int m, int N, const 
   const double* Aj = Ainv + (size_t)j * m * m;
   const TV* FY = F;
   const TV* FP = F + (size_t)(N + 1) * m;
-  if (i < m) sF[i] = (double)FP[(size_t)i * N + j];
+  double a[kMaxCoarse];
+  if (i < m) {
+    load_row(Aj, m, i, a);
+    sF[i] = (double)FP[(size_t)i * N + j];
+  }
   __syncthreads();
-  if (i < m) sT[i] = (double)FY[(size_t)i * N + j] - c[j] * row_dot(Aj, m, i, sF);
+  if (i < m) sT[i] = (double)FY[(size_t)i * N + j] - c[j] * dot_row(a, m, sF);
   __syncthreads();
-  if (i < m) ds[(size_t)j * m + i] = d[j] * row_dot(Aj, m, i, sT);
+  if (i < m) ds[(size_t)j * m + i] = d[j] * dot_row(a, m, sT);
 }
 
 // Phase 2 for sample j (one block of >= m threads); block j = 0 also writes u.
@@ -164,23 +177,32 @@ __device__ __forceinline__ void coarse_phase2_sample(int j, int m, int N, const 
   const TV* FY = F;
   const TV* FU = F + (size_t)N * m;
   const TV* FP = F + (size_t)(N + 1) * m;
+  double a[kMaxCoarse], si[kMaxCoarse];
   if (i < m) {
+    load_row(Aj, m, i, a);
+    load_row(Sinv, m, i, si);
+    // F_U - sum_j ds_j, in sample order; 16 loads in flight per round trip
     double s = (double)FU[i];
-#pragma unroll 8
-    for (int q = 0; q < N; ++q) s -= ds[(size_t)q * m + i];
+    for (int q0 = 0; q0 < N; q0 += 16) {
+      double t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) t[u] = ds[(size_t)(q0 + u < N ? q0 + u : N - 1) * m + i];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s -= q0 + u < N ? t[u] : 0.0;
+    }
     sR[i] = s;
   }
   __syncthreads();
-  if (i < m) sU[i] = row_dot(Sinv, m, i, sR);
+  if (i < m) sU[i] = dot_row(si, m, sR);
   __syncthreads();
   if (i < m) sT[i] = (double)FP[(size_t)i * N + j] - e[j] * sU[i];
   __syncthreads();
-  if (i < m) sY[i] = row_dot(Aj, m, i, sT);
+  if (i < m) sY[i] = dot_row(a, m, sT);
   __syncthreads();
   if (i < m) sT[i] = (double)FY[(size_t)i * N + j] - c[j] * sY[i];
   __syncthreads();
   if (i < m) {
-    const double p = row_dot(Aj, m, i, sT);
+    const double p = dot_row(a, m, sT);
     X[(size_t)i * N + j] = (TV)sY[i];
     X[(size_t)(N + 1) * m + (size_t)i * N + j] = (TV)p;
     if (j == 0) X[(size_t)N * m + i] = (TV)sU[i];

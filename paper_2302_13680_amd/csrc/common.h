@@ -143,6 +143,24 @@ __host__ __device__ inline void colour_node(int slot, int n, int colour, int S, 
   else { k = 2 * pr + 1; x = x0 + (1 - colour) + 2 * (rem - c0); }
 }
 
+// Node (x, k) of the slot-th node of an n x n grid (any n) traversed in vertical
+// strips of S columns (S >= n: row-major order), each strip row by row.
+__host__ __device__ inline void strip_node(int slot, int n, int S, int& x, int& k) {
+  int x0 = 0, w = n, l = slot;
+  if (S < n) {
+    const int per = n * S;
+    const int s = slot / per;
+    x0 = s * S;
+    w = n - x0 < S ? n - x0 : S;
+    l = slot - s * per;
+  }
+  k = l / w;
+  x = x0 + (l - k * w);
+}
+
+// Strip width on the next coarser grid that covers the same fine columns.
+__host__ __device__ inline int coarse_strip(int fine_strip) { return fine_strip >= 4 ? fine_strip / 2 : 2; }
+
 // Weights of 1D linear interpolation: 1 at the coinciding node, 1/2 next to it.
 __device__ __forceinline__ double lin_w(int d) { return d == 0 ? 1.0 : 0.5; }
 

@@ -16,8 +16,9 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
                                               int slot, int lane, int W, double (&acc)[4]) {
   const int n = L.n, N = L.N;
   const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
-  const int k = slot / n, xx = slot - k * n;
-  const size_t node = (size_t)slot;
+  int xx, k;
+  strip_node(slot, n, L.strip, xx, k);   // strips keep the rows above and below in L2
+  const size_t node = (size_t)k * n + xx;
   const TX* Y = x;
   const TX* P = x + (size_t)(N + 1) * nn;
   const T u = (T)x[(size_t)N * nn + node];

@@ -295,7 +295,8 @@ int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, i
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     const int per = kBlock / W;
     const int nb = (int)((nn + per - 1) / per);
-    hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N), x, f,
+    hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream,
+                       args(L, C->N, C->desc.strip), x, f,
                        out, mode, want_norm ? C->partials : (double*)nullptr);
     if (want_norm) {
       if (nb > kNormStageMin) {   // two stages: one block alone reads partials at ~50 GB/s
@@ -318,7 +319,8 @@ int restrict_to(smg_ctx* C, int nf, const T* fine, T* coarse) {
   seg_dispatch(C->N, [&](auto Wc, auto Jc) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     const int per = kBlock / W, nb = (nc * nc + per - 1) / per;
-    hipLaunchKernelGGL((k_restrict<T, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, nf, C->N, fine, coarse);
+    hipLaunchKernelGGL((k_restrict<T, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, nf, C->N, fine, coarse,
+                       coarse_strip(strip_for(nf, C->desc.strip)));
   });
   LAUNCH_CHECK();
   return SMG_OK;

@@ -4,15 +4,18 @@
 
 namespace smg {
 
-// coarse = R fine, R = P^T: coarse node (X, K) = slot sits on fine node
-// (2X+1, 2K+1) and gathers its 3x3 fine neighbourhood with weights w(dx) w(dk).
-// One group of W lanes per coarse node.
+// coarse = R fine, R = P^T: coarse node (X, K) sits on fine node (2X+1, 2K+1)
+// and gathers its 3x3 fine neighbourhood with weights w(dx) w(dk).  One group
+// of W lanes per coarse node; the slot-th coarse node in strips of cstrip
+// coarse columns (strip_node).
 template <typename T, int JM>
 __device__ __forceinline__ void restrict_node(int nf, int N, const T* __restrict__ fine,
-                                              T* __restrict__ coarse, int slot, int lane, int W) {
+                                              T* __restrict__ coarse, int slot, int lane, int W, int cstrip) {
   const int nc = (nf - 1) / 2;
   const size_t nnf = (size_t)nf * nf, nnc = (size_t)nc * nc;
-  const int K = slot / nc, X = slot - K * nc;
+  int X, K;
+  strip_node(slot, nc, cstrip, X, K);
+  const int cnode = K * nc + X;
   const size_t c0 = (size_t)(2 * K + 1) * nf + (2 * X + 1);
   const T* fY = fine;
   const T* fP = fine + (size_t)(N + 1) * nnf;
@@ -33,8 +36,8 @@ __device__ __forceinline__ void restrict_node(int nf, int N, const T* __restrict
         sP += w * fP[fi];
       }
     if (j0 < N) {
-      coarse[(size_t)slot * N + j] = sY;
-      coarse[(size_t)(N + 1) * nnc + (size_t)slot * N + j] = sP;
+      coarse[(size_t)cnode * N + j] = sY;
+      coarse[(size_t)(N + 1) * nnc + (size_t)cnode * N + j] = sP;
     }
   }
   if (lane == 0) {
@@ -45,19 +48,19 @@ __device__ __forceinline__ void restrict_node(int nf, int N, const T* __restrict
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx)
         sU += (T)(lin_w(dx) * lin_w(dk)) * fU[(long)c0 + (long)dk * nf + dx];
-    coarse[(size_t)N * nnc + slot] = sU;
+    coarse[(size_t)N * nnc + cnode] = sU;
   }
 }
 
 template <typename T, int W, int JM>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nf, int N, const T* __restrict__ fine,
-                                                     T* __restrict__ coarse) {
+                                                     T* __restrict__ coarse, int cstrip) {
   const int nc = (nf - 1) / 2;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (W - 1);
   const int slot = b * (kBlock / W) + threadIdx.x / W;
   if (slot >= nc * nc) return;
-  restrict_node<T, JM>(nf, N, fine, coarse, slot, lane, W);
+  restrict_node<T, JM>(nf, N, fine, coarse, slot, lane, W, cstrip);
 }
 
 // fine += P coarse, bilinear interpolation gathered per fine node.

@@ -100,6 +100,8 @@ def test_autotuned_lanes(B, O, tmp_path):
     lanes, table = autotune.tune(ctxs, cache)
     for p, w in zip(probs, lanes):
         assert w in (8, 16, 32, 64) and (p.N + w - 1) // w <= 8
+    # the batch-wide samples per lane stay at the smallest value the batch allows
+    assert max(-(-p.N // w) for p, w in zip(probs, lanes)) == -(-max(p.N for p in probs) // 64)
     lanes2, _ = autotune.tune(ctxs, cache)          # served from the cache
     assert lanes2 == lanes
     bt = B.Batch(ctxs, xs, fs, lanes=lanes)
