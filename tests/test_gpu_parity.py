@@ -49,7 +49,7 @@ def mk(n, N, seed=0, nu=1e-4, sigma=0.5, M=4, decay=False):
     return inputs.make_problem(n, N, nu, M=M, sigma=sigma, decay=decay, seed=seed)
 
 
-SMALL = [(15, 1), (15, 3), (31, 8), (15, 33), (15, 64), (15, 100), (7, 256), (63, 16)]
+SMALL = [(15, 1), (15, 3), (31, 8), (15, 33), (15, 64), (15, 100), (7, 256), (63, 16), (15, 300), (7, 512)]
 
 
 @pytest.mark.parametrize("n,N", SMALL)
@@ -143,7 +143,7 @@ def test_transfers(B, O, n, N):
     assert rel(node_to_paper(host(fd), n, N), O.prolong_add(nc, N, coarse, fine)) <= 1e-15
 
 
-@pytest.mark.parametrize("N", [1, 5, 64, 300])
+@pytest.mark.parametrize("N", [1, 5, 64, 300, 512])
 def test_coarse_solve(B, O, N):
     p = mk(7, N, seed=8)
     o = O.Oracle(p, coarsest_n=7)
