@@ -78,6 +78,88 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
   }
 }
 
+// One refinement update fused with the next residual: x_next = x + d (d: the
+// FP32 correction of the cycle) and out = f - S x_next rounded to FP32, by a group
+// of W lanes for one node; the neighbours' x + d are formed on the fly with the
+// same FP64 addition their own groups store, so no group reads x_next.  acc as
+// in residual_node.  x_next must not alias x.
+template <int JM>
+__device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, const double* __restrict__ x,
+                                                  const float* __restrict__ d, double* __restrict__ xn,
+                                                  const double* __restrict__ f, float* __restrict__ out,
+                                                  int slot, int lane, int W, double (&acc)[4]) {
+  const int n = L.n, N = L.N;
+  const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
+  int xx, k;
+  strip_node(slot, n, L.strip, xx, k);
+  const size_t node = (size_t)k * n + xx;
+  const size_t oU = (size_t)N * nn, oP = (size_t)(N + 1) * nn;
+  const double u = x[oU + node] + (double)d[oU + node];
+  const size_t kxb = ((size_t)k * (n + 1) + xx) * N;
+  const size_t kyb = node * N;
+  const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
+  const ptrdiff_t ow = hw ? -(ptrdiff_t)N : 0, oe = he ? (ptrdiff_t)N : 0;
+  const ptrdiff_t os = hs ? -(ptrdiff_t)rowN : 0, on = hn ? (ptrdiff_t)rowN : 0;
+  auto yv = [&](size_t i) { return x[i] + (double)d[i]; };
+  auto pv = [&](size_t i) { return x[oP + i] + (double)d[oP + i]; };
+  double dsum = 0;
+#pragma unroll
+  for (int q = 0; q < JM; ++q) {
+    const int j0 = lane + q * W;
+    const bool act = j0 < N;
+    const int j = act ? j0 : N - 1;
+    const double kw = L.kx[kxb + j], ke = L.kx[kxb + N + j];
+    const double ks = L.ky[kyb + j], kn = L.ky[kyb + rowN + j];
+    const size_t base = node * N + j;
+    const double y0 = yv(base), p0 = pv(base);
+    auto nbsum = [&](double vw, double ve, double vs, double vn) {
+      return ((hw ? kw * vw : 0.0) + (he ? ke * ve : 0.0)) + ((hs ? ks * vs : 0.0) + (hn ? kn * vn : 0.0));
+    };
+    const double sy = nbsum(yv(base + ow), yv(base + oe), yv(base + os), yv(base + on));
+    const double sp = nbsum(pv(base + ow), pv(base + oe), pv(base + os), pv(base + on));
+    const double a = (kw + ke) + (ks + kn);
+    const double fy = f[base], fp = f[oP + base];
+    const double rY = fy - (L.c[j] * y0 + (a * p0 - sp));
+    const double rP = fp - ((a * y0 - sy) + L.e[j] * u);
+    dsum += act ? L.d[j] * p0 : 0.0;
+    if (act) {
+      xn[base] = y0;
+      xn[oP + base] = p0;
+      out[base] = (float)rY;
+      out[oP + base] = (float)rP;
+      acc[0] += rY * rY;
+      acc[2] += rP * rP;
+      acc[3] += fy * fy + fp * fp;
+    }
+  }
+  dsum = group_sum_w(dsum, W);
+  if (lane == 0) {
+    const double fu = f[oU + node];
+    const double rU = fu - (L.g * u + dsum);
+    xn[oU + node] = u;
+    out[oU + node] = (float)rU;
+    acc[1] = rU * rU;
+    acc[3] += fu * fu;
+  }
+}
+
+template <int W, int JM>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, JM >= 4 ? 3 : 8)))
+void k_residual_add(LevelArgs<double> L, const double* __restrict__ x, const float* __restrict__ d,
+                    double* __restrict__ xn, const double* __restrict__ f, float* __restrict__ out,
+                    double* __restrict__ partials) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & (W - 1);
+  const int slot = b * (kBlock / W) + threadIdx.x / W;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (slot < L.n * L.n) residual_add_node<JM>(L, x, d, xn, f, out, slot, lane, W, acc);
+  block_sum<4>(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) partials[4 * (size_t)b + i] = acc[i];
+  }
+}
+
 // out = f - S x (mode 0) or out = S x (mode 1) over every node.  partials (if not
 // null) receives per block { sum r_Y^2, sum r_U^2, sum r_P^2, sum f^2 }.
 template <typename T, typename TX, typename TO, int W, int JM>

@@ -313,6 +313,27 @@ int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, i
   return SMG_OK;
 }
 
+// x_next = x + d, out = f - S x_next (FP32), norms into C->norms (FP32 refinement).
+int residual_add(smg_ctx* C, const double* x, const float* d, double* xn, const double* f, float* out) {
+  const Level<double>& L = C->L64[0];
+  const size_t nn = (size_t)L.n * L.n;
+  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    const int per = kBlock / W;
+    const int nb = (int)((nn + per - 1) / per);
+    hipLaunchKernelGGL((k_residual_add<W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N, C->desc.strip),
+                       x, d, xn, f, out, C->partials);
+    if (nb > kNormStageMin) {
+      hipLaunchKernelGGL(k_norms_stage, dim3(kNormStage), dim3(kBlock), 0, C->stream, C->partials, nb, C->partials2);
+      hipLaunchKernelGGL(k_finalize_norms, dim3(1), dim3(1024), 0, C->stream, C->partials2, kNormStage, C->norms);
+    } else {
+      hipLaunchKernelGGL(k_finalize_norms, dim3(1), dim3(1024), 0, C->stream, C->partials, nb, C->norms);
+    }
+  });
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
 template <typename T>
 int restrict_to(smg_ctx* C, int nf, const T* fine, T* coarse) {
   const int nc = (nf - 1) / 2;
@@ -1256,12 +1277,21 @@ int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, i
   double fn = -1.0;   // ||f||, from the first residual pass
   double h[5];
   int its = 0, inner = 0, rc = SMG_NOT_CONVERGED;
+  // FP32 stationary refinement keeps its iterate in x or in the scratch vector
+  // C->w, alternately: each update x + d is fused with the next residual.
+  double* xc = x;
   while (true) {
     if (!f32) {
       TRY(residual_norms64(C, x, f, nullptr, h));
     } else if (method == SMG_VCYCLE) {
-      // FP64 residual rounded straight into the FP32 cycle's right-hand side
-      TRY((residual<double, double, float>(C, C->L64[0], x, f, C->L32[0].f, 0, true)));
+      if (its == 0) {
+        // FP64 residual rounded straight into the FP32 cycle's right-hand side
+        TRY((residual<double, double, float>(C, C->L64[0], x, f, C->L32[0].f, 0, true)));
+      } else {
+        double* xo = xc == x ? C->w : x;
+        TRY(residual_add(C, xc, C->L32[0].x, xo, f, C->L32[0].f));
+        xc = xo;
+      }
       HIP_TRY(hipMemcpyAsync(C->host, C->norms, 5 * sizeof(double), hipMemcpyDeviceToHost, C->stream));
       TRY(sync(C));
       for (int i = 0; i < 5; ++i) h[i] = C->host[i];
@@ -1277,10 +1307,7 @@ int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, i
       TRY(vcycle64(C, x, f));
       ++inner;
     } else if (method == SMG_VCYCLE) {
-      TRY(run_cycle<float>(C, C->L32[0].x, C->L32[0].f, true));
-      hipLaunchKernelGGL((k_add<float>), dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, x,
-                         (const float*)C->L32[0].x);
-      LAUNCH_CHECK();
+      TRY(run_cycle<float>(C, C->L32[0].x, C->L32[0].f, true));   // the update waits for the next residual
       ++inner;
     } else {
       int done = 0;
@@ -1292,6 +1319,8 @@ int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, i
     }
     ++its;
   }
+  if (xc != x) HIP_TRY(hipMemcpyAsync(x, xc, C->len0 * sizeof(double), hipMemcpyDeviceToDevice, C->stream));
+  TRY(sync(C));
   if (st) {
     stats_norms(st, h, fn);
     st->iterations = its;
