@@ -36,14 +36,19 @@ struct BTask {
 
 // FP64 outer residual of one instance, rounded into the reduced-precision
 // right-hand side of its correction cycle; the task also owns a range of
-// norm partials (one triple per block).
+// norm partials (one triple per block).  With FP32 corrections (w set) the
+// update of the previous step is fused in: after c correction cycles the
+// iterate lives in x (c even) or w (c odd), and the pass forms it as the other
+// buffer plus the pending correction d.
 template <typename TO>
 struct BOuterTask {
   int inst, W, nitems, block0;
   LevelArgs<double> L;
-  const double* x;
+  double* x;
   const double* f;
   TO* out;
+  double* w;           // second iterate buffer, or null (separate update pass)
+  const TO* d;         // pending correction of the last cycle
 };
 
 template <typename TD>
@@ -139,6 +144,7 @@ __global__ __launch_bounds__(64) void kb_coarse2(const BTask<T>* __restrict__ ta
 template <typename TO, int JM>
 __global__ __launch_bounds__(kBlock) void kb_outer_residual(const BOuterTask<TO>* __restrict__ tasks, int ntasks,
                                                             const int* __restrict__ done,
+                                                            const int* __restrict__ iters,
                                                             double* __restrict__ partials) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const BOuterTask<TO>& t = tasks[find_task(tasks, ntasks, b)];
@@ -147,7 +153,20 @@ __global__ __launch_bounds__(kBlock) void kb_outer_residual(const BOuterTask<TO>
   const int lane = threadIdx.x & (W - 1);
   const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (slot < t.nitems) residual_node<double, double, TO, JM>(t.L, t.x, t.f, t.out, 0, slot, lane, W, acc);
+  const int c = t.w ? iters[t.inst] : 0;
+  if (slot < t.nitems) {
+    if constexpr (std::is_same<TO, float>::value) {
+      if (c > 0) {
+        double* cur = (c & 1) ? t.w : t.x;
+        const double* prev = (c & 1) ? t.x : t.w;
+        residual_add_node<JM>(t.L, prev, t.d, cur, t.f, t.out, slot, lane, W, acc);
+      } else {
+        residual_node<double, double, TO, JM>(t.L, t.x, t.f, t.out, 0, slot, lane, W, acc);
+      }
+    } else {
+      residual_node<double, double, TO, JM>(t.L, t.x, t.f, t.out, 0, slot, lane, W, acc);
+    }
+  }
   double r3[3] = {acc[0], acc[1], acc[2]};
   block_sum<3>(r3);
   if (threadIdx.x == 0) {

@@ -746,6 +746,7 @@ int check_level(const smg_ctx* C, int level, int need_coarser) {
 // the whole step is captured once into a hipGraph.
 struct smg_batch {
   std::vector<smg_ctx*> ctx;
+  std::vector<double*> xs;   // the instances' iterates (solutions out)
   int count = 0, precision = SMG_F64, jm = 1;
   hipStream_t stream = nullptr, cap_stream = nullptr;
   std::string err;
@@ -832,7 +833,10 @@ size_t batch_build(smg_batch* B, double* const* x, const double* const* f, std::
     const int n = C->L64[0].n;
     BOuterTask<T> t{};
     t.inst = i; t.W = B->lanes[i]; t.nitems = n * n; t.block0 = nb;
-    t.L = args(C->L64[0], C->N); t.x = x ? x[i] : nullptr; t.f = f ? f[i] : nullptr; t.out = f0(C);
+    t.L = args(C->L64[0], C->N, C->desc.strip); t.x = x ? x[i] : nullptr; t.f = f ? f[i] : nullptr;
+    t.out = f0(C);
+    if constexpr (std::is_same<T, float>::value) { t.w = C->w; t.d = x0(C); }   // fused update
+    else { t.w = nullptr; t.d = nullptr; }
     const int blocks = groups(i, n * n);
     chk[i].pb0 = nb; chk[i].pnb = blocks; chk[i].fnorm = 1.0;
     nb += blocks;
@@ -909,7 +913,7 @@ size_t batch_build(smg_batch* B, double* const* x, const double* const* f, std::
     sweep_phase(d, 1, kPlain, false);
     for (int s = 1; s < post; ++s) { sweep_phase(d, 0, kPlain, false); sweep_phase(d, 1, kPlain, false); }
   }
-  {
+  if constexpr (std::is_same<T, double>::value) {   // FP32 corrections are added by the next outer pass
     std::vector<BAddTask<T>> as;
     int blocks = 0;
     for (int i = 0; i < cnt; ++i) {
@@ -974,7 +978,8 @@ int batch_launch_step(smg_batch* B, hipStream_t s, double tol, int maxit) {
         jm_dispatch(B->jm, [&](auto Jc) {
           constexpr int JM = decltype(Jc)::value;
           hipLaunchKernelGGL((kb_outer_residual<T, JM>), dim3(nbk), dim3(kBlock), 0, s,
-                             (const BOuterTask<T>*)tasks, nt, (const int*)B->done, B->partials);
+                             (const BOuterTask<T>*)tasks, nt, (const int*)B->done, (const int*)B->iters,
+                             B->partials);
         });
         break;
       case kbCheck:
@@ -1386,6 +1391,7 @@ int smg_batch_setup(smg_ctx* const* ctxs, int count, double* const* x, const dou
   if (rc != SMG_OK) { delete B; return rc; }
   for (int i = 0; i < count; ++i)
     if (!x[i] || !f[i]) { delete B; return SMG_EINVAL; }
+  B->xs.assign(x, x + count);
   for (int i = 0; i < count; ++i) {
     double fn = 0.0;
     rc = vec_norm(ctxs[i], f[i], ctxs[i]->len0, &fn);
@@ -1468,6 +1474,13 @@ int smg_batch_solve(smg_batch* B, double rtol, int maxit, smg_stats* stats, doub
   BHIP(hipMemcpyAsync(td.data(), B->tdone, sizeof(long long) * cnt, hipMemcpyDeviceToHost, s));
   BHIP(hipMemcpyAsync(&t0, B->t0, sizeof(long long), hipMemcpyDeviceToHost, s));
   BHIP(hipStreamSynchronize(s));
+  if (B->precision == SMG_F32) {
+    // iterates after an odd number of FP32 corrections live in the context's w
+    for (int i = 0; i < cnt; ++i)
+      if (its[i] & 1)
+        BHIP(hipMemcpyAsync(B->xs[i], B->ctx[i]->w, B->ctx[i]->len0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    BHIP(hipStreamSynchronize(s));
+  }
   int dev = 0, khz = 0;
   BHIP(hipGetDevice(&dev));
   BHIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
