@@ -59,20 +59,37 @@ def load_traffic(kind: str):
     return t.get("bytes_per_launch")
 
 
-def time_halfsweep(ctx, x, f, stream, launches):
+def time_halfsweep(ctx, x, f, stream, launches, fp32=False):
     """Average duration (us) of `launches` finest-level half-sweeps, HIP events on
-    the library's stream."""
+    the library's stream (fp32: the FP32 smoother on float32 vectors)."""
     import torch
+    smooth = ctx.smooth32 if fp32 else ctx.smooth
     for _ in range(5):
-        ctx.smooth(0, 0, x, f)
+        smooth(0, 0, x, f)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for i in range(launches):
-        ctx.smooth(0, i & 1, x, f)
+        smooth(0, i & 1, x, f)
     e1.record(stream)
     e1.synchronize()
     return 1e3 * e0.elapsed_time(e1) / launches
+
+
+def halfsweep_counter_run(ctx, x, f, n, N):
+    """20 finest-level half-sweeps, then five 1 GiB device copies (the
+    calibration of the traffic counters)."""
+    import torch
+    for i in range(20):
+        ctx.smooth(0, i & 1, x, f)
+    a = torch.ones(1 << 27, dtype=torch.float64, device=x.device)   # 1 GiB
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters": "done", "n": n, "N": N, "halfsweep_launches": 20,
+                      "halfsweep_algorithmic_bytes": halfsweep_bytes(n, N, 8),
+                      "copy_bytes_each_way": a.numel() * 8, "copy_launches": 5}), flush=True)
 
 
 def timed_solve(ctx, x, f, method, rtol, maxit=200):
@@ -133,7 +150,13 @@ def large_mixed_section(dev):
     b64 = halfsweep_bytes(n, N, 8)
     out["roofline_fp64_halfsweep"] = {"avg_launch_us": round(us64, 2), "achieved_GBs": round(b64 / us64 / 1e3, 1),
                                       "frac": round(b64 / us64 / 1e3 / HBM_PEAK_GBS, 4)}
-    del x64, xs
+    x32 = torch.zeros(dof, dtype=torch.float32, device=dev)
+    f32 = f.float()
+    us32 = time_halfsweep(c32, x32, f32, c32.stream, 50, fp32=True)
+    b32 = halfsweep_bytes(n, N, 4)
+    out["roofline_fp32_halfsweep"] = {"avg_launch_us": round(us32, 2), "achieved_GBs": round(b32 / us32 / 1e3, 1),
+                                      "frac": round(b32 / us32 / 1e3 / HBM_PEAK_GBS, 4)}
+    del x64, xs, x32, f32
     return out, c32, f, x
 
 
@@ -235,8 +258,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune_lanes.json"))
-    ap.add_argument("--counters", action="store_true",
-                    help="launch only the finest-level half-sweep (20x) and a 1 GiB device copy (5x), "
+    ap.add_argument("--counters", nargs="?", const="medium", choices=["medium", "large"],
+                    help="launch only the finest-level FP64 half-sweep (20x) of the 255x255, N=64 "
+                         "(medium) or 511x511, N=256 (large) workload and a 1 GiB device copy (5x), "
                          "for hardware-counter passes")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -251,6 +275,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.counters == "large":
+        prob = inputs.large_mixed()
+        ctx, f = binding.context_from_problem(prob, device=dev, gmres_restart=0)
+        x = torch.zeros(prob.dof, dtype=torch.float64, device=dev)
+        halfsweep_counter_run(ctx, x, f, prob.n, prob.N)
+        return
     prob = inputs.medium_fp64()
     n, N = prob.n, prob.N
     dof = prob.dof
@@ -260,16 +290,7 @@ def main():
     levels = list(ctx.levels_n)
 
     if args.counters:
-        for i in range(20):
-            ctx.smooth(0, i & 1, x, f)
-        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"counters": "done", "halfsweep_launches": 20,
-                          "halfsweep_algorithmic_bytes": halfsweep_bytes(n, N, 8),
-                          "copy_bytes_each_way": a.numel() * 8, "copy_launches": 5}), flush=True)
+        halfsweep_counter_run(ctx, x, f, n, N)
         return
 
     def solve(method, rtol):
@@ -322,11 +343,26 @@ def main():
     t_launch_us = 1e3 * ev0.elapsed_time(ev1) / args.sweeps
     bytes_launch = halfsweep_bytes(n, N, 8)
     achieved = bytes_launch / (t_launch_us * 1e-6) / 1e9
+    # achievable-bandwidth reference: the library's plain streaming copy, 2 GiB moved per launch
+    ca = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        binding.stream_copy(cb, ca)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        binding.stream_copy(cb, ca)
+    c1.record()
+    c1.synchronize()
+    copy_gbs = 2 * ca.numel() * 8 / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
+    del ca, cb
     traffic = load_traffic("halfsweep_f64_medium")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_halfsweep<double,64,1> (finest level)", "avg_launch_us": round(t_launch_us, 2),
-                "algorithmic_bytes_per_launch": bytes_launch}
+                "algorithmic_bytes_per_launch": bytes_launch,
+                "stream_copy_GBs": round(copy_gbs, 1)}
 
     extra = {}
     if not args.quick:

@@ -161,6 +161,18 @@ int smg_residual(smg_ctx *ctx, const double *x, const double *f, double *r, doub
  * x, f: FP64 device vectors of that level's size. */
 int smg_smooth(smg_ctx *ctx, int level, int colour, double *x, const double *f);
 
+/* Device-to-device copy of `bytes` (a multiple of 16, both pointers 16-byte
+ * aligned) by a plain streaming kernel with 16-byte accesses, on `stream`
+ * (hipStream_t, NULL = default): the achievable-bandwidth reference quoted
+ * next to the kernels' rooflines.  SMG_EINVAL for bad sizes or alignment. */
+int smg_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* The same half-sweep in FP32 arithmetic on FP32 device vectors x, f of the
+ * level's size, with the context's FP32 copy of the level operator (the
+ * smoother of the FP32 cycle).  SMG_EINVAL unless the context was set up with
+ * precision SMG_F32. */
+int smg_smooth32(smg_ctx *ctx, int level, int colour, float *x, const float *f);
+
 /* coarse = R fine (R = P^T, full weighting with weights 1, 1/2, 1/4), fine of
  * level `level`, coarse of level + 1, all 2N+1 fields.  FP64 device vectors. */
 int smg_restrict(smg_ctx *ctx, int level, const double *fine, double *coarse);

@@ -53,6 +53,7 @@ def _load():
     L.or_apply.argtypes = [vp, C.c_int, _dp, _dp]
     L.or_residual.argtypes = [vp, C.c_int, _dp, _dp, _dp]
     L.or_halfsweep.argtypes = [vp, C.c_int, C.c_int, C.c_double, _dp, _dp]
+    L.or_halfsweep32.argtypes = [vp, C.c_int, C.c_int, C.c_double, _dp, _dp]
     L.or_jacobi.argtypes = [vp, C.c_int, C.c_double, _dp, _dp]
     L.or_restrict.argtypes = [C.c_int, C.c_int, _dp, _dp]
     L.or_prolong_add.argtypes = [C.c_int, C.c_int, _dp, _dp]
@@ -175,6 +176,12 @@ class Oracle:
     def halfsweep(self, x, f, colour: int, l: int = 0, theta: float = 1.0):
         x = _f64(x).copy()
         _load().or_halfsweep(self.ctx, l, colour, theta, x, _f64(f))
+        return x
+
+    def halfsweep32(self, x, f, colour: int, l: int = 0, theta: float = 1.0):
+        """The half-sweep in FP32 arithmetic (x, f rounded to FP32), widened back."""
+        x = _f64(x).copy()
+        _load().or_halfsweep32(self.ctx, l, colour, theta, x, _f64(f))
         return x
 
     def jacobi(self, x, f, theta: float, l: int = 0):

@@ -373,6 +373,16 @@ void or_vcycle32(or_ctx *C, double *x, const double *f, int ncycles) {
   free(x32); free(f32);
 }
 
+/* One FP32 half-sweep of level l on FP64 in/out buffers (x and f rounded to
+ * FP32 first, the result widened back): the reference of the FP32 smoother. */
+void or_halfsweep32(const or_ctx *C, int l, int colour, double theta, double *x, const double *f) {
+  size_t len = vlen(C->n[l], C->N);
+  float *x32 = to_f32(x, len), *f32 = to_f32(f, len);
+  or_halfsweep_f32(&C->L32[l], colour, (float)theta, x32, f32);
+  for (size_t i = 0; i < len; ++i) x[i] = (double)x32[i];
+  free(x32); free(f32);
+}
+
 /* threads the node loops run on (the CPU baseline reports it) */
 int or_num_threads(void) {
 #ifdef _OPENMP

@@ -24,7 +24,7 @@ SMG_FLAG_UNFUSED = 2
 
 EXPORTED = [
     "smg_workspace_bytes", "smg_setup", "smg_destroy", "smg_strerror", "smg_last_error",
-    "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_smooth", "smg_restrict",
+    "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_stream_copy", "smg_restrict",
     "smg_prolong_add", "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond",
     "smg_solve", "smg_batch_workspace_bytes", "smg_batch_setup", "smg_batch_solve", "smg_batch_destroy",
     "smg_batch_last_error", "smg_tune_lanes", "smg_net_param_count", "smg_net_workspace_bytes",
@@ -85,6 +85,9 @@ def load(path: str = LIB_PATH):
     L.smg_apply.argtypes = [vp, vp, vp]
     L.smg_residual.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
     L.smg_smooth.argtypes = [vp, i, i, vp, vp]
+    L.smg_smooth32.argtypes = [vp, i, i, vp, vp]
+    L.smg_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    L.smg_stream_copy.restype = i
     L.smg_restrict.argtypes = [vp, i, vp, vp]
     L.smg_prolong_add.argtypes = [vp, i, vp, vp]
     L.smg_coarse_solve.argtypes = [vp, vp, vp]
@@ -125,7 +128,7 @@ def load(path: str = LIB_PATH):
     for name in ["smg_net_set_params", "smg_net_get_params", "smg_net_forward", "smg_net_grad",
                  "smg_net_train_step", "smg_net_features", "smg_net_targets", "smg_net_lift"]:
         getattr(L, name).restype = i
-    for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_restrict", "smg_prolong_add",
+    for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_stream_copy", "smg_restrict", "smg_prolong_add",
                  "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond", "smg_solve",
                  "smg_num_levels", "smg_level_n"]:
         getattr(L, name).restype = i
@@ -219,6 +222,10 @@ class Context:
     def smooth(self, level, colour, x, f):
         return self._check(self.L.smg_smooth(self.ctx, level, colour, _ptr(x), _ptr(f)))
 
+    def smooth32(self, level, colour, x, f):
+        """FP32 half-sweep on float32 device vectors (SMG_F32 contexts)."""
+        return self._check(self.L.smg_smooth32(self.ctx, level, colour, _ptr(x), _ptr(f)))
+
     def restrict(self, level, fine, coarse):
         return self._check(self.L.smg_restrict(self.ctx, level, _ptr(fine), _ptr(coarse)))
 
@@ -300,6 +307,19 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def stream_copy(dst, src, stream=None):
+    """Copy src into dst (same byte size, device tensors) with the library's plain
+    streaming kernel on `stream` (default: the current stream)."""
+    import torch
+    L = load()
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    rc = L.smg_stream_copy(_ptr(dst), _ptr(src), nbytes, C.c_void_p(s.cuda_stream))
+    if rc != SMG_OK:
+        raise SmgError(rc, L.smg_strerror(rc).decode())
 
 
 def tune_lanes(ctx):

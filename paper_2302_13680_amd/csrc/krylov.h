@@ -5,6 +5,13 @@
 namespace smg {
 
 // ---------------------------------------------------------- vector kernels
+// Plain streaming copy, 16 bytes per lane and step (the bandwidth reference).
+__global__ __launch_bounds__(kBlock) void k_stream_copy(size_t n16, const double2* __restrict__ src,
+                                                        double2* __restrict__ dst) {
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n16; i += (size_t)gridDim.x * kBlock)
+    dst[i] = src[i];
+}
+
 template <typename TI, typename TO>
 __global__ void k_convert(size_t len, const TI* __restrict__ in, TO* __restrict__ out) {
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < len; i += (size_t)gridDim.x * kBlock)

@@ -1194,6 +1194,22 @@ int smg_smooth(smg_ctx* C, int level, int colour, double* x, const double* f) {
   return halfsweep<double>(C, C->L64[level], x, f, colour);
 }
 
+int smg_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || (bytes & 15) || (((uintptr_t)dst | (uintptr_t)src) & 15)) return SMG_EINVAL;
+  const size_t n16 = bytes / 16;
+  if (n16 == 0) return SMG_OK;
+  const size_t blocks = std::min<size_t>((n16 + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream, n16,
+                     (const double2*)src, (double2*)dst);
+  return hipGetLastError() == hipSuccess ? SMG_OK : SMG_EHIP;
+}
+
+int smg_smooth32(smg_ctx* C, int level, int colour, float* x, const float* f) {
+  if (!C || !x || !f || (colour != 0 && colour != 1) || C->desc.precision != SMG_F32) return SMG_EINVAL;
+  TRY(check_level(C, level, 0));
+  return halfsweep<float>(C, C->L32[level], x, f, colour);
+}
+
 int smg_restrict(smg_ctx* C, int level, const double* fine, double* coarse) {
   if (!C || !fine || !coarse) return SMG_EINVAL;
   TRY(check_level(C, level, 1));

@@ -292,3 +292,25 @@ def test_medium_size_cycle_against_oracle(B, O):
         x_o = o.vcycle(x_o, p.rhs_paper(), 1)
         ctx.vcycle(xd, f, 1)
         assert rel(node_to_paper(host(xd), p.n, p.N), x_o) <= 1e-12
+
+
+@pytest.mark.parametrize("n,N", [(63, 16), (31, 100), (15, 256)])
+def test_fp32_halfsweeps_against_fp32_oracle(B, O, n, N):
+    """The FP32 smoother (smg_smooth32) against the oracle's half-sweep in FP32
+    arithmetic from the same FP32-rounded iterate: agreement to FP32 rounding."""
+    p = mk(n, N, seed=3 * n + N)
+    o = O.Oracle(p, coarsest_n=7)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0, precision=B.SMG_F32)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(o.vlen()).astype(np.float32).astype(np.float64)
+    fp = p.rhs_paper().astype(np.float32).astype(np.float64)
+    xd = torch.from_numpy(paper_to_node(x, n, N).astype(np.float32)).cuda()
+    fd = torch.from_numpy(paper_to_node(fp, n, N).astype(np.float32)).cuda()
+    for colour in (0, 1, 0, 1):
+        x = o.halfsweep32(x, fp, colour)
+        ctx.smooth32(0, colour, xd, fd)
+        got = node_to_paper(host(xd).astype(np.float64), n, N)
+        assert rel(got, x) <= 2e-6, colour
+    with pytest.raises(B.SmgError):
+        c64, _ = B.context_from_problem(p, gmres_restart=0)
+        c64.smooth32(0, 0, xd, fd)
