@@ -227,8 +227,11 @@ size_t smg_batch_workspace_bytes(smg_ctx *const *ctxs, int count);
 
 /* Bind the instances' FP64 device vectors x[i] (initial guess in, solution
  * out) and f[i] to a batch.  lanes (host, may be NULL): lanes per grid node of
- * each instance (power of two <= 64 with nsamples/lanes <= 8), e.g. from
- * smg_tune_lanes; NULL picks min(64, pow2ceil(N)).  Computes ||f_i|| and
+ * each instance (power of two <= 64 with at most 8 samples per lane), e.g. from
+ * smg_tune_lanes; NULL picks the single-instance width: min(64, pow2ceil(N)),
+ * or min(64, pow2ceil(N/2)) for an SMG_F32 context with even N (whose FP32
+ * kernels take two consecutive samples per access when every instance's N is
+ * even).  Computes ||f_i|| and
  * copies the launch tables into the workspace (>= smg_batch_workspace_bytes,
  * 256-byte aligned, caller-owned). */
 int smg_batch_setup(smg_ctx *const *ctxs, int count, double *const *x, const double *const *f,
@@ -246,8 +249,9 @@ void smg_batch_destroy(smg_batch *batch);
 const char *smg_batch_last_error(const smg_batch *batch);
 
 /* Autotuner of the lanes-per-node width of the batched half-sweep for one
- * context: times the finest-level red half-sweep for each width W in
- * {64, 32, 16, 8} (W <= pow2ceil(N), N/W <= 8) with HIP events on the
+ * context: times the finest-level red half-sweep for each power-of-two width W
+ * up to the default one (see smg_batch_setup) with at most 8 samples per lane,
+ * with HIP events on the
  * context's stream.  lanes/us (host, cap entries) receive the candidates and
  * their average launch time in microseconds, *ncand their number, *best the
  * fastest width.  Overwrites the context's scratch vectors. */

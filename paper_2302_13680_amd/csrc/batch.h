@@ -79,7 +79,7 @@ __device__ __forceinline__ int find_task(const Task* __restrict__ tasks, int nta
   return s_idx;
 }
 
-template <typename T, int JM, int SRC>
+template <typename T, int JM, int SRC, int VW>
 __global__ __launch_bounds__(kBlock) void kb_halfsweep(const BTask<T>* __restrict__ tasks, int ntasks, int colour,
                                                        const int* __restrict__ done) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -89,11 +89,11 @@ __global__ __launch_bounds__(kBlock) void kb_halfsweep(const BTask<T>* __restric
   const int lane = threadIdx.x & (W - 1);
   const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
   if (slot >= t.nitems) return;
-  halfsweep_node<T, JM, SRC>(t.L, t.x, t.f, colour, T(1), slot, lane, W, t.b);
+  halfsweep_node<T, JM, SRC, VW>(t.L, t.x, t.f, colour, T(1), slot, lane, W, t.b);
 }
 
 // level residual r = f - S x into t.a
-template <typename T, int JM>
+template <typename T, int JM, int VW>
 __global__ __launch_bounds__(kBlock) void kb_residual(const BTask<T>* __restrict__ tasks, int ntasks,
                                                       const int* __restrict__ done) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -104,11 +104,11 @@ __global__ __launch_bounds__(kBlock) void kb_residual(const BTask<T>* __restrict
   const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
   if (slot >= t.nitems) return;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  residual_node<T, T, T, JM>(t.L, t.x, t.f, t.a, 0, slot, lane, W, acc);
+  residual_node<T, T, T, JM, VW>(t.L, t.x, t.f, t.a, 0, slot, lane, W, acc);
 }
 
 // coarse right-hand side t.a = R t.b (t.b: fine residual of grid t.L.n)
-template <typename T, int JM>
+template <typename T, int JM, int VW>
 __global__ __launch_bounds__(kBlock) void kb_restrict(const BTask<T>* __restrict__ tasks, int ntasks,
                                                       const int* __restrict__ done) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void kb_restrict(const BTask<T>* __restrict
   const int lane = threadIdx.x & (W - 1);
   const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
   if (slot >= t.nitems) return;
-  restrict_node<T, JM>(t.L.n, t.L.N, t.b, t.a, slot, lane, W, coarse_strip(t.L.strip));
+  restrict_node<T, JM, VW>(t.L.n, t.L.N, t.b, t.a, slot, lane, W, coarse_strip(t.L.strip));
 }
 
 // coarsest direct solve, one block per (instance, sample)

@@ -3,14 +3,18 @@
 // Layout (see include/smg.h): samples innermost.  A level vector is
 //   Y [n][n][N] | U [n][n] | P [n][n][N];  faces kx [n][n+1][N], ky [n+1][n][N].
 // A node's N samples are contiguous, so a group of W lanes of one wavefront
-// (W = 1..64, a power of two) holds one node and each lane handles JM samples
-// j = lane, lane + W, ...; the reductions over samples that the node solve and
+// (W = 1..64, a power of two) holds one node and each lane handles JM samples,
+// in chunks of VW consecutive ones: chunk c of a lane holds samples
+// VW (lane + c W) + [0, VW) (VW = 2 needs N even; FP32 uses it so that every
+// access is 8 bytes); the reductions over samples that the node solve and
 // the control row need stay inside that group (DPP lane moves and reads of row
 // sums, group_sum).  Every lane of a group ends with the bitwise-same sum (IEEE
 // addition is commutative), so all lanes agree on u_i.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace smg {
 
@@ -39,6 +43,33 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
   const int q = nblocks / kNumXcd, r = nblocks % kNumXcd;
   const int xcd = b % kNumXcd, idx = b / kNumXcd;
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// VW consecutive samples as one access (VW = 2: an 8-byte float2 or a 16-byte
+// double2; the address is a multiple of VW elements from a 256-byte aligned base).
+template <int VW, typename T>
+__device__ __forceinline__ void ldv(const T* __restrict__ p, T (&v)[VW]) {
+  if constexpr (VW == 1) {
+    v[0] = *p;
+  } else {
+    static_assert(VW == 2, "one or two samples per access");
+    using V2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+    const V2 t = *reinterpret_cast<const V2*>(p);
+    v[0] = t.x;
+    v[1] = t.y;
+  }
+}
+template <int VW, typename T>
+__device__ __forceinline__ void stv(T* __restrict__ p, const T (&v)[VW]) {
+  if constexpr (VW == 1) {
+    *p = v[0];
+  } else {
+    using V2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+    V2 t;
+    t.x = v[0];
+    t.y = v[1];
+    *reinterpret_cast<V2*>(p) = t;
+  }
 }
 
 // Move a value between lanes of a row of 16 lanes with DPP (CTRL: 0xB1 = xor 1

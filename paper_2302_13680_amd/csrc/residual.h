@@ -10,10 +10,12 @@ namespace smg {
 // Faces and arithmetic in T, x and f in TX, out in TO (out may be null).
 // acc[0..2] accumulate the squared Y, U (lane 0) and P residual entries, acc[3]
 // the squared entries of f (mode 0), which gives ||f|| in the same pass.
-template <typename T, typename TX, typename TO, int JM>
+template <typename T, typename TX, typename TO, int JM, int VW = 1>
 __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* __restrict__ x,
                                               const TX* __restrict__ f, TO* __restrict__ out, int mode,
                                               int slot, int lane, int W, double (&acc)[4]) {
+  static_assert(JM % VW == 0, "whole chunks per lane");
+  constexpr int NCH = JM / VW;
   const int n = L.n, N = L.N;
   const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
   int xx, k;
@@ -25,44 +27,67 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
   const size_t kxb = ((size_t)k * (n + 1) + xx) * N;
   const size_t kyb = node * N;
   const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
-  // Unconditional loads: a missing neighbour reads the node itself and a sample
-  // j >= N reads sample N-1; both are selected away (see halfsweep_node).
+  // Unconditional loads: a missing neighbour reads the node itself and a chunk
+  // past N reads the last chunk; both are selected away (see halfsweep_node).
   const ptrdiff_t ow = hw ? -(ptrdiff_t)N : 0, oe = he ? (ptrdiff_t)N : 0;
   const ptrdiff_t os = hs ? -(ptrdiff_t)rowN : 0, on = hn ? (ptrdiff_t)rowN : 0;
   T dsum = 0;
 #pragma unroll
-  for (int q = 0; q < JM; ++q) {
-    const int j0 = lane + q * W;
+  for (int c = 0; c < NCH; ++c) {
+    const int j0 = VW * (lane + c * W);
     const bool act = j0 < N;
-    const int j = act ? j0 : N - 1;
-    const T kw = L.kx[kxb + j], ke = L.kx[kxb + N + j];
-    const T ks = L.ky[kyb + j], kn = L.ky[kyb + rowN + j];
+    const int j = act ? j0 : N - VW;
+    T kw[VW], ke[VW], ks[VW], kn[VW];
+    ldv<VW>(L.kx + kxb + j, kw);
+    ldv<VW>(L.kx + kxb + N + j, ke);
+    ldv<VW>(L.ky + kyb + j, ks);
+    ldv<VW>(L.ky + kyb + rowN + j, kn);
     const size_t base = node * N + j;
-    const T y0 = (T)Y[base], p0 = (T)P[base];
-    auto nbsum = [&](T vw, T ve, T vs, T vn) -> T {
-      return ((hw ? kw * vw : T(0)) + (he ? ke * ve : T(0))) + ((hs ? ks * vs : T(0)) + (hn ? kn * vn : T(0)));
-    };
-    const T sy = nbsum((T)Y[base + ow], (T)Y[base + oe], (T)Y[base + os], (T)Y[base + on]);
-    const T sp = nbsum((T)P[base + ow], (T)P[base + oe], (T)P[base + os], (T)P[base + on]);
-    const T a = (kw + ke) + (ks + kn);
-    T rY = L.c[j] * y0 + (a * p0 - sp);     // C_j y_j + A_j^T p_j
-    T rP = (a * y0 - sy) + L.e[j] * u;      // A_j y_j + E_j u
-    dsum += act ? L.d[j] * p0 : T(0);
-    double ff = 0.0;
+    TX y0[VW], p0[VW], yw[VW], ye[VW], ys[VW], yn[VW], pw[VW], pe[VW], ps[VW], pn[VW];
+    ldv<VW>(Y + base, y0); ldv<VW>(P + base, p0);
+    ldv<VW>(Y + base + ow, yw); ldv<VW>(Y + base + oe, ye); ldv<VW>(Y + base + os, ys); ldv<VW>(Y + base + on, yn);
+    ldv<VW>(P + base + ow, pw); ldv<VW>(P + base + oe, pe); ldv<VW>(P + base + os, ps); ldv<VW>(P + base + on, pn);
+    T cj[VW], dj[VW], ej[VW];
+    ldv<VW>(L.c + j, cj);
+    ldv<VW>(L.d + j, dj);
+    ldv<VW>(L.e + j, ej);
+    TX fyv[VW], fpv[VW];
     if (mode == 0) {
-      const T fy = (T)f[base], fp = (T)f[(size_t)(N + 1) * nn + base];
-      rY = fy - rY;
-      rP = fp - rP;
-      ff = (double)fy * (double)fy + (double)fp * (double)fp;
+      ldv<VW>(f + base, fyv);
+      ldv<VW>(f + (size_t)(N + 1) * nn + base, fpv);
     }
-    if (act) {
-      if (out) {
-        out[base] = (TO)rY;
-        out[(size_t)(N + 1) * nn + base] = (TO)rP;
+    TO ry[VW], rp[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) {
+      auto nbsum = [&](T vw, T ve, T vs, T vn) -> T {
+        return ((hw ? kw[q] * vw : T(0)) + (he ? ke[q] * ve : T(0))) +
+               ((hs ? ks[q] * vs : T(0)) + (hn ? kn[q] * vn : T(0)));
+      };
+      const T sy = nbsum((T)yw[q], (T)ye[q], (T)ys[q], (T)yn[q]);
+      const T sp = nbsum((T)pw[q], (T)pe[q], (T)ps[q], (T)pn[q]);
+      const T a = (kw[q] + ke[q]) + (ks[q] + kn[q]);
+      const T yq = (T)y0[q], pq = (T)p0[q];
+      T rY = cj[q] * yq + (a * pq - sp);     // C_j y_j + A_j^T p_j
+      T rP = (a * yq - sy) + ej[q] * u;      // A_j y_j + E_j u
+      dsum += act ? dj[q] * pq : T(0);
+      double ff = 0.0;
+      if (mode == 0) {
+        const T fy = (T)fyv[q], fp = (T)fpv[q];
+        rY = fy - rY;
+        rP = fp - rP;
+        ff = (double)fy * (double)fy + (double)fp * (double)fp;
       }
-      acc[0] += (double)rY * (double)rY;
-      acc[2] += (double)rP * (double)rP;
-      acc[3] += ff;
+      ry[q] = (TO)rY;
+      rp[q] = (TO)rP;
+      if (act) {
+        acc[0] += (double)rY * (double)rY;
+        acc[2] += (double)rP * (double)rP;
+        acc[3] += ff;
+      }
+    }
+    if (act && out) {
+      stv<VW>(out + base, ry);
+      stv<VW>(out + (size_t)(N + 1) * nn + base, rp);
     }
   }
   dsum = group_sum_w(dsum, W);
@@ -162,7 +187,7 @@ void k_residual_add(LevelArgs<double> L, const double* __restrict__ x, const flo
 
 // out = f - S x (mode 0) or out = S x (mode 1) over every node.  partials (if not
 // null) receives per block { sum r_Y^2, sum r_U^2, sum r_P^2, sum f^2 }.
-template <typename T, typename TX, typename TO, int W, int JM>
+template <typename T, typename TX, typename TO, int W, int JM, int VW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, JM >= 4 ? 3 : 8)))
 void k_residual(LevelArgs<T> L, const TX* __restrict__ x, const TX* __restrict__ f, TO* __restrict__ out,
                 int mode, double* __restrict__ partials) {
@@ -170,7 +195,7 @@ void k_residual(LevelArgs<T> L, const TX* __restrict__ x, const TX* __restrict__
   const int lane = threadIdx.x & (W - 1);
   const int slot = b * (kBlock / W) + threadIdx.x / W;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (slot < L.n * L.n) residual_node<T, TX, TO, JM>(L, x, f, out, mode, slot, lane, W, acc);
+  if (slot < L.n * L.n) residual_node<T, TX, TO, JM, VW>(L, x, f, out, mode, slot, lane, W, acc);
   if (partials) {
     block_sum<4>(acc);
     if (threadIdx.x == 0) {

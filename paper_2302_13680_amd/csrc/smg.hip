@@ -74,6 +74,40 @@ void seg_dispatch(int N, F&& fn) {
   else fn(IC<64>{}, IC<8>{});
 }
 
+// Lanes per node W, samples per lane JM and samples per access VW of a
+// context's level kernels.  FP64 contexts, and FP32 contexts with odd N: one
+// sample per access, W = min(64, pow2ceil(N)).  FP32 contexts with even N:
+// W = min(64, pow2ceil(N/2)) lanes with two samples per access in FP32
+// arithmetic (8-byte accesses; 4-byte ones stream at ~65% of the 8-byte rate);
+// the FP64 kernels of such a context keep one sample per access on the same W
+// and JM, so the batched solver (which uses the same widths) reproduces them.
+bool vec2_ctx(int precision, int N) { return precision == SMG_F32 && (N & 1) == 0; }
+
+// The FP32 half-sweep keeps one sample per access with four or more samples per
+// lane: measured at 511x511, N=256 it runs 271 us that way against 283-291 us
+// with pairs (the residual and restriction gain from pairs at every N).
+constexpr int halfsweep_vw(int vw, int jm) { return vw == 2 && jm == 2 ? 2 : 1; }
+
+template <bool kVec2, typename F>
+void lane_dispatch(int precision, int N, F&& fn) {
+  if (vec2_ctx(precision, N)) {
+    auto go = [&](auto Wc, auto Jc) {
+      if constexpr (kVec2) fn(Wc, Jc, IC<2>{}); else fn(Wc, Jc, IC<1>{});
+    };
+    if (N <= 2) go(IC<1>{}, IC<2>{});
+    else if (N <= 4) go(IC<2>{}, IC<2>{});
+    else if (N <= 8) go(IC<4>{}, IC<2>{});
+    else if (N <= 16) go(IC<8>{}, IC<2>{});
+    else if (N <= 32) go(IC<16>{}, IC<2>{});
+    else if (N <= 64) go(IC<32>{}, IC<2>{});
+    else if (N <= 128) go(IC<64>{}, IC<2>{});
+    else if (N <= 256) go(IC<64>{}, IC<4>{});
+    else go(IC<64>{}, IC<8>{});
+  } else {
+    seg_dispatch(N, [&](auto Wc, auto Jc) { fn(Wc, Jc, IC<1>{}); });
+  }
+}
+
 int count_levels(int n, int nc) {
   int nl = 1, t = n;
   while (t > nc) {
@@ -269,18 +303,20 @@ int halfsweep(smg_ctx* C, const Level<T>& L, T* x, const T* f, int colour, int s
               const T* ec = nullptr) {
   const int nact = colour_count(L.n, colour);
   const T theta = (T)C->desc.theta;
-  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
+  const LevelArgs<T> a = args(L, C->N, C->desc.strip);
+  lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    constexpr int VW = halfsweep_vw(decltype(Vc)::value, JM);
     const int per = kBlock / W, nb = (nact + per - 1) / per;
     if (src == kZero)
-      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kZero>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N, C->desc.strip), x,
-                         f, colour, theta, nact, ec);
+      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kZero, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f, colour,
+                         theta, nact, ec);
     else if (src == kProlong)
-      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kProlong>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N, C->desc.strip),
-                         x, f, colour, theta, nact, ec);
+      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kProlong, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f,
+                         colour, theta, nact, ec);
     else
-      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kPlain>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N, C->desc.strip), x,
-                         f, colour, theta, nact, ec);
+      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kPlain, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f, colour,
+                         theta, nact, ec);
   });
   LAUNCH_CHECK();
   return SMG_OK;
@@ -291,11 +327,11 @@ int halfsweep(smg_ctx* C, const Level<T>& L, T* x, const T* f, int colour, int s
 template <typename T, typename TX, typename TO>
 int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, int mode, bool want_norm) {
   const size_t nn = (size_t)L.n * L.n;
-  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
-    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+  lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value, VW = decltype(Vc)::value;
     const int per = kBlock / W;
     const int nb = (int)((nn + per - 1) / per);
-    hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream,
+    hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM, VW>), dim3(nb), dim3(kBlock), 0, C->stream,
                        args(L, C->N, C->desc.strip), x, f,
                        out, mode, want_norm ? C->partials : (double*)nullptr);
     if (want_norm) {
@@ -317,7 +353,7 @@ int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, i
 int residual_add(smg_ctx* C, const double* x, const float* d, double* xn, const double* f, float* out) {
   const Level<double>& L = C->L64[0];
   const size_t nn = (size_t)L.n * L.n;
-  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
+  lane_dispatch<false>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     const int per = kBlock / W;
     const int nb = (int)((nn + per - 1) / per);
@@ -337,10 +373,10 @@ int residual_add(smg_ctx* C, const double* x, const float* d, double* xn, const 
 template <typename T>
 int restrict_to(smg_ctx* C, int nf, const T* fine, T* coarse) {
   const int nc = (nf - 1) / 2;
-  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
-    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+  lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value, VW = decltype(Vc)::value;
     const int per = kBlock / W, nb = (nc * nc + per - 1) / per;
-    hipLaunchKernelGGL((k_restrict<T, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, nf, C->N, fine, coarse,
+    hipLaunchKernelGGL((k_restrict<T, W, JM, VW>), dim3(nb), dim3(kBlock), 0, C->stream, nf, C->N, fine, coarse,
                        coarse_strip(strip_for(nf, C->desc.strip)));
   });
   LAUNCH_CHECK();
@@ -350,7 +386,7 @@ int restrict_to(smg_ctx* C, int nf, const T* fine, T* coarse) {
 template <typename T>
 int prolong_add(smg_ctx* C, int nc, const T* coarse, T* fine) {
   const int nf = 2 * nc + 1;
-  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
+  lane_dispatch<false>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     const int per = kBlock / W, nb = (nf * nf + per - 1) / per;
     hipLaunchKernelGGL((k_prolong_add<T, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, nc, C->N, coarse, fine);
@@ -748,6 +784,7 @@ struct smg_batch {
   std::vector<smg_ctx*> ctx;
   std::vector<double*> xs;   // the instances' iterates (solutions out)
   int count = 0, precision = SMG_F64, jm = 1;
+  int vw = 1;                // samples per access of the correction kernels (2: FP32, every N even)
   hipStream_t stream = nullptr, cap_stream = nullptr;
   std::string err;
   std::vector<int> lanes;
@@ -777,11 +814,16 @@ namespace {
 
 enum BPhaseKind { kbOuter, kbCheck, kbSweep, kbResidual, kbRestrict, kbCoarse1, kbCoarse2, kbAdd };
 
-int default_lanes(int N) {
+// Lanes per node of an instance by default (the single-instance widths).
+int default_lanes(int N, int precision) {
+  const int M = vec2_ctx(precision, N) ? N / 2 : N;
   int W = 1;
-  while (W < N && W < 64) W <<= 1;
+  while (W < M && W < 64) W <<= 1;
   return W;
 }
+
+// Samples per lane of an instance with W lanes and vw samples per access.
+int samples_per_lane(int N, int W, int vw) { return vw * ((N + vw * W - 1) / (vw * W)); }
 
 int pow2_ok(int W) { return W >= 1 && W <= 64 && (W & (W - 1)) == 0; }
 
@@ -959,6 +1001,21 @@ void jm_dispatch(int jm, F&& fn) {
   else fn(IC<8>{});
 }
 
+// (JM, VW) of the batched correction kernels in arithmetic T (two samples per
+// access only for FP32, JM then even).
+template <typename T, typename F>
+void jmv_dispatch(int jm, int vw, F&& fn) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (vw == 2) {
+      if (jm <= 2) fn(IC<2>{}, IC<2>{});
+      else if (jm <= 4) fn(IC<4>{}, IC<2>{});
+      else fn(IC<8>{}, IC<2>{});
+      return;
+    }
+  }
+  jm_dispatch(jm, [&](auto Jc) { fn(Jc, IC<1>{}); });
+}
+
 #define BHIP(call)                                                           \
   do {                                                                       \
     hipError_t e_ = (call);                                                  \
@@ -987,30 +1044,30 @@ int batch_launch_step(smg_batch* B, hipStream_t s, double tol, int maxit) {
                            (const double*)B->partials, tol, maxit, B->done, B->iters, B->relres, B->tdone);
         break;
       case kbSweep:
-        jm_dispatch(B->jm, [&](auto Jc) {
-          constexpr int JM = decltype(Jc)::value;
+        jmv_dispatch<T>(B->jm, B->vw, [&](auto Jc, auto Vc) {
+          constexpr int JM = decltype(Jc)::value, VW = halfsweep_vw(decltype(Vc)::value, JM);
           if (p.src == kZero)
-            hipLaunchKernelGGL((kb_halfsweep<T, JM, kZero>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks,
-                               nt, p.colour, (const int*)B->done);
+            hipLaunchKernelGGL((kb_halfsweep<T, JM, kZero, VW>), dim3(nbk), dim3(kBlock), 0, s,
+                               (const BTask<T>*)tasks, nt, p.colour, (const int*)B->done);
           else if (p.src == kProlong)
-            hipLaunchKernelGGL((kb_halfsweep<T, JM, kProlong>), dim3(nbk), dim3(kBlock), 0, s,
+            hipLaunchKernelGGL((kb_halfsweep<T, JM, kProlong, VW>), dim3(nbk), dim3(kBlock), 0, s,
                                (const BTask<T>*)tasks, nt, p.colour, (const int*)B->done);
           else
-            hipLaunchKernelGGL((kb_halfsweep<T, JM, kPlain>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks,
-                               nt, p.colour, (const int*)B->done);
+            hipLaunchKernelGGL((kb_halfsweep<T, JM, kPlain, VW>), dim3(nbk), dim3(kBlock), 0, s,
+                               (const BTask<T>*)tasks, nt, p.colour, (const int*)B->done);
         });
         break;
       case kbResidual:
-        jm_dispatch(B->jm, [&](auto Jc) {
-          constexpr int JM = decltype(Jc)::value;
-          hipLaunchKernelGGL((kb_residual<T, JM>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks, nt,
+        jmv_dispatch<T>(B->jm, B->vw, [&](auto Jc, auto Vc) {
+          constexpr int JM = decltype(Jc)::value, VW = decltype(Vc)::value;
+          hipLaunchKernelGGL((kb_residual<T, JM, VW>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks, nt,
                              (const int*)B->done);
         });
         break;
       case kbRestrict:
-        jm_dispatch(B->jm, [&](auto Jc) {
-          constexpr int JM = decltype(Jc)::value;
-          hipLaunchKernelGGL((kb_restrict<T, JM>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks, nt,
+        jmv_dispatch<T>(B->jm, B->vw, [&](auto Jc, auto Vc) {
+          constexpr int JM = decltype(Jc)::value, VW = decltype(Vc)::value;
+          hipLaunchKernelGGL((kb_restrict<T, JM, VW>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks, nt,
                              (const int*)B->done);
         });
         break;
@@ -1364,16 +1421,20 @@ static int batch_validate(smg_ctx* const* ctxs, int count, const int* lanes, smg
   B->fnorm.assign(count, 1.0);
   B->precision = ctxs[0] ? ctxs[0]->desc.precision : 0;
   B->jm = 1;
+  B->vw = B->precision == SMG_F32 ? 2 : 1;
+  for (int i = 0; i < count; ++i) {
+    if (!ctxs[i]) return SMG_EINVAL;
+    if (!vec2_ctx(B->precision, ctxs[i]->N)) B->vw = 1;
+  }
   for (int i = 0; i < count; ++i) {
     smg_ctx* C = ctxs[i];
-    if (!C) return SMG_EINVAL;
     if (C->desc.precision != B->precision || C->desc.theta != 1.0 || C->desc.pre < 1 || C->desc.post < 1 ||
         C->desc.pre != ctxs[0]->desc.pre || C->desc.post != ctxs[0]->desc.post || C->stream != ctxs[0]->stream)
       return SMG_EINVAL;
-    const int W = lanes ? lanes[i] : default_lanes(C->N);
-    if (!pow2_ok(W) || (C->N + W - 1) / W > 8) return SMG_EINVAL;
+    const int W = lanes ? lanes[i] : default_lanes(C->N, C->desc.precision);
+    if (!pow2_ok(W) || samples_per_lane(C->N, W, B->vw) > 8) return SMG_EINVAL;
     B->lanes[i] = W;
-    B->jm = std::max(B->jm, (C->N + W - 1) / W);
+    B->jm = std::max(B->jm, samples_per_lane(C->N, W, B->vw));
   }
   B->stream = ctxs[0]->stream;
   return SMG_OK;
@@ -1520,14 +1581,15 @@ int smg_batch_solve(smg_batch* B, double rtol, int maxit, smg_stats* stats, doub
 }
 
 // Autotuner of the lanes-per-node width of one context's half-sweep: times the
-// finest-level red half-sweep (the batched kernel, one task) for every width
-// W in {64, 32, 16, 8} with W <= pow2ceil(N) and N/W <= 8 samples per lane.
+// finest-level red half-sweep (the batched kernel, one task) for every
+// power-of-two width W up to default_lanes with at most 8 samples per lane.
 // lanes/us receive up to `cap` candidates, *ncand their number, *best the
 // fastest width.  Uses the context's correction buffers as scratch.
 int smg_tune_lanes(smg_ctx* C, int cap, int* lanes, double* us, int* ncand, int* best) {
   if (!C || cap < 1 || !lanes || !us || !ncand || !best) return SMG_EINVAL;
   const bool f32 = C->desc.precision == SMG_F32;
-  const int N = C->N, top = default_lanes(N);
+  const int N = C->N, top = default_lanes(N, C->desc.precision);
+  const int vw = vec2_ctx(C->desc.precision, N) ? 2 : 1;
   int k = 0;
   double best_us = 1e300;
   hipEvent_t e0, e1;
@@ -1549,11 +1611,11 @@ int smg_tune_lanes(smg_ctx* C, int cap, int* lanes, double* us, int* ncand, int*
     t.x = xs; t.f = fs;
     const int per = kBlock / W, nbk = (t.nitems + per - 1) / per;
     HIP_TRY(hipMemcpyAsync(C->mdp, &t, sizeof(t), hipMemcpyHostToDevice, C->stream));
-    const int jm = (N + W - 1) / W;
+    const int jm = samples_per_lane(N, W, vw);
     auto launch = [&]() {
-      jm_dispatch(jm, [&](auto Jc) {
-        constexpr int JM = decltype(Jc)::value;
-        hipLaunchKernelGGL((kb_halfsweep<T, JM, kPlain>), dim3(nbk), dim3(kBlock), 0, C->stream,
+      jmv_dispatch<T>(jm, vw, [&](auto Jc, auto Vc) {
+        constexpr int JM = decltype(Jc)::value, VW = halfsweep_vw(decltype(Vc)::value, JM);
+        hipLaunchKernelGGL((kb_halfsweep<T, JM, kPlain, VW>), dim3(nbk), dim3(kBlock), 0, C->stream,
                            (const BTask<T>*)C->mdp, 1, 0, (const int*)C->flag);
       });
     };
@@ -1571,8 +1633,8 @@ int smg_tune_lanes(smg_ctx* C, int cap, int* lanes, double* us, int* ncand, int*
     if (u < best_us) { best_us = u; *best = W; }
     return SMG_OK;
   };
-  for (int W = 64; W >= 8 && k < cap; W >>= 1) {
-    if (W > top || (N + W - 1) / W > 8) continue;
+  for (int W = 64; W >= 1 && k < cap; W >>= 1) {
+    if (W > top || samples_per_lane(N, W, vw) > 8) continue;
     const int rc = f32 ? run(float(0), W) : run(double(0), W);
     if (rc != SMG_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rc; }
   }

@@ -19,37 +19,42 @@ enum NbSource { kPlain = 0, kZero = 1, kProlong = 2 };
 // with coarse node (X, K) (x, k odd) or is the centre of a coarse cell (x, k
 // even); every neighbour lies on a coarse edge, so bilinear interpolation there
 // averages two coarse values.  Coarse nodes outside the grid are zero.
-template <typename T>
+template <int VW, typename T>
 __device__ __forceinline__ void prolong_nb(const T* __restrict__ e, int nc, int N, int j, int x, int k,
-                                           T& cw, T& ce, T& cs, T& cn) {
+                                           T (&cw)[VW], T (&ce)[VW], T (&cs)[VW], T (&cn)[VW]) {
   // Five unconditional loads (clamped into the grid, outside values selected to
   // zero) for both cases, so that they are in flight together with the node's
   // other loads.  x odd: v0 = (X, K) and its W, E, S, N coarse neighbours
   // v1..v4; x even: v1..v4 = the cell corners (X-1, K-1), (X, K-1), (X-1, K),
-  // (X, K) (v0 = v4 is read twice).
-  auto at = [&](int X, int K) -> T {
+  // (X, K) (v0 = v4 is read twice).  VW consecutive samples from j.
+  auto at = [&](int X, int K, T (&v)[VW]) {
     const bool in = X >= 0 && X < nc && K >= 0 && K < nc;
     const int Xc = X < 0 ? 0 : (X >= nc ? nc - 1 : X), Kc = K < 0 ? 0 : (K >= nc ? nc - 1 : K);
-    const T v = e[((size_t)Kc * nc + Xc) * N + j];
-    return in ? v : T(0);
+    ldv<VW>(e + ((size_t)Kc * nc + Xc) * N + j, v);
+#pragma unroll
+    for (int u = 0; u < VW; ++u) v[u] = in ? v[u] : T(0);
   };
   const bool odd = x & 1;
   const int X = odd ? (x - 1) >> 1 : x >> 1, K = odd ? (k - 1) >> 1 : k >> 1;
-  const T v0 = at(X, K);
-  const T v1 = at(X - 1, odd ? K : K - 1);
-  const T v2 = at(odd ? X + 1 : X, odd ? K : K - 1);
-  const T v3 = at(odd ? X : X - 1, odd ? K - 1 : K);
-  const T v4 = at(X, odd ? K + 1 : K);
-  cw = T(0.5) * (v1 + (odd ? v0 : v3));
-  ce = T(0.5) * ((odd ? v0 : v2) + (odd ? v2 : v4));
-  cs = T(0.5) * ((odd ? v3 : v1) + (odd ? v0 : v2));
-  cn = T(0.5) * ((odd ? v0 : v3) + v4);
+  T v0[VW], v1[VW], v2[VW], v3[VW], v4[VW];
+  at(X, K, v0);
+  at(X - 1, odd ? K : K - 1, v1);
+  at(odd ? X + 1 : X, odd ? K : K - 1, v2);
+  at(odd ? X : X - 1, odd ? K - 1 : K, v3);
+  at(X, odd ? K + 1 : K, v4);
+#pragma unroll
+  for (int u = 0; u < VW; ++u) {
+    cw[u] = T(0.5) * (v1[u] + (odd ? v0[u] : v3[u]));
+    ce[u] = T(0.5) * ((odd ? v0[u] : v2[u]) + (odd ? v2[u] : v4[u]));
+    cs[u] = T(0.5) * ((odd ? v3[u] : v1[u]) + (odd ? v0[u] : v2[u]));
+    cn[u] = T(0.5) * ((odd ? v0[u] : v3[u]) + v4[u]);
+  }
 }
 
 // Half-sweep update of the slot-th node of `colour` by one group of W lanes
-// (lane = index in the group, JM >= ceil(N/W) samples per lane).  The node is
-// replaced by the solution of its (2N+1)x(2N+1) system (eq.
-// solution_reduced_system) with the opposite-colour neighbours fixed:
+// (lane = index in the group; JM samples per lane in chunks of VW, see
+// common.h).  The node is replaced by the solution of its (2N+1)x(2N+1) system
+// (eq. solution_reduced_system) with the opposite-colour neighbours fixed:
 //   bP_j = fY_j + sum_nb k_nb p_j,nb      (rhs of the C_j / A_j^T row)
 //   bY_j = fP_j + sum_nb k_nb y_j,nb      (rhs of the A_j / E_j row)
 //   u    = (fU + sum_j d_j (c_j bY_j / a_j^2 - bP_j / a_j)) / (g + sum_j d_j c_j e_j / a_j^2)
@@ -57,10 +62,12 @@ __device__ __forceinline__ void prolong_nb(const T* __restrict__ e, int nc, int 
 // theta != 1 (relaxation) is supported for SRC == kPlain only; kProlong needs
 // colour 0.  W is a compile-time constant after inlining in the single-instance
 // kernel and a per-instance value in the batched one; the arithmetic is the same.
-template <typename T, int JM, int SRC>
+template <typename T, int JM, int SRC, int VW = 1>
 __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restrict__ x,
                                                const T* __restrict__ f, int colour, T theta, int slot,
                                                int lane, int W, const T* __restrict__ ec) {
+  static_assert(JM % VW == 0, "whole chunks per lane");
+  constexpr int NCH = JM / VW;
   const int n = L.n, N = L.N;
   const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
   int xx, k;
@@ -82,62 +89,96 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
   // Neighbour offsets; a missing (boundary) neighbour reads the node itself and
   // is discarded by a select (the node's own old value may be stale, e.g. the
   // other colour right after a zero-start sweep), so every load is
-  // unconditional.  Samples j >= N (ragged last lane group) read sample N-1 and
-  // are masked out of the sums.
+  // unconditional.  A chunk past N (ragged last lane group) reads the last
+  // chunk and is masked out of the sums.
   const ptrdiff_t ow = hw ? -(ptrdiff_t)N : 0, oe = he ? (ptrdiff_t)N : 0;
   const ptrdiff_t os = hs ? -(ptrdiff_t)rowN : 0, on = hn ? (ptrdiff_t)rowN : 0;
   T bP[JM], bY[JM], ia[JM], cq[JM], eq[JM];
   T num = 0, den = 0;
 #pragma unroll
-  for (int q = 0; q < JM; ++q) {
-    const int j0 = lane + q * W;
+  for (int c = 0; c < NCH; ++c) {
+    const int j0 = VW * (lane + c * W);
     const bool act = j0 < N;
-    const int j = act ? j0 : N - 1;
-    const T kw = L.kx[kxb + j], ke = L.kx[kxb + N + j];
-    const T ks = L.ky[kyb + j], kn = L.ky[kyb + rowN + j];
+    const int j = act ? j0 : N - VW;
+    T kw[VW], ke[VW], ks[VW], kn[VW];
+    ldv<VW>(L.kx + kxb + j, kw);
+    ldv<VW>(L.kx + kxb + N + j, ke);
+    ldv<VW>(L.ky + kyb + j, ks);
+    ldv<VW>(L.ky + kyb + rowN + j, kn);
     const size_t base = node * N + j;
     // sum over existing neighbours of face * value (missing ones selected away)
-    auto nbsum = [&](T vw, T ve, T vs, T vn) -> T {
-      return ((hw ? kw * vw : T(0)) + (he ? ke * ve : T(0))) + ((hs ? ks * vs : T(0)) + (hn ? kn * vn : T(0)));
+    auto nbsum = [&](int u, T vw, T ve, T vs, T vn) -> T {
+      return ((hw ? kw[u] * vw : T(0)) + (he ? ke[u] * ve : T(0))) +
+             ((hs ? ks[u] * vs : T(0)) + (hn ? kn[u] * vn : T(0)));
     };
-    T sy = 0, sp = 0;
+    T sy[VW], sp[VW];
+#pragma unroll
+    for (int u = 0; u < VW; ++u) { sy[u] = T(0); sp[u] = T(0); }
     if constexpr (SRC != kZero) {
-      sy = nbsum(Y[base + ow], Y[base + oe], Y[base + os], Y[base + on]);
-      sp = nbsum(P[base + ow], P[base + oe], P[base + os], P[base + on]);
+      T yw[VW], ye[VW], ys[VW], yn[VW], pw[VW], pe[VW], ps[VW], pn[VW];
+      ldv<VW>(Y + base + ow, yw); ldv<VW>(Y + base + oe, ye); ldv<VW>(Y + base + os, ys); ldv<VW>(Y + base + on, yn);
+      ldv<VW>(P + base + ow, pw); ldv<VW>(P + base + oe, pe); ldv<VW>(P + base + os, ps); ldv<VW>(P + base + on, pn);
+#pragma unroll
+      for (int u = 0; u < VW; ++u) {
+        sy[u] = nbsum(u, yw[u], ye[u], ys[u], yn[u]);
+        sp[u] = nbsum(u, pw[u], pe[u], ps[u], pn[u]);
+      }
     }
     if constexpr (SRC == kProlong) {
-      T cw, ce, cs, cn;
-      prolong_nb(eY, nc, N, j, xx, k, cw, ce, cs, cn);
-      sy += nbsum(cw, ce, cs, cn);
-      prolong_nb(eP, nc, N, j, xx, k, cw, ce, cs, cn);
-      sp += nbsum(cw, ce, cs, cn);
+      T cw[VW], ce[VW], cs[VW], cn[VW];
+      prolong_nb<VW>(eY, nc, N, j, xx, k, cw, ce, cs, cn);
+#pragma unroll
+      for (int u = 0; u < VW; ++u) sy[u] += nbsum(u, cw[u], ce[u], cs[u], cn[u]);
+      prolong_nb<VW>(eP, nc, N, j, xx, k, cw, ce, cs, cn);
+#pragma unroll
+      for (int u = 0; u < VW; ++u) sp[u] += nbsum(u, cw[u], ce[u], cs[u], cn[u]);
     }
-    const T a = (kw + ke) + (ks + kn);
-    const T ai = T(1) / a;
-    const T cj = L.c[j], dj = L.d[j], ej = L.e[j];
-    const T bp = fY[base] + sp, by = fP[base] + sy;
-    const T t = cj * ai * ai;
-    num += act ? dj * (t * by - ai * bp) : T(0);
-    den += act ? dj * t * ej : T(0);
-    bP[q] = bp; bY[q] = by; ia[q] = ai; cq[q] = cj; eq[q] = ej;
+    T cj[VW], dj[VW], ej[VW], fy[VW], fp[VW];
+    ldv<VW>(L.c + j, cj);
+    ldv<VW>(L.d + j, dj);
+    ldv<VW>(L.e + j, ej);
+    ldv<VW>(fY + base, fy);
+    ldv<VW>(fP + base, fp);
+#pragma unroll
+    for (int u = 0; u < VW; ++u) {
+      const int q = c * VW + u;
+      const T a = (kw[u] + ke[u]) + (ks[u] + kn[u]);
+      const T ai = T(1) / a;
+      const T bp = fy[u] + sp[u], by = fp[u] + sy[u];
+      const T t = cj[u] * ai * ai;
+      num += act ? dj[u] * (t * by - ai * bp) : T(0);
+      den += act ? dj[u] * t * ej[u] : T(0);
+      bP[q] = bp; bY[q] = by; ia[q] = ai; cq[q] = cj[u]; eq[q] = ej[u];
+    }
   }
   num = group_sum_w(num, W);
   den = group_sum_w(den, W);
   const T un = (fU[node] + num) / (L.g + den);
   const bool relax = SRC == kPlain && theta != T(1);
 #pragma unroll
-  for (int q = 0; q < JM; ++q) {
-    const int j = lane + q * W;
+  for (int c = 0; c < NCH; ++c) {
+    const int j = VW * (lane + c * W);
     if (j < N) {
       const size_t base = node * N + j;
-      T yn = ia[q] * (bY[q] - eq[q] * un);
-      T pn = ia[q] * (bP[q] - cq[q] * yn);
-      if (relax) {
-        yn = (T(1) - theta) * Y[base] + theta * yn;
-        pn = (T(1) - theta) * P[base] + theta * pn;
+      T yv[VW], pv[VW];
+#pragma unroll
+      for (int u = 0; u < VW; ++u) {
+        const int q = c * VW + u;
+        yv[u] = ia[q] * (bY[q] - eq[q] * un);
+        pv[u] = ia[q] * (bP[q] - cq[q] * yv[u]);
       }
-      Y[base] = yn;
-      P[base] = pn;
+      if (relax) {
+        T yo[VW], po[VW];
+        ldv<VW>(Y + base, yo);
+        ldv<VW>(P + base, po);
+#pragma unroll
+        for (int u = 0; u < VW; ++u) {
+          yv[u] = (T(1) - theta) * yo[u] + theta * yv[u];
+          pv[u] = (T(1) - theta) * po[u] + theta * pv[u];
+        }
+      }
+      stv<VW>(Y + base, yv);
+      stv<VW>(P + base, pv);
     }
   }
   if (lane == 0) U[node] = relax ? (T(1) - theta) * U[node] + theta * un : un;
@@ -152,17 +193,15 @@ template <int JM, int SRC>
 constexpr int halfsweep_waves() { return JM >= 4 && SRC != kProlong ? 3 : 8; }
 
 // One half-sweep of collective Gauss-Seidel over every node of `colour`.
-template <typename T, int W, int JM, int SRC>
+template <typename T, int W, int JM, int SRC, int VW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, halfsweep_waves<JM, SRC>())))
-void k_halfsweep(LevelArgs<T> L, T* __restrict__ x,
-                                                      const T* __restrict__ f, int colour,
-                                                      T theta, int nactive,
-                                                      const T* __restrict__ ec) {
+void k_halfsweep(LevelArgs<T> L, T* __restrict__ x, const T* __restrict__ f, int colour, T theta, int nactive,
+                 const T* __restrict__ ec) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (W - 1);
   const int slot = b * (kBlock / W) + threadIdx.x / W;
   if (slot >= nactive) return;  // whole W-lane groups leave together
-  halfsweep_node<T, JM, SRC>(L, x, f, colour, theta, slot, lane, W, ec);
+  halfsweep_node<T, JM, SRC, VW>(L, x, f, colour, theta, slot, lane, W, ec);
 }
 
 }  // namespace smg

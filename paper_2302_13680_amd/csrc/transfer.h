@@ -8,9 +8,11 @@ namespace smg {
 // and gathers its 3x3 fine neighbourhood with weights w(dx) w(dk).  One group
 // of W lanes per coarse node; the slot-th coarse node in strips of cstrip
 // coarse columns (strip_node).
-template <typename T, int JM>
+template <typename T, int JM, int VW = 1>
 __device__ __forceinline__ void restrict_node(int nf, int N, const T* __restrict__ fine,
                                               T* __restrict__ coarse, int slot, int lane, int W, int cstrip) {
+  static_assert(JM % VW == 0, "whole chunks per lane");
+  constexpr int NCH = JM / VW;
   const int nc = (nf - 1) / 2;
   const size_t nnf = (size_t)nf * nf, nnc = (size_t)nc * nc;
   int X, K;
@@ -20,24 +22,32 @@ __device__ __forceinline__ void restrict_node(int nf, int N, const T* __restrict
   const T* fY = fine;
   const T* fP = fine + (size_t)(N + 1) * nnf;
 #pragma unroll
-  for (int q = 0; q < JM; ++q) {
-    // loads for a ragged sample j >= N read sample N-1 (in bounds); only the
-    // stores are guarded, so all loads of the node can be in flight together
-    const int j0 = lane + q * W;
-    const int j = j0 < N ? j0 : N - 1;
-    T sY = 0, sP = 0;
+  for (int c = 0; c < NCH; ++c) {
+    // loads for a chunk past N read the last chunk (in bounds); only the stores
+    // are guarded, so all loads of the node can be in flight together
+    const int j0 = VW * (lane + c * W);
+    const int j = j0 < N ? j0 : N - VW;
+    T sY[VW], sP[VW];
+#pragma unroll
+    for (int u = 0; u < VW; ++u) { sY[u] = T(0); sP[u] = T(0); }
 #pragma unroll
     for (int dk = -1; dk <= 1; ++dk)
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const T w = (T)(lin_w(dx) * lin_w(dk));
         const size_t fi = (size_t)((long)c0 + (long)dk * nf + dx) * N + j;
-        sY += w * fY[fi];
-        sP += w * fP[fi];
+        T vy[VW], vp[VW];
+        ldv<VW>(fY + fi, vy);
+        ldv<VW>(fP + fi, vp);
+#pragma unroll
+        for (int u = 0; u < VW; ++u) {
+          sY[u] += w * vy[u];
+          sP[u] += w * vp[u];
+        }
       }
     if (j0 < N) {
-      coarse[(size_t)cnode * N + j] = sY;
-      coarse[(size_t)(N + 1) * nnc + (size_t)cnode * N + j] = sP;
+      stv<VW>(coarse + (size_t)cnode * N + j, sY);
+      stv<VW>(coarse + (size_t)(N + 1) * nnc + (size_t)cnode * N + j, sP);
     }
   }
   if (lane == 0) {
@@ -52,7 +62,7 @@ __device__ __forceinline__ void restrict_node(int nf, int N, const T* __restrict
   }
 }
 
-template <typename T, int W, int JM>
+template <typename T, int W, int JM, int VW>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nf, int N, const T* __restrict__ fine,
                                                      T* __restrict__ coarse, int cstrip) {
   const int nc = (nf - 1) / 2;
@@ -60,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nf, int N, const T* __r
   const int lane = threadIdx.x & (W - 1);
   const int slot = b * (kBlock / W) + threadIdx.x / W;
   if (slot >= nc * nc) return;
-  restrict_node<T, JM>(nf, N, fine, coarse, slot, lane, W, cstrip);
+  restrict_node<T, JM, VW>(nf, N, fine, coarse, slot, lane, W, cstrip);
 }
 
 // fine += P coarse, bilinear interpolation gathered per fine node.

@@ -99,9 +99,12 @@ def test_autotuned_lanes(B, O, tmp_path):
     cache = str(tmp_path / "tune.json")
     lanes, table = autotune.tune(ctxs, cache)
     for p, w in zip(probs, lanes):
-        assert w in (8, 16, 32, 64) and (p.N + w - 1) // w <= 8
+        assert w in (1, 2, 4, 8, 16, 32, 64) and (p.N + w - 1) // w <= 8
     # the batch-wide samples per lane stay at the smallest value the batch allows
-    assert max(-(-p.N // w) for p, w in zip(probs, lanes)) == -(-max(p.N for p in probs) // 64)
+    # (two samples per access: FP32 with every N even)
+    v = 2 if all(p.N % 2 == 0 for p in probs) else 1
+    jm = lambda N, w: v * -(-N // (v * w))
+    assert max(jm(p.N, w) for p, w in zip(probs, lanes)) == max(jm(p.N, 64) for p in probs)
     lanes2, _ = autotune.tune(ctxs, cache)          # served from the cache
     assert lanes2 == lanes
     bt = B.Batch(ctxs, xs, fs, lanes=lanes)
