@@ -177,6 +177,13 @@ int smg_smooth32(smg_ctx *ctx, int level, int colour, float *x, const float *f);
  * level `level`, coarse of level + 1, all 2N+1 fields.  FP64 device vectors. */
 int smg_restrict(smg_ctx *ctx, int level, const double *fine, double *coarse);
 
+/* coarse = R (f - S x) in one pass: the residual of Alg. 1 on level `level`
+ * restricted to level + 1 without storing the fine residual (the result of
+ * smg_residual followed by smg_restrict up to rounding order).  x, f: FP64 device vectors
+ * of level `level` (f is that level's right-hand side); coarse: level + 1.
+ * SMG_EINVAL if `level` has no coarser level. */
+int smg_residual_restrict(smg_ctx *ctx, int level, const double *x, const double *f, double *coarse);
+
 /* fine += P coarse (bilinear interpolation; Alg. 1 coarse correction). */
 int smg_prolong_add(smg_ctx *ctx, int level, const double *coarse, double *fine);
 

@@ -23,8 +23,8 @@ struct BTask {
   LevelArgs<T> L;      // level operator
   T* x;                // level iterate / coarsest solution
   const T* f;          // level right-hand side
-  T* a;                // phase output: fine residual, coarse right-hand side
-  const T* b;          // phase input: fine residual, coarse correction
+  T* a;                // phase output: coarse right-hand side
+  const T* b;          // phase input: coarse correction
   int m;               // coarsest unknowns per field
   const double* Ainv;  // coarsest factors (transposed storage) and scratch
   const double* Sinv;
@@ -92,10 +92,10 @@ __global__ __launch_bounds__(kBlock) void kb_halfsweep(const BTask<T>* __restric
   halfsweep_node<T, JM, SRC, VW>(t.L, t.x, t.f, colour, T(1), slot, lane, W, t.b);
 }
 
-// level residual r = f - S x into t.a
+// coarse right-hand side t.a = R (t.f - S t.x) of level t.L (fine residual never stored)
 template <typename T, int JM, int VW>
-__global__ __launch_bounds__(kBlock) void kb_residual(const BTask<T>* __restrict__ tasks, int ntasks,
-                                                      const int* __restrict__ done) {
+__global__ __launch_bounds__(kBlock) void kb_residual_restrict(const BTask<T>* __restrict__ tasks, int ntasks,
+                                                               const int* __restrict__ done) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const BTask<T>& t = tasks[find_task(tasks, ntasks, b)];
   if (done[t.inst]) return;
@@ -103,22 +103,7 @@ __global__ __launch_bounds__(kBlock) void kb_residual(const BTask<T>* __restrict
   const int lane = threadIdx.x & (W - 1);
   const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
   if (slot >= t.nitems) return;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  residual_node<T, T, T, JM, VW>(t.L, t.x, t.f, t.a, 0, slot, lane, W, acc);
-}
-
-// coarse right-hand side t.a = R t.b (t.b: fine residual of grid t.L.n)
-template <typename T, int JM, int VW>
-__global__ __launch_bounds__(kBlock) void kb_restrict(const BTask<T>* __restrict__ tasks, int ntasks,
-                                                      const int* __restrict__ done) {
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const BTask<T>& t = tasks[find_task(tasks, ntasks, b)];
-  if (done[t.inst]) return;
-  const int W = t.W;
-  const int lane = threadIdx.x & (W - 1);
-  const int slot = (b - t.block0) * (kBlock / W) + threadIdx.x / W;
-  if (slot >= t.nitems) return;
-  restrict_node<T, JM, VW>(t.L.n, t.L.N, t.b, t.a, slot, lane, W, coarse_strip(t.L.strip));
+  residual_restrict_node<T, JM, VW>(t.L, t.x, t.f, t.a, slot, lane, W, coarse_strip(t.L.strip));
 }
 
 // coarsest direct solve, one block per (instance, sample)

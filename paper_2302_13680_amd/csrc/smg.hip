@@ -108,6 +108,35 @@ void lane_dispatch(int precision, int N, F&& fn) {
   }
 }
 
+// Lanes per coarse node of the fused residual + restriction: the smoother's
+// widths while one chunk of VW samples per lane covers N (up to 64 lanes), then
+// groups of 128 or 256 lanes (several waves) so that every lane still handles
+// one chunk: with all ~90 loads of a chunk in flight at once, a second chunk per
+// lane would need more registers than two waves per SIMD leave.
+template <bool kVec2, typename F>
+void rr_dispatch(int precision, int N, F&& fn) {
+  const bool v2 = kVec2 && vec2_ctx(precision, N);
+  const int M = v2 ? N / 2 : N;   // accesses per node and field
+  if (M <= 64) {
+    if (v2) lane_dispatch<kVec2>(precision, N, fn);
+    else seg_dispatch(N, [&](auto Wc, auto Jc) { fn(Wc, Jc, IC<1>{}); });
+    return;
+  }
+  auto go = [&](auto Wc, auto Cc) {   // Cc: chunks per lane
+    constexpr int C = decltype(Cc)::value;
+    if constexpr (kVec2) {
+      if (v2) {
+        fn(Wc, IC<2 * C>{}, IC<2>{});
+        return;
+      }
+    }
+    fn(Wc, IC<C>{}, IC<1>{});
+  };
+  if (M <= 128) go(IC<128>{}, IC<1>{});
+  else if (M <= 256) go(IC<256>{}, IC<1>{});
+  else go(IC<256>{}, IC<2>{});
+}
+
 int count_levels(int n, int nc) {
   int nl = 1, t = n;
   while (t > nc) {
@@ -383,6 +412,21 @@ int restrict_to(smg_ctx* C, int nf, const T* fine, T* coarse) {
   return SMG_OK;
 }
 
+// coarse = R (f - S x) in one pass (the fine residual is never stored).
+template <typename T>
+int residual_restrict(smg_ctx* C, const Level<T>& L, const T* x, const T* f, T* coarse) {
+  const int nc = (L.n - 1) / 2;
+  const LevelArgs<T> a = args(L, C->N, C->desc.strip);
+  rr_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value, VW = decltype(Vc)::value;
+    const int per = kBlock / W, nb = (nc * nc + per - 1) / per;
+    hipLaunchKernelGGL((k_residual_restrict<T, W, JM, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f, coarse,
+                       coarse_strip(a.strip));
+  });
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
 template <typename T>
 int prolong_add(smg_ctx* C, int nc, const T* coarse, T* fine) {
   const int nf = 2 * nc + 1;
@@ -422,6 +466,7 @@ int coarse_solve(smg_ctx* C, const TV* F, TV* X) {
 //  - the coarse correction x += P e_c is folded into the first post-smoothing red
 //    half-sweep (kProlong): red nodes read their black neighbours corrected on
 //    the fly, and the black half-sweep that follows overwrites every black node.
+// For any theta the residual is restricted in the same pass that forms it.
 template <typename T>
 int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f, bool x_zero) {
   if (l == C->nlev - 1) return coarse_solve<T>(C, f, x);
@@ -442,8 +487,12 @@ int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f, bool x
     TRY(halfsweep<T>(C, L, x, f, 1));
   }
   Level<T>& Lc = Ls[l + 1];
-  TRY((residual<T, T, T>(C, L, x, f, r, 0, false)));
-  TRY(restrict_to<T>(C, L.n, r, Lc.f));
+  if (!(C->desc.flags & SMG_FLAG_UNFUSED)) {
+    TRY(residual_restrict<T>(C, L, x, f, Lc.f));
+  } else {
+    TRY((residual<T, T, T>(C, L, x, f, r, 0, false)));
+    TRY(restrict_to<T>(C, L.n, r, Lc.f));
+  }
   TRY(vcycle_level<T>(C, Ls, r, l + 1, Lc.x, Lc.f, true));
   int p0 = 0;
   if (fused && C->desc.post > 0) {
@@ -812,7 +861,7 @@ struct smg_batch {
 
 namespace {
 
-enum BPhaseKind { kbOuter, kbCheck, kbSweep, kbResidual, kbRestrict, kbCoarse1, kbCoarse2, kbAdd };
+enum BPhaseKind { kbOuter, kbCheck, kbSweep, kbResRestrict, kbCoarse1, kbCoarse2, kbAdd };
 
 // Lanes per node of an instance by default (the single-instance widths).
 int default_lanes(int N, int precision) {
@@ -840,9 +889,6 @@ size_t batch_build(smg_batch* B, double* const* x, const double* const* f, std::
   };
   auto f0 = [](smg_ctx* C) -> T* {
     if constexpr (std::is_same<T, double>::value) return C->rr; else return C->L32[0].f;
-  };
-  auto r0 = [](smg_ctx* C) -> T* {
-    if constexpr (std::is_same<T, double>::value) return C->r64; else return C->r32;
   };
   // level d of instance i (d = 0 is the finest): x, f, operator
   auto lvl_x = [&](int i, int d) -> T* { return d == 0 ? x0(B->ctx[i]) : levels(B->ctx[i])[d].x; };
@@ -909,27 +955,19 @@ size_t batch_build(smg_batch* B, double* const* x, const double* const* f, std::
     sweep_phase(d, 0, kZero, true);
     sweep_phase(d, 1, kPlain, true);
     for (int s = 1; s < pre; ++s) { sweep_phase(d, 0, kPlain, true); sweep_phase(d, 1, kPlain, true); }
-    std::vector<BTask<T>> rs, rr;
-    int brs = 0, brr = 0;
+    std::vector<BTask<T>> rr;
+    int brr = 0;
     for (int i = 0; i < cnt; ++i) {
       if (d >= B->ctx[i]->nlev - 1) continue;
       BTask<T> t{};
       t.inst = i; t.W = B->lanes[i]; t.L = lvl_args(i, d);
-      t.x = lvl_x(i, d); t.f = lvl_f(i, d); t.a = r0(B->ctx[i]);
-      t.nitems = t.L.n * t.L.n; t.block0 = brs;
-      brs += groups(i, t.nitems);
-      rs.push_back(t);
-      BTask<T> q{};
-      q.inst = i; q.W = B->lanes[i]; q.L = t.L; q.b = r0(B->ctx[i]); q.a = lvl_f(i, d + 1);
+      t.x = lvl_x(i, d); t.f = lvl_f(i, d); t.a = lvl_f(i, d + 1);
       const int nc = (t.L.n - 1) / 2;
-      q.nitems = nc * nc; q.block0 = brr;
-      brr += groups(i, q.nitems);
-      rr.push_back(q);
+      t.nitems = nc * nc; t.block0 = brr;
+      brr += groups(i, t.nitems);
+      rr.push_back(t);
     }
-    if (!rs.empty()) {
-      add_phase(kbResidual, 0, 0, rs.data(), sizeof(BTask<T>) * rs.size(), (int)rs.size(), brs);
-      add_phase(kbRestrict, 0, 0, rr.data(), sizeof(BTask<T>) * rr.size(), (int)rr.size(), brr);
-    }
+    if (!rr.empty()) add_phase(kbResRestrict, 0, 0, rr.data(), sizeof(BTask<T>) * rr.size(), (int)rr.size(), brr);
   }
   {
     std::vector<BTask<T>> cs;
@@ -1057,18 +1095,11 @@ int batch_launch_step(smg_batch* B, hipStream_t s, double tol, int maxit) {
                                (const BTask<T>*)tasks, nt, p.colour, (const int*)B->done);
         });
         break;
-      case kbResidual:
+      case kbResRestrict:
         jmv_dispatch<T>(B->jm, B->vw, [&](auto Jc, auto Vc) {
           constexpr int JM = decltype(Jc)::value, VW = decltype(Vc)::value;
-          hipLaunchKernelGGL((kb_residual<T, JM, VW>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks, nt,
-                             (const int*)B->done);
-        });
-        break;
-      case kbRestrict:
-        jmv_dispatch<T>(B->jm, B->vw, [&](auto Jc, auto Vc) {
-          constexpr int JM = decltype(Jc)::value, VW = decltype(Vc)::value;
-          hipLaunchKernelGGL((kb_restrict<T, JM, VW>), dim3(nbk), dim3(kBlock), 0, s, (const BTask<T>*)tasks, nt,
-                             (const int*)B->done);
+          hipLaunchKernelGGL((kb_residual_restrict<T, JM, VW>), dim3(nbk), dim3(kBlock), 0, s,
+                             (const BTask<T>*)tasks, nt, (const int*)B->done);
         });
         break;
       case kbCoarse1:
@@ -1271,6 +1302,12 @@ int smg_restrict(smg_ctx* C, int level, const double* fine, double* coarse) {
   if (!C || !fine || !coarse) return SMG_EINVAL;
   TRY(check_level(C, level, 1));
   return restrict_to<double>(C, C->L64[level].n, fine, coarse);
+}
+
+int smg_residual_restrict(smg_ctx* C, int level, const double* x, const double* f, double* coarse) {
+  if (!C || !x || !f || !coarse) return SMG_EINVAL;
+  TRY(check_level(C, level, 1));
+  return residual_restrict<double>(C, C->L64[level], x, f, coarse);
 }
 
 int smg_prolong_add(smg_ctx* C, int level, const double* coarse, double* fine) {

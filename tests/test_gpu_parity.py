@@ -143,6 +143,33 @@ def test_transfers(B, O, n, N):
     assert rel(node_to_paper(host(fd), n, N), O.prolong_add(nc, N, coarse, fine)) <= 1e-15
 
 
+@pytest.mark.parametrize("n,N", [(15, 1), (15, 3), (31, 8), (15, 33), (15, 64), (63, 16), (15, 100),
+                                 (15, 300), (31, 256)])
+def test_residual_restrict(B, O, n, N):
+    # one pass R (f - S x) on every level with a coarser one: against the
+    # oracle's residual then restriction, and against the two GPU passes (the
+    # control row sums over samples once instead of per fine node: rounding)
+    p = mk(n, N, seed=n + 2 * N)
+    o = O.Oracle(p)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0)
+    rng = np.random.default_rng(n * N)
+    for l in range(o.nlev - 1):
+        nl = o.levels_n[l]
+        nc = o.levels_n[l + 1]
+        x = rng.standard_normal((2 * N + 1) * nl * nl)
+        f = rng.standard_normal(x.size)
+        cd = torch.empty((2 * N + 1) * nc * nc, dtype=torch.float64, device="cuda")
+        ctx.residual_restrict(l, dev(paper_to_node(x, nl, N)), dev(paper_to_node(f, nl, N)), cd)
+        ref = O.restrict(nl, N, o.residual(x, f, l))
+        assert rel(node_to_paper(host(cd), nc, N), ref) <= 1e-14, l
+        if l == 0:
+            r = torch.empty(x.size, dtype=torch.float64, device="cuda")
+            c2 = torch.empty_like(cd)
+            ctx.residual(dev(paper_to_node(x, nl, N)), dev(paper_to_node(f, nl, N)), r)
+            ctx.restrict(0, r, c2)
+            assert rel(host(cd), host(c2)) <= 1e-15
+
+
 @pytest.mark.parametrize("N", [1, 5, 64, 300, 512])
 def test_coarse_solve(B, O, N):
     p = mk(7, N, seed=8)
@@ -277,6 +304,10 @@ def test_error_paths(B):
     f = dev(p.rhs_node())
     rc, st = ctx.solve(torch.zeros_like(f), f, B.SMG_VCYCLE, rtol=1e-10, maxit=1)
     assert rc == B.SMG_NOT_CONVERGED and st["iterations"] == 1
+    last = ctx.nlev - 1     # the coarsest level has no coarser one to restrict to
+    with pytest.raises(B.SmgError) as ei:
+        ctx.residual_restrict(last, x, f, x)
+    assert ei.value.code == -1
 
 
 def test_medium_size_cycle_against_oracle(B, O):
