@@ -45,6 +45,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Index of this thread's group of W lanes in a launch of kBlock-thread blocks
+// (b: the remapped block index).  A group of 64 or more lanes holds whole
+// waves, so its index is wave-uniform; readfirstlane tells the compiler, which
+// then keeps the node's index arithmetic and addresses in scalar registers.
+template <int W>
+__device__ __forceinline__ int group_slot(int b) {
+  const int s = b * (kBlock / W) + (int)threadIdx.x / W;
+  if constexpr (W >= 64) return __builtin_amdgcn_readfirstlane(s);
+  else return s;
+}
+
 // VW consecutive samples as one access (VW = 2: an 8-byte float2 or a 16-byte
 // double2; the address is a multiple of VW elements from a 256-byte aligned base).
 template <int VW, typename T>

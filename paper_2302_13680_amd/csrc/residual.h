@@ -175,7 +175,7 @@ void k_residual_add(LevelArgs<double> L, const double* __restrict__ x, const flo
                     double* __restrict__ partials) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (W - 1);
-  const int slot = b * (kBlock / W) + threadIdx.x / W;
+  const int slot = group_slot<W>(b);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (slot < L.n * L.n) residual_add_node<JM>(L, x, d, xn, f, out, slot, lane, W, acc);
   block_sum<4>(acc);
@@ -193,7 +193,7 @@ void k_residual(LevelArgs<T> L, const TX* __restrict__ x, const TX* __restrict__
                 int mode, double* __restrict__ partials) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (W - 1);
-  const int slot = b * (kBlock / W) + threadIdx.x / W;
+  const int slot = group_slot<W>(b);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (slot < L.n * L.n) residual_node<T, TX, TO, JM, VW>(L, x, f, out, mode, slot, lane, W, acc);
   if (partials) {

@@ -199,7 +199,7 @@ void k_halfsweep(LevelArgs<T> L, T* __restrict__ x, const T* __restrict__ f, int
                  const T* __restrict__ ec) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (W - 1);
-  const int slot = b * (kBlock / W) + threadIdx.x / W;
+  const int slot = group_slot<W>(b);
   if (slot >= nactive) return;  // whole W-lane groups leave together
   halfsweep_node<T, JM, SRC, VW>(L, x, f, colour, theta, slot, lane, W, ec);
 }

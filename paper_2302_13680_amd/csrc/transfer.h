@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(LevelArgs<T> L, co
   const int nc = (L.n - 1) / 2;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (W - 1);
-  const int slot = b * (kBlock / W) + threadIdx.x / W;
+  const int slot = group_slot<W>(b);
   if constexpr (W <= 64) {
     if (slot >= nc * nc) return;
     residual_restrict_node<T, JM, VW>(L, x, f, coarse, slot, lane, W, cstrip);
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nf, int N, const T* __r
   const int nc = (nf - 1) / 2;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (W - 1);
-  const int slot = b * (kBlock / W) + threadIdx.x / W;
+  const int slot = group_slot<W>(b);
   if (slot >= nc * nc) return;
   restrict_node<T, JM, VW>(nf, N, fine, coarse, slot, lane, W, cstrip);
 }
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(int nc, int N, const T* 
   const size_t nnf = (size_t)nf * nf, nnc = (size_t)nc * nc;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (W - 1);
-  const int slot = b * (kBlock / W) + threadIdx.x / W;
+  const int slot = group_slot<W>(b);
   if (slot >= (int)nnf) return;
   const int k = slot / nf, xx = slot - k * nf;
   // coarse columns/rows touching this fine node and their weights
