@@ -33,6 +33,7 @@ struct LevelArgs {
   const T* __restrict__ d;
   const T* __restrict__ e;
   T g;
+  const T* __restrict__ gden;   // [n][n] per node: g + sum_j d_j c_j e_j / a_j^2 (set up once)
   int strip;   // columns per strip of the colour traversal (colour_node)
 };
 

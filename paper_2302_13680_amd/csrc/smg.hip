@@ -35,6 +35,7 @@ struct Level {
   T* d = nullptr;
   T* e = nullptr;
   T g = 0;
+  T* gden = nullptr; // [n][n]: g + sum_j d_j c_j e_j / a_j^2 (node_den)
   T* x = nullptr;    // level iterate (levels >= 1, and level 0 of the FP32 cycle)
   T* f = nullptr;    // level right-hand side
 };
@@ -239,12 +240,14 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
     const size_t fx = (size_t)n * (n + 1) * N, len = vlen(n, N);
     if (l > 0) { L.kx = cv.take<double>(fx); L.ky = cv.take<double>(fx); }
     L.c = cv.take<double>(N); L.d = cv.take<double>(N); L.e = cv.take<double>(N);
+    L.gden = cv.take<double>((size_t)n * n);
     if (l > 0 && !f32) { L.x = cv.take<double>(len); L.f = cv.take<double>(len); }
     if (f32) {
       Level<float>& M = C->L32[l];
       M.n = n;
       M.kx = cv.take<float>(fx); M.ky = cv.take<float>(fx);
       M.c = cv.take<float>(N); M.d = cv.take<float>(N); M.e = cv.take<float>(N);
+      M.gden = cv.take<float>((size_t)n * n);
       M.x = cv.take<float>(len); M.f = cv.take<float>(len);
     }
     n = (n - 1) / 2;
@@ -307,7 +310,7 @@ int strip_for(int n, int requested) {
 template <typename T>
 LevelArgs<T> args(const Level<T>& L, int N, int strip = 0) {
   LevelArgs<T> a;
-  a.n = L.n; a.N = N; a.kx = L.kx; a.ky = L.ky; a.c = L.c; a.d = L.d; a.e = L.e; a.g = L.g;
+  a.n = L.n; a.N = N; a.kx = L.kx; a.ky = L.ky; a.c = L.c; a.d = L.d; a.e = L.e; a.g = L.g; a.gden = L.gden;
   a.strip = strip_for(L.n, strip);
   return a;
 }
@@ -346,6 +349,22 @@ int halfsweep(smg_ctx* C, const Level<T>& L, T* x, const T* f, int colour, int s
     else
       hipLaunchKernelGGL((k_halfsweep<T, W, JM, kPlain, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f, colour,
                          theta, nact, ec);
+  });
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+// L.gden = g + sum_j d_j c_j e_j / a_j^2 per node, in the lane layout (and so
+// the summation order) of the level's half-sweep.
+template <typename T>
+int node_den_level(smg_ctx* C, const Level<T>& L) {
+  const int nn = L.n * L.n;
+  const LevelArgs<T> a = args(L, C->N, C->desc.strip);
+  lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    constexpr int VW = halfsweep_vw(decltype(Vc)::value, JM);
+    const int per = kBlock / W, nb = (nn + per - 1) / per;
+    hipLaunchKernelGGL((k_node_den<T, W, JM, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, L.gden);
   });
   LAUNCH_CHECK();
   return SMG_OK;
@@ -1244,6 +1263,11 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
           convert<double, float>(C, C->L64[l].ky, C->L32[l].ky, fx) != SMG_OK)
         return fail(SMG_EHIP);
     }
+  }
+  // per-node denominators of the node solve, with the half-sweep's lane layout
+  for (int l = 0; l < C->nlev; ++l) {
+    if (node_den_level<double>(C, C->L64[l]) != SMG_OK) return fail(SMG_EHIP);
+    if (d.precision == SMG_F32 && node_den_level<float>(C, C->L32[l]) != SMG_OK) return fail(SMG_EHIP);
   }
   // coarsest factorization (FP64): A_j^{-1} and the control Schur complement inverse
   const Level<double>& Lc = C->L64[C->nlev - 1];

@@ -59,6 +59,8 @@ __device__ __forceinline__ void prolong_nb(const T* __restrict__ e, int nc, int 
 //   bY_j = fP_j + sum_nb k_nb y_j,nb      (rhs of the A_j / E_j row)
 //   u    = (fU + sum_j d_j (c_j bY_j / a_j^2 - bP_j / a_j)) / (g + sum_j d_j c_j e_j / a_j^2)
 //   y_j  = (bY_j - e_j u) / a_j,   p_j = (bP_j - c_j y_j) / a_j
+// The denominator of u depends on the operator only and is read from L.gden
+// (node_den, at setup).
 // theta != 1 (relaxation) is supported for SRC == kPlain only; kProlong needs
 // colour 0.  W is a compile-time constant after inlining in the single-instance
 // kernel and a per-instance value in the batched one; the arithmetic is the same.
@@ -93,8 +95,10 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
   // chunk and is masked out of the sums.
   const ptrdiff_t ow = hw ? -(ptrdiff_t)N : 0, oe = he ? (ptrdiff_t)N : 0;
   const ptrdiff_t os = hs ? -(ptrdiff_t)rowN : 0, on = hn ? (ptrdiff_t)rowN : 0;
+  // per-node values first, so that their loads are in flight with the rest
+  const T fu = fU[node], gd = L.gden[node];
   T bP[JM], bY[JM], ia[JM], cq[JM], eq[JM];
-  T num = 0, den = 0;
+  T num = 0;
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int j0 = VW * (lane + c * W);
@@ -147,13 +151,15 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
       const T bp = fy[u] + sp[u], by = fp[u] + sy[u];
       const T t = cj[u] * ai * ai;
       num += act ? dj[u] * (t * by - ai * bp) : T(0);
-      den += act ? dj[u] * t * ej[u] : T(0);
       bP[q] = bp; bY[q] = by; ia[q] = ai; cq[q] = cj[u]; eq[q] = ej[u];
     }
   }
+  // e_j is first used after the sum over samples; without this the compiler
+  // sinks its load there and every wave waits a full memory latency at the end
+#pragma unroll
+  for (int q = 0; q < JM; ++q) asm volatile("" ::"v"(eq[q]));
   num = group_sum_w(num, W);
-  den = group_sum_w(den, W);
-  const T un = (fU[node] + num) / (L.g + den);
+  const T un = (fu + num) / gd;
   const bool relax = SRC == kPlain && theta != T(1);
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
@@ -182,6 +188,52 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
     }
   }
   if (lane == 0) U[node] = relax ? (T(1) - theta) * U[node] + theta * un : un;
+}
+
+// Denominator of the control update of the node solve, per node, by a group
+// of W lanes: gden = g + sum_j d_j c_j e_j / a_j^2, a_j the sum of the node's
+// four faces of sample j (eq. solution_reduced_system; positive whenever the
+// faces are and d_j c_j e_j >= 0).  Set up once per level, since it depends on
+// the operator only.
+template <typename T, int JM, int VW = 1>
+__device__ __forceinline__ void node_den(const LevelArgs<T>& L, T* __restrict__ gden, int node, int lane, int W) {
+  static_assert(JM % VW == 0, "whole chunks per lane");
+  constexpr int NCH = JM / VW;
+  const int n = L.n, N = L.N;
+  const int k = node / n, xx = node - k * n;
+  const size_t kxb = ((size_t)k * (n + 1) + xx) * N, kyb = (size_t)node * N, rowN = (size_t)n * N;
+  T den = 0;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int j0 = VW * (lane + c * W);
+    const bool act = j0 < N;
+    const int j = act ? j0 : N - VW;
+    T kw[VW], ke[VW], ks[VW], kn[VW], cj[VW], dj[VW], ej[VW];
+    ldv<VW>(L.kx + kxb + j, kw);
+    ldv<VW>(L.kx + kxb + N + j, ke);
+    ldv<VW>(L.ky + kyb + j, ks);
+    ldv<VW>(L.ky + kyb + rowN + j, kn);
+    ldv<VW>(L.c + j, cj);
+    ldv<VW>(L.d + j, dj);
+    ldv<VW>(L.e + j, ej);
+#pragma unroll
+    for (int u = 0; u < VW; ++u) {
+      const T a = (kw[u] + ke[u]) + (ks[u] + kn[u]);
+      const T ai = T(1) / a;
+      const T t = cj[u] * ai * ai;
+      den += act ? dj[u] * t * ej[u] : T(0);
+    }
+  }
+  den = group_sum_w(den, W);
+  if (lane == 0) gden[node] = L.g + den;
+}
+
+template <typename T, int W, int JM, int VW>
+__global__ __launch_bounds__(kBlock) void k_node_den(LevelArgs<T> L, T* __restrict__ gden) {
+  const int lane = threadIdx.x & (W - 1);
+  const int node = group_slot<W>(blockIdx.x);
+  if (node >= L.n * L.n) return;
+  node_den<T, JM, VW>(L, gden, node, lane, W);
 }
 
 // Waves per SIMD the compiler schedules the half-sweep for.  With JM >= 4
