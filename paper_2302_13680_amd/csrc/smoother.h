@@ -110,6 +110,14 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
     ldv<VW>(L.ky + kyb + j, ks);
     ldv<VW>(L.ky + kyb + rowN + j, kn);
     const size_t base = node * N + j;
+    // every load of the chunk is written before the arithmetic that uses it, so
+    // that the compiler issues them together
+    T cj[VW], dj[VW], ej[VW], fy[VW], fp[VW];
+    ldv<VW>(L.c + j, cj);
+    ldv<VW>(L.d + j, dj);
+    ldv<VW>(L.e + j, ej);
+    ldv<VW>(fY + base, fy);
+    ldv<VW>(fP + base, fp);
     // sum over existing neighbours of face * value (missing ones selected away)
     auto nbsum = [&](int u, T vw, T ve, T vs, T vn) -> T {
       return ((hw ? kw[u] * vw : T(0)) + (he ? ke[u] * ve : T(0))) +
@@ -122,27 +130,21 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
       T yw[VW], ye[VW], ys[VW], yn[VW], pw[VW], pe[VW], ps[VW], pn[VW];
       ldv<VW>(Y + base + ow, yw); ldv<VW>(Y + base + oe, ye); ldv<VW>(Y + base + os, ys); ldv<VW>(Y + base + on, yn);
       ldv<VW>(P + base + ow, pw); ldv<VW>(P + base + oe, pe); ldv<VW>(P + base + os, ps); ldv<VW>(P + base + on, pn);
+      T cwy[VW], cey[VW], csy[VW], cny[VW], cwp[VW], cep[VW], csp[VW], cnp[VW];
+      if constexpr (SRC == kProlong) {
+        prolong_nb<VW>(eY, nc, N, j, xx, k, cwy, cey, csy, cny);
+        prolong_nb<VW>(eP, nc, N, j, xx, k, cwp, cep, csp, cnp);
+      }
 #pragma unroll
       for (int u = 0; u < VW; ++u) {
         sy[u] = nbsum(u, yw[u], ye[u], ys[u], yn[u]);
         sp[u] = nbsum(u, pw[u], pe[u], ps[u], pn[u]);
+        if constexpr (SRC == kProlong) {
+          sy[u] += nbsum(u, cwy[u], cey[u], csy[u], cny[u]);
+          sp[u] += nbsum(u, cwp[u], cep[u], csp[u], cnp[u]);
+        }
       }
     }
-    if constexpr (SRC == kProlong) {
-      T cw[VW], ce[VW], cs[VW], cn[VW];
-      prolong_nb<VW>(eY, nc, N, j, xx, k, cw, ce, cs, cn);
-#pragma unroll
-      for (int u = 0; u < VW; ++u) sy[u] += nbsum(u, cw[u], ce[u], cs[u], cn[u]);
-      prolong_nb<VW>(eP, nc, N, j, xx, k, cw, ce, cs, cn);
-#pragma unroll
-      for (int u = 0; u < VW; ++u) sp[u] += nbsum(u, cw[u], ce[u], cs[u], cn[u]);
-    }
-    T cj[VW], dj[VW], ej[VW], fy[VW], fp[VW];
-    ldv<VW>(L.c + j, cj);
-    ldv<VW>(L.d + j, dj);
-    ldv<VW>(L.e + j, ej);
-    ldv<VW>(fY + base, fy);
-    ldv<VW>(fP + base, fp);
 #pragma unroll
     for (int u = 0; u < VW; ++u) {
       const int q = c * VW + u;
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_node_den(LevelArgs<T> L, T* __restri
 // and 14% (FP32) faster at 511x511, N=256 than the default 8-wave schedule.
 // The prolongation variant holds more live values and stays on the default.
 template <int JM, int SRC>
-constexpr int halfsweep_waves() { return JM >= 4 && SRC != kProlong ? 3 : 8; }
+constexpr int halfsweep_waves() { return SRC == kProlong ? (JM <= 2 ? 4 : 8) : (JM >= 4 ? 3 : 8); }
 
 // One half-sweep of collective Gauss-Seidel over every node of `colour`.
 template <typename T, int W, int JM, int SRC, int VW>
