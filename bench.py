@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--large-only", action="store_true",
+                    help="run only the 511x511, N=256 workload and print its record (for profiling)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune_lanes.json"))
     ap.add_argument("--counters", nargs="?", const="medium", choices=["medium", "large"],
                     help="launch only the finest-level FP64 half-sweep (20x) of the 255x255, N=64 "
@@ -275,6 +277,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.large_only:
+        large, _, _, _ = large_mixed_section(dev)
+        print(json.dumps({"large_mixed": large}), flush=True)
+        return
     if args.counters == "large":
         prob = inputs.large_mixed()
         ctx, f = binding.context_from_problem(prob, device=dev, gmres_restart=0)
