@@ -156,6 +156,17 @@ __global__ __launch_bounds__(kBlock) void k_partials_finalize(const double* __re
   if (threadIdx.x == 0) out[i] = v[0];
 }
 
+// Copy nv FP64 values into host-mapped memory, then store seq into the host
+// publish word; the system-scope fence orders the values before the word, so a
+// host that reads seq reads complete values (one wave).
+__global__ __launch_bounds__(64) void k_publish(const double* __restrict__ src, int nv, double* __restrict__ dst,
+                                                unsigned* __restrict__ word, unsigned seq) {
+  for (int i = threadIdx.x; i < nv; i += 64) dst[i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(word, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 struct ArnCoef {
   double g[kMaxBasis];   // coefficients of V_0..V_k
   double inv_rho;

@@ -179,7 +179,11 @@ struct smg_ctx {
   double* w = nullptr;         // [len0]
   double* rr = nullptr;        // [len0]
   size_t len0 = 0;
-  double* host = nullptr;      // pinned host staging
+  double* host = nullptr;      // host-mapped staging of read-back values (pinned, coherent)
+  double* host_dev = nullptr;  // the same memory as the device addresses it
+  unsigned* pub_host = nullptr;   // publish word after the values, host and device views
+  unsigned* pub_dev = nullptr;
+  unsigned pub_seq = 0;
   size_t used_bytes = 0;
   // captured V-cycles, one per (x, f, kind); kind = precision * 2 + zero_first
   struct Graph {
@@ -580,12 +584,35 @@ int sync(smg_ctx* C) {
   return SMG_OK;
 }
 
+// Bring nv FP64 values from device memory to C->host[0..nv) at the current
+// point of the stream: a one-wave kernel stores them into the host-mapped
+// staging and then a sequence number into the publish word; the host spins on
+// that word (a few microseconds after the kernel, instead of a copy and a
+// stream synchronization) and falls back to querying the stream, so an error
+// is reported and a completed stream always ends the wait.
+int readback(smg_ctx* C, const double* src, int nv) {
+  const unsigned seq = ++C->pub_seq;
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, C->stream, src, nv, C->host_dev, C->pub_dev, seq);
+  LAUNCH_CHECK();
+  for (unsigned long it = 1;; ++it) {
+    if (__atomic_load_n(C->pub_host, __ATOMIC_ACQUIRE) == seq) return SMG_OK;
+    if ((it & 255) == 0) {
+      const hipError_t q = hipStreamQuery(C->stream);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(C->pub_host, __ATOMIC_ACQUIRE) == seq) return SMG_OK;
+        C->err = "readback: stream complete without the published values";
+        return SMG_EHIP;
+      }
+      if (q != hipErrorNotReady) return hip_fail(C, q, "hipStreamQuery");
+    }
+  }
+}
+
 // FP64 residual of the finest level into out (may be null); norms to host
 // h[0..4] = { ||r||, ||r_Y||, ||r_U||, ||r_P||, ||f|| }.
 int residual_norms64(smg_ctx* C, const double* x, const double* f, double* out, double* h) {
   TRY((residual<double, double, double>(C, C->L64[0], x, f, out, 0, true)));
-  HIP_TRY(hipMemcpyAsync(C->host, C->norms, 5 * sizeof(double), hipMemcpyDeviceToHost, C->stream));
-  TRY(sync(C));
+  TRY(readback(C, C->norms, 5));
   for (int i = 0; i < 5; ++i) h[i] = C->host[i];
   return SMG_OK;
 }
@@ -597,8 +624,7 @@ int vec_norm(smg_ctx* C, const double* v, size_t len, double* out) {
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_mdot_finalize, dim3(kMaxBasis + 1), dim3(kBlock), 0, C->stream, C->mdp, kPartials, 0, 1, C->hdev, 0);
   LAUNCH_CHECK();
-  HIP_TRY(hipMemcpyAsync(C->host, C->hdev + kMaxBasis, sizeof(double), hipMemcpyDeviceToHost, C->stream));
-  TRY(sync(C));
+  TRY(readback(C, C->hdev + kMaxBasis, 1));
   *out = std::sqrt(C->host[0]);
   return SMG_OK;
 }
@@ -709,8 +735,7 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
     hipLaunchKernelGGL(k_partials_finalize, dim3(nslots), dim3(kBlock), 0, C->stream, (const double*)C->mdp,
                        kPartials, kArnSlots, C->hdev);
     LAUNCH_CHECK();
-    HIP_TRY(hipMemcpyAsync(C->host, C->hdev, sizeof(double) * nslots, hipMemcpyDeviceToHost, C->stream));
-    TRY(sync(C));
+    TRY(readback(C, C->hdev, nslots));
     const double* R = C->host;          // stored V_l . V_k
     const double* B = C->host + KMv;    // stored V_l . w
     const double c = C->host[2 * KMv], d = C->host[2 * KMv + 1], e = C->host[2 * KMv + 2];
@@ -782,8 +807,7 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
       hipLaunchKernelGGL(k_partials_finalize, dim3(1), dim3(kBlock), 0, C->stream, (const double*)C->mdp, kPartials,
                          1, C->hdev);
       LAUNCH_CHECK();
-      HIP_TRY(hipMemcpyAsync(C->host, C->hdev, sizeof(double), hipMemcpyDeviceToHost, C->stream));
-      TRY(sync(C));
+      TRY(readback(C, C->hdev, 1));
       hn = std::sqrt(std::max(C->host[0], 0.0));
       updated = true;
     }
@@ -1213,8 +1237,16 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
   }
   C->used_bytes = need;
   auto fail = [&](int rc) { smg_destroy(C); return rc; };
-  if (hipHostMalloc((void**)&C->host, sizeof(double) * 4 * (kMaxBasis + 1), hipHostMallocDefault) != hipSuccess)
-    return fail(SMG_EHIP);
+  {
+    const size_t nd = 4 * (kMaxBasis + 1);
+    if (hipHostMalloc((void**)&C->host, sizeof(double) * nd + 256, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void**)&C->host_dev, C->host, 0) != hipSuccess)
+      return fail(SMG_EHIP);
+    C->pub_host = (unsigned*)(C->host + nd);
+    C->pub_dev = (unsigned*)(C->host_dev + nd);
+    *C->pub_host = 0;
+  }
   if (!(d.flags & SMG_FLAG_EAGER) &&
       hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(SMG_EHIP);
@@ -1431,8 +1463,7 @@ int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, i
         TRY(residual_add(C, xc, C->L32[0].x, xo, f, C->L32[0].f));
         xc = xo;
       }
-      HIP_TRY(hipMemcpyAsync(C->host, C->norms, 5 * sizeof(double), hipMemcpyDeviceToHost, C->stream));
-      TRY(sync(C));
+      TRY(readback(C, C->norms, 5));
       for (int i = 0; i < 5; ++i) h[i] = C->host[i];
     } else {
       TRY(residual_norms64(C, x, f, C->V, h));   // r0 straight into the Krylov basis
