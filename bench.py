@@ -369,6 +369,13 @@ def main():
                 "kernel": "k_halfsweep<double,64,1> (finest level)", "avg_launch_us": round(t_launch_us, 2),
                 "algorithmic_bytes_per_launch": bytes_launch,
                 "stream_copy_GBs": round(copy_gbs, 1)}
+    # the same launch priced at half of a whole red+black sweep's 8 words per
+    # node-sample (faces, y, p and both right-hand sides read once per sweep), the
+    # bound of a sweep fused across both colours, which two launches cannot reach
+    sweep_half = 4.0 * N * n * n * 8 + n * n * 8
+    roofline["at_half_of_8_words_per_sweep"] = {
+        "bytes_per_launch": sweep_half,
+        "frac": round(sweep_half / (t_launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
 
     extra = {}
     if not args.quick:
