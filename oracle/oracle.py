@@ -42,6 +42,7 @@ def _load():
         build_oracle()
     L = C.CDLL(_LIB)
     vp = C.c_void_p
+    L.or_set_smoother.argtypes = [vp, C.c_int]
     L.or_create.restype = vp
     L.or_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                             _dp, _dp, _dp, _dp, _dp, C.c_double]
@@ -126,15 +127,21 @@ def norm(v) -> float:
 class Oracle:
     """Level hierarchy + coarsest factorization for one problem instance."""
 
-    def __init__(self, prob, coarsest_n: int = 7, pre: int = 2, post: int = 2, theta: float = 1.0):
+    def __init__(self, prob, coarsest_n: int = 7, pre: int = 2, post: int = 2, theta: float = 1.0,
+                 smoother: str = "gs"):
+        """smoother: "gs" (red-black collective Gauss-Seidel sweeps) or "jacobi"
+        (damped collective Jacobi steps, eq. collective_smoothing, damping theta)."""
         L = _load()
         self.n, self.N = prob.n, prob.N
         self.prob = prob
+        if smoother not in ("gs", "jacobi"):
+            raise ValueError("smoother must be 'gs' or 'jacobi'")
         self.ctx = L.or_create(prob.n, prob.N, coarsest_n, pre, post, theta, _f64(prob.kx),
                                _f64(prob.ky), _f64(prob.c), _f64(prob.d), _f64(prob.e),
                                float(prob.g))
         if not self.ctx:
             raise ValueError("oracle: invalid grid size or singular coarsest block")
+        L.or_set_smoother(self.ctx, 1 if smoother == "jacobi" else 0)
         self.nlev = L.or_nlevels(self.ctx)
         self.levels_n = [L.or_level_n(self.ctx, l) for l in range(self.nlev)]
 

@@ -141,7 +141,8 @@ static void SFX(or_halfsweep)(const SFX(or_lvl) *L, int colour, REAL theta,
 }
 
 /* Collective damped Jacobi step, eq. collective_smoothing as printed:
- * x <- x + theta sum_i P_i S~_i^{-1} R_i (f - S x).  Only used by checks. */
+ * x <- x + theta sum_i P_i S~_i^{-1} R_i (f - S x) (the smoother of the paper's
+ * experiments, with theta = 1/2). */
 static void SFX(or_jacobi)(const SFX(or_lvl) *L, REAL theta, REAL *xv, const REAL *f) {
   int n = L->n, N = L->N;
   size_t nn = (size_t)n * n, len = (size_t)(2 * N + 1) * nn;

@@ -43,6 +43,7 @@
 typedef struct {
   int nlev, N, pre, post;
   double theta;
+  int smoother;   /* 0: red-black collective Gauss-Seidel, 1: damped collective Jacobi */
   int n[OR_MAXLEV];
   double *kx[OR_MAXLEV], *ky[OR_MAXLEV];
   double *c[OR_MAXLEV], *d[OR_MAXLEV], *e[OR_MAXLEV];
@@ -310,25 +311,42 @@ void or_node_solve(int N, const double *a, const double *c, const double *d, con
 }
 
 /* --------------------------------------------------------------- V-cycle */
-/* Alg. 1 with n1 = pre and n2 = post collective Gauss-Seidel sweeps (red then
- * black half-sweeps), residual, restriction, recursive call from a zero
- * initial guess, coarse correction, post-smoothing. */
-static void vcycle_f64(or_ctx *C, int l, double *x, const double *f) {
-  if (l == C->nlev - 1) { or_coarse_solve(C, f, x); return; }
-  const or_lvl_f64 *L = &C->L[l];
-  for (int s = 0; s < C->pre; ++s) {
+/* One smoothing step: a collective Gauss-Seidel sweep (red then black
+ * half-sweeps) or a damped collective Jacobi step (eq. collective_smoothing). */
+static void smooth_f64(const or_ctx *C, const or_lvl_f64 *L, double *x, const double *f) {
+  if (C->smoother == 1) {
+    or_jacobi_f64(L, C->theta, x, f);
+  } else {
     or_halfsweep_f64(L, 0, C->theta, x, f);
     or_halfsweep_f64(L, 1, C->theta, x, f);
   }
+}
+static void smooth_f32(const or_ctx *C, const or_lvl_f32 *L, float *x, const float *f) {
+  float th = (float)C->theta;
+  if (C->smoother == 1) {
+    or_jacobi_f32(L, th, x, f);
+  } else {
+    or_halfsweep_f32(L, 0, th, x, f);
+    or_halfsweep_f32(L, 1, th, x, f);
+  }
+}
+
+/* Set the smoother of the context's V-cycles: 0 = collective Gauss-Seidel
+ * (default), 1 = damped collective Jacobi with damping theta. */
+void or_set_smoother(or_ctx *C, int smoother) { C->smoother = smoother; }
+
+/* Alg. 1 with n1 = pre and n2 = post smoothing steps, residual, restriction,
+ * recursive call from a zero initial guess, coarse correction, post-smoothing. */
+static void vcycle_f64(or_ctx *C, int l, double *x, const double *f) {
+  if (l == C->nlev - 1) { or_coarse_solve(C, f, x); return; }
+  const or_lvl_f64 *L = &C->L[l];
+  for (int s = 0; s < C->pre; ++s) smooth_f64(C, L, x, f);
   or_residual_f64(L, x, f, C->rw[l]);
   or_restrict_f64(C->n[l], C->N, C->rw[l], C->fw[l + 1]);
   memset(C->xw[l + 1], 0, sizeof(double) * vlen(C->n[l + 1], C->N));
   vcycle_f64(C, l + 1, C->xw[l + 1], C->fw[l + 1]);
   or_prolong_add_f64(C->n[l + 1], C->N, C->xw[l + 1], x);
-  for (int s = 0; s < C->post; ++s) {
-    or_halfsweep_f64(L, 0, C->theta, x, f);
-    or_halfsweep_f64(L, 1, C->theta, x, f);
-  }
+  for (int s = 0; s < C->post; ++s) smooth_f64(C, L, x, f);
 }
 
 /* The same cycle in FP32 arithmetic; the coarsest direct solve stays FP64. */
@@ -344,20 +362,13 @@ static void vcycle_f32(or_ctx *C, int l, float *x, const float *f) {
     return;
   }
   const or_lvl_f32 *L = &C->L32[l];
-  float th = (float)C->theta;
-  for (int s = 0; s < C->pre; ++s) {
-    or_halfsweep_f32(L, 0, th, x, f);
-    or_halfsweep_f32(L, 1, th, x, f);
-  }
+  for (int s = 0; s < C->pre; ++s) smooth_f32(C, L, x, f);
   or_residual_f32(L, x, f, C->rw32[l]);
   or_restrict_f32(C->n[l], N, C->rw32[l], C->fw32[l + 1]);
   memset(C->xw32[l + 1], 0, sizeof(float) * vlen(C->n[l + 1], N));
   vcycle_f32(C, l + 1, C->xw32[l + 1], C->fw32[l + 1]);
   or_prolong_add_f32(C->n[l + 1], N, C->xw32[l + 1], x);
-  for (int s = 0; s < C->post; ++s) {
-    or_halfsweep_f32(L, 0, th, x, f);
-    or_halfsweep_f32(L, 1, th, x, f);
-  }
+  for (int s = 0; s < C->post; ++s) smooth_f32(C, L, x, f);
 }
 
 void or_vcycle(or_ctx *C, double *x, const double *f, int ncycles) {
