@@ -102,6 +102,11 @@ typedef struct {
 #define SMG_FLAG_UNFUSED 2    /* separate residual, restriction, prolongation and zero-fill
                                  kernels (the default fuses them into neighbouring kernels when
                                  theta = 1; both compute the same iteration) */
+#define SMG_FLAG_JACOBI 4     /* smooth with damped collective Jacobi steps (eq.
+                                 collective_smoothing; the smoother of the paper's experiments,
+                                 which use theta = 0.5) instead of red-black collective
+                                 Gauss-Seidel sweeps; theta is the damping and pre / post count
+                                 Jacobi steps.  Not accepted by the batched solver. */
 
 typedef struct {
   const double *kx;   /* device, [n][n+1][N] */
@@ -176,6 +181,12 @@ int smg_smooth32(smg_ctx *ctx, int level, int colour, float *x, const float *f);
 /* coarse = R fine (R = P^T, full weighting with weights 1, 1/2, 1/4), fine of
  * level `level`, coarse of level + 1, all 2N+1 fields.  FP64 device vectors. */
 int smg_restrict(smg_ctx *ctx, int level, const double *fine, double *coarse);
+
+/* One damped collective Jacobi step on level `level` (eq. collective_smoothing):
+ * xout = x + theta D^{-1} (f - S x), D the block diagonal of the (2N+1)x(2N+1)
+ * node blocks of eq. reduced_matrices, theta the context's.  x, xout, f: FP64
+ * device vectors of that level's size; xout must not alias x (SMG_EINVAL). */
+int smg_jacobi(smg_ctx *ctx, int level, const double *x, double *xout, const double *f);
 
 /* coarse = R (f - S x) in one pass: the residual of Alg. 1 on level `level`
  * restricted to level + 1 without storing the fine residual (the result of

@@ -21,11 +21,12 @@ SMG_F64, SMG_F32 = 0, 1
 SMG_VCYCLE, SMG_GMRES = 0, 1
 SMG_FLAG_EAGER = 1
 SMG_FLAG_UNFUSED = 2
+SMG_FLAG_JACOBI = 4
 
 EXPORTED = [
     "smg_workspace_bytes", "smg_setup", "smg_destroy", "smg_strerror", "smg_last_error",
     "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_stream_copy", "smg_restrict",
-    "smg_residual_restrict", "smg_prolong_add", "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond",
+    "smg_residual_restrict", "smg_jacobi", "smg_prolong_add", "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond",
     "smg_solve", "smg_batch_workspace_bytes", "smg_batch_setup", "smg_batch_solve", "smg_batch_destroy",
     "smg_batch_last_error", "smg_tune_lanes", "smg_net_param_count", "smg_net_workspace_bytes",
     "smg_net_setup", "smg_net_destroy", "smg_net_last_error", "smg_net_set_params", "smg_net_get_params",
@@ -90,6 +91,7 @@ def load(path: str = LIB_PATH):
     L.smg_stream_copy.restype = i
     L.smg_restrict.argtypes = [vp, i, vp, vp]
     L.smg_residual_restrict.argtypes = [vp, i, vp, vp, vp]
+    L.smg_jacobi.argtypes = [vp, i, vp, vp, vp]
     L.smg_prolong_add.argtypes = [vp, i, vp, vp]
     L.smg_coarse_solve.argtypes = [vp, vp, vp]
     L.smg_level_faces.argtypes = [vp, i, vp, vp]
@@ -129,7 +131,7 @@ def load(path: str = LIB_PATH):
     for name in ["smg_net_set_params", "smg_net_get_params", "smg_net_forward", "smg_net_grad",
                  "smg_net_train_step", "smg_net_features", "smg_net_targets", "smg_net_lift"]:
         getattr(L, name).restype = i
-    for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_stream_copy", "smg_restrict", "smg_residual_restrict", "smg_prolong_add",
+    for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_stream_copy", "smg_restrict", "smg_residual_restrict", "smg_jacobi", "smg_prolong_add",
                  "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond", "smg_solve",
                  "smg_num_levels", "smg_level_n"]:
         getattr(L, name).restype = i
@@ -229,6 +231,9 @@ class Context:
 
     def restrict(self, level, fine, coarse):
         return self._check(self.L.smg_restrict(self.ctx, level, _ptr(fine), _ptr(coarse)))
+
+    def jacobi(self, level, x, xout, f):
+        return self._check(self.L.smg_jacobi(self.ctx, level, _ptr(x), _ptr(xout), _ptr(f)))
 
     def residual_restrict(self, level, x, f, coarse):
         return self._check(self.L.smg_residual_restrict(self.ctx, level, _ptr(x), _ptr(f), _ptr(coarse)))

@@ -220,7 +220,7 @@ bool desc_valid(const smg_desc& d, std::string* why) {
   if (!(d.theta > 0.0 && d.theta < 2.0)) return fail("theta must lie in (0, 2)");
   if (d.precision != SMG_F64 && d.precision != SMG_F32) return fail("precision must be SMG_F64 or SMG_F32");
   if (d.gmres_restart < 0 || d.gmres_restart > kMaxBasis - 1) return fail("gmres_restart must be in [0, 31]");
-  if (d.flags & ~(SMG_FLAG_EAGER | SMG_FLAG_UNFUSED)) return fail("unknown flag bits");
+  if (d.flags & ~(SMG_FLAG_EAGER | SMG_FLAG_UNFUSED | SMG_FLAG_JACOBI)) return fail("unknown flag bits");
   if (d.strip < 0 || (d.strip & 1)) return fail("strip must be 0 or a positive even number");
   return true;
 }
@@ -358,6 +358,23 @@ int halfsweep(smg_ctx* C, const Level<T>& L, T* x, const T* f, int colour, int s
   return SMG_OK;
 }
 
+// xout = xin + theta D^{-1} (f - S xin): one damped collective Jacobi step
+// (D the node block diagonal); xin and xout must not alias.
+template <typename T>
+int jacobi(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const T* f) {
+  const int nn = L.n * L.n;
+  const T theta = (T)C->desc.theta;
+  const LevelArgs<T> a = args(L, C->N, C->desc.strip);
+  lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    constexpr int VW = halfsweep_vw(decltype(Vc)::value, JM);
+    const int per = kBlock / W, nb = (nn + per - 1) / per;
+    hipLaunchKernelGGL((k_jacobi<T, W, JM, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, xin, xout, f, theta);
+  });
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
 // L.gden = g + sum_j d_j c_j e_j / a_j^2 per node, in the lane layout (and so
 // the summation order) of the level's half-sweep.
 template <typename T>
@@ -490,8 +507,40 @@ int coarse_solve(smg_ctx* C, const TV* F, TV* X) {
 //    half-sweep (kProlong): red nodes read their black neighbours corrected on
 //    the fly, and the black half-sweep that follows overwrites every black node.
 // For any theta the residual is restricted in the same pass that forms it.
+// count damped collective Jacobi steps on x, alternating between x and the
+// scratch t (an odd count ends with a copy back).
+template <typename T>
+int jacobi_steps(smg_ctx* C, const Level<T>& L, T* x, T* t, const T* f, int count) {
+  for (int s = 0; s < count; ++s) TRY(s % 2 == 0 ? jacobi<T>(C, L, x, t, f) : jacobi<T>(C, L, t, x, f));
+  if (count % 2) TRY((convert<T, T>(C, t, x, vlen(L.n, C->N))));
+  return SMG_OK;
+}
+
+// Alg. 1 with the damped collective Jacobi smoother (SMG_FLAG_JACOBI): the
+// smoothing steps are out of place through the level-0-sized scratch t, the
+// residual is restricted in the pass that forms it (unless unfused), and the
+// coarse correction is a separate prolongation pass.
+template <typename T>
+int vcycle_level_jacobi(smg_ctx* C, Level<T>* Ls, T* t, int l, T* x, const T* f, bool x_zero) {
+  if (l == C->nlev - 1) return coarse_solve<T>(C, f, x);
+  const Level<T>& L = Ls[l];
+  if (x_zero) TRY(fill<T>(C, x, vlen(L.n, C->N), T(0)));
+  TRY(jacobi_steps<T>(C, L, x, t, f, C->desc.pre));
+  Level<T>& Lc = Ls[l + 1];
+  if (!(C->desc.flags & SMG_FLAG_UNFUSED)) {
+    TRY(residual_restrict<T>(C, L, x, f, Lc.f));
+  } else {
+    TRY((residual<T, T, T>(C, L, x, f, t, 0, false)));
+    TRY(restrict_to<T>(C, L.n, t, Lc.f));
+  }
+  TRY(vcycle_level_jacobi<T>(C, Ls, t, l + 1, Lc.x, Lc.f, true));
+  TRY(prolong_add<T>(C, Lc.n, Lc.x, x));
+  return jacobi_steps<T>(C, L, x, t, f, C->desc.post);
+}
+
 template <typename T>
 int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f, bool x_zero) {
+  if (C->desc.flags & SMG_FLAG_JACOBI) return vcycle_level_jacobi<T>(C, Ls, r, l, x, f, x_zero);
   if (l == C->nlev - 1) return coarse_solve<T>(C, f, x);
   const Level<T>& L = Ls[l];
   const bool fused = C->desc.theta == 1.0 && !(C->desc.flags & SMG_FLAG_UNFUSED);
@@ -1366,6 +1415,12 @@ int smg_residual_restrict(smg_ctx* C, int level, const double* x, const double* 
   return residual_restrict<double>(C, C->L64[level], x, f, coarse);
 }
 
+int smg_jacobi(smg_ctx* C, int level, const double* x, double* xout, const double* f) {
+  if (!C || !x || !xout || !f || x == xout) return SMG_EINVAL;
+  TRY(check_level(C, level, 0));
+  return jacobi<double>(C, C->L64[level], x, xout, f);
+}
+
 int smg_prolong_add(smg_ctx* C, int level, const double* coarse, double* fine) {
   if (!C || !fine || !coarse) return SMG_EINVAL;
   TRY(check_level(C, level, 1));
@@ -1520,7 +1575,8 @@ static int batch_validate(smg_ctx* const* ctxs, int count, const int* lanes, smg
   }
   for (int i = 0; i < count; ++i) {
     smg_ctx* C = ctxs[i];
-    if (C->desc.precision != B->precision || C->desc.theta != 1.0 || C->desc.pre < 1 || C->desc.post < 1 ||
+    if (C->desc.precision != B->precision || C->desc.theta != 1.0 || (C->desc.flags & SMG_FLAG_JACOBI) ||
+        C->desc.pre < 1 || C->desc.post < 1 ||
         C->desc.pre != ctxs[0]->desc.pre || C->desc.post != ctxs[0]->desc.post || C->stream != ctxs[0]->stream)
       return SMG_EINVAL;
     const int W = lanes ? lanes[i] : default_lanes(C->N, C->desc.precision);

@@ -1,0 +1,144 @@
+"""GPU parity of the damped collective Jacobi smoother (eq. collective_smoothing,
+SMG_FLAG_JACOBI) against the oracle, through the C ABI.
+
+Tolerances as in test_gpu_parity: one step 1e-13 relative (rounding order only),
+iterates after k cycles 1e-12, solves to the oracle-evaluated residual with the
+oracle's count (+-1 for GMRES)."""
+import numpy as np
+import pytest
+
+from paper_2302_13680_amd import inputs
+from paper_2302_13680_amd.inputs import node_to_paper, paper_to_node
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_13680_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as o
+    return o
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def mk(n, N, seed=0, M=6):
+    return inputs.make_problem(n, N, 1e-4, M=M, sigma=0.5, decay=True, seed=seed)
+
+
+@pytest.mark.parametrize("n,N", [(15, 1), (15, 3), (31, 8), (15, 64), (15, 100), (7, 256), (63, 16),
+                                 (15, 300), (7, 512)])
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_jacobi_step(B, O, n, N, theta):
+    p = mk(n, N, seed=n + N)
+    o = O.Oracle(p, coarsest_n=7 if n >= 7 else 1)
+    ctx, f = B.context_from_problem(p, gmres_restart=0, theta=theta)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(o.vlen())
+    fr = rng.standard_normal(o.vlen())
+    ref = o.jacobi(x, fr, theta)
+    out = torch.empty(o.vlen(), dtype=torch.float64, device="cuda")
+    ctx.jacobi(0, dev(paper_to_node(x, n, N)), out, dev(paper_to_node(fr, n, N)))
+    assert rel(node_to_paper(host(out), n, N), ref) <= 1e-13
+
+
+def test_jacobi_rejects_aliased_output(B):
+    p = mk(15, 2, seed=1)
+    ctx, f = B.context_from_problem(p, gmres_restart=0, theta=0.5)
+    x = torch.zeros_like(f)
+    with pytest.raises(B.SmgError) as ei:
+        ctx.jacobi(0, x, x, f)
+    assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("n,N,pre", [(31, 8, 2), (63, 16, 2), (127, 64, 2), (31, 100, 2), (63, 16, 3)])
+def test_jacobi_vcycle_iterates(B, O, n, N, pre):
+    """k = 1..4 V(pre,pre) cycles with Jacobi steps (theta 1/2) from zero."""
+    p = mk(n, N, seed=n * N)
+    o = O.Oracle(p, pre=pre, post=pre, theta=0.5, smoother="jacobi")
+    ctx, f = B.context_from_problem(p, gmres_restart=0, pre=pre, post=pre, theta=0.5, flags=B.SMG_FLAG_JACOBI)
+    x_o = np.zeros(o.vlen())
+    xd = torch.zeros(o.vlen(), dtype=torch.float64, device="cuda")
+    for k in range(4):
+        x_o = o.vcycle(x_o, p.rhs_paper(), 1)
+        ctx.vcycle(xd, f, 1)
+        assert rel(node_to_paper(host(xd), n, N), x_o) <= 1e-12, k
+
+
+@pytest.mark.parametrize("n,N", [(63, 16), (127, 8)])
+def test_jacobi_solves(B, O, n, N):
+    """Stationary V(2,2) and GMRES(30) with the Jacobi-smoothed cycle to 1e-9:
+    the oracle's counts, and the oracle's residual below the tolerance."""
+    p = mk(n, N, seed=2 * n + N)
+    o = O.Oracle(p, theta=0.5, smoother="jacobi")
+    fp = p.rhs_paper()
+    _, its_v, _ = o.solve_vcycle(fp, tol=1e-9, maxit=100)
+    _, its_g, _ = o.gmres(fp, m=30, tol=1e-9, maxit=100)
+    ctx, f = B.context_from_problem(p, gmres_restart=30, theta=0.5, flags=B.SMG_FLAG_JACOBI)
+    for method, its_o, slack in ((B.SMG_VCYCLE, its_v, 0), (B.SMG_GMRES, its_g, 1)):
+        x = torch.zeros(o.vlen(), dtype=torch.float64, device="cuda")
+        rc, st = ctx.solve(x, f, method, rtol=1e-9, maxit=100)
+        assert rc == B.SMG_OK
+        assert abs(st["iterations"] - its_o) <= slack, (method, st["iterations"], its_o)
+        xg = node_to_paper(host(x), n, N)
+        assert np.linalg.norm(o.residual(xg, fp)) <= 1e-9 * np.linalg.norm(fp)
+
+
+def test_jacobi_graph_eager_and_unfused_agree(B):
+    p = mk(63, 16, seed=5)
+    kw = dict(gmres_restart=0, theta=0.5)
+    ga, f = B.context_from_problem(p, flags=B.SMG_FLAG_JACOBI, **kw)
+    ea, _ = B.context_from_problem(p, flags=B.SMG_FLAG_JACOBI | B.SMG_FLAG_EAGER, **kw)
+    uf, _ = B.context_from_problem(p, flags=B.SMG_FLAG_JACOBI | B.SMG_FLAG_EAGER | B.SMG_FLAG_UNFUSED, **kw)
+    xg = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    xe = torch.zeros_like(xg)
+    xu = torch.zeros_like(xg)
+    for k in range(4):
+        ga.vcycle(xg, f, 1)
+        ea.vcycle(xe, f, 1)
+        uf.vcycle(xu, f, 1)
+        scratch = torch.randn(1 << 20, device="cuda").sum()   # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe), k
+        assert (torch.linalg.norm(xu - xe) / torch.linalg.norm(xe)).item() <= 1e-13, k
+        del scratch
+
+
+@pytest.mark.parametrize("n,N", [(63, 16), (31, 100)])
+def test_jacobi_fp32_cycle_against_fp32_oracle(B, O, n, N):
+    p = mk(n, N, seed=13)
+    o = O.Oracle(p, theta=0.5, smoother="jacobi")
+    ctx, f = B.context_from_problem(p, gmres_restart=0, precision=B.SMG_F32, theta=0.5,
+                                    flags=B.SMG_FLAG_JACOBI)
+    x_o = o.vcycle32(np.zeros(o.vlen()), p.rhs_paper(), 2)
+    xd = torch.zeros(o.vlen(), dtype=torch.float64, device="cuda")
+    ctx.vcycle(xd, f, 2)
+    assert rel(node_to_paper(host(xd), n, N), x_o) <= 2e-5
+
+
+def test_batch_rejects_jacobi_contexts(B):
+    p = mk(31, 4, seed=2)
+    ctx, f = B.context_from_problem(p, gmres_restart=0, precision=B.SMG_F32, flags=B.SMG_FLAG_JACOBI)
+    x = torch.zeros_like(f)
+    with pytest.raises(B.SmgError):
+        B.Batch([ctx], [x], [f])
