@@ -2,6 +2,7 @@
 #pragma once
 #include "common.h"
 #include "smoother.h"
+#include "jacobi.h"
 #include "residual.h"
 #include "transfer.h"
 #include "coarse.h"
