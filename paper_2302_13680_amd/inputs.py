@@ -16,7 +16,9 @@ Discretization (5-point finite differences on the unit square, Dirichlet):
     those faces, the mass matrix is lumped, ``M = h^2 I``.
 
 Blocks of S (eq. (2) notation): C_j = zeta_j h^2 I, G = nu h^2 I,
-D_j = E_j = -h^2 I, with Monte Carlo weights zeta_j = 1/N.  Right-hand side:
+D_j = E_j = -h^2 I, with Monte Carlo weights zeta_j = 1/N or the weights of a
+quadrature rule in the random variables (``stochastic_collocation``: tensor
+Gauss-Hermite nodes and weights, the paper's SC setting).  Right-hand side:
 f_Y,j = zeta_j h^2 y_d, f_U = 0, f_P,j = h^2 f.  This is the paper's system
 with B = M after the adjoint is rescaled by zeta (the symmetrization remarked
 on at the end of Section 2).
@@ -109,15 +111,30 @@ def log_kappa(xi: np.ndarray, amps: np.ndarray, X: np.ndarray, Y: np.ndarray) ->
     return out
 
 
+def stochastic_collocation(M: int, q: int):
+    """Tensor Gauss-Hermite rule for M independent standard normal variables with
+    q points per variable: nodes xi (q^M, M) and weights zeta (q^M,) summing to 1
+    (Section 3.2's stochastic collocation; numpy's probabilists' Hermite rule,
+    weight exp(-t^2/2), normalized).  Node j has digits (i_1..i_M) in base q, the
+    last variable fastest."""
+    t, w = np.polynomial.hermite_e.hermegauss(q)
+    w = w / w.sum()
+    idx = np.array(np.meshgrid(*([np.arange(q)] * M), indexing="ij")).reshape(M, -1).T
+    xi = t[idx]
+    zeta = np.prod(w[idx], axis=1)
+    return xi, zeta
+
+
 def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float = 0.5,
                  decay: bool = False, seed: int = 0, yd: str | np.ndarray = "sin",
                  f: float = 1.0, xi: np.ndarray | None = None,
-                 kappa_const: float | None = None) -> Problem:
+                 kappa_const: float | None = None, weights: np.ndarray | None = None) -> Problem:
     """Build one seeded instance.
 
     ``decay=False`` gives amplitudes a_m = sigma (the 31x31, N=8 case, four modes
     of amplitude 0.5); ``decay=True`` gives a_m = sigma/m.  ``kappa_const`` replaces
-    the random field by a constant (used by closed-form checks).
+    the random field by a constant (used by closed-form checks).  ``weights`` are
+    the quadrature weights zeta_j of the samples (default 1/N, Monte Carlo).
     """
     h = 1.0 / (n + 1)
     if xi is None:
@@ -144,7 +161,9 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
             raise ValueError(yd)
     else:
         ydv = np.asarray(yd, dtype=np.float64).reshape(n, n)
-    zeta = np.full(N, 1.0 / N)
+    zeta = np.full(N, 1.0 / N) if weights is None else np.asarray(weights, dtype=np.float64)
+    if zeta.shape != (N,) or not np.all(zeta > 0):
+        raise ValueError("weights must be N positive numbers")
     c = zeta * h * h
     d = np.full(N, -h * h)
     e = np.full(N, -h * h)
@@ -154,7 +173,16 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
     fP = np.full((N, n, n), h * h * f)
     return Problem(n=n, N=N, nu=nu, kx=np.ascontiguousarray(kx), ky=np.ascontiguousarray(ky),
                    c=c, d=d, e=e, g=g, fY=fY, fU=fU, fP=fP, xi=xi, yd=ydv,
-                   meta=dict(M=xi.shape[1], sigma=sigma, decay=decay, seed=seed, f=f))
+                   meta=dict(M=xi.shape[1], sigma=sigma, decay=decay, seed=seed, f=f,
+                             quadrature="mc" if weights is None else "weights"))
+
+
+def collocation_problem(n: int, q: int, nu: float = 1e-4, *, M: int = 3, sigma: float = 0.5,
+                        decay: bool = True, **kw) -> Problem:
+    """The same model with the N = q^M tensor Gauss-Hermite nodes as samples and
+    their weights as zeta_j (the paper's SC columns use M = 3, N in {8, 27, 64, 125})."""
+    xi, zeta = stochastic_collocation(M, q)
+    return make_problem(n, xi.shape[0], nu, M=M, sigma=sigma, decay=decay, xi=xi, weights=zeta, **kw)
 
 
 def random_yd(n: int, rng: np.random.Generator, terms: int = 3, kmax: int = 4) -> np.ndarray:
