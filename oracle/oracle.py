@@ -43,6 +43,8 @@ def _load():
     L = C.CDLL(_LIB)
     vp = C.c_void_p
     L.or_set_smoother.argtypes = [vp, C.c_int]
+    L.or_set_control.restype = C.c_int
+    L.or_set_control.argtypes = [vp, _dp]
     L.or_create.restype = vp
     L.or_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                             _dp, _dp, _dp, _dp, _dp, C.c_double]
@@ -142,6 +144,9 @@ class Oracle:
         if not self.ctx:
             raise ValueError("oracle: invalid grid size or singular coarsest block")
         L.or_set_smoother(self.ctx, 1 if smoother == "jacobi" else 0)
+        if getattr(prob, "ctrl", None) is not None:
+            if L.or_set_control(self.ctx, _f64(prob.ctrl)) != 0:
+                raise ValueError("oracle: singular coarsest block with this control mask")
         self.nlev = L.or_nlevels(self.ctx)
         self.levels_n = [L.or_level_n(self.ctx, l) for l in range(self.nlev)]
 

@@ -16,7 +16,12 @@ typedef struct {
   const REAL *kx, *ky;       /* [N][n][n+1], [N][n+1][n] */
   const REAL *c, *d, *e;     /* [N] diagonal values of C_j, D_j, E_j */
   REAL g;                    /* diagonal value of G */
+  const REAL *mk;            /* [n][n] control mask m_i (NULL: 1 everywhere): the node
+                                entries of D_j and E_j are m_i d_j and m_i e_j */
 } SFX(or_lvl);
+
+/* control mask of node i */
+static inline REAL SFX(or_mask)(const SFX(or_lvl) *L, size_t i) { return L->mk ? L->mk[i] : (REAL)1; }
 
 #define OR_KX(L, j, k, f) ((L)->kx[((size_t)(j) * (L)->n + (k)) * ((L)->n + 1) + (f)])
 #define OR_KY(L, j, gg, x) ((L)->ky[((size_t)(j) * ((L)->n + 1) + (gg)) * (L)->n + (x)])
@@ -58,12 +63,12 @@ static void SFX(or_apply)(const SFX(or_lvl) *L, const REAL *xv, REAL *out) {
       for (int x = 0; x < n; ++x) {
         size_t i = (size_t)k * n + x;
         oY[i] = L->c[j] * Y[i] + SFX(or_stencil)(L, j, P, x, k);
-        oP[i] = SFX(or_stencil)(L, j, Y, x, k) + L->e[j] * U[i];
+        oP[i] = SFX(or_stencil)(L, j, Y, x, k) + (SFX(or_mask)(L, i) * L->e[j]) * U[i];
       }
   }
   for (size_t i = 0; i < nn; ++i) {
-    REAL s = L->g * U[i];
-    for (int j = 0; j < N; ++j) s += L->d[j] * xv[(size_t)(N + 1) * nn + (size_t)j * nn + i];
+    REAL s = L->g * U[i], mi = SFX(or_mask)(L, i);
+    for (int j = 0; j < N; ++j) s += (mi * L->d[j]) * xv[(size_t)(N + 1) * nn + (size_t)j * nn + i];
     oU[i] = s;
   }
 }
@@ -108,11 +113,15 @@ static void SFX(or_halfsweep)(const SFX(or_lvl) *L, int colour, REAL theta,
   const REAL *fU = f + (size_t)N * nn;
 #pragma omp parallel for schedule(static)
   for (int k = 0; k < n; ++k) {
-    REAL *a = (REAL *)malloc(sizeof(REAL) * 5 * (size_t)N);
-    REAL *bP = a + N, *bY = a + 2 * N, *yn = a + 3 * N, *pn = a + 4 * N;
+    REAL *a = (REAL *)malloc(sizeof(REAL) * 7 * (size_t)N);
+    REAL *bP = a + N, *bY = a + 2 * N, *yn = a + 3 * N, *pn = a + 4 * N, *dm = a + 5 * N, *em = a + 6 * N;
     for (int x = 0; x < n; ++x) {
       if (((x + k) & 1) != colour) continue;
       size_t i = (size_t)k * n + x;
+      for (int j = 0; j < N; ++j) {
+        dm[j] = SFX(or_mask)(L, i) * L->d[j];
+        em[j] = SFX(or_mask)(L, i) * L->e[j];
+      }
       for (int j = 0; j < N; ++j) {
         const REAL *Y = xv + (size_t)j * nn;
         const REAL *P = xv + (size_t)(N + 1) * nn + (size_t)j * nn;
@@ -127,7 +136,7 @@ static void SFX(or_halfsweep)(const SFX(or_lvl) *L, int colour, REAL theta,
               + ks * SFX(or_at)(Y, n, x, k - 1) + kn * SFX(or_at)(Y, n, x, k + 1);
       }
       REAL un;
-      SFX(or_node_solve)(N, a, L->c, L->d, L->e, L->g, bP, fU[i], bY, yn, &un, pn);
+      SFX(or_node_solve)(N, a, L->c, dm, em, L->g, bP, fU[i], bY, yn, &un, pn);
       for (int j = 0; j < N; ++j) {
         REAL *Y = xv + (size_t)j * nn;
         REAL *P = xv + (size_t)(N + 1) * nn + (size_t)j * nn;
@@ -147,19 +156,21 @@ static void SFX(or_jacobi)(const SFX(or_lvl) *L, REAL theta, REAL *xv, const REA
   int n = L->n, N = L->N;
   size_t nn = (size_t)n * n, len = (size_t)(2 * N + 1) * nn;
   REAL *r = (REAL *)malloc(sizeof(REAL) * len);
-  REAL *w = (REAL *)malloc(sizeof(REAL) * 5 * (size_t)N);
-  REAL *a = w, *bP = w + N, *bY = w + 2 * N, *yn = w + 3 * N, *pn = w + 4 * N;
+  REAL *w = (REAL *)malloc(sizeof(REAL) * 7 * (size_t)N);
+  REAL *a = w, *bP = w + N, *bY = w + 2 * N, *yn = w + 3 * N, *pn = w + 4 * N, *dm = w + 5 * N, *em = w + 6 * N;
   SFX(or_residual)(L, xv, f, r);
   for (int k = 0; k < n; ++k)
     for (int x = 0; x < n; ++x) {
       size_t i = (size_t)k * n + x;
       for (int j = 0; j < N; ++j) {
+        dm[j] = SFX(or_mask)(L, i) * L->d[j];
+        em[j] = SFX(or_mask)(L, i) * L->e[j];
         a[j] = OR_KX(L, j, k, x) + OR_KX(L, j, k, x + 1) + OR_KY(L, j, k, x) + OR_KY(L, j, k + 1, x);
         bP[j] = r[(size_t)j * nn + i];
         bY[j] = r[(size_t)(N + 1) * nn + (size_t)j * nn + i];
       }
       REAL un;
-      SFX(or_node_solve)(N, a, L->c, L->d, L->e, L->g, bP, r[(size_t)N * nn + i], bY, yn, &un, pn);
+      SFX(or_node_solve)(N, a, L->c, dm, em, L->g, bP, r[(size_t)N * nn + i], bY, yn, &un, pn);
       for (int j = 0; j < N; ++j) {
         xv[(size_t)j * nn + i] += theta * yn[j];
         xv[(size_t)(N + 1) * nn + (size_t)j * nn + i] += theta * pn[j];

@@ -53,6 +53,7 @@ class Problem:
     xi: np.ndarray = field(default=None, repr=False)
     yd: np.ndarray = field(default=None, repr=False)
     meta: dict = field(default_factory=dict)
+    ctrl: np.ndarray = field(default=None, repr=False)   # (n, n) control mask, None: everywhere
 
     @property
     def h(self) -> float:
@@ -128,13 +129,17 @@ def stochastic_collocation(M: int, q: int):
 def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float = 0.5,
                  decay: bool = False, seed: int = 0, yd: str | np.ndarray = "sin",
                  f: float = 1.0, xi: np.ndarray | None = None,
-                 kappa_const: float | None = None, weights: np.ndarray | None = None) -> Problem:
+                 kappa_const: float | None = None, weights: np.ndarray | None = None,
+                 control_region: tuple | None = None) -> Problem:
     """Build one seeded instance.
 
     ``decay=False`` gives amplitudes a_m = sigma (the 31x31, N=8 case, four modes
     of amplitude 0.5); ``decay=True`` gives a_m = sigma/m.  ``kappa_const`` replaces
     the random field by a constant (used by closed-form checks).  ``weights`` are
     the quadrature weights zeta_j of the samples (default 1/N, Monte Carlo).
+    ``control_region = (x0, x1, y0, y1)`` restricts the control to the nodes in
+    the closed rectangle [x0, x1] x [y0, y1] (local control; the mask of the
+    node entries of D_j and E_j); None lets it act everywhere.
     """
     h = 1.0 / (n + 1)
     if xi is None:
@@ -171,8 +176,14 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
     fY = (zeta * h * h)[:, None, None] * ydv[None]
     fU = np.zeros((n, n))
     fP = np.full((N, n, n), h * h * f)
+    ctrl = None
+    if control_region is not None:
+        x0, x1, y0, y1 = control_region
+        eps = 1e-12
+        ctrl = (((XX >= x0 - eps) & (XX <= x1 + eps) & (YY >= y0 - eps) & (YY <= y1 + eps))
+                .astype(np.float64))
     return Problem(n=n, N=N, nu=nu, kx=np.ascontiguousarray(kx), ky=np.ascontiguousarray(ky),
-                   c=c, d=d, e=e, g=g, fY=fY, fU=fU, fP=fP, xi=xi, yd=ydv,
+                   c=c, d=d, e=e, g=g, fY=fY, fU=fU, fP=fP, xi=xi, yd=ydv, ctrl=ctrl,
                    meta=dict(M=xi.shape[1], sigma=sigma, decay=decay, seed=seed, f=f,
                              quadrature="mc" if weights is None else "weights"))
 
