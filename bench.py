@@ -360,6 +360,39 @@ def main():
     csc.close()
     del csc, fsc, xsc
 
+    # ---------------- local control on [0.25, 0.75]^2 (the paper's square-domain experiment)
+    plc = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=1, control_region=(0.25, 0.75, 0.25, 0.75))
+    clc, flc = binding.context_from_problem(plc, device=dev, gmres_restart=30)
+    xlc = torch.zeros(plc.dof, dtype=torch.float64, device=dev)
+    lc = {"control": "on the nodes of [0.25, 0.75]^2 only (control mask)"}
+    for name, method in (("gmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
+        timed_solve(clc, xlc, flc, method, args.rtol)             # warm-up (graph capture)
+        t, stl = timed_solve(clc, xlc, flc, method, args.rtol)
+        lc[name + "_time_to_1e-8_ms"] = round(t, 3)
+        lc[name + "_iterations"] = stl["iterations"]
+    clc.close()
+    del clc, flc, xlc
+    # the configuration of the paper's local-control table (31x31 interior nodes, three
+    # levels, 5^3 Gauss-Hermite nodes, nu 1e-4, collective Jacobi theta 1/2, V(2,2),
+    # tolerance 1e-9; y_d = exp(y^2) sin(2 pi x) sin(2 pi y), no source) with this
+    # build's finite differences and analytic coefficient expansion
+    h31 = 1.0 / 32
+    g31 = (np.arange(31) + 1) * h31
+    X31, Y31 = np.meshgrid(g31, g31)
+    yd31 = np.exp(Y31 ** 2) * np.sin(2 * np.pi * X31) * np.sin(2 * np.pi * Y31)
+    pt = inputs.collocation_problem(31, 5, 1e-4, M=3, sigma=float(np.sqrt(0.5)), decay=True, yd=yd31, f=0.0,
+                                    control_region=(0.25, 0.75, 0.25, 0.75))
+    ct, ft = binding.context_from_problem(pt, device=dev, gmres_restart=30, theta=0.5,
+                                          flags=binding.SMG_FLAG_JACOBI)
+    xt = torch.zeros(pt.dof, dtype=torch.float64, device=dev)
+    _, st_v = timed_solve(ct, xt, ft, binding.SMG_VCYCLE, 1e-9)
+    _, st_g = timed_solve(ct, xt, ft, binding.SMG_GMRES, 1e-9)
+    lc["paper_local_control_setting"] = {
+        "n": 31, "N": pt.N, "levels": list(ct.levels_n), "vcycle_iterations": st_v["iterations"],
+        "gmres_iterations": st_g["iterations"], "paper_printed_vcycle_gmres": [20, 13]}
+    ct.close()
+    del ct, ft, xt
+
     # ---------------- roofline of the dominant kernel: finest-level half-sweep
     xs = torch.zeros(dof, dtype=torch.float64, device=dev)
     for _ in range(10):
@@ -446,6 +479,7 @@ def main():
         "gmres_iterations_1e-10": st10["iterations"],
         "jacobi_smoother": jac,
         "stochastic_collocation": sc,
+        "local_control": lc,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

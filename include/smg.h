@@ -115,6 +115,12 @@ typedef struct {
   const double *d;    /* host, [N]: D_j = d_j I */
   const double *e;    /* host, [N]: E_j = e_j I */
   double g;           /* G = g I (> 0) */
+  const double *ctrl; /* host, [n][n] or NULL: control mask m_i in [0, 1] (local control, e.g.
+                         the indicator of the control region): the node entries of D_j and E_j
+                         become m_i d_j and m_i e_j, so where m_i = 0 the node solve has no
+                         control (eq. solution_reduced_system2) and, with f_U = 0 there,
+                         u_i = 0.  Coarse levels take the mask by injection.  NULL: the
+                         control acts everywhere.  Values outside [0, 1]: SMG_EINVAL. */
 } smg_blocks;
 
 typedef struct {

@@ -43,7 +43,8 @@ class Desc(C.Structure):
 
 class Blocks(C.Structure):
     _fields_ = [("kx", C.c_void_p), ("ky", C.c_void_p), ("c", C.POINTER(C.c_double)),
-                ("d", C.POINTER(C.c_double)), ("e", C.POINTER(C.c_double)), ("g", C.c_double)]
+                ("d", C.POINTER(C.c_double)), ("e", C.POINTER(C.c_double)), ("g", C.c_double),
+                ("ctrl", C.POINTER(C.c_double))]
 
 
 class Stats(C.Structure):
@@ -156,11 +157,12 @@ class Context:
     """One smg_ctx: hierarchy + coarsest factorization for one instance.
 
     kx, ky: float64 device tensors in the node layout ([n][n+1][N], [n+1][n][N]);
-    c, d, e: per-sample diagonal values (host sequences), g: scalar.
+    c, d, e: per-sample diagonal values (host sequences), g: scalar; ctrl: optional
+    (n, n) host control mask in [0, 1] (local control), None: control everywhere.
     """
 
     def __init__(self, n, N, kx, ky, c, d, e, g, *, coarsest_n=7, pre=2, post=2, theta=1.0,
-                 precision=SMG_F64, gmres_restart=30, flags=0, strip=0, stream=None):
+                 precision=SMG_F64, gmres_restart=30, flags=0, strip=0, stream=None, ctrl=None):
         import torch
         L = load()
         self.L = L
@@ -177,8 +179,10 @@ class Context:
         self._d = np.ascontiguousarray(d, dtype=np.float64)
         self._e = np.ascontiguousarray(e, dtype=np.float64)
         dp = C.POINTER(C.c_double)
+        self._ctrl = None if ctrl is None else np.ascontiguousarray(ctrl, dtype=np.float64).reshape(n * n)
         blocks = Blocks(_ptr(kx), _ptr(ky), self._c.ctypes.data_as(dp), self._d.ctypes.data_as(dp),
-                        self._e.ctypes.data_as(dp), float(g))
+                        self._e.ctypes.data_as(dp), float(g),
+                        None if self._ctrl is None else self._ctrl.ctypes.data_as(dp))
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = C.c_void_p()
         rc = L.smg_setup(C.byref(self.desc), C.byref(blocks), _ptr(self.workspace), nbytes,
@@ -429,6 +433,7 @@ def context_from_problem(prob, device="cuda", **kw):
     kxn, kyn = prob.faces_node()
     kx = torch.from_numpy(kxn).to(device)
     ky = torch.from_numpy(kyn).to(device)
+    kw.setdefault("ctrl", getattr(prob, "ctrl", None))
     ctx = Context(prob.n, prob.N, kx, ky, prob.c, prob.d, prob.e, prob.g, **kw)
     f = torch.from_numpy(prob.rhs_node()).to(device)
     return ctx, f

@@ -32,6 +32,7 @@ struct BTask {
   const double* c64;   // coarsest diagonal blocks in FP64
   const double* d64;
   const double* e64;
+  const double* mk64;  // coarsest control mask in FP64
 };
 
 // FP64 outer residual of one instance, rounded into the reduced-precision
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(64) void kb_coarse1(const BTask<T>* __restrict__ ta
   const int b = blockIdx.x;
   const BTask<T>& t = tasks[find_task(tasks, ntasks, b)];
   if (done[t.inst]) return;
-  coarse_phase1_sample<T>(b - t.block0, t.m, t.L.N, t.Ainv, t.c64, t.d64, t.f, t.ds);
+  coarse_phase1_sample<T>(b - t.block0, t.m, t.L.N, t.Ainv, t.c64, t.d64, t.mk64, t.f, t.ds);
 }
 
 template <typename T>
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(64) void kb_coarse2(const BTask<T>* __restrict__ ta
   const int b = blockIdx.x;
   const BTask<T>& t = tasks[find_task(tasks, ntasks, b)];
   if (done[t.inst]) return;
-  coarse_phase2_sample<T>(b - t.block0, t.m, t.L.N, t.Ainv, t.Sinv, t.c64, t.e64, t.f, t.ds, t.x);
+  coarse_phase2_sample<T>(b - t.block0, t.m, t.L.N, t.Ainv, t.Sinv, t.c64, t.e64, t.mk64, t.f, t.ds, t.x);
 }
 
 // FP64 outer residual, rounded into t.out; per-block squared norms into partials.

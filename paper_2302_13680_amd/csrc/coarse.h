@@ -86,11 +86,13 @@ __global__ __launch_bounds__(kBlock) void k_coarse_invert_A(int n, int N, const 
   }
 }
 
-// terms[j] = (d_j c_j e_j Ainv_j Ainv_j)^T from the transposed inverses (one block per sample)
+// terms[j] = (d_j c_j e_j diag(mk) Ainv_j Ainv_j diag(mk))^T from the transposed
+// inverses (one block per sample; mk: control mask)
 __global__ __launch_bounds__(kBlock) void k_coarse_schur_terms(int m, const double* __restrict__ Ainv,
                                                                const double* __restrict__ c,
                                                                const double* __restrict__ d,
                                                                const double* __restrict__ e,
+                                                               const double* __restrict__ mk,
                                                                double* __restrict__ terms) {
   __shared__ double A[kMaxCoarse * kMaxCoarse];
   const int j = blockIdx.x;
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_schur_terms(int m, const doub
     const int i = idx / m, q = idx - i * m;
     double t = 0.0;
     for (int r = 0; r < m; ++r) t += A[i * m + r] * A[r * m + q];
-    terms[(size_t)j * m * m + idx] = s * t;
+    terms[(size_t)j * m * m + idx] = (mk[i] * s * mk[q]) * t;
   }
 }
 
@@ -122,8 +124,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_schur_invert(int m, int N, co
 
 // ------------------------------------------------------------ coarsest solve
 // Block elimination of eq. (2) on the coarsest grid, one block per sample j:
-//   phase 1: ds_j = d_j A_j^{-1} (F_Y,j - c_j A_j^{-1} F_P,j)
-//   phase 2: u = Sinv (F_U - sum_j ds_j);  y_j = A_j^{-1}(F_P,j - e_j u);
+//   phase 1: ds_j = D_j A_j^{-1} (F_Y,j - c_j A_j^{-1} F_P,j)
+//   phase 2: u = Sinv (F_U - sum_j ds_j);  y_j = A_j^{-1}(F_P,j - E_j u);
+// with D_j = d_j diag(mk), E_j = e_j diag(mk) (mk: control mask);
 //            p_j = A_j^{-1}(F_Y,j - c_j y_j)
 // Vectors in the level layout (type TV), arithmetic in FP64.
 // (M v)_i with M stored transposed (MT[c][i] = M[i][c]): coalesced across threads i.
@@ -147,21 +150,24 @@ __device__ __forceinline__ double dot_row(const double (&a)[kMaxCoarse], int m, 
 template <typename TV>
 __device__ __forceinline__ void coarse_phase1_sample(int j, int m, int N, const double* __restrict__ Ainv,
                                                      const double* __restrict__ c, const double* __restrict__ d,
-                                                     const TV* __restrict__ F, double* __restrict__ ds) {
+                                                     const double* __restrict__ mk, const TV* __restrict__ F,
+                                                     double* __restrict__ ds) {
   __shared__ double sF[kMaxCoarse], sT[kMaxCoarse];
   const int i = threadIdx.x;
   const double* Aj = Ainv + (size_t)j * m * m;
   const TV* FY = F;
   const TV* FP = F + (size_t)(N + 1) * m;
   double a[kMaxCoarse];
+  double dm = 0.0;   // this row's D_j entry, loaded with the rest
   if (i < m) {
     load_row(Aj, m, i, a);
     sF[i] = (double)FP[(size_t)i * N + j];
+    dm = mk[i] * d[j];
   }
   __syncthreads();
   if (i < m) sT[i] = (double)FY[(size_t)i * N + j] - c[j] * dot_row(a, m, sF);
   __syncthreads();
-  if (i < m) ds[(size_t)j * m + i] = d[j] * dot_row(a, m, sT);
+  if (i < m) ds[(size_t)j * m + i] = dm * dot_row(a, m, sT);
 }
 
 // Phase 2 for sample j (one block of >= m threads); block j = 0 also writes u.
@@ -169,8 +175,8 @@ template <typename TV>
 __device__ __forceinline__ void coarse_phase2_sample(int j, int m, int N, const double* __restrict__ Ainv,
                                                      const double* __restrict__ Sinv,
                                                      const double* __restrict__ c, const double* __restrict__ e,
-                                                     const TV* __restrict__ F, const double* __restrict__ ds,
-                                                     TV* __restrict__ X) {
+                                                     const double* __restrict__ mk, const TV* __restrict__ F,
+                                                     const double* __restrict__ ds, TV* __restrict__ X) {
   __shared__ double sR[kMaxCoarse], sU[kMaxCoarse], sT[kMaxCoarse], sY[kMaxCoarse];
   const int i = threadIdx.x;
   const double* Aj = Ainv + (size_t)j * m * m;
@@ -178,9 +184,11 @@ __device__ __forceinline__ void coarse_phase2_sample(int j, int m, int N, const 
   const TV* FU = F + (size_t)N * m;
   const TV* FP = F + (size_t)(N + 1) * m;
   double a[kMaxCoarse], si[kMaxCoarse];
+  double em = 0.0;   // this row's E_j entry, loaded with the rest
   if (i < m) {
     load_row(Aj, m, i, a);
     load_row(Sinv, m, i, si);
+    em = mk[i] * e[j];
     // F_U - sum_j ds_j, in sample order; 16 loads in flight per round trip
     double s = (double)FU[i];
     for (int q0 = 0; q0 < N; q0 += 16) {
@@ -195,7 +203,7 @@ __device__ __forceinline__ void coarse_phase2_sample(int j, int m, int N, const 
   __syncthreads();
   if (i < m) sU[i] = dot_row(si, m, sR);
   __syncthreads();
-  if (i < m) sT[i] = (double)FP[(size_t)i * N + j] - e[j] * sU[i];
+  if (i < m) sT[i] = (double)FP[(size_t)i * N + j] - em * sU[i];
   __syncthreads();
   if (i < m) sY[i] = dot_row(a, m, sT);
   __syncthreads();
@@ -212,17 +220,18 @@ __device__ __forceinline__ void coarse_phase2_sample(int j, int m, int N, const 
 template <typename TV>
 __global__ __launch_bounds__(64) void k_coarse_phase1(int m, int N, const double* __restrict__ Ainv,
                                                       const double* __restrict__ c, const double* __restrict__ d,
-                                                      const TV* __restrict__ F, double* __restrict__ ds) {
-  coarse_phase1_sample<TV>(blockIdx.x, m, N, Ainv, c, d, F, ds);
+                                                      const double* __restrict__ mk, const TV* __restrict__ F,
+                                                      double* __restrict__ ds) {
+  coarse_phase1_sample<TV>(blockIdx.x, m, N, Ainv, c, d, mk, F, ds);
 }
 
 template <typename TV>
 __global__ __launch_bounds__(64) void k_coarse_phase2(int m, int N, const double* __restrict__ Ainv,
                                                       const double* __restrict__ Sinv,
                                                       const double* __restrict__ c, const double* __restrict__ e,
-                                                      const TV* __restrict__ F, const double* __restrict__ ds,
-                                                      TV* __restrict__ X) {
-  coarse_phase2_sample<TV>(blockIdx.x, m, N, Ainv, Sinv, c, e, F, ds, X);
+                                                      const double* __restrict__ mk, const TV* __restrict__ F,
+                                                      const double* __restrict__ ds, TV* __restrict__ X) {
+  coarse_phase2_sample<TV>(blockIdx.x, m, N, Ainv, Sinv, c, e, mk, F, ds, X);
 }
 
 }  // namespace smg

@@ -34,8 +34,17 @@ struct LevelArgs {
   const T* __restrict__ e;
   T g;
   const T* __restrict__ gden;   // [n][n] per node: g + sum_j d_j c_j e_j / a_j^2 (set up once)
+  const T* __restrict__ mk;     // [n][n] control mask m_i (all ones when the control acts
+                                // everywhere): D_j, E_j node entries m_i d_j, m_i e_j
   int strip;   // columns per strip of the colour traversal (colour_node)
 };
+
+// control mask of node i; kernels compiled with MK = false (contexts whose control
+// acts everywhere) use 1 without a load
+template <bool MK, typename T>
+__device__ __forceinline__ T ctrl_mask(const LevelArgs<T>& L, size_t i) {
+  if constexpr (MK) return L.mk[i]; else return T(1);
+}
 
 // MI355X dispatches workgroup b to XCD b % 8.  Remap so that every XCD works on
 // one contiguous range of logical tiles (neighbouring grid rows then share that
@@ -44,6 +53,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
   const int q = nblocks / kNumXcd, r = nblocks % kNumXcd;
   const int xcd = b % kNumXcd, idx = b / kNumXcd;
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// Blocks of a launch that gives each of `units` groups W lanes: the grid every
+// per-node kernel is launched with.  Computed from an argument that the kernel
+// loads anyway, rather than read from the dispatch's hidden arguments, which
+// would cost each block's start one more kernel-argument cache line (measured:
+// a few percent on the latency-bound coarse levels).
+template <int W>
+__device__ __forceinline__ int group_blocks(int units) {
+  constexpr int per = kBlock / W;
+  return (units + per - 1) / per;
 }
 
 // Index of this thread's group of W lanes in a launch of kBlock-thread blocks

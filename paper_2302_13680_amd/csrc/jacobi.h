@@ -12,7 +12,7 @@ namespace smg {
 // halfsweep_node (with the residual rows as right-hand sides and no neighbour
 // terms), and xout_i = xin_i + theta d.  Out of place: xin and xout must not
 // alias (every node reads its neighbours' old values).
-template <typename T, int JM, int VW = 1>
+template <typename T, int JM, int VW = 1, bool MK = true>
 __device__ __forceinline__ void jacobi_node(const LevelArgs<T>& L, const T* __restrict__ xin, T* __restrict__ xout,
                                             const T* __restrict__ f, T theta, int slot, int lane, int W) {
   static_assert(JM % VW == 0, "whole chunks per lane");
@@ -34,6 +34,7 @@ __device__ __forceinline__ void jacobi_node(const LevelArgs<T>& L, const T* __re
   const ptrdiff_t ow = hw ? -(ptrdiff_t)N : 0, oe = he ? (ptrdiff_t)N : 0;
   const ptrdiff_t os = hs ? -(ptrdiff_t)rowN : 0, on = hn ? (ptrdiff_t)rowN : 0;
   const T u = xin[(size_t)N * nn + node], fu = f[(size_t)N * nn + node], gd = L.gden[node];
+  const T mi = ctrl_mask<MK>(L, node);
   T rYq[JM], rPq[JM], ia[JM], cq[JM], eq[JM], yo[JM], po[JM];
   T dsum = 0, num = 0;
 #pragma unroll
@@ -67,12 +68,12 @@ __device__ __forceinline__ void jacobi_node(const LevelArgs<T>& L, const T* __re
       const T sp = nbsum(pw[v], pe[v], ps[v], pn[v]);
       const T a = (kw[v] + ke[v]) + (ks[v] + kn[v]);
       const T rY = fy[v] - (cj[v] * y0[v] + (a * p0[v] - sp));   // Y row: C_j y_j + A_j^T p_j
-      const T rP = fp[v] - ((a * y0[v] - sy) + ej[v] * u);       // P row: A_j y_j + E_j u
-      dsum += act ? dj[v] * p0[v] : T(0);
+      const T rP = fp[v] - ((a * y0[v] - sy) + (mi * ej[v]) * u);   // P row: A_j y_j + E_j u
+      dsum += act ? (mi * dj[v]) * p0[v] : T(0);
       const T ai = T(1) / a;
       const T t = cj[v] * ai * ai;
-      num += act ? dj[v] * (t * rP - ai * rY) : T(0);
-      rYq[q] = rY; rPq[q] = rP; ia[q] = ai; cq[q] = cj[v]; eq[q] = ej[v]; yo[q] = y0[v]; po[q] = p0[v];
+      num += act ? (mi * dj[v]) * (t * rP - ai * rY) : T(0);
+      rYq[q] = rY; rPq[q] = rP; ia[q] = ai; cq[q] = cj[v]; eq[q] = mi * ej[v]; yo[q] = y0[v]; po[q] = p0[v];
     }
   }
   dsum = group_sum_w(dsum, W);
@@ -100,14 +101,14 @@ __device__ __forceinline__ void jacobi_node(const LevelArgs<T>& L, const T* __re
   if (lane == 0) xout[(size_t)N * nn + node] = u + theta * du;
 }
 
-template <typename T, int W, int JM, int VW>
+template <typename T, int W, int JM, int VW, bool MK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, JM >= 4 ? 3 : 8)))
 void k_jacobi(LevelArgs<T> L, const T* __restrict__ xin, T* __restrict__ xout, const T* __restrict__ f, T theta) {
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = xcd_remap(blockIdx.x, group_blocks<W>(L.n * L.n));
   const int lane = threadIdx.x & (W - 1);
   const int slot = group_slot<W>(b);
   if (slot >= L.n * L.n) return;
-  jacobi_node<T, JM, VW>(L, xin, xout, f, theta, slot, lane, W);
+  jacobi_node<T, JM, VW, MK>(L, xin, xout, f, theta, slot, lane, W);
 }
 
 }  // namespace smg

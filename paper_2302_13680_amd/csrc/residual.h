@@ -10,7 +10,7 @@ namespace smg {
 // Faces and arithmetic in T, x and f in TX, out in TO (out may be null).
 // acc[0..2] accumulate the squared Y, U (lane 0) and P residual entries, acc[3]
 // the squared entries of f (mode 0), which gives ||f|| in the same pass.
-template <typename T, typename TX, typename TO, int JM, int VW = 1>
+template <typename T, typename TX, typename TO, int JM, int VW = 1, bool MK = true>
 __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* __restrict__ x,
                                               const TX* __restrict__ f, TO* __restrict__ out, int mode,
                                               int slot, int lane, int W, double (&acc)[4]) {
@@ -24,6 +24,7 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
   const TX* Y = x;
   const TX* P = x + (size_t)(N + 1) * nn;
   const T u = (T)x[(size_t)N * nn + node];
+  const T mi = ctrl_mask<MK>(L, node);
   const size_t kxb = ((size_t)k * (n + 1) + xx) * N;
   const size_t kyb = node * N;
   const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
@@ -68,8 +69,8 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
       const T a = (kw[q] + ke[q]) + (ks[q] + kn[q]);
       const T yq = (T)y0[q], pq = (T)p0[q];
       T rY = cj[q] * yq + (a * pq - sp);     // C_j y_j + A_j^T p_j
-      T rP = (a * yq - sy) + ej[q] * u;      // A_j y_j + E_j u
-      dsum += act ? dj[q] * pq : T(0);
+      T rP = (a * yq - sy) + (mi * ej[q]) * u;   // A_j y_j + E_j u
+      dsum += act ? (mi * dj[q]) * pq : T(0);
       double ff = 0.0;
       if (mode == 0) {
         const T fy = (T)fyv[q], fp = (T)fpv[q];
@@ -108,7 +109,7 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
 // of W lanes for one node; the neighbours' x + d are formed on the fly with the
 // same FP64 addition their own groups store, so no group reads x_next.  acc as
 // in residual_node.  x_next must not alias x.
-template <int JM>
+template <int JM, bool MK = true>
 __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, const double* __restrict__ x,
                                                   const float* __restrict__ d, double* __restrict__ xn,
                                                   const double* __restrict__ f, float* __restrict__ out,
@@ -120,6 +121,7 @@ __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, co
   const size_t node = (size_t)k * n + xx;
   const size_t oU = (size_t)N * nn, oP = (size_t)(N + 1) * nn;
   const double u = x[oU + node] + (double)d[oU + node];
+  const double mi = ctrl_mask<MK>(L, node);
   const size_t kxb = ((size_t)k * (n + 1) + xx) * N;
   const size_t kyb = node * N;
   const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
@@ -145,8 +147,8 @@ __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, co
     const double a = (kw + ke) + (ks + kn);
     const double fy = f[base], fp = f[oP + base];
     const double rY = fy - (L.c[j] * y0 + (a * p0 - sp));
-    const double rP = fp - ((a * y0 - sy) + L.e[j] * u);
-    dsum += act ? L.d[j] * p0 : 0.0;
+    const double rP = fp - ((a * y0 - sy) + (mi * L.e[j]) * u);
+    dsum += act ? (mi * L.d[j]) * p0 : 0.0;
     if (act) {
       xn[base] = y0;
       xn[oP + base] = p0;
@@ -168,16 +170,16 @@ __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, co
   }
 }
 
-template <int W, int JM>
+template <int W, int JM, bool MK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, JM >= 4 ? 3 : 8)))
 void k_residual_add(LevelArgs<double> L, const double* __restrict__ x, const float* __restrict__ d,
                     double* __restrict__ xn, const double* __restrict__ f, float* __restrict__ out,
                     double* __restrict__ partials) {
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = xcd_remap(blockIdx.x, group_blocks<W>(L.n * L.n));
   const int lane = threadIdx.x & (W - 1);
   const int slot = group_slot<W>(b);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (slot < L.n * L.n) residual_add_node<JM>(L, x, d, xn, f, out, slot, lane, W, acc);
+  if (slot < L.n * L.n) residual_add_node<JM, MK>(L, x, d, xn, f, out, slot, lane, W, acc);
   block_sum<4>(acc);
   if (threadIdx.x == 0) {
 #pragma unroll
@@ -187,15 +189,15 @@ void k_residual_add(LevelArgs<double> L, const double* __restrict__ x, const flo
 
 // out = f - S x (mode 0) or out = S x (mode 1) over every node.  partials (if not
 // null) receives per block { sum r_Y^2, sum r_U^2, sum r_P^2, sum f^2 }.
-template <typename T, typename TX, typename TO, int W, int JM, int VW>
+template <typename T, typename TX, typename TO, int W, int JM, int VW, bool MK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, JM >= 4 ? 3 : 8)))
 void k_residual(LevelArgs<T> L, const TX* __restrict__ x, const TX* __restrict__ f, TO* __restrict__ out,
                 int mode, double* __restrict__ partials) {
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = xcd_remap(blockIdx.x, group_blocks<W>(L.n * L.n));
   const int lane = threadIdx.x & (W - 1);
   const int slot = group_slot<W>(b);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (slot < L.n * L.n) residual_node<T, TX, TO, JM, VW>(L, x, f, out, mode, slot, lane, W, acc);
+  if (slot < L.n * L.n) residual_node<T, TX, TO, JM, VW, MK>(L, x, f, out, mode, slot, lane, W, acc);
   if (partials) {
     block_sum<4>(acc);
     if (threadIdx.x == 0) {

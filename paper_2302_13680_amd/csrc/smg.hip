@@ -36,6 +36,7 @@ struct Level {
   T* e = nullptr;
   T g = 0;
   T* gden = nullptr; // [n][n]: g + sum_j d_j c_j e_j / a_j^2 (node_den)
+  T* mk = nullptr;   // [n][n] control mask (local control; all ones when the control acts everywhere)
   T* x = nullptr;    // level iterate (levels >= 1, and level 0 of the FP32 cycle)
   T* f = nullptr;    // level right-hand side
 };
@@ -88,6 +89,13 @@ bool vec2_ctx(int precision, int N) { return precision == SMG_F32 && (N & 1) == 
 // lane: measured at 511x511, N=256 it runs 271 us that way against 283-291 us
 // with pairs (the residual and restriction gain from pairs at every N).
 constexpr int halfsweep_vw(int vw, int jm) { return vw == 2 && jm == 2 ? 2 : 1; }
+
+// Kernels compiled without the control mask (MK = false) for contexts whose
+// control acts on every node, with it otherwise.
+template <typename F>
+void mask_dispatch(bool masked, F&& fn) {
+  if (masked) fn(std::true_type{}); else fn(std::false_type{});
+}
 
 template <bool kVec2, typename F>
 void lane_dispatch(int precision, int N, F&& fn) {
@@ -184,6 +192,7 @@ struct smg_ctx {
   unsigned* pub_host = nullptr;   // publish word after the values, host and device views
   unsigned* pub_dev = nullptr;
   unsigned pub_seq = 0;
+  bool masked = false;         // a control mask with an entry other than 1 (local control)
   size_t used_bytes = 0;
   // captured V-cycles, one per (x, f, kind); kind = precision * 2 + zero_first
   struct Graph {
@@ -279,6 +288,12 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
     C->V = cv.take<double>(len0 * (mr + 1));
     if (f32) C->Z32 = cv.take<float>(len0 * mr); else C->Z64 = cv.take<double>(len0 * mr);
   }
+  // control masks last: the other buffers keep the places they have without them
+  for (int l = 0; l < nl; ++l) {
+    const size_t nn = (size_t)C->L64[l].n * C->L64[l].n;
+    C->L64[l].mk = cv.take<double>(nn);
+    if (f32) C->L32[l].mk = cv.take<float>(nn);
+  }
   return cv.off + 256;
 }
 
@@ -314,7 +329,7 @@ int strip_for(int n, int requested) {
 template <typename T>
 LevelArgs<T> args(const Level<T>& L, int N, int strip = 0) {
   LevelArgs<T> a;
-  a.n = L.n; a.N = N; a.kx = L.kx; a.ky = L.ky; a.c = L.c; a.d = L.d; a.e = L.e; a.g = L.g; a.gden = L.gden;
+  a.n = L.n; a.N = N; a.kx = L.kx; a.ky = L.ky; a.c = L.c; a.d = L.d; a.e = L.e; a.g = L.g; a.gden = L.gden; a.mk = L.mk;
   a.strip = strip_for(L.n, strip);
   return a;
 }
@@ -344,15 +359,18 @@ int halfsweep(smg_ctx* C, const Level<T>& L, T* x, const T* f, int colour, int s
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     constexpr int VW = halfsweep_vw(decltype(Vc)::value, JM);
     const int per = kBlock / W, nb = (nact + per - 1) / per;
-    if (src == kZero)
-      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kZero, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f, colour,
-                         theta, nact, ec);
-    else if (src == kProlong)
-      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kProlong, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f,
-                         colour, theta, nact, ec);
-    else
-      hipLaunchKernelGGL((k_halfsweep<T, W, JM, kPlain, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f, colour,
-                         theta, nact, ec);
+    mask_dispatch(C->masked, [&](auto Mc) {
+      constexpr bool MK = decltype(Mc)::value;
+      if (src == kZero)
+        hipLaunchKernelGGL((k_halfsweep<T, W, JM, kZero, VW, MK>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f,
+                           colour, theta, nact, ec);
+      else if (src == kProlong)
+        hipLaunchKernelGGL((k_halfsweep<T, W, JM, kProlong, VW, MK>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f,
+                           colour, theta, nact, ec);
+      else
+        hipLaunchKernelGGL((k_halfsweep<T, W, JM, kPlain, VW, MK>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f,
+                           colour, theta, nact, ec);
+    });
   });
   LAUNCH_CHECK();
   return SMG_OK;
@@ -369,7 +387,10 @@ int jacobi(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const T* f) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     constexpr int VW = halfsweep_vw(decltype(Vc)::value, JM);
     const int per = kBlock / W, nb = (nn + per - 1) / per;
-    hipLaunchKernelGGL((k_jacobi<T, W, JM, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, xin, xout, f, theta);
+    mask_dispatch(C->masked, [&](auto Mc) {
+      hipLaunchKernelGGL((k_jacobi<T, W, JM, VW, decltype(Mc)::value>), dim3(nb), dim3(kBlock), 0, C->stream, a, xin,
+                         xout, f, theta);
+    });
   });
   LAUNCH_CHECK();
   return SMG_OK;
@@ -400,9 +421,11 @@ int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, i
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value, VW = decltype(Vc)::value;
     const int per = kBlock / W;
     const int nb = (int)((nn + per - 1) / per);
-    hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM, VW>), dim3(nb), dim3(kBlock), 0, C->stream,
-                       args(L, C->N, C->desc.strip), x, f,
-                       out, mode, want_norm ? C->partials : (double*)nullptr);
+    mask_dispatch(C->masked, [&](auto Mc) {
+      hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM, VW, decltype(Mc)::value>), dim3(nb), dim3(kBlock), 0,
+                         C->stream, args(L, C->N, C->desc.strip), x, f, out, mode,
+                         want_norm ? C->partials : (double*)nullptr);
+    });
     if (want_norm) {
       if (nb > kNormStageMin) {   // two stages: one block alone reads partials at ~50 GB/s
         hipLaunchKernelGGL(k_norms_stage, dim3(kNormStage), dim3(kBlock), 0, C->stream, C->partials, nb,
@@ -426,8 +449,10 @@ int residual_add(smg_ctx* C, const double* x, const float* d, double* xn, const 
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     const int per = kBlock / W;
     const int nb = (int)((nn + per - 1) / per);
-    hipLaunchKernelGGL((k_residual_add<W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N, C->desc.strip),
-                       x, d, xn, f, out, C->partials);
+    mask_dispatch(C->masked, [&](auto Mc) {
+      hipLaunchKernelGGL((k_residual_add<W, JM, decltype(Mc)::value>), dim3(nb), dim3(kBlock), 0, C->stream,
+                         args(L, C->N, C->desc.strip), x, d, xn, f, out, C->partials);
+    });
     if (nb > kNormStageMin) {
       hipLaunchKernelGGL(k_norms_stage, dim3(kNormStage), dim3(kBlock), 0, C->stream, C->partials, nb, C->partials2);
       hipLaunchKernelGGL(k_finalize_norms, dim3(1), dim3(1024), 0, C->stream, C->partials2, kNormStage, C->norms);
@@ -460,8 +485,10 @@ int residual_restrict(smg_ctx* C, const Level<T>& L, const T* x, const T* f, T* 
   rr_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value, VW = decltype(Vc)::value;
     const int per = kBlock / W, nb = (nc * nc + per - 1) / per;
-    hipLaunchKernelGGL((k_residual_restrict<T, W, JM, VW>), dim3(nb), dim3(kBlock), 0, C->stream, a, x, f, coarse,
-                       coarse_strip(a.strip));
+    mask_dispatch(C->masked, [&](auto Mc) {
+      hipLaunchKernelGGL((k_residual_restrict<T, W, JM, VW, decltype(Mc)::value>), dim3(nb), dim3(kBlock), 0,
+                         C->stream, a, x, f, coarse, coarse_strip(a.strip));
+    });
   });
   LAUNCH_CHECK();
   return SMG_OK;
@@ -483,10 +510,10 @@ template <typename TV>
 int coarse_solve(smg_ctx* C, const TV* F, TV* X) {
   const Level<double>& L = C->L64[C->nlev - 1];
   hipLaunchKernelGGL((k_coarse_phase1<TV>), dim3(C->N), dim3(64), 0, C->stream, C->m, C->N, C->Ainv, L.c, L.d,
-                     F, C->ds);
+                     (const double*)L.mk, F, C->ds);
   LAUNCH_CHECK();
   hipLaunchKernelGGL((k_coarse_phase2<TV>), dim3(C->N), dim3(64), 0, C->stream, C->m, C->N, C->Ainv, C->Sinv,
-                     L.c, L.e, F, C->ds, X);
+                     L.c, L.e, (const double*)L.mk, F, C->ds, X);
   LAUNCH_CHECK();
   return SMG_OK;
 }
@@ -1071,7 +1098,7 @@ size_t batch_build(smg_batch* B, double* const* x, const double* const* f, std::
       t.inst = i; t.W = B->lanes[i]; t.L = lvl_args(i, d);
       t.x = lvl_x(i, d); t.f = lvl_f(i, d);
       t.m = C->m; t.Ainv = C->Ainv; t.Sinv = C->Sinv; t.ds = C->ds;
-      t.c64 = C->L64[d].c; t.d64 = C->L64[d].d; t.e64 = C->L64[d].e;
+      t.c64 = C->L64[d].c; t.d64 = C->L64[d].d; t.e64 = C->L64[d].e; t.mk64 = C->L64[d].mk;
       t.nitems = C->N; t.block0 = blocks;
       blocks += C->N;
       cs.push_back(t);
@@ -1274,6 +1301,9 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
       return SMG_ESINGULAR;
     if (B->d[j] * B->c[j] * B->e[j] < 0.0) return SMG_ESINGULAR;
   }
+  if (B->ctrl)
+    for (size_t i = 0; i < (size_t)d.n * d.n; ++i)
+      if (!(B->ctrl[i] >= 0.0 && B->ctrl[i] <= 1.0)) return SMG_EINVAL;
   smg_ctx* C = new smg_ctx();
   C->desc = d;
   C->N = N;
@@ -1345,6 +1375,33 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
         return fail(SMG_EHIP);
     }
   }
+  // control mask (local control): the caller's on the finest level, by injection
+  // below (coarse node (X, K) is fine node (2X+1, 2K+1)), all ones without one;
+  // FP32 copies for the FP32 cycle
+  {
+    std::vector<double> mk((size_t)d.n * d.n, 1.0), mkc;
+    if (B->ctrl) mk.assign(B->ctrl, B->ctrl + (size_t)d.n * d.n);
+    C->masked = false;
+    for (double v : mk) C->masked |= (v != 1.0);
+    std::vector<float> mk32;
+    for (int l = 0; l < C->nlev; ++l) {
+      const int nl = C->L64[l].n;
+      if (l > 0) {
+        const int nf = C->L64[l - 1].n;
+        mkc.assign((size_t)nl * nl, 0.0);
+        for (int K = 0; K < nl; ++K)
+          for (int X = 0; X < nl; ++X) mkc[(size_t)K * nl + X] = mk[(size_t)(2 * K + 1) * nf + 2 * X + 1];
+        mk.swap(mkc);
+      }
+      if (hipMemcpy(C->L64[l].mk, mk.data(), sizeof(double) * mk.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(SMG_EHIP);
+      if (d.precision == SMG_F32) {
+        mk32.assign(mk.begin(), mk.end());
+        if (hipMemcpy(C->L32[l].mk, mk32.data(), sizeof(float) * mk32.size(), hipMemcpyHostToDevice) != hipSuccess)
+          return fail(SMG_EHIP);
+      }
+    }
+  }
   // per-node denominators of the node solve, with the half-sweep's lane layout
   for (int l = 0; l < C->nlev; ++l) {
     if (node_den_level<double>(C, C->L64[l]) != SMG_OK) return fail(SMG_EHIP);
@@ -1354,7 +1411,7 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
   const Level<double>& Lc = C->L64[C->nlev - 1];
   hipLaunchKernelGGL(k_coarse_invert_A, dim3(N), dim3(kBlock), 0, C->stream, Lc.n, N, Lc.kx, Lc.ky, C->Ainv);
   hipLaunchKernelGGL(k_coarse_schur_terms, dim3(N), dim3(kBlock), 0, C->stream, C->m, C->Ainv, Lc.c, Lc.d, Lc.e,
-                     C->terms);
+                     (const double*)Lc.mk, C->terms);
   hipLaunchKernelGGL(k_coarse_schur_invert, dim3(1), dim3(kBlock), 0, C->stream, C->m, N, C->terms, Lc.g, C->Sinv);
   if (hipGetLastError() != hipSuccess) return fail(SMG_EHIP);
   int flag = 0;

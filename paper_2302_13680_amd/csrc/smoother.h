@@ -64,7 +64,7 @@ __device__ __forceinline__ void prolong_nb(const T* __restrict__ e, int nc, int 
 // theta != 1 (relaxation) is supported for SRC == kPlain only; kProlong needs
 // colour 0.  W is a compile-time constant after inlining in the single-instance
 // kernel and a per-instance value in the batched one; the arithmetic is the same.
-template <typename T, int JM, int SRC, int VW = 1>
+template <typename T, int JM, int SRC, int VW = 1, bool MK = true>
 __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restrict__ x,
                                                const T* __restrict__ f, int colour, T theta, int slot,
                                                int lane, int W, const T* __restrict__ ec) {
@@ -96,7 +96,7 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
   const ptrdiff_t ow = hw ? -(ptrdiff_t)N : 0, oe = he ? (ptrdiff_t)N : 0;
   const ptrdiff_t os = hs ? -(ptrdiff_t)rowN : 0, on = hn ? (ptrdiff_t)rowN : 0;
   // per-node values first, so that their loads are in flight with the rest
-  const T fu = fU[node], gd = L.gden[node];
+  const T fu = fU[node], gd = L.gden[node], mi = ctrl_mask<MK>(L, node);
   T bP[JM], bY[JM], ia[JM], cq[JM], eq[JM];
   T num = 0;
 #pragma unroll
@@ -152,8 +152,8 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
       const T ai = T(1) / a;
       const T bp = fy[u] + sp[u], by = fp[u] + sy[u];
       const T t = cj[u] * ai * ai;
-      num += act ? dj[u] * (t * by - ai * bp) : T(0);
-      bP[q] = bp; bY[q] = by; ia[q] = ai; cq[q] = cj[u]; eq[q] = ej[u];
+      num += act ? (mi * dj[u]) * (t * by - ai * bp) : T(0);
+      bP[q] = bp; bY[q] = by; ia[q] = ai; cq[q] = cj[u]; eq[q] = mi * ej[u];
     }
   }
   // e_j is first used after the sum over samples; without this the compiler
@@ -204,6 +204,7 @@ __device__ __forceinline__ void node_den(const LevelArgs<T>& L, T* __restrict__ 
   const int n = L.n, N = L.N;
   const int k = node / n, xx = node - k * n;
   const size_t kxb = ((size_t)k * (n + 1) + xx) * N, kyb = (size_t)node * N, rowN = (size_t)n * N;
+  const T mi = ctrl_mask<true>(L, node);
   T den = 0;
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
@@ -223,7 +224,7 @@ __device__ __forceinline__ void node_den(const LevelArgs<T>& L, T* __restrict__ 
       const T a = (kw[u] + ke[u]) + (ks[u] + kn[u]);
       const T ai = T(1) / a;
       const T t = cj[u] * ai * ai;
-      den += act ? dj[u] * t * ej[u] : T(0);
+      den += act ? (mi * dj[u]) * t * (mi * ej[u]) : T(0);
     }
   }
   den = group_sum_w(den, W);
@@ -247,15 +248,15 @@ template <int JM, int SRC>
 constexpr int halfsweep_waves() { return SRC == kProlong ? (JM <= 2 ? 4 : 8) : (JM >= 4 ? 3 : 8); }
 
 // One half-sweep of collective Gauss-Seidel over every node of `colour`.
-template <typename T, int W, int JM, int SRC, int VW>
+template <typename T, int W, int JM, int SRC, int VW, bool MK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, halfsweep_waves<JM, SRC>())))
 void k_halfsweep(LevelArgs<T> L, T* __restrict__ x, const T* __restrict__ f, int colour, T theta, int nactive,
                  const T* __restrict__ ec) {
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = xcd_remap(blockIdx.x, group_blocks<W>(nactive));
   const int lane = threadIdx.x & (W - 1);
   const int slot = group_slot<W>(b);
   if (slot >= nactive) return;  // whole W-lane groups leave together
-  halfsweep_node<T, JM, SRC, VW>(L, x, f, colour, theta, slot, lane, W, ec);
+  halfsweep_node<T, JM, SRC, VW, MK>(L, x, f, colour, theta, slot, lane, W, ec);
 }
 
 }  // namespace smg

@@ -76,7 +76,7 @@ __device__ __forceinline__ void restrict_node(int nf, int N, const T* __restrict
 // The Y and P rows of coarse node (X, K) by lane `lane` of a group of W lanes
 // (W <= 256: groups wider than a wave span several waves); returns the lane's
 // part of sum_j d_j sum_f w_f p_j(f), which residual_restrict_urow completes.
-template <typename T, int JM, int VW = 1>
+template <typename T, int JM, int VW = 1, bool MK = true>
 __device__ __forceinline__ T residual_restrict_rows(const LevelArgs<T>& L, const T* __restrict__ x,
                                                     const T* __restrict__ f, T* __restrict__ coarse, int X,
                                                     int K, int lane, int W) {
@@ -166,6 +166,7 @@ __device__ __forceinline__ T residual_restrict_rows(const LevelArgs<T>& L, const
         const int wi = i + 1, wk = k + 1;
         const T w = (T)(lin_w(k - 1) * lin_w(i - 1));
         const T u = U[(size_t)(kc - 1 + i) * n + (xc - 1 + k)];
+        const T mf = ctrl_mask<MK>(L, (size_t)(kc - 1 + i) * n + (xc - 1 + k));
 #pragma unroll
         for (int q = 0; q < VW; ++q) {
           const T kw = kxv[i][k][q], ke = kxv[i][k + 1][q], ks = kyv[i][k][q], kn = kyv[i + 1][k][q];
@@ -175,7 +176,7 @@ __device__ __forceinline__ T residual_restrict_rows(const LevelArgs<T>& L, const
           const T a = (kw + ke) + (ks + kn);
           const T yq = yv[wi][wk][q], pq = pv[wi][wk][q];
           const T rY = fyv[i][k][q] - (cj[q] * yq + (a * pq - sp));
-          const T rP = fpv[i][k][q] - ((a * yq - sy) + ej[q] * u);
+          const T rP = fpv[i][k][q] - ((a * yq - sy) + (mf * ej[q]) * u);
           sY[q] += w * rY;
           sP[q] += w * rP;
         }
@@ -187,7 +188,9 @@ __device__ __forceinline__ T residual_restrict_rows(const LevelArgs<T>& L, const
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) wp += (T)(lin_w(k - 1) * lin_w(i - 1)) * pv[i + 1][k + 1][q];
+        for (int k = 0; k < 3; ++k)
+          wp += ((T)(lin_w(k - 1) * lin_w(i - 1)) * ctrl_mask<MK>(L, (size_t)(kc - 1 + i) * n + (xc - 1 + k))) *
+                pv[i + 1][k + 1][q];
       dw += act ? dj[q] * wp : T(0);
     }
     if (act) {
@@ -221,37 +224,37 @@ __device__ __forceinline__ void residual_restrict_urow(const LevelArgs<T>& L, co
 }
 
 // Group of W <= 64 lanes (one wave or part of one) per coarse node.
-template <typename T, int JM, int VW = 1>
+template <typename T, int JM, int VW = 1, bool MK = true>
 __device__ __forceinline__ void residual_restrict_node(const LevelArgs<T>& L, const T* __restrict__ x,
                                                        const T* __restrict__ f, T* __restrict__ coarse,
                                                        int slot, int lane, int W, int cstrip) {
   int X, K;
   strip_node(slot, (L.n - 1) / 2, cstrip, X, K);
-  const T dw = residual_restrict_rows<T, JM, VW>(L, x, f, coarse, X, K, lane, W);
+  const T dw = residual_restrict_rows<T, JM, VW, MK>(L, x, f, coarse, X, K, lane, W);
   const T D = group_sum_w(dw, W);
   if (lane == 0) residual_restrict_urow<T>(L, x, f, coarse, X, K, D);
 }
 
 // coarse = R (f - S x) over every coarse node, W lanes per node (W <= 256; a
 // node of W > 64 lanes spans W / 64 waves whose partial sums meet in LDS).
-template <typename T, int W, int JM, int VW>
+template <typename T, int W, int JM, int VW, bool MK>
 __global__ __launch_bounds__(kBlock) void k_residual_restrict(LevelArgs<T> L, const T* __restrict__ x,
                                                               const T* __restrict__ f, T* __restrict__ coarse,
                                                               int cstrip) {
   static_assert(W >= 1 && W <= kBlock && (W & (W - 1)) == 0, "power-of-two group");
   const int nc = (L.n - 1) / 2;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = xcd_remap(blockIdx.x, group_blocks<W>(nc * nc));
   const int lane = threadIdx.x & (W - 1);
   const int slot = group_slot<W>(b);
   if constexpr (W <= 64) {
     if (slot >= nc * nc) return;
-    residual_restrict_node<T, JM, VW>(L, x, f, coarse, slot, lane, W, cstrip);
+    residual_restrict_node<T, JM, VW, MK>(L, x, f, coarse, slot, lane, W, cstrip);
   } else {
     __shared__ T part[kBlock / 64];
     const bool live = slot < nc * nc;
     int X = 0, K = 0;
     if (live) strip_node(slot, nc, cstrip, X, K);
-    T dw = live ? residual_restrict_rows<T, JM, VW>(L, x, f, coarse, X, K, lane, W) : T(0);
+    T dw = live ? residual_restrict_rows<T, JM, VW, MK>(L, x, f, coarse, X, K, lane, W) : T(0);
     dw = group_sum<64>(dw);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = dw;
     __syncthreads();
@@ -268,7 +271,7 @@ template <typename T, int W, int JM, int VW>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nf, int N, const T* __restrict__ fine,
                                                      T* __restrict__ coarse, int cstrip) {
   const int nc = (nf - 1) / 2;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = xcd_remap(blockIdx.x, group_blocks<W>(nc * nc));
   const int lane = threadIdx.x & (W - 1);
   const int slot = group_slot<W>(b);
   if (slot >= nc * nc) return;
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(int nc, int N, const T* 
                                                         T* __restrict__ fine) {
   const int nf = 2 * nc + 1;
   const size_t nnf = (size_t)nf * nf, nnc = (size_t)nc * nc;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = xcd_remap(blockIdx.x, group_blocks<W>((int)nnf));
   const int lane = threadIdx.x & (W - 1);
   const int slot = group_slot<W>(b);
   if (slot >= (int)nnf) return;
