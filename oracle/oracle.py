@@ -45,6 +45,8 @@ def _load():
     L.or_set_smoother.argtypes = [vp, C.c_int]
     L.or_set_control.restype = C.c_int
     L.or_set_control.argtypes = [vp, _dp]
+    L.or_set_masks.restype = C.c_int
+    L.or_set_masks.argtypes = [vp, C.c_void_p, C.c_void_p]
     L.or_create.restype = vp
     L.or_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                             _dp, _dp, _dp, _dp, _dp, C.c_double]
@@ -149,6 +151,14 @@ class Oracle:
                 raise ValueError("oracle: singular coarsest block with this control mask")
         self.nlev = L.or_nlevels(self.ctx)
         self.levels_n = [L.or_level_n(self.ctx, l) for l in range(self.nlev)]
+
+    def set_masks(self, md, me):
+        """Node factors of D_j (md) and E_j (me), [n][n] arrays of the finest level or
+        None for 1; coarse levels by injection, coarsest factorization rebuilt."""
+        keep = [None if m is None else _f64(np.asarray(m).reshape(self.n, self.n)) for m in (md, me)]
+        ptr = [None if m is None else m.ctypes.data for m in keep]
+        if _load().or_set_masks(self.ctx, ptr[0], ptr[1]) != 0:
+            raise ValueError("oracle: singular coarsest block with these node factors")
 
     def __del__(self):
         if getattr(self, "ctx", None):

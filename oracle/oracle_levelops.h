@@ -16,12 +16,15 @@ typedef struct {
   const REAL *kx, *ky;       /* [N][n][n+1], [N][n+1][n] */
   const REAL *c, *d, *e;     /* [N] diagonal values of C_j, D_j, E_j */
   REAL g;                    /* diagonal value of G */
-  const REAL *mk;            /* [n][n] control mask m_i (NULL: 1 everywhere): the node
-                                entries of D_j and E_j are m_i d_j and m_i e_j */
+  const REAL *md, *me;       /* [n][n] node factors (NULL: 1 everywhere): the node entries
+                                of D_j and E_j are md_i d_j and me_i e_j.  Local control:
+                                md = me = the control mask; the semismooth Newton system
+                                of Section 5: md = the active-set indicator, me = 1 */
 } SFX(or_lvl);
 
-/* control mask of node i */
-static inline REAL SFX(or_mask)(const SFX(or_lvl) *L, size_t i) { return L->mk ? L->mk[i] : (REAL)1; }
+/* node factors of D_j and E_j at node i */
+static inline REAL SFX(or_mask_d)(const SFX(or_lvl) *L, size_t i) { return L->md ? L->md[i] : (REAL)1; }
+static inline REAL SFX(or_mask_e)(const SFX(or_lvl) *L, size_t i) { return L->me ? L->me[i] : (REAL)1; }
 
 #define OR_KX(L, j, k, f) ((L)->kx[((size_t)(j) * (L)->n + (k)) * ((L)->n + 1) + (f)])
 #define OR_KY(L, j, gg, x) ((L)->ky[((size_t)(j) * ((L)->n + 1) + (gg)) * (L)->n + (x)])
@@ -63,11 +66,11 @@ static void SFX(or_apply)(const SFX(or_lvl) *L, const REAL *xv, REAL *out) {
       for (int x = 0; x < n; ++x) {
         size_t i = (size_t)k * n + x;
         oY[i] = L->c[j] * Y[i] + SFX(or_stencil)(L, j, P, x, k);
-        oP[i] = SFX(or_stencil)(L, j, Y, x, k) + (SFX(or_mask)(L, i) * L->e[j]) * U[i];
+        oP[i] = SFX(or_stencil)(L, j, Y, x, k) + (SFX(or_mask_e)(L, i) * L->e[j]) * U[i];
       }
   }
   for (size_t i = 0; i < nn; ++i) {
-    REAL s = L->g * U[i], mi = SFX(or_mask)(L, i);
+    REAL s = L->g * U[i], mi = SFX(or_mask_d)(L, i);
     for (int j = 0; j < N; ++j) s += (mi * L->d[j]) * xv[(size_t)(N + 1) * nn + (size_t)j * nn + i];
     oU[i] = s;
   }
@@ -119,8 +122,8 @@ static void SFX(or_halfsweep)(const SFX(or_lvl) *L, int colour, REAL theta,
       if (((x + k) & 1) != colour) continue;
       size_t i = (size_t)k * n + x;
       for (int j = 0; j < N; ++j) {
-        dm[j] = SFX(or_mask)(L, i) * L->d[j];
-        em[j] = SFX(or_mask)(L, i) * L->e[j];
+        dm[j] = SFX(or_mask_d)(L, i) * L->d[j];
+        em[j] = SFX(or_mask_e)(L, i) * L->e[j];
       }
       for (int j = 0; j < N; ++j) {
         const REAL *Y = xv + (size_t)j * nn;
@@ -163,8 +166,8 @@ static void SFX(or_jacobi)(const SFX(or_lvl) *L, REAL theta, REAL *xv, const REA
     for (int x = 0; x < n; ++x) {
       size_t i = (size_t)k * n + x;
       for (int j = 0; j < N; ++j) {
-        dm[j] = SFX(or_mask)(L, i) * L->d[j];
-        em[j] = SFX(or_mask)(L, i) * L->e[j];
+        dm[j] = SFX(or_mask_d)(L, i) * L->d[j];
+        em[j] = SFX(or_mask_e)(L, i) * L->e[j];
         a[j] = OR_KX(L, j, k, x) + OR_KX(L, j, k, x + 1) + OR_KY(L, j, k, x) + OR_KY(L, j, k + 1, x);
         bP[j] = r[(size_t)j * nn + i];
         bY[j] = r[(size_t)(N + 1) * nn + (size_t)j * nn + i];

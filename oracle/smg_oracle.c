@@ -44,8 +44,8 @@ typedef struct {
   int nlev, N, pre, post;
   double theta;
   int smoother;   /* 0: red-black collective Gauss-Seidel, 1: damped collective Jacobi */
-  double *mk[OR_MAXLEV];   /* control masks per level (NULL: control everywhere) */
-  float *mk32[OR_MAXLEV];
+  double *md[OR_MAXLEV], *me[OR_MAXLEV];   /* node factors of D_j, E_j per level (NULL: 1) */
+  float *md32[OR_MAXLEV], *me32[OR_MAXLEV];
   int n[OR_MAXLEV];
   double *kx[OR_MAXLEV], *ky[OR_MAXLEV];
   double *c[OR_MAXLEV], *d[OR_MAXLEV], *e[OR_MAXLEV];
@@ -144,8 +144,8 @@ static int or_coarse_setup(or_ctx *C) {
   double *col = (double *)malloc(sizeof(double) * (size_t)m);
   or_lvl_f64 *L = &C->L[l];
   for (int i = 0; i < m; ++i) Sch[(size_t)i * m + i] = L->g;
-  /* with a control mask, D_j = d_j diag(mask) and E_j = e_j diag(mask) */
-  const double *mk = L->mk;
+  /* with node factors, D_j = d_j diag(md) and E_j = e_j diag(me) */
+  const double *md = L->md, *me = L->me;
   for (int j = 0; j < N; ++j) {
     /* assemble A_j column by column from the stencil */
     for (int q = 0; q < m; ++q) {
@@ -163,7 +163,7 @@ static int or_coarse_setup(or_ctx *C) {
       for (int i = 0; i < m; ++i) {
         double t = 0;
         for (int r = 0; r < m; ++r) t += Ai[(size_t)i * m + r] * col[r];
-        Sch[(size_t)i * m + q] += mk ? (mk[i] * s * mk[q]) * t : s * t;
+        Sch[(size_t)i * m + q] += ((md ? md[i] : 1.0) * s * (me ? me[q] : 1.0)) * t;
       }
     }
   }
@@ -187,7 +187,7 @@ void or_coarse_solve(const or_ctx *C, const double *F, double *X) {
     matvec(m, Ai, FP, t1);                                        /* A^{-1} F_P */
     for (int i = 0; i < m; ++i) t2[i] = FY[i] - L->c[j] * t1[i];
     matvec(m, Ai, t2, t1);                                        /* A^{-1}(F_Y - C A^{-1} F_P) */
-    for (int i = 0; i < m; ++i) rhs[i] -= (or_mask_f64(L, i) * L->d[j]) * t1[i];
+    for (int i = 0; i < m; ++i) rhs[i] -= (or_mask_d_f64(L, i) * L->d[j]) * t1[i];
   }
   matvec(m, C->Sinv, rhs, uu);
   for (int i = 0; i < m; ++i) X[(size_t)N * m + i] = uu[i];
@@ -195,7 +195,7 @@ void or_coarse_solve(const or_ctx *C, const double *F, double *X) {
     const double *Ai = C->Ainv + (size_t)j * m * m;
     const double *FY = F + (size_t)j * m, *FP = F + (size_t)(N + 1) * m + (size_t)j * m;
     double *Y = X + (size_t)j * m, *P = X + (size_t)(N + 1) * m + (size_t)j * m;
-    for (int i = 0; i < m; ++i) t2[i] = FP[i] - (or_mask_f64(L, i) * L->e[j]) * uu[i];
+    for (int i = 0; i < m; ++i) t2[i] = FP[i] - (or_mask_e_f64(L, i) * L->e[j]) * uu[i];
     matvec(m, Ai, t2, Y);                                         /* y = A^{-1}(F_P - E u) */
     for (int i = 0; i < m; ++i) t2[i] = FY[i] - L->c[j] * Y[i];
     matvec(m, Ai, t2, P);                                         /* p = A^{-1}(F_Y - C y) */
@@ -210,7 +210,7 @@ void or_destroy(or_ctx *C) {
     free(C->xw[l]); free(C->fw[l]); free(C->rw[l]);
     free(C->xw32[l]); free(C->fw32[l]); free(C->rw32[l]);
   }
-  for (int l = 0; l < C->nlev; ++l) { free(C->mk[l]); free(C->mk32[l]); }
+  for (int l = 0; l < C->nlev; ++l) { free(C->md[l]); free(C->md32[l]); free(C->me[l]); free(C->me32[l]); }
   free(C->Ainv); free(C->Sinv); free(C->cw);
   free(C);
 }
@@ -283,39 +283,49 @@ or_ctx *or_create(int n, int N, int coarsest_n, int pre, int post, double theta,
   return C;
 }
 
-/* Control acting only where mask[i] != 0 (local control; eq.
- * solution_reduced_system2 at nodes without control): the node entries of D_j
- * and E_j become mask_i d_j and mask_i e_j on every level, coarse masks by
- * injection (coarse node (X, K) is fine node (2X+1, 2K+1)); the coarsest
- * factorization is rebuilt.  mask: [n][n] of the finest level, or NULL for
- * control everywhere.  Returns 0, or -1 if the coarsest system is singular. */
-int or_set_control(or_ctx *C, const double *mask) {
+/* Per-level copies of a finest-level node factor: coarse node (X, K) takes the
+ * value of fine node (2X+1, 2K+1) (injection).  src NULL: all levels NULL. */
+static void set_factor(or_ctx *C, const double *src, double **lv, float **lv32) {
   for (int l = 0; l < C->nlev; ++l) {
-    free(C->mk[l]); free(C->mk32[l]);
-    C->mk[l] = NULL; C->mk32[l] = NULL;
-    C->L[l].mk = NULL; C->L32[l].mk = NULL;
+    free(lv[l]); free(lv32[l]);
+    lv[l] = NULL; lv32[l] = NULL;
   }
-  if (mask) {
-    for (int l = 0; l < C->nlev; ++l) {
-      int nl = C->n[l];
-      C->mk[l] = (double *)malloc(sizeof(double) * (size_t)nl * nl);
-      if (l == 0) {
-        memcpy(C->mk[0], mask, sizeof(double) * (size_t)nl * nl);
-      } else {
-        int nf = C->n[l - 1];
-        for (int K = 0; K < nl; ++K)
-          for (int X = 0; X < nl; ++X)
-            C->mk[l][(size_t)K * nl + X] = C->mk[l - 1][(size_t)(2 * K + 1) * nf + 2 * X + 1];
-      }
-      C->mk32[l] = to_f32(C->mk[l], (size_t)nl * nl);
-      C->L[l].mk = C->mk[l];
-      C->L32[l].mk = C->mk32[l];
+  if (!src) return;
+  for (int l = 0; l < C->nlev; ++l) {
+    int nl = C->n[l];
+    lv[l] = (double *)malloc(sizeof(double) * (size_t)nl * nl);
+    if (l == 0) {
+      memcpy(lv[0], src, sizeof(double) * (size_t)nl * nl);
+    } else {
+      int nf = C->n[l - 1];
+      for (int K = 0; K < nl; ++K)
+        for (int X = 0; X < nl; ++X)
+          lv[l][(size_t)K * nl + X] = lv[l - 1][(size_t)(2 * K + 1) * nf + 2 * X + 1];
     }
+    lv32[l] = to_f32(lv[l], (size_t)nl * nl);
+  }
+}
+
+/* Node factors of D_j and E_j: the node entries become md_i d_j and me_i e_j on
+ * every level, coarse factors by injection; the coarsest factorization is
+ * rebuilt.  md, me: [n][n] of the finest level, or NULL for 1 everywhere.
+ * Returns 0, or -1 if the coarsest system is singular. */
+int or_set_masks(or_ctx *C, const double *md, const double *me) {
+  set_factor(C, md, C->md, C->md32);
+  set_factor(C, me, C->me, C->me32);
+  for (int l = 0; l < C->nlev; ++l) {
+    C->L[l].md = C->md[l]; C->L32[l].md = C->md32[l];
+    C->L[l].me = C->me[l]; C->L32[l].me = C->me32[l];
   }
   free(C->Ainv); free(C->Sinv); free(C->cw);
   C->Ainv = C->Sinv = C->cw = NULL;
   return or_coarse_setup(C);
 }
+
+/* Control acting only where mask[i] != 0 (local control; eq.
+ * solution_reduced_system2 at nodes without control): the node entries of D_j
+ * and E_j become mask_i d_j and mask_i e_j.  mask NULL: control everywhere. */
+int or_set_control(or_ctx *C, const double *mask) { return or_set_masks(C, mask, mask); }
 
 int or_nlevels(const or_ctx *C) { return C->nlev; }
 int or_level_n(const or_ctx *C, int l) { return C->n[l]; }
