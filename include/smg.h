@@ -107,6 +107,8 @@ typedef struct {
                                  which use theta = 0.5) instead of red-black collective
                                  Gauss-Seidel sweeps; theta is the damping and pre / post count
                                  Jacobi steps.  Not accepted by the batched solver. */
+#define SMG_FLAG_SSN 8        /* reserve the semismooth Newton solver's buffers in the workspace
+                                 (two vectors and six node-sized arrays; SMG_F64 only) */
 
 typedef struct {
   const double *kx;   /* device, [n][n+1][N] */
@@ -134,6 +136,33 @@ typedef struct {
   int history_cap;      /* its length (0 = none) */
   int history_len;      /* entries written */
 } smg_stats;
+
+/* Parameters of the semismooth Newton solver (Section 5, eq. l1_OCP and Algorithm 2). */
+typedef struct {
+  double nu;          /* nu > 0, the control cost */
+  double beta;        /* beta >= 0, the L^1 weight */
+  double a, b;        /* box a < 0 < b on the control (-INFINITY / INFINITY: no bound) */
+  double mass;        /* M = mass I, the lumped mass matrix (h^2 for these grids) */
+  double tol;         /* stop once phi(u) = sqrt(F^T M F) <= tol (the paper: 1e-9) */
+  double inner_rtol;  /* relative residual of every linear solve (the paper: 1e-11) */
+  int inner_method;   /* SMG_VCYCLE or SMG_GMRES (V-cycle-preconditioned) */
+  int maxit;          /* Newton iterations at most */
+  int inner_maxit;    /* iterations of each linear solve at most */
+  double sigma, rho;  /* line search: sufficient decrease sigma, step factor rho (0: 1e-4, 1/2) */
+} smg_ssn_params;
+
+typedef struct {
+  int iterations;       /* Newton iterations */
+  int inner_total;      /* linear-solver iterations over all Newton systems */
+  int init_iterations;  /* iterations of the initial state and adjoint solve */
+  double phi_final;     /* final merit phi(u) */
+  double time_ms;       /* wall time of the call, host clock */
+  double *phi;          /* optional caller buffers of cap entries: merit per iterate (u^0, u^1, ...), */
+  double *gamma;        /*   step length and linear-solver iterations per Newton iteration */
+  int *inner;
+  int cap;
+  int len;              /* iterates recorded (iterations + 1) */
+} smg_ssn_stats;
 
 /* Bytes of device workspace smg_setup needs for this descriptor.  Pure host
  * computation; returns 0 for an invalid descriptor. */
@@ -231,6 +260,58 @@ int smg_gmres_precond(smg_ctx *ctx, double *x, const double *f, int restart, dou
  * current residual). */
 int smg_solve(smg_ctx *ctx, double *x, const double *f, int method, double rtol, int maxit,
               smg_stats *stats);
+
+/* Node factors of D_j and E_j: the node entries become md_i d_j and me_i e_j
+ * on every level (coarse node (X, K) takes the factors of fine node
+ * (2X+1, 2K+1), level by level), and the per-node denominators and the
+ * coarsest Schur complement are rebuilt.  Local control is md = me = the
+ * control mask; the Newton system of Section 5
+ * (eq. full_space_optimality_systeMemismooth2) is md = the active-set
+ * indicator, me = 1.  md, me: device, [n][n] (row k, column x) of the finest
+ * level, values in [0, 1]; NULL: 1 everywhere.  Replaces the control mask
+ * given to smg_setup.  Synchronizes the context's stream.  A value outside
+ * [0, 1] or not finite: SMG_EINVAL, nothing changed. */
+int smg_set_node_factors(smg_ctx *ctx, const double *md, const double *me);
+
+/* ------------------------------------------------------- semismooth Newton
+ * The control problem with an L^1 penalty and box constraints (Section 5,
+ * eq. l1_OCP), solved by the globalized semismooth Newton method of
+ * Algorithm 2 with the collective multigrid for every Newton system.
+ *
+ * The context must have SMG_FLAG_SSN and SMG_F64, and hold the Newton
+ * system's blocks (eq. full_space_optimality_systeMemismooth2 with the
+ * adjoint rescaled by the sample weights, p~_j = zeta_j p_j): C_j = zeta_j M,
+ * E_j = -M and faces as in the linear-quadratic problem, and the U row as
+ * printed, G = M and D_j = -M / nu.  E[p] = sum_j zeta_j p_j is then the sum
+ * of the P block's samples at a node.  Vectors in the node layout. */
+
+/* Per node of x (device, finest level): w = E[p] (device [n][n]); when F and
+ * chi are given (both or neither) also F(u) of the discrete optimality
+ * condition, the indicator chi of the active sets I+ u I- (eq. activesets,
+ * 1.0 or 0.0) and, if phi is given, the merit phi = sqrt(F^T M F) (host). */
+int smg_ssn_eval(smg_ctx *ctx, const double *x, const smg_ssn_params *prm, double *w, double *F,
+                 double *chi, double *phi);
+
+/* Line-search merits: phis[q] = phi(u + gammas[q] du) with the trial E[p]
+ * taken as w + gammas[q] dw (exact: y and p are affine in u), q < ng <= 8.
+ * u, du, w, dw: device [n][n]; gammas, phis: host. */
+int smg_ssn_merit(smg_ctx *ctx, const double *u, const double *du, const double *w, const double *dw,
+                  const smg_ssn_params *prm, int ng, const double *gammas, double *phis);
+
+/* Algorithm 2.  x (device, node layout): on entry its U block is u^0 and its
+ * Y and P blocks are the initial guess of the first solve (zero is fine); on
+ * exit (y, u, p~) of the last iterate.  f: the linear-quadratic right-hand
+ * side (f_Y,j = zeta_j M y_d, f_P,j = M f; its U block is not used).  Steps:
+ * the state and adjoint equations for u^0 (the system with D_j = 0 and U
+ * block M u^0); then until phi(u^k) <= tol: node factors md = chi(u^k),
+ * me = 1, the Newton system with right-hand side (0, -M F(u^k), 0) solved from
+ * zero to inner_rtol, the first step length of 1, rho, rho^2, ... (at most 64)
+ * with phi(u + gamma du) - phi(u) <= -sigma phi(u), x += gamma dx.  The
+ * context keeps the last node factors.  Returns SMG_OK, SMG_NOT_CONVERGED
+ * (maxit reached, no step of sufficient decrease, or the initial solve did not
+ * converge) or an error. */
+int smg_ssn_solve(smg_ctx *ctx, double *x, const double *f, const smg_ssn_params *prm,
+                  smg_ssn_stats *stats);
 
 /* ------------------------------------------------------------------ batches
  * Many independent problem instances (different n, N and blocks) solved

@@ -22,6 +22,7 @@ SMG_VCYCLE, SMG_GMRES = 0, 1
 SMG_FLAG_EAGER = 1
 SMG_FLAG_UNFUSED = 2
 SMG_FLAG_JACOBI = 4
+SMG_FLAG_SSN = 8
 
 EXPORTED = [
     "smg_workspace_bytes", "smg_setup", "smg_destroy", "smg_strerror", "smg_last_error",
@@ -31,7 +32,7 @@ EXPORTED = [
     "smg_batch_last_error", "smg_tune_lanes", "smg_net_param_count", "smg_net_workspace_bytes",
     "smg_net_setup", "smg_net_destroy", "smg_net_last_error", "smg_net_set_params", "smg_net_get_params",
     "smg_net_forward", "smg_net_grad", "smg_net_train_step", "smg_net_features", "smg_net_targets",
-    "smg_net_lift",
+    "smg_net_lift", "smg_set_node_factors", "smg_ssn_eval", "smg_ssn_merit", "smg_ssn_solve",
 ]
 
 
@@ -53,6 +54,27 @@ class Stats(C.Structure):
                 ("relres_p", C.c_double), ("time_ms", C.c_double),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int),
                 ("history_len", C.c_int)]
+
+
+class SsnParams(C.Structure):
+    _fields_ = [("nu", C.c_double), ("beta", C.c_double), ("a", C.c_double), ("b", C.c_double),
+                ("mass", C.c_double), ("tol", C.c_double), ("inner_rtol", C.c_double),
+                ("inner_method", C.c_int), ("maxit", C.c_int), ("inner_maxit", C.c_int),
+                ("sigma", C.c_double), ("rho", C.c_double)]
+
+
+class SsnStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("inner_total", C.c_int), ("init_iterations", C.c_int),
+                ("phi_final", C.c_double), ("time_ms", C.c_double), ("phi", C.POINTER(C.c_double)),
+                ("gamma", C.POINTER(C.c_double)), ("inner", C.POINTER(C.c_int)), ("cap", C.c_int),
+                ("len", C.c_int)]
+
+
+def ssn_params(nu, beta, a, b, mass, *, tol=1e-9, inner_rtol=1e-11, inner_method=SMG_GMRES, maxit=100,
+               inner_maxit=500, sigma=1e-4, rho=0.5):
+    """smg_ssn_params (Section 5, Algorithm 2); a, b may be -inf / inf."""
+    return SsnParams(float(nu), float(beta), float(a), float(b), float(mass), float(tol), float(inner_rtol),
+                     int(inner_method), int(maxit), int(inner_maxit), float(sigma), float(rho))
 
 
 class SmgError(RuntimeError):
@@ -131,6 +153,13 @@ def load(path: str = LIB_PATH):
     L.smg_net_lift.argtypes = [vp, vp, i, fp, vp]
     for name in ["smg_net_set_params", "smg_net_get_params", "smg_net_forward", "smg_net_grad",
                  "smg_net_train_step", "smg_net_features", "smg_net_targets", "smg_net_lift"]:
+        getattr(L, name).restype = i
+    L.smg_set_node_factors.argtypes = [vp, vp, vp]
+    L.smg_ssn_eval.argtypes = [vp, vp, C.POINTER(SsnParams), vp, vp, vp, C.POINTER(C.c_double)]
+    L.smg_ssn_merit.argtypes = [vp, vp, vp, vp, vp, C.POINTER(SsnParams), i, C.POINTER(C.c_double),
+                                C.POINTER(C.c_double)]
+    L.smg_ssn_solve.argtypes = [vp, vp, vp, C.POINTER(SsnParams), C.POINTER(SsnStats)]
+    for name in ["smg_set_node_factors", "smg_ssn_eval", "smg_ssn_merit", "smg_ssn_solve"]:
         getattr(L, name).restype = i
     for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_stream_copy", "smg_restrict", "smg_residual_restrict", "smg_jacobi", "smg_prolong_add",
                  "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond", "smg_solve",
@@ -273,6 +302,40 @@ class Context:
         rc = self._check(self.L.smg_solve(self.ctx, _ptr(x), _ptr(f), method, rtol, maxit, C.byref(st)),
                          allow_nc=True)
         return rc, _stats_dict(st)
+
+    # --- node factors and the semismooth Newton solver ----------------------
+    def set_node_factors(self, md=None, me=None):
+        """md, me: float64 device tensors [n][n] (or None for 1)."""
+        return self._check(self.L.smg_set_node_factors(
+            self.ctx, None if md is None else _ptr(md), None if me is None else _ptr(me)))
+
+    def ssn_eval(self, x, prm, w, F=None, chi=None):
+        """w = E[p] per node; with F, chi also F(u), the active set and the merit (returned)."""
+        phi = C.c_double(0.0)
+        self._check(self.L.smg_ssn_eval(self.ctx, _ptr(x), C.byref(prm), _ptr(w),
+                                        None if F is None else _ptr(F), None if chi is None else _ptr(chi),
+                                        C.byref(phi)))
+        return phi.value
+
+    def ssn_merit(self, u, du, w, dw, prm, gammas):
+        ng = len(gammas)
+        g = (C.c_double * ng)(*[float(v) for v in gammas])
+        out = (C.c_double * ng)()
+        self._check(self.L.smg_ssn_merit(self.ctx, _ptr(u), _ptr(du), _ptr(w), _ptr(dw), C.byref(prm), ng, g, out))
+        return list(out)
+
+    def ssn_solve(self, x, f, prm, cap=256):
+        """Algorithm 2 in place on x (its U block: u^0).  Returns (rc, stats dict)."""
+        phi = (C.c_double * cap)()
+        gam = (C.c_double * cap)()
+        inner = (C.c_int * cap)()
+        st = SsnStats(0, 0, 0, 0.0, 0.0, phi, gam, inner, cap, 0)
+        rc = self._check(self.L.smg_ssn_solve(self.ctx, _ptr(x), _ptr(f), C.byref(prm), C.byref(st)),
+                         allow_nc=True)
+        k = min(st.len, cap)
+        return rc, dict(iterations=st.iterations, inner_total=st.inner_total,
+                        init_iterations=st.init_iterations, phi_final=st.phi_final, time_ms=st.time_ms,
+                        phi=list(phi[:k]), gammas=list(gam[:max(k - 1, 0)]), inner=list(inner[:max(k - 1, 0)]))
 
 
 class Batch:
@@ -427,13 +490,21 @@ def _stats_dict(st):
                 time_ms=st.time_ms, history=hist)
 
 
-def context_from_problem(prob, device="cuda", **kw):
-    """Upload a problem's faces (node layout) and build a Context; returns (ctx, f)."""
+def context_from_problem(prob, device="cuda", ssn=False, **kw):
+    """Upload a problem's faces (node layout) and build a Context; returns (ctx, f).
+
+    ssn=True builds the semismooth Newton solver's context instead: the Newton
+    system's U row as printed (G = M, D_j / nu: the linear-quadratic row divided
+    by nu) and SMG_FLAG_SSN."""
     import torch
     kxn, kyn = prob.faces_node()
     kx = torch.from_numpy(kxn).to(device)
     ky = torch.from_numpy(kyn).to(device)
     kw.setdefault("ctrl", getattr(prob, "ctrl", None))
-    ctx = Context(prob.n, prob.N, kx, ky, prob.c, prob.d, prob.e, prob.g, **kw)
+    g, d = prob.g, prob.d
+    if ssn:
+        g, d = prob.g / prob.nu, np.asarray(prob.d) / prob.nu
+        kw["flags"] = kw.get("flags", 0) | SMG_FLAG_SSN
+    ctx = Context(prob.n, prob.N, kx, ky, prob.c, d, prob.e, g, **kw)
     f = torch.from_numpy(prob.rhs_node()).to(device)
     return ctx, f

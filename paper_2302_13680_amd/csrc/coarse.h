@@ -27,6 +27,31 @@ __global__ void k_coarsen_faces(int nf, int N, const T* __restrict__ kxf, const 
   }
 }
 
+// Node factor pairs (md, me) of a level with nl x nl nodes from the finest
+// level's arrays md, me ([n0][n0], null: 1): coarse node (X, K) of level l takes
+// fine node (s (X+1) - 1, s (K+1) - 1), s = 2^l (injection, the same as taking
+// node (2X+1, 2K+1) of the level above, level by level).
+template <typename T>
+__global__ void k_node_factors(int nl, int n0, int s, const double* __restrict__ md, const double* __restrict__ me,
+                               T* __restrict__ out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nl * nl) return;
+  const int K = i / nl, X = i - K * nl;
+  const size_t fi = (size_t)(s * (K + 1) - 1) * n0 + (size_t)(s * (X + 1) - 1);
+  out[2 * (size_t)i] = md ? (T)md[fi] : T(1);
+  out[2 * (size_t)i + 1] = me ? (T)me[fi] : T(1);
+}
+
+// flags[0] = 1 if any value is not finite or lies outside [0, 1].
+__global__ void k_check_unit(size_t len, const double* __restrict__ a, int* __restrict__ flag) {
+  int bad = 0;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < len; i += (size_t)gridDim.x * kBlock) {
+    const double v = a[i];
+    if (!(v >= 0.0 && v <= 1.0)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 // flags[0] = 1 if any face is not finite or <= 0 (A_j would lose its positive diagonal).
 __global__ void k_check_faces(size_t len, const double* __restrict__ a, const double* __restrict__ b,
                               int* __restrict__ flag) {
@@ -38,8 +63,10 @@ __global__ void k_check_faces(size_t len, const double* __restrict__ a, const do
   if (bad) atomicOr(flag, 1);
 }
 
-// In-place Gauss-Jordan inversion of an m x m matrix held in LDS (no pivoting:
-// used on symmetric positive definite matrices only).  All threads call it.
+// In-place Gauss-Jordan inversion of an m x m matrix held in LDS, without pivoting:
+// used on the SPD A_j and on Schur complements g I + diag(md) K diag(me) (K SPD,
+// g > 0, factors >= 0), whose leading minors are all positive (their eigenvalues
+// are those of g I + a symmetric positive semidefinite matrix).  All threads call it.
 __device__ void lds_invert_spd(double* A, double* col, int m) {
   for (int p = 0; p < m; ++p) {
     __syncthreads();
@@ -86,8 +113,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_invert_A(int n, int N, const 
   }
 }
 
-// terms[j] = (d_j c_j e_j diag(mk) Ainv_j Ainv_j diag(mk))^T from the transposed
-// inverses (one block per sample; mk: control mask)
+// terms[j] = (d_j c_j e_j diag(md) Ainv_j Ainv_j diag(me))^T from the transposed
+// inverses (one block per sample; mk: node factor pairs (md, me))
 __global__ __launch_bounds__(kBlock) void k_coarse_schur_terms(int m, const double* __restrict__ Ainv,
                                                                const double* __restrict__ c,
                                                                const double* __restrict__ d,
@@ -103,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_schur_terms(int m, const doub
     const int i = idx / m, q = idx - i * m;
     double t = 0.0;
     for (int r = 0; r < m; ++r) t += A[i * m + r] * A[r * m + q];
-    terms[(size_t)j * m * m + idx] = (mk[i] * s * mk[q]) * t;
+    terms[(size_t)j * m * m + idx] = (mk[2 * q] * s * mk[2 * i + 1]) * t;   // row q, column i
   }
 }
 
@@ -126,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_schur_invert(int m, int N, co
 // Block elimination of eq. (2) on the coarsest grid, one block per sample j:
 //   phase 1: ds_j = D_j A_j^{-1} (F_Y,j - c_j A_j^{-1} F_P,j)
 //   phase 2: u = Sinv (F_U - sum_j ds_j);  y_j = A_j^{-1}(F_P,j - E_j u);
-// with D_j = d_j diag(mk), E_j = e_j diag(mk) (mk: control mask);
+// with D_j = d_j diag(md), E_j = e_j diag(me) (mk: node factor pairs (md, me));
 //            p_j = A_j^{-1}(F_Y,j - c_j y_j)
 // Vectors in the level layout (type TV), arithmetic in FP64.
 // (M v)_i with M stored transposed (MT[c][i] = M[i][c]): coalesced across threads i.
@@ -162,7 +189,7 @@ __device__ __forceinline__ void coarse_phase1_sample(int j, int m, int N, const 
   if (i < m) {
     load_row(Aj, m, i, a);
     sF[i] = (double)FP[(size_t)i * N + j];
-    dm = mk[i] * d[j];
+    dm = mk[2 * i] * d[j];
   }
   __syncthreads();
   if (i < m) sT[i] = (double)FY[(size_t)i * N + j] - c[j] * dot_row(a, m, sF);
@@ -188,7 +215,7 @@ __device__ __forceinline__ void coarse_phase2_sample(int j, int m, int N, const 
   if (i < m) {
     load_row(Aj, m, i, a);
     load_row(Sinv, m, i, si);
-    em = mk[i] * e[j];
+    em = mk[2 * i + 1] * e[j];
     // F_U - sum_j ds_j, in sample order; 16 loads in flight per round trip
     double s = (double)FU[i];
     for (int q0 = 0; q0 < N; q0 += 16) {

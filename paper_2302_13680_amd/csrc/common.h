@@ -34,16 +34,28 @@ struct LevelArgs {
   const T* __restrict__ e;
   T g;
   const T* __restrict__ gden;   // [n][n] per node: g + sum_j d_j c_j e_j / a_j^2 (set up once)
-  const T* __restrict__ mk;     // [n][n] control mask m_i (all ones when the control acts
-                                // everywhere): D_j, E_j node entries m_i d_j, m_i e_j
+  const T* __restrict__ mk;     // [n][n][2] node factors (md_i, me_i): the node entries of D_j
+                                // and E_j are md_i d_j and me_i e_j (local control: both the
+                                // control mask; the semismooth Newton system: md = active set)
   int strip;   // columns per strip of the colour traversal (colour_node)
 };
 
-// control mask of node i; kernels compiled with MK = false (contexts whose control
-// acts everywhere) use 1 without a load
+template <typename T>
+struct NodeFactors {
+  T d, e;   // factors of the node entries of D_j and E_j
+};
+
+// node factors of node i, one 2-element load; kernels compiled with MK = false
+// (contexts whose factors are all 1) use 1 without a load
 template <bool MK, typename T>
-__device__ __forceinline__ T ctrl_mask(const LevelArgs<T>& L, size_t i) {
-  if constexpr (MK) return L.mk[i]; else return T(1);
+__device__ __forceinline__ NodeFactors<T> node_factors(const LevelArgs<T>& L, size_t i) {
+  if constexpr (MK) {
+    using V = typename std::conditional<std::is_same<T, double>::value, double2, float2>::type;
+    const V v = *reinterpret_cast<const V*>(L.mk + 2 * i);
+    return {v.x, v.y};
+  } else {
+    return {T(1), T(1)};
+  }
 }
 
 // MI355X dispatches workgroup b to XCD b % 8.  Remap so that every XCD works on

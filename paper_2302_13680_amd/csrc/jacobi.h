@@ -34,7 +34,7 @@ __device__ __forceinline__ void jacobi_node(const LevelArgs<T>& L, const T* __re
   const ptrdiff_t ow = hw ? -(ptrdiff_t)N : 0, oe = he ? (ptrdiff_t)N : 0;
   const ptrdiff_t os = hs ? -(ptrdiff_t)rowN : 0, on = hn ? (ptrdiff_t)rowN : 0;
   const T u = xin[(size_t)N * nn + node], fu = f[(size_t)N * nn + node], gd = L.gden[node];
-  const T mi = ctrl_mask<MK>(L, node);
+  const NodeFactors<T> mf = node_factors<MK>(L, node);
   T rYq[JM], rPq[JM], ia[JM], cq[JM], eq[JM], yo[JM], po[JM];
   T dsum = 0, num = 0;
 #pragma unroll
@@ -68,12 +68,12 @@ __device__ __forceinline__ void jacobi_node(const LevelArgs<T>& L, const T* __re
       const T sp = nbsum(pw[v], pe[v], ps[v], pn[v]);
       const T a = (kw[v] + ke[v]) + (ks[v] + kn[v]);
       const T rY = fy[v] - (cj[v] * y0[v] + (a * p0[v] - sp));   // Y row: C_j y_j + A_j^T p_j
-      const T rP = fp[v] - ((a * y0[v] - sy) + (mi * ej[v]) * u);   // P row: A_j y_j + E_j u
-      dsum += act ? (mi * dj[v]) * p0[v] : T(0);
+      const T rP = fp[v] - ((a * y0[v] - sy) + (mf.e * ej[v]) * u);   // P row: A_j y_j + E_j u
+      dsum += act ? (mf.d * dj[v]) * p0[v] : T(0);
       const T ai = T(1) / a;
       const T t = cj[v] * ai * ai;
-      num += act ? (mi * dj[v]) * (t * rP - ai * rY) : T(0);
-      rYq[q] = rY; rPq[q] = rP; ia[q] = ai; cq[q] = cj[v]; eq[q] = mi * ej[v]; yo[q] = y0[v]; po[q] = p0[v];
+      num += act ? (mf.d * dj[v]) * (t * rP - ai * rY) : T(0);
+      rYq[q] = rY; rPq[q] = rP; ia[q] = ai; cq[q] = cj[v]; eq[q] = mf.e * ej[v]; yo[q] = y0[v]; po[q] = p0[v];
     }
   }
   dsum = group_sum_w(dsum, W);

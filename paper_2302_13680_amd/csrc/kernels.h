@@ -7,5 +7,6 @@
 #include "transfer.h"
 #include "coarse.h"
 #include "krylov.h"
+#include "ssn.h"
 #include "batch.h"
 #include "netio.h"

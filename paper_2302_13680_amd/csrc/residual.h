@@ -24,7 +24,7 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
   const TX* Y = x;
   const TX* P = x + (size_t)(N + 1) * nn;
   const T u = (T)x[(size_t)N * nn + node];
-  const T mi = ctrl_mask<MK>(L, node);
+  const NodeFactors<T> mf = node_factors<MK>(L, node);
   const size_t kxb = ((size_t)k * (n + 1) + xx) * N;
   const size_t kyb = node * N;
   const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
@@ -69,8 +69,8 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
       const T a = (kw[q] + ke[q]) + (ks[q] + kn[q]);
       const T yq = (T)y0[q], pq = (T)p0[q];
       T rY = cj[q] * yq + (a * pq - sp);     // C_j y_j + A_j^T p_j
-      T rP = (a * yq - sy) + (mi * ej[q]) * u;   // A_j y_j + E_j u
-      dsum += act ? (mi * dj[q]) * pq : T(0);
+      T rP = (a * yq - sy) + (mf.e * ej[q]) * u;   // A_j y_j + E_j u
+      dsum += act ? (mf.d * dj[q]) * pq : T(0);
       double ff = 0.0;
       if (mode == 0) {
         const T fy = (T)fyv[q], fp = (T)fpv[q];
@@ -121,7 +121,7 @@ __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, co
   const size_t node = (size_t)k * n + xx;
   const size_t oU = (size_t)N * nn, oP = (size_t)(N + 1) * nn;
   const double u = x[oU + node] + (double)d[oU + node];
-  const double mi = ctrl_mask<MK>(L, node);
+  const NodeFactors<double> mf = node_factors<MK>(L, node);
   const size_t kxb = ((size_t)k * (n + 1) + xx) * N;
   const size_t kyb = node * N;
   const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
@@ -147,8 +147,8 @@ __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, co
     const double a = (kw + ke) + (ks + kn);
     const double fy = f[base], fp = f[oP + base];
     const double rY = fy - (L.c[j] * y0 + (a * p0 - sp));
-    const double rP = fp - ((a * y0 - sy) + (mi * L.e[j]) * u);
-    dsum += act ? (mi * L.d[j]) * p0 : 0.0;
+    const double rP = fp - ((a * y0 - sy) + (mf.e * L.e[j]) * u);
+    dsum += act ? (mf.d * L.d[j]) * p0 : 0.0;
     if (act) {
       xn[base] = y0;
       xn[oP + base] = p0;

@@ -192,7 +192,11 @@ struct smg_ctx {
   unsigned* pub_host = nullptr;   // publish word after the values, host and device views
   unsigned* pub_dev = nullptr;
   unsigned pub_seq = 0;
-  bool masked = false;         // a control mask with an entry other than 1 (local control)
+  bool masked = false;         // node factors other than 1 somewhere (local control, Newton systems)
+  // semismooth Newton buffers (SMG_FLAG_SSN): increment, right-hand side, node vectors
+  // E[p], E[dp], F, chi, per-block partials and their sums
+  double *sdx = nullptr, *sr = nullptr, *sw = nullptr, *sdw = nullptr, *sF = nullptr, *schi = nullptr;
+  double *spart = nullptr, *sout = nullptr;
   size_t used_bytes = 0;
   // captured V-cycles, one per (x, f, kind); kind = precision * 2 + zero_first
   struct Graph {
@@ -229,7 +233,8 @@ bool desc_valid(const smg_desc& d, std::string* why) {
   if (!(d.theta > 0.0 && d.theta < 2.0)) return fail("theta must lie in (0, 2)");
   if (d.precision != SMG_F64 && d.precision != SMG_F32) return fail("precision must be SMG_F64 or SMG_F32");
   if (d.gmres_restart < 0 || d.gmres_restart > kMaxBasis - 1) return fail("gmres_restart must be in [0, 31]");
-  if (d.flags & ~(SMG_FLAG_EAGER | SMG_FLAG_UNFUSED | SMG_FLAG_JACOBI)) return fail("unknown flag bits");
+  if (d.flags & ~(SMG_FLAG_EAGER | SMG_FLAG_UNFUSED | SMG_FLAG_JACOBI | SMG_FLAG_SSN)) return fail("unknown flag bits");
+  if ((d.flags & SMG_FLAG_SSN) && d.precision != SMG_F64) return fail("SMG_FLAG_SSN needs SMG_F64");
   if (d.strip < 0 || (d.strip & 1)) return fail("strip must be 0 or a positive even number");
   return true;
 }
@@ -288,11 +293,22 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
     C->V = cv.take<double>(len0 * (mr + 1));
     if (f32) C->Z32 = cv.take<float>(len0 * mr); else C->Z64 = cv.take<double>(len0 * mr);
   }
-  // control masks last: the other buffers keep the places they have without them
+  if (d.flags & SMG_FLAG_SSN) {
+    const size_t nn = (size_t)d.n * d.n;
+    C->sdx = cv.take<double>(len0);
+    C->sr = cv.take<double>(len0);
+    C->sw = cv.take<double>(nn);
+    C->sdw = cv.take<double>(nn);
+    C->sF = cv.take<double>(nn);
+    C->schi = cv.take<double>(nn);
+    C->spart = cv.take<double>(std::max(nn / 4 + 1, (size_t)kSsnMeritBlocks * kSsnGammas));
+    C->sout = cv.take<double>(kSsnGammas);
+  }
+  // node factor pairs last: the other buffers keep the places they have without them
   for (int l = 0; l < nl; ++l) {
     const size_t nn = (size_t)C->L64[l].n * C->L64[l].n;
-    C->L64[l].mk = cv.take<double>(nn);
-    if (f32) C->L32[l].mk = cv.take<float>(nn);
+    C->L64[l].mk = cv.take<double>(2 * nn);
+    if (f32) C->L32[l].mk = cv.take<float>(2 * nn);
   }
   return cv.off + 256;
 }
@@ -309,6 +325,11 @@ int hip_fail(smg_ctx* C, hipError_t e, const char* where) {
   } while (0)
 
 #define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+#define TRY(expr)                  \
+  do {                             \
+    int rc_ = (expr);              \
+    if (rc_ != SMG_OK) return rc_; \
+  } while (0)
 
 int grid_for(size_t len) {
   size_t b = (len + kBlock - 1) / kBlock;
@@ -410,6 +431,42 @@ int node_den_level(smg_ctx* C, const Level<T>& L) {
   });
   LAUNCH_CHECK();
   return SMG_OK;
+}
+
+// Node factor pairs of every level from the finest level's md, me (device
+// [n][n], null: 1), then what depends on them: the per-node denominators and
+// the coarsest Schur complement (A_j^{-1} must be in place).
+int factors_setup(smg_ctx* C, const double* md, const double* me) {
+  const bool f32 = C->desc.precision == SMG_F32;
+  for (int l = 0; l < C->nlev; ++l) {
+    const int nl = C->L64[l].n, nb = (nl * nl + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_node_factors<double>, dim3(nb), dim3(kBlock), 0, C->stream, nl, C->desc.n, 1 << l, md, me,
+                       C->L64[l].mk);
+    if (f32)
+      hipLaunchKernelGGL(k_node_factors<float>, dim3(nb), dim3(kBlock), 0, C->stream, nl, C->desc.n, 1 << l, md, me,
+                         C->L32[l].mk);
+  }
+  LAUNCH_CHECK();
+  for (int l = 0; l < C->nlev; ++l) {
+    TRY(node_den_level<double>(C, C->L64[l]));
+    if (f32) TRY(node_den_level<float>(C, C->L32[l]));
+  }
+  const Level<double>& Lc = C->L64[C->nlev - 1];
+  hipLaunchKernelGGL(k_coarse_schur_terms, dim3(C->N), dim3(kBlock), 0, C->stream, C->m, C->Ainv, Lc.c, Lc.d, Lc.e,
+                     (const double*)Lc.mk, C->terms);
+  hipLaunchKernelGGL(k_coarse_schur_invert, dim3(1), dim3(kBlock), 0, C->stream, C->m, C->N, C->terms, Lc.g,
+                     C->Sinv);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+// Kernels with node factors from now on (factors != 1 somewhere): captured
+// V-cycles hold the other instantiation, so they are dropped when this changes.
+void set_masked(smg_ctx* C, bool masked) {
+  if (C->masked == masked) return;
+  for (auto& g : C->graphs) (void)hipGraphExecDestroy(g.exec);
+  C->graphs.clear();
+  C->masked = masked;
 }
 
 // out = f - S x (mode 0) or S x (mode 1); when want_norm, C->norms receives
@@ -517,12 +574,6 @@ int coarse_solve(smg_ctx* C, const TV* F, TV* X) {
   LAUNCH_CHECK();
   return SMG_OK;
 }
-
-#define TRY(expr)                  \
-  do {                             \
-    int rc_ = (expr);              \
-    if (rc_ != SMG_OK) return rc_; \
-  } while (0)
 
 // Alg. 1 on level l (Levels Ls of type T), x and f of that level; x_zero: x
 // holds (or is to be taken as) zero on entry.
@@ -1375,51 +1426,43 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
         return fail(SMG_EHIP);
     }
   }
-  // control mask (local control): the caller's on the finest level, by injection
-  // below (coarse node (X, K) is fine node (2X+1, 2K+1)), all ones without one;
-  // FP32 copies for the FP32 cycle
-  {
-    std::vector<double> mk((size_t)d.n * d.n, 1.0), mkc;
-    if (B->ctrl) mk.assign(B->ctrl, B->ctrl + (size_t)d.n * d.n);
-    C->masked = false;
-    for (double v : mk) C->masked |= (v != 1.0);
-    std::vector<float> mk32;
-    for (int l = 0; l < C->nlev; ++l) {
-      const int nl = C->L64[l].n;
-      if (l > 0) {
-        const int nf = C->L64[l - 1].n;
-        mkc.assign((size_t)nl * nl, 0.0);
-        for (int K = 0; K < nl; ++K)
-          for (int X = 0; X < nl; ++X) mkc[(size_t)K * nl + X] = mk[(size_t)(2 * K + 1) * nf + 2 * X + 1];
-        mk.swap(mkc);
-      }
-      if (hipMemcpy(C->L64[l].mk, mk.data(), sizeof(double) * mk.size(), hipMemcpyHostToDevice) != hipSuccess)
-        return fail(SMG_EHIP);
-      if (d.precision == SMG_F32) {
-        mk32.assign(mk.begin(), mk.end());
-        if (hipMemcpy(C->L32[l].mk, mk32.data(), sizeof(float) * mk32.size(), hipMemcpyHostToDevice) != hipSuccess)
-          return fail(SMG_EHIP);
-      }
-    }
-  }
-  // per-node denominators of the node solve, with the half-sweep's lane layout
-  for (int l = 0; l < C->nlev; ++l) {
-    if (node_den_level<double>(C, C->L64[l]) != SMG_OK) return fail(SMG_EHIP);
-    if (d.precision == SMG_F32 && node_den_level<float>(C, C->L32[l]) != SMG_OK) return fail(SMG_EHIP);
-  }
-  // coarsest factorization (FP64): A_j^{-1} and the control Schur complement inverse
+  // coarsest factorization (FP64): A_j^{-1}
   const Level<double>& Lc = C->L64[C->nlev - 1];
   hipLaunchKernelGGL(k_coarse_invert_A, dim3(N), dim3(kBlock), 0, C->stream, Lc.n, N, Lc.kx, Lc.ky, C->Ainv);
-  hipLaunchKernelGGL(k_coarse_schur_terms, dim3(N), dim3(kBlock), 0, C->stream, C->m, C->Ainv, Lc.c, Lc.d, Lc.e,
-                     (const double*)Lc.mk, C->terms);
-  hipLaunchKernelGGL(k_coarse_schur_invert, dim3(1), dim3(kBlock), 0, C->stream, C->m, N, C->terms, Lc.g, C->Sinv);
   if (hipGetLastError() != hipSuccess) return fail(SMG_EHIP);
+  // control mask (local control): the caller's, as both node factors (staged
+  // through the scratch vector rr); all ones without one
+  {
+    const double* mk = nullptr;
+    C->masked = false;
+    if (B->ctrl) {
+      for (size_t i = 0; i < (size_t)d.n * d.n; ++i) C->masked |= (B->ctrl[i] != 1.0);
+      if (hipMemcpyAsync(C->rr, B->ctrl, sizeof(double) * d.n * d.n, hipMemcpyHostToDevice, C->stream) != hipSuccess)
+        return fail(SMG_EHIP);
+      mk = C->rr;
+    }
+    if (factors_setup(C, mk, mk) != SMG_OK) return fail(SMG_EHIP);
+  }
   int flag = 0;
   if (hipMemcpyAsync(&flag, C->flag, sizeof(int), hipMemcpyDeviceToHost, C->stream) != hipSuccess) return fail(SMG_EHIP);
   if (hipStreamSynchronize(C->stream) != hipSuccess) return fail(SMG_EHIP);
   if (flag) return fail(SMG_ESINGULAR);
   *out = C;
   return SMG_OK;
+}
+
+int smg_set_node_factors(smg_ctx* C, const double* md, const double* me) {
+  if (!C) return SMG_EINVAL;
+  const size_t nn = (size_t)C->desc.n * C->desc.n;
+  HIP_TRY(hipMemsetAsync(C->flag, 0, sizeof(int), C->stream));
+  for (const double* a : {md, me})
+    if (a) hipLaunchKernelGGL(k_check_unit, dim3(grid_for(nn)), dim3(kBlock), 0, C->stream, nn, a, C->flag);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(C->host, C->flag, sizeof(int), hipMemcpyDeviceToHost, C->stream));
+  TRY(sync(C));
+  if (*(const int*)C->host) return SMG_EINVAL;
+  set_masked(C, md || me);
+  return factors_setup(C, md, me);
 }
 
 int smg_apply(smg_ctx* C, const double* x, double* Sx) {
@@ -1607,6 +1650,166 @@ int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, i
     stats_norms(st, h, fn);
     st->iterations = its;
     st->inner_iterations = inner;
+    st->time_ms = now_ms() - t0;
+  }
+  return rc;
+}
+
+}  // extern "C"
+
+// ======================================================= semismooth Newton
+namespace {
+
+SsnArgs ssn_args(const smg_ssn_params& p) { return {p.nu, p.beta, p.nu * p.b, p.nu * p.a}; }
+
+bool ssn_params_valid(const smg_ssn_params& p) {
+  return p.nu > 0 && std::isfinite(p.nu) && p.beta >= 0 && std::isfinite(p.beta) && p.a < 0 && p.b > 0 &&
+         !std::isnan(p.a) && !std::isnan(p.b) && p.mass > 0 && std::isfinite(p.mass) && p.tol > 0 &&
+         p.inner_rtol > 0 && p.maxit >= 0 && p.inner_maxit >= 1 &&
+         (p.inner_method == SMG_VCYCLE || p.inner_method == SMG_GMRES) && p.sigma >= 0 && p.sigma < 1 &&
+         p.rho >= 0 && p.rho < 1;
+}
+
+// w = E[p] of x per node; with F: also F, chi, -mass F into rU (if given) and
+// the merit sqrt(mass sum F^2) into *phi (if given; reads it back).
+int ssn_eval(smg_ctx* C, const double* x, const SsnArgs& a, double mass, double* w, double* F, double* chi,
+             double* rU, double* phi) {
+  const int nn = C->desc.n * C->desc.n;
+  int nb = 0;
+  seg_dispatch(C->N, [&](auto Wc, auto Jc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    const int per = kBlock / W;
+    nb = (nn + per - 1) / per;
+    hipLaunchKernelGGL((k_ssn_eval<W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, nn, C->N, x, a, mass, w, F, chi,
+                       rU, F ? C->spart : (double*)nullptr);
+  });
+  LAUNCH_CHECK();
+  if (F && phi) {
+    hipLaunchKernelGGL(k_partials_finalize, dim3(1), dim3(kBlock), 0, C->stream, C->spart, nb, 1, C->sout);
+    LAUNCH_CHECK();
+    TRY(readback(C, C->sout, 1));
+    *phi = std::sqrt(mass * C->host[0]);
+  }
+  return SMG_OK;
+}
+
+// phis[q] = merit at u + gammas[q] du (trial E[p] = w + gammas[q] dw), q < ng.
+int ssn_merit(smg_ctx* C, const double* u, const double* du, const double* w, const double* dw, const SsnArgs& a,
+              double mass, const double* gammas, int ng, double* phis) {
+  const int nn = C->desc.n * C->desc.n;
+  const int nb = std::min(kSsnMeritBlocks, (nn + kBlock - 1) / kBlock);
+  SsnGammas G{};
+  for (int q = 0; q < ng; ++q) G.g[q] = gammas[q];
+  hipLaunchKernelGGL(k_ssn_merit, dim3(nb), dim3(kBlock), 0, C->stream, nn, u, du, w, dw, a, G, ng, C->spart);
+  hipLaunchKernelGGL(k_partials_finalize, dim3(ng), dim3(kBlock), 0, C->stream, C->spart, nb, kSsnGammas, C->sout);
+  LAUNCH_CHECK();
+  TRY(readback(C, C->sout, ng));
+  for (int q = 0; q < ng; ++q) phis[q] = std::sqrt(mass * C->host[q]);
+  return SMG_OK;
+}
+
+void ssn_push(smg_ssn_stats* st, double phi, double gamma, int inner) {
+  if (!st) return;
+  const int k = st->len;
+  if (st->phi && k < st->cap) st->phi[k] = phi;
+  if (k > 0 && k - 1 < st->cap) {
+    if (st->gamma) st->gamma[k - 1] = gamma;
+    if (st->inner) st->inner[k - 1] = inner;
+  }
+  st->len = k + 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int smg_ssn_eval(smg_ctx* C, const double* x, const smg_ssn_params* p, double* w, double* F, double* chi,
+                 double* phi) {
+  if (!C || !x || !p || !w || ((F == nullptr) != (chi == nullptr)) || !ssn_params_valid(*p)) return SMG_EINVAL;
+  if (!(C->desc.flags & SMG_FLAG_SSN)) return SMG_EINVAL;
+  double ph = 0.0;
+  TRY(ssn_eval(C, x, ssn_args(*p), p->mass, w, F, chi, nullptr, F ? &ph : nullptr));
+  if (phi) *phi = F ? ph : 0.0;
+  return SMG_OK;
+}
+
+int smg_ssn_merit(smg_ctx* C, const double* u, const double* du, const double* w, const double* dw,
+                  const smg_ssn_params* p, int ng, const double* gammas, double* phis) {
+  if (!C || !u || !du || !w || !dw || !p || !gammas || !phis || ng < 1 || ng > kSsnGammas || !ssn_params_valid(*p))
+    return SMG_EINVAL;
+  if (!(C->desc.flags & SMG_FLAG_SSN)) return SMG_EINVAL;
+  return ssn_merit(C, u, du, w, dw, ssn_args(*p), p->mass, gammas, ng, phis);
+}
+
+int smg_ssn_solve(smg_ctx* C, double* x, const double* f, const smg_ssn_params* prm, smg_ssn_stats* st) {
+  if (!C || !x || !f || !prm || !ssn_params_valid(*prm)) return SMG_EINVAL;
+  if (!(C->desc.flags & SMG_FLAG_SSN)) return SMG_EINVAL;
+  if (prm->inner_method == SMG_GMRES && C->desc.gmres_restart < 1) return SMG_EINVAL;
+  const double t0 = now_ms();
+  const smg_ssn_params& p = *prm;
+  const double sigma = p.sigma > 0 ? p.sigma : 1e-4, rho = p.rho > 0 ? p.rho : 0.5;
+  const SsnArgs a = ssn_args(p);
+  const int N = C->N, nn = C->desc.n * C->desc.n;
+  const size_t len = C->len0;
+  double* const xU = x + (size_t)N * nn;
+  if (st) { st->iterations = 0; st->inner_total = 0; st->init_iterations = 0; st->len = 0; st->phi_final = 0.0; }
+  set_masked(C, true);
+  // Algorithm 2, first step: the state and adjoint equations for u0 = x's U
+  // block, as the system with D_j = 0 (md = 0) whose U row M u = M u0 fixes u
+  TRY(fill(C, C->schi, (size_t)nn, 0.0));
+  TRY(factors_setup(C, C->schi, nullptr));
+  HIP_TRY(hipMemcpyAsync(C->sr, f, len * sizeof(double), hipMemcpyDeviceToDevice, C->stream));
+  hipLaunchKernelGGL(k_scale, dim3((nn + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, nn, xU, p.mass,
+                     C->sr + (size_t)N * nn);
+  LAUNCH_CHECK();
+  smg_stats ist{};
+  int rc = smg_solve(C, x, C->sr, p.inner_method, p.inner_rtol, p.inner_maxit, &ist);
+  if (rc < 0) return rc;
+  if (st) st->init_iterations = ist.iterations;
+  if (rc != SMG_OK) { C->err = "initial state and adjoint solve did not converge"; return SMG_NOT_CONVERGED; }
+  // Newton right-hand side: zero but for its U block, -M F(u^k), which every
+  // evaluation rewrites
+  TRY(fill(C, C->sr, len, 0.0));
+  double* const rU = C->sr + (size_t)N * nn;
+  double phi = 0.0;
+  TRY(ssn_eval(C, x, a, p.mass, C->sw, C->sF, C->schi, rU, &phi));
+  ssn_push(st, phi, 0.0, 0);
+  int k = 0, inner_total = 0;
+  rc = SMG_NOT_CONVERGED;
+  while (true) {
+    if (!std::isfinite(phi)) { rc = SMG_ENONFINITE; break; }
+    if (phi <= p.tol) { rc = SMG_OK; break; }
+    if (k >= p.maxit) break;
+    // Newton system of the current active set (md = chi, E_j unchanged), solved from zero
+    TRY(factors_setup(C, C->schi, nullptr));
+    TRY(fill(C, C->sdx, len, 0.0));
+    smg_stats ns{};
+    const int lr = smg_solve(C, C->sdx, C->sr, p.inner_method, p.inner_rtol, p.inner_maxit, &ns);
+    if (lr < 0) return lr;
+    inner_total += ns.iterations;
+    TRY(ssn_eval(C, C->sdx, a, p.mass, C->sdw, nullptr, nullptr, nullptr, nullptr));
+    // line search: the first of 1, rho, rho^2, ... (at most 64) with sufficient
+    // decrease of the merit, priced kSsnGammas at a time
+    double g[kSsnGammas], phis[kSsnGammas], gamma = 0.0, next = 1.0;
+    bool found = false;
+    for (int batch = 0; batch < 64 / kSsnGammas && !found; ++batch) {
+      for (int q = 0; q < kSsnGammas; ++q) { g[q] = next; next *= rho; }
+      TRY(ssn_merit(C, xU, C->sdx + (size_t)N * nn, C->sw, C->sdw, a, p.mass, g, kSsnGammas, phis));
+      for (int q = 0; q < kSsnGammas && !found; ++q)
+        if (phis[q] - phi <= -sigma * phi) { gamma = g[q]; found = true; }
+    }
+    if (!found) { C->err = "line search found no decrease of the merit"; rc = SMG_NOT_CONVERGED; break; }
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x, gamma, C->sdx);
+    LAUNCH_CHECK();
+    TRY(ssn_eval(C, x, a, p.mass, C->sw, C->sF, C->schi, rU, &phi));
+    ++k;
+    ssn_push(st, phi, gamma, ns.iterations);
+  }
+  TRY(sync(C));
+  if (st) {
+    st->iterations = k;
+    st->inner_total = inner_total;
+    st->phi_final = phi;
     st->time_ms = now_ms() - t0;
   }
   return rc;

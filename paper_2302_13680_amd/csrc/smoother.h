@@ -96,7 +96,8 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
   const ptrdiff_t ow = hw ? -(ptrdiff_t)N : 0, oe = he ? (ptrdiff_t)N : 0;
   const ptrdiff_t os = hs ? -(ptrdiff_t)rowN : 0, on = hn ? (ptrdiff_t)rowN : 0;
   // per-node values first, so that their loads are in flight with the rest
-  const T fu = fU[node], gd = L.gden[node], mi = ctrl_mask<MK>(L, node);
+  const T fu = fU[node], gd = L.gden[node];
+  const NodeFactors<T> mf = node_factors<MK>(L, node);
   T bP[JM], bY[JM], ia[JM], cq[JM], eq[JM];
   T num = 0;
 #pragma unroll
@@ -152,8 +153,8 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
       const T ai = T(1) / a;
       const T bp = fy[u] + sp[u], by = fp[u] + sy[u];
       const T t = cj[u] * ai * ai;
-      num += act ? (mi * dj[u]) * (t * by - ai * bp) : T(0);
-      bP[q] = bp; bY[q] = by; ia[q] = ai; cq[q] = cj[u]; eq[q] = mi * ej[u];
+      num += act ? (mf.d * dj[u]) * (t * by - ai * bp) : T(0);
+      bP[q] = bp; bY[q] = by; ia[q] = ai; cq[q] = cj[u]; eq[q] = mf.e * ej[u];
     }
   }
   // e_j is first used after the sum over samples; without this the compiler
@@ -204,7 +205,7 @@ __device__ __forceinline__ void node_den(const LevelArgs<T>& L, T* __restrict__ 
   const int n = L.n, N = L.N;
   const int k = node / n, xx = node - k * n;
   const size_t kxb = ((size_t)k * (n + 1) + xx) * N, kyb = (size_t)node * N, rowN = (size_t)n * N;
-  const T mi = ctrl_mask<true>(L, node);
+  const NodeFactors<T> mf = node_factors<true>(L, node);
   T den = 0;
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
@@ -224,7 +225,7 @@ __device__ __forceinline__ void node_den(const LevelArgs<T>& L, T* __restrict__ 
       const T a = (kw[u] + ke[u]) + (ks[u] + kn[u]);
       const T ai = T(1) / a;
       const T t = cj[u] * ai * ai;
-      den += act ? (mi * dj[u]) * t * (mi * ej[u]) : T(0);
+      den += act ? (mf.d * dj[u]) * t * (mf.e * ej[u]) : T(0);
     }
   }
   den = group_sum_w(den, W);

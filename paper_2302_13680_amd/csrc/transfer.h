@@ -166,7 +166,7 @@ __device__ __forceinline__ T residual_restrict_rows(const LevelArgs<T>& L, const
         const int wi = i + 1, wk = k + 1;
         const T w = (T)(lin_w(k - 1) * lin_w(i - 1));
         const T u = U[(size_t)(kc - 1 + i) * n + (xc - 1 + k)];
-        const T mf = ctrl_mask<MK>(L, (size_t)(kc - 1 + i) * n + (xc - 1 + k));
+        const T mf = node_factors<MK>(L, (size_t)(kc - 1 + i) * n + (xc - 1 + k)).e;
 #pragma unroll
         for (int q = 0; q < VW; ++q) {
           const T kw = kxv[i][k][q], ke = kxv[i][k + 1][q], ks = kyv[i][k][q], kn = kyv[i + 1][k][q];
@@ -189,7 +189,7 @@ __device__ __forceinline__ T residual_restrict_rows(const LevelArgs<T>& L, const
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-          wp += ((T)(lin_w(k - 1) * lin_w(i - 1)) * ctrl_mask<MK>(L, (size_t)(kc - 1 + i) * n + (xc - 1 + k))) *
+          wp += ((T)(lin_w(k - 1) * lin_w(i - 1)) * node_factors<MK>(L, (size_t)(kc - 1 + i) * n + (xc - 1 + k)).d) *
                 pv[i + 1][k + 1][q];
       dw += act ? dj[q] * wp : T(0);
     }

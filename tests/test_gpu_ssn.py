@@ -1,0 +1,276 @@
+"""GPU parity of the semismooth Newton path (Section 5, Algorithm 2) against the
+pinned oracle, through the C ABI: node factors on D_j and E_j in every step
+and cycle, the pointwise evaluation (E[p], F, active set, merit), the batched
+line-search merits, and whole solves (Newton and inner iteration counts,
+step lengths, the solution)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2302_13680_amd import inputs
+from paper_2302_13680_amd.inputs import node_to_paper, paper_to_node
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_13680_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as o
+    return o
+
+
+@pytest.fixture(scope="module")
+def S():
+    from oracle import ssn
+    return ssn
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def paper_yd(n):
+    h = 1.0 / (n + 1)
+    t = (np.arange(n) + 1.0) * h
+    X, Y = np.meshgrid(t, t)
+    return np.exp(Y ** 2) * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+
+
+def problem(n, N, nu=1e-4, seed=3):
+    return inputs.make_problem(n, N, nu, M=3, sigma=0.5, decay=True, seed=seed, yd=paper_yd(n), f=0.0)
+
+
+def factors(n, kind, seed):
+    rng = np.random.default_rng(seed)
+    md = rng.integers(0, 2, (n, n)).astype(np.float64)
+    me = None if kind == "d" else rng.uniform(0.0, 1.0, (n, n))
+    return md, me
+
+
+@pytest.mark.parametrize("kind", ["d", "de"])
+@pytest.mark.parametrize("n,N", [(15, 3), (31, 8), (63, 16), (31, 100)])
+def test_node_factor_steps(B, O, n, N, kind):
+    """Residual, Jacobi step, half-sweeps, residual + restriction on every level
+    and the coarsest solve with node factors on D_j (and E_j) set on the device."""
+    p = problem(n, N, seed=n + N)
+    md, me = factors(n, kind, seed=n)
+    o = O.Oracle(p)
+    o.set_masks(md, me)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0, theta=0.5)
+    ctx.set_node_factors(dev(md), None if me is None else dev(me))
+    rng = np.random.default_rng(n + 1)
+    x = rng.standard_normal(o.vlen())
+    f = rng.standard_normal(o.vlen())
+    xd, fd = dev(paper_to_node(x, n, N)), dev(paper_to_node(f, n, N))
+    r = torch.empty_like(xd)
+    ctx.residual(xd, fd, r)
+    assert rel(node_to_paper(host(r), n, N), o.residual(x, f)) <= 1e-14
+    out = torch.empty_like(xd)
+    ctx.jacobi(0, xd, out, fd)
+    assert rel(node_to_paper(host(out), n, N), o.jacobi(x, f, 0.5)) <= 1e-13
+    xs, xo = xd.clone(), x.copy()
+    for colour in (0, 1):
+        ctx.smooth(0, colour, xs, fd)
+        xo = o.halfsweep(xo, f, colour, theta=0.5)
+        assert rel(node_to_paper(host(xs), n, N), xo) <= 1e-13, colour
+    for l in range(o.nlev - 1):
+        nl, nc = o.levels_n[l], o.levels_n[l + 1]
+        xl = rng.standard_normal(o.vlen(l))
+        fl = rng.standard_normal(o.vlen(l))
+        cd = torch.empty(o.vlen(l + 1), dtype=torch.float64, device="cuda")
+        ctx.residual_restrict(l, dev(paper_to_node(xl, nl, N)), dev(paper_to_node(fl, nl, N)), cd)
+        assert rel(node_to_paper(host(cd), nc, N), O.restrict(nl, N, o.residual(xl, fl, l))) <= 1e-14, l
+    F = rng.standard_normal(o.vlen(o.nlev - 1))
+    X = torch.empty(F.size, dtype=torch.float64, device="cuda")
+    nc = o.levels_n[-1]
+    ctx.coarse_solve(dev(paper_to_node(F, nc, N)), X)
+    assert rel(node_to_paper(host(X), nc, N), o.coarse_solve(F)) <= 1e-11
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_node_factor_cycles_and_captured_graphs(B, O, precision):
+    """V-cycle iterates with the factors of a Newton system, replayed from
+    captured graphs: first unmasked (graph captured without factors), then
+    with factors (the graph must be recaptured), then back to none."""
+    n, N = 63, 16
+    p = problem(n, N, seed=7)
+    md, _ = factors(n, "d", seed=8)
+    o = O.Oracle(p)
+    ctx, f = B.context_from_problem(p, gmres_restart=0, precision=precision)
+    fp = p.rhs_paper()
+    tol = 1e-12 if precision == 0 else 2e-5
+    cyc = o.vcycle if precision == 0 else o.vcycle32
+    for stage, m in enumerate([None, md, None]):
+        o.set_masks(m, None)
+        ctx.set_node_factors(None if m is None else dev(m), None)
+        x_o = np.zeros(o.vlen())
+        xd = torch.zeros(o.vlen(), dtype=torch.float64, device="cuda")
+        for k in range(3):
+            x_o = cyc(x_o, fp, 1)
+            ctx.vcycle(xd, f, 1)
+            assert rel(node_to_paper(host(xd), n, N), x_o) <= tol, (stage, k)
+
+
+def test_set_node_factors_rejects_values_outside_unit_interval(B):
+    p = problem(15, 3)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0)
+    for bad in (1.5, -0.25, float("nan")):
+        md = np.ones((15, 15))
+        md[3, 4] = bad
+        with pytest.raises(B.SmgError) as e:
+            ctx.set_node_factors(dev(md), None)
+        assert e.value.code == -1
+        with pytest.raises(B.SmgError):
+            ctx.set_node_factors(None, dev(md))
+
+
+def ssn_prm(B, p, beta, a, b, **kw):
+    h = 1.0 / (p.n + 1)
+    return B.ssn_params(p.nu, beta, a, b, h * h, **kw)
+
+
+@pytest.mark.parametrize("n,N", [(15, 3), (31, 8), (63, 100), (127, 64)])
+def test_ssn_eval_and_merit(B, S, n, N):
+    """E[p], F, the active set and the merit of a state, and the line-search
+    merits of a step, against the oracle's pointwise maps."""
+    p = problem(n, N, nu=1e-3)
+    nn = n * n
+    rng = np.random.default_rng(n + N)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0, ssn=True)
+    beta, a, b = 4e-3, -6.0, 6.0
+    prm = ssn_prm(B, p, beta, a, b)
+    x = rng.standard_normal((2 * N + 1) * nn)
+    x[(N + 1) * nn:] *= 0.03 / math.sqrt(N)    # E[p] over the five pieces of F
+    x[N * nn:(N + 1) * nn] *= 5
+    xd = dev(paper_to_node(x, n, N))
+    w, F, chi = (torch.empty(nn, dtype=torch.float64, device="cuda") for _ in range(3))
+    phi = ctx.ssn_eval(xd, prm, w, F, chi)
+    w_o = S.expected_p(x, n, N)
+    u = x[N * nn:(N + 1) * nn]
+    assert np.abs(host(w) - w_o).max() <= 1e-15 * max(1.0, np.abs(w_o).max()) * 8
+    wg = host(w)
+    kinks = np.array([-beta, beta, beta + p.nu * b, p.nu * a - beta])
+    far = np.min(np.abs(wg[:, None] - kinks[None]), axis=1) > 1e-13
+    chi_o = S.active_set(wg, p.nu, beta, a, b)
+    assert 0.05 < chi_o.mean() < 0.95
+    np.testing.assert_array_equal(host(chi)[far], chi_o[far])
+    F_o = S.F_map(u, wg, p.nu, beta, a, b)
+    np.testing.assert_array_equal(host(F), F_o)   # same w: same operations
+    h = 1.0 / (n + 1)
+    assert abs(phi - S.merit(F_o, h)) <= 1e-13 * S.merit(F_o, h)
+    # w only
+    w2 = torch.empty_like(w)
+    assert ctx.ssn_eval(xd, prm, w2) == 0.0
+    np.testing.assert_array_equal(host(w2), host(w))
+    # merits of a step
+    du, dw = rng.standard_normal(nn) * 3, rng.standard_normal(nn) * 0.01
+    gam = [1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125, 1e-3, 0.0][: 8 if n > 15 else 3]
+    phis = ctx.ssn_merit(dev(u), dev(du), w, dev(dw), prm, gam)
+    for g, ph in zip(gam, phis):
+        ref = S.merit(S.F_map(u + g * du, wg + g * dw, p.nu, beta, a, b), h)
+        assert abs(ph - ref) <= 1e-12 * ref, g
+
+
+def run_pair(B, S, p, beta, a, b, method, maxit=100, u0=None):
+    n, N = p.n, p.N
+    nn = n * n
+    linear = "gmres" if method == B.SMG_GMRES else "vcycle"
+    ref = S.ssn_solve(p, beta, a, b, linear=linear, inner_tol=1e-11, maxit=maxit, u0=u0)
+    ctx, f = B.context_from_problem(p, gmres_restart=30, ssn=True)
+    x = torch.zeros((2 * N + 1) * nn, dtype=torch.float64, device="cuda")
+    if u0 is not None:
+        x[N * nn:(N + 1) * nn] = dev(u0)
+    prm = ssn_prm(B, p, beta, a, b, inner_method=method, maxit=maxit)
+    rc, st = ctx.ssn_solve(x, f, prm)
+    return ref, rc, st, node_to_paper(host(x), n, N)
+
+
+@pytest.mark.parametrize("method", [1, 0])
+@pytest.mark.parametrize("n,N", [(31, 8), (63, 16)])
+def test_ssn_solve_matches_oracle(B, S, n, N, method):
+    """The paper's setting (nu = 1e-4, beta = 1e-2, |u| <= 50, tolerances 1e-9
+    and 1e-11): the same Newton iterations and step lengths, inner counts
+    within one, the same solution."""
+    p = problem(n, N)
+    ref, rc, st, xg = run_pair(B, S, p, 1e-2, -50.0, 50.0, method)
+    assert rc == B.SMG_OK and ref["converged"]
+    assert st["iterations"] == ref["iterations"]
+    assert st["gammas"] == ref["gammas"]
+    assert all(abs(a - b) <= 1 for a, b in zip(st["inner"], ref["inner"])), (st["inner"], ref["inner"])
+    assert st["phi_final"] <= 1e-9
+    np.testing.assert_allclose(st["phi"][:-1], ref["phi"][:-1], rtol=1e-6)
+    nn = n * n
+    ug = xg[N * nn:(N + 1) * nn]
+    assert np.abs(ug - ref["u"]).max() <= 1e-8 * np.abs(ref["u"]).max()
+    assert rel(xg, ref["x"]) <= 1e-8
+    assert np.abs(ug).max() <= 50.0 + 1e-9
+
+
+def test_ssn_solve_backtracking(B, S):
+    """nu = 1e-6: the line search backtracks; the same step lengths as the oracle."""
+    p = problem(31, 4, nu=1e-6)
+    ref, rc, st, xg = run_pair(B, S, p, 1e-2, -50.0, 50.0, B.SMG_GMRES, maxit=200)
+    assert rc == B.SMG_OK and ref["converged"]
+    assert min(ref["gammas"]) < 1.0
+    assert st["iterations"] == ref["iterations"]
+    assert st["gammas"] == ref["gammas"]
+    nn = p.n * p.n
+    ug = xg[p.N * nn:(p.N + 1) * nn]
+    assert np.abs(ug - ref["u"]).max() <= 1e-7 * np.abs(ref["u"]).max()
+
+
+def test_ssn_closed_cases(B, S, O):
+    """beta = 0 without bounds: one step to the linear-quadratic solution (the
+    GPU's own LQ solve); beta above every |E[p]|: u = 0."""
+    n, N = 31, 8
+    p = problem(n, N)
+    nn = n * n
+    ref, rc, st, xg = run_pair(B, S, p, 0.0, -np.inf, np.inf, B.SMG_GMRES)
+    assert rc == B.SMG_OK and st["iterations"] == 1
+    ctx, f = B.context_from_problem(p, gmres_restart=30)
+    x = torch.zeros(ctx.vlen(), dtype=torch.float64, device="cuda")
+    ctx.solve(x, f, B.SMG_GMRES, rtol=1e-12, maxit=100)
+    u_lq = node_to_paper(host(x), n, N)[N * nn:(N + 1) * nn]
+    assert np.abs(xg[N * nn:(N + 1) * nn] - u_lq).max() <= 1e-8 * np.abs(u_lq).max()
+    q = inputs.make_problem(n, N, 1e-3, M=3, sigma=0.5, decay=True, seed=5, yd=paper_yd(n), f=1.0)
+    w0 = S.expected_p(S.initial_state(q, np.zeros(nn)), n, N)
+    u0 = 1e-3 * np.random.default_rng(6).standard_normal(nn)
+    ref, rc, st, xg = run_pair(B, S, q, 10 * np.abs(w0).max(), -1.0, 1.0, B.SMG_GMRES, u0=u0)
+    assert rc == B.SMG_OK and st["iterations"] == 1 == ref["iterations"]
+    assert np.abs(xg[N * nn:(N + 1) * nn]).max() <= 1e-11 * np.abs(u0).max()
+
+
+def test_ssn_rejects_bad_use(B):
+    p = problem(15, 3)
+    ctx, f = B.context_from_problem(p, gmres_restart=30)     # no SMG_FLAG_SSN
+    x = torch.zeros(ctx.vlen(), dtype=torch.float64, device="cuda")
+    prm = ssn_prm(B, p, 1e-2, -1.0, 1.0)
+    with pytest.raises(B.SmgError):
+        ctx.ssn_solve(x, f, prm)
+    ctx2, f2 = B.context_from_problem(p, gmres_restart=30, ssn=True)
+    for bad in (ssn_prm(B, p, 1e-2, 0.5, 1.0), ssn_prm(B, p, -1.0, -1.0, 1.0),
+                B.ssn_params(-1e-4, 1e-2, -1.0, 1.0, 1.0 / 256), ssn_prm(B, p, 1e-2, -1.0, 1.0, sigma=1.5)):
+        with pytest.raises(B.SmgError):
+            ctx2.ssn_solve(x, f2, bad)
+    with pytest.raises(B.SmgError):
+        B.context_from_problem(p, gmres_restart=30, ssn=True, precision=1)
