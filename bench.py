@@ -248,6 +248,70 @@ def learned_section(dev, n_train=2000, n_test=200, epochs=20):
     return summ
 
 
+def ssn_run(ctx, x, f, prm, u0=None):
+    """One timed smg_ssn_solve from u0 (zero) with zero state and adjoint guesses."""
+    import numpy as np
+    import torch
+    from paper_2302_13680_amd import binding, inputs
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = ctx.ssn_solve(x, f, prm)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0), rc, st
+
+
+def ssn_section(dev, n, N, args):
+    import numpy as np
+    import torch
+    from paper_2302_13680_amd import binding, inputs
+    p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=1, yd=inputs.paper_target(n), f=0.0)
+    ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, ssn=True)
+    x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
+    h2 = (1.0 / (n + 1)) ** 2
+    out = {"problem": f"{n}x{n}, N={N}, nu=1e-4, beta=1e-2, -50 <= u <= 50, y_d = exp(y^2) sin 2pi x sin 2pi y, f=0",
+           "tol_phi": 1e-9, "inner_rtol": 1e-11}
+    for name, method in (("gmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
+        prm = binding.ssn_params(1e-4, 1e-2, -50.0, 50.0, h2, inner_method=method)
+        ssn_run(ctx, x, f, prm)                                    # warm-up (graph capture)
+        t, rc, st = ssn_run(ctx, x, f, prm)
+        u = x[N * n * n:(N + 1) * n * n]
+        out[name] = {"time_ms": round(t, 2), "converged": rc == binding.SMG_OK,
+                     "newton_iterations": st["iterations"], "initial_solve_iterations": st["init_iterations"],
+                     "inner_iterations": st["inner"],
+                     "mean_inner_per_newton": round(float(np.mean(st["inner"])), 2) if st["inner"] else 0.0,
+                     "step_lengths": st["gammas"], "phi": [float(f"{v:.3e}") for v in st["phi"]],
+                     "ms_per_newton_step": round(t / max(st["iterations"], 1), 2),
+                     "control_zero_fraction": round(float((u.abs() <= 1e-8).float().mean()), 4),
+                     "control_at_bounds_fraction": round(float((u.abs() >= 50.0 - 1e-9).float().mean()), 4)}
+    ctx.close()
+    return out
+
+
+def ssn_paper_setting(dev):
+    """The paper's L1 table setting (N_h = 705 on its L-shape, three levels, 5^3
+    collocation nodes, sigma^2 = 0.5, nu 1e-4, beta 1e-2, |u| <= 50, collective
+    Jacobi theta 1/2) on this build's 31x31 square grid: Newton iterations and
+    mean inner iterations per Newton step, beside the printed 5 | 22.6 | 14.2."""
+    import numpy as np
+    import torch
+    from paper_2302_13680_amd import binding, inputs
+    p = inputs.collocation_problem(31, 5, 1e-4, M=3, sigma=float(np.sqrt(0.5)), decay=True,
+                                   yd=inputs.paper_target(31), f=0.0)
+    ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5, flags=binding.SMG_FLAG_JACOBI,
+                                          ssn=True)
+    x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
+    out = {"n": 31, "N": p.N, "levels": list(ctx.levels_n), "paper_printed_newton_vcycle_gmres": [5, 22.6, 14.2]}
+    for name, method in (("gmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
+        prm = binding.ssn_params(1e-4, 1e-2, -50.0, 50.0, (1.0 / 32) ** 2, inner_method=method)
+        _, rc, st = ssn_run(ctx, x, f, prm)
+        out[name + "_newton_iterations"] = st["iterations"]
+        out[name + "_mean_inner"] = round(float(np.mean(st["inner"])), 2) if st["inner"] else 0.0
+        out[name + "_converged"] = rc == binding.SMG_OK
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,10 +440,7 @@ def main():
     # levels, 5^3 Gauss-Hermite nodes, nu 1e-4, collective Jacobi theta 1/2, V(2,2),
     # tolerance 1e-9; y_d = exp(y^2) sin(2 pi x) sin(2 pi y), no source) with this
     # build's finite differences and analytic coefficient expansion
-    h31 = 1.0 / 32
-    g31 = (np.arange(31) + 1) * h31
-    X31, Y31 = np.meshgrid(g31, g31)
-    yd31 = np.exp(Y31 ** 2) * np.sin(2 * np.pi * X31) * np.sin(2 * np.pi * Y31)
+    yd31 = inputs.paper_target(31)
     pt = inputs.collocation_problem(31, 5, 1e-4, M=3, sigma=float(np.sqrt(0.5)), decay=True, yd=yd31, f=0.0,
                                     control_region=(0.25, 0.75, 0.25, 0.75))
     ct, ft = binding.context_from_problem(pt, device=dev, gmres_restart=30, theta=0.5,
@@ -392,6 +453,12 @@ def main():
         "gmres_iterations": st_g["iterations"], "paper_printed_vcycle_gmres": [20, 13]}
     ct.close()
     del ct, ft, xt
+
+    # ---------------- semismooth Newton for the L1-penalized, box-constrained control
+    # (Section 5, Algorithm 2): nu 1e-4, beta 1e-2, -50 <= u <= 50, phi <= 1e-9,
+    # every Newton system to 1e-11; the paper's target, no source
+    ssn = ssn_section(dev, n, N, args)
+    ssn["paper_l1_setting"] = ssn_paper_setting(dev)
 
     # ---------------- roofline of the dominant kernel: finest-level half-sweep
     xs = torch.zeros(dof, dtype=torch.float64, device=dev)
@@ -480,6 +547,7 @@ def main():
         "jacobi_smoother": jac,
         "stochastic_collocation": sc,
         "local_control": lc,
+        "semismooth_newton": ssn,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

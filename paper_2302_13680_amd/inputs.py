@@ -196,6 +196,14 @@ def collocation_problem(n: int, q: int, nu: float = 1e-4, *, M: int = 3, sigma: 
     return make_problem(n, xi.shape[0], nu, M=M, sigma=sigma, decay=decay, xi=xi, weights=zeta, **kw)
 
 
+def paper_target(n: int) -> np.ndarray:
+    """y_d = exp(y^2) sin(2 pi x) sin(2 pi y) at the interior nodes, the target
+    state of the paper's experiments (Section 3.2 and after)."""
+    t = (np.arange(n) + 1.0) / (n + 1)
+    X, Y = np.meshgrid(t, t)
+    return np.exp(Y ** 2) * np.sin(2 * math.pi * X) * np.sin(2 * math.pi * Y)
+
+
 def random_yd(n: int, rng: np.random.Generator, terms: int = 3, kmax: int = 4) -> np.ndarray:
     """Target state drawn as a random sum of ``terms`` sine products
     sum_t c_t sin(k_t pi x) sin(l_t pi y), c_t ~ U[-1, 1], k_t, l_t ~ U{1..kmax}."""
