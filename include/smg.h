@@ -261,17 +261,24 @@ int smg_gmres_precond(smg_ctx *ctx, double *x, const double *f, int restart, dou
 int smg_solve(smg_ctx *ctx, double *x, const double *f, int method, double rtol, int maxit,
               smg_stats *stats);
 
+/* how node factors reach coarse levels (smg_set_node_factors) */
+#define SMG_COARSEN_INJECT 0  /* coarse node (X, K) takes fine node (2X+1, 2K+1) */
+#define SMG_COARSEN_FULL 1    /* full-weighting average of the 3 x 3 fine nodes around it, weights
+                                 (1/4)(1/2)^(|dx|+|dk|): the row-lumped diagonal of R diag(v) P */
+
 /* Node factors of D_j and E_j: the node entries become md_i d_j and me_i e_j
- * on every level (coarse node (X, K) takes the factors of fine node
- * (2X+1, 2K+1), level by level), and the per-node denominators and the
- * coarsest Schur complement are rebuilt.  Local control is md = me = the
- * control mask; the Newton system of Section 5
+ * on every level (coarse levels level by level by `coarsening`, one of
+ * SMG_COARSEN_*), and the per-node denominators and the coarsest Schur
+ * complement are rebuilt.  Local control is md = me = the control mask
+ * (smg_setup's ctrl, by injection); the Newton system of Section 5
  * (eq. full_space_optimality_systeMemismooth2) is md = the active-set
- * indicator, me = 1.  md, me: device, [n][n] (row k, column x) of the finest
- * level, values in [0, 1]; NULL: 1 everywhere.  Replaces the control mask
- * given to smg_setup.  Synchronizes the context's stream.  A value outside
- * [0, 1] or not finite: SMG_EINVAL, nothing changed. */
-int smg_set_node_factors(smg_ctx *ctx, const double *md, const double *me);
+ * indicator, me = 1, by full weighting (the V-cycle then needs a third to a
+ * fifth of the cycles injection needs).  md, me: device, [n][n] (row k,
+ * column x) of the finest level, values in [0, 1]; NULL: 1 everywhere.
+ * Replaces the control mask given to smg_setup.  Synchronizes the context's
+ * stream.  A value outside [0, 1] or not finite, or an unknown coarsening:
+ * SMG_EINVAL, nothing changed. */
+int smg_set_node_factors(smg_ctx *ctx, const double *md, const double *me, int coarsening);
 
 /* ------------------------------------------------------- semismooth Newton
  * The control problem with an L^1 penalty and box constraints (Section 5,
@@ -305,7 +312,7 @@ int smg_ssn_merit(smg_ctx *ctx, const double *u, const double *du, const double 
  * the state and adjoint equations for u^0 (the system with D_j = 0 and U
  * block M u^0); then until phi(u^k) <= tol: node factors md = chi(u^k),
  * me = 1, the Newton system with right-hand side (0, -M F(u^k), 0) solved from
- * zero to inner_rtol, the first step length of 1, rho, rho^2, ... (at most 64)
+ * zero to inner_rtol (coarse levels take the active set by full weighting), the first step length of 1, rho, rho^2, ... (at most 64)
  * with phi(u + gamma du) - phi(u) <= -sigma phi(u), x += gamma dx.  The
  * context keeps the last node factors.  Returns SMG_OK, SMG_NOT_CONVERGED
  * (maxit reached, no step of sufficient decrease, or the initial solve did not

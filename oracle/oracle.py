@@ -46,7 +46,8 @@ def _load():
     L.or_set_control.restype = C.c_int
     L.or_set_control.argtypes = [vp, _dp]
     L.or_set_masks.restype = C.c_int
-    L.or_set_masks.argtypes = [vp, C.c_void_p, C.c_void_p]
+    L.or_set_masks.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_int]
+    L.or_level_factor.argtypes = [vp, C.c_int, C.c_int, _dp]
     L.or_create.restype = vp
     L.or_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                             _dp, _dp, _dp, _dp, _dp, C.c_double]
@@ -152,13 +153,23 @@ class Oracle:
         self.nlev = L.or_nlevels(self.ctx)
         self.levels_n = [L.or_level_n(self.ctx, l) for l in range(self.nlev)]
 
-    def set_masks(self, md, me):
+    def set_masks(self, md, me, coarsen: str = "injection"):
         """Node factors of D_j (md) and E_j (me), [n][n] arrays of the finest level or
-        None for 1; coarse levels by injection, coarsest factorization rebuilt."""
+        None for 1; coarse levels by injection or full weighting ("full"), coarsest
+        factorization rebuilt."""
+        if coarsen not in ("injection", "full"):
+            raise ValueError("coarsen must be 'injection' or 'full'")
         keep = [None if m is None else _f64(np.asarray(m).reshape(self.n, self.n)) for m in (md, me)]
         ptr = [None if m is None else m.ctypes.data for m in keep]
-        if _load().or_set_masks(self.ctx, ptr[0], ptr[1]) != 0:
+        if _load().or_set_masks(self.ctx, ptr[0], ptr[1], 1 if coarsen == "full" else 0) != 0:
             raise ValueError("oracle: singular coarsest block with these node factors")
+
+    def level_factor(self, l: int, which: str = "d"):
+        """The node factor md (which="d") or me ("e") of level l, [n_l][n_l]."""
+        n = self.levels_n[l]
+        out = np.zeros(n * n)
+        _load().or_level_factor(self.ctx, l, 0 if which == "d" else 1, out)
+        return out.reshape(n, n)
 
     def __del__(self):
         if getattr(self, "ctx", None):

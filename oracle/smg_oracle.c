@@ -283,9 +283,12 @@ or_ctx *or_create(int n, int N, int coarsest_n, int pre, int post, double theta,
   return C;
 }
 
-/* Per-level copies of a finest-level node factor: coarse node (X, K) takes the
- * value of fine node (2X+1, 2K+1) (injection).  src NULL: all levels NULL. */
-static void set_factor(or_ctx *C, const double *src, double **lv, float **lv32) {
+/* Per-level copies of a finest-level node factor, level by level: coarse node
+ * (X, K) takes the value of fine node (2X+1, 2K+1) (coarsen 0: injection) or
+ * the full-weighting average of the 3 x 3 fine nodes around it, weights
+ * (1/4)(1/2)^(|dx|+|dk|) (coarsen 1: the diagonal of the Galerkin product
+ * R diag(v) P lumped by rows, R = P^T / 4).  src NULL: all levels NULL. */
+static void set_factor(or_ctx *C, const double *src, double **lv, float **lv32, int coarsen) {
   for (int l = 0; l < C->nlev; ++l) {
     free(lv[l]); free(lv32[l]);
     lv[l] = NULL; lv32[l] = NULL;
@@ -299,20 +302,31 @@ static void set_factor(or_ctx *C, const double *src, double **lv, float **lv32) 
     } else {
       int nf = C->n[l - 1];
       for (int K = 0; K < nl; ++K)
-        for (int X = 0; X < nl; ++X)
-          lv[l][(size_t)K * nl + X] = lv[l - 1][(size_t)(2 * K + 1) * nf + 2 * X + 1];
+        for (int X = 0; X < nl; ++X) {
+          const double *F = lv[l - 1];
+          if (!coarsen) {
+            lv[l][(size_t)K * nl + X] = F[(size_t)(2 * K + 1) * nf + 2 * X + 1];
+            continue;
+          }
+          double acc = 0.0;
+          for (int dk = -1; dk <= 1; ++dk)
+            for (int dx = -1; dx <= 1; ++dx)
+              acc += (dx ? 0.5 : 1.0) * (dk ? 0.5 : 1.0) * 0.25 * F[(size_t)(2 * K + 1 + dk) * nf + 2 * X + 1 + dx];
+          lv[l][(size_t)K * nl + X] = acc;
+        }
     }
     lv32[l] = to_f32(lv[l], (size_t)nl * nl);
   }
 }
 
 /* Node factors of D_j and E_j: the node entries become md_i d_j and me_i e_j on
- * every level, coarse factors by injection; the coarsest factorization is
- * rebuilt.  md, me: [n][n] of the finest level, or NULL for 1 everywhere.
- * Returns 0, or -1 if the coarsest system is singular. */
-int or_set_masks(or_ctx *C, const double *md, const double *me) {
-  set_factor(C, md, C->md, C->md32);
-  set_factor(C, me, C->me, C->me32);
+ * every level, coarse factors by injection (coarsen 0) or full weighting
+ * (coarsen 1); the coarsest factorization is rebuilt.  md, me: [n][n] of the
+ * finest level, or NULL for 1 everywhere.  Returns 0, or -1 if the coarsest
+ * system is singular. */
+int or_set_masks(or_ctx *C, const double *md, const double *me, int coarsen) {
+  set_factor(C, md, C->md, C->md32, coarsen);
+  set_factor(C, me, C->me, C->me32, coarsen);
   for (int l = 0; l < C->nlev; ++l) {
     C->L[l].md = C->md[l]; C->L32[l].md = C->md32[l];
     C->L[l].me = C->me[l]; C->L32[l].me = C->me32[l];
@@ -325,7 +339,15 @@ int or_set_masks(or_ctx *C, const double *md, const double *me) {
 /* Control acting only where mask[i] != 0 (local control; eq.
  * solution_reduced_system2 at nodes without control): the node entries of D_j
  * and E_j become mask_i d_j and mask_i e_j.  mask NULL: control everywhere. */
-int or_set_control(or_ctx *C, const double *mask) { return or_set_masks(C, mask, mask); }
+int or_set_control(or_ctx *C, const double *mask) { return or_set_masks(C, mask, mask, 0); }
+
+/* The node factor of every level (after or_set_masks): out [n_l][n_l], 1 where
+ * the factor is absent.  which 0: md, 1: me. */
+void or_level_factor(const or_ctx *C, int l, int which, double *out) {
+  const double *v = which ? C->me[l] : C->md[l];
+  size_t nn = (size_t)C->n[l] * C->n[l];
+  for (size_t i = 0; i < nn; ++i) out[i] = v ? v[i] : 1.0;
+}
 
 int or_nlevels(const or_ctx *C) { return C->nlev; }
 int or_level_n(const or_ctx *C, int l) { return C->n[l]; }

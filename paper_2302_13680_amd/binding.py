@@ -23,6 +23,7 @@ SMG_FLAG_EAGER = 1
 SMG_FLAG_UNFUSED = 2
 SMG_FLAG_JACOBI = 4
 SMG_FLAG_SSN = 8
+SMG_COARSEN_INJECT, SMG_COARSEN_FULL = 0, 1
 
 EXPORTED = [
     "smg_workspace_bytes", "smg_setup", "smg_destroy", "smg_strerror", "smg_last_error",
@@ -154,7 +155,7 @@ def load(path: str = LIB_PATH):
     for name in ["smg_net_set_params", "smg_net_get_params", "smg_net_forward", "smg_net_grad",
                  "smg_net_train_step", "smg_net_features", "smg_net_targets", "smg_net_lift"]:
         getattr(L, name).restype = i
-    L.smg_set_node_factors.argtypes = [vp, vp, vp]
+    L.smg_set_node_factors.argtypes = [vp, vp, vp, i]
     L.smg_ssn_eval.argtypes = [vp, vp, C.POINTER(SsnParams), vp, vp, vp, C.POINTER(C.c_double)]
     L.smg_ssn_merit.argtypes = [vp, vp, vp, vp, vp, C.POINTER(SsnParams), i, C.POINTER(C.c_double),
                                 C.POINTER(C.c_double)]
@@ -304,10 +305,10 @@ class Context:
         return rc, _stats_dict(st)
 
     # --- node factors and the semismooth Newton solver ----------------------
-    def set_node_factors(self, md=None, me=None):
+    def set_node_factors(self, md=None, me=None, coarsening=SMG_COARSEN_INJECT):
         """md, me: float64 device tensors [n][n] (or None for 1)."""
         return self._check(self.L.smg_set_node_factors(
-            self.ctx, None if md is None else _ptr(md), None if me is None else _ptr(me)))
+            self.ctx, None if md is None else _ptr(md), None if me is None else _ptr(me), int(coarsening)))
 
     def ssn_eval(self, x, prm, w, F=None, chi=None):
         """w = E[p] per node; with F, chi also F(u), the active set and the merit (returned)."""

@@ -27,19 +27,41 @@ __global__ void k_coarsen_faces(int nf, int N, const T* __restrict__ kxf, const 
   }
 }
 
-// Node factor pairs (md, me) of a level with nl x nl nodes from the finest
-// level's arrays md, me ([n0][n0], null: 1): coarse node (X, K) of level l takes
-// fine node (s (X+1) - 1, s (K+1) - 1), s = 2^l (injection, the same as taking
-// node (2X+1, 2K+1) of the level above, level by level).
-template <typename T>
-__global__ void k_node_factors(int nl, int n0, int s, const double* __restrict__ md, const double* __restrict__ me,
-                               T* __restrict__ out) {
+// Node factor pairs (md, me) of the finest level from the caller's arrays md,
+// me ([n][n], null: 1).
+__global__ void k_node_factors(int nn, const double* __restrict__ md, const double* __restrict__ me,
+                               double* __restrict__ out) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= nl * nl) return;
-  const int K = i / nl, X = i - K * nl;
-  const size_t fi = (size_t)(s * (K + 1) - 1) * n0 + (size_t)(s * (X + 1) - 1);
-  out[2 * (size_t)i] = md ? (T)md[fi] : T(1);
-  out[2 * (size_t)i + 1] = me ? (T)me[fi] : T(1);
+  if (i >= nn) return;
+  out[2 * (size_t)i] = md ? md[i] : 1.0;
+  out[2 * (size_t)i + 1] = me ? me[i] : 1.0;
+}
+
+// Node factor pairs of a level with nc x nc nodes from those of the level above
+// (nf = 2 nc + 1): coarse node (X, K) takes fine node (2X+1, 2K+1) (full = 0,
+// injection) or the full-weighting average of the 3 x 3 fine nodes around it,
+// weights (1/4)(1/2)^(|dx|+|dk|) (full = 1: the diagonal of R diag(v) P lumped
+// by rows, R = P^T / 4).  Every such fine node is interior.
+__global__ void k_coarsen_factors(int nc, int full, const double* __restrict__ fine, double* __restrict__ coarse) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nc * nc) return;
+  const int nf = 2 * nc + 1;
+  const int K = i / nc, X = i - K * nc;
+  const size_t c = (size_t)(2 * K + 1) * nf + (2 * X + 1);
+  double d = fine[2 * c], e = fine[2 * c + 1];
+  if (full) {
+    d = 0.0;
+    e = 0.0;
+    for (int dk = -1; dk <= 1; ++dk)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const double w = (dx ? 0.5 : 1.0) * (dk ? 0.5 : 1.0) * 0.25;
+        const size_t f = (size_t)((ptrdiff_t)c + (ptrdiff_t)dk * nf + dx);
+        d += w * fine[2 * f];
+        e += w * fine[2 * f + 1];
+      }
+  }
+  coarse[2 * (size_t)i] = d;
+  coarse[2 * (size_t)i + 1] = e;
 }
 
 // flags[0] = 1 if any value is not finite or lies outside [0, 1].

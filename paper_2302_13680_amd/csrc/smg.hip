@@ -434,19 +434,24 @@ int node_den_level(smg_ctx* C, const Level<T>& L) {
 }
 
 // Node factor pairs of every level from the finest level's md, me (device
-// [n][n], null: 1), then what depends on them: the per-node denominators and
-// the coarsest Schur complement (A_j^{-1} must be in place).
-int factors_setup(smg_ctx* C, const double* md, const double* me) {
+// [n][n], null: 1), coarse levels by injection (full = 0) or full weighting
+// (full = 1), FP32 copies for the FP32 cycle; then what depends on them: the
+// per-node denominators and the coarsest Schur complement (A_j^{-1} must be in
+// place).
+int factors_setup(smg_ctx* C, const double* md, const double* me, int full) {
   const bool f32 = C->desc.precision == SMG_F32;
-  for (int l = 0; l < C->nlev; ++l) {
-    const int nl = C->L64[l].n, nb = (nl * nl + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_node_factors<double>, dim3(nb), dim3(kBlock), 0, C->stream, nl, C->desc.n, 1 << l, md, me,
-                       C->L64[l].mk);
-    if (f32)
-      hipLaunchKernelGGL(k_node_factors<float>, dim3(nb), dim3(kBlock), 0, C->stream, nl, C->desc.n, 1 << l, md, me,
-                         C->L32[l].mk);
+  const int n0 = C->desc.n;
+  hipLaunchKernelGGL(k_node_factors, dim3((n0 * n0 + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, n0 * n0,
+                     md, me, C->L64[0].mk);
+  for (int l = 1; l < C->nlev; ++l) {
+    const int nl = C->L64[l].n;
+    hipLaunchKernelGGL(k_coarsen_factors, dim3((nl * nl + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, nl,
+                       full, (const double*)C->L64[l - 1].mk, C->L64[l].mk);
   }
   LAUNCH_CHECK();
+  if (f32)
+    for (int l = 0; l < C->nlev; ++l)
+      TRY((convert<double, float>(C, C->L64[l].mk, C->L32[l].mk, 2 * (size_t)C->L64[l].n * C->L64[l].n)));
   for (int l = 0; l < C->nlev; ++l) {
     TRY(node_den_level<double>(C, C->L64[l]));
     if (f32) TRY(node_den_level<float>(C, C->L32[l]));
@@ -1441,7 +1446,7 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
         return fail(SMG_EHIP);
       mk = C->rr;
     }
-    if (factors_setup(C, mk, mk) != SMG_OK) return fail(SMG_EHIP);
+    if (factors_setup(C, mk, mk, SMG_COARSEN_INJECT) != SMG_OK) return fail(SMG_EHIP);
   }
   int flag = 0;
   if (hipMemcpyAsync(&flag, C->flag, sizeof(int), hipMemcpyDeviceToHost, C->stream) != hipSuccess) return fail(SMG_EHIP);
@@ -1451,8 +1456,8 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
   return SMG_OK;
 }
 
-int smg_set_node_factors(smg_ctx* C, const double* md, const double* me) {
-  if (!C) return SMG_EINVAL;
+int smg_set_node_factors(smg_ctx* C, const double* md, const double* me, int coarsening) {
+  if (!C || (coarsening != SMG_COARSEN_INJECT && coarsening != SMG_COARSEN_FULL)) return SMG_EINVAL;
   const size_t nn = (size_t)C->desc.n * C->desc.n;
   HIP_TRY(hipMemsetAsync(C->flag, 0, sizeof(int), C->stream));
   for (const double* a : {md, me})
@@ -1462,7 +1467,7 @@ int smg_set_node_factors(smg_ctx* C, const double* md, const double* me) {
   TRY(sync(C));
   if (*(const int*)C->host) return SMG_EINVAL;
   set_masked(C, md || me);
-  return factors_setup(C, md, me);
+  return factors_setup(C, md, me, coarsening);
 }
 
 int smg_apply(smg_ctx* C, const double* x, double* Sx) {
@@ -1757,7 +1762,7 @@ int smg_ssn_solve(smg_ctx* C, double* x, const double* f, const smg_ssn_params* 
   // Algorithm 2, first step: the state and adjoint equations for u0 = x's U
   // block, as the system with D_j = 0 (md = 0) whose U row M u = M u0 fixes u
   TRY(fill(C, C->schi, (size_t)nn, 0.0));
-  TRY(factors_setup(C, C->schi, nullptr));
+  TRY(factors_setup(C, C->schi, nullptr, SMG_COARSEN_FULL));
   HIP_TRY(hipMemcpyAsync(C->sr, f, len * sizeof(double), hipMemcpyDeviceToDevice, C->stream));
   hipLaunchKernelGGL(k_scale, dim3((nn + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, nn, xU, p.mass,
                      C->sr + (size_t)N * nn);
@@ -1780,8 +1785,9 @@ int smg_ssn_solve(smg_ctx* C, double* x, const double* f, const smg_ssn_params* 
     if (!std::isfinite(phi)) { rc = SMG_ENONFINITE; break; }
     if (phi <= p.tol) { rc = SMG_OK; break; }
     if (k >= p.maxit) break;
-    // Newton system of the current active set (md = chi, E_j unchanged), solved from zero
-    TRY(factors_setup(C, C->schi, nullptr));
+    // Newton system of the current active set (md = chi, E_j unchanged; coarse
+    // levels by full weighting), solved from zero
+    TRY(factors_setup(C, C->schi, nullptr, SMG_COARSEN_FULL));
     TRY(fill(C, C->sdx, len, 0.0));
     smg_stats ns{};
     const int lr = smg_solve(C, C->sdx, C->sr, p.inner_method, p.inner_rtol, p.inner_maxit, &ns);

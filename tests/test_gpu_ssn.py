@@ -67,17 +67,20 @@ def factors(n, kind, seed):
     return md, me
 
 
+@pytest.mark.parametrize("coarsen", ["injection", "full"])
 @pytest.mark.parametrize("kind", ["d", "de"])
 @pytest.mark.parametrize("n,N", [(15, 3), (31, 8), (63, 16), (31, 100)])
-def test_node_factor_steps(B, O, n, N, kind):
+def test_node_factor_steps(B, O, n, N, kind, coarsen):
     """Residual, Jacobi step, half-sweeps, residual + restriction on every level
-    and the coarsest solve with node factors on D_j (and E_j) set on the device."""
+    and the coarsest solve with node factors on D_j (and E_j) set on the device,
+    coarse levels by either rule."""
     p = problem(n, N, seed=n + N)
     md, me = factors(n, kind, seed=n)
     o = O.Oracle(p)
-    o.set_masks(md, me)
+    o.set_masks(md, me, coarsen=coarsen)
     ctx, _ = B.context_from_problem(p, gmres_restart=0, theta=0.5)
-    ctx.set_node_factors(dev(md), None if me is None else dev(me))
+    ctx.set_node_factors(dev(md), None if me is None else dev(me),
+                         B.SMG_COARSEN_FULL if coarsen == "full" else B.SMG_COARSEN_INJECT)
     rng = np.random.default_rng(n + 1)
     x = rng.standard_normal(o.vlen())
     f = rng.standard_normal(o.vlen())
@@ -121,8 +124,8 @@ def test_node_factor_cycles_and_captured_graphs(B, O, precision):
     tol = 1e-12 if precision == 0 else 2e-5
     cyc = o.vcycle if precision == 0 else o.vcycle32
     for stage, m in enumerate([None, md, None]):
-        o.set_masks(m, None)
-        ctx.set_node_factors(None if m is None else dev(m), None)
+        o.set_masks(m, None, coarsen="full")
+        ctx.set_node_factors(None if m is None else dev(m), None, B.SMG_COARSEN_FULL)
         x_o = np.zeros(o.vlen())
         xd = torch.zeros(o.vlen(), dtype=torch.float64, device="cuda")
         for k in range(3):
@@ -142,6 +145,8 @@ def test_set_node_factors_rejects_values_outside_unit_interval(B):
         assert e.value.code == -1
         with pytest.raises(B.SmgError):
             ctx.set_node_factors(None, dev(md))
+    with pytest.raises(B.SmgError):
+        ctx.set_node_factors(None, None, 2)
 
 
 def ssn_prm(B, p, beta, a, b, **kw):

@@ -243,3 +243,44 @@ def test_invalid_settings_raise():
     q = inputs.make_problem(7, 2, 1e-3, control_region=(0.25, 0.75, 0.25, 0.75))
     with pytest.raises(ValueError):
         ssn.ssn_solve(q, 1e-2, -1.0, 1.0)
+
+
+def test_node_factor_coarsening_rules():
+    """Injection takes fine node (2X+1, 2K+1); full weighting averages the 3 x 3
+    fine nodes with weights (1/4, 1/2, 1/4) per direction: constants are kept
+    and x^2 + y^2 becomes x^2 + y^2 + h^2 (h/2 per direction, h the fine spacing),
+    level by level."""
+    p = problem(n=31, N=2)
+    o = Oracle(p)
+    n = p.n
+    t = (np.arange(n) + 1.0) / (n + 1)
+    X, Y = np.meshgrid(t, t)
+    q = X ** 2 + Y ** 2
+    o.set_masks(np.full((n, n), 0.375), q, coarsen="full")
+    hf = 1.0 / (n + 1)
+    expect = q
+    for l in range(1, o.nlev):
+        nl = o.levels_n[l]
+        np.testing.assert_array_equal(o.level_factor(l, "d"), np.full((nl, nl), 0.375))
+        tc = (np.arange(nl) + 1.0) / (nl + 1)
+        Xc, Yc = np.meshgrid(tc, tc)
+        h = hf * 2 ** (l - 1)
+        expect = expect[1::2, 1::2] + h * h     # the fine level's quadratic plus h^2
+        np.testing.assert_allclose(o.level_factor(l, "e"), expect, rtol=0, atol=1e-14)
+        if l == 1:   # coarse nodes sit on fine nodes: x_c^2 + y_c^2 + h^2
+            np.testing.assert_allclose(expect, Xc ** 2 + Yc ** 2 + hf * hf, rtol=0, atol=1e-15)
+    o.set_masks(q, None, coarsen="injection")
+    for l in range(1, o.nlev):
+        np.testing.assert_array_equal(o.level_factor(l, "d"), o.level_factor(l - 1, "d")[1::2, 1::2])
+        assert np.all(o.level_factor(l, "e") == 1.0)
+
+
+def test_multigrid_inner_counts_are_mesh_independent():
+    """With the active set carried to coarse levels by full weighting, the
+    V-cycles per Newton step stay bounded as the grid is refined."""
+    means = []
+    for n in (31, 63):
+        p = problem(n=n, N=4, nu=1e-4)
+        res = ssn.ssn_solve(p, 1e-2, -50.0, 50.0, linear="vcycle")
+        means.append(np.mean(res["inner"]))
+    assert max(means) <= 16 and abs(means[1] - means[0]) <= 3, means
