@@ -163,8 +163,15 @@ __global__ __launch_bounds__(kBlock) void k_coarse_schur_invert(int m, int N, co
   __shared__ double A[kMaxCoarse * kMaxCoarse];
   __shared__ double col[kMaxCoarse];
   for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+    // summed in sample order; 16 loads in flight per round trip
     double s = (idx / m == idx % m) ? g : 0.0;
-    for (int j = 0; j < N; ++j) s += terms[(size_t)j * m * m + idx];
+    for (int q0 = 0; q0 < N; q0 += 16) {
+      double t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) t[u] = terms[(size_t)(q0 + u < N ? q0 + u : N - 1) * m * m + idx];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += q0 + u < N ? t[u] : 0.0;
+    }
     A[idx] = s;
   }
   lds_invert_spd(A, col, m);
