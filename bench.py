@@ -288,27 +288,48 @@ def ssn_section(dev, n, N, args):
     return out
 
 
-def ssn_paper_setting(dev):
-    """The paper's L1 table setting (N_h = 705 on its L-shape, three levels, 5^3
-    collocation nodes, sigma^2 = 0.5, nu 1e-4, beta 1e-2, |u| <= 50, collective
-    Jacobi theta 1/2) on this build's 31x31 square grid: Newton iterations and
-    mean inner iterations per Newton step, beside the printed 5 | 22.6 | 14.2."""
+def paper_tables(dev):
+    """The settings of the paper's iteration-count tables on this build's 31x31
+    square grid (three levels): the Gaussian-covariance field of eq. log_normal
+    (sigma^2 = 0.5, L^2 = 0.5, M = 3) on 5^3 Gauss-Hermite collocation nodes,
+    y_d = exp(y^2) sin(2 pi x) sin(2 pi y), no source, damped collective Jacobi
+    (theta 1/2) V(2,2), tolerance 1e-9.  Counts beside the printed ones (the
+    paper: P1 elements; its distributed-control table is on an L-shape)."""
     import numpy as np
     import torch
     from paper_2302_13680_amd import binding, inputs
-    p = inputs.collocation_problem(31, 5, 1e-4, M=3, sigma=float(np.sqrt(0.5)), decay=True,
-                                   yd=inputs.paper_target(31), f=0.0)
+    kw = dict(M=3, sigma=float(np.sqrt(0.5)), decay=True, yd=inputs.paper_target(31), f=0.0, field="gaussian",
+              corr_len2=0.5)
+    printed = {"distributed": {1e-2: [18, 11], 1e-4: [19, 13], 1e-6: [19, 15], 1e-8: [19, 15]},
+               "local": {1e-2: [17, 11], 1e-4: [20, 13], 1e-6: [26, 16], 1e-8: [26, 18]}}
+    out = {"grid": "31x31, levels 31/15/7, N = 125", "field": "Gaussian covariance, sigma^2 0.5, L^2 0.5, M 3",
+           "smoother": "collective Jacobi theta 1/2, V(2,2)", "tol": 1e-9}
+    for case, region in (("distributed", None), ("local", (0.25, 0.75, 0.25, 0.75))):
+        rows = []
+        for nu in (1e-2, 1e-4, 1e-6, 1e-8):
+            p = inputs.collocation_problem(31, 5, nu, control_region=region, **kw)
+            ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5,
+                                                  flags=binding.SMG_FLAG_JACOBI)
+            x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
+            _, sv = timed_solve(ctx, x, f, binding.SMG_VCYCLE, 1e-9)
+            _, sg = timed_solve(ctx, x, f, binding.SMG_GMRES, 1e-9)
+            rows.append({"nu": nu, "vcycle": sv["iterations"], "gmres": sg["iterations"],
+                         "paper_vcycle_gmres": printed[case][nu]})
+            ctx.close()
+        out[case] = rows
+    p = inputs.collocation_problem(31, 5, 1e-4, **kw)
     ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5, flags=binding.SMG_FLAG_JACOBI,
                                           ssn=True)
     x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
-    out = {"n": 31, "N": p.N, "levels": list(ctx.levels_n), "paper_printed_newton_vcycle_gmres": [5, 22.6, 14.2]}
-    for name, method in (("gmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
+    l1 = {"nu": 1e-4, "beta": 1e-2, "box": [-50.0, 50.0], "paper_newton_vcycle_gmres": [5, 22.6, 14.2]}
+    for name, method in (("gmres", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
         prm = binding.ssn_params(1e-4, 1e-2, -50.0, 50.0, (1.0 / 32) ** 2, inner_method=method)
         _, rc, st = ssn_run(ctx, x, f, prm)
-        out[name + "_newton_iterations"] = st["iterations"]
-        out[name + "_mean_inner"] = round(float(np.mean(st["inner"])), 2) if st["inner"] else 0.0
-        out[name + "_converged"] = rc == binding.SMG_OK
+        l1[name + "_newton"] = st["iterations"]
+        l1[name + "_mean_inner"] = round(float(np.mean(st["inner"])), 2) if st["inner"] else 0.0
+        l1[name + "_converged"] = rc == binding.SMG_OK
     ctx.close()
+    out["l1_semismooth_newton"] = l1
     return out
 
 
@@ -436,29 +457,12 @@ def main():
         lc[name + "_iterations"] = stl["iterations"]
     clc.close()
     del clc, flc, xlc
-    # the configuration of the paper's local-control table (31x31 interior nodes, three
-    # levels, 5^3 Gauss-Hermite nodes, nu 1e-4, collective Jacobi theta 1/2, V(2,2),
-    # tolerance 1e-9; y_d = exp(y^2) sin(2 pi x) sin(2 pi y), no source) with this
-    # build's finite differences and analytic coefficient expansion
-    yd31 = inputs.paper_target(31)
-    pt = inputs.collocation_problem(31, 5, 1e-4, M=3, sigma=float(np.sqrt(0.5)), decay=True, yd=yd31, f=0.0,
-                                    control_region=(0.25, 0.75, 0.25, 0.75))
-    ct, ft = binding.context_from_problem(pt, device=dev, gmres_restart=30, theta=0.5,
-                                          flags=binding.SMG_FLAG_JACOBI)
-    xt = torch.zeros(pt.dof, dtype=torch.float64, device=dev)
-    _, st_v = timed_solve(ct, xt, ft, binding.SMG_VCYCLE, 1e-9)
-    _, st_g = timed_solve(ct, xt, ft, binding.SMG_GMRES, 1e-9)
-    lc["paper_local_control_setting"] = {
-        "n": 31, "N": pt.N, "levels": list(ct.levels_n), "vcycle_iterations": st_v["iterations"],
-        "gmres_iterations": st_g["iterations"], "paper_printed_vcycle_gmres": [20, 13]}
-    ct.close()
-    del ct, ft, xt
 
     # ---------------- semismooth Newton for the L1-penalized, box-constrained control
     # (Section 5, Algorithm 2): nu 1e-4, beta 1e-2, -50 <= u <= 50, phi <= 1e-9,
     # every Newton system to 1e-11; the paper's target, no source
     ssn = ssn_section(dev, n, N, args)
-    ssn["paper_l1_setting"] = ssn_paper_setting(dev)
+    paper = paper_tables(dev)
 
     # ---------------- roofline of the dominant kernel: finest-level half-sweep
     xs = torch.zeros(dof, dtype=torch.float64, device=dev)
@@ -548,6 +552,7 @@ def main():
         "stochastic_collocation": sc,
         "local_control": lc,
         "semismooth_newton": ssn,
+        "paper_settings": paper,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

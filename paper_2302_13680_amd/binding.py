@@ -94,6 +94,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_2302_13680_amd.build.build()")
+    # The PyTorch ROCm wheel carries its own HIP runtime.  Loaded first, it is
+    # the runtime the library binds to, so the streams and device pointers torch
+    # hands over belong to the runtime the library calls; loaded after the
+    # library, a second runtime would come in beside the system one and every
+    # call on torch's memory would fail.
+    import torch  # noqa: F401
     L = C.CDLL(path)
     vp, i, d = C.c_void_p, C.c_int, C.c_double
     L.smg_workspace_bytes.restype = C.c_size_t

@@ -112,6 +112,46 @@ def log_kappa(xi: np.ndarray, amps: np.ndarray, X: np.ndarray, Y: np.ndarray) ->
     return out
 
 
+def gaussian_kl(M: int, corr_len2: float, nq: int = 80):
+    """The M largest eigenpairs (lambda_m, b_m) of the covariance operator
+    (T f)(x) = int_D exp(-|x - y|^2 / L^2) f(y) dy on the unit square D (eq.
+    log_normal with unit variance: the paper's pairs are (b_m, sigma^2 lambda_m)).
+
+    The kernel is a product of 1D kernels exp(-(s - t)^2 / L^2), so the 2D pairs
+    are products mu_a mu_b, phi_a(x) phi_b(y) of the 1D ones, computed by the
+    Nystrom method with nq Gauss-Legendre points on [0, 1] (the symmetric form
+    W^1/2 K W^1/2) and evaluated anywhere by Nystrom interpolation.  Signs: every
+    phi_a is positive at the first quadrature point; equal lambda are ordered by
+    (a, b).  Returns a dict with lam (M,), the 1D index pairs, and what
+    ``kl_modes`` needs."""
+    s, w = np.polynomial.legendre.leggauss(nq)
+    s = 0.5 * (s + 1.0)
+    w = 0.5 * w
+    K = np.exp(-(s[:, None] - s[None, :]) ** 2 / corr_len2)
+    sw = np.sqrt(w)
+    mu, V = np.linalg.eigh(sw[:, None] * K * sw[None, :])
+    order = np.argsort(-mu, kind="stable")
+    mu, V = mu[order], V[:, order]
+    phi = V / sw[:, None]                       # phi_a at the quadrature points
+    phi *= np.where(phi[0] < 0, -1.0, 1.0)[None, :]
+    cand = sorted(((-(mu[a] * mu[b]), a, b) for a in range(min(nq, M + 1)) for b in range(min(nq, M + 1))))
+    pairs = [(a, b) for _, a, b in cand[:M]]
+    lam = np.array([mu[a] * mu[b] for a, b in pairs])
+    return dict(lam=lam, pairs=pairs, mu=mu, s=s, w=w, phi=phi, corr_len2=float(corr_len2),
+                variance_kept=float(lam.sum()))
+
+
+def kl_modes(kl, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """b_m(X, Y) for every mode of ``gaussian_kl``: shape (M,) + X.shape."""
+    s, w, phi, mu, L2 = kl["s"], kl["w"], kl["phi"], kl["mu"], kl["corr_len2"]
+
+    def phi_at(a, t):   # Nystrom interpolation of the 1D eigenfunction a
+        t = np.asarray(t, dtype=np.float64)
+        k = np.exp(-(t[..., None] - s) ** 2 / L2)
+        return (k @ (w * phi[:, a])) / mu[a]
+    return np.stack([phi_at(a, X) * phi_at(b, Y) for a, b in kl["pairs"]])
+
+
 def stochastic_collocation(M: int, q: int):
     """Tensor Gauss-Hermite rule for M independent standard normal variables with
     q points per variable: nodes xi (q^M, M) and weights zeta (q^M,) summing to 1
@@ -130,12 +170,17 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
                  decay: bool = False, seed: int = 0, yd: str | np.ndarray = "sin",
                  f: float = 1.0, xi: np.ndarray | None = None,
                  kappa_const: float | None = None, weights: np.ndarray | None = None,
-                 control_region: tuple | None = None) -> Problem:
+                 control_region: tuple | None = None, field: str = "sine",
+                 corr_len2: float = 0.5) -> Problem:
     """Build one seeded instance.
 
     ``decay=False`` gives amplitudes a_m = sigma (the 31x31, N=8 case, four modes
     of amplitude 0.5); ``decay=True`` gives a_m = sigma/m.  ``kappa_const`` replaces
-    the random field by a constant (used by closed-form checks).  ``weights`` are
+    the random field by a constant (used by closed-form checks).  ``field =
+    "gaussian"`` takes the paper's expansion instead (eq. log_normal):
+    log kappa_j = sigma sum_m sqrt(lambda_m) b_m xi_{j,m} with the eigenpairs of
+    the Gaussian covariance of correlation length^2 ``corr_len2`` on the unit
+    square (``gaussian_kl``); sigma is then the field's standard deviation.  ``weights`` are
     the quadrature weights zeta_j of the samples (default 1/N, Monte Carlo).
     ``control_region = (x0, x1, y0, y1)`` restricts the control to the nodes in
     the closed rectangle [x0, x1] x [y0, y1] (local control; the mask of the
@@ -151,6 +196,15 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
     if kappa_const is not None:
         kx = np.full((N, n, n + 1), float(kappa_const))
         ky = np.full((N, n + 1, n), float(kappa_const))
+    elif field == "gaussian":
+        kl = gaussian_kl(xi.shape[1], corr_len2)
+        coef = sigma * np.sqrt(kl["lam"])[None, :] * xi          # (N, M)
+        FX, KY_ = np.meshgrid(faces, nodes)
+        kx = np.exp(np.tensordot(coef, kl_modes(kl, FX, KY_), axes=1))
+        XN, GF = np.meshgrid(nodes, faces)
+        ky = np.exp(np.tensordot(coef, kl_modes(kl, XN, GF), axes=1))
+    elif field != "sine":
+        raise ValueError(field)
     else:
         FX, KY_ = np.meshgrid(faces, nodes)          # kx: rows k (y = nodes), faces f (x = faces)
         kx = np.exp(log_kappa(xi, amps, FX, KY_))
@@ -184,7 +238,7 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
                 .astype(np.float64))
     return Problem(n=n, N=N, nu=nu, kx=np.ascontiguousarray(kx), ky=np.ascontiguousarray(ky),
                    c=c, d=d, e=e, g=g, fY=fY, fU=fU, fP=fP, xi=xi, yd=ydv, ctrl=ctrl,
-                   meta=dict(M=xi.shape[1], sigma=sigma, decay=decay, seed=seed, f=f,
+                   meta=dict(M=xi.shape[1], sigma=sigma, decay=decay, seed=seed, f=f, field=field,
                              quadrature="mc" if weights is None else "weights"))
 
 
