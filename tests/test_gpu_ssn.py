@@ -279,3 +279,46 @@ def test_ssn_rejects_bad_use(B):
             ctx2.ssn_solve(x, f2, bad)
     with pytest.raises(B.SmgError):
         B.context_from_problem(p, gmres_restart=30, ssn=True, precision=1)
+
+
+@pytest.mark.parametrize("n,N,a,b,beta,u0s", [
+    (7, 1, -50.0, 50.0, 1e-2, 0.0),          # one level (the coarsest solve is the whole cycle), one sample
+    (15, 2, -np.inf, 20.0, 5e-3, 3.0),       # upper bound only, nonzero start
+    (31, 5, -10.0, np.inf, 0.0, -1.0),       # lower bound only, no L^1 term
+])
+def test_ssn_edge_cases(B, S, n, N, a, b, beta, u0s):
+    p = problem(n, N, nu=1e-3, seed=n)
+    u0 = u0s * np.random.default_rng(n).standard_normal(n * n)
+    ref, rc, st, xg = run_pair(B, S, p, beta, a, b, B.SMG_GMRES, u0=u0)
+    assert rc == B.SMG_OK and ref["converged"]
+    assert st["iterations"] == ref["iterations"]
+    nn = n * n
+    ug = xg[N * nn:(N + 1) * nn]
+    assert np.abs(ug - ref["u"]).max() <= 1e-8 * max(np.abs(ref["u"]).max(), 1.0)
+    assert ug.min() >= a - 1e-9 and ug.max() <= b + 1e-9
+
+
+def test_ssn_maxit_zero_reports_the_initial_merit(B, S):
+    p = problem(15, 3)
+    nn = p.n * p.n
+    ctx, f = B.context_from_problem(p, gmres_restart=30, ssn=True)
+    x = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    prm = ssn_prm(B, p, 1e-2, -50.0, 50.0, maxit=0)
+    rc, st = ctx.ssn_solve(x, f, prm)
+    assert rc == B.SMG_NOT_CONVERGED and st["iterations"] == 0 and len(st["phi"]) == 1
+    x0 = S.initial_state(p, np.zeros(nn))
+    w0 = S.expected_p(x0, p.n, p.N)
+    phi0 = S.merit(S.F_map(np.zeros(nn), w0, p.nu, 1e-2, -50.0, 50.0), 1.0 / (p.n + 1))
+    assert abs(st["phi"][0] - phi0) <= 1e-9 * phi0
+    # the state and adjoint of u0 = 0 left in x
+    assert rel(node_to_paper(host(x), p.n, p.N), x0) <= 1e-9
+
+
+def test_ssn_gauss_seidel_vcycle_solve(B, S):
+    """The red-black Gauss-Seidel V-cycle as the inner solver (stationary)."""
+    p = problem(63, 8)
+    ref, rc, st, xg = run_pair(B, S, p, 1e-2, -50.0, 50.0, B.SMG_VCYCLE)
+    assert rc == B.SMG_OK
+    assert st["iterations"] == ref["iterations"]
+    assert all(abs(x - y) <= 1 for x, y in zip(st["inner"], ref["inner"]))
+    assert max(st["inner"]) <= 16
