@@ -108,7 +108,7 @@ typedef struct {
                                  Gauss-Seidel sweeps; theta is the damping and pre / post count
                                  Jacobi steps.  Not accepted by the batched solver. */
 #define SMG_FLAG_SSN 8        /* reserve the semismooth Newton solver's buffers in the workspace
-                                 (two vectors and six node-sized arrays; SMG_F64 only) */
+                                 (two vectors and six node-sized arrays) */
 
 typedef struct {
   const double *kx;   /* device, [n][n+1][N] */
@@ -285,12 +285,14 @@ int smg_set_node_factors(smg_ctx *ctx, const double *md, const double *me, int c
  * eq. l1_OCP), solved by the globalized semismooth Newton method of
  * Algorithm 2 with the collective multigrid for every Newton system.
  *
- * The context must have SMG_FLAG_SSN and SMG_F64, and hold the Newton
+ * The context must have SMG_FLAG_SSN and hold the Newton
  * system's blocks (eq. full_space_optimality_systeMemismooth2 with the
  * adjoint rescaled by the sample weights, p~_j = zeta_j p_j): C_j = zeta_j M,
  * E_j = -M and faces as in the linear-quadratic problem, and the U row as
  * printed, G = M and D_j = -M / nu.  E[p] = sum_j zeta_j p_j is then the sum
- * of the P block's samples at a node.  Vectors in the node layout. */
+ * of the P block's samples at a node.  Vectors in the node layout, FP64; in
+ * SMG_F32 mode every linear solve is FP64 refinement around FP32 cycles (see
+ * smg_solve), which reaches the same FP64 tolerances. */
 
 /* Per node of x (device, finest level): w = E[p] (device [n][n]); when F and
  * chi are given (both or neither) also F(u) of the discrete optimality

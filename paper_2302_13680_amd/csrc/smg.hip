@@ -234,7 +234,6 @@ bool desc_valid(const smg_desc& d, std::string* why) {
   if (d.precision != SMG_F64 && d.precision != SMG_F32) return fail("precision must be SMG_F64 or SMG_F32");
   if (d.gmres_restart < 0 || d.gmres_restart > kMaxBasis - 1) return fail("gmres_restart must be in [0, 31]");
   if (d.flags & ~(SMG_FLAG_EAGER | SMG_FLAG_UNFUSED | SMG_FLAG_JACOBI | SMG_FLAG_SSN)) return fail("unknown flag bits");
-  if ((d.flags & SMG_FLAG_SSN) && d.precision != SMG_F64) return fail("SMG_FLAG_SSN needs SMG_F64");
   if (d.strip < 0 || (d.strip & 1)) return fail("strip must be 0 or a positive even number");
   return true;
 }

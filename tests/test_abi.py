@@ -49,7 +49,6 @@ def test_workspace_bytes_validation(lib):
                 Desc(255, 64, 7, 2, 2, 1.0, 2, 30, 0),   # unknown precision
                 Desc(255, 64, 7, 2, 2, 1.0, 0, 40, 0),   # restart too long
                 Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 16),  # unknown flags
-                Desc(255, 64, 7, 2, 2, 1.0, 1, 30, 8),   # semismooth Newton buffers with FP32
                 Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 0, 33),   # odd strip width
                 Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 0, -2)]:  # negative strip width
         assert lib.smg_workspace_bytes(C.byref(bad)) == 0

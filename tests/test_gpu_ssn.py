@@ -277,8 +277,6 @@ def test_ssn_rejects_bad_use(B):
                 B.ssn_params(-1e-4, 1e-2, -1.0, 1.0, 1.0 / 256), ssn_prm(B, p, 1e-2, -1.0, 1.0, sigma=1.5)):
         with pytest.raises(B.SmgError):
             ctx2.ssn_solve(x, f2, bad)
-    with pytest.raises(B.SmgError):
-        B.context_from_problem(p, gmres_restart=30, ssn=True, precision=1)
 
 
 @pytest.mark.parametrize("n,N,a,b,beta,u0s", [
@@ -322,3 +320,20 @@ def test_ssn_gauss_seidel_vcycle_solve(B, S):
     assert st["iterations"] == ref["iterations"]
     assert all(abs(x - y) <= 1 for x, y in zip(st["inner"], ref["inner"]))
     assert max(st["inner"]) <= 16
+
+
+@pytest.mark.parametrize("method", [1, 0])
+def test_ssn_solve_with_fp32_cycles(B, S, method):
+    """SMG_F32: every Newton system by FP64 refinement around FP32 cycles; the
+    same Newton iterations and solution as the FP64 oracle."""
+    n, N = 63, 16
+    p = problem(n, N)
+    nn = n * n
+    ref = S.ssn_solve(p, 1e-2, -50.0, 50.0, linear="gmres", inner_tol=1e-11)
+    ctx, f = B.context_from_problem(p, gmres_restart=30, ssn=True, precision=1)
+    x = torch.zeros((2 * N + 1) * nn, dtype=torch.float64, device="cuda")
+    rc, st = ctx.ssn_solve(x, f, ssn_prm(B, p, 1e-2, -50.0, 50.0, inner_method=method))
+    assert rc == B.SMG_OK
+    assert st["iterations"] == ref["iterations"]
+    ug = node_to_paper(host(x), n, N)[N * nn:(N + 1) * nn]
+    assert np.abs(ug - ref["u"]).max() <= 1e-8 * np.abs(ref["u"]).max()
