@@ -337,3 +337,25 @@ def test_ssn_solve_with_fp32_cycles(B, S, method):
     assert st["iterations"] == ref["iterations"]
     ug = node_to_paper(host(x), n, N)[N * nn:(N + 1) * nn]
     assert np.abs(ug - ref["u"]).max() <= 1e-8 * np.abs(ref["u"]).max()
+
+
+def test_ssn_full_size_properties(B, S, O):
+    """255x255, N=64 (the benchmark's instance): the GPU solution satisfies the
+    state and adjoint equations in the oracle's operator (Y and P rows of the
+    linear-quadratic system) and the oracle's F at the GPU's u and E[p] has a
+    merit below the tolerance; the control respects the bounds."""
+    n, N = 255, 64
+    p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=1, yd=inputs.paper_target(n), f=0.0)
+    nn = n * n
+    ctx, f = B.context_from_problem(p, gmres_restart=30, ssn=True)
+    x = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    rc, st = ctx.ssn_solve(x, f, ssn_prm(B, p, 1e-2, -50.0, 50.0))
+    assert rc == B.SMG_OK and st["phi_final"] <= 1e-9
+    xg = node_to_paper(host(x), n, N)
+    r = O.Oracle(p).residual(xg, p.rhs_paper())
+    fn = np.linalg.norm(p.rhs_paper())
+    assert np.linalg.norm(r[:N * nn]) <= 1e-9 * fn and np.linalg.norm(r[(N + 1) * nn:]) <= 1e-9 * fn
+    u = xg[N * nn:(N + 1) * nn]
+    Fv = S.F_map(u, S.expected_p(xg, n, N), p.nu, 1e-2, -50.0, 50.0)
+    assert S.merit(Fv, 1.0 / (n + 1)) <= 1e-8
+    assert u.min() >= -50.0 - 1e-9 and u.max() <= 50.0 + 1e-9
