@@ -322,11 +322,12 @@ def ssn_section(dev, n, N, args):
 
 def paper_tables(dev):
     """The settings of the paper's iteration-count tables on this build's 31x31
-    square grid (three levels): the Gaussian-covariance field of eq. log_normal
+    grid (three levels): the Gaussian-covariance field of eq. log_normal
     (sigma^2 = 0.5, L^2 = 0.5, M = 3) on 5^3 Gauss-Hermite collocation nodes,
     y_d = exp(y^2) sin(2 pi x) sin(2 pi y), no source, damped collective Jacobi
-    (theta 1/2) V(2,2), tolerance 1e-9.  Counts beside the printed ones (the
-    paper: P1 elements; its distributed-control table is on an L-shape)."""
+    (theta 1/2) V(2,2), tolerance 1e-9; distributed control and the L^1 problem
+    on the L-shape (N_h = 705, as printed), local control on the square
+    (N_h = 961).  Counts beside the printed ones (the paper: P1 elements)."""
     import numpy as np
     import torch
     from paper_2302_13680_amd import binding, inputs
@@ -336,24 +337,25 @@ def paper_tables(dev):
                "local": {1e-2: [17, 11], 1e-4: [20, 13], 1e-6: [26, 16], 1e-8: [26, 18]}}
     out = {"grid": "31x31, levels 31/15/7, N = 125", "field": "Gaussian covariance, sigma^2 0.5, L^2 0.5, M 3",
            "smoother": "collective Jacobi theta 1/2, V(2,2)", "tol": 1e-9}
-    for case, region in (("distributed", None), ("local", (0.25, 0.75, 0.25, 0.75))):
+    for case, region, dom in (("distributed", None, "lshape"), ("local", (0.25, 0.75, 0.25, 0.75), "square")):
         rows = []
         for nu in (1e-2, 1e-4, 1e-6, 1e-8):
-            p = inputs.collocation_problem(31, 5, nu, control_region=region, **kw)
+            p = inputs.collocation_problem(31, 5, nu, control_region=region, domain=dom, **kw)
             ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5,
                                                   flags=binding.SMG_FLAG_JACOBI)
             x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
             _, sv = timed_solve(ctx, x, f, binding.SMG_VCYCLE, 1e-9)
             _, sg = timed_solve(ctx, x, f, binding.SMG_GMRES, 1e-9)
             rows.append({"nu": nu, "vcycle": sv["iterations"], "gmres": sg["iterations"],
-                         "paper_vcycle_gmres": printed[case][nu]})
+                         "paper_vcycle_gmres": printed[case][nu], "nodes": int(p.domain.sum()) if dom == "lshape" else 961})
             ctx.close()
         out[case] = rows
-    p = inputs.collocation_problem(31, 5, 1e-4, **kw)
+    p = inputs.collocation_problem(31, 5, 1e-4, domain="lshape", **kw)
     ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5, flags=binding.SMG_FLAG_JACOBI,
                                           ssn=True)
     x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
-    l1 = {"nu": 1e-4, "beta": 1e-2, "box": [-50.0, 50.0], "paper_newton_vcycle_gmres": [5, 22.6, 14.2]}
+    l1 = {"nu": 1e-4, "beta": 1e-2, "box": [-50.0, 50.0], "domain": "L-shape, 705 nodes",
+          "paper_newton_vcycle_gmres": [5, 22.6, 14.2]}
     for name, method in (("gmres", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
         prm = binding.ssn_params(1e-4, 1e-2, -50.0, 50.0, (1.0 / 32) ** 2, inner_method=method)
         _, rc, st = ssn_run(ctx, x, f, prm)

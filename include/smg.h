@@ -123,6 +123,17 @@ typedef struct {
                          control (eq. solution_reduced_system2) and, with f_U = 0 there,
                          u_i = 0.  Coarse levels take the mask by injection.  NULL: the
                          control acts everywhere.  Values outside [0, 1]: SMG_EINVAL. */
+  const double *domain; /* host, [n][n] or NULL: 1 inside the domain, 0 outside (e.g. the
+                         paper's L-shape (0,1)^2 minus [1/2,1)^2: the nodes with x, y >= 1/2
+                         removed).  Nodes outside are homogeneous Dirichlet nodes: their
+                         rows of S are zero, every kernel keeps x there at zero and reads
+                         those zeros as the Dirichlet values of the nodes inside, and the
+                         solvers (smg_vcycle, smg_gmres_precond, smg_solve, smg_ssn_solve)
+                         zero x there on entry; the step entry points expect x zero there.
+                         Coarse levels by injection: the domain's edges must lie on grid
+                         lines of every level (true for the L-shape).  Values other than 0
+                         and 1: SMG_EINVAL.  Not accepted by the batched solver.  NULL:
+                         the whole square. */
 } smg_blocks;
 
 typedef struct {

@@ -45,9 +45,12 @@ def _load():
     L.or_set_smoother.argtypes = [vp, C.c_int]
     L.or_set_control.restype = C.c_int
     L.or_set_control.argtypes = [vp, _dp]
+    L.or_set_domain.restype = C.c_int
+    L.or_set_domain.argtypes = [vp, _dp]
     L.or_set_masks.restype = C.c_int
     L.or_set_masks.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_int]
     L.or_level_factor.argtypes = [vp, C.c_int, C.c_int, _dp]
+    L.or_level_domain.argtypes = [vp, C.c_int, _dp]
     L.or_create.restype = vp
     L.or_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                             _dp, _dp, _dp, _dp, _dp, C.c_double]
@@ -147,6 +150,9 @@ class Oracle:
         if not self.ctx:
             raise ValueError("oracle: invalid grid size or singular coarsest block")
         L.or_set_smoother(self.ctx, 1 if smoother == "jacobi" else 0)
+        if getattr(prob, "domain", None) is not None:
+            if L.or_set_domain(self.ctx, _f64(prob.domain)) != 0:
+                raise ValueError("oracle: singular coarsest block with this domain")
         if getattr(prob, "ctrl", None) is not None:
             if L.or_set_control(self.ctx, _f64(prob.ctrl)) != 0:
                 raise ValueError("oracle: singular coarsest block with this control mask")
@@ -163,6 +169,13 @@ class Oracle:
         ptr = [None if m is None else m.ctypes.data for m in keep]
         if _load().or_set_masks(self.ctx, ptr[0], ptr[1], 1 if coarsen == "full" else 0) != 0:
             raise ValueError("oracle: singular coarsest block with these node factors")
+
+    def level_domain(self, l: int):
+        """The domain of level l, [n_l][n_l] (1 inside, 0 outside)."""
+        n = self.levels_n[l]
+        out = np.zeros(n * n)
+        _load().or_level_domain(self.ctx, l, out)
+        return out.reshape(n, n)
 
     def level_factor(self, l: int, which: str = "d"):
         """The node factor md (which="d") or me ("e") of level l, [n_l][n_l]."""

@@ -20,18 +20,35 @@ typedef struct {
                                 of D_j and E_j are md_i d_j and me_i e_j.  Local control:
                                 md = me = the control mask; the semismooth Newton system
                                 of Section 5: md = the active-set indicator, me = 1 */
+  const REAL *dom;           /* [n][n] domain (NULL: the whole square): 0 marks a node
+                                outside it (the L-shape's removed quadrant), a Dirichlet
+                                node held at 0 whose rows of S are zero */
 } SFX(or_lvl);
 
-/* node factors of D_j and E_j at node i */
-static inline REAL SFX(or_mask_d)(const SFX(or_lvl) *L, size_t i) { return L->md ? L->md[i] : (REAL)1; }
-static inline REAL SFX(or_mask_e)(const SFX(or_lvl) *L, size_t i) { return L->me ? L->me[i] : (REAL)1; }
+/* node i inside the domain */
+static inline int SFX(or_live)(const SFX(or_lvl) *L, size_t i) { return !L->dom || L->dom[i] != (REAL)0; }
+
+/* node factors of D_j and E_j at node i (0 outside the domain) */
+static inline REAL SFX(or_mask_d)(const SFX(or_lvl) *L, size_t i) {
+  return SFX(or_live)(L, i) ? (L->md ? L->md[i] : (REAL)1) : (REAL)0;
+}
+static inline REAL SFX(or_mask_e)(const SFX(or_lvl) *L, size_t i) {
+  return SFX(or_live)(L, i) ? (L->me ? L->me[i] : (REAL)1) : (REAL)0;
+}
 
 #define OR_KX(L, j, k, f) ((L)->kx[((size_t)(j) * (L)->n + (k)) * ((L)->n + 1) + (f)])
 #define OR_KY(L, j, gg, x) ((L)->ky[((size_t)(j) * ((L)->n + 1) + (gg)) * (L)->n + (x)])
 
-/* value of grid function v (an n x n plane) at (x, k), zero outside */
+/* value of grid function v (an n x n plane) at (x, k), zero outside the grid */
 static inline REAL SFX(or_at)(const REAL *v, int n, int x, int k) {
   if (x < 0 || x >= n || k < 0 || k >= n) return (REAL)0;
+  return v[(size_t)k * n + x];
+}
+
+/* the same, also zero outside the domain (homogeneous Dirichlet there) */
+static inline REAL SFX(or_atd)(const SFX(or_lvl) *L, const REAL *v, int x, int k) {
+  int n = L->n;
+  if (x < 0 || x >= n || k < 0 || k >= n || !SFX(or_live)(L, (size_t)k * n + x)) return (REAL)0;
   return v[(size_t)k * n + x];
 }
 
@@ -42,9 +59,10 @@ static REAL SFX(or_stencil)(const SFX(or_lvl) *L, int j, const REAL *v, int x, i
   REAL kw = OR_KX(L, j, k, x), ke = OR_KX(L, j, k, x + 1);
   REAL ks = OR_KY(L, j, k, x), kn = OR_KY(L, j, k + 1, x);
   REAL diag = kw + ke + ks + kn;
-  return diag * SFX(or_at)(v, n, x, k)
-       - kw * SFX(or_at)(v, n, x - 1, k) - ke * SFX(or_at)(v, n, x + 1, k)
-       - ks * SFX(or_at)(v, n, x, k - 1) - kn * SFX(or_at)(v, n, x, k + 1);
+  (void)n;
+  return diag * SFX(or_atd)(L, v, x, k)
+       - kw * SFX(or_atd)(L, v, x - 1, k) - ke * SFX(or_atd)(L, v, x + 1, k)
+       - ks * SFX(or_atd)(L, v, x, k - 1) - kn * SFX(or_atd)(L, v, x, k + 1);
 }
 
 /* out = S x, block rows as in eq. (2):
@@ -65,11 +83,13 @@ static void SFX(or_apply)(const SFX(or_lvl) *L, const REAL *xv, REAL *out) {
     for (int k = 0; k < n; ++k)
       for (int x = 0; x < n; ++x) {
         size_t i = (size_t)k * n + x;
+        if (!SFX(or_live)(L, i)) { oY[i] = 0; oP[i] = 0; continue; }   /* zero rows outside */
         oY[i] = L->c[j] * Y[i] + SFX(or_stencil)(L, j, P, x, k);
         oP[i] = SFX(or_stencil)(L, j, Y, x, k) + (SFX(or_mask_e)(L, i) * L->e[j]) * U[i];
       }
   }
   for (size_t i = 0; i < nn; ++i) {
+    if (!SFX(or_live)(L, i)) { oU[i] = 0; continue; }
     REAL s = L->g * U[i], mi = SFX(or_mask_d)(L, i);
     for (int j = 0; j < N; ++j) s += (mi * L->d[j]) * xv[(size_t)(N + 1) * nn + (size_t)j * nn + i];
     oU[i] = s;
@@ -78,9 +98,9 @@ static void SFX(or_apply)(const SFX(or_lvl) *L, const REAL *xv, REAL *out) {
 
 /* r = f - S x */
 static void SFX(or_residual)(const SFX(or_lvl) *L, const REAL *xv, const REAL *f, REAL *r) {
-  size_t len = (size_t)(2 * L->N + 1) * L->n * L->n;
+  size_t nn = (size_t)L->n * L->n, len = (size_t)(2 * L->N + 1) * nn;
   SFX(or_apply)(L, xv, r);
-  for (size_t i = 0; i < len; ++i) r[i] = f[i] - r[i];
+  for (size_t i = 0; i < len; ++i) r[i] = SFX(or_live)(L, i % nn) ? f[i] - r[i] : (REAL)0;
 }
 
 /* Node solve of eq. solution_reduced_system: the (2N+1)x(2N+1) system
@@ -121,6 +141,14 @@ static void SFX(or_halfsweep)(const SFX(or_lvl) *L, int colour, REAL theta,
     for (int x = 0; x < n; ++x) {
       if (((x + k) & 1) != colour) continue;
       size_t i = (size_t)k * n + x;
+      if (!SFX(or_live)(L, i)) {   /* outside the domain: held at zero */
+        for (int j = 0; j < N; ++j) {
+          xv[(size_t)j * nn + i] = 0;
+          xv[(size_t)(N + 1) * nn + (size_t)j * nn + i] = 0;
+        }
+        U[i] = 0;
+        continue;
+      }
       for (int j = 0; j < N; ++j) {
         dm[j] = SFX(or_mask_d)(L, i) * L->d[j];
         em[j] = SFX(or_mask_e)(L, i) * L->e[j];
@@ -132,11 +160,11 @@ static void SFX(or_halfsweep)(const SFX(or_lvl) *L, int colour, REAL theta,
         REAL ks = OR_KY(L, j, k, x), kn = OR_KY(L, j, k + 1, x);
         a[j] = kw + ke + ks + kn;
         bP[j] = f[(size_t)j * nn + i]
-              + kw * SFX(or_at)(P, n, x - 1, k) + ke * SFX(or_at)(P, n, x + 1, k)
-              + ks * SFX(or_at)(P, n, x, k - 1) + kn * SFX(or_at)(P, n, x, k + 1);
+              + kw * SFX(or_atd)(L, P, x - 1, k) + ke * SFX(or_atd)(L, P, x + 1, k)
+              + ks * SFX(or_atd)(L, P, x, k - 1) + kn * SFX(or_atd)(L, P, x, k + 1);
         bY[j] = f[(size_t)(N + 1) * nn + (size_t)j * nn + i]
-              + kw * SFX(or_at)(Y, n, x - 1, k) + ke * SFX(or_at)(Y, n, x + 1, k)
-              + ks * SFX(or_at)(Y, n, x, k - 1) + kn * SFX(or_at)(Y, n, x, k + 1);
+              + kw * SFX(or_atd)(L, Y, x - 1, k) + ke * SFX(or_atd)(L, Y, x + 1, k)
+              + ks * SFX(or_atd)(L, Y, x, k - 1) + kn * SFX(or_atd)(L, Y, x, k + 1);
       }
       REAL un;
       SFX(or_node_solve)(N, a, L->c, dm, em, L->g, bP, fU[i], bY, yn, &un, pn);
@@ -165,6 +193,14 @@ static void SFX(or_jacobi)(const SFX(or_lvl) *L, REAL theta, REAL *xv, const REA
   for (int k = 0; k < n; ++k)
     for (int x = 0; x < n; ++x) {
       size_t i = (size_t)k * n + x;
+      if (!SFX(or_live)(L, i)) {   /* outside the domain: held at zero */
+        for (int j = 0; j < N; ++j) {
+          xv[(size_t)j * nn + i] = 0;
+          xv[(size_t)(N + 1) * nn + (size_t)j * nn + i] = 0;
+        }
+        xv[(size_t)N * nn + i] = 0;
+        continue;
+      }
       for (int j = 0; j < N; ++j) {
         dm[j] = SFX(or_mask_d)(L, i) * L->d[j];
         em[j] = SFX(or_mask_e)(L, i) * L->e[j];
@@ -182,6 +218,16 @@ static void SFX(or_jacobi)(const SFX(or_lvl) *L, REAL theta, REAL *xv, const REA
     }
   free(w);
   free(r);
+}
+
+/* Zero every field of v at the nodes outside the domain (a restricted residual
+ * there is no equation of the coarse system). */
+static void SFX(zero_outside)(const SFX(or_lvl) *L, REAL *v) {
+  if (!L->dom) return;
+  size_t nn = (size_t)L->n * L->n;
+  for (int b = 0; b < 2 * L->N + 1; ++b)
+    for (size_t i = 0; i < nn; ++i)
+      if (!SFX(or_live)(L, i)) v[b * nn + i] = 0;
 }
 
 /* 1D weights of bilinear interpolation: w(0)=1, w(+-1)=1/2. */

@@ -46,6 +46,8 @@ typedef struct {
   int smoother;   /* 0: red-black collective Gauss-Seidel, 1: damped collective Jacobi */
   double *md[OR_MAXLEV], *me[OR_MAXLEV];   /* node factors of D_j, E_j per level (NULL: 1) */
   float *md32[OR_MAXLEV], *me32[OR_MAXLEV];
+  double *dom[OR_MAXLEV];                  /* domain per level (NULL: the whole square) */
+  float *dom32[OR_MAXLEV];
   int n[OR_MAXLEV];
   double *kx[OR_MAXLEV], *ky[OR_MAXLEV];
   double *c[OR_MAXLEV], *d[OR_MAXLEV], *e[OR_MAXLEV];
@@ -144,16 +146,21 @@ static int or_coarse_setup(or_ctx *C) {
   double *col = (double *)malloc(sizeof(double) * (size_t)m);
   or_lvl_f64 *L = &C->L[l];
   for (int i = 0; i < m; ++i) Sch[(size_t)i * m + i] = L->g;
-  /* with node factors, D_j = d_j diag(md) and E_j = e_j diag(me) */
-  const double *md = L->md, *me = L->me;
+  /* with node factors, D_j = d_j diag(md) and E_j = e_j diag(me) (0 outside the domain) */
   for (int j = 0; j < N; ++j) {
-    /* assemble A_j column by column from the stencil */
+    /* assemble A_j column by column from the stencil; nodes outside the domain
+     * get identity rows (their couplings vanish: the stencil reads them as 0) */
     for (int q = 0; q < m; ++q) {
       memset(e_i, 0, sizeof(double) * m);
       e_i[q] = 1.0;
       for (int k = 0; k < n; ++k)
         for (int x = 0; x < n; ++x) A[(size_t)(k * n + x) * m + q] = or_stencil_f64(L, j, e_i, x, k);
     }
+    for (int r = 0; r < m; ++r)
+      if (!or_live_f64(L, (size_t)r)) {
+        for (int q = 0; q < m; ++q) A[(size_t)r * m + q] = 0.0;
+        A[(size_t)r * m + r] = 1.0;
+      }
     double *Ai = C->Ainv + (size_t)j * m * m;
     if (or_dense_inverse(m, A, Ai) != 0) goto fail;
     /* Sch += d_j c_j e_j Ainv_j Ainv_j */
@@ -163,7 +170,7 @@ static int or_coarse_setup(or_ctx *C) {
       for (int i = 0; i < m; ++i) {
         double t = 0;
         for (int r = 0; r < m; ++r) t += Ai[(size_t)i * m + r] * col[r];
-        Sch[(size_t)i * m + q] += ((md ? md[i] : 1.0) * s * (me ? me[q] : 1.0)) * t;
+        Sch[(size_t)i * m + q] += (or_mask_d_f64(L, (size_t)i) * s * or_mask_e_f64(L, (size_t)q)) * t;
       }
     }
   }
@@ -211,6 +218,7 @@ void or_destroy(or_ctx *C) {
     free(C->xw32[l]); free(C->fw32[l]); free(C->rw32[l]);
   }
   for (int l = 0; l < C->nlev; ++l) { free(C->md[l]); free(C->md32[l]); free(C->me[l]); free(C->me32[l]); }
+  for (int l = 0; l < C->nlev; ++l) { free(C->dom[l]); free(C->dom32[l]); }
   free(C->Ainv); free(C->Sinv); free(C->cw);
   free(C);
 }
@@ -336,6 +344,19 @@ int or_set_masks(or_ctx *C, const double *md, const double *me, int coarsen) {
   return or_coarse_setup(C);
 }
 
+/* The domain: dom [n][n] of the finest level, 1 inside, 0 outside (NULL: the
+ * whole square).  Nodes outside are homogeneous Dirichlet nodes held at zero;
+ * coarse levels by injection, which keeps the domain exactly when its edges
+ * lie on grid lines of every level (the L-shape (0,1)^2 minus [1/2,1)^2 does).
+ * The coarsest factorization is rebuilt.  Returns 0, or -1 if singular. */
+int or_set_domain(or_ctx *C, const double *dom) {
+  set_factor(C, dom, C->dom, C->dom32, 0);
+  for (int l = 0; l < C->nlev; ++l) { C->L[l].dom = C->dom[l]; C->L32[l].dom = C->dom32[l]; }
+  free(C->Ainv); free(C->Sinv); free(C->cw);
+  C->Ainv = C->Sinv = C->cw = NULL;
+  return or_coarse_setup(C);
+}
+
 /* Control acting only where mask[i] != 0 (local control; eq.
  * solution_reduced_system2 at nodes without control): the node entries of D_j
  * and E_j become mask_i d_j and mask_i e_j.  mask NULL: control everywhere. */
@@ -347,6 +368,12 @@ void or_level_factor(const or_ctx *C, int l, int which, double *out) {
   const double *v = which ? C->me[l] : C->md[l];
   size_t nn = (size_t)C->n[l] * C->n[l];
   for (size_t i = 0; i < nn; ++i) out[i] = v ? v[i] : 1.0;
+}
+
+/* The domain of level l: out [n_l][n_l], 1 inside (everywhere without one). */
+void or_level_domain(const or_ctx *C, int l, double *out) {
+  size_t nn = (size_t)C->n[l] * C->n[l];
+  for (size_t i = 0; i < nn; ++i) out[i] = C->dom[l] ? C->dom[l][i] : 1.0;
 }
 
 int or_nlevels(const or_ctx *C) { return C->nlev; }
@@ -414,6 +441,7 @@ static void vcycle_f64(or_ctx *C, int l, double *x, const double *f) {
   for (int s = 0; s < C->pre; ++s) smooth_f64(C, L, x, f);
   or_residual_f64(L, x, f, C->rw[l]);
   or_restrict_f64(C->n[l], C->N, C->rw[l], C->fw[l + 1]);
+  zero_outside_f64(&C->L[l + 1], C->fw[l + 1]);
   memset(C->xw[l + 1], 0, sizeof(double) * vlen(C->n[l + 1], C->N));
   vcycle_f64(C, l + 1, C->xw[l + 1], C->fw[l + 1]);
   or_prolong_add_f64(C->n[l + 1], C->N, C->xw[l + 1], x);
@@ -436,6 +464,7 @@ static void vcycle_f32(or_ctx *C, int l, float *x, const float *f) {
   for (int s = 0; s < C->pre; ++s) smooth_f32(C, L, x, f);
   or_residual_f32(L, x, f, C->rw32[l]);
   or_restrict_f32(C->n[l], N, C->rw32[l], C->fw32[l + 1]);
+  zero_outside_f32(&C->L32[l + 1], C->fw32[l + 1]);
   memset(C->xw32[l + 1], 0, sizeof(float) * vlen(C->n[l + 1], N));
   vcycle_f32(C, l + 1, C->xw32[l + 1], C->fw32[l + 1]);
   or_prolong_add_f32(C->n[l + 1], N, C->xw32[l + 1], x);

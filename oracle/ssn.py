@@ -86,8 +86,24 @@ def newton_problem(prob):
 
 
 # ---------------------------------------------------------------- sparse blocks
+def _on_domain(prob, M, fields):
+    """M restricted to the problem's domain: rows and columns of the unknowns of
+    nodes outside become identity ones (M unchanged without a domain).  fields:
+    how many n x n planes the matrix acts on."""
+    if getattr(prob, "domain", None) is None:
+        return M
+    live = np.tile(np.asarray(prob.domain, dtype=np.float64).ravel(), fields)
+    D = sp.diags(live)
+    return (D @ M @ D + sp.diags(1.0 - live)).tocsc()
+
+
 def stiffness(prob, j):
-    """A_j: the h^2-scaled 5-point stencil of sample j from its face coefficients."""
+    """A_j: the h^2-scaled 5-point stencil of sample j from its face coefficients
+    (on the problem's domain: the Dirichlet problem there, identity rows outside)."""
+    return _on_domain(prob, _stiffness_square(prob, j), 1)
+
+
+def _stiffness_square(prob, j):
     n = prob.n
     kx, ky = prob.kx[j], prob.ky[j]
     rows, cols, vals = [], [], []
@@ -118,7 +134,7 @@ def assemble(prob, md=None, me=None):
         blocks[N + 1 + j][j] = A
         blocks[N + 1 + j][N] = sp.diags(me * prob.e[j])
     blocks[N][N] = prob.g * I
-    return sp.bmat(blocks, format="csc")
+    return _on_domain(prob, sp.bmat(blocks, format="csc"), 2 * N + 1)
 
 
 def initial_state(prob, u0):
@@ -128,12 +144,15 @@ def initial_state(prob, u0):
     n, N = prob.n, prob.N
     nn = n * n
     u0 = np.asarray(u0, dtype=np.float64).ravel()
+    if getattr(prob, "domain", None) is not None:
+        u0 = u0 * np.asarray(prob.domain).ravel()     # no control outside the domain
     x = np.zeros((2 * N + 1) * nn)
     x[N * nn:(N + 1) * nn] = u0
     for j in range(N):
         lu = spla.splu(stiffness(prob, j).tocsc())
-        y = lu.solve(prob.fP[j].ravel() - prob.e[j] * u0)
-        p = lu.solve(prob.fY[j].ravel() - prob.c[j] * y, trans="T")
+        live = 1.0 if getattr(prob, "domain", None) is None else np.asarray(prob.domain).ravel()
+        y = lu.solve(live * (prob.fP[j].ravel() - prob.e[j] * u0))
+        p = lu.solve(live * (prob.fY[j].ravel() - prob.c[j] * y), trans="T")
         x[j * nn:(j + 1) * nn] = y
         x[(N + 1 + j) * nn:(N + 2 + j) * nn] = p
     return x

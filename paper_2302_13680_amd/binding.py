@@ -46,7 +46,7 @@ class Desc(C.Structure):
 class Blocks(C.Structure):
     _fields_ = [("kx", C.c_void_p), ("ky", C.c_void_p), ("c", C.POINTER(C.c_double)),
                 ("d", C.POINTER(C.c_double)), ("e", C.POINTER(C.c_double)), ("g", C.c_double),
-                ("ctrl", C.POINTER(C.c_double))]
+                ("ctrl", C.POINTER(C.c_double)), ("domain", C.POINTER(C.c_double))]
 
 
 class Stats(C.Structure):
@@ -194,11 +194,12 @@ class Context:
 
     kx, ky: float64 device tensors in the node layout ([n][n+1][N], [n+1][n][N]);
     c, d, e: per-sample diagonal values (host sequences), g: scalar; ctrl: optional
-    (n, n) host control mask in [0, 1] (local control), None: control everywhere.
+    (n, n) host control mask in [0, 1] (local control), None: control everywhere; domain:
+    optional (n, n) host 0/1 mask of the domain (the L-shape), None: the square.
     """
 
     def __init__(self, n, N, kx, ky, c, d, e, g, *, coarsest_n=7, pre=2, post=2, theta=1.0,
-                 precision=SMG_F64, gmres_restart=30, flags=0, strip=0, stream=None, ctrl=None):
+                 precision=SMG_F64, gmres_restart=30, flags=0, strip=0, stream=None, ctrl=None, domain=None):
         import torch
         L = load()
         self.L = L
@@ -216,9 +217,11 @@ class Context:
         self._e = np.ascontiguousarray(e, dtype=np.float64)
         dp = C.POINTER(C.c_double)
         self._ctrl = None if ctrl is None else np.ascontiguousarray(ctrl, dtype=np.float64).reshape(n * n)
+        self._dom = None if domain is None else np.ascontiguousarray(domain, dtype=np.float64).reshape(n * n)
         blocks = Blocks(_ptr(kx), _ptr(ky), self._c.ctypes.data_as(dp), self._d.ctypes.data_as(dp),
                         self._e.ctypes.data_as(dp), float(g),
-                        None if self._ctrl is None else self._ctrl.ctypes.data_as(dp))
+                        None if self._ctrl is None else self._ctrl.ctypes.data_as(dp),
+                        None if self._dom is None else self._dom.ctypes.data_as(dp))
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = C.c_void_p()
         rc = L.smg_setup(C.byref(self.desc), C.byref(blocks), _ptr(self.workspace), nbytes,
@@ -508,6 +511,7 @@ def context_from_problem(prob, device="cuda", ssn=False, **kw):
     kx = torch.from_numpy(kxn).to(device)
     ky = torch.from_numpy(kyn).to(device)
     kw.setdefault("ctrl", getattr(prob, "ctrl", None))
+    kw.setdefault("domain", getattr(prob, "domain", None))
     g, d = prob.g, prob.d
     if ssn:
         g, d = prob.g / prob.nu, np.asarray(prob.d) / prob.nu

@@ -64,6 +64,35 @@ __global__ void k_coarsen_factors(int nc, int full, const double* __restrict__ f
   coarse[2 * (size_t)i + 1] = e;
 }
 
+// Domain of a level from the level above (nf = 2 nc + 1) by injection.
+__global__ void k_inject_domain(int nc, const double* __restrict__ fine, double* __restrict__ coarse) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nc * nc) return;
+  const int K = i / nc, X = i - K * nc;
+  coarse[i] = fine[(size_t)(2 * K + 1) * (2 * nc + 1) + (2 * X + 1)];
+}
+
+// Factor pairs of the nodes outside the domain set to (0, -0) (see node_live).
+__global__ void k_apply_domain(int nn, const double* __restrict__ dom, double* __restrict__ pairs) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nn || dom[i] != 0.0) return;
+  pairs[2 * (size_t)i] = 0.0;
+  pairs[2 * (size_t)i + 1] = -0.0;
+}
+
+// Every field of x set to zero at the nodes outside the domain (y, p: N samples each, u).
+__global__ void k_zero_outside(int nn, int N, const double* __restrict__ dom, double* __restrict__ x) {
+  const size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x;
+  const size_t per = 2 * (size_t)N + 1;
+  if (t >= (size_t)nn * per) return;
+  const int i = (int)(t / per);
+  const size_t r = t - (size_t)i * per;
+  if (dom[i] != 0.0) return;
+  if (r < (size_t)N) x[(size_t)i * N + r] = 0.0;                                   // y_j
+  else if (r == (size_t)N) x[(size_t)N * nn + i] = 0.0;                            // u
+  else x[(size_t)(N + 1) * nn + (size_t)i * N + (r - N - 1)] = 0.0;                // p_j
+}
+
 // flags[0] = 1 if any value is not finite or lies outside [0, 1].
 __global__ void k_check_unit(size_t len, const double* __restrict__ a, int* __restrict__ flag) {
   int bad = 0;
@@ -109,8 +138,11 @@ __device__ void lds_invert_spd(double* A, double* col, int m) {
 }
 
 // One block per sample: assemble the coarsest A_j (m = n^2) from its faces and invert it.
+// dom (null: no domain): nodes outside (0) get identity rows; the couplings of the
+// nodes inside to them act on values that are zero.
 __global__ __launch_bounds__(kBlock) void k_coarse_invert_A(int n, int N, const double* __restrict__ kx,
                                                             const double* __restrict__ ky,
+                                                            const double* __restrict__ dom,
                                                             double* __restrict__ Ainv) {
   __shared__ double A[kMaxCoarse * kMaxCoarse];
   __shared__ double col[kMaxCoarse];
@@ -127,6 +159,13 @@ __global__ __launch_bounds__(kBlock) void k_coarse_invert_A(int n, int N, const 
     if (k > 0) A[r * m + r - n] = -ks;
     if (k < n - 1) A[r * m + r + n] = -kn;
   }
+  __syncthreads();
+  if (dom)
+    for (int r = threadIdx.x; r < m; r += blockDim.x)
+      if (dom[r] == 0.0) {
+        for (int q = 0; q < m; ++q) A[r * m + q] = 0.0;
+        A[r * m + r] = 1.0;
+      }
   lds_invert_spd(A, col, m);
   // stored transposed: AinvT[c][r] = Ainv[r][c], so that a thread per row reads coalesced
   for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {

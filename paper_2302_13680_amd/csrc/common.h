@@ -45,6 +45,15 @@ struct NodeFactors {
   T d, e;   // factors of the node entries of D_j and E_j
 };
 
+// A node outside the domain (the L-shape's removed quadrant: a homogeneous
+// Dirichlet node held at zero) carries the factor pair (0, -0): both factors
+// vanish, and the sign bit of the E factor marks it.  Kernels compiled with
+// MK = false (no factors, no domain) see every node inside.
+template <typename T>
+__device__ __forceinline__ bool node_live(const NodeFactors<T>& f) {
+  return !signbit(f.e);
+}
+
 // node factors of node i, one 2-element load; kernels compiled with MK = false
 // (contexts whose factors are all 1) use 1 without a load
 template <bool MK, typename T>

@@ -91,14 +91,14 @@ __device__ __forceinline__ void jacobi_node(const LevelArgs<T>& L, const T* __re
         const int q = c * VW + v;
         const T dy = ia[q] * (rPq[q] - eq[q] * du);
         const T dp = ia[q] * (rYq[q] - cq[q] * dy);
-        yv[v] = yo[q] + theta * dy;
-        pv[v] = po[q] + theta * dp;
+        yv[v] = node_live(mf) ? yo[q] + theta * dy : T(0);   // outside the domain: zero
+        pv[v] = node_live(mf) ? po[q] + theta * dp : T(0);
       }
       stv<VW>(xout + base, yv);
       stv<VW>(xout + (size_t)(N + 1) * nn + base, pv);
     }
   }
-  if (lane == 0) xout[(size_t)N * nn + node] = u + theta * du;
+  if (lane == 0) xout[(size_t)N * nn + node] = node_live(mf) ? u + theta * du : T(0);
 }
 
 template <typename T, int W, int JM, int VW, bool MK>

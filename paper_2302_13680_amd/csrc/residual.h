@@ -78,6 +78,8 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
         rP = fp - rP;
         ff = (double)fy * (double)fy + (double)fp * (double)fp;
       }
+      rY = node_live(mf) ? rY : T(0);   // zero rows outside the domain
+      rP = node_live(mf) ? rP : T(0);
       ry[q] = (TO)rY;
       rp[q] = (TO)rP;
       if (act) {
@@ -99,6 +101,7 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
       rU = fu - rU;
       acc[3] += (double)fu * (double)fu;
     }
+    rU = node_live(mf) ? rU : T(0);
     if (out) out[(size_t)N * nn + node] = (TO)rU;
     acc[1] = (double)rU * (double)rU;
   }
@@ -146,8 +149,8 @@ __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, co
     const double sp = nbsum(pv(base + ow), pv(base + oe), pv(base + os), pv(base + on));
     const double a = (kw + ke) + (ks + kn);
     const double fy = f[base], fp = f[oP + base];
-    const double rY = fy - (L.c[j] * y0 + (a * p0 - sp));
-    const double rP = fp - ((a * y0 - sy) + (mf.e * L.e[j]) * u);
+    const double rY = node_live(mf) ? fy - (L.c[j] * y0 + (a * p0 - sp)) : 0.0;   // zero rows outside
+    const double rP = node_live(mf) ? fp - ((a * y0 - sy) + (mf.e * L.e[j]) * u) : 0.0;
     dsum += act ? (mf.d * L.d[j]) * p0 : 0.0;
     if (act) {
       xn[base] = y0;
@@ -162,7 +165,7 @@ __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, co
   dsum = group_sum_w(dsum, W);
   if (lane == 0) {
     const double fu = f[oU + node];
-    const double rU = fu - (L.g * u + dsum);
+    const double rU = node_live(mf) ? fu - (L.g * u + dsum) : 0.0;
     xn[oU + node] = u;
     out[oU + node] = (float)rU;
     acc[1] = rU * rU;

@@ -36,7 +36,8 @@ struct Level {
   T* e = nullptr;
   T g = 0;
   T* gden = nullptr; // [n][n]: g + sum_j d_j c_j e_j / a_j^2 (node_den)
-  T* mk = nullptr;   // [n][n] control mask (local control; all ones when the control acts everywhere)
+  T* mk = nullptr;   // [n][n][2] node factor pairs (md, me); (0, -0) outside the domain
+  T* dom = nullptr;  // [n][n] domain (FP64 levels, contexts with a domain): 1 inside, 0 outside
   T* x = nullptr;    // level iterate (levels >= 1, and level 0 of the FP32 cycle)
   T* f = nullptr;    // level right-hand side
 };
@@ -193,6 +194,7 @@ struct smg_ctx {
   unsigned* pub_dev = nullptr;
   unsigned pub_seq = 0;
   bool masked = false;         // node factors other than 1 somewhere (local control, Newton systems)
+  bool domain = false;         // a domain other than the square (nodes held at zero outside)
   // semismooth Newton buffers (SMG_FLAG_SSN): increment, right-hand side, node vectors
   // E[p], E[dp], F, chi, per-block partials and their sums
   double *sdx = nullptr, *sr = nullptr, *sw = nullptr, *sdw = nullptr, *sF = nullptr, *schi = nullptr;
@@ -308,6 +310,7 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
     const size_t nn = (size_t)C->L64[l].n * C->L64[l].n;
     C->L64[l].mk = cv.take<double>(2 * nn);
     if (f32) C->L32[l].mk = cv.take<float>(2 * nn);
+    C->L64[l].dom = cv.take<double>(nn);
   }
   return cv.off + 256;
 }
@@ -442,10 +445,14 @@ int factors_setup(smg_ctx* C, const double* md, const double* me, int full) {
   const int n0 = C->desc.n;
   hipLaunchKernelGGL(k_node_factors, dim3((n0 * n0 + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, n0 * n0,
                      md, me, C->L64[0].mk);
-  for (int l = 1; l < C->nlev; ++l) {
-    const int nl = C->L64[l].n;
-    hipLaunchKernelGGL(k_coarsen_factors, dim3((nl * nl + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, nl,
-                       full, (const double*)C->L64[l - 1].mk, C->L64[l].mk);
+  for (int l = 0; l < C->nlev; ++l) {
+    const int nl = C->L64[l].n, nb = (nl * nl + kBlock - 1) / kBlock;
+    if (l > 0)
+      hipLaunchKernelGGL(k_coarsen_factors, dim3(nb), dim3(kBlock), 0, C->stream, nl, full,
+                         (const double*)C->L64[l - 1].mk, C->L64[l].mk);
+    if (C->domain)   // nodes outside the domain: (0, -0)
+      hipLaunchKernelGGL(k_apply_domain, dim3(nb), dim3(kBlock), 0, C->stream, nl * nl,
+                         (const double*)C->L64[l].dom, C->L64[l].mk);
   }
   LAUNCH_CHECK();
   if (f32)
@@ -460,6 +467,19 @@ int factors_setup(smg_ctx* C, const double* md, const double* me, int full) {
                      (const double*)Lc.mk, C->terms);
   hipLaunchKernelGGL(k_coarse_schur_invert, dim3(1), dim3(kBlock), 0, C->stream, C->m, C->N, C->terms, Lc.g,
                      C->Sinv);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+// x (a finest-level FP64 vector) set to zero outside the domain: the kernels
+// keep those values at zero and read them as the Dirichlet values of the nodes
+// inside, so every solver starts from such an x.
+int zero_outside(smg_ctx* C, double* x) {
+  if (!C->domain) return SMG_OK;
+  const int nn = C->desc.n * C->desc.n;
+  const size_t tot = (size_t)nn * (2 * (size_t)C->N + 1);
+  hipLaunchKernelGGL(k_zero_outside, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, C->stream, nn,
+                     C->N, (const double*)C->L64[0].dom, x);
   LAUNCH_CHECK();
   return SMG_OK;
 }
@@ -1359,6 +1379,9 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
   if (B->ctrl)
     for (size_t i = 0; i < (size_t)d.n * d.n; ++i)
       if (!(B->ctrl[i] >= 0.0 && B->ctrl[i] <= 1.0)) return SMG_EINVAL;
+  if (B->domain)
+    for (size_t i = 0; i < (size_t)d.n * d.n; ++i)
+      if (!(B->domain[i] == 0.0 || B->domain[i] == 1.0)) return SMG_EINVAL;
   smg_ctx* C = new smg_ctx();
   C->desc = d;
   C->N = N;
@@ -1430,15 +1453,29 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
         return fail(SMG_EHIP);
     }
   }
+  // domain on every level (the caller's on the finest, coarse levels by injection)
+  C->domain = B->domain != nullptr;
+  if (C->domain) {
+    if (hipMemcpyAsync(C->L64[0].dom, B->domain, sizeof(double) * d.n * d.n, hipMemcpyHostToDevice, C->stream) !=
+        hipSuccess)
+      return fail(SMG_EHIP);
+    for (int l = 1; l < C->nlev; ++l) {
+      const int nl = C->L64[l].n;
+      hipLaunchKernelGGL(k_inject_domain, dim3((nl * nl + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, nl,
+                         (const double*)C->L64[l - 1].dom, C->L64[l].dom);
+    }
+    if (hipGetLastError() != hipSuccess) return fail(SMG_EHIP);
+  }
   // coarsest factorization (FP64): A_j^{-1}
   const Level<double>& Lc = C->L64[C->nlev - 1];
-  hipLaunchKernelGGL(k_coarse_invert_A, dim3(N), dim3(kBlock), 0, C->stream, Lc.n, N, Lc.kx, Lc.ky, C->Ainv);
+  hipLaunchKernelGGL(k_coarse_invert_A, dim3(N), dim3(kBlock), 0, C->stream, Lc.n, N, Lc.kx, Lc.ky,
+                     C->domain ? (const double*)Lc.dom : (const double*)nullptr, C->Ainv);
   if (hipGetLastError() != hipSuccess) return fail(SMG_EHIP);
   // control mask (local control): the caller's, as both node factors (staged
   // through the scratch vector rr); all ones without one
   {
     const double* mk = nullptr;
-    C->masked = false;
+    C->masked = C->domain;
     if (B->ctrl) {
       for (size_t i = 0; i < (size_t)d.n * d.n; ++i) C->masked |= (B->ctrl[i] != 1.0);
       if (hipMemcpyAsync(C->rr, B->ctrl, sizeof(double) * d.n * d.n, hipMemcpyHostToDevice, C->stream) != hipSuccess)
@@ -1465,7 +1502,7 @@ int smg_set_node_factors(smg_ctx* C, const double* md, const double* me, int coa
   HIP_TRY(hipMemcpyAsync(C->host, C->flag, sizeof(int), hipMemcpyDeviceToHost, C->stream));
   TRY(sync(C));
   if (*(const int*)C->host) return SMG_EINVAL;
-  set_masked(C, md || me);
+  set_masked(C, md || me || C->domain);
   return factors_setup(C, md, me, coarsening);
 }
 
@@ -1548,6 +1585,7 @@ int smg_level_faces(smg_ctx* C, int level, double* kx, double* ky) {
 
 int smg_vcycle(smg_ctx* C, double* x, const double* f, int ncycles) {
   if (!C || !x || !f || ncycles < 0) return SMG_EINVAL;
+  TRY(zero_outside(C, x));
   if (C->desc.precision == SMG_F64) {
     for (int i = 0; i < ncycles; ++i) TRY(vcycle64(C, x, f));
     return SMG_OK;
@@ -1564,6 +1602,7 @@ int smg_gmres_precond(smg_ctx* C, double* x, const double* f, int restart, doubl
                       smg_stats* st) {
   if (!C || !x || !f || restart < 1 || restart > C->desc.gmres_restart || !(rtol > 0) || maxit < 1)
     return SMG_EINVAL;
+  TRY(zero_outside(C, x));
   const double t0 = now_ms();
   stats_begin(st);
   double h[5];
@@ -1595,6 +1634,7 @@ int smg_gmres_precond(smg_ctx* C, double* x, const double* f, int restart, doubl
 int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, int maxit, smg_stats* st) {
   if (!C || !x || !f || !(rtol > 0) || maxit < 1) return SMG_EINVAL;
   if (method != SMG_VCYCLE && method != SMG_GMRES) return SMG_EINVAL;
+  TRY(zero_outside(C, x));
   const double t0 = now_ms();
   const bool f32 = C->desc.precision == SMG_F32;
   if (method == SMG_GMRES && !f32) {
@@ -1749,6 +1789,7 @@ int smg_ssn_solve(smg_ctx* C, double* x, const double* f, const smg_ssn_params* 
   if (!C || !x || !f || !prm || !ssn_params_valid(*prm)) return SMG_EINVAL;
   if (!(C->desc.flags & SMG_FLAG_SSN)) return SMG_EINVAL;
   if (prm->inner_method == SMG_GMRES && C->desc.gmres_restart < 1) return SMG_EINVAL;
+  TRY(zero_outside(C, x));
   const double t0 = now_ms();
   const smg_ssn_params& p = *prm;
   const double sigma = p.sigma > 0 ? p.sigma : 1e-4, rho = p.rho > 0 ? p.rho : 0.5;
@@ -1840,7 +1881,7 @@ static int batch_validate(smg_ctx* const* ctxs, int count, const int* lanes, smg
   }
   for (int i = 0; i < count; ++i) {
     smg_ctx* C = ctxs[i];
-    if (C->desc.precision != B->precision || C->desc.theta != 1.0 || (C->desc.flags & SMG_FLAG_JACOBI) ||
+    if (C->desc.precision != B->precision || C->desc.theta != 1.0 || (C->desc.flags & SMG_FLAG_JACOBI) || C->domain ||
         C->desc.pre < 1 || C->desc.post < 1 ||
         C->desc.pre != ctxs[0]->desc.pre || C->desc.post != ctxs[0]->desc.post || C->stream != ctxs[0]->stream)
       return SMG_EINVAL;

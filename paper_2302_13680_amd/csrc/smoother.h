@@ -164,6 +164,7 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
   num = group_sum_w(num, W);
   const T un = (fu + num) / gd;
   const bool relax = SRC == kPlain && theta != T(1);
+  const bool live = node_live(mf);   // outside the domain: held at zero
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int j = VW * (lane + c * W);
@@ -186,11 +187,16 @@ __device__ __forceinline__ void halfsweep_node(const LevelArgs<T>& L, T* __restr
           pv[u] = (T(1) - theta) * po[u] + theta * pv[u];
         }
       }
+#pragma unroll
+      for (int u = 0; u < VW; ++u) {
+        yv[u] = live ? yv[u] : T(0);
+        pv[u] = live ? pv[u] : T(0);
+      }
       stv<VW>(Y + base, yv);
       stv<VW>(P + base, pv);
     }
   }
-  if (lane == 0) U[node] = relax ? (T(1) - theta) * U[node] + theta * un : un;
+  if (lane == 0) U[node] = !live ? T(0) : relax ? (T(1) - theta) * U[node] + theta * un : un;
 }
 
 // Denominator of the control update of the node solve, per node, by a group

@@ -164,9 +164,11 @@ __device__ __forceinline__ T residual_restrict_rows(const LevelArgs<T>& L, const
 #pragma unroll
       for (int k = 0; k < 3; ++k) {   // fine column xc - 1 + k (dx = k - 1)
         const int wi = i + 1, wk = k + 1;
-        const T w = (T)(lin_w(k - 1) * lin_w(i - 1));
+        // a fine node outside the domain has no residual rows
+        const NodeFactors<T> nf = node_factors<MK>(L, (size_t)(kc - 1 + i) * n + (xc - 1 + k));
+        const T w = node_live(nf) ? (T)(lin_w(k - 1) * lin_w(i - 1)) : T(0);
         const T u = U[(size_t)(kc - 1 + i) * n + (xc - 1 + k)];
-        const T mf = node_factors<MK>(L, (size_t)(kc - 1 + i) * n + (xc - 1 + k)).e;
+        const T mf = nf.e;
 #pragma unroll
         for (int q = 0; q < VW; ++q) {
           const T kw = kxv[i][k][q], ke = kxv[i][k + 1][q], ks = kyv[i][k][q], kn = kyv[i + 1][k][q];
@@ -194,6 +196,13 @@ __device__ __forceinline__ T residual_restrict_rows(const LevelArgs<T>& L, const
       dw += act ? dj[q] * wp : T(0);
     }
     if (act) {
+      // a coarse node outside the domain (the fine node it sits on is) has no equation
+      const bool clive = node_live(node_factors<MK>(L, (size_t)kc * n + xc));
+#pragma unroll
+      for (int q = 0; q < VW; ++q) {
+        sY[q] = clive ? sY[q] : T(0);
+        sP[q] = clive ? sP[q] : T(0);
+      }
       stv<VW>(coarse + (size_t)cnode * N + j, sY);
       stv<VW>(coarse + (size_t)(N + 1) * nnc + (size_t)cnode * N + j, sP);
     }
@@ -203,7 +212,7 @@ __device__ __forceinline__ T residual_restrict_rows(const LevelArgs<T>& L, const
 
 // U row of coarse node (X, K): sum_f w_f (f_U(f) - g u(f)) - D, with D the
 // group's sum of the residual_restrict_rows partials.
-template <typename T>
+template <typename T, bool MK = true>
 __device__ __forceinline__ void residual_restrict_urow(const LevelArgs<T>& L, const T* __restrict__ x,
                                                        const T* __restrict__ f, T* __restrict__ coarse, int X,
                                                        int K, T D) {
@@ -218,9 +227,11 @@ __device__ __forceinline__ void residual_restrict_urow(const LevelArgs<T>& L, co
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const size_t o = (size_t)(kc - 1 + i) * n + (xc - 1 + k);
-      sU += (T)(lin_w(k - 1) * lin_w(i - 1)) * (fU[o] - L.g * U[o]);
+      const T w = node_live(node_factors<MK>(L, o)) ? (T)(lin_w(k - 1) * lin_w(i - 1)) : T(0);
+      sU += w * (fU[o] - L.g * U[o]);
     }
-  coarse[(size_t)N * nc * nc + (size_t)K * nc + X] = sU - D;
+  const bool clive = node_live(node_factors<MK>(L, (size_t)kc * n + xc));
+  coarse[(size_t)N * nc * nc + (size_t)K * nc + X] = clive ? sU - D : T(0);
 }
 
 // Group of W <= 64 lanes (one wave or part of one) per coarse node.
@@ -232,7 +243,7 @@ __device__ __forceinline__ void residual_restrict_node(const LevelArgs<T>& L, co
   strip_node(slot, (L.n - 1) / 2, cstrip, X, K);
   const T dw = residual_restrict_rows<T, JM, VW, MK>(L, x, f, coarse, X, K, lane, W);
   const T D = group_sum_w(dw, W);
-  if (lane == 0) residual_restrict_urow<T>(L, x, f, coarse, X, K, D);
+  if (lane == 0) residual_restrict_urow<T, MK>(L, x, f, coarse, X, K, D);
 }
 
 // coarse = R (f - S x) over every coarse node, W lanes per node (W <= 256; a
@@ -262,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(LevelArgs<T> L, co
       const int w0 = (threadIdx.x >> 6);
       T D = part[w0];
       for (int q = 1; q < W / 64; ++q) D += part[w0 + q];
-      residual_restrict_urow<T>(L, x, f, coarse, X, K, D);
+      residual_restrict_urow<T, MK>(L, x, f, coarse, X, K, D);
     }
   }
 }

@@ -54,6 +54,7 @@ class Problem:
     yd: np.ndarray = field(default=None, repr=False)
     meta: dict = field(default_factory=dict)
     ctrl: np.ndarray = field(default=None, repr=False)   # (n, n) control mask, None: everywhere
+    domain: np.ndarray = field(default=None, repr=False)  # (n, n) 1 inside / 0 outside, None: the square
 
     @property
     def h(self) -> float:
@@ -171,7 +172,7 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
                  f: float = 1.0, xi: np.ndarray | None = None,
                  kappa_const: float | None = None, weights: np.ndarray | None = None,
                  control_region: tuple | None = None, field: str = "sine",
-                 corr_len2: float = 0.5) -> Problem:
+                 corr_len2: float = 0.5, domain: str = "square") -> Problem:
     """Build one seeded instance.
 
     ``decay=False`` gives amplitudes a_m = sigma (the 31x31, N=8 case, four modes
@@ -180,7 +181,10 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
     "gaussian"`` takes the paper's expansion instead (eq. log_normal):
     log kappa_j = sigma sum_m sqrt(lambda_m) b_m xi_{j,m} with the eigenpairs of
     the Gaussian covariance of correlation length^2 ``corr_len2`` on the unit
-    square (``gaussian_kl``); sigma is then the field's standard deviation.  ``weights`` are
+    square (``gaussian_kl``); sigma is then the field's standard deviation.
+    ``domain = "lshape"``: the paper's L-shaped domain (0,1)^2 minus [1/2,1)^2,
+    as the nodes of the square grid with x < 1/2 or y < 1/2 (nodes outside are
+    homogeneous Dirichlet nodes; the right-hand side is zero there).  ``weights`` are
     the quadrature weights zeta_j of the samples (default 1/N, Monte Carlo).
     ``control_region = (x0, x1, y0, y1)`` restricts the control to the nodes in
     the closed rectangle [x0, x1] x [y0, y1] (local control; the mask of the
@@ -230,6 +234,14 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
     fY = (zeta * h * h)[:, None, None] * ydv[None]
     fU = np.zeros((n, n))
     fP = np.full((N, n, n), h * h * f)
+    dom = None
+    if domain == "lshape":
+        eps = 1e-12
+        dom = (~((XX >= 0.5 - eps) & (YY >= 0.5 - eps))).astype(np.float64)
+        fY = fY * dom[None]
+        fP = fP * dom[None]
+    elif domain != "square":
+        raise ValueError(domain)
     ctrl = None
     if control_region is not None:
         x0, x1, y0, y1 = control_region
@@ -237,7 +249,7 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
         ctrl = (((XX >= x0 - eps) & (XX <= x1 + eps) & (YY >= y0 - eps) & (YY <= y1 + eps))
                 .astype(np.float64))
     return Problem(n=n, N=N, nu=nu, kx=np.ascontiguousarray(kx), ky=np.ascontiguousarray(ky),
-                   c=c, d=d, e=e, g=g, fY=fY, fU=fU, fP=fP, xi=xi, yd=ydv, ctrl=ctrl,
+                   c=c, d=d, e=e, g=g, fY=fY, fU=fU, fP=fP, xi=xi, yd=ydv, ctrl=ctrl, domain=dom,
                    meta=dict(M=xi.shape[1], sigma=sigma, decay=decay, seed=seed, f=f, field=field,
                              quadrature="mc" if weights is None else "weights"))
 

@@ -1,0 +1,169 @@
+"""GPU parity on the paper's L-shaped domain (0,1)^2 minus [1/2,1)^2 (nodes with
+x, y >= 1/2 held at zero) against the pinned oracle, through the C ABI: every
+step, V-cycle iterates in FP64 and FP32, solves, the zeroing of x outside on
+entry, the semismooth Newton solver, the paper's table settings, and the
+batched solver's refusal."""
+import numpy as np
+import pytest
+
+from paper_2302_13680_amd import inputs
+from paper_2302_13680_amd.inputs import node_to_paper, paper_to_node
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_13680_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as o
+    return o
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def lshape(n, N, nu=1e-4, seed=4, **kw):
+    return inputs.make_problem(n, N, nu, M=6, sigma=0.5, decay=True, seed=seed, yd=inputs.paper_target(n), f=1.0,
+                               domain="lshape", **kw)
+
+
+def live(p, l_n=None, o=None, l=0):
+    d = p.domain if o is None else o.level_domain(l)
+    return np.tile(d.ravel(), 2 * p.N + 1)
+
+
+@pytest.mark.parametrize("n,N", [(15, 3), (31, 8), (63, 16), (31, 100)])
+def test_lshape_steps(B, O, n, N):
+    p = lshape(n, N, seed=n + N)
+    o = O.Oracle(p, theta=0.5)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0, theta=0.5)
+    rng = np.random.default_rng(n)
+    m = live(p)
+    x = rng.standard_normal(o.vlen()) * m          # zero outside (the kernels' invariant)
+    f = rng.standard_normal(o.vlen())              # anything outside: never used there
+    xd, fd = dev(paper_to_node(x, n, N)), dev(paper_to_node(f, n, N))
+    r = torch.empty_like(xd)
+    ctx.residual(xd, fd, r)
+    assert rel(node_to_paper(host(r), n, N), o.residual(x, f)) <= 1e-14
+    out = torch.empty_like(xd)
+    ctx.jacobi(0, xd, out, fd)
+    assert rel(node_to_paper(host(out), n, N), o.jacobi(x, f, 0.5)) <= 1e-13
+    xs, xo = xd.clone(), x.copy()
+    for colour in (0, 1):
+        ctx.smooth(0, colour, xs, fd)
+        xo = o.halfsweep(xo, f, colour, theta=0.5)
+        assert rel(node_to_paper(host(xs), n, N), xo) <= 1e-13, colour
+    for l in range(o.nlev - 1):
+        nl, nc = o.levels_n[l], o.levels_n[l + 1]
+        xl = rng.standard_normal(o.vlen(l)) * live(p, o=o, l=l)
+        fl = rng.standard_normal(o.vlen(l))
+        cd = torch.empty(o.vlen(l + 1), dtype=torch.float64, device="cuda")
+        ctx.residual_restrict(l, dev(paper_to_node(xl, nl, N)), dev(paper_to_node(fl, nl, N)), cd)
+        ref = O.restrict(nl, N, o.residual(xl, fl, l)) * live(p, o=o, l=l + 1)
+        assert rel(node_to_paper(host(cd), nc, N), ref) <= 1e-14, l
+    lc = o.nlev - 1
+    nc = o.levels_n[lc]
+    F = rng.standard_normal(o.vlen(lc)) * live(p, o=o, l=lc)
+    X = torch.empty(F.size, dtype=torch.float64, device="cuda")
+    ctx.coarse_solve(dev(paper_to_node(F, nc, N)), X)
+    assert rel(node_to_paper(host(X), nc, N), o.coarse_solve(F)) <= 1e-11
+
+
+@pytest.mark.parametrize("smoother", ["gs", "jacobi"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lshape_vcycle_iterates(B, O, smoother, precision):
+    n, N = 63, 16
+    p = lshape(n, N, seed=9)
+    theta = 0.5 if smoother == "jacobi" else 1.0
+    flags = B.SMG_FLAG_JACOBI if smoother == "jacobi" else 0
+    o = O.Oracle(p, theta=theta, smoother=smoother)
+    ctx, f = B.context_from_problem(p, gmres_restart=0, theta=theta, flags=flags, precision=precision)
+    x_o = np.zeros(o.vlen())
+    xd = torch.zeros(o.vlen(), dtype=torch.float64, device="cuda")
+    cyc = o.vcycle if precision == 0 else o.vcycle32
+    for k in range(3):
+        x_o = cyc(x_o, p.rhs_paper(), 1)
+        ctx.vcycle(xd, f, 1)
+        assert rel(node_to_paper(host(xd), n, N), x_o) <= (1e-12 if precision == 0 else 2e-5), k
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_lshape_solves_and_zeroing_on_entry(B, O, method):
+    n, N = 127, 32
+    p = lshape(n, N, seed=5)
+    o = O.Oracle(p)
+    fp = p.rhs_paper()
+    ctx, f = B.context_from_problem(p, gmres_restart=30)
+    x = dev(paper_to_node(np.random.default_rng(1).standard_normal(o.vlen()) * (1 - live(p)), n, N))
+    rc, st = ctx.solve(x, f, method, rtol=1e-10, maxit=200)   # garbage outside: zeroed on entry
+    assert rc == B.SMG_OK
+    xg = node_to_paper(host(x), n, N)
+    assert np.all(xg[live(p) == 0] == 0)
+    assert np.linalg.norm(o.residual(xg, fp)) <= 1.01e-10 * np.linalg.norm(fp)
+    _, its, _ = o.solve_vcycle(fp, tol=1e-10, maxit=200) if method == 0 else o.gmres(fp, tol=1e-10)
+    assert abs(st["iterations"] - its) <= 1
+
+
+def test_lshape_semismooth_newton(B):
+    from oracle import ssn
+    n, N = 63, 8
+    p = lshape(n, N, seed=6)
+    p.fP[:] = 0.0
+    ref = ssn.ssn_solve(p, 1e-2, -50.0, 50.0, linear="gmres")
+    ctx, f = B.context_from_problem(p, gmres_restart=30, ssn=True)
+    x = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    prm = B.ssn_params(1e-4, 1e-2, -50.0, 50.0, (1.0 / (n + 1)) ** 2)
+    rc, st = ctx.ssn_solve(x, f, prm)
+    assert rc == B.SMG_OK and ref["converged"]
+    assert st["iterations"] == ref["iterations"]
+    assert all(abs(a - b) <= 1 for a, b in zip(st["inner"], ref["inner"]))
+    nn = n * n
+    ug = node_to_paper(host(x), n, N)[N * nn:(N + 1) * nn]
+    assert np.all(ug[p.domain.ravel() == 0] == 0)
+    assert np.abs(ug - ref["u"]).max() <= 1e-8 * np.abs(ref["u"]).max()
+
+
+def test_lshape_paper_setting(B, O):
+    """The paper's distributed-control setting on its L-shape (N_h = 705): the
+    Gaussian field, 5^3 collocation nodes, Jacobi theta 1/2, 1e-9."""
+    p = inputs.collocation_problem(31, 5, 1e-4, M=3, sigma=float(np.sqrt(0.5)), decay=True,
+                                   yd=inputs.paper_target(31), f=0.0, field="gaussian", corr_len2=0.5,
+                                   domain="lshape")
+    assert int(p.domain.sum()) == 705
+    o = O.Oracle(p, smoother="jacobi", theta=0.5)
+    ctx, f = B.context_from_problem(p, gmres_restart=30, theta=0.5, flags=B.SMG_FLAG_JACOBI)
+    fp = p.rhs_paper()
+    for method, solve in ((B.SMG_VCYCLE, lambda: o.solve_vcycle(fp, tol=1e-9, maxit=300)),
+                          (B.SMG_GMRES, lambda: o.gmres(fp, tol=1e-9))):
+        x = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+        rc, st = ctx.solve(x, f, method, rtol=1e-9, maxit=300)
+        assert rc == B.SMG_OK
+        _, its, _ = solve()
+        assert abs(st["iterations"] - its) <= 1
+
+
+def test_batch_refuses_a_domain(B):
+    p = lshape(31, 4)
+    ctx, f = B.context_from_problem(p, gmres_restart=0)
+    x = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.SmgError):
+        B.Batch([ctx], [x], [f])

@@ -284,3 +284,18 @@ def test_multigrid_inner_counts_are_mesh_independent():
         res = ssn.ssn_solve(p, 1e-2, -50.0, 50.0, linear="vcycle")
         means.append(np.mean(res["inner"]))
     assert max(means) <= 16 and abs(means[1] - means[0]) <= 3, means
+
+
+def test_solution_matches_proximal_gradient_on_the_lshape():
+    """The same independent check on the paper's L-shaped domain (nodes with
+    x, y >= 1/2 removed): u stays zero outside, and inside it is the reduced
+    problem's minimizer."""
+    p = inputs.make_problem(15, 3, 1e-3, M=3, sigma=0.5, decay=True, seed=3, yd=paper_yd(15), f=0.0,
+                            domain="lshape")
+    beta, a, b = 4e-3, -6.0, 6.0
+    res = ssn.ssn_solve(p, beta, a, b)
+    assert res["converged"]
+    outside = p.domain.ravel() == 0
+    assert np.all(res["u"][outside] == 0)
+    u_ref = fista(p, beta, a, b)
+    np.testing.assert_allclose(res["u"], u_ref, rtol=0, atol=1e-9 * np.abs(u_ref).max())
