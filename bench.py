@@ -321,36 +321,57 @@ def ssn_section(dev, n, N, args):
 
 
 def paper_tables(dev):
-    """The settings of the paper's iteration-count tables on this build's 31x31
-    grid (three levels): the Gaussian-covariance field of eq. log_normal
-    (sigma^2 = 0.5, L^2 = 0.5, M = 3) on 5^3 Gauss-Hermite collocation nodes,
-    y_d = exp(y^2) sin(2 pi x) sin(2 pi y), no source, damped collective Jacobi
-    (theta 1/2) V(2,2), tolerance 1e-9; distributed control and the L^1 problem
-    on the L-shape (N_h = 705, as printed), local control on the square
-    (N_h = 961).  Counts beside the printed ones (the paper: P1 elements)."""
+    """The settings of the paper's iteration-count tables on this build's grids
+    (finite differences; the paper: P1 elements): the Gaussian-covariance field
+    of eq. log_normal, y_d = exp(y^2) sin(2 pi x) sin(2 pi y), no source, damped
+    collective Jacobi (theta 1/2) V(2,2), tolerance 1e-9.  Distributed control
+    and the L^1 problem on the L-shape (N_h = 705 at 31x31, as printed), local
+    control on the square (N_h = 961).  Defaults of the sub-tables: nu 1e-4,
+    sigma^2 0.5, L^2 0.5 with M = 3 and 5^3 collocation nodes, 31x31 (three
+    levels); the Monte Carlo sub-tables take sigma^2 1.5, L^2 0.1, M = 15.
+    Counts beside the printed ones."""
     import numpy as np
     import torch
     from paper_2302_13680_amd import binding, inputs
-    kw = dict(M=3, sigma=float(np.sqrt(0.5)), decay=True, yd=inputs.paper_target(31), f=0.0, field="gaussian",
-              corr_len2=0.5)
-    printed = {"distributed": {1e-2: [18, 11], 1e-4: [19, 13], 1e-6: [19, 15], 1e-8: [19, 15]},
-               "local": {1e-2: [17, 11], 1e-4: [20, 13], 1e-6: [26, 16], 1e-8: [26, 18]}}
-    out = {"grid": "31x31, levels 31/15/7, N = 125", "field": "Gaussian covariance, sigma^2 0.5, L^2 0.5, M 3",
-           "smoother": "collective Jacobi theta 1/2, V(2,2)", "tol": 1e-9}
-    for case, region, dom in (("distributed", None, "lshape"), ("local", (0.25, 0.75, 0.25, 0.75), "square")):
-        rows = []
-        for nu in (1e-2, 1e-4, 1e-6, 1e-8):
-            p = inputs.collocation_problem(31, 5, nu, control_region=region, domain=dom, **kw)
-            ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5,
-                                                  flags=binding.SMG_FLAG_JACOBI)
-            x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
-            _, sv = timed_solve(ctx, x, f, binding.SMG_VCYCLE, 1e-9)
-            _, sg = timed_solve(ctx, x, f, binding.SMG_GMRES, 1e-9)
-            rows.append({"nu": nu, "vcycle": sv["iterations"], "gmres": sg["iterations"],
-                         "paper_vcycle_gmres": printed[case][nu], "nodes": int(p.domain.sum()) if dom == "lshape" else 961})
-            ctx.close()
-        out[case] = rows
-    p = inputs.collocation_problem(31, 5, 1e-4, domain="lshape", **kw)
+
+    def problem(n=31, q=5, nu=1e-4, sigma2=0.5, L2=0.5, M=3, mc=None, **kw):
+        common = dict(sigma=float(np.sqrt(sigma2)), decay=True, yd=inputs.paper_target(n), f=0.0,
+                      field="gaussian", corr_len2=L2)
+        if mc:
+            return inputs.make_problem(n, mc, nu, M=M, seed=17, **common, **kw)
+        return inputs.collocation_problem(n, q, nu, M=M, **common, **kw)
+
+    def counts(p):
+        ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5,
+                                              flags=binding.SMG_FLAG_JACOBI)
+        x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
+        _, sv = timed_solve(ctx, x, f, binding.SMG_VCYCLE, 1e-9, maxit=300)
+        _, sg = timed_solve(ctx, x, f, binding.SMG_GMRES, 1e-9, maxit=300)
+        ctx.close()
+        return [sv["iterations"], sg["iterations"]]
+
+    out = {"field": "Gaussian covariance (eq. log_normal)", "smoother": "collective Jacobi theta 1/2, V(2,2)",
+           "tol": 1e-9, "format": "[V-cycles, GMRES] (this build) beside [printed]"}
+    L = dict(domain="lshape")
+    t1 = {}
+    t1["nu"] = [{"nu": nu, "counts": counts(problem(nu=nu, **L)), "paper": pr}
+                for nu, pr in ((1e-2, [18, 11]), (1e-4, [19, 13]), (1e-6, [19, 15]), (1e-8, [19, 15]))]
+    t1["sigma2"] = [{"sigma2": s2, "counts": counts(problem(sigma2=s2, **L)), "paper": pr}
+                    for s2, pr in ((0.1, [19, 13]), (0.5, [19, 13]), (1.0, [20, 13]), (1.5, [20, 13]))]
+    t1["mesh"] = [{"n": n, "nodes": nh, "counts": counts(problem(n=n, **L)), "paper": pr}
+                  for n, nh, pr in ((15, 161, [19, 13]), (31, 705, [19, 13]), (63, 2945, [20, 13]))]
+    t1["N_collocation"] = [{"N": q ** 3, "counts": counts(problem(q=q, **L)), "paper": [19, 13]} for q in (2, 3, 4, 5)]
+    t1["N_monte_carlo"] = [{"N": N, "counts": counts(problem(mc=N, sigma2=1.5, L2=0.1, M=15, **L)), "paper": pr}
+                           for N, pr in ((100, [22, 16]), (500, [22, 15]), (1000, [22, 15]), (2000, [22, 15]))]
+    out["distributed_lshape"] = t1
+    R = dict(control_region=(0.25, 0.75, 0.25, 0.75))
+    t2 = {}
+    t2["nu"] = [{"nu": nu, "counts": counts(problem(nu=nu, **R)), "paper": pr}
+                for nu, pr in ((1e-2, [17, 11]), (1e-4, [20, 13]), (1e-6, [26, 16]), (1e-8, [26, 18]))]
+    t2["N_monte_carlo"] = [{"N": N, "counts": counts(problem(mc=N, sigma2=1.5, L2=0.1, M=15, **R)), "paper": pr}
+                           for N, pr in ((100, [20, 14]), (1000, [21, 15]), (2000, [21, 14]))]
+    out["local_square"] = t2
+    p = problem(**L)
     ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5, flags=binding.SMG_FLAG_JACOBI,
                                           ssn=True)
     x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
@@ -363,7 +384,7 @@ def paper_tables(dev):
         l1[name + "_mean_inner"] = round(float(np.mean(st["inner"])), 2) if st["inner"] else 0.0
         l1[name + "_converged"] = rc == binding.SMG_OK
     ctx.close()
-    out["l1_semismooth_newton"] = l1
+    out["l1_semismooth_newton_lshape"] = l1
     return out
 
 

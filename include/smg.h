@@ -82,7 +82,7 @@ typedef struct smg_ctx smg_ctx;
 
 typedef struct {
   int n;              /* interior nodes per direction: (coarsest_n+1) 2^k - 1 */
-  int nsamples;       /* N >= 1 (at most 512) */
+  int nsamples;       /* N >= 1 (at most 2048; the batched solver takes at most 512) */
   int coarsest_n;     /* odd, 1..7; grid of the direct solve (0 selects 7) */
   int pre, post;      /* smoothing sweeps n1, n2 per level (red + black half-sweeps each) */
   double theta;       /* relaxation of the node update (1 = Gauss-Seidel; 0 selects 1) */

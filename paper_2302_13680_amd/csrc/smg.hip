@@ -24,7 +24,7 @@ using namespace smg;
 namespace {
 
 constexpr int kMaxLevels = 16;
-constexpr int kMaxSamples = 512;
+constexpr int kMaxSamples = 2048;
 
 template <typename T>
 struct Level {
@@ -74,7 +74,9 @@ void seg_dispatch(int N, F&& fn) {
   else if (N <= 64) fn(IC<64>{}, IC<1>{});
   else if (N <= 128) fn(IC<64>{}, IC<2>{});
   else if (N <= 256) fn(IC<64>{}, IC<4>{});
-  else fn(IC<64>{}, IC<8>{});
+  else if (N <= 512) fn(IC<64>{}, IC<8>{});
+  else if (N <= 1024) fn(IC<64>{}, IC<16>{});
+  else fn(IC<64>{}, IC<32>{});
 }
 
 // Lanes per node W, samples per lane JM and samples per access VW of a
@@ -112,7 +114,9 @@ void lane_dispatch(int precision, int N, F&& fn) {
     else if (N <= 64) go(IC<32>{}, IC<2>{});
     else if (N <= 128) go(IC<64>{}, IC<2>{});
     else if (N <= 256) go(IC<64>{}, IC<4>{});
-    else go(IC<64>{}, IC<8>{});
+    else if (N <= 512) go(IC<64>{}, IC<8>{});
+    else if (N <= 1024) go(IC<64>{}, IC<16>{});
+    else go(IC<64>{}, IC<32>{});
   } else {
     seg_dispatch(N, [&](auto Wc, auto Jc) { fn(Wc, Jc, IC<1>{}); });
   }
@@ -144,7 +148,9 @@ void rr_dispatch(int precision, int N, F&& fn) {
   };
   if (M <= 128) go(IC<128>{}, IC<1>{});
   else if (M <= 256) go(IC<256>{}, IC<1>{});
-  else go(IC<256>{}, IC<2>{});
+  else if (M <= 512) go(IC<256>{}, IC<2>{});
+  else if (M <= 1024) go(IC<256>{}, IC<4>{});
+  else go(IC<256>{}, IC<8>{});
 }
 
 int count_levels(int n, int nc) {
@@ -228,7 +234,7 @@ struct Carver {
 
 bool desc_valid(const smg_desc& d, std::string* why) {
   auto fail = [&](const char* m) { if (why) *why = m; return false; };
-  if (d.nsamples < 1 || d.nsamples > kMaxSamples) return fail("nsamples must be in [1, 512]");
+  if (d.nsamples < 1 || d.nsamples > kMaxSamples) return fail("nsamples must be in [1, 2048]");
   if (d.coarsest_n < 1 || d.coarsest_n > 7 || (d.coarsest_n & 1) == 0) return fail("coarsest_n must be odd and <= 7");
   if (d.n < 1 || count_levels(d.n, d.coarsest_n) < 1) return fail("n must be (coarsest_n+1)*2^k - 1");
   if (d.pre < 0 || d.post < 0 || d.pre > 64 || d.post > 64) return fail("pre/post out of range");

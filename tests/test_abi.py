@@ -43,7 +43,7 @@ def test_workspace_bytes_validation(lib):
     assert lib.smg_workspace_bytes(C.byref(f32)) > 0
     for bad in [Desc(254, 64, 7, 2, 2, 1.0, 0, 30, 0),   # n not (nc+1)2^k - 1
                 Desc(255, 0, 7, 2, 2, 1.0, 0, 30, 0),    # no samples
-                Desc(255, 513, 7, 2, 2, 1.0, 0, 30, 0),  # too many samples
+                Desc(255, 2049, 7, 2, 2, 1.0, 0, 30, 0),  # too many samples
                 Desc(255, 64, 6, 2, 2, 1.0, 0, 30, 0),   # even coarsest grid
                 Desc(255, 64, 7, 2, 2, 2.5, 0, 30, 0),   # theta out of range
                 Desc(255, 64, 7, 2, 2, 1.0, 2, 30, 0),   # unknown precision
