@@ -388,6 +388,71 @@ def paper_tables(dev):
     return out
 
 
+def ssn_tables(dev):
+    """The settings of the paper's L^1 tables (Section 5) on the L-shape with the
+    Gaussian field, collocation nodes and the Jacobi-smoothed V-cycle: Newton
+    iterations and the mean V-cycle and GMRES iterations per Newton system
+    (merit 1e-9, systems 1e-11), beside the printed [Newton, V-cycles, GMRES].
+    Defaults: 31x31 (705 nodes), 5^3 nodes, sigma^2 0.5, L^2 0.5, nu 1e-4,
+    beta 1e-2, -50 <= u <= 50.  The nu sweep runs from u = 0 and by continuation
+    (each nu = 10^-j, j = 2..8, started from the control of the previous one)."""
+    import numpy as np
+    import torch
+    from paper_2302_13680_amd import binding, inputs
+
+    def problem(n=31, q=5, nu=1e-4, sigma2=0.5):
+        return inputs.collocation_problem(n, q, nu, M=3, sigma=float(np.sqrt(sigma2)), decay=True,
+                                          yd=inputs.paper_target(n), f=0.0, field="gaussian", corr_len2=0.5,
+                                          domain="lshape")
+
+    def run(p, beta=1e-2, u0=None, methods=("gmres", "vcycle")):
+        ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5,
+                                              flags=binding.SMG_FLAG_JACOBI, ssn=True)
+        x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
+        res = {}
+        nn = p.n * p.n
+        for name in methods:
+            method = binding.SMG_GMRES if name == "gmres" else binding.SMG_VCYCLE
+            prm = binding.ssn_params(p.nu, beta, -50.0, 50.0, (1.0 / (p.n + 1)) ** 2, inner_method=method,
+                                     maxit=100)
+            x.zero_()
+            if u0 is not None:
+                x[p.N * nn:(p.N + 1) * nn] = u0
+            rc, st = ctx.ssn_solve(x, f, prm)
+            res[name] = [st["iterations"], round(float(np.mean(st["inner"])), 1) if st["inner"] else 0.0,
+                         rc == binding.SMG_OK]
+        u = x[p.N * nn:(p.N + 1) * nn].clone()
+        ctx.close()
+        return res, u
+
+    def row(key, val, p, printed, beta=1e-2):
+        r, _ = run(p, beta)
+        return {key: val, "gmres [newton, mean its, converged]": r["gmres"],
+                "vcycle [newton, mean its, converged]": r["vcycle"], "paper": printed}
+
+    out = {"domain": "L-shape, 705 nodes at 31x31", "smoother": "collective Jacobi theta 1/2, V(2,2)"}
+    out["sigma2"] = [row("sigma2", s2, problem(sigma2=s2), pr) for s2, pr in
+                     ((0.1, [4, 22.5, 14]), (0.5, [5, 22.6, 14.2]), (1.0, [8, 23.0, 11.8]), (1.5, [14.9, 22.9, 15.0]))]
+    out["mesh"] = [row("nodes", nh, problem(n=n), pr) for n, nh, pr in
+                   ((15, 161, [5, 22.0, 15.2]), (31, 705, [5, 22.6, 14.2]), (63, 2945, [5, 22.2, 14.0]))]
+    out["N_collocation"] = [row("N", q ** 3, problem(q=q), pr) for q, pr in
+                            ((2, [5, 21.0, 13.0]), (3, [5, 21.6, 14.0]), (4, [5, 22.0, 14.0]), (5, [5, 22.6, 14.2]))]
+    out["beta"] = [row("beta", b, problem(), pr, beta=b) for b, pr in
+                   ((0.0, [4, 22.5, 14.8]), (1e-4, [4, 22.5, 14.5]), (1e-3, [5, 22.4, 14.8]), (1e-2, [5, 22.6, 14.2]))]
+    out["nu_from_zero"] = [row("nu", nu, problem(nu=nu), pr) for nu, pr in
+                           ((1e-2, [2, 23.0, 14.5]), (1e-4, [5, 22.7, 14.2]), (1e-6, [17, 25.6, 15.0]),
+                            (1e-8, [50, 41.4, 17.2]))]
+    printed_cont = {1e-2: [2, 23.0, 14.5], 1e-4: [4, 22.7, 14.2], 1e-6: [5, 22.25, 15.4], 1e-8: [8, 58.8, 20.9]}
+    cont, u = [], None
+    for j in range(2, 9):
+        nu = 10.0 ** -j
+        r, u = run(problem(nu=nu), u0=u, methods=("gmres",))
+        if nu in printed_cont:
+            cont.append({"nu": nu, "gmres [newton, mean its, converged]": r["gmres"], "paper": printed_cont[nu]})
+    out["nu_continuation"] = cont
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -518,6 +583,7 @@ def main():
     # every Newton system to 1e-11; the paper's target, no source
     ssn = ssn_section(dev, n, N, args)
     paper = paper_tables(dev)
+    paper["l1_tables"] = ssn_tables(dev)
 
     # ---------------- roofline of the dominant kernel: finest-level half-sweep
     xs = torch.zeros(dof, dtype=torch.float64, device=dev)
