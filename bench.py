@@ -350,6 +350,18 @@ def paper_tables(dev):
         ctx.close()
         return [sv["iterations"], sg["iterations"]]
 
+    def counts_or_stall(p, maxit=100):
+        """counts(), a V-cycle that stalls reported as "stall (relres after maxit)"."""
+        ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5,
+                                              flags=binding.SMG_FLAG_JACOBI)
+        res = []
+        for method in (binding.SMG_VCYCLE, binding.SMG_GMRES):
+            x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
+            rc, st = ctx.solve(x, f, method, rtol=1e-9, maxit=maxit)
+            res.append(st["iterations"] if rc == binding.SMG_OK else "stall (%.1e after %d)" % (st["relres"], maxit))
+        ctx.close()
+        return res
+
     out = {"field": "Gaussian covariance (eq. log_normal)", "smoother": "collective Jacobi theta 1/2, V(2,2)",
            "tol": 1e-9, "format": "[V-cycles, GMRES] (this build) beside [printed]"}
     L = dict(domain="lshape")
@@ -371,6 +383,25 @@ def paper_tables(dev):
     t2["N_monte_carlo"] = [{"N": N, "counts": counts(problem(mc=N, sigma2=1.5, L2=0.1, M=15, **R)), "paper": pr}
                            for N, pr in ((100, [20, 14]), (1000, [21, 15]), (2000, [21, 14]))]
     out["local_square"] = t2
+
+    def bproblem(n=63, q=5, nu=1e-4, sigma2=0.5, L2=0.5, M=3, mc=None):
+        common = dict(sigma=float(np.sqrt(sigma2)), decay=True, field="gaussian", corr_len2=L2)
+        if mc:
+            return inputs.boundary_control_problem(n, mc, nu, M=M, seed=17, **common)
+        return inputs.boundary_collocation_problem(n, q, nu, M=M, **common)
+    t3 = {"construction": "reflection across Gamma: a domain and a control on the mirror row, "
+                          "control blocks x2 per coarsening"}
+    t3["nu"] = [{"nu": nu, "counts": counts_or_stall(bproblem(nu=nu)), "paper": pr}
+                for nu, pr in ((1e-2, [17, 14]), (1e-4, [22, 15]), (1e-6, [23, 17]), (1e-8, [21, 16]))]
+    t3["sigma2"] = [{"sigma2": s2, "counts": counts(bproblem(sigma2=s2)), "paper": pr}
+                    for s2, pr in ((0.1, [16, 13]), (0.5, [17, 14]), (1.0, [17, 14]), (1.5, [17, 14]))]
+    t3["mesh"] = [{"nodes": nh, "counts": counts(bproblem(n=n)), "paper": pr}
+                  for n, nh, pr in ((31, 240, [16, 12]), (63, 992, [17, 14]), (127, 4032, [21, 16]))]
+    t3["N_collocation"] = [{"N": q ** 3, "counts": counts(bproblem(q=q)), "paper": pr}
+                           for q, pr in ((2, [16, 13]), (3, [17, 14]), (4, [17, 14]), (5, [17, 14]))]
+    t3["N_monte_carlo"] = [{"N": N, "counts": counts(bproblem(mc=N, sigma2=1.5, L2=0.1, M=15)), "paper": pr}
+                           for N, pr in ((100, [18, 15]), (1000, [19, 16]), (2000, [20, 16]))]
+    out["boundary_control"] = t3
     p = problem(**L)
     ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5, flags=binding.SMG_FLAG_JACOBI,
                                           ssn=True)

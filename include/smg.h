@@ -134,6 +134,10 @@ typedef struct {
                          lines of every level (true for the L-shape).  Values other than 0
                          and 1: SMG_EINVAL.  Not accepted by the batched solver.  NULL:
                          the whole square. */
+  double control_growth; /* factor by which d_j, e_j and g grow per coarsening (0: 4, the
+                         h^2 of an area mass, like c_j).  2 for a control on a line (the
+                         boundary control by reflection: the 1D mass h of the control
+                         line).  Other values: SMG_EINVAL unless in (0, 16]. */
 } smg_blocks;
 
 typedef struct {
@@ -236,12 +240,18 @@ int smg_jacobi(smg_ctx *ctx, int level, const double *x, double *xout, const dou
 
 /* coarse = R (f - S x) in one pass: the residual of Alg. 1 on level `level`
  * restricted to level + 1 without storing the fine residual (the result of
- * smg_residual followed by smg_restrict up to rounding order).  x, f: FP64 device vectors
+ * smg_residual followed by smg_restrict up to rounding order, except that the U
+ * block is restricted within the control space: U residuals of fine nodes without
+ * a control (factors of D_j and E_j both zero) are dropped, and a coarse node
+ * whose coincident fine node has none gets a zero U row).  x, f: FP64 device vectors
  * of level `level` (f is that level's right-hand side); coarse: level + 1.
  * SMG_EINVAL if `level` has no coarser level. */
 int smg_residual_restrict(smg_ctx *ctx, int level, const double *x, const double *f, double *coarse);
 
-/* fine += P coarse (bilinear interpolation; Alg. 1 coarse correction). */
+/* fine += P coarse (bilinear interpolation; Alg. 1 coarse correction).  The U
+ * block is prolongated into the control space only: fine nodes whose factors
+ * of D_j and E_j are both zero (no control there, e.g. outside a local control
+ * region or off a boundary-control line) keep their u. */
 int smg_prolong_add(smg_ctx *ctx, int level, const double *coarse, double *fine);
 
 /* X = S^{-1} F on the coarsest level (Alg. 1 direct solver), FP64. */

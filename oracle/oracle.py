@@ -45,6 +45,8 @@ def _load():
     L.or_set_smoother.argtypes = [vp, C.c_int]
     L.or_set_control.restype = C.c_int
     L.or_set_control.argtypes = [vp, _dp]
+    L.or_set_control_growth.restype = C.c_int
+    L.or_set_control_growth.argtypes = [vp, C.c_double]
     L.or_set_domain.restype = C.c_int
     L.or_set_domain.argtypes = [vp, _dp]
     L.or_set_masks.restype = C.c_int
@@ -65,6 +67,8 @@ def _load():
     L.or_halfsweep32.argtypes = [vp, C.c_int, C.c_int, C.c_double, _dp, _dp]
     L.or_jacobi.argtypes = [vp, C.c_int, C.c_double, _dp, _dp]
     L.or_restrict.argtypes = [C.c_int, C.c_int, _dp, _dp]
+    L.or_residual_restrict.argtypes = [vp, C.c_int, _dp, _dp, _dp]
+    L.or_prolong_control.argtypes = [vp, C.c_int, _dp, _dp]
     L.or_prolong_add.argtypes = [C.c_int, C.c_int, _dp, _dp]
     L.or_coarsen_faces.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
     L.or_coarse_solve.argtypes = [vp, _dp, _dp]
@@ -150,6 +154,9 @@ class Oracle:
         if not self.ctx:
             raise ValueError("oracle: invalid grid size or singular coarsest block")
         L.or_set_smoother(self.ctx, 1 if smoother == "jacobi" else 0)
+        growth = float((getattr(prob, "meta", None) or {}).get("control_growth", 0.0))
+        if growth and L.or_set_control_growth(self.ctx, growth) != 0:
+            raise ValueError("oracle: singular coarsest block with this control growth")
         if getattr(prob, "domain", None) is not None:
             if L.or_set_domain(self.ctx, _f64(prob.domain)) != 0:
                 raise ValueError("oracle: singular coarsest block with this domain")
@@ -218,6 +225,21 @@ class Oracle:
         out = np.zeros(self.vlen(l))
         _load().or_residual(self.ctx, l, _f64(x), _f64(f), out)
         return out
+
+    def residual_restrict(self, x, f, l: int = 0):
+        """The coarse right-hand side of Alg. 1 from level l: R (f - S x), the U
+        block restricted within the control space (nodes whose D and E factors
+        are not both zero), zero outside the domain."""
+        out = np.zeros(self.vlen(l + 1))
+        _load().or_residual_restrict(self.ctx, l, _f64(x), _f64(f), out)
+        return out
+
+    def prolong_control(self, coarse, fine, l: int = 0):
+        """fine (level l) + P coarse, the U block prolongated into the control
+        space only."""
+        fine = _f64(fine).copy()
+        _load().or_prolong_control(self.ctx, l, _f64(coarse), fine)
+        return fine
 
     def halfsweep(self, x, f, colour: int, l: int = 0, theta: float = 1.0):
         x = _f64(x).copy()

@@ -230,6 +230,35 @@ static void SFX(zero_outside)(const SFX(or_lvl) *L, REAL *v) {
       if (!SFX(or_live)(L, i)) v[b * nn + i] = 0;
 }
 
+/* Node i of level L carries a control: a U unknown coupled to the state and
+ * adjoint rows (its md or me factor nonzero, inside the domain).  The control
+ * space U_h spans the basis functions of these nodes only (Section 2: a local
+ * or a boundary control lives on part of the mesh), so the multigrid transfer
+ * of the U block stays inside it. */
+static inline int SFX(or_control)(const SFX(or_lvl) *L, size_t i) {
+  return SFX(or_mask_d)(L, i) != (REAL)0 || SFX(or_mask_e)(L, i) != (REAL)0;
+}
+
+/* U block of the fine-level residual r zeroed at nodes without a control:
+ * restriction of the control residual is the transpose of the control
+ * prolongation below. */
+static void SFX(control_residual)(const SFX(or_lvl) *L, REAL *r) {
+  size_t nn = (size_t)L->n * L->n;
+  REAL *U = r + (size_t)L->N * nn;
+  for (size_t i = 0; i < nn; ++i)
+    if (!SFX(or_control)(L, i)) U[i] = 0;
+}
+
+/* U block of the restricted residual fc (level nc) zeroed at coarse nodes
+ * whose coincident fine node (level F) has no control: the coarse control
+ * space is that of the fine level taken at the coarse nodes. */
+static void SFX(control_coarse_rows)(const SFX(or_lvl) *F, int nc, REAL *fc) {
+  REAL *U = fc + (size_t)F->N * nc * nc;
+  for (int K = 0; K < nc; ++K)
+    for (int X = 0; X < nc; ++X)
+      if (!SFX(or_control)(F, (size_t)(2 * K + 1) * F->n + (2 * X + 1))) U[(size_t)K * nc + X] = 0;
+}
+
 /* 1D weights of bilinear interpolation: w(0)=1, w(+-1)=1/2. */
 static inline REAL SFX(or_w)(int d) { return d == 0 ? (REAL)1 : (REAL)0.5; }
 
@@ -253,8 +282,10 @@ static void SFX(or_restrict)(int nf, int N, const REAL *fine, REAL *coarse) {
   }
 }
 
-/* fine += P coarse, P bilinear interpolation (Alg. 1, coarse correction). */
-static void SFX(or_prolong_add)(int nc, int N, const REAL *coarse, REAL *fine) {
+/* fine += P coarse, P bilinear interpolation (Alg. 1, coarse correction).
+ * With the fine level Lf given, the U block is prolongated into the control
+ * space only: fine nodes without a control (or_control) keep their u. */
+static void SFX(or_prolong_add)(int nc, int N, const REAL *coarse, REAL *fine, const SFX(or_lvl) *Lf) {
   int nf = 2 * nc + 1;
   size_t nnf = (size_t)nf * nf, nnc = (size_t)nc * nc;
   for (int b = 0; b < 2 * N + 1; ++b) {
@@ -263,8 +294,10 @@ static void SFX(or_prolong_add)(int nc, int N, const REAL *coarse, REAL *fine) {
     for (int K = 0; K < nc; ++K)
       for (int X = 0; X < nc; ++X)
         for (int dk = -1; dk <= 1; ++dk)
-          for (int dx = -1; dx <= 1; ++dx)
-            F[(size_t)(2 * K + 1 + dk) * nf + (2 * X + 1 + dx)] +=
-                SFX(or_w)(dx) * SFX(or_w)(dk) * C[(size_t)K * nc + X];
+          for (int dx = -1; dx <= 1; ++dx) {
+            size_t i = (size_t)(2 * K + 1 + dk) * nf + (2 * X + 1 + dx);
+            if (b == N && Lf && !SFX(or_control)(Lf, i)) continue;
+            F[i] += SFX(or_w)(dx) * SFX(or_w)(dk) * C[(size_t)K * nc + X];
+          }
   }
 }

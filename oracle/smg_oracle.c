@@ -357,6 +357,29 @@ int or_set_domain(or_ctx *C, const double *dom) {
   return or_coarse_setup(C);
 }
 
+/* Rediscretized control blocks for a control on a line: D_j, E_j and G of level
+ * l >= 1 become growth^l times the finest ones (growth 2: the 1D mass of the
+ * control line doubles with the spacing; or_create's default 4 is the h^2 of an
+ * area mass, as for C_j).  The coarsest factorization is rebuilt.  Returns 0,
+ * -1 if singular or growth is not positive. */
+int or_set_control_growth(or_ctx *C, double growth) {
+  if (!(growth > 0.0)) return -1;
+  for (int l = 1; l < C->nlev; ++l) {
+    for (int j = 0; j < C->N; ++j) {
+      C->d[l][j] = growth * C->d[l - 1][j];
+      C->e[l][j] = growth * C->e[l - 1][j];
+      C->d32[l][j] = (float)C->d[l][j];
+      C->e32[l][j] = (float)C->e[l][j];
+    }
+    C->g[l] = growth * C->g[l - 1];
+    C->L[l].g = C->g[l];
+    C->L32[l].g = (float)C->g[l];
+  }
+  free(C->Ainv); free(C->Sinv); free(C->cw);
+  C->Ainv = C->Sinv = C->cw = NULL;
+  return or_coarse_setup(C);
+}
+
 /* Control acting only where mask[i] != 0 (local control; eq.
  * solution_reduced_system2 at nodes without control): the node entries of D_j
  * and E_j become mask_i d_j and mask_i e_j.  mask NULL: control everywhere. */
@@ -402,7 +425,20 @@ void or_jacobi(const or_ctx *C, int l, double theta, double *x, const double *f)
   or_jacobi_f64(&C->L[l], theta, x, f);
 }
 void or_restrict(int nf, int N, const double *fine, double *coarse) { or_restrict_f64(nf, N, fine, coarse); }
-void or_prolong_add(int nc, int N, const double *coarse, double *fine) { or_prolong_add_f64(nc, N, coarse, fine); }
+void or_prolong_add(int nc, int N, const double *coarse, double *fine) { or_prolong_add_f64(nc, N, coarse, fine, NULL); }
+/* The coarse right-hand side of Alg. 1 from level l: R (f - S x) with the U
+ * block restricted within the control space, zero outside the domain. */
+void or_residual_restrict(or_ctx *C, int l, const double *x, const double *f, double *coarse) {
+  or_residual_f64(&C->L[l], x, f, C->rw[l]);
+  control_residual_f64(&C->L[l], C->rw[l]);
+  or_restrict_f64(C->n[l], C->N, C->rw[l], coarse);
+  control_coarse_rows_f64(&C->L[l], C->n[l + 1], coarse);
+  zero_outside_f64(&C->L[l + 1], coarse);
+}
+/* fine (level l) += P coarse, the U block into the control space only. */
+void or_prolong_control(const or_ctx *C, int l, const double *coarse, double *fine) {
+  or_prolong_add_f64(C->n[l + 1], C->N, coarse, fine, &C->L[l]);
+}
 void or_node_solve(int N, const double *a, const double *c, const double *d, const double *e, double g,
                    const double *bP, double bU, const double *bY, double *y, double *u, double *p) {
   or_node_solve_f64(N, a, c, d, e, g, bP, bU, bY, y, u, p);
@@ -440,11 +476,13 @@ static void vcycle_f64(or_ctx *C, int l, double *x, const double *f) {
   const or_lvl_f64 *L = &C->L[l];
   for (int s = 0; s < C->pre; ++s) smooth_f64(C, L, x, f);
   or_residual_f64(L, x, f, C->rw[l]);
+  control_residual_f64(L, C->rw[l]);
   or_restrict_f64(C->n[l], C->N, C->rw[l], C->fw[l + 1]);
+  control_coarse_rows_f64(L, C->n[l + 1], C->fw[l + 1]);
   zero_outside_f64(&C->L[l + 1], C->fw[l + 1]);
   memset(C->xw[l + 1], 0, sizeof(double) * vlen(C->n[l + 1], C->N));
   vcycle_f64(C, l + 1, C->xw[l + 1], C->fw[l + 1]);
-  or_prolong_add_f64(C->n[l + 1], C->N, C->xw[l + 1], x);
+  or_prolong_add_f64(C->n[l + 1], C->N, C->xw[l + 1], x, L);
   for (int s = 0; s < C->post; ++s) smooth_f64(C, L, x, f);
 }
 
@@ -463,11 +501,13 @@ static void vcycle_f32(or_ctx *C, int l, float *x, const float *f) {
   const or_lvl_f32 *L = &C->L32[l];
   for (int s = 0; s < C->pre; ++s) smooth_f32(C, L, x, f);
   or_residual_f32(L, x, f, C->rw32[l]);
+  control_residual_f32(L, C->rw32[l]);
   or_restrict_f32(C->n[l], N, C->rw32[l], C->fw32[l + 1]);
+  control_coarse_rows_f32(L, C->n[l + 1], C->fw32[l + 1]);
   zero_outside_f32(&C->L32[l + 1], C->fw32[l + 1]);
   memset(C->xw32[l + 1], 0, sizeof(float) * vlen(C->n[l + 1], N));
   vcycle_f32(C, l + 1, C->xw32[l + 1], C->fw32[l + 1]);
-  or_prolong_add_f32(C->n[l + 1], N, C->xw32[l + 1], x);
+  or_prolong_add_f32(C->n[l + 1], N, C->xw32[l + 1], x, L);
   for (int s = 0; s < C->post; ++s) smooth_f32(C, L, x, f);
 }
 

@@ -46,7 +46,8 @@ class Desc(C.Structure):
 class Blocks(C.Structure):
     _fields_ = [("kx", C.c_void_p), ("ky", C.c_void_p), ("c", C.POINTER(C.c_double)),
                 ("d", C.POINTER(C.c_double)), ("e", C.POINTER(C.c_double)), ("g", C.c_double),
-                ("ctrl", C.POINTER(C.c_double)), ("domain", C.POINTER(C.c_double))]
+                ("ctrl", C.POINTER(C.c_double)), ("domain", C.POINTER(C.c_double)),
+                ("control_growth", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -195,11 +196,13 @@ class Context:
     kx, ky: float64 device tensors in the node layout ([n][n+1][N], [n+1][n][N]);
     c, d, e: per-sample diagonal values (host sequences), g: scalar; ctrl: optional
     (n, n) host control mask in [0, 1] (local control), None: control everywhere; domain:
-    optional (n, n) host 0/1 mask of the domain (the L-shape), None: the square.
+    optional (n, n) host 0/1 mask of the domain (the L-shape), None: the square;
+    control_growth: per-coarsening factor of d, e, g (0: 4; 2 for a control on a line).
     """
 
     def __init__(self, n, N, kx, ky, c, d, e, g, *, coarsest_n=7, pre=2, post=2, theta=1.0,
-                 precision=SMG_F64, gmres_restart=30, flags=0, strip=0, stream=None, ctrl=None, domain=None):
+                 precision=SMG_F64, gmres_restart=30, flags=0, strip=0, stream=None, ctrl=None, domain=None,
+                 control_growth=0.0):
         import torch
         L = load()
         self.L = L
@@ -221,7 +224,7 @@ class Context:
         blocks = Blocks(_ptr(kx), _ptr(ky), self._c.ctypes.data_as(dp), self._d.ctypes.data_as(dp),
                         self._e.ctypes.data_as(dp), float(g),
                         None if self._ctrl is None else self._ctrl.ctypes.data_as(dp),
-                        None if self._dom is None else self._dom.ctypes.data_as(dp))
+                        None if self._dom is None else self._dom.ctypes.data_as(dp), float(control_growth))
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = C.c_void_p()
         rc = L.smg_setup(C.byref(self.desc), C.byref(blocks), _ptr(self.workspace), nbytes,
@@ -512,6 +515,7 @@ def context_from_problem(prob, device="cuda", ssn=False, **kw):
     ky = torch.from_numpy(kyn).to(device)
     kw.setdefault("ctrl", getattr(prob, "ctrl", None))
     kw.setdefault("domain", getattr(prob, "domain", None))
+    kw.setdefault("control_growth", float((getattr(prob, "meta", None) or {}).get("control_growth", 0.0)))
     g, d = prob.g, prob.d
     if ssn:
         g, d = prob.g / prob.nu, np.asarray(prob.d) / prob.nu

@@ -54,14 +54,28 @@ __device__ __forceinline__ bool node_live(const NodeFactors<T>& f) {
   return !signbit(f.e);
 }
 
-// node factors of node i, one 2-element load; kernels compiled with MK = false
-// (contexts whose factors are all 1) use 1 without a load
+// A node with a control: a U unknown coupled to the state and adjoint rows
+// (md or me nonzero; never outside the domain).  The control space spans these
+// nodes only, so restriction and prolongation of the U block stay inside it.
+template <typename T>
+__device__ __forceinline__ bool node_control(const NodeFactors<T>& f) {
+  return f.d != T(0) || f.e != T(0);
+}
+
+// the factor pair of node i from a [n][n][2] array, one 2-element load
+template <typename T>
+__device__ __forceinline__ NodeFactors<T> load_factors(const T* __restrict__ mk, size_t i) {
+  using V = typename std::conditional<std::is_same<T, double>::value, double2, float2>::type;
+  const V v = *reinterpret_cast<const V*>(mk + 2 * i);
+  return {v.x, v.y};
+}
+
+// node factors of node i; kernels compiled with MK = false (contexts whose
+// factors are all 1) use 1 without a load
 template <bool MK, typename T>
 __device__ __forceinline__ NodeFactors<T> node_factors(const LevelArgs<T>& L, size_t i) {
   if constexpr (MK) {
-    using V = typename std::conditional<std::is_same<T, double>::value, double2, float2>::type;
-    const V v = *reinterpret_cast<const V*>(L.mk + 2 * i);
-    return {v.x, v.y};
+    return load_factors(L.mk, i);
   } else {
     return {T(1), T(1)};
   }

@@ -581,14 +581,36 @@ int residual_restrict(smg_ctx* C, const Level<T>& L, const T* x, const T* f, T* 
   return SMG_OK;
 }
 
+// fine += P coarse; fmk: the fine level's node factors (the U block is
+// prolongated into the control space only)
 template <typename T>
-int prolong_add(smg_ctx* C, int nc, const T* coarse, T* fine) {
+int prolong_add(smg_ctx* C, int nc, const T* coarse, T* fine, const T* fmk) {
   const int nf = 2 * nc + 1;
   lane_dispatch<false>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     const int per = kBlock / W, nb = (nf * nf + per - 1) / per;
-    hipLaunchKernelGGL((k_prolong_add<T, W, JM>), dim3(nb), dim3(kBlock), 0, C->stream, nc, C->N, coarse, fine);
+    mask_dispatch(C->masked, [&](auto Mc) {
+      hipLaunchKernelGGL((k_prolong_add<T, W, JM, decltype(Mc)::value>), dim3(nb), dim3(kBlock), 0, C->stream, nc,
+                         C->N, coarse, fine, fmk);
+    });
   });
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+// The unfused restriction's control space, as the fused residual-restriction
+// has it: U entries of the fine residual r (level F; before restricting) or of
+// the restricted coarse vector fc (after) zeroed at nodes without a control.
+template <typename T>
+int control_rows(smg_ctx* C, const Level<T>& F, T* r, T* fc) {
+  if (!C->masked) return SMG_OK;
+  const int nf = F.n, nc = (nf - 1) / 2, N = C->N;
+  if (r)
+    hipLaunchKernelGGL(k_control_rows<T>, dim3((nf * nf + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, nf, 1,
+                       nf, (const T*)F.mk, r + (size_t)N * nf * nf);
+  if (fc)
+    hipLaunchKernelGGL(k_control_rows<T>, dim3((nc * nc + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, nc, 2,
+                       nf, (const T*)F.mk, fc + (size_t)N * nc * nc);
   LAUNCH_CHECK();
   return SMG_OK;
 }
@@ -639,10 +661,12 @@ int vcycle_level_jacobi(smg_ctx* C, Level<T>* Ls, T* t, int l, T* x, const T* f,
     TRY(residual_restrict<T>(C, L, x, f, Lc.f));
   } else {
     TRY((residual<T, T, T>(C, L, x, f, t, 0, false)));
+    TRY(control_rows<T>(C, L, t, nullptr));
     TRY(restrict_to<T>(C, L.n, t, Lc.f));
+    TRY(control_rows<T>(C, L, nullptr, Lc.f));
   }
   TRY(vcycle_level_jacobi<T>(C, Ls, t, l + 1, Lc.x, Lc.f, true));
-  TRY(prolong_add<T>(C, Lc.n, Lc.x, x));
+  TRY(prolong_add<T>(C, Lc.n, Lc.x, x, L.mk));
   return jacobi_steps<T>(C, L, x, t, f, C->desc.post);
 }
 
@@ -671,7 +695,9 @@ int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f, bool x
     TRY(residual_restrict<T>(C, L, x, f, Lc.f));
   } else {
     TRY((residual<T, T, T>(C, L, x, f, r, 0, false)));
+    TRY(control_rows<T>(C, L, r, nullptr));
     TRY(restrict_to<T>(C, L.n, r, Lc.f));
+    TRY(control_rows<T>(C, L, nullptr, Lc.f));
   }
   TRY(vcycle_level<T>(C, Ls, r, l + 1, Lc.x, Lc.f, true));
   int p0 = 0;
@@ -680,7 +706,7 @@ int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f, bool x
     TRY(halfsweep<T>(C, L, x, f, 1));
     p0 = 1;
   } else {
-    TRY(prolong_add<T>(C, Lc.n, Lc.x, x));
+    TRY(prolong_add<T>(C, Lc.n, Lc.x, x, L.mk));
   }
   for (int s = p0; s < C->desc.post; ++s) {
     TRY(halfsweep<T>(C, L, x, f, 0));
@@ -1377,6 +1403,7 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
   const int N = d.nsamples;
   // node denominators g + sum_j d_j c_j e_j / a_j^2 stay positive for every a_j > 0
   if (!(B->g > 0.0) || !std::isfinite(B->g)) return SMG_ESINGULAR;
+  if (B->control_growth != 0.0 && !(B->control_growth > 0.0 && B->control_growth <= 16.0)) return SMG_EINVAL;
   for (int j = 0; j < N; ++j) {
     if (!(B->c[j] > 0.0) || !std::isfinite(B->c[j]) || !std::isfinite(B->d[j]) || !std::isfinite(B->e[j]))
       return SMG_ESINGULAR;
@@ -1418,6 +1445,7 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
   C->L64[0].ky = const_cast<double*>(B->ky);
   std::vector<double> cc(B->c, B->c + N), dd(B->d, B->d + N), ee(B->e, B->e + N);
   double g = B->g;
+  const double growth = B->control_growth == 0.0 ? 4.0 : B->control_growth;
   std::vector<float> cf(N), df(N), ef(N);
   for (int l = 0; l < C->nlev; ++l) {
     Level<double>& L = C->L64[l];
@@ -1435,9 +1463,10 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
           hipMemcpy(M.e, ef.data(), sizeof(float) * N, hipMemcpyHostToDevice) != hipSuccess)
         return fail(SMG_EHIP);
     }
-    // mass-type blocks carry h^2: x4 per coarsening
-    for (int j = 0; j < N; ++j) { cc[j] *= 4.0; dd[j] *= 4.0; ee[j] *= 4.0; }
-    g *= 4.0;
+    // the state mass carries h^2 (x4 per coarsening); the control blocks grow by
+    // control_growth (x4 too for an area control, x2 for a control on a line)
+    for (int j = 0; j < N; ++j) { cc[j] *= 4.0; dd[j] *= growth; ee[j] *= growth; }
+    g *= growth;
   }
   const size_t fx0 = (size_t)d.n * (d.n + 1) * N;
   if (hipMemsetAsync(C->flag, 0, sizeof(int), C->stream) != hipSuccess) return fail(SMG_EHIP);
@@ -1571,7 +1600,7 @@ int smg_jacobi(smg_ctx* C, int level, const double* x, double* xout, const doubl
 int smg_prolong_add(smg_ctx* C, int level, const double* coarse, double* fine) {
   if (!C || !fine || !coarse) return SMG_EINVAL;
   TRY(check_level(C, level, 1));
-  return prolong_add<double>(C, C->L64[level + 1].n, coarse, fine);
+  return prolong_add<double>(C, C->L64[level + 1].n, coarse, fine, C->L64[level].mk);
 }
 
 int smg_coarse_solve(smg_ctx* C, const double* F, double* X) {

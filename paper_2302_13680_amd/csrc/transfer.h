@@ -211,7 +211,10 @@ __device__ __forceinline__ T residual_restrict_rows(const LevelArgs<T>& L, const
 }
 
 // U row of coarse node (X, K): sum_f w_f (f_U(f) - g u(f)) - D, with D the
-// group's sum of the residual_restrict_rows partials.
+// group's sum of the residual_restrict_rows partials.  The U residual is
+// restricted within the control space: fine nodes without a control carry
+// weight 0, and a coarse node whose coincident fine node has none gets a zero
+// U row (coarse factors by injection: the coarse node has none either).
 template <typename T, bool MK = true>
 __device__ __forceinline__ void residual_restrict_urow(const LevelArgs<T>& L, const T* __restrict__ x,
                                                        const T* __restrict__ f, T* __restrict__ coarse, int X,
@@ -227,11 +230,11 @@ __device__ __forceinline__ void residual_restrict_urow(const LevelArgs<T>& L, co
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const size_t o = (size_t)(kc - 1 + i) * n + (xc - 1 + k);
-      const T w = node_live(node_factors<MK>(L, o)) ? (T)(lin_w(k - 1) * lin_w(i - 1)) : T(0);
+      const T w = node_control(node_factors<MK>(L, o)) ? (T)(lin_w(k - 1) * lin_w(i - 1)) : T(0);
       sU += w * (fU[o] - L.g * U[o]);
     }
-  const bool clive = node_live(node_factors<MK>(L, (size_t)kc * n + xc));
-  coarse[(size_t)N * nc * nc + (size_t)K * nc + X] = clive ? sU - D : T(0);
+  const bool cctrl = node_control(node_factors<MK>(L, (size_t)kc * n + xc));
+  coarse[(size_t)N * nc * nc + (size_t)K * nc + X] = cctrl ? sU - D : T(0);
 }
 
 // Group of W <= 64 lanes (one wave or part of one) per coarse node.
@@ -278,6 +281,18 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(LevelArgs<T> L, co
   }
 }
 
+// U entries of the n x n level vector u zeroed at nodes without a control,
+// read from factors mk of an nm x nm level at node (s k + s - 1, s x + s - 1)
+// (s = 1: the same level; s = 2: the coincident node of the finer level).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_control_rows(int n, int s, int nm, const T* __restrict__ mk,
+                                                         T* __restrict__ u) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n * n) return;
+  const int k = i / n, x = i - k * n;
+  if (!node_control(load_factors(mk, (size_t)(s * k + s - 1) * nm + (s * x + s - 1)))) u[i] = T(0);
+}
+
 template <typename T, int W, int JM, int VW>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nf, int N, const T* __restrict__ fine,
                                                      T* __restrict__ coarse, int cstrip) {
@@ -289,10 +304,11 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nf, int N, const T* __r
   restrict_node<T, JM, VW>(nf, N, fine, coarse, slot, lane, W, cstrip);
 }
 
-// fine += P coarse, bilinear interpolation gathered per fine node.
-template <typename T, int W, int JM>
+// fine += P coarse, bilinear interpolation gathered per fine node; with MK the
+// U block only at fine nodes with a control (fmk: the fine level's factors).
+template <typename T, int W, int JM, bool MK>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(int nc, int N, const T* __restrict__ coarse,
-                                                        T* __restrict__ fine) {
+                                                        T* __restrict__ fine, const T* __restrict__ fmk) {
   const int nf = 2 * nc + 1;
   const size_t nnf = (size_t)nf * nf, nnc = (size_t)nc * nc;
   const int b = xcd_remap(blockIdx.x, group_blocks<W>((int)nnf));
@@ -333,6 +349,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(int nc, int N, const T* 
     }
   }
   if (lane == 0) {
+    if constexpr (MK) {
+      if (!node_control(load_factors(fmk, slot))) return;
+    }
     const T* cU = coarse + (size_t)N * nnc;
     T sU = 0;
     for (int a = 0; a < nk; ++a)

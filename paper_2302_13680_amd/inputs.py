@@ -270,6 +270,80 @@ def paper_target(n: int) -> np.ndarray:
     return np.exp(Y ** 2) * np.sin(2 * math.pi * X) * np.sin(2 * math.pi * Y)
 
 
+def boundary_control_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 3, sigma: float = 0.5,
+                             decay: bool = True, seed: int = 0, field: str = "sine", corr_len2: float = 0.5,
+                             weights: np.ndarray | None = None, xi: np.ndarray | None = None,
+                             f: float = 0.0) -> Problem:
+    """Neumann boundary control on Gamma = (0,1) x {0} of the unit square (the
+    paper's boundary-control table), Dirichlet on the rest of the boundary.
+
+    Built by reflection: the state and adjoint extend evenly across Gamma to the
+    rectangle (0,1) x (-1,1), where the boundary control becomes a control on the
+    mirror line.  That rectangle is the left half (the domain; the right half is
+    removed) of an n x n grid of the square (0,1)^2 scaled by 2, so the physical
+    spacing is h = 2/(n+1): 15x16, 31x32 and 63x64 physical nodes (the paper's
+    N_h = 240, 992, 4032) for n = 31, 63, 127; the mirror row is a grid line of
+    every level.  Restricted to y >= 0 the even system is the half-cell
+    discretization of the Neumann row (half faces along Gamma, half mass, boundary
+    flux h u).  Blocks: C_j = zeta_j h^2 I, D_j = E_j = -2 h (the line source of
+    both halves), G = 2 nu h (the doubled cost), the control acting on the mirror
+    row only; on coarse levels D_j, E_j and G grow x2 per coarsening (the 1D mass
+    of a line, meta["control_growth"]) while C_j grows x4; kappa, y_d (the paper's target) and f taken at (x, |y|).  The
+    coefficient models are those of ``make_problem`` evaluated at physical
+    points; the solution's U block on the mirror row is the boundary control, its
+    Y and P blocks above it (and on it) the state and the adjoint."""
+    if n < 3 or (n + 1) % 4:
+        raise ValueError("n + 1 must be a multiple of 4")
+    H = 2.0 / (n + 1)                                   # physical spacing
+    if xi is None:
+        xi = np.random.default_rng(seed).standard_normal((N, M))
+    xi = np.asarray(xi, dtype=np.float64)
+    zeta = np.full(N, 1.0 / N) if weights is None else np.asarray(weights, dtype=np.float64)
+    g_nodes = (np.arange(n) + 1.0) / (n + 1)            # grid coordinates in (0, 1)
+    g_faces = (np.arange(n + 1) + 0.5) / (n + 1)
+    px = lambda X: 2.0 * X                              # physical x
+    py = lambda Y: np.abs(2.0 * Y - 1.0)                # physical |y|
+
+    def log_field(X, Y):
+        if field == "gaussian":
+            kl = gaussian_kl(xi.shape[1], corr_len2)
+            coef = sigma * np.sqrt(kl["lam"])[None, :] * xi
+            return np.tensordot(coef, kl_modes(kl, px(X), py(Y)), axes=1)
+        if field != "sine":
+            raise ValueError(field)
+        return log_kappa(xi, kl_amplitudes(xi.shape[1], sigma, decay), px(X), py(Y))
+
+    FX, KY_ = np.meshgrid(g_faces, g_nodes)
+    kx = np.exp(log_field(FX, KY_))
+    XN, GF = np.meshgrid(g_nodes, g_faces)
+    ky = np.exp(log_field(XN, GF))
+    XX, YY = np.meshgrid(g_nodes, g_nodes)
+    xp, yp = px(XX), py(YY)
+    ydv = np.exp(yp ** 2) * np.sin(2 * math.pi * xp) * np.sin(2 * math.pi * yp)
+    mid = (n + 1) // 2 - 1                              # the mirror row (y = 0)
+    dom = (XX < 0.5 - 1e-12).astype(np.float64)         # x < 1
+    ctrl = np.zeros((n, n))
+    ctrl[mid, :] = dom[mid, :]
+    c = zeta * H * H
+    d = np.full(N, -2.0 * H)
+    e = np.full(N, -2.0 * H)
+    g = 2.0 * nu * H
+    fY = (zeta * H * H)[:, None, None] * (ydv * dom)[None]
+    fU = np.zeros((n, n))
+    fP = np.full((N, n, n), H * H * f) * dom[None]
+    return Problem(n=n, N=N, nu=nu, kx=np.ascontiguousarray(kx), ky=np.ascontiguousarray(ky), c=c, d=d, e=e, g=g,
+                   fY=fY, fU=fU, fP=fP, xi=xi, yd=ydv, ctrl=ctrl, domain=dom,
+                   meta=dict(M=xi.shape[1], sigma=sigma, decay=decay, seed=seed, f=f, field=field,
+                             boundary_control=True, h=H, mirror_row=mid, control_growth=2.0,
+                             quadrature="mc" if weights is None else "weights"))
+
+
+def boundary_collocation_problem(n: int, q: int, nu: float = 1e-4, *, M: int = 3, **kw) -> Problem:
+    """``boundary_control_problem`` with q^M tensor Gauss-Hermite nodes and weights."""
+    xi, zeta = stochastic_collocation(M, q)
+    return boundary_control_problem(n, xi.shape[0], nu, M=M, xi=xi, weights=zeta, **kw)
+
+
 def random_yd(n: int, rng: np.random.Generator, terms: int = 3, kmax: int = 4) -> np.ndarray:
     """Target state drawn as a random sum of ``terms`` sine products
     sum_t c_t sin(k_t pi x) sin(l_t pi y), c_t ~ U[-1, 1], k_t, l_t ~ U{1..kmax}."""

@@ -75,5 +75,7 @@ def test_setup_rejects_bad_arguments_before_any_launch(lib):
     dd = (C.c_double * 8)(*([-1.0] * 8))
     b = Blocks(C.c_void_p(256), C.c_void_p(256), c, dd, dd, -1.0)   # g < 0: rejected on the host
     assert lib.smg_setup(C.byref(d), C.byref(b), C.c_void_p(256), 1 << 30, None, C.byref(out)) == -2
+    b = Blocks(C.c_void_p(256), C.c_void_p(256), c, dd, dd, 1.0, None, None, -2.0)   # control growth <= 0
+    assert lib.smg_setup(C.byref(d), C.byref(b), C.c_void_p(256), 1 << 30, None, C.byref(out)) == -1
     b = Blocks(C.c_void_p(256), C.c_void_p(256), c, dd, dd, 1.0)
     assert lib.smg_setup(C.byref(d), C.byref(b), None, 0, None, C.byref(out)) == -5

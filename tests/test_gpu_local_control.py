@@ -75,7 +75,11 @@ def test_masked_steps(B, O, n, N):
         fl = rng.standard_normal(o.vlen(l))
         cd = torch.empty(o.vlen(l + 1), dtype=torch.float64, device="cuda")
         ctx.residual_restrict(l, dev(paper_to_node(xl, nl, N)), dev(paper_to_node(fl, nl, N)), cd)
-        assert rel(node_to_paper(host(cd), nc, N), O.restrict(nl, N, o.residual(xl, fl, l))) <= 1e-14, l
+        assert rel(node_to_paper(host(cd), nc, N), o.residual_restrict(xl, fl, l)) <= 1e-14, l
+        cl = rng.standard_normal(o.vlen(l + 1))
+        fd = dev(paper_to_node(xl, nl, N))
+        ctx.prolong_add(l, dev(paper_to_node(cl, nc, N)), fd)
+        assert rel(node_to_paper(host(fd), nl, N), o.prolong_control(cl, xl, l)) <= 1e-14, l
     F = rng.standard_normal(o.vlen(o.nlev - 1))
     X = torch.empty(F.size, dtype=torch.float64, device="cuda")
     nc = o.levels_n[-1]

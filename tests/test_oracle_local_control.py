@@ -139,3 +139,40 @@ def test_masked_coarse_solve_is_a_dense_solve(oracle_mod, N):
     F = np.random.default_rng(N).standard_normal(o.vlen(l))
     ref = np.linalg.solve(S, F)
     assert np.linalg.norm(o.coarse_solve(F) - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_control_space_transfer(oracle_mod):
+    """The U block moves between levels within the control space (the control
+    lives on the region's nodes only): the oracle's coarse right-hand side and
+    correction equal the plain full-weighting restriction and bilinear
+    prolongation with the U entries of nodes outside the region dropped (the
+    coarse node keeping the region of the fine node it coincides with), and the
+    two are transposes of each other on the U block."""
+    n, N = 31, 3
+    p = _prob(n, N, seed=7)
+    o = oracle_mod.Oracle(p)
+    rng = np.random.default_rng(3)
+    nc, nn, nnc = 15, n * n, 15 * 15
+    ctrl = p.ctrl.reshape(nn) != 0
+    cctrl = p.ctrl[1::2, 1::2].reshape(nnc) != 0
+    x = rng.standard_normal(o.vlen(0))
+    f = rng.standard_normal(o.vlen(0))
+    r = o.residual(x, f)
+    r[N * nn:(N + 1) * nn] *= ctrl
+    want = oracle_mod.restrict(n, N, r)
+    want[N * nnc:(N + 1) * nnc] *= cctrl
+    np.testing.assert_allclose(o.residual_restrict(x, f), want, rtol=0, atol=1e-13 * np.abs(want).max())
+    c = rng.standard_normal(o.vlen(1))
+    fine = rng.standard_normal(o.vlen(0))
+    plain = oracle_mod.prolong_add(nc, N, c, fine)
+    got = o.prolong_control(c, fine)
+    keep = np.concatenate([np.ones(N * nn, bool), ctrl, np.ones(N * nn, bool)])
+    np.testing.assert_array_equal(got[keep], plain[keep])
+    np.testing.assert_array_equal(got[~keep], fine[~keep])
+    # <R r, c>_U = <r, P c>_U for c zero at coarse nodes without a control
+    cU = c[N * nnc:(N + 1) * nnc] * cctrl
+    cz = np.zeros_like(c)
+    cz[N * nnc:(N + 1) * nnc] = cU
+    Rr = o.residual_restrict(np.zeros(o.vlen(0)), f)[N * nnc:(N + 1) * nnc]
+    Pc = o.prolong_control(cz, np.zeros(o.vlen(0)))[N * nn:(N + 1) * nn]
+    assert abs(Rr @ cU - f[N * nn:(N + 1) * nn] @ Pc) <= 1e-12 * np.abs(Rr).sum() * np.abs(cU).max()
