@@ -45,6 +45,8 @@ def _load():
     L.or_set_smoother.argtypes = [vp, C.c_int]
     L.or_set_control.restype = C.c_int
     L.or_set_control.argtypes = [vp, _dp]
+    L.or_set_sample_c.restype = C.c_int
+    L.or_set_sample_c.argtypes = [vp, _dp]
     L.or_set_control_growth.restype = C.c_int
     L.or_set_control_growth.argtypes = [vp, C.c_double]
     L.or_set_domain.restype = C.c_int
@@ -176,6 +178,12 @@ class Oracle:
         ptr = [None if m is None else m.ctypes.data for m in keep]
         if _load().or_set_masks(self.ctx, ptr[0], ptr[1], 1 if coarsen == "full" else 0) != 0:
             raise ValueError("oracle: singular coarsest block with these node factors")
+
+    def set_sample_c(self, c):
+        """Per-sample C_j = c_j I of the finest level (c_j >= 0), coarse levels
+        4^l c_j, coarsest factorization rebuilt."""
+        if _load().or_set_sample_c(self.ctx, _f64(np.asarray(c, dtype=np.float64).reshape(self.N))) != 0:
+            raise ValueError("oracle: negative c_j or singular coarsest block")
 
     def level_domain(self, l: int):
         """The domain of level l, [n_l][n_l] (1 inside, 0 outside)."""

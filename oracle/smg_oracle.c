@@ -357,6 +357,23 @@ int or_set_domain(or_ctx *C, const double *dom) {
   return or_coarse_setup(C);
 }
 
+/* Per-sample state-mass values c_j of the finest level (c_j >= 0; the Y-block
+ * blocks C_j = c_j I of the risk-averse Newton systems, Section 6): level l
+ * takes 4^l c_j, as at creation.  The coarsest factorization is rebuilt.
+ * Returns 0, -1 if a value is negative or the coarsest block singular. */
+int or_set_sample_c(or_ctx *C, const double *c) {
+  for (int j = 0; j < C->N; ++j)
+    if (!(c[j] >= 0.0)) return -1;
+  for (int l = 0; l < C->nlev; ++l)
+    for (int j = 0; j < C->N; ++j) {
+      C->c[l][j] = l == 0 ? c[j] : 4.0 * C->c[l - 1][j];
+      C->c32[l][j] = (float)C->c[l][j];
+    }
+  free(C->Ainv); free(C->Sinv); free(C->cw);
+  C->Ainv = C->Sinv = C->cw = NULL;
+  return or_coarse_setup(C);
+}
+
 /* Rediscretized control blocks for a control on a line: D_j, E_j and G of level
  * l >= 1 become growth^l times the finest ones (growth 2: the 1D mass of the
  * control line doubles with the spacing; or_create's default 4 is the h^2 of an
