@@ -109,6 +109,8 @@ typedef struct {
                                  Jacobi steps.  Not accepted by the batched solver. */
 #define SMG_FLAG_SSN 8        /* reserve the semismooth Newton solver's buffers in the workspace
                                  (two vectors and six node-sized arrays) */
+#define SMG_FLAG_CVAR 16      /* reserve the risk-averse solver's buffers (seven vectors, the
+                                 rank-one vectors z_j and per-sample arrays); FP64 contexts only */
 
 typedef struct {
   const double *kx;   /* device, [n][n+1][N] */
@@ -342,6 +344,74 @@ int smg_ssn_merit(smg_ctx *ctx, const double *u, const double *du, const double 
  * converge) or an error. */
 int smg_ssn_solve(smg_ctx *ctx, double *x, const double *f, const smg_ssn_params *prm,
                   smg_ssn_stats *stats);
+
+/* ------------------------------------------------------- risk-averse (CVaR)
+ * The smoothed-CVaR control problem (Section 6, eq. OCP) and the nonlinear
+ * preconditioned Newton method of Algorithm 3.  Its Newton matrices J_11 are
+ * the linear-quadratic operator with per-sample C_j = c_j I plus one rank-one
+ * term w_j z_j z_j^T per sample in the Y-Y blocks (eq. equation_C). */
+
+/* Per-sample state-mass values of the finest level: C_j = c[j] I (host, N
+ * values, each >= 0 and finite), coarse levels 4^l c_j; the per-node control
+ * denominators and the coarsest factorization are rebuilt.  SMG_EINVAL for a
+ * bad value. */
+int smg_set_sample_weights(smg_ctx *ctx, const double *c);
+
+/* Rank-one terms of the finest level: the Y-Y block of sample j becomes
+ * C_j + w_j z_j z_j^T.  z: device [n][n][N] (the Y block's layout), w: device
+ * [N]; both copied.  From then on smg_apply, smg_residual, smg_gmres_precond
+ * and smg_solve(SMG_GMRES) use that operator, with the V-cycle of the operator
+ * without them as the preconditioner; smg_solve(SMG_VCYCLE) and the cycle and
+ * step entry points keep the operator without them.  z = w = NULL clears.
+ * Needs SMG_FLAG_CVAR (else SMG_EINVAL). */
+int smg_set_lowrank(smg_ctx *ctx, const double *z, const double *w);
+
+typedef struct {
+  double lambda;      /* confidence level, 0 <= lambda < 1 */
+  double eps;         /* smoothing width of g_eps (eq. smoothapproximation), > 0 */
+  double mass;        /* M = mass I, the lumped mass (h^2 for these grids) */
+  const double *zeta; /* host [N]: sample weights (sum 1) */
+  double tol;         /* outer stop |F(t)| <= tol (the paper: 1e-6) */
+  double inner_tol;   /* h(t): stop once max(||F_1|| / ||F_1(x^0)||, ||F_1||) <= inner_tol (1e-8) */
+  double lin_rtol;    /* GMRES relative residual of every Newton system (1e-9) */
+  int maxit;          /* outer iterations at most */
+  int inner_maxit;    /* Newton iterations per evaluation of h(t) at most */
+  int lin_maxit;      /* GMRES iterations per system at most (the paper: 80) */
+  double sigma, rho;  /* line search on t (0: 1e-4, 1/2) */
+} smg_cvar_params;
+
+typedef struct {
+  int outer;            /* outer (preconditioned) Newton iterations */
+  int inner_total;      /* Newton iterations for h(t) over the whole run */
+  int linear_solves;    /* GMRES solves (Newton systems and the J_11 solves of F'(t)) */
+  int linear_total;     /* GMRES iterations over all of them */
+  double t;             /* final t */
+  double F_final;       /* |F(t)| at the final iterate */
+  double time_ms;
+  double *F;            /* optional caller buffer of cap entries: |F(t^k)| per iterate */
+  int cap;
+  int len;
+} smg_cvar_stats;
+
+/* Algorithm 3 for the smoothed risk-averse problem: x (device, the linear-
+ * quadratic layout; in: the initial guess, out: (y, u, p~) with the adjoint
+ * scaled by zeta_j as for the linear-quadratic systems), f (device: its U and P
+ * blocks are the problem's f_U and M f; its Y block is not read), yd (device
+ * [n][n]: the target), *t (host; in: t^0, out: t).  The context's blocks give
+ * A_j, D_j, E_j and G = nu M; its C_j are overwritten (c_j = zeta_j g'(Q_j)
+ * mass / (1 - lambda)) and the rank-one terms are cleared on return.  F_1(x; t)
+ * is S(c) x - [c_j y_d | f_U | f_P]; every Newton system J_11 dx = -F_1 and the
+ * solve for F'(t) = J_22 - J_21 J_11^{-1} J_12 run GMRES preconditioned by one
+ * V-cycle of S(c) from zero.  h(t) is computed by Newton from the current x
+ * without a line search; when every g''(Q_j) vanishes (eq. condition) the step
+ * is the split one (h(t^k), the root of F_2(x; t) = 0 by bisection, h at that
+ * root); else
+ * the Newton step on t with backtracking |F(t + gamma d)| - |F(t)| <=
+ * -sigma |F(t)| (gamma = 1, rho, rho^2, ..., at most 30 reductions).  Needs
+ * SMG_FLAG_CVAR and an FP64 context.  Returns SMG_OK, SMG_NOT_CONVERGED or an
+ * error. */
+int smg_cvar_solve(smg_ctx *ctx, double *x, const double *f, const double *yd, double *t,
+                   const smg_cvar_params *prm, smg_cvar_stats *stats);
 
 /* ------------------------------------------------------------------ batches
  * Many independent problem instances (different n, N and blocks) solved

@@ -42,7 +42,9 @@ Readings (the paper leaves them open): the smoothing function's middle branch is
 g(x) = s^3/eps^2 - s^4/(2 eps^3) with s = x + eps/2 (the printed branch has a
 typo; this is the C^2 piece that joins 0 and x); t^0 = 0; the Newton iterates
 for h(t) start from the current x; no line search inside that inner Newton;
-the split step solves F_2(x; t) = 0 by bisection (F_2 is nondecreasing in t);
+the split step solves F_2(x; t) = 0 by bisection (F_2 is nondecreasing in t)
+and then recomputes x = h(t) at the new t, since F(t) = F_2(h(t), t) is what the
+next test reads;
 the line search of the outer Newton uses sigma = 1e-4, rho = 1/2.
 """
 from __future__ import annotations
@@ -233,6 +235,9 @@ class Cvar:
                 x, kk = self.inner(x, t, method, lin=lin)
                 inner_total += kk
                 t = self.split_t(self.z_q(x)[1])
+                # F(t) = F_2(h(t), t): the next test needs h at the new t
+                x, kk = self.inner(x, t, method, lin=lin)
+                inner_total += kk
             else:
                 self.F1(x, t)                              # S(c) at (x^k, t^k)
                 rhs = np.zeros_like(x)

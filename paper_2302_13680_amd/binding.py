@@ -23,6 +23,7 @@ SMG_FLAG_EAGER = 1
 SMG_FLAG_UNFUSED = 2
 SMG_FLAG_JACOBI = 4
 SMG_FLAG_SSN = 8
+SMG_FLAG_CVAR = 16
 SMG_COARSEN_INJECT, SMG_COARSEN_FULL = 0, 1
 
 EXPORTED = [
@@ -34,6 +35,7 @@ EXPORTED = [
     "smg_net_setup", "smg_net_destroy", "smg_net_last_error", "smg_net_set_params", "smg_net_get_params",
     "smg_net_forward", "smg_net_grad", "smg_net_train_step", "smg_net_features", "smg_net_targets",
     "smg_net_lift", "smg_set_node_factors", "smg_ssn_eval", "smg_ssn_merit", "smg_ssn_solve",
+    "smg_set_sample_weights", "smg_set_lowrank", "smg_cvar_solve",
 ]
 
 
@@ -63,6 +65,19 @@ class SsnParams(C.Structure):
                 ("mass", C.c_double), ("tol", C.c_double), ("inner_rtol", C.c_double),
                 ("inner_method", C.c_int), ("maxit", C.c_int), ("inner_maxit", C.c_int),
                 ("sigma", C.c_double), ("rho", C.c_double)]
+
+
+class CvarParams(C.Structure):
+    _fields_ = [("lam", C.c_double), ("eps", C.c_double), ("mass", C.c_double),
+                ("zeta", C.POINTER(C.c_double)), ("tol", C.c_double), ("inner_tol", C.c_double),
+                ("lin_rtol", C.c_double), ("maxit", C.c_int), ("inner_maxit", C.c_int),
+                ("lin_maxit", C.c_int), ("sigma", C.c_double), ("rho", C.c_double)]
+
+
+class CvarStats(C.Structure):
+    _fields_ = [("outer", C.c_int), ("inner_total", C.c_int), ("linear_solves", C.c_int),
+                ("linear_total", C.c_int), ("t", C.c_double), ("F_final", C.c_double),
+                ("time_ms", C.c_double), ("F", C.POINTER(C.c_double)), ("cap", C.c_int), ("len", C.c_int)]
 
 
 class SsnStats(C.Structure):
@@ -168,6 +183,12 @@ def load(path: str = LIB_PATH):
                                 C.POINTER(C.c_double)]
     L.smg_ssn_solve.argtypes = [vp, vp, vp, C.POINTER(SsnParams), C.POINTER(SsnStats)]
     for name in ["smg_set_node_factors", "smg_ssn_eval", "smg_ssn_merit", "smg_ssn_solve"]:
+        getattr(L, name).restype = i
+    L.smg_set_sample_weights.argtypes = [vp, C.POINTER(C.c_double)]
+    L.smg_set_lowrank.argtypes = [vp, vp, vp]
+    L.smg_cvar_solve.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), C.POINTER(CvarParams),
+                                 C.POINTER(CvarStats)]
+    for name in ["smg_set_sample_weights", "smg_set_lowrank", "smg_cvar_solve"]:
         getattr(L, name).restype = i
     for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_stream_copy", "smg_restrict", "smg_residual_restrict", "smg_jacobi", "smg_prolong_add",
                  "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond", "smg_solve",
@@ -349,6 +370,31 @@ class Context:
         return rc, dict(iterations=st.iterations, inner_total=st.inner_total,
                         init_iterations=st.init_iterations, phi_final=st.phi_final, time_ms=st.time_ms,
                         phi=list(phi[:k]), gammas=list(gam[:max(k - 1, 0)]), inner=list(inner[:max(k - 1, 0)]))
+
+    def set_sample_weights(self, c):
+        """C_j = c_j I on the finest level (host sequence of N values >= 0)."""
+        self._cw = np.ascontiguousarray(c, dtype=np.float64)
+        return self._check(self.L.smg_set_sample_weights(self.ctx, self._cw.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def set_lowrank(self, z, w):
+        """Rank-one terms w_j z_j z_j^T (device tensors z [n][n][N], w [N]); None clears."""
+        return self._check(self.L.smg_set_lowrank(self.ctx, None if z is None else _ptr(z),
+                                                  None if w is None else _ptr(w)))
+
+    def cvar_solve(self, x, f, yd, zeta, lam, eps, mass, t0=0.0, tol=1e-6, inner_tol=1e-8, lin_rtol=1e-9,
+                   maxit=50, inner_maxit=50, lin_maxit=80, cap=256):
+        """Algorithm 3 in place on x (device); yd: device [n][n].  Returns (rc, stats dict)."""
+        zeta = np.ascontiguousarray(zeta, dtype=np.float64)
+        prm = CvarParams(lam, eps, mass, zeta.ctypes.data_as(C.POINTER(C.c_double)), tol, inner_tol, lin_rtol,
+                         maxit, inner_maxit, lin_maxit, 0.0, 0.0)
+        F = (C.c_double * cap)()
+        st = CvarStats(0, 0, 0, 0, 0.0, 0.0, 0.0, F, cap, 0)
+        t = C.c_double(t0)
+        rc = self._check(self.L.smg_cvar_solve(self.ctx, _ptr(x), _ptr(f), _ptr(yd), C.byref(t), C.byref(prm),
+                                               C.byref(st)), allow_nc=True)
+        return rc, dict(outer=st.outer, inner_total=st.inner_total, linear_solves=st.linear_solves,
+                        linear_total=st.linear_total, t=t.value, F_final=st.F_final, time_ms=st.time_ms,
+                        F=list(F[:min(st.len, cap)]))
 
 
 class Batch:

@@ -8,5 +8,6 @@
 #include "coarse.h"
 #include "krylov.h"
 #include "ssn.h"
+#include "cvar.h"
 #include "batch.h"
 #include "netio.h"

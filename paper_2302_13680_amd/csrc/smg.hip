@@ -205,6 +205,13 @@ struct smg_ctx {
   // E[p], E[dp], F, chi, per-block partials and their sums
   double *sdx = nullptr, *sr = nullptr, *sw = nullptr, *sdw = nullptr, *sF = nullptr, *schi = nullptr;
   double *spart = nullptr, *sout = nullptr;
+  // risk-averse buffers (SMG_FLAG_CVAR): rank-one vectors z_j [nn][N], weights w_j,
+  // per-sample scratch, partials, c_j on the device; right-hand side b(c), residual
+  // -F_1, Newton increment, saved iterate, J_12, J_11^{-1} J_12, residual scratch
+  double *cz = nullptr, *cwv = nullptr, *cs = nullptr, *cpart = nullptr, *cc = nullptr;
+  double *cb = nullptr, *cr = nullptr, *cdx = nullptr, *cxk = nullptr, *cj12 = nullptr, *cxi = nullptr,
+         *clr = nullptr;
+  bool lr_on = false;          // rank-one terms in the finest-level operator
   size_t used_bytes = 0;
   // captured V-cycles, one per (x, f, kind); kind = precision * 2 + zero_first
   struct Graph {
@@ -241,7 +248,9 @@ bool desc_valid(const smg_desc& d, std::string* why) {
   if (!(d.theta > 0.0 && d.theta < 2.0)) return fail("theta must lie in (0, 2)");
   if (d.precision != SMG_F64 && d.precision != SMG_F32) return fail("precision must be SMG_F64 or SMG_F32");
   if (d.gmres_restart < 0 || d.gmres_restart > kMaxBasis - 1) return fail("gmres_restart must be in [0, 31]");
-  if (d.flags & ~(SMG_FLAG_EAGER | SMG_FLAG_UNFUSED | SMG_FLAG_JACOBI | SMG_FLAG_SSN)) return fail("unknown flag bits");
+  if (d.flags & ~(SMG_FLAG_EAGER | SMG_FLAG_UNFUSED | SMG_FLAG_JACOBI | SMG_FLAG_SSN | SMG_FLAG_CVAR))
+    return fail("unknown flag bits");
+  if ((d.flags & SMG_FLAG_CVAR) && d.precision != SMG_F64) return fail("SMG_FLAG_CVAR needs SMG_F64");
   if (d.strip < 0 || (d.strip & 1)) return fail("strip must be 0 or a positive even number");
   return true;
 }
@@ -310,6 +319,21 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
     C->schi = cv.take<double>(nn);
     C->spart = cv.take<double>(std::max(nn / 4 + 1, (size_t)kSsnMeritBlocks * kSsnGammas));
     C->sout = cv.take<double>(kSsnGammas);
+  }
+  if (d.flags & SMG_FLAG_CVAR) {
+    const size_t nn = (size_t)d.n * d.n, N = d.nsamples;
+    C->cz = cv.take<double>(nn * N);
+    C->cwv = cv.take<double>(N);
+    C->cs = cv.take<double>(N);
+    C->cc = cv.take<double>(N);
+    C->cpart = cv.take<double>((size_t)kSampleBlocks * N);
+    C->cb = cv.take<double>(len0);
+    C->cr = cv.take<double>(len0);
+    C->cdx = cv.take<double>(len0);
+    C->cxk = cv.take<double>(len0);
+    C->cj12 = cv.take<double>(len0);
+    C->cxi = cv.take<double>(len0);
+    C->clr = cv.take<double>(len0);
   }
   // node factor pairs last: the other buffers keep the places they have without them
   for (int l = 0; l < nl; ++l) {
@@ -446,6 +470,8 @@ int node_den_level(smg_ctx* C, const Level<T>& L) {
 // (full = 1), FP32 copies for the FP32 cycle; then what depends on them: the
 // per-node denominators and the coarsest Schur complement (A_j^{-1} must be in
 // place).
+int node_terms(smg_ctx* C);
+
 int factors_setup(smg_ctx* C, const double* md, const double* me, int full) {
   const bool f32 = C->desc.precision == SMG_F32;
   const int n0 = C->desc.n;
@@ -464,6 +490,13 @@ int factors_setup(smg_ctx* C, const double* md, const double* me, int full) {
   if (f32)
     for (int l = 0; l < C->nlev; ++l)
       TRY((convert<double, float>(C, C->L64[l].mk, C->L32[l].mk, 2 * (size_t)C->L64[l].n * C->L64[l].n)));
+  return node_terms(C);
+}
+
+// Per-node control denominators of every level and the coarsest Schur
+// complement, from the current blocks and node factors.
+int node_terms(smg_ctx* C) {
+  const bool f32 = C->desc.precision == SMG_F32;
   for (int l = 0; l < C->nlev; ++l) {
     TRY(node_den_level<double>(C, C->L64[l]));
     if (f32) TRY(node_den_level<float>(C, C->L32[l]));
@@ -791,15 +824,6 @@ int readback(smg_ctx* C, const double* src, int nv) {
   }
 }
 
-// FP64 residual of the finest level into out (may be null); norms to host
-// h[0..4] = { ||r||, ||r_Y||, ||r_U||, ||r_P||, ||f|| }.
-int residual_norms64(smg_ctx* C, const double* x, const double* f, double* out, double* h) {
-  TRY((residual<double, double, double>(C, C->L64[0], x, f, out, 0, true)));
-  TRY(readback(C, C->norms, 5));
-  for (int i = 0; i < 5; ++i) h[i] = C->host[i];
-  return SMG_OK;
-}
-
 // ||v||_2 (one multi-dot pass with no basis vectors).
 int vec_norm(smg_ctx* C, const double* v, size_t len, double* out) {
   hipLaunchKernelGGL((k_mdot<double, 4>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, v,
@@ -809,6 +833,45 @@ int vec_norm(smg_ctx* C, const double* v, size_t len, double* out) {
   LAUNCH_CHECK();
   TRY(readback(C, C->hdev + kMaxBasis, 1));
   *out = std::sqrt(C->host[0]);
+  return SMG_OK;
+}
+
+// out_j = scale_j sum_i A_j(i) B_j(i) over the finest level's nodes (device, N values).
+int sample_dots(smg_ctx* C, const double* A, const double* B, const double* scale, double* out) {
+  const int nn = C->desc.n * C->desc.n, N = C->N, nb = std::min(kSampleBlocks, nn);
+  hipLaunchKernelGGL(k_sample_dots, dim3(nb), dim3(kBlock), 0, C->stream, nn, N, A, B, C->cpart);
+  hipLaunchKernelGGL(k_sample_finalize, dim3((N + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, nb, N,
+                     (const double*)C->cpart, scale, out);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+// out_Y += sign sum_j w_j z_j (z_j . x_Y,j): the rank-one terms of the finest
+// level (nothing unless they are set).
+int lowrank_add(smg_ctx* C, const double* x, double* out, double sign) {
+  if (!C->lr_on) return SMG_OK;
+  const int nn = C->desc.n * C->desc.n, N = C->N;
+  TRY(sample_dots(C, C->cz, x, C->cwv, C->cs));
+  hipLaunchKernelGGL(k_lowrank_add, dim3(grid_for((size_t)nn * N)), dim3(kBlock), 0, C->stream, nn, N, sign,
+                     (const double*)C->cs, (const double*)C->cz, out);
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+// FP64 residual of the finest level into out (may be null); norms to host
+// h[0..4] = { ||r||, ||r_Y||, ||r_U||, ||r_P||, ||f|| }.  With rank-one terms
+// the residual is corrected and its block norms taken again.
+int residual_norms64(smg_ctx* C, const double* x, const double* f, double* out, double* h) {
+  double* o = out ? out : C->clr;
+  TRY((residual<double, double, double>(C, C->L64[0], x, f, C->lr_on ? o : out, 0, true)));
+  TRY(readback(C, C->norms, 5));
+  for (int i = 0; i < 5; ++i) h[i] = C->host[i];
+  if (C->lr_on) {
+    const size_t nn = (size_t)C->desc.n * C->desc.n, N = C->N;
+    TRY(lowrank_add(C, x, o, -1.0));
+    TRY(vec_norm(C, o, N * nn, &h[1]));
+    h[0] = std::sqrt(h[1] * h[1] + h[2] * h[2] + h[3] * h[3]);
+  }
   return SMG_OK;
 }
 
@@ -837,6 +900,7 @@ int precond_and_apply(smg_ctx* C, int k) {
     double* zk = C->Z64 + (size_t)k * len;
     TRY(run_cycle<double>(C, zk, vk, true));
     TRY((residual<double, double, double>(C, C->L64[0], zk, (const double*)nullptr, C->w, 1, false)));
+    TRY(lowrank_add(C, zk, C->w, 1.0));
   } else {
     float* zk = C->Z32 + (size_t)k * len;
     TRY((convert<double, float>(C, vk, C->L32[0].f, len)));
@@ -1543,7 +1607,8 @@ int smg_set_node_factors(smg_ctx* C, const double* md, const double* me, int coa
 
 int smg_apply(smg_ctx* C, const double* x, double* Sx) {
   if (!C || !x || !Sx) return SMG_EINVAL;
-  return residual<double, double, double>(C, C->L64[0], x, (const double*)nullptr, Sx, 1, false);
+  TRY((residual<double, double, double>(C, C->L64[0], x, (const double*)nullptr, Sx, 1, false)));
+  return lowrank_add(C, x, Sx, 1.0);
 }
 
 int smg_residual(smg_ctx* C, const double* x, const double* f, double* r, double* norms) {
@@ -1554,7 +1619,8 @@ int smg_residual(smg_ctx* C, const double* x, const double* f, double* r, double
     for (int i = 0; i < 4; ++i) norms[i] = h[i];
     return SMG_OK;
   }
-  return residual<double, double, double>(C, C->L64[0], x, f, r, 0, false);
+  TRY((residual<double, double, double>(C, C->L64[0], x, f, r, 0, false)));
+  return lowrank_add(C, x, r, -1.0);
 }
 
 int smg_smooth(smg_ctx* C, int level, int colour, double* x, const double* f) {
@@ -1669,6 +1735,7 @@ int smg_gmres_precond(smg_ctx* C, double* x, const double* f, int restart, doubl
 int smg_solve(smg_ctx* C, double* x, const double* f, int method, double rtol, int maxit, smg_stats* st) {
   if (!C || !x || !f || !(rtol > 0) || maxit < 1) return SMG_EINVAL;
   if (method != SMG_VCYCLE && method != SMG_GMRES) return SMG_EINVAL;
+  if (C->lr_on && method != SMG_GMRES) return SMG_EINVAL;
   TRY(zero_outside(C, x));
   const double t0 = now_ms();
   const bool f32 = C->desc.precision == SMG_F32;
@@ -1892,6 +1959,242 @@ int smg_ssn_solve(smg_ctx* C, double* x, const double* f, const smg_ssn_params* 
     st->inner_total = inner_total;
     st->phi_final = phi;
     st->time_ms = now_ms() - t0;
+  }
+  return rc;
+}
+
+}  // extern "C"
+
+// ======================================================= risk-averse (CVaR)
+namespace {
+
+// The C^2 smoothing of max(0, x) (eq. smoothapproximation; middle branch in
+// s = x + eps/2: s^3/eps^2 - s^4/(2 eps^3)) and its first two derivatives.
+double cv_dg(double x, double eps) {
+  if (x <= -0.5 * eps) return 0.0;
+  if (x >= 0.5 * eps) return 1.0;
+  const double s = x + 0.5 * eps;
+  return 3.0 * s * s / (eps * eps) - 2.0 * s * s * s / (eps * eps * eps);
+}
+double cv_ddg(double x, double eps) {
+  if (x <= -0.5 * eps || x >= 0.5 * eps) return 0.0;
+  const double s = x + 0.5 * eps;
+  return 6.0 * s / (eps * eps) - 6.0 * s * s / (eps * eps * eps);
+}
+
+int set_sample_c(smg_ctx* C, const double* c) {
+  const int N = C->N;
+  std::vector<double> cc(c, c + N);
+  for (int l = 0; l < C->nlev; ++l) {
+    if (l > 0)
+      for (int j = 0; j < N; ++j) cc[j] *= 4.0;
+    HIP_TRY(hipMemcpyAsync(C->L64[l].c, cc.data(), sizeof(double) * N, hipMemcpyHostToDevice, C->stream));
+    TRY(sync(C));   // cc is reused for the next level
+  }
+  return node_terms(C);
+}
+
+struct CvarRun {
+  smg_ctx* C;
+  const smg_cvar_params* p;
+  const double* f;
+  const double* yd;
+  std::vector<double> q, w, c;   // per sample: Q_j + t, w_j, c_j
+  int inner_total = 0, lin_solves = 0, lin_total = 0;
+
+  double F4(double t) const {
+    double s = 0.0;
+    for (int j = 0; j < C->N; ++j) s += p->zeta[j] * cv_dg(q[j] - t, p->eps);
+    return 1.0 - s / (1.0 - p->lambda);
+  }
+  // z at x into C->cz; q_j = z_j . z_j / (2 mass) to the host
+  int zq(const double* x) {
+    const int nn = C->desc.n * C->desc.n, N = C->N;
+    hipLaunchKernelGGL(k_cvar_z, dim3(grid_for((size_t)nn * N)), dim3(kBlock), 0, C->stream, nn, N, p->mass, x, yd,
+                       C->domain ? (const double*)C->L64[0].dom : (const double*)nullptr, C->cz);
+    LAUNCH_CHECK();
+    TRY(sample_dots(C, C->cz, C->cz, nullptr, C->cs));
+    HIP_TRY(hipMemcpyAsync(q.data(), C->cs, sizeof(double) * N, hipMemcpyDeviceToHost, C->stream));
+    TRY(sync(C));
+    for (int j = 0; j < N; ++j) q[j] *= 0.5 / p->mass;
+    return SMG_OK;
+  }
+  // C_j = c_j(x, t) I, b(c) into C->cb, C->cr = b - S(c) x = -F_1; ||F_1|| to fn
+  int F1(const double* x, double t, double* fn) {
+    const int nn = C->desc.n * C->desc.n, N = C->N;
+    TRY(zq(x));
+    for (int j = 0; j < N; ++j) c[j] = p->zeta[j] * cv_dg(q[j] - t, p->eps) * p->mass / (1.0 - p->lambda);
+    TRY(set_sample_c(C, c.data()));
+    HIP_TRY(hipMemcpyAsync(C->cc, c.data(), sizeof(double) * N, hipMemcpyHostToDevice, C->stream));
+    HIP_TRY(hipMemcpyAsync(C->cb, f, sizeof(double) * C->len0, hipMemcpyDeviceToDevice, C->stream));
+    hipLaunchKernelGGL(k_cvar_rhs, dim3(grid_for((size_t)nn * N)), dim3(kBlock), 0, C->stream, nn, N,
+                       (const double*)C->cc, yd, C->domain ? (const double*)C->L64[0].dom : (const double*)nullptr,
+                       C->cb);
+    LAUNCH_CHECK();
+    C->lr_on = false;
+    double h[5];
+    TRY(residual_norms64(C, x, C->cb, C->cr, h));
+    *fn = h[0];
+    return SMG_OK;
+  }
+  // w_j at (q, t) to the host and the device; rank-one terms on where any is nonzero
+  int set_w(double t, bool* any) {
+    *any = false;
+    for (int j = 0; j < C->N; ++j) {
+      w[j] = p->zeta[j] * cv_ddg(q[j] - t, p->eps) / (1.0 - p->lambda);
+      *any = *any || w[j] != 0.0;
+    }
+    HIP_TRY(hipMemcpyAsync(C->cwv, w.data(), sizeof(double) * C->N, hipMemcpyHostToDevice, C->stream));
+    return SMG_OK;
+  }
+  // sol = J_11^{-1} rhs by GMRES from zero (rank-one terms as set_w left them)
+  int solve(double* sol, const double* rhs, bool lowrank) {
+    HIP_TRY(hipMemsetAsync(sol, 0, sizeof(double) * C->len0, C->stream));
+    C->lr_on = lowrank;
+    smg_stats st{};
+    const int rc = smg_gmres_precond(C, sol, rhs, C->desc.gmres_restart, p->lin_rtol, p->lin_maxit, &st);
+    C->lr_on = false;
+    if (rc != SMG_OK && rc != SMG_NOT_CONVERGED) return rc;
+    ++lin_solves;
+    lin_total += st.iterations;
+    return SMG_OK;
+  }
+  // h(t): Newton on F_1(.; t) = 0 from x, no line search
+  int inner(double* x, double t) {
+    double fn, f0;
+    TRY(F1(x, t, &fn));
+    f0 = fn;
+    for (int k = 0; k < p->inner_maxit; ++k) {
+      if (fn == 0.0 || std::max(fn / f0, fn) <= p->inner_tol) break;
+      bool any;
+      TRY(set_w(t, &any));
+      TRY(solve(C->cdx, C->cr, any));
+      hipLaunchKernelGGL(k_axpy, dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, x, 1.0,
+                         (const double*)C->cdx);
+      LAUNCH_CHECK();
+      ++inner_total;
+      TRY(F1(x, t, &fn));
+    }
+    return SMG_OK;
+  }
+  // the root of F_2(x; t) = 0 in t for the current q (bisection)
+  double split_t() const {
+    double lo = q[0], hi = q[0];
+    for (double v : q) { lo = std::min(lo, v); hi = std::max(hi, v); }
+    lo -= p->eps;
+    hi += p->eps;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid == lo || mid == hi) break;
+      if (F4(mid) < 0.0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+  }
+};
+
+bool cvar_params_valid(const smg_cvar_params& p, int N) {
+  if (!(p.lambda >= 0.0 && p.lambda < 1.0) || !(p.eps > 0.0 && std::isfinite(p.eps)) ||
+      !(p.mass > 0.0 && std::isfinite(p.mass)) || !p.zeta || !(p.tol > 0) || !(p.inner_tol > 0) ||
+      !(p.lin_rtol > 0) || p.maxit < 0 || p.inner_maxit < 1 || p.lin_maxit < 1 || !(p.sigma >= 0 && p.sigma < 1) ||
+      !(p.rho >= 0 && p.rho < 1))
+    return false;
+  for (int j = 0; j < N; ++j)
+    if (!(p.zeta[j] >= 0.0 && std::isfinite(p.zeta[j]))) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int smg_set_sample_weights(smg_ctx* C, const double* c) {
+  if (!C || !c) return SMG_EINVAL;
+  for (int j = 0; j < C->N; ++j)
+    if (!(c[j] >= 0.0 && std::isfinite(c[j]))) return SMG_EINVAL;
+  return set_sample_c(C, c);
+}
+
+int smg_set_lowrank(smg_ctx* C, const double* z, const double* w) {
+  if (!C || !(C->desc.flags & SMG_FLAG_CVAR) || (!z) != (!w)) return SMG_EINVAL;
+  if (!z) { C->lr_on = false; return SMG_OK; }
+  const size_t nn = (size_t)C->desc.n * C->desc.n;
+  HIP_TRY(hipMemcpyAsync(C->cz, z, sizeof(double) * nn * C->N, hipMemcpyDeviceToDevice, C->stream));
+  HIP_TRY(hipMemcpyAsync(C->cwv, w, sizeof(double) * C->N, hipMemcpyDeviceToDevice, C->stream));
+  C->lr_on = true;
+  return SMG_OK;
+}
+
+int smg_cvar_solve(smg_ctx* C, double* x, const double* f, const double* yd, double* t,
+                   const smg_cvar_params* prm, smg_cvar_stats* st) {
+  if (!C || !x || !f || !yd || !t || !prm || !std::isfinite(*t)) return SMG_EINVAL;
+  if (!(C->desc.flags & SMG_FLAG_CVAR) || C->desc.gmres_restart < 1) return SMG_EINVAL;
+  smg_cvar_params p = *prm;
+  if (p.sigma == 0.0) p.sigma = 1e-4;
+  if (p.rho == 0.0) p.rho = 0.5;
+  if (!cvar_params_valid(p, C->N)) return SMG_EINVAL;
+  const double t0ms = now_ms();
+  TRY(zero_outside(C, x));
+  const int N = C->N;
+  CvarRun R{C, &p, f, yd, std::vector<double>(N), std::vector<double>(N), std::vector<double>(N)};
+  double tk = *t;
+  if (st) st->len = 0;
+  auto push = [&](double v) { if (st && st->F && st->len < st->cap) st->F[st->len++] = v; };
+  TRY(R.inner(x, tk));
+  int k = 0, rc = SMG_NOT_CONVERGED;
+  double Fk = NAN;
+  while (true) {
+    Fk = R.F4(tk);
+    push(std::fabs(Fk));
+    if (!std::isfinite(Fk)) { rc = SMG_ENONFINITE; break; }
+    if (std::fabs(Fk) <= p.tol) { rc = SMG_OK; break; }
+    if (k >= p.maxit) break;
+    bool any = false;
+    for (int j = 0; j < N && !any; ++j) any = cv_ddg(R.q[j] - tk, p.eps) != 0.0;
+    if (!any) {   // eq. condition: the split step
+      TRY(R.inner(x, tk));
+      tk = R.split_t();
+      TRY(R.inner(x, tk));   // F(t) = F_2(h(t), t): the next test needs h at the new t
+    } else {
+      double fn;
+      TRY(R.F1(x, tk, &fn));                       // S(c) and z at (x^k, t^k)
+      TRY(R.set_w(tk, &any));
+      const size_t nn = (size_t)C->desc.n * C->desc.n;
+      HIP_TRY(hipMemsetAsync(C->cj12, 0, sizeof(double) * C->len0, C->stream));
+      hipLaunchKernelGGL(k_lowrank_add, dim3(grid_for(nn * N)), dim3(kBlock), 0, C->stream, (int)nn, N, -1.0,
+                         (const double*)C->cwv, (const double*)C->cz, C->cj12);   // J_12 = -w_j z_j
+      LAUNCH_CHECK();
+      TRY(R.solve(C->cxi, C->cj12, true));
+      TRY(sample_dots(C, C->cz, C->cxi, C->cwv, C->cs));
+      std::vector<double> zx(N);
+      HIP_TRY(hipMemcpyAsync(zx.data(), C->cs, sizeof(double) * N, hipMemcpyDeviceToHost, C->stream));
+      TRY(sync(C));
+      double Fp = 0.0;
+      for (int j = 0; j < N; ++j) Fp += R.w[j] + zx[j];
+      const double d = -Fk / Fp;
+      HIP_TRY(hipMemcpyAsync(C->cxk, x, sizeof(double) * C->len0, hipMemcpyDeviceToDevice, C->stream));
+      double gamma = 1.0;
+      for (int ls = 0; ls <= 30; ++ls) {
+        if (ls > 0)
+          HIP_TRY(hipMemcpyAsync(x, C->cxk, sizeof(double) * C->len0, hipMemcpyDeviceToDevice, C->stream));
+        TRY(R.inner(x, tk + gamma * d));
+        if (std::fabs(R.F4(tk + gamma * d)) - std::fabs(Fk) <= -p.sigma * std::fabs(Fk)) break;
+        if (ls < 30) gamma *= p.rho;
+      }
+      tk += gamma * d;
+    }
+    ++k;
+  }
+  C->lr_on = false;
+  TRY(sync(C));
+  *t = tk;
+  if (st) {
+    st->outer = k;
+    st->inner_total = R.inner_total;
+    st->linear_solves = R.lin_solves;
+    st->linear_total = R.lin_total;
+    st->t = tk;
+    st->F_final = std::fabs(Fk);
+    st->time_ms = now_ms() - t0ms;
   }
   return rc;
 }
