@@ -484,6 +484,70 @@ def ssn_tables(dev):
     return out
 
 
+def cvar_tables(dev):
+    """The settings of the paper's risk-averse table (Section 6, Algorithm 3) on
+    the L-shape with the Gaussian field (sigma^2 1, L^2 0.1, 15 modes), Monte
+    Carlo samples, nu 1e-4 and the Jacobi-smoothed V-cycle inside GMRES(30):
+    [outer Newton, inner Newton, mean GMRES iterations per system] beside the
+    printed [outer, inner, mean V-cycles, mean GMRES]; the eps sweep continues
+    from the previous eps's solution (x and t), as the paper does.  Wall time of
+    every run on the device."""
+    import numpy as np
+    import torch
+    from paper_2302_13680_amd import binding, inputs
+
+    def problem(n=31, N=500, seed=23):
+        return inputs.make_problem(n, N, 1e-4, M=15, sigma=1.0, seed=seed, yd=inputs.paper_target(n), f=0.0,
+                                   field="gaussian", corr_len2=0.1, domain="lshape")
+
+    def run(p, lam, eps, x=None, t0=0.0):
+        ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5,
+                                              flags=binding.SMG_FLAG_JACOBI | binding.SMG_FLAG_CVAR)
+        mass = -float(p.d[0])
+        zeta = np.asarray(p.c) / mass
+        live = np.ones(p.n * p.n) if p.domain is None else np.asarray(p.domain).reshape(-1)
+        yd = torch.tensor((np.asarray(p.yd).reshape(-1) * live).reshape(p.n, p.n), dtype=torch.float64,
+                          device=dev)
+        if x is None:
+            x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        rc, st = ctx.cvar_solve(x, f, yd, zeta, lam, eps, mass, t0=t0)
+        torch.cuda.synchronize()
+        wall = 1e3 * (time.perf_counter() - t_start)
+        ctx.close()
+        mean = st["linear_total"] / max(st["linear_solves"], 1)
+        row = {"counts": [st["outer"], st["inner_total"], round(mean, 1)], "converged": rc == binding.SMG_OK,
+               "t": st["t"], "wall_ms": round(wall, 1)}
+        print("cvar", p.n, p.N, lam, eps, json.dumps(row), file=sys.stderr, flush=True)
+        return x, st, row
+
+    out = {"method": "GMRES(30), one V-cycle of S(c) as preconditioner, rank-one terms in the operator",
+           "format": "[outer, inner Newton, mean GMRES] (this build) beside [outer, inner, mean V-cycles, mean GMRES]"}
+    out["mesh"] = []
+    for n, nh, pr in ((15, 161, [5, 62, 23.0, 13.9]), (31, 705, [6, 79, 28.0, 15.5]), (63, 2945, [6, 79, 26.2, 14.8])):
+        _, _, r = run(problem(n=n), 0.9, 1e-2)
+        out["mesh"].append(dict(nodes=nh, **r, paper=pr))
+    out["N"] = []
+    for N, pr in ((500, [6, 63, 55.4, 17.5]), (1000, [5, 66, 24.4, 14.0]), (2000, [4, 51, 24.4, 14.0])):
+        _, _, r = run(problem(N=N), 0.95, 1e-2)
+        out["N"].append(dict(N=N, **r, paper=pr))
+    out["lambda"] = []
+    for lam, pr in ((0.0, [0, 1, 21.0, 14.0]), (0.5, [5, 21, 19.4, 13.6]), (0.95, [5, 64, 23.2, 13.8]),
+                    (0.99, [8, 129, 33.4, 17.5])):
+        _, _, r = run(problem(N=2000), lam, 1e-2)
+        out["lambda"].append(dict(lam=lam, **r, paper=pr))
+    out["eps_continuation"] = []
+    p = problem(N=1000)
+    x, t = None, 0.0
+    for eps, pr in ((1e-1, [7, 67, 22.5, 17.0]), (1e-2, [3, 42, 29.1, 14.8]), (1e-3, [2, 20, None, 27.9]),
+                    (1e-4, [1, 15, 58.0, 55.6])):
+        x, st, r = run(p, 0.95, eps, x=x, t0=t)
+        t = st["t"]
+        out["eps_continuation"].append(dict(eps=eps, **r, paper=pr))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -615,6 +679,7 @@ def main():
     ssn = ssn_section(dev, n, N, args)
     paper = paper_tables(dev)
     paper["l1_tables"] = ssn_tables(dev)
+    paper["cvar_tables"] = cvar_tables(dev)
 
     # ---------------- roofline of the dominant kernel: finest-level half-sweep
     xs = torch.zeros(dof, dtype=torch.float64, device=dev)

@@ -109,7 +109,7 @@ typedef struct {
                                  Jacobi steps.  Not accepted by the batched solver. */
 #define SMG_FLAG_SSN 8        /* reserve the semismooth Newton solver's buffers in the workspace
                                  (two vectors and six node-sized arrays) */
-#define SMG_FLAG_CVAR 16      /* reserve the risk-averse solver's buffers (seven vectors, the
+#define SMG_FLAG_CVAR 16      /* reserve the risk-averse solver's buffers (eight vectors, the
                                  rank-one vectors z_j and per-sample arrays); FP64 contexts only */
 
 typedef struct {
@@ -372,7 +372,7 @@ typedef struct {
   double mass;        /* M = mass I, the lumped mass (h^2 for these grids) */
   const double *zeta; /* host [N]: sample weights (sum 1) */
   double tol;         /* outer stop |F(t)| <= tol (the paper: 1e-6) */
-  double inner_tol;   /* h(t): stop once max(||F_1|| / ||F_1(x^0)||, ||F_1||) <= inner_tol (1e-8) */
+  double inner_tol;   /* h(t): stop once min(||F_1|| / ||F_1(x^0)||, ||F_1||) <= inner_tol (1e-8) */
   double lin_rtol;    /* GMRES relative residual of every Newton system (1e-9) */
   int maxit;          /* outer iterations at most */
   int inner_maxit;    /* Newton iterations per evaluation of h(t) at most */
@@ -402,8 +402,9 @@ typedef struct {
  * mass / (1 - lambda)) and the rank-one terms are cleared on return.  F_1(x; t)
  * is S(c) x - [c_j y_d | f_U | f_P]; every Newton system J_11 dx = -F_1 and the
  * solve for F'(t) = J_22 - J_21 J_11^{-1} J_12 run GMRES preconditioned by one
- * V-cycle of S(c) from zero.  h(t) is computed by Newton from the current x
- * without a line search; when every g''(Q_j) vanishes (eq. condition) the step
+ * V-cycle of S(c) from zero.  h(t) is computed by Newton from the current x,
+ * each step backtracking (1, 1/2, ..., at most 30 halvings) until
+ * ||F_1(x + a dx)|| <= (1 - 1e-4 a) ||F_1(x)||; when every g''(Q_j) vanishes (eq. condition) the step
  * is the split one (h(t^k), the root of F_2(x; t) = 0 by bisection, h at that
  * root); else
  * the Newton step on t with backtracking |F(t + gamma d)| - |F(t)| <=

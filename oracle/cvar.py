@@ -41,7 +41,11 @@ as in the paper; 300 for the V-cycle iteration).
 Readings (the paper leaves them open): the smoothing function's middle branch is
 g(x) = s^3/eps^2 - s^4/(2 eps^3) with s = x + eps/2 (the printed branch has a
 typo; this is the C^2 piece that joins 0 and x); t^0 = 0; the Newton iterates
-for h(t) start from the current x; no line search inside that inner Newton;
+for h(t) start from the current x; the inner stopping rule is taken with min
+(either the relative or the absolute residual below 1e-8: with max, a warm
+start near h(t) could never meet the relative part, its residual being at the
+rounding floor already); the inner Newton backtracks on ||F_1|| (without a
+globalization it cycles when few samples lie in the smoothing band);
 the split step solves F_2(x; t) = 0 by bisection (F_2 is nondecreasing in t)
 and then recomputes x = h(t) at the new t, since F(t) = F_2(h(t), t) is what the
 next test reads;
@@ -181,22 +185,30 @@ class Cvar:
     # --- the two Newton iterations ----------------------------------------
     def inner(self, x, t, method, tol=1e-8, maxit=50, lin=None):
         """h(t): Newton on F_1(.; t) = 0 from x; stops once
-        max(||F_1(x^k)|| / ||F_1(x^0)||, ||F_1(x^k)||) <= tol."""
+        min(||F_1(x^k)|| / ||F_1(x^0)||, ||F_1(x^k)||) <= tol; each step
+        backtracks (1, 1/2, ..., at most 30 halvings) until
+        ||F_1(x + a dx)|| <= (1 - 1e-4 a) ||F_1(x)||."""
         x = np.array(x, dtype=np.float64)
         F = self.F1(x, t)
-        f0 = np.linalg.norm(F)
+        fn = f0 = np.linalg.norm(F)
         k = 0
         while k < maxit:
-            fn = np.linalg.norm(F)
-            if fn == 0.0 or max(fn / f0, fn) <= tol:
+            if fn == 0.0 or min(fn / f0, fn) <= tol:
                 break
             z, q = self.z_q(x)
             dx, its = self.solve(-F, self.w_of(q, t), z, method)
             if lin is not None:
                 lin.append(its)
-            x = x + dx
+            a = 1.0
+            for ls in range(31):
+                xt = x + a * dx
+                Ft = self.F1(xt, t)
+                ft = np.linalg.norm(Ft)
+                if ft <= (1.0 - 1e-4 * a) * fn or ls == 30:
+                    break
+                a *= 0.5
+            x, F, fn = xt, Ft, ft
             k += 1
-            F = self.F1(x, t)
         return x, k
 
     def split_t(self, q):

@@ -210,7 +210,7 @@ struct smg_ctx {
   // -F_1, Newton increment, saved iterate, J_12, J_11^{-1} J_12, residual scratch
   double *cz = nullptr, *cwv = nullptr, *cs = nullptr, *cpart = nullptr, *cc = nullptr;
   double *cb = nullptr, *cr = nullptr, *cdx = nullptr, *cxk = nullptr, *cj12 = nullptr, *cxi = nullptr,
-         *clr = nullptr;
+         *clr = nullptr, *cxt = nullptr;
   bool lr_on = false;          // rank-one terms in the finest-level operator
   size_t used_bytes = 0;
   // captured V-cycles, one per (x, f, kind); kind = precision * 2 + zero_first
@@ -334,6 +334,7 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
     C->cj12 = cv.take<double>(len0);
     C->cxi = cv.take<double>(len0);
     C->clr = cv.take<double>(len0);
+    C->cxt = cv.take<double>(len0);
   }
   // node factor pairs last: the other buffers keep the places they have without them
   for (int l = 0; l < nl; ++l) {
@@ -2059,21 +2060,30 @@ struct CvarRun {
     lin_total += st.iterations;
     return SMG_OK;
   }
-  // h(t): Newton on F_1(.; t) = 0 from x, no line search
+  // h(t): Newton on F_1(.; t) = 0 from x, each step backtracking on ||F_1||
   int inner(double* x, double t) {
     double fn, f0;
     TRY(F1(x, t, &fn));
     f0 = fn;
+    const size_t bytes = sizeof(double) * C->len0;
     for (int k = 0; k < p->inner_maxit; ++k) {
-      if (fn == 0.0 || std::max(fn / f0, fn) <= p->inner_tol) break;
+      if (fn == 0.0 || std::min(fn / f0, fn) <= p->inner_tol) break;
       bool any;
       TRY(set_w(t, &any));
       TRY(solve(C->cdx, C->cr, any));
-      hipLaunchKernelGGL(k_axpy, dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, x, 1.0,
-                         (const double*)C->cdx);
-      LAUNCH_CHECK();
+      double a = 1.0, ft = 0.0;
+      for (int ls = 0; ls <= 30; ++ls) {
+        HIP_TRY(hipMemcpyAsync(C->cxt, x, bytes, hipMemcpyDeviceToDevice, C->stream));
+        hipLaunchKernelGGL(k_axpy, dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, C->cxt, a,
+                           (const double*)C->cdx);
+        LAUNCH_CHECK();
+        TRY(F1(C->cxt, t, &ft));
+        if (ft <= (1.0 - 1e-4 * a) * fn || ls == 30) break;
+        a *= 0.5;
+      }
+      HIP_TRY(hipMemcpyAsync(x, C->cxt, bytes, hipMemcpyDeviceToDevice, C->stream));
+      fn = ft;
       ++inner_total;
-      TRY(F1(x, t, &fn));
     }
     return SMG_OK;
   }
