@@ -677,9 +677,11 @@ def main():
     # (Section 5, Algorithm 2): nu 1e-4, beta 1e-2, -50 <= u <= 50, phi <= 1e-9,
     # every Newton system to 1e-11; the paper's target, no source
     ssn = ssn_section(dev, n, N, args)
-    paper = paper_tables(dev)
-    paper["l1_tables"] = ssn_tables(dev)
-    paper["cvar_tables"] = cvar_tables(dev)
+    paper = None
+    if not args.quick:   # the paper's table settings: many small solves
+        paper = paper_tables(dev)
+        paper["l1_tables"] = ssn_tables(dev)
+        paper["cvar_tables"] = cvar_tables(dev)
 
     # ---------------- roofline of the dominant kernel: finest-level half-sweep
     xs = torch.zeros(dof, dtype=torch.float64, device=dev)
