@@ -103,3 +103,25 @@ def test_cvar_solve_matches_the_oracle(B, cv, lam, eps, N):
     # the GPU's final iterate solves F_1 = 0 and F_2 = 0 in the oracle's arithmetic
     assert np.linalg.norm(c.F1(xg, st["t"])) <= 1e-7
     assert abs(c.F4(c.z_q(xg)[1], st["t"])) <= 1e-6
+
+
+def test_cvar_on_the_square_with_collocation_weights(B, cv):
+    """Non-uniform sample weights (Gauss-Hermite nodes, 2^3) on the square, and
+    lambda = 0 (the risk-neutral limit: t^0 = 0 already solves F_2 = 0)."""
+    p = inputs.collocation_problem(15, 2, 1e-3, M=3, sigma=0.5, decay=True, yd=inputs.paper_target(15), f=0.0,
+                                   field="gaussian", corr_len2=0.5)
+    for lam, eps in ((0.75, 0.05), (0.0, 0.01)):
+        c = cv.Cvar(p, lam, eps)
+        ref = c.run("gmres")
+        assert ref["converged"]
+        ctx, f = context(B, p)
+        x = torch.zeros(c.o.vlen(), dtype=torch.float64, device="cuda")
+        rc, st = ctx.cvar_solve(x, f, dev(c.yd.reshape(p.n, p.n)), c.zeta, lam, eps, c.mass)
+        assert rc == B.SMG_OK
+        assert st["outer"] == ref["outer"] and abs(st["inner_total"] - ref["inner_total"]) <= 2
+        if lam == 0.0:
+            assert st["outer"] == 0 and st["t"] == 0.0
+        assert abs(st["t"] - ref["t"]) <= 1e-7 * max(1.0, abs(ref["t"]))
+        u = c.blocks(node_to_paper(host(x), p.n, p.N))[1]
+        assert np.abs(u - ref["u"]).max() <= 1e-6 * np.abs(ref["u"]).max()
+        ctx.close()
