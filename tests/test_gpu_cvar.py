@@ -125,3 +125,26 @@ def test_cvar_on_the_square_with_collocation_weights(B, cv):
         u = c.blocks(node_to_paper(host(x), p.n, p.N))[1]
         assert np.abs(u - ref["u"]).max() <= 1e-6 * np.abs(ref["u"]).max()
         ctx.close()
+
+
+def test_cvar_entry_points_reject_bad_arguments(B, cv):
+    p = problem()
+    c = cv.Cvar(p, 0.5, 0.05)
+    ctx, f = context(B, p)
+    x = torch.zeros(c.o.vlen(), dtype=torch.float64, device="cuda")
+    yd = dev(c.yd.reshape(p.n, p.n))
+    for lam, eps, zeta in ((1.0, 0.05, c.zeta), (0.5, 0.0, c.zeta), (-0.1, 0.05, c.zeta),
+                           (0.5, 0.05, -c.zeta)):
+        with pytest.raises(B.SmgError):
+            ctx.cvar_solve(x, f, yd, zeta, lam, eps, c.mass)
+    with pytest.raises(B.SmgError):
+        ctx.set_sample_weights(np.full(p.N, -1.0))
+    assert ctx.L.smg_set_lowrank(ctx.ctx, B._ptr(x), None) != B.SMG_OK   # z without w
+    ctx.close()
+    # contexts without the risk-averse buffers refuse the rank-one terms and the solver
+    plain, f2 = B.context_from_problem(p, gmres_restart=30, theta=0.5, flags=B.SMG_FLAG_JACOBI)
+    with pytest.raises(B.SmgError):
+        plain.set_lowrank(dev(np.zeros((p.n * p.n, p.N))), dev(np.zeros(p.N)))
+    with pytest.raises(B.SmgError):
+        plain.cvar_solve(x, f2, yd, c.zeta, 0.5, 0.05, c.mass)
+    plain.close()
