@@ -148,3 +148,25 @@ def test_cvar_entry_points_reject_bad_arguments(B, cv):
     with pytest.raises(B.SmgError):
         plain.cvar_solve(x, f2, yd, c.zeta, 0.5, 0.05, c.mass)
     plain.close()
+
+
+def test_cvar_at_the_papers_table_size(B, cv):
+    """The risk-averse table's setting (L-shape with 705 nodes, Gaussian field
+    sigma^2 1, L^2 0.1, 15 modes, N = 500 Monte Carlo samples, lambda 0.9, eps
+    1e-2) as the benchmark runs it: the GPU's result zeroes F_1 and F_2 in the
+    oracle's arithmetic (one residual evaluation, no oracle solve)."""
+    p = inputs.make_problem(31, 500, 1e-4, M=15, sigma=1.0, seed=23, yd=inputs.paper_target(31), f=0.0,
+                            field="gaussian", corr_len2=0.1, domain="lshape")
+    c = cv.Cvar(p, 0.9, 1e-2)
+    ctx, f = context(B, p)
+    x = torch.zeros(c.o.vlen(), dtype=torch.float64, device="cuda")
+    rc, st = ctx.cvar_solve(x, f, dev(c.yd.reshape(p.n, p.n)), c.zeta, 0.9, 1e-2, c.mass)
+    assert rc == B.SMG_OK and 1 <= st["outer"] <= 10
+    xg = node_to_paper(host(x), p.n, p.N)
+    z, q = c.z_q(xg)
+    assert abs(c.F4(q, st["t"])) <= 1e-6
+    F1 = c.F1(xg, st["t"])
+    assert np.linalg.norm(F1) <= 1e-8 * max(1.0, np.linalg.norm(c.rhs(c.c_of(q, st["t"]))))
+    # a tenth of the samples (the upper tail) carries the weight: sum zeta g'(Q) = 1 - lambda
+    assert abs(np.sum(c.zeta * cv.dg_eps(q - st["t"], 1e-2)) - 0.1) <= 1e-6
+    ctx.close()
