@@ -484,6 +484,41 @@ def ssn_tables(dev):
     return out
 
 
+def cvar_problem(n=31, N=500, seed=23):
+    """The risk-averse table's problem: L-shape, Gaussian field sigma^2 1, L^2 0.1,
+    15 modes, Monte Carlo samples, nu 1e-4, the paper's target, f = 0."""
+    from paper_2302_13680_amd import inputs
+    return inputs.make_problem(n, N, 1e-4, M=15, sigma=1.0, seed=seed, yd=inputs.paper_target(n), f=0.0,
+                               field="gaussian", corr_len2=0.1, domain="lshape")
+
+
+def cvar_run(dev, p, lam, eps, x=None, t0=0.0):
+    """Algorithm 3 on problem p (GMRES(30) with the Jacobi V-cycle): returns x,
+    the solver's stats and a table row with the device wall time."""
+    import numpy as np
+    import torch
+    from paper_2302_13680_amd import binding
+    ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5,
+                                          flags=binding.SMG_FLAG_JACOBI | binding.SMG_FLAG_CVAR)
+    mass = -float(p.d[0])
+    zeta = np.asarray(p.c) / mass
+    live = np.ones(p.n * p.n) if p.domain is None else np.asarray(p.domain).reshape(-1)
+    yd = torch.tensor((np.asarray(p.yd).reshape(-1) * live).reshape(p.n, p.n), dtype=torch.float64, device=dev)
+    if x is None:
+        x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    rc, st = ctx.cvar_solve(x, f, yd, zeta, lam, eps, mass, t0=t0)
+    torch.cuda.synchronize()
+    wall = 1e3 * (time.perf_counter() - t_start)
+    ctx.close()
+    mean = st["linear_total"] / max(st["linear_solves"], 1)
+    row = {"counts": [st["outer"], st["inner_total"], round(mean, 1)], "converged": rc == binding.SMG_OK,
+           "t": st["t"], "wall_ms": round(wall, 1)}
+    print("cvar", p.n, p.N, lam, eps, json.dumps(row), file=sys.stderr, flush=True)
+    return x, st, row
+
+
 def cvar_tables(dev):
     """The settings of the paper's risk-averse table (Section 6, Algorithm 3) on
     the L-shape with the Gaussian field (sigma^2 1, L^2 0.1, 15 modes), Monte
@@ -492,35 +527,10 @@ def cvar_tables(dev):
     printed [outer, inner, mean V-cycles, mean GMRES]; the eps sweep continues
     from the previous eps's solution (x and t), as the paper does.  Wall time of
     every run on the device."""
-    import numpy as np
-    import torch
-    from paper_2302_13680_amd import binding, inputs
-
-    def problem(n=31, N=500, seed=23):
-        return inputs.make_problem(n, N, 1e-4, M=15, sigma=1.0, seed=seed, yd=inputs.paper_target(n), f=0.0,
-                                   field="gaussian", corr_len2=0.1, domain="lshape")
+    problem = cvar_problem
 
     def run(p, lam, eps, x=None, t0=0.0):
-        ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5,
-                                              flags=binding.SMG_FLAG_JACOBI | binding.SMG_FLAG_CVAR)
-        mass = -float(p.d[0])
-        zeta = np.asarray(p.c) / mass
-        live = np.ones(p.n * p.n) if p.domain is None else np.asarray(p.domain).reshape(-1)
-        yd = torch.tensor((np.asarray(p.yd).reshape(-1) * live).reshape(p.n, p.n), dtype=torch.float64,
-                          device=dev)
-        if x is None:
-            x = torch.zeros(p.dof, dtype=torch.float64, device=dev)
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        rc, st = ctx.cvar_solve(x, f, yd, zeta, lam, eps, mass, t0=t0)
-        torch.cuda.synchronize()
-        wall = 1e3 * (time.perf_counter() - t_start)
-        ctx.close()
-        mean = st["linear_total"] / max(st["linear_solves"], 1)
-        row = {"counts": [st["outer"], st["inner_total"], round(mean, 1)], "converged": rc == binding.SMG_OK,
-               "t": st["t"], "wall_ms": round(wall, 1)}
-        print("cvar", p.n, p.N, lam, eps, json.dumps(row), file=sys.stderr, flush=True)
-        return x, st, row
+        return cvar_run(dev, p, lam, eps, x=x, t0=t0)
 
     out = {"method": "GMRES(30), one V-cycle of S(c) as preconditioner, rank-one terms in the operator",
            "format": "[outer, inner Newton, mean GMRES] (this build) beside [outer, inner, mean V-cycles, mean GMRES]"}
@@ -559,6 +569,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the 511x511, N=256 workload and print its record (for profiling)")
+    ap.add_argument("--cvar-only", action="store_true",
+                    help="run only the risk-averse solver at 705 nodes, N=2000, lambda 0.95 (for profiling)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune_lanes.json"))
     ap.add_argument("--counters", nargs="?", const="medium", choices=["medium", "large"],
                     help="launch only the finest-level FP64 half-sweep (20x) of the 255x255, N=64 "
@@ -577,6 +589,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.cvar_only:
+        p = cvar_problem(31, 2000)
+        cvar_run(dev, p, 0.95, 1e-2)                 # warm-up (graph capture)
+        _, _, row = cvar_run(dev, p, 0.95, 1e-2)
+        print(json.dumps({"cvar": dict(workload="L-shape 705 nodes, N=2000, lambda 0.95, eps 1e-2", **row)}),
+              flush=True)
+        return
     if args.large_only:
         large, _, _, _ = large_mixed_section(dev)
         print(json.dumps({"large_mixed": large}), flush=True)

@@ -195,6 +195,27 @@ __global__ __launch_bounds__(kBlock) void k_coarse_schur_terms(int m, const doub
   }
 }
 
+// Pre-reduction of the Schur terms over samples: part[q] = sum of terms[j] over
+// the samples j of chunk q (kSchurChunk consecutive samples, in order), one
+// block per chunk, so that the single-block inversion below sums N / kSchurChunk
+// partials instead of N terms.
+constexpr int kSchurChunk = 64;
+__global__ __launch_bounds__(kBlock) void k_coarse_schur_chunks(int m, int N, const double* __restrict__ terms,
+                                                                double* __restrict__ part) {
+  const int j0 = blockIdx.x * kSchurChunk, j1 = min(N, j0 + kSchurChunk);
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+    double s = 0.0;
+    for (int q0 = j0; q0 < j1; q0 += 16) {
+      double t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) t[u] = terms[(size_t)(q0 + u < j1 ? q0 + u : j1 - 1) * m * m + idx];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += q0 + u < j1 ? t[u] : 0.0;
+    }
+    part[(size_t)blockIdx.x * m * m + idx] = s;
+  }
+}
+
 // Transposed Schur complement (g I + sum_j terms[j])^T (fixed order over j) inverted in
 // place; the result is the transposed storage of its inverse.  One block.
 __global__ __launch_bounds__(kBlock) void k_coarse_schur_invert(int m, int N, const double* __restrict__ terms,
@@ -271,7 +292,8 @@ __device__ __forceinline__ void coarse_phase2_sample(int j, int m, int N, const 
                                                      const double* __restrict__ Sinv,
                                                      const double* __restrict__ c, const double* __restrict__ e,
                                                      const double* __restrict__ mk, const TV* __restrict__ F,
-                                                     const double* __restrict__ ds, TV* __restrict__ X) {
+                                                     const double* __restrict__ ds, TV* __restrict__ X,
+                                                     const double* __restrict__ upre = nullptr) {
   __shared__ double sR[kMaxCoarse], sU[kMaxCoarse], sT[kMaxCoarse], sY[kMaxCoarse];
   const int i = threadIdx.x;
   const double* Aj = Ainv + (size_t)j * m * m;
@@ -282,21 +304,25 @@ __device__ __forceinline__ void coarse_phase2_sample(int j, int m, int N, const 
   double em = 0.0;   // this row's E_j entry, loaded with the rest
   if (i < m) {
     load_row(Aj, m, i, a);
-    load_row(Sinv, m, i, si);
     em = mk[2 * i + 1] * e[j];
-    // F_U - sum_j ds_j, in sample order; 16 loads in flight per round trip
-    double s = (double)FU[i];
-    for (int q0 = 0; q0 < N; q0 += 16) {
-      double t[16];
+    if (upre) {                 // u computed once for all samples (k_coarse_u)
+      sU[i] = upre[i];
+    } else {
+      load_row(Sinv, m, i, si);
+      // F_U - sum_j ds_j, in sample order; 16 loads in flight per round trip
+      double s = (double)FU[i];
+      for (int q0 = 0; q0 < N; q0 += 16) {
+        double t[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) t[u] = ds[(size_t)(q0 + u < N ? q0 + u : N - 1) * m + i];
+        for (int u = 0; u < 16; ++u) t[u] = ds[(size_t)(q0 + u < N ? q0 + u : N - 1) * m + i];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) s -= q0 + u < N ? t[u] : 0.0;
+        for (int u = 0; u < 16; ++u) s -= q0 + u < N ? t[u] : 0.0;
+      }
+      sR[i] = s;
     }
-    sR[i] = s;
   }
   __syncthreads();
-  if (i < m) sU[i] = dot_row(si, m, sR);
+  if (!upre && i < m) sU[i] = dot_row(si, m, sR);
   __syncthreads();
   if (i < m) sT[i] = (double)FP[(size_t)i * N + j] - em * sU[i];
   __syncthreads();
@@ -325,8 +351,50 @@ __global__ __launch_bounds__(64) void k_coarse_phase2(int m, int N, const double
                                                       const double* __restrict__ Sinv,
                                                       const double* __restrict__ c, const double* __restrict__ e,
                                                       const double* __restrict__ mk, const TV* __restrict__ F,
-                                                      const double* __restrict__ ds, TV* __restrict__ X) {
-  coarse_phase2_sample<TV>(blockIdx.x, m, N, Ainv, Sinv, c, e, mk, F, ds, X);
+                                                      const double* __restrict__ ds, TV* __restrict__ X,
+                                                      const double* __restrict__ upre) {
+  coarse_phase2_sample<TV>(blockIdx.x, m, N, Ainv, Sinv, c, e, mk, F, ds, X, upre);
+}
+
+// u = Sinv (F_U - sum_j ds_j) once for all samples, for many samples (every
+// phase-2 block would otherwise sum all N of them): 16 slices of 64 lanes sum
+// the samples j = slice (mod 16), then meet in LDS in slice order.  One block.
+constexpr int kCoarseUSlices = 16;
+template <typename TV>
+__global__ __launch_bounds__(64 * kCoarseUSlices) void k_coarse_u(int m, int N, const double* __restrict__ Sinv,
+                                                                   const TV* __restrict__ F,
+                                                                   const double* __restrict__ ds,
+                                                                   double* __restrict__ u) {
+  __shared__ double part[kCoarseUSlices][kMaxCoarse];
+  __shared__ double sR[kMaxCoarse];
+  const int i = threadIdx.x % 64, sl = threadIdx.x / 64;
+  if (i < m) {
+    double s = 0.0;
+    for (int j0 = sl; j0 < N; j0 += 8 * kCoarseUSlices) {
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int jj = j0 + q * kCoarseUSlices;
+        t[q] = jj < N ? ds[(size_t)jj * m + i] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += t[q];
+    }
+    part[sl][i] = s;
+  }
+  __syncthreads();
+  if (sl == 0 && i < m) {
+    double r = (double)F[(size_t)N * m + i];
+#pragma unroll
+    for (int q = 0; q < kCoarseUSlices; ++q) r -= part[q][i];
+    sR[i] = r;
+  }
+  __syncthreads();
+  if (sl == 0 && i < m) {
+    double si[kMaxCoarse];
+    load_row(Sinv, m, i, si);
+    u[i] = dot_row(si, m, sR);
+  }
 }
 
 }  // namespace smg

@@ -34,15 +34,30 @@ __global__ __launch_bounds__(kBlock) void k_sample_dots(int nn, int N, const dou
   }
 }
 
-// out_j = scale_j sum_b part[b][j] (scale NULL: 1).
+// out_j = scale_j sum_b part[b][j] (scale NULL: 1).  A block takes 64
+// samples; its 4 waves sum every fourth partial (independent loads in flight)
+// and meet in LDS.
+constexpr int kFinalizeSamples = 64;
 __global__ __launch_bounds__(kBlock) void k_sample_finalize(int nb, int N, const double* __restrict__ part,
                                                             const double* __restrict__ scale,
                                                             double* __restrict__ out) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= N) return;
+  constexpr int kSlices = kBlock / kFinalizeSamples;
+  __shared__ double acc[kSlices][kFinalizeSamples];
+  const int jl = threadIdx.x % kFinalizeSamples, slice = threadIdx.x / kFinalizeSamples;
+  const int j = blockIdx.x * kFinalizeSamples + jl;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(size_t)b * N + j];
-  out[j] = scale ? scale[j] * s : s;
+  if (j < N) {
+#pragma unroll 8
+    for (int b = slice; b < nb; b += kSlices) s += part[(size_t)b * N + j];
+  }
+  acc[slice][jl] = s;
+  __syncthreads();
+  if (slice == 0 && j < N) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSlices; ++q) t += acc[q][jl];
+    out[j] = scale ? scale[j] * t : t;
+  }
 }
 
 // Y_j += sign coef_j z_j (the rank-one terms w_j z_j (z_j . x_j) once coef_j =

@@ -25,6 +25,7 @@ namespace {
 
 constexpr int kMaxLevels = 16;
 constexpr int kMaxSamples = 2048;
+constexpr int kCoarseUMin = 512;   // above this many samples the coarsest u is computed once
 
 template <typename T>
 struct Level {
@@ -181,6 +182,8 @@ struct smg_ctx {
   double* Sinv = nullptr;      // [m][m]
   double* ds = nullptr;        // [N][m]
   double* terms = nullptr;     // [N][m][m], setup only
+  double* schur_part = nullptr;   // [ceil(N / kSchurChunk)][m][m]: terms summed per chunk of samples
+  double* cu = nullptr;           // [m]: the coarsest u, computed once when N > kCoarseUMin
   double* partials = nullptr;  // [npart][4] per-block squared norms of a residual and of f
   size_t npart = 0;
   double* partials2 = nullptr; // [kNormStage][4] first-stage sums of many partials
@@ -336,6 +339,8 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
     C->clr = cv.take<double>(len0);
     C->cxt = cv.take<double>(len0);
   }
+  C->schur_part = cv.take<double>((size_t)((N + kSchurChunk - 1) / kSchurChunk) * m * m);
+  C->cu = cv.take<double>((size_t)m);
   // node factor pairs last: the other buffers keep the places they have without them
   for (int l = 0; l < nl; ++l) {
     const size_t nn = (size_t)C->L64[l].n * C->L64[l].n;
@@ -505,8 +510,11 @@ int node_terms(smg_ctx* C) {
   const Level<double>& Lc = C->L64[C->nlev - 1];
   hipLaunchKernelGGL(k_coarse_schur_terms, dim3(C->N), dim3(kBlock), 0, C->stream, C->m, C->Ainv, Lc.c, Lc.d, Lc.e,
                      (const double*)Lc.mk, C->terms);
-  hipLaunchKernelGGL(k_coarse_schur_invert, dim3(1), dim3(kBlock), 0, C->stream, C->m, C->N, C->terms, Lc.g,
-                     C->Sinv);
+  const int nchunks = (C->N + kSchurChunk - 1) / kSchurChunk;
+  hipLaunchKernelGGL(k_coarse_schur_chunks, dim3(nchunks), dim3(kBlock), 0, C->stream, C->m, C->N,
+                     (const double*)C->terms, C->schur_part);
+  hipLaunchKernelGGL(k_coarse_schur_invert, dim3(1), dim3(kBlock), 0, C->stream, C->m, nchunks,
+                     (const double*)C->schur_part, Lc.g, C->Sinv);
   LAUNCH_CHECK();
   return SMG_OK;
 }
@@ -655,8 +663,15 @@ int coarse_solve(smg_ctx* C, const TV* F, TV* X) {
   hipLaunchKernelGGL((k_coarse_phase1<TV>), dim3(C->N), dim3(64), 0, C->stream, C->m, C->N, C->Ainv, L.c, L.d,
                      (const double*)L.mk, F, C->ds);
   LAUNCH_CHECK();
+  // many samples: u once (k_coarse_u) instead of a sum over all samples in every block
+  const bool upre = C->N > kCoarseUMin;
+  if (upre) {
+    hipLaunchKernelGGL((k_coarse_u<TV>), dim3(1), dim3(64 * kCoarseUSlices), 0, C->stream, C->m, C->N,
+                       (const double*)C->Sinv, F, (const double*)C->ds, C->cu);
+    LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL((k_coarse_phase2<TV>), dim3(C->N), dim3(64), 0, C->stream, C->m, C->N, C->Ainv, C->Sinv,
-                     L.c, L.e, (const double*)L.mk, F, C->ds, X);
+                     L.c, L.e, (const double*)L.mk, F, C->ds, X, upre ? (const double*)C->cu : nullptr);
   LAUNCH_CHECK();
   return SMG_OK;
 }
@@ -841,7 +856,8 @@ int vec_norm(smg_ctx* C, const double* v, size_t len, double* out) {
 int sample_dots(smg_ctx* C, const double* A, const double* B, const double* scale, double* out) {
   const int nn = C->desc.n * C->desc.n, N = C->N, nb = std::min(kSampleBlocks, nn);
   hipLaunchKernelGGL(k_sample_dots, dim3(nb), dim3(kBlock), 0, C->stream, nn, N, A, B, C->cpart);
-  hipLaunchKernelGGL(k_sample_finalize, dim3((N + kBlock - 1) / kBlock), dim3(kBlock), 0, C->stream, nb, N,
+  hipLaunchKernelGGL(k_sample_finalize, dim3((N + kFinalizeSamples - 1) / kFinalizeSamples), dim3(kBlock), 0,
+                     C->stream, nb, N,
                      (const double*)C->cpart, scale, out);
   LAUNCH_CHECK();
   return SMG_OK;
