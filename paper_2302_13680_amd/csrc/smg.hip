@@ -628,6 +628,18 @@ int residual_restrict(smg_ctx* C, const Level<T>& L, const T* x, const T* f, T* 
 template <typename T>
 int prolong_add(smg_ctx* C, int nc, const T* coarse, T* fine, const T* fmk) {
   const int nf = 2 * nc + 1;
+  if (C->N > 512) {   // many samples: 256 lanes per fine node (4 or 8 samples per lane), 4x the waves
+    auto go = [&](auto Jc) {
+      constexpr int JM = decltype(Jc)::value;
+      mask_dispatch(C->masked, [&](auto Mc) {
+        hipLaunchKernelGGL((k_prolong_add<T, 256, JM, decltype(Mc)::value>), dim3(nf * nf), dim3(kBlock), 0,
+                           C->stream, nc, C->N, coarse, fine, fmk);
+      });
+    };
+    if (C->N <= 1024) go(IC<4>{}); else go(IC<8>{});
+    LAUNCH_CHECK();
+    return SMG_OK;
+  }
   lane_dispatch<false>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     const int per = kBlock / W, nb = (nf * nf + per - 1) / per;
