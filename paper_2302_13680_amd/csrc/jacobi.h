@@ -12,7 +12,29 @@ namespace smg {
 // halfsweep_node (with the residual rows as right-hand sides and no neighbour
 // terms), and xout_i = xin_i + theta d.  Out of place: xin and xout must not
 // alias (every node reads its neighbours' old values).
-template <typename T, int JM, int VW = 1, bool MK = true>
+// dsum and num summed over the node's group: W <= 64 lanes within a wave;
+// WT = kBlock (a block per node, for many samples) across its waves in LDS.
+template <int WT, typename T>
+__device__ __forceinline__ void jacobi_group_sums(T& a, T& b, int W) {
+  if constexpr (WT > 64) {
+    static_assert(WT == kBlock, "a wide group is one block");
+    __shared__ T sa[kBlock / 64], sb[kBlock / 64];
+    a = group_sum<64>(a);
+    b = group_sum<64>(b);
+    if ((threadIdx.x & 63) == 0) { sa[threadIdx.x >> 6] = a; sb[threadIdx.x >> 6] = b; }
+    __syncthreads();
+    T ra = 0, rb = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) { ra += sa[q]; rb += sb[q]; }
+    a = ra;
+    b = rb;
+  } else {
+    a = group_sum_w(a, W);
+    b = group_sum_w(b, W);
+  }
+}
+
+template <typename T, int JM, int VW = 1, bool MK = true, int WT = 0>
 __device__ __forceinline__ void jacobi_node(const LevelArgs<T>& L, const T* __restrict__ xin, T* __restrict__ xout,
                                             const T* __restrict__ f, T theta, int slot, int lane, int W) {
   static_assert(JM % VW == 0, "whole chunks per lane");
@@ -76,8 +98,7 @@ __device__ __forceinline__ void jacobi_node(const LevelArgs<T>& L, const T* __re
       rYq[q] = rY; rPq[q] = rP; ia[q] = ai; cq[q] = cj[v]; eq[q] = mf.e * ej[v]; yo[q] = y0[v]; po[q] = p0[v];
     }
   }
-  dsum = group_sum_w(dsum, W);
-  num = group_sum_w(num, W);
+  jacobi_group_sums<WT>(dsum, num, W);
   const T rU = fu - (L.g * u + dsum);                         // U row: G u + sum_j D_j p_j
   const T du = (rU + num) / gd;
 #pragma unroll
@@ -108,7 +129,7 @@ void k_jacobi(LevelArgs<T> L, const T* __restrict__ xin, T* __restrict__ xout, c
   const int lane = threadIdx.x & (W - 1);
   const int slot = group_slot<W>(b);
   if (slot >= L.n * L.n) return;
-  jacobi_node<T, JM, VW, MK>(L, xin, xout, f, theta, slot, lane, W);
+  jacobi_node<T, JM, VW, MK, W>(L, xin, xout, f, theta, slot, lane, W);
 }
 
 }  // namespace smg

@@ -442,6 +442,18 @@ int jacobi(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const T* f) {
   const int nn = L.n * L.n;
   const T theta = (T)C->desc.theta;
   const LevelArgs<T> a = args(L, C->N, C->desc.strip);
+  if (C->N > 512) {   // many samples: a block of 256 lanes per node (4 or 8 samples per lane), 4x the waves
+    auto go = [&](auto Jc) {
+      constexpr int JM = decltype(Jc)::value;
+      mask_dispatch(C->masked, [&](auto Mc) {
+        hipLaunchKernelGGL((k_jacobi<T, kBlock, JM, 1, decltype(Mc)::value>), dim3(nn), dim3(kBlock), 0, C->stream,
+                           a, xin, xout, f, theta);
+      });
+    };
+    if (C->N <= 1024) go(IC<4>{}); else go(IC<8>{});
+    LAUNCH_CHECK();
+    return SMG_OK;
+  }
   lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     constexpr int VW = halfsweep_vw(decltype(Vc)::value, JM);

@@ -64,6 +64,10 @@ def test_many_sample_steps(B, O, N):
     cd = torch.empty(o.vlen(1), dtype=torch.float64, device="cuda")
     ctx.residual_restrict(0, xd, fd, cd)
     assert rel(node_to_paper(host(cd), nc, N), O.restrict(n, N, o.residual(x, f))) <= 1e-14
+    cl = rng.standard_normal(o.vlen(1))
+    fine = xd.clone()
+    ctx.prolong_add(0, dev(paper_to_node(cl, nc, N)), fine)
+    assert rel(node_to_paper(host(fine), n, N), O.prolong_add(nc, N, cl, x)) <= 1e-15
     F = rng.standard_normal(o.vlen(1))
     X = torch.empty(F.size, dtype=torch.float64, device="cuda")
     ctx.coarse_solve(dev(paper_to_node(F, nc, N)), X)
