@@ -372,13 +372,22 @@ typedef struct {
   double mass;        /* M = mass I, the lumped mass (h^2 for these grids) */
   const double *zeta; /* host [N]: sample weights (sum 1) */
   double tol;         /* outer stop |F(t)| <= tol (the paper: 1e-6) */
-  double inner_tol;   /* h(t): stop once min(||F_1|| / ||F_1(x^0)||, ||F_1||) <= inner_tol (1e-8) */
+  double inner_tol;   /* h(t): stop once max(||F_1|| / ||F_1(x^0)||, ||F_1||) <= inner_tol (the
+                         paper: 1e-8; x^0 the start of that Newton iteration) */
   double lin_rtol;    /* GMRES relative residual of every Newton system (1e-9) */
   int maxit;          /* outer iterations at most */
   int inner_maxit;    /* Newton iterations per evaluation of h(t) at most */
   int lin_maxit;      /* GMRES iterations per system at most (the paper: 80) */
   double sigma, rho;  /* line search on t (0: 1e-4, 1/2) */
+  int inner_rule;     /* 0: the printed rule with max (both parts small); SMG_CVAR_INNER_MIN:
+                         min (either part small).  Not the paper's; a named option */
+  int inner_backtrack;/* 0: full Newton steps for h(t) (Algorithm 3 states no line search
+                         there); 1: halve each step (at most 30 times) until
+                         ||F_1(x + a dx)|| <= (1 - 1e-4 a) ||F_1(x)||.  Not the paper's */
 } smg_cvar_params;
+
+#define SMG_CVAR_INNER_MAX 0
+#define SMG_CVAR_INNER_MIN 1
 
 typedef struct {
   int outer;            /* outer (preconditioned) Newton iterations */
@@ -391,6 +400,12 @@ typedef struct {
   double *F;            /* optional caller buffer of cap entries: |F(t^k)| per iterate */
   int cap;
   int len;
+  int inner_capped;     /* evaluations of h(t) that ended at inner_maxit (with the printed rule:
+                           a warm start within 1/inner_tol of the rounding floor) */
+  int *inner_counts;    /* optional caller buffer of inner_cap entries: Newton count of every
+                           evaluation of h(t), in order */
+  int inner_cap;
+  int inner_len;
 } smg_cvar_stats;
 
 /* Algorithm 3 for the smoothed risk-averse problem: x (device, the linear-
@@ -402,9 +417,10 @@ typedef struct {
  * mass / (1 - lambda)) and the rank-one terms are cleared on return.  F_1(x; t)
  * is S(c) x - [c_j y_d | f_U | f_P]; every Newton system J_11 dx = -F_1 and the
  * solve for F'(t) = J_22 - J_21 J_11^{-1} J_12 run GMRES preconditioned by one
- * V-cycle of S(c) from zero.  h(t) is computed by Newton from the current x,
- * each step backtracking (1, 1/2, ..., at most 30 halvings) until
- * ||F_1(x + a dx)|| <= (1 - 1e-4 a) ||F_1(x)||; when every g''(Q_j) vanishes (eq. condition) the step
+ * V-cycle of S(c) from zero.  h(t) is computed by Newton from the current x with
+ * full steps, stopped by the rule of the risk-averse experiments (Section 6):
+ * max(||F_1(x^k)|| / ||F_1(x^0)||, ||F_1(x^k)||) <= inner_tol (inner_rule and
+ * inner_backtrack select the non-default variants); when every g''(Q_j) vanishes (eq. condition) the step
  * is the split one (h(t^k), the root of F_2(x; t) = 0 by bisection, h at that
  * root); else
  * the Newton step on t with backtracking |F(t + gamma d)| - |F(t)| <=

@@ -41,11 +41,13 @@ as in the paper; 300 for the V-cycle iteration).
 Readings (the paper leaves them open): the smoothing function's middle branch is
 g(x) = s^3/eps^2 - s^4/(2 eps^3) with s = x + eps/2 (the printed branch has a
 typo; this is the C^2 piece that joins 0 and x); t^0 = 0; the Newton iterates
-for h(t) start from the current x; the inner stopping rule is taken with min
-(either the relative or the absolute residual below 1e-8: with max, a warm
-start near h(t) could never meet the relative part, its residual being at the
-rounding floor already); the inner Newton backtracks on ||F_1|| (without a
-globalization it cycles when few samples lie in the smoothing band);
+for h(t) start from the current x; the inner Newton stops by the printed rule
+max(||F_1(x^k)|| / ||F_1(x^0)||, ||F_1(x^k)||) <= 1e-8 with x^0 the start of that
+inner iteration, and takes full steps (Algorithm 3 states no line search for
+h); an evaluation that cannot meet the relative part (a warm start whose
+||F_1(x^0)|| is within 1e8 of the rounding floor) runs to the iteration cap,
+which is counted; the rule with min and a backtracking on ||F_1|| are kept as
+named options (``inner_rule="min"``, ``inner_backtrack=True``), not defaults;
 the split step solves F_2(x; t) = 0 by bisection (F_2 is nondecreasing in t)
 and then recomputes x = h(t) at the new t, since F(t) = F_2(h(t), t) is what the
 next test reads;
@@ -183,31 +185,45 @@ class Cvar:
             x = x + np.array(Zs).T @ y
 
     # --- the two Newton iterations ----------------------------------------
-    def inner(self, x, t, method, tol=1e-8, maxit=50, lin=None):
-        """h(t): Newton on F_1(.; t) = 0 from x; stops once
-        min(||F_1(x^k)|| / ||F_1(x^0)||, ||F_1(x^k)||) <= tol; each step
-        backtracks (1, 1/2, ..., at most 30 halvings) until
-        ||F_1(x + a dx)|| <= (1 - 1e-4 a) ||F_1(x)||."""
+    def inner(self, x, t, method, tol=1e-8, maxit=50, lin=None, rule="max", backtrack=False, hist=None):
+        """h(t): Newton on F_1(.; t) = 0 from x.
+
+        rule="max" (Section 6, the stopping rules stated with the risk-averse
+        table): stop once max(||F_1(x^k)|| / ||F_1(x^0)||, ||F_1(x^k)||) <= tol,
+        i.e. both the relative and the absolute residual are small; plain
+        Newton steps x^{k+1} = x^k + dx (Algorithm 3 states no line search for
+        h).  rule="min" stops once either part is small; backtrack=True halves
+        each step (1, 1/2, ..., at most 30 halvings) until
+        ||F_1(x + a dx)|| <= (1 - 1e-4 a) ||F_1(x)||.  Neither option is the
+        paper's; both are kept as named variants.  hist (a list) receives
+        ||F_1|| at every iterate."""
+        if rule not in ("max", "min"):
+            raise ValueError("rule must be 'max' or 'min'")
+        stop = max if rule == "max" else min
         x = np.array(x, dtype=np.float64)
         F = self.F1(x, t)
         fn = f0 = np.linalg.norm(F)
+        if hist is not None:
+            hist.append(fn)
         k = 0
         while k < maxit:
-            if fn == 0.0 or min(fn / f0, fn) <= tol:
+            if fn == 0.0 or stop(fn / f0, fn) <= tol:
                 break
             z, q = self.z_q(x)
             dx, its = self.solve(-F, self.w_of(q, t), z, method)
             if lin is not None:
                 lin.append(its)
             a = 1.0
-            for ls in range(31):
+            for ls in range(31 if backtrack else 1):
                 xt = x + a * dx
                 Ft = self.F1(xt, t)
                 ft = np.linalg.norm(Ft)
-                if ft <= (1.0 - 1e-4 * a) * fn or ls == 30:
+                if not backtrack or ft <= (1.0 - 1e-4 * a) * fn or ls == 30:
                     break
                 a *= 0.5
             x, F, fn = xt, Ft, ft
+            if hist is not None:
+                hist.append(fn)
             k += 1
         return x, k
 
@@ -225,13 +241,23 @@ class Cvar:
         return 0.5 * (lo + hi)
 
     def run(self, method: str = "gmres", t0: float = 0.0, tol: float = 1e-6, maxit: int = 50,
-            sigma: float = 1e-4, rho: float = 0.5, max_ls: int = 30, x0=None):
+            sigma: float = 1e-4, rho: float = 0.5, max_ls: int = 30, x0=None, inner_tol: float = 1e-8,
+            inner_maxit: int = 50, inner_rule: str = "max", inner_backtrack: bool = False):
         """Algorithm 3.  Returns t, x, u, the outer and inner Newton counts, the
+        Newton count of every evaluation of h (``inner_counts``; an entry equal
+        to inner_maxit is an evaluation that ended at the cap), the
         linear-solver iterations of every solve and |F(t^k)| per iterate."""
-        lin = []
+        lin, counts = [], []
         t = float(t0)
         x = np.zeros((2 * self.N + 1) * self.nn) if x0 is None else np.array(x0, dtype=np.float64)
-        x, inner_total = self.inner(x, t, method, lin=lin)
+        base_inner = self.inner
+
+        def inner(x, t, method, lin=None):
+            xx, kk = base_inner(x, t, method, tol=inner_tol, maxit=inner_maxit, lin=lin, rule=inner_rule,
+                                backtrack=inner_backtrack)
+            counts.append(kk)
+            return xx, kk
+        x, inner_total = inner(x, t, method, lin=lin)
         hist, k, converged = [], 0, False
         while True:
             z, q = self.z_q(x)
@@ -244,11 +270,11 @@ class Cvar:
                 break
             w = self.w_of(q, t)
             if not np.any(w != 0.0):                       # eq. condition: split step
-                x, kk = self.inner(x, t, method, lin=lin)
+                x, kk = inner(x, t, method, lin=lin)
                 inner_total += kk
                 t = self.split_t(self.z_q(x)[1])
                 # F(t) = F_2(h(t), t): the next test needs h at the new t
-                x, kk = self.inner(x, t, method, lin=lin)
+                x, kk = inner(x, t, method, lin=lin)
                 inner_total += kk
             else:
                 self.F1(x, t)                              # S(c) at (x^k, t^k)
@@ -261,7 +287,7 @@ class Cvar:
                 d = -Ft / Fp
                 gamma = 1.0
                 for ls in range(max_ls + 1):
-                    xt, kk = self.inner(x, t + gamma * d, method, lin=lin)
+                    xt, kk = inner(x, t + gamma * d, method, lin=lin)
                     inner_total += kk
                     Fn = self.F4(self.z_q(xt)[1], t + gamma * d)
                     if abs(Fn) - abs(Ft) <= -sigma * abs(Ft):
@@ -271,7 +297,9 @@ class Cvar:
                 t, x = t + gamma * d, xt
             k += 1
         u = self.blocks(x)[1].copy()
-        return dict(t=t, x=x, u=u, outer=k, inner_total=inner_total, linear=lin, F=hist, converged=converged)
+        return dict(t=t, x=x, u=u, outer=k, inner_total=inner_total, inner_counts=counts,
+                    inner_capped=sum(1 for c in counts if c >= inner_maxit), linear=lin, F=hist,
+                    converged=converged)
 
     def objective(self, y_of_u, u, t):
         """t + E[g(Q)] / (1 - lambda) + nu/2 u^T M u for states y_of_u(u) (N, nn)."""

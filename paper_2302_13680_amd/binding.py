@@ -71,13 +71,16 @@ class CvarParams(C.Structure):
     _fields_ = [("lam", C.c_double), ("eps", C.c_double), ("mass", C.c_double),
                 ("zeta", C.POINTER(C.c_double)), ("tol", C.c_double), ("inner_tol", C.c_double),
                 ("lin_rtol", C.c_double), ("maxit", C.c_int), ("inner_maxit", C.c_int),
-                ("lin_maxit", C.c_int), ("sigma", C.c_double), ("rho", C.c_double)]
+                ("lin_maxit", C.c_int), ("sigma", C.c_double), ("rho", C.c_double),
+                ("inner_rule", C.c_int), ("inner_backtrack", C.c_int)]
 
 
 class CvarStats(C.Structure):
     _fields_ = [("outer", C.c_int), ("inner_total", C.c_int), ("linear_solves", C.c_int),
                 ("linear_total", C.c_int), ("t", C.c_double), ("F_final", C.c_double),
-                ("time_ms", C.c_double), ("F", C.POINTER(C.c_double)), ("cap", C.c_int), ("len", C.c_int)]
+                ("time_ms", C.c_double), ("F", C.POINTER(C.c_double)), ("cap", C.c_int), ("len", C.c_int),
+                ("inner_capped", C.c_int), ("inner_counts", C.POINTER(C.c_int)), ("inner_cap", C.c_int),
+                ("inner_len", C.c_int)]
 
 
 class SsnStats(C.Structure):
@@ -382,19 +385,26 @@ class Context:
                                                   None if w is None else _ptr(w)))
 
     def cvar_solve(self, x, f, yd, zeta, lam, eps, mass, t0=0.0, tol=1e-6, inner_tol=1e-8, lin_rtol=1e-9,
-                   maxit=50, inner_maxit=50, lin_maxit=80, cap=256):
-        """Algorithm 3 in place on x (device); yd: device [n][n].  Returns (rc, stats dict)."""
+                   maxit=50, inner_maxit=50, lin_maxit=80, cap=256, inner_rule="max", inner_backtrack=False):
+        """Algorithm 3 in place on x (device); yd: device [n][n].  inner_rule "max"
+        (the printed rule) or "min"; inner_backtrack: the non-default line search
+        for h(t).  Returns (rc, stats dict)."""
+        if inner_rule not in ("max", "min"):
+            raise ValueError("inner_rule must be 'max' or 'min'")
         zeta = np.ascontiguousarray(zeta, dtype=np.float64)
         prm = CvarParams(lam, eps, mass, zeta.ctypes.data_as(C.POINTER(C.c_double)), tol, inner_tol, lin_rtol,
-                         maxit, inner_maxit, lin_maxit, 0.0, 0.0)
+                         maxit, inner_maxit, lin_maxit, 0.0, 0.0, 1 if inner_rule == "min" else 0,
+                         1 if inner_backtrack else 0)
         F = (C.c_double * cap)()
-        st = CvarStats(0, 0, 0, 0, 0.0, 0.0, 0.0, F, cap, 0)
+        counts = (C.c_int * cap)()
+        st = CvarStats(0, 0, 0, 0, 0.0, 0.0, 0.0, F, cap, 0, 0, counts, cap, 0)
         t = C.c_double(t0)
         rc = self._check(self.L.smg_cvar_solve(self.ctx, _ptr(x), _ptr(f), _ptr(yd), C.byref(t), C.byref(prm),
                                                C.byref(st)), allow_nc=True)
         return rc, dict(outer=st.outer, inner_total=st.inner_total, linear_solves=st.linear_solves,
                         linear_total=st.linear_total, t=t.value, F_final=st.F_final, time_ms=st.time_ms,
-                        F=list(F[:min(st.len, cap)]))
+                        F=list(F[:min(st.len, cap)]), inner_capped=st.inner_capped,
+                        inner_counts=list(counts[:min(st.inner_len, cap)]))
 
 
 class Batch:

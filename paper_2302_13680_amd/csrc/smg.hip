@@ -2041,7 +2041,8 @@ struct CvarRun {
   const double* f;
   const double* yd;
   std::vector<double> q, w, c;   // per sample: Q_j + t, w_j, c_j
-  int inner_total = 0, lin_solves = 0, lin_total = 0;
+  int inner_total = 0, lin_solves = 0, lin_total = 0, inner_capped = 0;
+  std::vector<int> counts;       // Newton steps of every evaluation of h(t)
 
   double F4(double t) const {
     double s = 0.0;
@@ -2100,31 +2101,47 @@ struct CvarRun {
     lin_total += st.iterations;
     return SMG_OK;
   }
-  // h(t): Newton on F_1(.; t) = 0 from x, each step backtracking on ||F_1||
+  // h(t): Newton on F_1(.; t) = 0 from x.  Default (Section 6, the rules stated
+  // with the risk-averse table): full steps, stop once both the relative and the
+  // absolute residual are at most inner_tol.  Options: either part small (min),
+  // and a backtracking on ||F_1|| per step.
   int inner(double* x, double t) {
     double fn, f0;
     TRY(F1(x, t, &fn));
     f0 = fn;
     const size_t bytes = sizeof(double) * C->len0;
-    for (int k = 0; k < p->inner_maxit; ++k) {
-      if (fn == 0.0 || std::min(fn / f0, fn) <= p->inner_tol) break;
+    const bool use_min = p->inner_rule == SMG_CVAR_INNER_MIN;
+    int k = 0;
+    for (; k < p->inner_maxit; ++k) {
+      const double part = use_min ? std::min(fn / f0, fn) : std::max(fn / f0, fn);
+      if (fn == 0.0 || part <= p->inner_tol) break;
       bool any;
       TRY(set_w(t, &any));
       TRY(solve(C->cdx, C->cr, any));
-      double a = 1.0, ft = 0.0;
-      for (int ls = 0; ls <= 30; ++ls) {
-        HIP_TRY(hipMemcpyAsync(C->cxt, x, bytes, hipMemcpyDeviceToDevice, C->stream));
-        hipLaunchKernelGGL(k_axpy, dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, C->cxt, a,
+      double ft = 0.0;
+      if (!p->inner_backtrack) {
+        hipLaunchKernelGGL(k_axpy, dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, x, 1.0,
                            (const double*)C->cdx);
         LAUNCH_CHECK();
-        TRY(F1(C->cxt, t, &ft));
-        if (ft <= (1.0 - 1e-4 * a) * fn || ls == 30) break;
-        a *= 0.5;
+        TRY(F1(x, t, &ft));
+      } else {
+        double a = 1.0;
+        for (int ls = 0; ls <= 30; ++ls) {
+          HIP_TRY(hipMemcpyAsync(C->cxt, x, bytes, hipMemcpyDeviceToDevice, C->stream));
+          hipLaunchKernelGGL(k_axpy, dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, C->cxt, a,
+                             (const double*)C->cdx);
+          LAUNCH_CHECK();
+          TRY(F1(C->cxt, t, &ft));
+          if (ft <= (1.0 - 1e-4 * a) * fn || ls == 30) break;
+          a *= 0.5;
+        }
+        HIP_TRY(hipMemcpyAsync(x, C->cxt, bytes, hipMemcpyDeviceToDevice, C->stream));
       }
-      HIP_TRY(hipMemcpyAsync(x, C->cxt, bytes, hipMemcpyDeviceToDevice, C->stream));
       fn = ft;
       ++inner_total;
     }
+    if (k >= p->inner_maxit) ++inner_capped;
+    counts.push_back(k);
     return SMG_OK;
   }
   // the root of F_2(x; t) = 0 in t for the current q (bisection)
@@ -2146,7 +2163,8 @@ bool cvar_params_valid(const smg_cvar_params& p, int N) {
   if (!(p.lambda >= 0.0 && p.lambda < 1.0) || !(p.eps > 0.0 && std::isfinite(p.eps)) ||
       !(p.mass > 0.0 && std::isfinite(p.mass)) || !p.zeta || !(p.tol > 0) || !(p.inner_tol > 0) ||
       !(p.lin_rtol > 0) || p.maxit < 0 || p.inner_maxit < 1 || p.lin_maxit < 1 || !(p.sigma >= 0 && p.sigma < 1) ||
-      !(p.rho >= 0 && p.rho < 1))
+      !(p.rho >= 0 && p.rho < 1) || (p.inner_rule != SMG_CVAR_INNER_MAX && p.inner_rule != SMG_CVAR_INNER_MIN) ||
+      (p.inner_backtrack != 0 && p.inner_backtrack != 1))
     return false;
   for (int j = 0; j < N; ++j)
     if (!(p.zeta[j] >= 0.0 && std::isfinite(p.zeta[j]))) return false;
@@ -2245,6 +2263,11 @@ int smg_cvar_solve(smg_ctx* C, double* x, const double* f, const double* yd, dou
     st->t = tk;
     st->F_final = std::fabs(Fk);
     st->time_ms = now_ms() - t0ms;
+    st->inner_capped = R.inner_capped;
+    st->inner_len = 0;
+    if (st->inner_counts)
+      for (int c : R.counts)
+        if (st->inner_len < st->inner_cap) st->inner_counts[st->inner_len++] = c;
   }
   return rc;
 }

@@ -142,3 +142,79 @@ def test_both_linear_solvers_agree():
     assert a["outer"] == b["outer"]
     assert abs(a["t"] - b["t"]) <= 1e-7 * max(1.0, abs(a["t"]))
     assert np.abs(a["u"] - b["u"]).max() <= 1e-6 * np.abs(a["u"]).max()
+
+
+def _quadratic_trace(c, t):
+    """||F_1|| along the inner Newton iteration at t from a point near h(t)."""
+    x0 = np.zeros(c.o.vlen())
+    xh, _ = c.inner(x0, t, "gmres", tol=1e-14, maxit=30)        # close to h(t)
+    hist = []
+    c.inner(xh, t + 5e-2, "gmres", tol=1e-14, maxit=8, hist=hist)
+    return hist
+
+
+def test_inner_newton_converges_quadratically():
+    """Newton's method for h(t) (Algorithm 3, the inner iteration) with the exact
+    Jacobian J_11 = S(c) + w_j z_j z_j^T contracts quadratically near the root:
+    ||F_1(x^{k+1})|| <= K ||F_1(x^k)||^2 until the rounding floor, with
+    several samples inside the smoothing band (w_j != 0).  A Jacobian missing its
+    rank-one terms (a plausible mistake) only contracts linearly and fails."""
+    p = _problem()
+    c = cv.Cvar(p, 0.5, 0.5)
+    z, q = c.z_q(np.zeros(c.o.vlen()))
+    t = float(np.median(q))
+    assert np.count_nonzero(c.w_of(q, t)) >= 2
+
+    def check(hist):
+        steps = [(a, b) for a, b in zip(hist, hist[1:]) if b > 1e-14]   # above the floor (~2e-15)
+        assert len(steps) >= 3, hist
+        for a, b in steps:
+            assert b <= 1e2 * a * a, (a, b, hist)      # quadratic; the exact Jacobian gives K ~ 30
+        assert hist[-1] <= 1e-12, hist
+    check(_quadratic_trace(c, t))
+
+    class NoRankOne(cv.Cvar):
+        def J11(self, v, w, z):
+            return self.o.apply(v)
+    bad = NoRankOne(p, 0.5, 0.5)
+    with pytest.raises(AssertionError):
+        check(_quadratic_trace(bad, t))
+
+
+def test_inner_stopping_rules():
+    """The printed rule (max of relative and absolute residual) stops later than
+    the min variant and never before both parts are below the tolerance; an
+    evaluation whose start sits within 1/tol of the rounding floor runs to the
+    cap under the printed rule."""
+    p = _problem()
+    c = cv.Cvar(p, 0.5, 0.05)
+    x0 = np.zeros(c.o.vlen())
+    for rule in ("max", "min"):
+        hist = []
+        x, k = c.inner(x0, 0.0, "gmres", rule=rule, hist=hist)
+        assert k == len(hist) - 1
+        rel, ab = hist[-1] / hist[0], hist[-1]
+        if rule == "max":
+            assert max(rel, ab) <= 1e-8 and k < 50
+            kmax = k
+        else:
+            assert min(rel, ab) <= 1e-8 and k <= kmax
+    # from h(0) itself: ||F_1(x^0)|| is at the floor, the relative part cannot be met
+    hist = []
+    _, k = c.inner(x, 0.0, "gmres", rule="max", maxit=4, hist=hist)
+    assert k == 4 and max(hist) < 1e-10
+    _, k = c.inner(x, 0.0, "gmres", rule="min", maxit=4)
+    assert k == 0
+
+
+def test_named_variants_reach_the_same_solution():
+    """The min rule with backtracking (a non-default option) and the printed rule
+    find the same (u, t)."""
+    p = _problem()
+    a = cv.Cvar(p, 0.5, 0.05).run("gmres")
+    b = cv.Cvar(p, 0.5, 0.05).run("gmres", inner_rule="min", inner_backtrack=True)
+    assert a["converged"] and b["converged"] and a["outer"] == b["outer"]
+    assert abs(a["t"] - b["t"]) <= 1e-7 * max(1.0, abs(a["t"]))
+    assert np.abs(a["u"] - b["u"]).max() <= 1e-6 * np.abs(a["u"]).max()
+    assert len(a["inner_counts"]) == len(b["inner_counts"])
+    assert a["inner_total"] >= b["inner_total"]
