@@ -1,17 +1,22 @@
 """Benchmark of the collective multigrid solver on one MI355X.
 
-One step = one full solve of the 255x255, N = 64 linear-quadratic OCPUU
-(FP64, six KL modes of amplitude 0.5/m, nu = 1e-4) from a zero initial guess
-to a relative residual of 1e-8 with GMRES(30) preconditioned by one V(2,2)
-cycle, inputs resident in HBM.  Prints one JSON line.
+One step = one full solve of the 511x511, N = 256 linear-quadratic OCPUU
+(FP64, six KL modes of amplitude 1.0/m, nu = 1e-4; 1.34e8 unknowns) from a
+zero initial guess to a relative residual of 1e-8 with GMRES(30) preconditioned
+by one V(2,2) cycle, inputs resident in HBM.
+
+Output: one JSON line per further section (255x255 figures, batched and
+learned forms, the paper's table settings), then the headline record as the
+LAST line:
 
 value  = whole-job DoF-sweeps/s: (2N+1) n^2 unknowns x fine-level smoothing
          sweeps performed in the solve (4 per V-cycle) / solve wall time.
 roofline: the dominant kernel (the collective Gauss-Seidel half-sweep on the
-         finest level) timed with HIP events on the library's stream, its
-         algorithmic bytes per launch against the 8 TB/s HBM peak.
-cpu_baseline: the CPU oracle solving the same instance with the same method
-         on the host's cores (rank 0 only).
+         finest level) timed with HIP events on the library's stream, priced at
+         half of a red+black sweep's algorithmic bytes (8 words per
+         node-sample, 2 per node) against the 8 TB/s HBM peak.
+cpu_baseline: the FP64 CPU oracle on the same instance (V(2,2) cycles from
+         zero, about 10 s of CPU work) on the host's cores.
 """
 from __future__ import annotations
 
@@ -513,7 +518,8 @@ def cvar_run(dev, p, lam, eps, x=None, t0=0.0):
     wall = 1e3 * (time.perf_counter() - t_start)
     ctx.close()
     mean = st["linear_total"] / max(st["linear_solves"], 1)
-    row = {"counts": [st["outer"], st["inner_total"], round(mean, 1)], "converged": rc == binding.SMG_OK,
+    row = {"counts": [st["outer"], st["inner_total"], round(mean, 1)], "inner_capped": st["inner_capped"],
+           "converged": rc == binding.SMG_OK,
            "t": st["t"], "wall_ms": round(wall, 1)}
     print("cvar", p.n, p.N, lam, eps, json.dumps(row), file=sys.stderr, flush=True)
     return x, st, row
@@ -533,6 +539,9 @@ def cvar_tables(dev):
         return cvar_run(dev, p, lam, eps, x=x, t0=t0)
 
     out = {"method": "GMRES(30), one V-cycle of S(c) as preconditioner, rank-one terms in the operator",
+           "inner_rule": "printed: max(||F_1||/||F_1(x^0)||, ||F_1||) <= 1e-8, full Newton steps, at most 50; "
+                         "inner_capped counts evaluations that ended at the cap (start within 1e8 of the "
+                         "rounding floor)",
            "format": "[outer, inner Newton, mean GMRES] (this build) beside [outer, inner, mean V-cycles, mean GMRES]"}
     out["mesh"] = []
     for n, nh, pr in ((15, 161, [5, 62, 23.0, 13.9]), (31, 705, [6, 79, 28.0, 15.5]), (63, 2945, [6, 79, 26.2, 14.8])):
@@ -558,17 +567,158 @@ def cvar_tables(dev):
     return out
 
 
+def sweep_bytes(n: int, N: int, word: int) -> float:
+    """Algorithmic bytes of one red+black sweep: per node-sample y, p, the two
+    right-hand sides and the two face arrays read once and y, p written once (8
+    words), per node u and f_U (2 words)."""
+    return float((8 * N + 2) * n * n * word)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_oracle_sample(prob, budget_s: float = 10.0, max_cycles: int = 3):
+    """The FP64 CPU oracle on the same instance: V(2,2) cycles from zero until
+    budget_s has elapsed (at least one), setup excluded.  Returns the record."""
+    import numpy as np
+    from oracle import oracle as orc
+    o = orc.Oracle(prob)
+    fp = prob.rhs_paper()
+    x = np.zeros(o.vlen())
+    cycles, t = 0, 0.0
+    while cycles < max_cycles and (cycles == 0 or t < budget_s):
+        t0 = time.perf_counter()
+        x = o.vcycle(x, fp, 1)
+        t += time.perf_counter() - t0
+        cycles += 1
+    return {"value": round(prob.dof * 4 * cycles / t, 1), "unit": "DoF-sweeps/s",
+            "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{cycles} V(2,2) cycles of the FP64 oracle from zero on the same instance "
+                      f"({t:.1f} s, setup excluded)",
+            "cpu": cpu_model()}
+
+
+def roofline_halfsweep(ctx, f, n, N, dev, launches, traffic_kind):
+    """Finest-level FP64 half-sweep: average launch duration from HIP events on
+    the library's stream, priced at half of a sweep's algorithmic bytes."""
+    import torch
+    xs = torch.zeros(ctx.vlen(), dtype=torch.float64, device=dev)
+    us = time_halfsweep(ctx, xs, f, ctx.stream, launches)
+    algo = sweep_bytes(n, N, 8) / 2
+    achieved = algo / (us * 1e-6) / 1e9
+    del xs
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(traffic_kind),
+            "kernel": "k_halfsweep<double,64,4> finest level", "avg_launch_us": round(us, 2),
+            "bytes_per_launch": algo}
+
+
+def stream_copy_gbs(dev):
+    """Achievable-bandwidth reference: the library's streaming copy, 1 GiB each way."""
+    import torch
+    from paper_2302_13680_amd import binding
+    ca = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        binding.stream_copy(cb, ca)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        binding.stream_copy(cb, ca)
+    c1.record()
+    c1.synchronize()
+    gbs = 2 * ca.numel() * 8 / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
+    del ca, cb
+    return round(gbs, 1)
+
+
+def medium_section(dev, args):
+    """255x255, N=64 (FP64): GMRES(30) and stationary V(2,2) to 1e-8 and 1e-10,
+    the Jacobi smoother, collocation, local control and the semismooth Newton
+    method on the same grid.  The working set (~0.2 GB) stays in the 256 MB
+    Infinity Cache, so the bandwidth figures here are not HBM figures."""
+    import torch
+    from paper_2302_13680_amd import binding, inputs
+    prob = inputs.medium_fp64()
+    n, N, dof = prob.n, prob.N, prob.dof
+    ctx, f = binding.context_from_problem(prob, device=dev, gmres_restart=30)
+    x = torch.zeros(dof, dtype=torch.float64, device=dev)
+    out = {"section": "medium_fp64", "workload": "255x255, N=64, 6 KL modes a_m=0.5/m, nu=1e-4, FP64",
+           "infinity_cache_resident": True}
+    for name, method, rtol in (("gmres30", binding.SMG_GMRES, 1e-8), ("vcycle", binding.SMG_VCYCLE, 1e-8),
+                               ("gmres30_1e-10", binding.SMG_GMRES, 1e-10)):
+        timed_solve(ctx, x, f, method, rtol)
+        ts = []
+        for _ in range(3):
+            t, st = timed_solve(ctx, x, f, method, rtol)
+            ts.append(t)
+        out[name] = {"time_ms": round(sorted(ts)[1], 3), "iterations": st["iterations"],
+                     "vcycles": st["inner_iterations"] if method == binding.SMG_GMRES else st["iterations"]}
+    us = time_halfsweep(ctx, torch.zeros(dof, dtype=torch.float64, device=dev), f, ctx.stream, 200)
+    out["finest_halfsweep_us"] = round(us, 2)
+    out["finest_halfsweep_rate_GBs_at_sweep_bytes"] = round(sweep_bytes(n, N, 8) / 2 / (us * 1e-6) / 1e9, 1)
+    cj = binding.Context(n, N, ctx.kx, ctx.ky, prob.c, prob.d, prob.e, prob.g, gmres_restart=30, theta=0.5,
+                         flags=binding.SMG_FLAG_JACOBI)
+    jac = {"smoother": "damped collective Jacobi, theta=0.5, V(2,2)"}
+    for name, method in (("gmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
+        timed_solve(cj, x, f, method, 1e-8)
+        t, stj = timed_solve(cj, x, f, method, 1e-8)
+        jac[name + "_time_to_1e-8_ms"] = round(t, 3)
+        jac[name + "_iterations"] = stj["iterations"]
+    cj.close()
+    out["jacobi_smoother"] = jac
+    psc = inputs.collocation_problem(n, 4, 1e-4, M=3, sigma=0.5, decay=True)
+    csc, fsc = binding.context_from_problem(psc, device=dev, gmres_restart=30)
+    xsc = torch.zeros(psc.dof, dtype=torch.float64, device=dev)
+    sc = {"samples": "tensor Gauss-Hermite, M=3 variables, 4 points each (N=64), weights zeta_j"}
+    for name, method in (("gmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
+        timed_solve(csc, xsc, fsc, method, 1e-8)
+        t, stc = timed_solve(csc, xsc, fsc, method, 1e-8)
+        sc[name + "_time_to_1e-8_ms"] = round(t, 3)
+        sc[name + "_iterations"] = stc["iterations"]
+    csc.close()
+    out["stochastic_collocation"] = sc
+    plc = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=1,
+                              control_region=(0.25, 0.75, 0.25, 0.75))
+    clc, flc = binding.context_from_problem(plc, device=dev, gmres_restart=30)
+    xlc = torch.zeros(plc.dof, dtype=torch.float64, device=dev)
+    lc = {"control": "on the nodes of [0.25, 0.75]^2 only (control mask)"}
+    for name, method in (("gmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
+        timed_solve(clc, xlc, flc, method, 1e-8)
+        t, stl = timed_solve(clc, xlc, flc, method, 1e-8)
+        lc[name + "_time_to_1e-8_ms"] = round(t, 3)
+        lc[name + "_iterations"] = stl["iterations"]
+    clc.close()
+    out["local_control"] = lc
+    ctx.close()
+    out["semismooth_newton"] = ssn_section(dev, n, N, args)
+    return out
+
+
+def emit(rec):
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--sweeps", type=int, default=200, help="half-sweep launches timed for the roofline")
+    ap.add_argument("--sweeps", type=int, default=100, help="half-sweep launches timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--quick", action="store_true", help="the headline workload only")
     ap.add_argument("--large-only", action="store_true",
-                    help="run only the 511x511, N=256 workload and print its record (for profiling)")
+                    help="run only the 511x511, N=256 mixed-precision section (for profiling)")
     ap.add_argument("--cvar-only", action="store_true",
                     help="run only the risk-averse solver at 705 nodes, N=2000, lambda 0.95 (for profiling)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune_lanes.json"))
@@ -582,7 +732,6 @@ def main():
                                    "note, not an implemented path", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2302_13680_amd import binding, inputs
@@ -593,30 +742,25 @@ def main():
         p = cvar_problem(31, 2000)
         cvar_run(dev, p, 0.95, 1e-2)                 # warm-up (graph capture)
         _, _, row = cvar_run(dev, p, 0.95, 1e-2)
-        print(json.dumps({"cvar": dict(workload="L-shape 705 nodes, N=2000, lambda 0.95, eps 1e-2", **row)}),
-              flush=True)
+        emit({"cvar": dict(workload="L-shape 705 nodes, N=2000, lambda 0.95, eps 1e-2", **row)})
         return
     if args.large_only:
         large, _, _, _ = large_mixed_section(dev)
-        print(json.dumps({"large_mixed": large}), flush=True)
+        emit({"large_mixed": large})
         return
-    if args.counters == "large":
-        prob = inputs.large_mixed()
+    if args.counters:
+        prob = inputs.large_mixed() if args.counters == "large" else inputs.medium_fp64()
         ctx, f = binding.context_from_problem(prob, device=dev, gmres_restart=0)
         x = torch.zeros(prob.dof, dtype=torch.float64, device=dev)
         halfsweep_counter_run(ctx, x, f, prob.n, prob.N)
         return
-    prob = inputs.medium_fp64()
-    n, N = prob.n, prob.N
-    dof = prob.dof
-    ctx, f = binding.context_from_problem(prob, device=dev, gmres_restart=30)
-    x = torch.zeros(dof, dtype=torch.float64, device=dev)
-    stream = ctx.stream
-    levels = list(ctx.levels_n)
 
-    if args.counters:
-        halfsweep_counter_run(ctx, x, f, n, N)
-        return
+    # ---------------- headline: 511x511, N=256, FP64 GMRES(30) + V(2,2) to 1e-8
+    prob = inputs.large_mixed()
+    n, N, dof = prob.n, prob.N, prob.dof
+    ctx, f = binding.context_from_problem(prob, device=dev, gmres_restart=30)
+    levels = list(ctx.levels_n)
+    x = torch.zeros(dof, dtype=torch.float64, device=dev)
 
     def solve(method, rtol):
         x.zero_()
@@ -625,7 +769,6 @@ def main():
             raise RuntimeError(f"solve did not converge: {st}")
         return st
 
-    # ---------------- headline: GMRES(30) + V(2,2) to 1e-8, K timed steps
     for _ in range(args.warmup):
         solve(binding.SMG_GMRES, args.rtol)
     torch.cuda.synchronize()
@@ -637,167 +780,89 @@ def main():
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
     ms_per_step = 1e3 * t_total / args.steps
+    value = dof * 4 * cycles / t_total
     gmres_its = st["iterations"]
-    sweeps_per_cycle = 4
-    value = dof * sweeps_per_cycle * cycles / t_total
 
-    # ---------------- plain FP64 stationary V-cycle (the comparison baseline)
-    solve(binding.SMG_VCYCLE, args.rtol)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stv = solve(binding.SMG_VCYCLE, args.rtol)
-    torch.cuda.synchronize()
-    t_vcycle_ms = 1e3 * (time.perf_counter() - t0)
-    # tolerance of the workload definition
-    t0 = time.perf_counter()
-    st10 = solve(binding.SMG_GMRES, 1e-10)
-    torch.cuda.synchronize()
-    t_gmres10_ms = 1e3 * (time.perf_counter() - t0)
+    # the plain FP64 stationary V-cycle on the same GPU (the comparison baseline)
+    tv = []
+    for i in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stv = solve(binding.SMG_VCYCLE, args.rtol)
+        torch.cuda.synchronize()
+        if i:
+            tv.append(1e3 * (time.perf_counter() - t0))
+    t_vcycle_ms = sorted(tv)[1]
+    roofline = roofline_halfsweep(ctx, f, n, N, dev, args.sweeps, "halfsweep_f64_large")
+    ctx.close()
+    del ctx, x
+    torch.cuda.empty_cache()
+    roofline["stream_copy_GBs"] = stream_copy_gbs(dev)
 
-    # ---------------- the paper's own smoother: damped collective Jacobi, theta 1/2
-    cj = binding.Context(n, N, ctx.kx, ctx.ky, prob.c, prob.d, prob.e, prob.g, gmres_restart=30, theta=0.5,
-                         flags=binding.SMG_FLAG_JACOBI)
-    jac = {"smoother": "damped collective Jacobi, theta=0.5, V(2,2)"}
-    for name, method in (("gmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
-        timed_solve(cj, x, f, method, args.rtol)                  # warm-up (graph capture)
-        t, stj = timed_solve(cj, x, f, method, args.rtol)
-        jac[name + "_time_to_1e-8_ms"] = round(t, 3)
-        jac[name + "_iterations"] = stj["iterations"]
-    cj.close()
-    del cj
+    # FP32 smoother, residual and transfers inside FP64 refinement (FGMRES(30) and stationary)
+    c32 = binding.Context(n, N, torch.from_numpy(prob.faces_node()[0]).to(dev),
+                          torch.from_numpy(prob.faces_node()[1]).to(dev), prob.c, prob.d, prob.e, prob.g,
+                          gmres_restart=30, precision=binding.SMG_F32)
+    x = torch.zeros(dof, dtype=torch.float64, device=dev)
+    mixed = {}
+    for name, method in (("fgmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
+        timed_solve(c32, x, f, method, args.rtol)
+        ts = []
+        for _ in range(3):
+            t, st32 = timed_solve(c32, x, f, method, args.rtol)
+            ts.append(t)
+        mixed[name] = (round(sorted(ts)[1], 2), st32["iterations"], st32["inner_iterations"])
+    c32.close()
+    del c32, x, f
+    torch.cuda.empty_cache()
 
-    # ---------------- stochastic collocation: 4^3 tensor Gauss-Hermite nodes (N = 64)
-    psc = inputs.collocation_problem(n, 4, 1e-4, M=3, sigma=0.5, decay=True)
-    csc, fsc = binding.context_from_problem(psc, device=dev, gmres_restart=30)
-    xsc = torch.zeros(psc.dof, dtype=torch.float64, device=dev)
-    sc = {"samples": "tensor Gauss-Hermite, M=3 variables, 4 points each (N=64), weights zeta_j"}
-    for name, method in (("gmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
-        timed_solve(csc, xsc, fsc, method, args.rtol)             # warm-up (graph capture)
-        t, stc = timed_solve(csc, xsc, fsc, method, args.rtol)
-        sc[name + "_time_to_1e-8_ms"] = round(t, 3)
-        sc[name + "_iterations"] = stc["iterations"]
-    csc.close()
-    del csc, fsc, xsc
-
-    # ---------------- local control on [0.25, 0.75]^2 (the paper's square-domain experiment)
-    plc = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=1, control_region=(0.25, 0.75, 0.25, 0.75))
-    clc, flc = binding.context_from_problem(plc, device=dev, gmres_restart=30)
-    xlc = torch.zeros(plc.dof, dtype=torch.float64, device=dev)
-    lc = {"control": "on the nodes of [0.25, 0.75]^2 only (control mask)"}
-    for name, method in (("gmres30", binding.SMG_GMRES), ("vcycle", binding.SMG_VCYCLE)):
-        timed_solve(clc, xlc, flc, method, args.rtol)             # warm-up (graph capture)
-        t, stl = timed_solve(clc, xlc, flc, method, args.rtol)
-        lc[name + "_time_to_1e-8_ms"] = round(t, 3)
-        lc[name + "_iterations"] = stl["iterations"]
-    clc.close()
-    del clc, flc, xlc
-
-    # ---------------- semismooth Newton for the L1-penalized, box-constrained control
-    # (Section 5, Algorithm 2): nu 1e-4, beta 1e-2, -50 <= u <= 50, phi <= 1e-9,
-    # every Newton system to 1e-11; the paper's target, no source
-    ssn = ssn_section(dev, n, N, args)
-    paper = None
-    if not args.quick:   # the paper's table settings: many small solves
-        paper = paper_tables(dev)
-        paper["l1_tables"] = ssn_tables(dev)
-        paper["cvar_tables"] = cvar_tables(dev)
-
-    # ---------------- roofline of the dominant kernel: finest-level half-sweep
-    xs = torch.zeros(dof, dtype=torch.float64, device=dev)
-    for _ in range(10):
-        ctx.smooth(0, 0, xs, f)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for i in range(args.sweeps):
-        ctx.smooth(0, i & 1, xs, f)
-    ev1.record(stream)
-    ev1.synchronize()
-    t_launch_us = 1e3 * ev0.elapsed_time(ev1) / args.sweeps
-    bytes_launch = halfsweep_bytes(n, N, 8)
-    achieved = bytes_launch / (t_launch_us * 1e-6) / 1e9
-    # achievable-bandwidth reference: the library's plain streaming copy, 2 GiB moved per launch
-    ca = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-    cb = torch.empty_like(ca)
-    for _ in range(3):
-        binding.stream_copy(cb, ca)
-    c0 = torch.cuda.Event(enable_timing=True)
-    c1 = torch.cuda.Event(enable_timing=True)
-    c0.record()
-    for _ in range(10):
-        binding.stream_copy(cb, ca)
-    c1.record()
-    c1.synchronize()
-    copy_gbs = 2 * ca.numel() * 8 / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
-    del ca, cb
-    traffic = load_traffic("halfsweep_f64_medium")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_halfsweep<double,64,1> (finest level)", "avg_launch_us": round(t_launch_us, 2),
-                "algorithmic_bytes_per_launch": bytes_launch,
-                "stream_copy_GBs": round(copy_gbs, 1)}
-    # the same launch priced at half of a whole red+black sweep's 8 words per
-    # node-sample (faces, y, p and both right-hand sides read once per sweep), the
-    # bound of a sweep fused across both colours, which two launches cannot reach
-    sweep_half = 4.0 * N * n * n * 8 + n * n * 8
-    roofline["at_half_of_8_words_per_sweep"] = {
-        "bytes_per_launch": sweep_half,
-        "frac": round(sweep_half / (t_launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
-
-    extra = {}
+    # ---------------- further sections, one JSON line each
+    failed = []
     if not args.quick:
-        del ctx, x, xs
-        torch.cuda.empty_cache()
-        large, c32, fl, xl = large_mixed_section(dev)
-        extra["large_mixed"] = large
-        del c32, fl, xl
-        torch.cuda.empty_cache()
-        extra["large_semismooth_newton"] = large_ssn_section(dev)
-        torch.cuda.empty_cache()
-        extra["batch"] = batch_section(dev, args.tune_cache)
-        torch.cuda.empty_cache()
-        extra["learned"] = learned_section(dev)
-        torch.cuda.empty_cache()
+        def run_section(name, fn):
+            try:
+                rec = fn()
+                rec.setdefault("section", name)
+                emit(rec)
+            except Exception as exc:   # a failing section is reported, the headline still printed
+                failed.append(name)
+                emit({"section": name, "error": repr(exc)})
+            torch.cuda.empty_cache()
 
-    # ---------------- CPU oracle on the host cores (same instance, same method)
+        def large():
+            rec, c32b, fl, xl = large_mixed_section(dev)
+            del c32b, fl, xl
+            return rec
+        run_section("large_mixed", large)
+        run_section("medium_fp64", lambda: medium_section(dev, args))
+        run_section("large_semismooth_newton", lambda: large_ssn_section(dev))
+        run_section("batch", lambda: batch_section(dev, args.tune_cache))
+        run_section("learned", lambda: learned_section(dev))
+
+        def paper():
+            rec = paper_tables(dev)
+            rec["l1_tables"] = ssn_tables(dev)
+            rec["cvar_tables"] = cvar_tables(dev)
+            return rec
+        run_section("paper_settings", paper)
+
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import oracle as orc
-        o = orc.Oracle(prob)
-        fp = prob.rhs_paper()
-        t0 = time.perf_counter()
-        _, its_o, _ = o.gmres(fp, m=30, tol=args.rtol, maxit=200)
-        t_cpu = time.perf_counter() - t0
-        cpu = {"value": round(dof * sweeps_per_cycle * its_o / t_cpu, 1), "unit": "DoF-sweeps/s",
-               "cores": orc.num_threads(), "kind": "oracle",
-               "sample": f"one full GMRES(30)+V(2,2) solve to {args.rtol:g} of the same instance "
-                         f"({its_o} iterations, {t_cpu:.2f} s)",
-               "time_to_tol_s": round(t_cpu, 3)}
+        cpu = cpu_oracle_sample(prob)
 
-    out = {
+    emit({
         "metric": METRIC, "value": round(value, 1), "unit": "DoF-sweeps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "LQ-OCPUU 255x255 interior grid, N=64 samples, 6 KL modes a_m=0.5/m, "
-                               "nu=1e-4, FP64, GMRES(30)+V(2,2) to rel. residual 1e-8",
-                   "n": n, "N": N, "dof": dof, "levels": levels},
-        "time_to_1e-8_ms": round(ms_per_step, 3),
-        "gmres_iterations": gmres_its,
-        "fp64_vcycle_time_to_1e-8_ms": round(t_vcycle_ms, 3),
-        "fp64_vcycle_cycles": stv["iterations"],
-        "gmres_time_to_1e-10_ms": round(t_gmres10_ms, 3),
-        "gmres_iterations_1e-10": st10["iterations"],
-        "jacobi_smoother": jac,
-        "stochastic_collocation": sc,
-        "local_control": lc,
-        "semismooth_newton": ssn,
-        "paper_settings": paper,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    out.update(extra)
-    print(json.dumps(out), flush=True)
+        "config": {"workload": "LQ-OCPUU 511x511 grid, N=256 samples, 6 KL modes a_m=1.0/m, nu=1e-4; "
+                               "FP64 GMRES(30) + V(2,2) red-black collective GS to rel. residual 1e-8",
+                   "dof": dof, "levels": levels},
+        "time_to_1e-8_ms": round(ms_per_step, 2), "gmres_iterations": gmres_its,
+        "fp64_vcycle_time_to_1e-8_ms": round(t_vcycle_ms, 2), "fp64_vcycle_cycles": stv["iterations"],
+        "fp32_refined_fgmres30_ms": mixed["fgmres30"][0], "fp32_refined_vcycle_ms": mixed["vcycle"][0],
+        "roofline": roofline, "cpu_baseline": cpu, "sections_failed": failed,
+    })
 
 
 if __name__ == "__main__":
