@@ -216,8 +216,11 @@ __global__ __launch_bounds__(kBlock) void k_coarse_schur_chunks(int m, int N, co
   }
 }
 
-// Transposed Schur complement (g I + sum_j terms[j])^T (fixed order over j) inverted in
-// place; the result is the transposed storage of its inverse.  One block.
+// Transposed Schur complement (g I + sum of the terms)^T inverted in place; the
+// result is the transposed storage of its inverse.  One block.  `terms` holds the
+// N = ceil(samples / kSchurChunk) chunk partials of k_coarse_schur_chunks, summed
+// here in order: the sum over samples is two-stage, in sample order within each
+// chunk of 64, then over the chunks in order.
 __global__ __launch_bounds__(kBlock) void k_coarse_schur_invert(int m, int N, const double* __restrict__ terms,
                                                                 double g, double* __restrict__ Sinv) {
   __shared__ double A[kMaxCoarse * kMaxCoarse];
@@ -242,6 +245,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_schur_invert(int m, int N, co
 // Block elimination of eq. (2) on the coarsest grid, one block per sample j:
 //   phase 1: ds_j = D_j A_j^{-1} (F_Y,j - c_j A_j^{-1} F_P,j)
 //   phase 2: u = Sinv (F_U - sum_j ds_j);  y_j = A_j^{-1}(F_P,j - E_j u);
+//            (up to kCoarseUMin samples every block forms u itself from the N ds_j in
+//            sample order; above that k_coarse_u forms it once, summing the ds_j
+//            in sixteen interleaved slices, and the blocks read it as `upre`)
 // with D_j = d_j diag(md), E_j = e_j diag(me) (mk: node factor pairs (md, me));
 //            p_j = A_j^{-1}(F_Y,j - c_j y_j)
 // Vectors in the level layout (type TV), arithmetic in FP64.
@@ -287,6 +293,8 @@ __device__ __forceinline__ void coarse_phase1_sample(int j, int m, int N, const 
 }
 
 // Phase 2 for sample j (one block of >= m threads); block j = 0 also writes u.
+// Without upre the block computes u from the N ds_j; with upre (N > kCoarseUMin)
+// it takes the u that k_coarse_u computed once.
 template <typename TV>
 __device__ __forceinline__ void coarse_phase2_sample(int j, int m, int N, const double* __restrict__ Ainv,
                                                      const double* __restrict__ Sinv,

@@ -129,3 +129,28 @@ def test_batch_iteration_limit(B):
     rc, stats, _ = bt.solve(rtol=1e-12, maxit=2)
     assert rc == B.SMG_NOT_CONVERGED
     assert all(st["iterations"] == 2 for st in stats)
+
+
+def test_batch_with_the_largest_instances(B, O):
+    """The extremes of the uneven workload in one batch: 255x255 with N = 128 and
+    with N = 16, 63x63 with N = 128 and N = 16, nu from 1e-6 to 1e-2, in the
+    FP32-refined form; every instance meets 1e-8 by the oracle's FP64 residual
+    with the oracle's refinement count within one."""
+    specs = [(255, 128, 1e-6, 201), (63, 16, 1e-2, 202), (255, 16, 1e-4, 203), (63, 128, 1e-3, 204)]
+    probs = [inputs.make_problem(n, N, nu, M=6, sigma=0.5, decay=True, seed=s) for (n, N, nu, s) in specs]
+    ctxs, xs, fs = [], [], []
+    for p in probs:
+        c, f = B.context_from_problem(p, gmres_restart=0, precision=1)
+        ctxs.append(c); fs.append(f)
+        xs.append(torch.zeros(p.dof, dtype=torch.float64, device="cuda"))
+    bt = B.Batch(ctxs, xs, fs)
+    rc, stats, _ = bt.solve(rtol=1e-8, maxit=60)
+    assert rc == B.SMG_OK
+    torch.cuda.synchronize()
+    for p, x, st in zip(probs, xs, stats):
+        o = O.Oracle(p)
+        fp = p.rhs_paper()
+        xg = node_to_paper(x.cpu().numpy(), p.n, p.N)
+        assert np.linalg.norm(o.residual(xg, fp)) <= 1e-8 * np.linalg.norm(fp), (p.n, p.N)
+        _, its, _, _ = o.solve_ir(fp, tol=1e-8, m=0)
+        assert abs(st["iterations"] - its) <= 1, (p.n, p.N, st["iterations"], its)

@@ -5,6 +5,7 @@ import pytest
 
 from paper_2302_13680_amd import inputs
 from paper_2302_13680_amd.inputs import node_to_paper
+from parity_util import assert_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -44,7 +45,7 @@ def test_collocation_vcycle_iterates(B, O, n, q):
     for k in range(3):
         x_o = o.vcycle(x_o, p.rhs_paper(), 1)
         ctx.vcycle(xd, f, 1)
-        assert rel(node_to_paper(host(xd), n, p.N), x_o) <= 1e-12, k
+        assert_blocks(node_to_paper(host(xd), n, p.N), x_o, n, p.N, 1e-12, k)
 
 
 @pytest.mark.parametrize("n,q", [(63, 2), (63, 4)])

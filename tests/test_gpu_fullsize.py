@@ -1,16 +1,19 @@
 """The 511x511, N=256 workload at full size, in the launch configuration the
-benchmark times: FP64 V-cycle iterates against the oracle on the whole vector,
-and the FP32-refined solution checked by the oracle's own FP64 residual.
+solver runs: FP64 V-cycle iterates against the oracle in every block (Y, U, P),
+the FP32-refined solution checked by the oracle's own FP64 residual, and its
+per-field error against the oracle's FP64 solution.
 
-The oracle takes ~5 s per V-cycle at this size on the GPU host's cores.
-Tolerances as in test_gpu_parity: iterates 1e-12 relative; the refined solve
-meets ||f - S x|| <= 1e-10 ||f|| with S applied by the oracle.
+The oracle takes ~2-5 s per V-cycle at this size on the GPU host's cores.
+Tolerances: iterates 1e-12 relative per block; the refined solve meets
+||f - S x|| <= 1e-10 ||f|| with S applied by the oracle, and every block lies
+within 1e-7 (relative) of the oracle's solution.
 """
 import numpy as np
 import pytest
 
 from paper_2302_13680_amd import inputs
 from paper_2302_13680_amd.inputs import node_to_paper
+from parity_util import assert_blocks
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +50,7 @@ def test_large_vcycle_iterates_against_oracle(B, problem):
         x_o = o.vcycle(x_o, fp, 1)
         ctx.vcycle(xd, f, 1)
         torch.cuda.synchronize()
-        assert _rel(node_to_paper(xd.cpu().numpy(), p.n, p.N), x_o) <= 1e-12
+        assert_blocks(node_to_paper(xd.cpu().numpy(), p.n, p.N), x_o, p.n, p.N, 1e-12)
 
 
 def test_large_fp32_refinement_meets_oracle_residual(B, problem):
@@ -66,3 +69,10 @@ def test_large_fp32_refinement_meets_oracle_residual(B, problem):
     n2, N = p.n * p.n, p.N
     for blk in (r[:N * n2], r[N * n2:(N + 1) * n2], r[(N + 1) * n2:]):
         assert np.linalg.norm(blk) <= 1e-10 * nf
+    # per-field error against the oracle's own FP64 solution (stationary V(2,2)
+    # from zero to 1e-11): the FP32 cycles leave an error at the level that the
+    # 1e-10 residual allows, in every block
+    x_ref, its, _ = o.solve_vcycle(fp, tol=1e-11, maxit=60)
+    assert its > 0
+    e = assert_blocks(xg, x_ref, p.n, p.N, 1e-7)
+    print("511x511 FP32-refined per-field error vs the FP64 oracle:", e, flush=True)

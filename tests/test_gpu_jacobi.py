@@ -9,6 +9,7 @@ import pytest
 
 from paper_2302_13680_amd import inputs
 from paper_2302_13680_amd.inputs import node_to_paper, paper_to_node
+from parity_util import assert_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -82,7 +83,7 @@ def test_jacobi_vcycle_iterates(B, O, n, N, pre):
     for k in range(4):
         x_o = o.vcycle(x_o, p.rhs_paper(), 1)
         ctx.vcycle(xd, f, 1)
-        assert rel(node_to_paper(host(xd), n, N), x_o) <= 1e-12, k
+        assert_blocks(node_to_paper(host(xd), n, N), x_o, n, N, 1e-12, k)
 
 
 @pytest.mark.parametrize("n,N", [(63, 16), (127, 8)])
@@ -133,7 +134,7 @@ def test_jacobi_fp32_cycle_against_fp32_oracle(B, O, n, N):
     x_o = o.vcycle32(np.zeros(o.vlen()), p.rhs_paper(), 2)
     xd = torch.zeros(o.vlen(), dtype=torch.float64, device="cuda")
     ctx.vcycle(xd, f, 2)
-    assert rel(node_to_paper(host(xd), n, N), x_o) <= 2e-5
+    assert_blocks(node_to_paper(host(xd), n, N), x_o, n, N, 2e-5)
 
 
 def test_batch_rejects_jacobi_contexts(B):

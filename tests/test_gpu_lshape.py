@@ -8,6 +8,7 @@ import pytest
 
 from paper_2302_13680_amd import inputs
 from paper_2302_13680_amd.inputs import node_to_paper, paper_to_node
+from parity_util import assert_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -102,7 +103,7 @@ def test_lshape_vcycle_iterates(B, O, smoother, precision):
     for k in range(3):
         x_o = cyc(x_o, p.rhs_paper(), 1)
         ctx.vcycle(xd, f, 1)
-        assert rel(node_to_paper(host(xd), n, N), x_o) <= (1e-12 if precision == 0 else 2e-5), k
+        assert_blocks(node_to_paper(host(xd), n, N), x_o, n, N, 1e-12 if precision == 0 else 2e-5, k)
 
 
 @pytest.mark.parametrize("method", [0, 1])

@@ -10,6 +10,7 @@ import pytest
 
 from paper_2302_13680_amd import inputs
 from paper_2302_13680_amd.inputs import node_to_paper, paper_to_node
+from parity_util import assert_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -131,7 +132,7 @@ def test_node_factor_cycles_and_captured_graphs(B, O, precision):
         for k in range(3):
             x_o = cyc(x_o, fp, 1)
             ctx.vcycle(xd, f, 1)
-            assert rel(node_to_paper(host(xd), n, N), x_o) <= tol, (stage, k)
+            assert_blocks(node_to_paper(host(xd), n, N), x_o, n, N, tol, (stage, k))
 
 
 def test_set_node_factors_rejects_values_outside_unit_interval(B):
