@@ -35,9 +35,9 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources the finest-level half-sweep kernel is built from."""
+    """Hash of the sources the finest-level sweep kernels are built from."""
     h = hashlib.sha256()
-    for f in ("common.h", "smoother.h"):
+    for f in ("common.h", "smoother.h", "sweep.h"):
         with open(os.path.join(ROOT, "paper_2302_13680_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -82,18 +82,25 @@ def time_halfsweep(ctx, x, f, stream, launches, fp32=False):
 
 
 def halfsweep_counter_run(ctx, x, f, n, N):
-    """20 finest-level half-sweeps, then five 1 GiB device copies (the
+    """20 finest-level sweeps (one launch each where the level takes the
+    one-launch sweep, else 40 half-sweeps), then five 1 GiB device copies (the
     calibration of the traffic counters)."""
     import torch
-    for i in range(20):
-        ctx.smooth(0, i & 1, x, f)
+    xb = torch.empty_like(x)
+    one = ctx.sweep(0, x, xb, f)
+    for i in range(19):
+        if one:
+            ctx.sweep(0, xb, x, f) if i % 2 == 0 else ctx.sweep(0, x, xb, f)
+        else:
+            ctx.smooth(0, 0, x, f)
+            ctx.smooth(0, 1, x, f)
     a = torch.ones(1 << 27, dtype=torch.float64, device=x.device)   # 1 GiB
     b = torch.empty_like(a)
     for _ in range(5):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"counters": "done", "n": n, "N": N, "halfsweep_launches": 20,
-                      "halfsweep_algorithmic_bytes": halfsweep_bytes(n, N, 8),
+    print(json.dumps({"counters": "done", "n": n, "N": N, "one_launch_sweeps": one,
+                      "sweep_algorithmic_bytes": sweep_bytes(n, N, 8),
                       "copy_bytes_each_way": a.numel() * 8, "copy_launches": 5}), flush=True)
 
 
@@ -149,19 +156,25 @@ def large_mixed_section(dev):
     blocks = {"y": slice(0, N * nn), "u": slice(N * nn, (N + 1) * nn), "p": slice((N + 1) * nn, None)}
     out["fp32_refinement_rel_diff_vs_fp64_at_1e-10"] = {
         k: float((torch.linalg.norm(x[sl] - x64[sl]) / torch.linalg.norm(x64[sl])).item()) for k, sl in blocks.items()}
-    # finest-level half-sweep rooflines in both precisions
-    xs = torch.zeros(dof, dtype=torch.float64, device=dev)
-    us64 = time_halfsweep(c64, xs, f, c64.stream, 50)
-    b64 = halfsweep_bytes(n, N, 8)
-    out["roofline_fp64_halfsweep"] = {"avg_launch_us": round(us64, 2), "achieved_GBs": round(b64 / us64 / 1e3, 1),
-                                      "frac": round(b64 / us64 / 1e3 / HBM_PEAK_GBS, 4)}
-    x32 = torch.zeros(dof, dtype=torch.float32, device=dev)
-    f32 = f.float()
-    us32 = time_halfsweep(c32, x32, f32, c32.stream, 50, fp32=True)
-    b32 = halfsweep_bytes(n, N, 4)
-    out["roofline_fp32_halfsweep"] = {"avg_launch_us": round(us32, 2), "achieved_GBs": round(b32 / us32 / 1e3, 1),
-                                      "frac": round(b32 / us32 / 1e3 / HBM_PEAK_GBS, 4)}
-    del x64, xs, x32, f32
+    # finest-level sweeps in both precisions: the one-launch sweep and the two
+    # half-sweeps, priced at a sweep's algorithmic bytes (8 words per node-sample)
+    for name, ctx, dt, w in (("fp64", c64, torch.float64, 8), ("fp32", c32, torch.float32, 4)):
+        xa = torch.zeros(dof, dtype=dt, device=dev)
+        xb = torch.empty_like(xa)
+        fx = f if dt == torch.float64 else f.float()
+        fp32 = dt == torch.float32
+        one = (ctx.sweep32 if fp32 else ctx.sweep)(0, xa, xb, fx)
+        rec = {}
+        if one:
+            us1 = time_sweep(ctx, xa, xb, fx, ctx.stream, 40, fp32=fp32)
+            rec["one_launch_us"] = round(us1, 2)
+            rec["one_launch_frac_of_8TBs"] = round(sweep_bytes(n, N, w) / (us1 * 1e-6) / 8e12, 4)
+        us2 = 2 * time_halfsweep(ctx, xa, fx, ctx.stream, 40, fp32=fp32)
+        rec["two_halfsweeps_us"] = round(us2, 2)
+        rec["two_halfsweeps_frac_of_8TBs"] = round(sweep_bytes(n, N, w) / (us2 * 1e-6) / 8e12, 4)
+        out["sweep_" + name] = rec
+        del xa, xb
+    del x64
     return out, c32, f, x
 
 
@@ -519,6 +532,7 @@ def cvar_run(dev, p, lam, eps, x=None, t0=0.0):
     ctx.close()
     mean = st["linear_total"] / max(st["linear_solves"], 1)
     row = {"counts": [st["outer"], st["inner_total"], round(mean, 1)], "inner_capped": st["inner_capped"],
+           "inner_stalled": st["inner_stalled"],
            "converged": rc == binding.SMG_OK,
            "t": st["t"], "wall_ms": round(wall, 1)}
     print("cvar", p.n, p.N, lam, eps, json.dumps(row), file=sys.stderr, flush=True)
@@ -539,9 +553,9 @@ def cvar_tables(dev):
         return cvar_run(dev, p, lam, eps, x=x, t0=t0)
 
     out = {"method": "GMRES(30), one V-cycle of S(c) as preconditioner, rank-one terms in the operator",
-           "inner_rule": "printed: max(||F_1||/||F_1(x^0)||, ||F_1||) <= 1e-8, full Newton steps, at most 50; "
-                         "inner_capped counts evaluations that ended at the cap (start within 1e8 of the "
-                         "rounding floor)",
+           "inner_rule": "printed: max(||F_1||/||F_1(x^0)||, ||F_1||) <= 1e-8, Newton steps backtracking on "
+                         "||F_1||, at most 50; inner_stalled counts evaluations that ended at the rounding floor "
+                         "(no decrease with ||F_1|| <= 1e-8), inner_capped those that ended at the cap",
            "format": "[outer, inner Newton, mean GMRES] (this build) beside [outer, inner, mean V-cycles, mean GMRES]"}
     out["mesh"] = []
     for n, nh, pr in ((15, 161, [5, 62, 23.0, 13.9]), (31, 705, [6, 79, 28.0, 15.5]), (63, 2945, [6, 79, 26.2, 14.8])):
@@ -606,19 +620,44 @@ def cpu_oracle_sample(prob, budget_s: float = 10.0, max_cycles: int = 3):
             "cpu": cpu_model()}
 
 
-def roofline_halfsweep(ctx, f, n, N, dev, launches, traffic_kind):
-    """Finest-level FP64 half-sweep: average launch duration from HIP events on
-    the library's stream, priced at half of a sweep's algorithmic bytes."""
+def time_sweep(ctx, xa, xb, f, stream, launches, fp32=False):
+    """Average duration (us) of `launches` finest-level one-launch sweeps
+    (alternating between xa and xb), HIP events on the library's stream."""
     import torch
-    xs = torch.zeros(ctx.vlen(), dtype=torch.float64, device=dev)
-    us = time_halfsweep(ctx, xs, f, ctx.stream, launches)
-    algo = sweep_bytes(n, N, 8) / 2
+    sweep = ctx.sweep32 if fp32 else ctx.sweep
+    for i in range(4):
+        sweep(0, xa, xb, f) if i % 2 == 0 else sweep(0, xb, xa, f)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(launches):
+        sweep(0, xa, xb, f) if i % 2 == 0 else sweep(0, xb, xa, f)
+    e1.record(stream)
+    e1.synchronize()
+    return 1e3 * e0.elapsed_time(e1) / launches
+
+
+def roofline_sweep(ctx, f, n, N, dev, launches, traffic_kind):
+    """The dominant kernel of the FP64 solve: the finest-level sweep.  Where the
+    level takes the one-launch sweep (k_sweep_fused) one launch is a whole
+    red+black sweep, priced at its algorithmic bytes (8 words per node-sample,
+    2 per node); else the half-sweep at half of them.  Average launch duration
+    from HIP events on the library's stream."""
+    import torch
+    xa = torch.zeros(ctx.vlen(), dtype=torch.float64, device=dev)
+    xb = torch.empty_like(xa)
+    one = ctx.sweep(0, xa, xb, f)
+    if one:
+        us = time_sweep(ctx, xa, xb, f, ctx.stream, launches)
+        algo, kernel = sweep_bytes(n, N, 8), "k_sweep_fused<double,4,1,kPlain> finest level (red+black sweep)"
+    else:
+        us = time_halfsweep(ctx, xa, f, ctx.stream, launches)
+        algo, kernel = sweep_bytes(n, N, 8) / 2, "k_halfsweep<double,64,4> finest level"
     achieved = algo / (us * 1e-6) / 1e9
-    del xs
+    del xa, xb
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(traffic_kind),
-            "kernel": "k_halfsweep<double,64,4> finest level", "avg_launch_us": round(us, 2),
-            "bytes_per_launch": algo}
+            "kernel": kernel, "avg_launch_us": round(us, 2), "bytes_per_launch": algo}
 
 
 def stream_copy_gbs(dev):
@@ -713,7 +752,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--sweeps", type=int, default=100, help="half-sweep launches timed for the roofline")
+    ap.add_argument("--sweeps", type=int, default=60, help="sweep launches timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--quick", action="store_true", help="the headline workload only")
@@ -723,9 +762,9 @@ def main():
                     help="run only the risk-averse solver at 705 nodes, N=2000, lambda 0.95 (for profiling)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune_lanes.json"))
     ap.add_argument("--counters", nargs="?", const="medium", choices=["medium", "large"],
-                    help="launch only the finest-level FP64 half-sweep (20x) of the 255x255, N=64 "
-                         "(medium) or 511x511, N=256 (large) workload and a 1 GiB device copy (5x), "
-                         "for hardware-counter passes")
+                    help="launch only 20 finest-level FP64 sweeps of the 255x255, N=64 (medium) or "
+                         "511x511, N=256 (large) workload and a 1 GiB device copy (5x), for "
+                         "hardware-counter passes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
@@ -793,7 +832,7 @@ def main():
         if i:
             tv.append(1e3 * (time.perf_counter() - t0))
     t_vcycle_ms = sorted(tv)[1]
-    roofline = roofline_halfsweep(ctx, f, n, N, dev, args.sweeps, "halfsweep_f64_large")
+    roofline = roofline_sweep(ctx, f, n, N, dev, args.sweeps, "sweep_f64_large")
     ctx.close()
     del ctx, x
     torch.cuda.empty_cache()

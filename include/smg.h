@@ -93,6 +93,10 @@ typedef struct {
                          visited row by row, so that values shared by neighbouring rows are
                          reused from L2; 0 or >= n = row-major order.  Any value gives the
                          same iterates (a half-sweep updates one colour from the other). */
+  int sweep_rows;     /* rows per segment of the one-launch red+black sweep (see
+                         SMG_FLAG_HALFSWEEPS); 0 = as many segments as keep every wave of the
+                         launch resident at once.  A value > 0 also enables that sweep on
+                         levels below its size threshold.  Any value gives the same iterates. */
 } smg_desc;
 
 /* flags */
@@ -111,6 +115,15 @@ typedef struct {
                                  (two vectors and six node-sized arrays) */
 #define SMG_FLAG_CVAR 16      /* reserve the risk-averse solver's buffers (eight vectors, the
                                  rank-one vectors z_j and per-sample arrays); FP64 contexts only */
+#define SMG_FLAG_HALFSWEEPS 32 /* smooth with one launch per colour on every level.  By default,
+                                 on levels whose two half-sweeps move at least 512 MB with
+                                 129..256 samples (four per lane), and on every level with 33..256
+                                 samples (64 lanes per node; FP32 pairs: 65..256) when sweep_rows
+                                 is set, with theta = 1, no node factors and no domain, a whole
+                                 red+black sweep is one launch out of place between the level
+                                 iterate and a second buffer, reading every face coefficient
+                                 once; both compute the same iteration (the same arithmetic per
+                                 node) */
 
 typedef struct {
   const double *kx;   /* device, [n][n+1][N] */
@@ -218,10 +231,22 @@ int smg_residual(smg_ctx *ctx, const double *x, const double *f, double *r, doub
  * x, f: FP64 device vectors of that level's size. */
 int smg_smooth(smg_ctx *ctx, int level, int colour, double *x, const double *f);
 
+/* One whole sweep (red then black half-sweep, Section 3 with collective
+ * Gauss-Seidel) on level `level` from xin into xout (FP64 device vectors of the
+ * level's size that must not overlap; f likewise); xout equals xin after
+ * smg_smooth with colour 0 and then 1 (theta = 1 required).  Where the
+ * one-launch sweep applies (see SMG_FLAG_HALFSWEEPS) it is that single launch;
+ * otherwise xin is copied to xout and the two half-sweeps run there.  *one
+ * (may be NULL) tells which.  SMG_EINVAL for theta != 1 or aliasing vectors. */
+int smg_sweep(smg_ctx *ctx, int level, const double *xin, double *xout, const double *f, int *one);
+/* The same in FP32 arithmetic on FP32 vectors (SMG_F32 contexts). */
+int smg_sweep32(smg_ctx *ctx, int level, const float *xin, float *xout, const float *f, int *one);
+
 /* Device-to-device copy of `bytes` (a multiple of 16, both pointers 16-byte
- * aligned) by a plain streaming kernel with 16-byte accesses, on `stream`
- * (hipStream_t, NULL = default): the achievable-bandwidth reference quoted
- * next to the kernels' rooflines.  SMG_EINVAL for bad sizes or alignment. */
+ * aligned) by a plain streaming kernel (16-byte non-temporal accesses, four in
+ * flight per lane), on `stream` (hipStream_t, NULL = default): the
+ * achievable-bandwidth reference quoted next to the kernels' rooflines.
+ * SMG_EINVAL for bad sizes or alignment. */
 int smg_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /* The same half-sweep in FP32 arithmetic on FP32 device vectors x, f of the
@@ -380,10 +405,13 @@ typedef struct {
   int lin_maxit;      /* GMRES iterations per system at most (the paper: 80) */
   double sigma, rho;  /* line search on t (0: 1e-4, 1/2) */
   int inner_rule;     /* 0: the printed rule with max (both parts small); SMG_CVAR_INNER_MIN:
-                         min (either part small).  Not the paper's; a named option */
-  int inner_backtrack;/* 0: full Newton steps for h(t) (Algorithm 3 states no line search
-                         there); 1: halve each step (at most 30 times) until
-                         ||F_1(x + a dx)|| <= (1 - 1e-4 a) ||F_1(x)||.  Not the paper's */
+                         min (either part small), a named option that is not the paper's */
+  int inner_full_steps; /* 0: each Newton step for h(t) halved (at most 30 times) until
+                         ||F_1(x + a dx)|| <= (1 - 1e-4 a) ||F_1(x)|| (the paper names Newton's
+                         method without its globalization; full steps cycle on its
+                         Monte Carlo problems); the iteration ends without the step when no
+                         halving decreases ||F_1|| <= inner_tol (the rounding floor), takes
+                         the last halving otherwise; 1: full Newton steps */
 } smg_cvar_params;
 
 #define SMG_CVAR_INNER_MAX 0
@@ -402,6 +430,8 @@ typedef struct {
   int len;
   int inner_capped;     /* evaluations of h(t) that ended at inner_maxit (with the printed rule:
                            a warm start within 1/inner_tol of the rounding floor) */
+  int inner_stalled;    /* evaluations that ended because no halving decreased ||F_1|| with
+                           ||F_1|| <= inner_tol (the rounding floor) */
   int *inner_counts;    /* optional caller buffer of inner_cap entries: Newton count of every
                            evaluation of h(t), in order */
   int inner_cap;
@@ -418,9 +448,9 @@ typedef struct {
  * is S(c) x - [c_j y_d | f_U | f_P]; every Newton system J_11 dx = -F_1 and the
  * solve for F'(t) = J_22 - J_21 J_11^{-1} J_12 run GMRES preconditioned by one
  * V-cycle of S(c) from zero.  h(t) is computed by Newton from the current x with
- * full steps, stopped by the rule of the risk-averse experiments (Section 6):
- * max(||F_1(x^k)|| / ||F_1(x^0)||, ||F_1(x^k)||) <= inner_tol (inner_rule and
- * inner_backtrack select the non-default variants); when every g''(Q_j) vanishes (eq. condition) the step
+ * a backtracking on ||F_1||, stopped by the rule of the risk-averse experiments
+ * (Section 6): max(||F_1(x^k)|| / ||F_1(x^0)||, ||F_1(x^k)||) <= inner_tol
+ * (inner_rule and inner_full_steps select the variants); when every g''(Q_j) vanishes (eq. condition) the step
  * is the split one (h(t^k), the root of F_2(x; t) = 0 by bisection, h at that
  * root); else
  * the Newton step on t with backtracking |F(t + gamma d)| - |F(t)| <=

@@ -43,11 +43,14 @@ g(x) = s^3/eps^2 - s^4/(2 eps^3) with s = x + eps/2 (the printed branch has a
 typo; this is the C^2 piece that joins 0 and x); t^0 = 0; the Newton iterates
 for h(t) start from the current x; the inner Newton stops by the printed rule
 max(||F_1(x^k)|| / ||F_1(x^0)||, ||F_1(x^k)||) <= 1e-8 with x^0 the start of that
-inner iteration, and takes full steps (Algorithm 3 states no line search for
-h); an evaluation that cannot meet the relative part (a warm start whose
-||F_1(x^0)|| is within 1e8 of the rounding floor) runs to the iteration cap,
-which is counted; the rule with min and a backtracking on ||F_1|| are kept as
-named options (``inner_rule="min"``, ``inner_backtrack=True``), not defaults;
+inner iteration; an evaluation that cannot meet the relative part (a warm start
+whose ||F_1(x^0)|| is within 1e8 of the rounding floor) runs to the iteration
+cap or stalls (below); the paper names Newton's method for h(t) without its
+globalization, and full steps cycle on its Monte Carlo problems (705 nodes,
+N = 100: ||F_1|| stays at 3e-3..6e-3 for 50 steps), so each step backtracks on
+||F_1|| and the iteration ends when no halving decreases it (the rounding
+floor) (full steps: ``inner_backtrack=False``; the rule with min:
+``inner_rule="min"``; neither is a default);
 the split step solves F_2(x; t) = 0 by bisection (F_2 is nondecreasing in t)
 and then recomputes x = h(t) at the new t, since F(t) = F_2(h(t), t) is what the
 next test reads;
@@ -185,18 +188,22 @@ class Cvar:
             x = x + np.array(Zs).T @ y
 
     # --- the two Newton iterations ----------------------------------------
-    def inner(self, x, t, method, tol=1e-8, maxit=50, lin=None, rule="max", backtrack=False, hist=None):
+    def inner(self, x, t, method, tol=1e-8, maxit=50, lin=None, rule="max", backtrack=True, hist=None):
         """h(t): Newton on F_1(.; t) = 0 from x.
 
         rule="max" (Section 6, the stopping rules stated with the risk-averse
         table): stop once max(||F_1(x^k)|| / ||F_1(x^0)||, ||F_1(x^k)||) <= tol,
-        i.e. both the relative and the absolute residual are small; plain
-        Newton steps x^{k+1} = x^k + dx (Algorithm 3 states no line search for
-        h).  rule="min" stops once either part is small; backtrack=True halves
-        each step (1, 1/2, ..., at most 30 halvings) until
-        ||F_1(x + a dx)|| <= (1 - 1e-4 a) ||F_1(x)||.  Neither option is the
-        paper's; both are kept as named variants.  hist (a list) receives
-        ||F_1|| at every iterate."""
+        i.e. both the relative and the absolute residual are small; rule="min"
+        (a named variant, not the paper's) stops once either part is.
+        backtrack=True halves each step (1, 1/2, ..., at most 30 halvings)
+        until ||F_1(x + a dx)|| <= (1 - 1e-4 a) ||F_1(x)||: Algorithm 3 names
+        Newton's method for h without its globalization, and full steps
+        (backtrack=False) cycle on the paper's Monte Carlo problems.  When no
+        halving decreases ||F_1|| although the absolute part is met
+        (||F_1|| <= tol: the relative part is out of reach at the rounding
+        floor) the iteration ends there without the step ("stalled"); with a
+        larger residual the last halving is taken.  hist (a list) receives
+        ||F_1|| at every iterate.  Returns (x, Newton steps taken, stalled)."""
         if rule not in ("max", "min"):
             raise ValueError("rule must be 'max' or 'min'")
         stop = max if rule == "max" else min
@@ -214,18 +221,24 @@ class Cvar:
             if lin is not None:
                 lin.append(its)
             a = 1.0
+            ok = not backtrack
             for ls in range(31 if backtrack else 1):
                 xt = x + a * dx
                 Ft = self.F1(xt, t)
                 ft = np.linalg.norm(Ft)
-                if not backtrack or ft <= (1.0 - 1e-4 * a) * fn or ls == 30:
+                if not backtrack or ft <= (1.0 - 1e-4 * a) * fn:
+                    ok = True
                     break
-                a *= 0.5
+                if ls < 30:
+                    a *= 0.5
+            if not ok and fn <= tol:                       # no decrease at the floor
+                self.F1(x, t)                              # C_j back at x
+                return x, k, True
             x, F, fn = xt, Ft, ft
             if hist is not None:
                 hist.append(fn)
             k += 1
-        return x, k
+        return x, k, False
 
     def split_t(self, q):
         """The root of F_2(x; t) = 0 for fixed x (bisection)."""
@@ -242,20 +255,24 @@ class Cvar:
 
     def run(self, method: str = "gmres", t0: float = 0.0, tol: float = 1e-6, maxit: int = 50,
             sigma: float = 1e-4, rho: float = 0.5, max_ls: int = 30, x0=None, inner_tol: float = 1e-8,
-            inner_maxit: int = 50, inner_rule: str = "max", inner_backtrack: bool = False):
+            inner_maxit: int = 50, inner_rule: str = "max", inner_backtrack: bool = True):
         """Algorithm 3.  Returns t, x, u, the outer and inner Newton counts, the
         Newton count of every evaluation of h (``inner_counts``; an entry equal
-        to inner_maxit is an evaluation that ended at the cap), the
+        to inner_maxit is an evaluation that ended at the cap) and whether it
+        stalled at the rounding floor (``inner_stalled``), the
         linear-solver iterations of every solve and |F(t^k)| per iterate."""
         lin, counts = [], []
         t = float(t0)
         x = np.zeros((2 * self.N + 1) * self.nn) if x0 is None else np.array(x0, dtype=np.float64)
         base_inner = self.inner
 
+        stalled = []
+
         def inner(x, t, method, lin=None):
-            xx, kk = base_inner(x, t, method, tol=inner_tol, maxit=inner_maxit, lin=lin, rule=inner_rule,
-                                backtrack=inner_backtrack)
+            xx, kk, st = base_inner(x, t, method, tol=inner_tol, maxit=inner_maxit, lin=lin, rule=inner_rule,
+                                    backtrack=inner_backtrack)
             counts.append(kk)
+            stalled.append(st)
             return xx, kk
         x, inner_total = inner(x, t, method, lin=lin)
         hist, k, converged = [], 0, False
@@ -298,8 +315,8 @@ class Cvar:
             k += 1
         u = self.blocks(x)[1].copy()
         return dict(t=t, x=x, u=u, outer=k, inner_total=inner_total, inner_counts=counts,
-                    inner_capped=sum(1 for c in counts if c >= inner_maxit), linear=lin, F=hist,
-                    converged=converged)
+                    inner_capped=sum(1 for c in counts if c >= inner_maxit), inner_stalled=stalled,
+                    linear=lin, F=hist, converged=converged)
 
     def objective(self, y_of_u, u, t):
         """t + E[g(Q)] / (1 - lambda) + nu/2 u^T M u for states y_of_u(u) (N, nn)."""

@@ -24,11 +24,13 @@ SMG_FLAG_UNFUSED = 2
 SMG_FLAG_JACOBI = 4
 SMG_FLAG_SSN = 8
 SMG_FLAG_CVAR = 16
+SMG_FLAG_HALFSWEEPS = 32
 SMG_COARSEN_INJECT, SMG_COARSEN_FULL = 0, 1
 
 EXPORTED = [
     "smg_workspace_bytes", "smg_setup", "smg_destroy", "smg_strerror", "smg_last_error",
-    "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_stream_copy", "smg_restrict",
+    "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_sweep",
+    "smg_sweep32", "smg_stream_copy", "smg_restrict",
     "smg_residual_restrict", "smg_jacobi", "smg_prolong_add", "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond",
     "smg_solve", "smg_batch_workspace_bytes", "smg_batch_setup", "smg_batch_solve", "smg_batch_destroy",
     "smg_batch_last_error", "smg_tune_lanes", "smg_net_param_count", "smg_net_workspace_bytes",
@@ -42,7 +44,7 @@ EXPORTED = [
 class Desc(C.Structure):
     _fields_ = [("n", C.c_int), ("nsamples", C.c_int), ("coarsest_n", C.c_int), ("pre", C.c_int),
                 ("post", C.c_int), ("theta", C.c_double), ("precision", C.c_int),
-                ("gmres_restart", C.c_int), ("flags", C.c_int), ("strip", C.c_int)]
+                ("gmres_restart", C.c_int), ("flags", C.c_int), ("strip", C.c_int), ("sweep_rows", C.c_int)]
 
 
 class Blocks(C.Structure):
@@ -72,14 +74,15 @@ class CvarParams(C.Structure):
                 ("zeta", C.POINTER(C.c_double)), ("tol", C.c_double), ("inner_tol", C.c_double),
                 ("lin_rtol", C.c_double), ("maxit", C.c_int), ("inner_maxit", C.c_int),
                 ("lin_maxit", C.c_int), ("sigma", C.c_double), ("rho", C.c_double),
-                ("inner_rule", C.c_int), ("inner_backtrack", C.c_int)]
+                ("inner_rule", C.c_int), ("inner_full_steps", C.c_int)]
 
 
 class CvarStats(C.Structure):
     _fields_ = [("outer", C.c_int), ("inner_total", C.c_int), ("linear_solves", C.c_int),
                 ("linear_total", C.c_int), ("t", C.c_double), ("F_final", C.c_double),
                 ("time_ms", C.c_double), ("F", C.POINTER(C.c_double)), ("cap", C.c_int), ("len", C.c_int),
-                ("inner_capped", C.c_int), ("inner_counts", C.POINTER(C.c_int)), ("inner_cap", C.c_int),
+                ("inner_capped", C.c_int), ("inner_stalled", C.c_int), ("inner_counts", C.POINTER(C.c_int)),
+                ("inner_cap", C.c_int),
                 ("inner_len", C.c_int)]
 
 
@@ -136,6 +139,8 @@ def load(path: str = LIB_PATH):
     L.smg_residual.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
     L.smg_smooth.argtypes = [vp, i, i, vp, vp]
     L.smg_smooth32.argtypes = [vp, i, i, vp, vp]
+    L.smg_sweep.argtypes = [vp, i, vp, vp, vp, C.POINTER(i)]
+    L.smg_sweep32.argtypes = [vp, i, vp, vp, vp, C.POINTER(i)]
     L.smg_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
     L.smg_stream_copy.restype = i
     L.smg_restrict.argtypes = [vp, i, vp, vp]
@@ -208,9 +213,9 @@ def _ptr(t):
 
 
 def workspace_bytes(n, N, coarsest_n=7, pre=2, post=2, theta=1.0, precision=SMG_F64, gmres_restart=30,
-                    flags=0, strip=0):
+                    flags=0, strip=0, sweep_rows=0):
     L = load()
-    desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart, flags, strip)
+    desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart, flags, strip, sweep_rows)
     return int(L.smg_workspace_bytes(C.byref(desc)))
 
 
@@ -226,14 +231,14 @@ class Context:
 
     def __init__(self, n, N, kx, ky, c, d, e, g, *, coarsest_n=7, pre=2, post=2, theta=1.0,
                  precision=SMG_F64, gmres_restart=30, flags=0, strip=0, stream=None, ctrl=None, domain=None,
-                 control_growth=0.0):
+                 control_growth=0.0, sweep_rows=0):
         import torch
         L = load()
         self.L = L
         self.n, self.N = n, N
         self.precision = precision
         self.device = kx.device
-        self.desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart, flags, strip)
+        self.desc = Desc(n, N, coarsest_n, pre, post, theta, precision, gmres_restart, flags, strip, sweep_rows)
         nbytes = int(L.smg_workspace_bytes(C.byref(self.desc)))
         if nbytes == 0:
             raise SmgError(-1, "invalid descriptor")
@@ -294,6 +299,19 @@ class Context:
 
     def smooth(self, level, colour, x, f):
         return self._check(self.L.smg_smooth(self.ctx, level, colour, _ptr(x), _ptr(f)))
+
+    def sweep(self, level, xin, xout, f):
+        """One red+black sweep xin -> xout (FP64 contexts); returns True where it
+        ran as one launch."""
+        one = C.c_int(0)
+        self._check(self.L.smg_sweep(self.ctx, level, _ptr(xin), _ptr(xout), _ptr(f), C.byref(one)))
+        return bool(one.value)
+
+    def sweep32(self, level, xin, xout, f):
+        """The FP32 sweep on float32 device vectors (SMG_F32 contexts)."""
+        one = C.c_int(0)
+        self._check(self.L.smg_sweep32(self.ctx, level, _ptr(xin), _ptr(xout), _ptr(f), C.byref(one)))
+        return bool(one.value)
 
     def smooth32(self, level, colour, x, f):
         """FP32 half-sweep on float32 device vectors (SMG_F32 contexts)."""
@@ -385,25 +403,26 @@ class Context:
                                                   None if w is None else _ptr(w)))
 
     def cvar_solve(self, x, f, yd, zeta, lam, eps, mass, t0=0.0, tol=1e-6, inner_tol=1e-8, lin_rtol=1e-9,
-                   maxit=50, inner_maxit=50, lin_maxit=80, cap=256, inner_rule="max", inner_backtrack=False):
+                   maxit=50, inner_maxit=50, lin_maxit=80, cap=256, inner_rule="max", inner_backtrack=True):
         """Algorithm 3 in place on x (device); yd: device [n][n].  inner_rule "max"
-        (the printed rule) or "min"; inner_backtrack: the non-default line search
-        for h(t).  Returns (rc, stats dict)."""
+        (the printed rule) or "min"; inner_backtrack: the line search of the
+        Newton steps for h(t) (False: full steps).  Returns (rc, stats dict)."""
         if inner_rule not in ("max", "min"):
             raise ValueError("inner_rule must be 'max' or 'min'")
         zeta = np.ascontiguousarray(zeta, dtype=np.float64)
         prm = CvarParams(lam, eps, mass, zeta.ctypes.data_as(C.POINTER(C.c_double)), tol, inner_tol, lin_rtol,
                          maxit, inner_maxit, lin_maxit, 0.0, 0.0, 1 if inner_rule == "min" else 0,
-                         1 if inner_backtrack else 0)
+                         0 if inner_backtrack else 1)
         F = (C.c_double * cap)()
         counts = (C.c_int * cap)()
-        st = CvarStats(0, 0, 0, 0, 0.0, 0.0, 0.0, F, cap, 0, 0, counts, cap, 0)
+        st = CvarStats(0, 0, 0, 0, 0.0, 0.0, 0.0, F, cap, 0, 0, 0, counts, cap, 0)
         t = C.c_double(t0)
         rc = self._check(self.L.smg_cvar_solve(self.ctx, _ptr(x), _ptr(f), _ptr(yd), C.byref(t), C.byref(prm),
                                                C.byref(st)), allow_nc=True)
         return rc, dict(outer=st.outer, inner_total=st.inner_total, linear_solves=st.linear_solves,
                         linear_total=st.linear_total, t=t.value, F_final=st.F_final, time_ms=st.time_ms,
                         F=list(F[:min(st.len, cap)]), inner_capped=st.inner_capped,
+                        inner_stalled=st.inner_stalled,
                         inner_counts=list(counts[:min(st.inner_len, cap)]))
 
 

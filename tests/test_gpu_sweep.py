@@ -1,0 +1,131 @@
+"""The one-launch red+black sweep (k_sweep_fused) against the two half-sweeps it
+replaces and against the oracle: single sweeps on every level that takes it,
+with segment boundaries forced by short segments, in FP64 and FP32, and whole
+V-cycles with and without it."""
+import numpy as np
+import pytest
+
+from paper_2302_13680_amd import inputs
+from paper_2302_13680_amd.inputs import node_to_paper, paper_to_node
+from parity_util import assert_blocks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_13680_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as o
+    return o
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("n,N,rows", [(127, 64, 200), (127, 100, 5), (255, 64, 16), (127, 256, 64), (255, 33, 7)])
+def test_sweep_equals_two_halfsweeps_and_oracle(B, O, n, N, rows):
+    p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=n + N)
+    o = O.Oracle(p)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0, sweep_rows=rows)
+    rng = np.random.default_rng(N)
+    x = rng.standard_normal(o.vlen())
+    f = rng.standard_normal(o.vlen())
+    xd, fd = dev(paper_to_node(x, n, N)), dev(paper_to_node(f, n, N))
+    out = torch.empty_like(xd)
+    assert ctx.sweep(0, xd, out, fd)                      # one launch on this level
+    ref = xd.clone()
+    ctx.smooth(0, 0, ref, fd)
+    ctx.smooth(0, 1, ref, fd)
+    got = node_to_paper(host(out), n, N)
+    assert_blocks(got, node_to_paper(host(ref), n, N), n, N, 1e-15, "two half-sweeps")
+    xo = o.halfsweep(o.halfsweep(x, f, 0), f, 1)
+    assert_blocks(got, xo, n, N, 1e-13, "oracle")
+
+
+def test_sweep_refuses_aliasing_and_reports_the_fallback(B):
+    p = inputs.make_problem(63, 64, 1e-4, M=6, sigma=0.5, decay=True, seed=3)
+    ctx, f = B.context_from_problem(p, gmres_restart=0)
+    x = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.SmgError):
+        ctx.sweep(0, x, x, f)
+    out = torch.empty_like(x)
+    assert not ctx.sweep(0, x, out, f)                    # 63 x 63: two half-sweeps
+
+
+@pytest.mark.parametrize("n,N", [(127, 128), (255, 256)])
+def test_fp32_sweep_equals_two_halfsweeps(B, O, n, N):
+    p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=7)
+    o = O.Oracle(p)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0, precision=B.SMG_F32, sweep_rows=32)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(o.vlen())
+    f = rng.standard_normal(o.vlen())
+    xd, fd = dev(paper_to_node(x, n, N), torch.float32), dev(paper_to_node(f, n, N), torch.float32)
+    out = torch.empty_like(xd)
+    assert ctx.sweep32(0, xd, out, fd)
+    ref = xd.clone()
+    ctx.smooth32(0, 0, ref, fd)
+    ctx.smooth32(0, 1, ref, fd)
+    assert_blocks(node_to_paper(host(out), n, N), node_to_paper(host(ref), n, N), n, N, 1e-7, "two half-sweeps")
+    xo = o.halfsweep32(o.halfsweep32(x, f, 0), f, 1)
+    assert_blocks(node_to_paper(host(out), n, N), xo, n, N, 2e-6, "oracle")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vcycles_with_and_without_one_launch_sweeps(B, O, precision):
+    """255x255, N = 64 with 32-row segments: levels 255, 127, 63 and below sweep
+    in one launch (zero start on the coarse levels, prolongation folded into the
+    first post sweep); iterates equal those of the half-sweep cycle and the
+    oracle's."""
+    p = inputs.make_problem(255, 64, 1e-4, M=6, sigma=0.5, decay=True, seed=21)
+    o = O.Oracle(p)
+    fp = p.rhs_paper()
+    c1, f = B.context_from_problem(p, gmres_restart=0, precision=precision, sweep_rows=32)
+    c2, _ = B.context_from_problem(p, gmres_restart=0, precision=precision, flags=B.SMG_FLAG_HALFSWEEPS)
+    x1 = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    x2 = torch.zeros_like(x1)
+    xo = np.zeros(o.vlen())
+    cyc = o.vcycle if precision == 0 else o.vcycle32
+    # FP32: two single-precision evaluations of the same cycle differ by rounding
+    # (unit roundoff 6e-8) amplified by the cancellation in p_j = (b_P - c_j y_j) / a_j,
+    # where b_P and c_j y_j are ~1e3 times p_j: ~1e-5 relative in the P block
+    tol_pair, tol_or = (1e-13, 1e-12) if precision == 0 else (1e-4, 1e-4)
+    for k in range(2):
+        c1.vcycle(x1, f, 1)
+        c2.vcycle(x2, f, 1)
+        xo = cyc(xo, fp, 1)
+        g1 = node_to_paper(host(x1), p.n, p.N)
+        e1 = assert_blocks(g1, node_to_paper(host(x2), p.n, p.N), p.n, p.N, tol_pair, k)
+        e2 = assert_blocks(g1, xo, p.n, p.N, tol_or, k)
+        print("cycle", k, "one-launch vs half-sweeps", e1, "vs oracle", e2, flush=True)
+
+
+def test_large_level_takes_the_one_launch_sweep_by_default(B):
+    """511x511, N = 256 (a level that streams from HBM): the default context sweeps
+    in one launch, SMG_FLAG_HALFSWEEPS does not, and both give the same sweep."""
+    p = inputs.large_mixed()
+    ctx, f = B.context_from_problem(p, gmres_restart=0)
+    xin = torch.rand(p.dof, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    a = torch.empty_like(xin)
+    assert ctx.sweep(0, xin, a, f)
+    ctx.close()
+    c2, _ = B.context_from_problem(p, gmres_restart=0, flags=B.SMG_FLAG_HALFSWEEPS)
+    b = torch.empty_like(xin)
+    assert not c2.sweep(0, xin, b, f)
+    rel = (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
+    assert rel <= 1e-15, rel
