@@ -225,6 +225,19 @@ int smg_apply(smg_ctx *ctx, const double *x, double *Sx);
  * { ||r||, ||r_Y||, ||r_U||, ||r_P|| } (2-norms). */
 int smg_residual(smg_ctx *ctx, const double *x, const double *f, double *r, double *norms);
 
+/* The same residual r = f - S x for callers that cannot allocate device memory
+ * or read back to the host (code under HIP graph capture, serving loops): the
+ * kernels' per-block partial sums live in a static device array of the library
+ * (8.4 MB per GPU, held until the process ends; enough for 1023 x 1023 grids)
+ * instead of the context's workspace, and the five norms
+ * { ||r||, ||r_Y||, ||r_U||, ||r_P||, ||f|| } go to norms_dev (device, 5
+ * doubles) with no host synchronization.  Launches kernels only (no
+ * allocation, no memset, no copy).  Calls that overlap on one GPU (other
+ * streams or threads) share that array and race.  SMG_EWORKSPACE when the grid
+ * needs more scratch than the array holds, SMG_EINVAL with rank-one terms set
+ * (smg_set_lowrank) or null pointers. */
+int smg_residual_static(smg_ctx *ctx, const double *x, const double *f, double *r, double *norms_dev);
+
 /* One half-sweep of the collective Gauss-Seidel smoother on level `level`
  * (eq. collective_smoothing, node solve eq. solution_reduced_system): every
  * node with (x + k) % 2 == colour gets (1-theta) x_i + theta S~_i^{-1} b_i.

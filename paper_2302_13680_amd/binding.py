@@ -29,7 +29,7 @@ SMG_COARSEN_INJECT, SMG_COARSEN_FULL = 0, 1
 
 EXPORTED = [
     "smg_workspace_bytes", "smg_setup", "smg_destroy", "smg_strerror", "smg_last_error",
-    "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_sweep",
+    "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_residual_static", "smg_smooth", "smg_smooth32", "smg_sweep",
     "smg_sweep32", "smg_stream_copy", "smg_restrict",
     "smg_residual_restrict", "smg_jacobi", "smg_prolong_add", "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond",
     "smg_solve", "smg_batch_workspace_bytes", "smg_batch_setup", "smg_batch_solve", "smg_batch_destroy",
@@ -137,6 +137,7 @@ def load(path: str = LIB_PATH):
     L.smg_level_n.argtypes = [vp, i]
     L.smg_apply.argtypes = [vp, vp, vp]
     L.smg_residual.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
+    L.smg_residual_static.argtypes = [vp, vp, vp, vp, vp]
     L.smg_smooth.argtypes = [vp, i, i, vp, vp]
     L.smg_smooth32.argtypes = [vp, i, i, vp, vp]
     L.smg_sweep.argtypes = [vp, i, vp, vp, vp, C.POINTER(i)]
@@ -296,6 +297,11 @@ class Context:
             return list(buf)
         self._check(self.L.smg_residual(self.ctx, _ptr(x), _ptr(f), _ptr(r), None))
         return None
+
+    def residual_static(self, x, f, r, norms_dev):
+        """r = f - S x with the five norms written to the device tensor norms_dev
+        (float64, 5 entries), partial sums in the library's static scratch."""
+        return self._check(self.L.smg_residual_static(self.ctx, _ptr(x), _ptr(f), _ptr(r), _ptr(norms_dev)))
 
     def smooth(self, level, colour, x, f):
         return self._check(self.L.smg_smooth(self.ctx, level, colour, _ptr(x), _ptr(f)))

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <mutex>
 #include <vector>
 
 #include "../../include/smg.h"
@@ -206,6 +207,7 @@ struct smg_ctx {
   smg_desc desc{};
   int nlev = 0, N = 0;
   hipStream_t stream = nullptr;
+  int device = 0;              // the device current at setup (the stream's)
   std::string err;
   Level<double> L64[kMaxLevels];
   Level<float> L32[kMaxLevels];
@@ -681,8 +683,23 @@ void set_masked(smg_ctx* C, bool masked) {
 
 // out = f - S x (mode 0) or S x (mode 1); when want_norm, C->norms receives
 // { ||r||, ||r_Y||, ||r_U||, ||r_P||, ||f|| } (||f|| = 0 in mode 1).
+// Blocks of the residual kernel on a level of n x n nodes (one partial sum per block).
+int residual_blocks(const smg_ctx* C, int n) {
+  int nb = 0;
+  lane_dispatch<false>(C->desc.precision, C->N, [&](auto Wc, auto, auto) {
+    const int per = kBlock / decltype(Wc)::value;
+    nb = (int)(((size_t)n * n + per - 1) / per);
+  });
+  return nb;
+}
+
+// out = f - S x (mode 0) or S x (mode 1); with partials given, also the five
+// norms { ||r||, ||r_Y||, ||r_U||, ||r_P||, ||f|| } into norms (device), the
+// per-block sums in partials (residual_blocks x 4) and, above kNormStageMin
+// blocks, partials2 (kNormStage x 4).
 template <typename T, typename TX, typename TO>
-int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, int mode, bool want_norm) {
+int residual_into(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, int mode, double* partials,
+                  double* partials2, double* norms) {
   const size_t nn = (size_t)L.n * L.n;
   lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value, VW = decltype(Vc)::value;
@@ -690,22 +707,26 @@ int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, i
     const int nb = (int)((nn + per - 1) / per);
     mask_dispatch(C->masked, [&](auto Mc) {
       hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM, VW, decltype(Mc)::value>), dim3(nb), dim3(kBlock), 0,
-                         C->stream, args(L, C->N, C->desc.strip), x, f, out, mode,
-                         want_norm ? C->partials : (double*)nullptr);
+                         C->stream, args(L, C->N, C->desc.strip), x, f, out, mode, partials);
     });
-    if (want_norm) {
+    if (partials) {
       if (nb > kNormStageMin) {   // two stages: one block alone reads partials at ~50 GB/s
-        hipLaunchKernelGGL(k_norms_stage, dim3(kNormStage), dim3(kBlock), 0, C->stream, C->partials, nb,
-                           C->partials2);
-        hipLaunchKernelGGL(k_finalize_norms, dim3(1), dim3(1024), 0, C->stream, C->partials2, kNormStage,
-                           C->norms);
+        hipLaunchKernelGGL(k_norms_stage, dim3(kNormStage), dim3(kBlock), 0, C->stream, (const double*)partials, nb,
+                           partials2);
+        hipLaunchKernelGGL(k_finalize_norms, dim3(1), dim3(1024), 0, C->stream, (const double*)partials2,
+                           kNormStage, norms);
       } else {
-        hipLaunchKernelGGL(k_finalize_norms, dim3(1), dim3(1024), 0, C->stream, C->partials, nb, C->norms);
+        hipLaunchKernelGGL(k_finalize_norms, dim3(1), dim3(1024), 0, C->stream, (const double*)partials, nb, norms);
       }
     }
   });
   LAUNCH_CHECK();
   return SMG_OK;
+}
+
+template <typename T, typename TX, typename TO>
+int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, int mode, bool want_norm) {
+  return residual_into<T, TX, TO>(C, L, x, f, out, mode, want_norm ? C->partials : nullptr, C->partials2, C->norms);
 }
 
 // x_next = x + d, out = f - S x_next (FP32), norms into C->norms (FP32 refinement).
@@ -1660,6 +1681,7 @@ int smg_setup(const smg_desc* desc_in, const smg_blocks* B, void* workspace, siz
   C->N = N;
   C->nlev = count_levels(d.n, d.coarsest_n);
   C->stream = (hipStream_t)stream;
+  if (hipGetDevice(&C->device) != hipSuccess) C->device = 0;
   const size_t need = plan(d, C, workspace);
   if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255) != 0) {
     delete C;
@@ -1785,6 +1807,67 @@ int smg_apply(smg_ctx* C, const double* x, double* Sx) {
   if (!C || !x || !Sx) return SMG_EINVAL;
   TRY((residual<double, double, double>(C, C->L64[0], x, (const double*)nullptr, Sx, 1, false)));
   return lowrank_add(C, x, Sx, 1.0);
+}
+
+}  // extern "C"
+
+// ============================================== allocation-free residual
+// The library's own device scratch for smg_residual_static: the residual's
+// per-block partial sums (and the first stage of their reduction).  Each GPU the
+// library runs on holds its own copy until the process ends.  Host code uses
+// only the address hipGetSymbolAddress gives for the current device, never the
+// array's name.
+constexpr size_t kScratchDoubles = ((size_t)1 << 20) + 4 * kNormStage;   // 8.4 MB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the context's device, looked up once per
+// device with that device current (the caller's current device is restored).
+int scratch_address(smg_ctx* C, double** out) {
+  const int dev = C->device;
+  if (dev < 0 || dev >= kMaxDevices) {
+    C->err = "smg_residual_static: device index beyond the library's table";
+    return SMG_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != dev) HIP_TRY(hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) HIP_TRY(hipSetDevice(cur));
+    if (e != hipSuccess || !p) return hip_fail(C, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SMG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int smg_residual_static(smg_ctx* C, const double* x, const double* f, double* r, double* norms_dev) {
+  if (!C || !x || !f || !r || !norms_dev) return SMG_EINVAL;
+  if (C->lr_on) {
+    C->err = "smg_residual_static: the rank-one terms are not supported (use smg_residual)";
+    return SMG_EINVAL;
+  }
+  const int nb = residual_blocks(C, C->desc.n);
+  const size_t need = 4 * (size_t)nb + 4 * (size_t)kNormStage;
+  if (need > kScratchDoubles) {
+    C->err = "smg_residual_static: this grid needs " + std::to_string(need) + " doubles of scratch, the library holds " +
+             std::to_string(kScratchDoubles);
+    return SMG_EWORKSPACE;
+  }
+  double* s = nullptr;
+  TRY(scratch_address(C, &s));
+  // every partial is written before it is read: nothing needs clearing
+  return residual_into<double, double, double>(C, C->L64[0], x, f, r, 0, s, s + 4 * (size_t)nb, norms_dev);
 }
 
 int smg_residual(smg_ctx* C, const double* x, const double* f, double* r, double* norms) {

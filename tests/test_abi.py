@@ -48,13 +48,15 @@ def test_workspace_bytes_validation(lib):
                 Desc(255, 64, 7, 2, 2, 2.5, 0, 30, 0),   # theta out of range
                 Desc(255, 64, 7, 2, 2, 1.0, 2, 30, 0),   # unknown precision
                 Desc(255, 64, 7, 2, 2, 1.0, 0, 40, 0),   # restart too long
-                Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 32),  # unknown flags
+                Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 64),  # unknown flags
                 Desc(255, 64, 7, 2, 2, 1.0, 1, 30, 16),  # risk-averse buffers in an FP32 context
                 Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 0, 33),   # odd strip width
-                Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 0, -2)]:  # negative strip width
+                Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 0, -2),   # negative strip width
+                Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 0, 0, -1)]:  # negative sweep segment
         assert lib.smg_workspace_bytes(C.byref(bad)) == 0
-    # every defined flag is accepted (eager, unfused, Jacobi smoother, Newton and risk-averse buffers)
-    assert lib.smg_workspace_bytes(C.byref(Desc(255, 64, 7, 2, 2, 0.5, 0, 30, 31))) > 0
+    # every defined flag is accepted (eager, unfused, Jacobi smoother, Newton and risk-averse
+    # buffers, half-sweeps only)
+    assert lib.smg_workspace_bytes(C.byref(Desc(255, 64, 7, 2, 2, 0.5, 0, 30, 63))) > 0
     # the Newton buffers: two more vectors and six node arrays at least
     ssn = lib.smg_workspace_bytes(C.byref(Desc(255, 64, 7, 2, 2, 1.0, 0, 30, 8)))
     assert ssn - nb >= (2 * (2 * 64 + 1) + 4) * 255 * 255 * 8
