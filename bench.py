@@ -269,14 +269,18 @@ def batch_section(dev, cache_path):
 def learned_section(dev, n_train=2000, n_test=200, epochs=20):
     """Warm start on 127x127, N=128 (nu log-uniform in [1e-5, 1e-3], y_d random
     sums of three sine products): 2000 multigrid solves as training data, the
-    network trained on the GPU by the library's kernels, 200 held-out seeds."""
+    network trained on the GPU by the library's kernels, 200 held-out seeds,
+    judged after one V-cycle against the zero start's first-cycle residual."""
+    import numpy as np
     import torch
     from paper_2302_13680_amd import binding, learn
     n, N = 127, 128
     H = learn.grid_for(n)
     t0 = time.perf_counter()
-    feats, raw = learn.make_dataset(list(range(10000, 10000 + n_train)), n=n, N=N, device=dev)
+    first = []
+    feats, raw = learn.make_dataset(list(range(10000, 10000 + n_train)), n=n, N=N, device=dev, first_cycle=first)
     t_data = time.perf_counter() - t0
+    rho0 = float(np.median(first))
     norm = learn.standardization(raw, n)
     tg = learn.standardize(raw, norm, n)
     del raw
@@ -288,7 +292,7 @@ def learned_section(dev, n_train=2000, n_test=200, epochs=20):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del feats, tg
-    recs = learn.evaluate(net, list(range(20000, 20000 + n_test)), norm, n=n, N=N, device=dev)
+    recs = learn.evaluate(net, list(range(20000, 20000 + n_test)), norm, n=n, N=N, device=dev, rho0=rho0)
     summ = learn.summarize(recs)
     summ.update({"workload": "127x127, N=128, nu log-uniform [1e-5,1e-3], y_d random sums of 3 sine "
                              "products; FP64 V(2,2) to 1e-8",

@@ -475,16 +475,19 @@ int smg_cvar_solve(smg_ctx *ctx, double *x, const double *f, const double *yd, d
 
 /* ------------------------------------------------------------------ batches
  * Many independent problem instances (different n, N and blocks) solved
- * together: every refinement step of all unretired instances -- FP64 residual
- * r_i = f_i - S_i x_i, convergence check, one correction V-cycle from zero in
- * the contexts' precision (red-black collective Gauss-Seidel V(pre,post),
- * Alg. 1), x_i += correction -- is one fixed sequence of batched launches,
- * each covering one phase of all instances at the same hierarchy depth,
- * captured once into a hipGraph and replayed.  An instance is retired on the
- * device as soon as its relative residual meets the tolerance; its blocks then
- * exit at once.  The instances' contexts must share precision, pre, post and
- * stream and use theta = 1 (pre, post >= 1).  Calls that overlap on the same
- * contexts race (the batch uses their scratch buffers). */
+ * together.  The instances are grouped by finest grid size and the groups run
+ * one after another (smallest first) on the contexts' stream, so small
+ * instances retire early.  Within a group every refinement step of all unretired
+ * instances -- FP64 residual r_i = f_i - S_i x_i, convergence check, one
+ * correction V-cycle from zero in the contexts' precision (red-black collective
+ * Gauss-Seidel V(pre,post), Alg. 1), x_i += correction -- is one fixed sequence
+ * of batched launches, each covering one phase of the group's instances at the
+ * same hierarchy depth, captured once into a hipGraph and replayed.  An instance
+ * is retired on the device as soon as its relative residual meets the
+ * tolerance; its blocks then exit at once.  The instances' contexts must share
+ * precision, pre, post and stream and use theta = 1 (pre, post >= 1).  Calls
+ * that overlap on the same contexts race (the batch uses their scratch
+ * buffers). */
 typedef struct smg_batch smg_batch;
 
 /* Device workspace bytes a batch over these contexts needs (0 if invalid). */

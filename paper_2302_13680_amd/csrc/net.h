@@ -1,13 +1,17 @@
 // net.h -- kernels of the warm-start network: 3x3 / 1x1 convolutions as
-// implicit GEMMs on the gfx950 matrix cores (v_mfma_f32_16x16x16_bf16: BF16
-// operands, FP32 accumulation), SiLU, masked MSE loss and Adam.
+// implicit GEMMs on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16: BF16
+// operands, FP32 accumulation, K = 32 per instruction), SiLU, masked MSE loss
+// and Adam.
 //
 // Tensors are NHWC.  Activations feeding a matrix product are BF16; pre-
 // activations, gradients of activations, weight gradients and the master
-// weights are FP32.  MFMA operand layout (one wavefront, 16x16x16):
-//   A (16 x 16, M x K): lane l holds A[l % 16][4 (l / 16) + j], j = 0..3
-//   B (16 x 16, K x N): lane l holds B[4 (l / 16) + j][l % 16]
-//   D (16 x 16, M x N): lane l holds D[4 (l / 16) + j][l % 16]
+// weights are FP32.  MFMA operand layout (one wavefront, 16x16x32; checked on
+// the device with small integer matrices):
+//   A (16 x 32, M x K): lane l holds A[l % 16][8 (l / 16) + j], j = 0..7
+//   B (32 x 16, K x N): lane l holds B[8 (l / 16) + j][l % 16]
+//   D (16 x 16, M x N): lane l holds D[4 (l / 16) + i][l % 16], i = 0..3
+// Each lane's eight K values are two runs of four (channel counts are multiples
+// of four), loaded as two 8-byte accesses.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -15,7 +19,17 @@
 namespace smgnet {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8s __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// acc += A B for one 16x16x32 tile (operands as 8 BF16 bit patterns per lane)
+__device__ __forceinline__ f32x4 mfma_k32(bf16x4 alo, bf16x4 ahi, bf16x4 blo, bf16x4 bhi, f32x4 acc) {
+  const bf16x8s a = __builtin_shufflevector(alo, ahi, 0, 1, 2, 3, 4, 5, 6, 7);
+  const bf16x8s b = __builtin_shufflevector(blo, bhi, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), acc,
+                                                 0, 0, 0);
+}
 
 constexpr int kNetBlock = 256;   // 4 wavefronts
 
@@ -75,23 +89,33 @@ __global__ __launch_bounds__(kNetBlock) void k_conv_fwd(ConvGeom g, const uint16
   f32x4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int kq = 4 * (lane >> 4);
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const int k4 = k0 + kq;
-    bf16x4 av = bf16x4{0, 0, 0, 0};
-    if (rvalid && k4 < K) {
-      const int tap = k4 / g.Cin, ci = k4 - tap * g.Cin;
-      int yi, xi;
-      if (tap_src(g, ryo, rxo, tap, yi, xi))
-        av = *(const bf16x4*)(in + (((size_t)rb * g.Hin + yi) * g.Win + xi) * g.Cin + ci);
+  const int kq = 4 * (lane >> 4);      // D rows of this lane
+  const int k8 = 8 * (lane >> 4);      // first of this lane's eight K values
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x4 av[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k4 = k0 + k8 + 4 * h;
+      av[h] = bf16x4{0, 0, 0, 0};
+      if (rvalid && k4 < K) {
+        const int tap = k4 / g.Cin, ci = k4 - tap * g.Cin;
+        int yi, xi;
+        if (tap_src(g, ryo, rxo, tap, yi, xi))
+          av[h] = *(const bf16x4*)(in + (((size_t)rb * g.Hin + yi) * g.Win + xi) * g.Cin + ci);
+      }
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (t < NT) {
         const int co = 16 * t + (lane & 15);
-        bf16x4 bv = bf16x4{0, 0, 0, 0};
-        if (co < g.Cout && k4 < K) bv = *(const bf16x4*)(W + (size_t)co * K + k4);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+        bf16x4 bv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k4 = k0 + k8 + 4 * h;
+          bv[h] = bf16x4{0, 0, 0, 0};
+          if (co < g.Cout && k4 < K) bv[h] = *(const bf16x4*)(W + (size_t)co * K + k4);
+        }
+        acc[t] = mfma_k32(av[0], av[1], bv[0], bv[1], acc[t]);
       }
     }
   }
@@ -157,7 +181,8 @@ __global__ __launch_bounds__(kNetBlock) void k_conv_bwd_data(ConvGeom g, const u
   f32x4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int kq = 4 * (lane >> 4);
+  const int kq = 4 * (lane >> 4);      // D rows of this lane
+  const int k8 = 8 * (lane >> 4);      // first of this lane's eight reduction values
   for (int tap = 0; tap < g.taps; ++tap) {
     const int ky = tap / k, kx = tap - ky * k;
     for (int sub = 0; sub < nsub; ++sub) {
@@ -175,17 +200,27 @@ __global__ __launch_bounds__(kNetBlock) void k_conv_bwd_data(ConvGeom g, const u
       }
       ok = ok && yo >= 0 && yo < g.Hout && xo >= 0 && xo < g.Wout;
       const size_t orow = ((size_t)rb * g.Hout + (ok ? yo : 0)) * g.Wout + (ok ? xo : 0);
-      for (int c0 = 0; c0 < g.CoutP; c0 += 16) {
-        const int co = c0 + kq;
-        bf16x4 av = bf16x4{0, 0, 0, 0};
-        if (ok && co < g.CoutP) av = *(const bf16x4*)(dz16 + orow * g.CoutP + co);
+      for (int c0 = 0; c0 < g.CoutP; c0 += 32) {
+        bf16x4 av[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int co = c0 + k8 + 4 * h;
+          av[h] = bf16x4{0, 0, 0, 0};
+          if (ok && co < g.CoutP) av[h] = *(const bf16x4*)(dz16 + orow * g.CoutP + co);
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           if (t < NT) {
             const int ci = 16 * t + (lane & 15);
-            bf16x4 bv = bf16x4{0, 0, 0, 0};
-            if (ci < g.Cin && co < g.CoutP) bv = *(const bf16x4*)(WT + ((size_t)ci * g.taps + tap) * g.CoutP + co);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+            bf16x4 bv[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int co = c0 + k8 + 4 * h;
+              bv[h] = bf16x4{0, 0, 0, 0};
+              if (ci < g.Cin && co < g.CoutP)
+                bv[h] = *(const bf16x4*)(WT + ((size_t)ci * g.taps + tap) * g.CoutP + co);
+            }
+            acc[t] = mfma_k32(av[0], av[1], bv[0], bv[1], acc[t]);
           }
         }
       }
@@ -225,13 +260,14 @@ __global__ __launch_bounds__(kNetBlock) void k_conv_bwd_weight(ConvGeom g, const
   const int kcol = 16 * kt + (lane & 15);        // B column (k) of this lane
   const int tap = kcol / g.Cin, ci = kcol - (kcol / g.Cin) * g.Cin;
   const bool colv = kcol < K;
-  const int kq = 4 * (lane >> 4);
+  const int kq = 4 * (lane >> 4);      // D rows of this lane
+  const int k8 = 8 * (lane >> 4);      // first of this lane's eight pixels
   f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int q0 = pbeg; q0 < pend; q0 += 16) {
-    bf16x4 av, bv;
+  for (int q0 = pbeg; q0 < pend; q0 += 32) {
+    bf16x4 av[2], bv[2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int p = q0 + kq + j;
+    for (int j = 0; j < 8; ++j) {
+      const int p = q0 + k8 + j;
       short aj = 0, bj = 0;
       if (p < pend) {
         if (co_r < g.Cout) aj = (short)dz16[(size_t)p * g.CoutP + co_r];
@@ -243,10 +279,10 @@ __global__ __launch_bounds__(kNetBlock) void k_conv_bwd_weight(ConvGeom g, const
           if (tap_src(g, yo, xo, tap, yi, xi)) bj = (short)in[(((size_t)b * g.Hin + yi) * g.Win + xi) * g.Cin + ci];
         }
       }
-      av[j] = aj;
-      bv[j] = bj;
+      av[j >> 2][j & 3] = aj;
+      bv[j >> 2][j & 3] = bj;
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    acc = mfma_k32(av[0], av[1], bv[0], bv[1], acc);
   }
   // D[co = 16 ct + kq + i][k = kcol]
 #pragma unroll

@@ -9,8 +9,11 @@ solution are extracted by the library (smg_net_features / smg_net_targets).
 Training: mean squared error of the per-channel standardized fields over the
 interior nodes, Adam, mini-batches, every step in smg_net_train_step.
 Evaluation: for held-out seeds, V-cycles and wall time to 1e-8 from the zero
-start and from the lifted prediction x0 (smg_net_lift); x0 is used only when
-||f - S x0|| <= ||f||, the residual of the zero start (fallback otherwise).
+start and from the lifted prediction x0 (smg_net_lift), inference at batch 1.
+The zero start judges the warm start after one V-cycle: the warm solve goes on
+from V(x0) when ||f - S V(x0)|| <= rho0 ||f||, where rho0 is the relative
+residual one V-cycle from zero leaves (the median over the training solves);
+otherwise it falls back to the zero-start solve (the judging cycle is counted).
 """
 from __future__ import annotations
 
@@ -68,9 +71,10 @@ def solve_time(inst, x, rtol=1e-8, maxit=100):
     return 1e3 * (time.perf_counter() - t0), st, rc
 
 
-def make_dataset(seeds, n=127, N=128, device="cuda", log=None):
+def make_dataset(seeds, n=127, N=128, device="cuda", log=None, first_cycle=None):
     """Solve every seed to 1e-8 and return (features, raw targets) as device tensors
-    (S, H, H, 4) and (S, H, H, 3) (targets not yet standardized)."""
+    (S, H, H, 4) and (S, H, H, 3) (targets not yet standardized).  first_cycle (a
+    list) receives each solve's relative residual after its first V-cycle."""
     import torch
     H = grid_for(n)
     S = len(seeds)
@@ -81,9 +85,12 @@ def make_dataset(seeds, n=127, N=128, device="cuda", log=None):
     for i, s in enumerate(seeds):
         inst = Instance(s, n, N, device)
         x = torch.zeros(inst.dof, dtype=torch.float64, device=device)
-        rc, st = inst.ctx.solve(x, inst.f, binding.SMG_VCYCLE, rtol=1e-8, maxit=100, history=0)
+        rc, st = inst.ctx.solve(x, inst.f, binding.SMG_VCYCLE, rtol=1e-8, maxit=100,
+                                history=4 if first_cycle is not None else 0)
         if rc != binding.SMG_OK:
             raise RuntimeError(f"training solve {s} did not converge: {st}")
+        if first_cycle is not None:
+            first_cycle.append(st["history"][1] / st["history"][0])
         binding.net_features(inst.ctx, inst.f, H, feats[i])
         binding.net_targets(inst.ctx, x, H, ident, raw[i])
         # third field as N mean(p) / nu: the control row (f_U = 0, G = nu h^2 I,
@@ -161,12 +168,19 @@ def predict(net, feats):
     return out
 
 
-def evaluate(net, seeds, norm, n=127, N=128, device="cuda", rtol=1e-8):
-    """Warm start against zero start on held-out seeds.  Returns per-seed records."""
+def evaluate(net, seeds, norm, n=127, N=128, device="cuda", rtol=1e-8, rho0=None):
+    """Warm start against zero start on held-out seeds, inference at batch 1 (a
+    batch-1 copy of the trained network).  rho0: the zero start's relative
+    residual after one V-cycle (median over the training solves; None: judge by
+    ||f - S x0|| <= ||f|| before any cycle).  Returns per-seed records."""
     import torch
     H = grid_for(n)
-    feat = torch.zeros((net.B, H, H, 4), dtype=torch.float32, device=device)
-    pred = torch.empty((net.B, H, H, 3), dtype=torch.float32, device=device)
+    net1 = binding.Net(1, H, device=device)
+    theta = torch.empty(net.np, dtype=torch.float32, device=device)
+    net.get_params(theta)
+    net1.set_params(theta)
+    feat = torch.zeros((1, H, H, 4), dtype=torch.float32, device=device)
+    pred = torch.empty((1, H, H, 3), dtype=torch.float32, device=device)
     recs = []
     truth = torch.empty((H, H, 3), dtype=torch.float32, device=device)
     ident = [0.0, 0.0, 0.0, 1.0, 1.0, 1.0]
@@ -182,42 +196,53 @@ def evaluate(net, seeds, norm, n=127, N=128, device="cuda", rtol=1e-8):
         truth[:, :, 2] *= N / inst.nu
         r = torch.empty_like(x)
         fnorm = float(torch.linalg.norm(inst.f))
-        # warm start: features -> network -> lift -> residual check -> solve
+        k = inst.nu / N                      # mean(p) = nu/N times the third field
+        lift_norm = norm[:2] + [norm[2] * k] + norm[3:5] + [norm[5] * k]
+        # warm start: features -> network -> lift -> one V-cycle -> judge -> solve
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        feat.zero_()
         binding.net_features(inst.ctx, inst.f, H, feat[0])
-        net.forward(feat, pred)
-        k = inst.nu / N                      # mean(p) = nu/N times the third field
-        binding.net_lift(inst.ctx, pred[0], H, norm[:2] + [norm[2] * k] + norm[3:5] + [norm[5] * k], x)
-        rn = inst.ctx.residual(x, inst.f, r, norms=True)
-        fell_back = not (rn[0] <= fnorm)
+        net1.forward(feat, pred)
+        binding.net_lift(inst.ctx, pred[0], H, lift_norm, x)
+        torch.cuda.synchronize()
         t_inf = 1e3 * (time.perf_counter() - t0)
+        rn0 = inst.ctx.residual(x, inst.f, r, norms=True)
+        if rho0 is None:
+            fell_back = not (rn0[0] <= fnorm)
+            judge_cycles = 0
+            rel1 = None
+        else:
+            inst.ctx.vcycle(x, inst.f, 1)
+            rn1 = inst.ctx.residual(x, inst.f, r, norms=True)
+            rel1 = rn1[0] / fnorm
+            fell_back = not (rel1 <= rho0)
+            judge_cycles = 1
+        if fell_back:
+            x.zero_()
+        rc, st = inst.ctx.solve(x, inst.f, binding.SMG_VCYCLE, rtol=rtol, maxit=100, history=0)
+        torch.cuda.synchronize()
+        t_warm = 1e3 * (time.perf_counter() - t0)
         got = pred[0, :n, :n] * std + mean
         ref = truth[:n, :n]
         err = [float((torch.linalg.norm(got[..., c] - ref[..., c]) / torch.linalg.norm(ref[..., c])).item())
                for c in range(3)]
         err_mean = [float((torch.linalg.norm(mean[c] - ref[..., c]) / torch.linalg.norm(ref[..., c])).item())
                     for c in range(3)]
-        # solve from the lifted x0 (what the warm start gives without the residual rule)
+        # the lifted x0 without any rule: cycles and time from x0 (inference included)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        t1 = time.perf_counter()
+        binding.net_lift(inst.ctx, pred[0], H, lift_norm, x)
         rc2, st2 = inst.ctx.solve(x, inst.f, binding.SMG_VCYCLE, rtol=rtol, maxit=100, history=0)
         torch.cuda.synchronize()
-        t_lifted = 1e3 * (time.perf_counter() - t0)
-        nofb = st2["iterations"]
-        # with the rule: the zero-start solve replaces it when x0's residual exceeds ||f||
-        if fell_back:
-            rc, st, t_solve = rc0, st0, t_zero
-        else:
-            rc, st, t_solve = rc2, st2, t_lifted
-        t_warm = t_inf + t_solve
+        t_lifted = 1e3 * (time.perf_counter() - t1)
         recs.append(dict(seed=s, nu=inst.nu, zero_cycles=st0["iterations"], zero_ms=t_zero,
-                         warm_cycles=st["iterations"], warm_ms=t_warm, fell_back=fell_back,
-                         warm_cycles_no_fallback=nofb, warm_ms_no_fallback=t_inf + t_lifted, inference_ms=t_inf,
-                         pred_rel_err=err, mean_pred_rel_err=err_mean,
-                         x0_relres=rn[0] / fnorm, converged=(rc == 0 and rc0 == 0 and rc2 == 0)))
+                         warm_cycles=st["iterations"] + judge_cycles, warm_ms=t_warm, fell_back=fell_back,
+                         warm_cycles_no_fallback=st2["iterations"], warm_ms_no_fallback=t_inf + t_lifted,
+                         inference_ms=t_inf, pred_rel_err=err, mean_pred_rel_err=err_mean,
+                         x0_relres=rn0[0] / fnorm, relres_after_one_cycle=rel1, rho0=rho0,
+                         converged=(rc == 0 and rc0 == 0 and rc2 == 0)))
         inst.ctx.close()
+    net1.close()
     return recs
 
 
@@ -235,6 +260,10 @@ def summarize(recs):
                 warm_start_mean_ms=float(wt.mean()),
                 fallback_rate=float(np.mean([r["fell_back"] for r in recs])),
                 median_x0_relres=float(np.median([r["x0_relres"] for r in recs])),
+                median_relres_after_one_warm_cycle=(float(np.median([r["relres_after_one_cycle"] for r in recs]))
+                                                    if recs and recs[0]["relres_after_one_cycle"] is not None
+                                                    else None),
+                rho0=recs[0]["rho0"] if recs else None,
                 pred_rel_err_u_ybar_q=[float(np.mean([r["pred_rel_err"][c] for r in recs])) for c in range(3)],
                 dataset_mean_rel_err_u_ybar_q=[float(np.mean([r["mean_pred_rel_err"][c] for r in recs]))
                                                for c in range(3)],

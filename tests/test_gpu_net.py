@@ -141,3 +141,37 @@ def test_warm_start_gain_small(B):
         assert r["fell_back"] == (r["x0_relres"] > 1.0)
         if r["fell_back"]:
             assert r["warm_cycles"] == r["zero_cycles"]
+
+
+def test_warm_start_on_the_learned_workload_judged_after_one_cycle(B):
+    """127x127, N = 128 (the learned workload's grid and samples), trained on 400
+    multigrid solves, 24 held-out seeds, the zero start judging the warm start
+    after one V-cycle (||f - S V(x0)|| against the median relative residual one
+    cycle from zero leaves on the training solves): the warm start is kept on
+    most seeds and, counting the judging cycle, needs fewer V-cycles than the
+    zero start; every solve converges.  Wall time (inference at batch 1
+    included) is reported, not asserted: the broadcast lift cannot carry the
+    per-sample part of the state, so the warm start saves well under one cycle
+    (the measured result is recorded with the benchmark)."""
+    import numpy as np
+    from paper_2302_13680_amd import learn
+    n, N = 127, 128
+    H = learn.grid_for(n)
+    first = []
+    feats, raw = learn.make_dataset(list(range(50000, 50400)), n=n, N=N, first_cycle=first)
+    rho0 = float(np.median(first))
+    norm = learn.standardization(raw, n)
+    tg = learn.standardize(raw, norm, n)
+    net = B.Net(16, H)
+    net.set_params(torch.tensor(learn.param_init(0), device="cuda"))
+    learn.train(net, feats, tg, n, epochs=12, lr=2e-3, seed=0)
+    recs = learn.evaluate(net, list(range(60000, 60024)), norm, n=n, N=N, rho0=rho0)
+    s = learn.summarize(recs)
+    print({k: s[k] for k in ("fallback_rate", "zero_start_mean_cycles", "warm_start_mean_cycles",
+                             "zero_start_mean_ms", "warm_start_mean_ms", "inference_mean_ms", "rho0",
+                             "median_relres_after_one_warm_cycle")}, flush=True)
+    assert s["all_converged"]
+    assert s["fallback_rate"] < 0.5, s
+    assert s["warm_start_mean_cycles"] < s["zero_start_mean_cycles"], s
+    for r in recs:
+        assert r["fell_back"] == (r["relres_after_one_cycle"] > rho0)
