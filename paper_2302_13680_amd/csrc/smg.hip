@@ -510,13 +510,12 @@ int resident_waves(const void* fn) {
   return cus * per * (kBlock / 64);
 }
 
-// One whole red+black sweep, xin -> xout (must not alias); src: kPlain,
-// kZero (xin taken as zero, not read) or kProlong (xin + P ec).
+// One whole red+black sweep, xin -> xout (must not alias); src: kPlain or
+// kZero (xin taken as zero, not read).
 template <typename T>
-int sweep_one_launch(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const T* f, int src,
-                     const T* ec = nullptr) {
+int sweep_one_launch(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const T* f, int src) {
   const LevelArgs<T> a = args(L, C->N, C->desc.strip);
-  const SweepPtrs<T> P{xin, xout, f, ec};
+  const SweepPtrs<T> P{xin, xout, f};
   const int npair = (L.n + 1) / 2, npg = (npair + kBlock / 64 - 1) / (kBlock / 64);
   bool launched = false;
   lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
@@ -530,7 +529,6 @@ int sweep_one_launch(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const
         hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, C->stream, a, P, rows);
       };
       if (src == kZero) go(k_sweep_fused<T, JM, VW, kZero>);
-      else if (src == kProlong) go(k_sweep_fused<T, JM, VW, kProlong>);
       else go(k_sweep_fused<T, JM, VW, kPlain>);
       launched = true;
     }
@@ -543,9 +541,33 @@ int sweep_one_launch(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const
   return SMG_OK;
 }
 
+// x += P ec at the black nodes of level L (Y and P blocks), ahead of a
+// one-launch sweep (see k_prolong_black).
+template <typename T>
+int prolong_black(smg_ctx* C, const Level<T>& L, T* x, const T* ec) {
+  bool launched = false;
+  lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    constexpr int VW = halfsweep_vw(decltype(Vc)::value, JM);
+    if constexpr (W == 64 && JM <= 4) {
+      const int nblack = L.n * L.n / 2, nb = (nblack + kBlock / 64 - 1) / (kBlock / 64);
+      hipLaunchKernelGGL((k_prolong_black<T, JM, VW>), dim3(nb), dim3(kBlock), 0, C->stream, L.n, C->N, ec, x);
+      launched = true;
+    }
+  });
+  if (!launched) {
+    C->err = "black prolongation: layout without 64 lanes per node";
+    return SMG_EINVAL;
+  }
+  LAUNCH_CHECK();
+  return SMG_OK;
+}
+
 // count >= 1 sweeps of collective Gauss-Seidel on x (level L), the first with
-// neighbour source src: one launch per sweep between x and alt (an even number,
-// ending in x), an odd count starting with one sweep in place by half-sweeps.
+// neighbour source src (kProlong: x + P ec): one launch per sweep between x and
+// alt (an even number, ending in x), an odd count starting with one sweep in
+// place by half-sweeps; with kProlong and an even count the correction is added
+// at the black nodes first (the only old values a sweep reads).
 template <typename T>
 int sweeps_one_launch(smg_ctx* C, const Level<T>& L, T* x, T* alt, const T* f, int count, int src,
                       const T* ec) {
@@ -556,8 +578,12 @@ int sweeps_one_launch(smg_ctx* C, const Level<T>& L, T* x, T* alt, const T* f, i
     s = 1;
     src = kPlain;
   }
+  if (s < count && src == kProlong) {   // the correction at the blacks, then plain sweeps
+    TRY(prolong_black<T>(C, L, x, ec));
+    src = kPlain;
+  }
   for (; s < count; s += 2, src = kPlain) {
-    TRY(sweep_one_launch<T>(C, L, x, alt, f, src, ec));
+    TRY(sweep_one_launch<T>(C, L, x, alt, f, src));
     TRY(sweep_one_launch<T>(C, L, alt, x, f, kPlain));
   }
   return SMG_OK;
@@ -847,16 +873,6 @@ int coarse_solve(smg_ctx* C, const TV* F, TV* X) {
   return SMG_OK;
 }
 
-// Alg. 1 on level l (Levels Ls of type T), x and f of that level; x_zero: x
-// holds (or is to be taken as) zero on entry.
-//
-// With theta = 1 the launch sequence is fused without changing the iteration:
-//  - from a zero guess the first red half-sweep reads no neighbours (kZero) and
-//    no zero fill is written;
-//  - the coarse correction x += P e_c is folded into the first post-smoothing red
-//    half-sweep (kProlong): red nodes read their black neighbours corrected on
-//    the fly, and the black half-sweep that follows overwrites every black node.
-// For any theta the residual is restricted in the same pass that forms it.
 // count damped collective Jacobi steps on x, alternating between x and the
 // scratch t (an odd count ends with a copy back).
 template <typename T>
@@ -890,6 +906,17 @@ int vcycle_level_jacobi(smg_ctx* C, Level<T>* Ls, T* t, int l, T* x, const T* f,
   return jacobi_steps<T>(C, L, x, t, f, C->desc.post);
 }
 
+// Alg. 1 on level l (Levels Ls of type T), x and f of that level; x_zero: x
+// holds (or is to be taken as) zero on entry.
+//
+// With theta = 1 the launch sequence is fused without changing the iteration:
+//  - from a zero guess the first red half-sweep reads no neighbours (kZero) and
+//    no zero fill is written;
+//  - the coarse correction x += P e_c is folded into the first post-smoothing red
+//    half-sweep (kProlong): red nodes read their black neighbours corrected on
+//    the fly, and the black half-sweep that follows overwrites every black node;
+//    on levels swept in one launch per sweep it is added at the black nodes only.
+// For any theta the residual is restricted in the same pass that forms it.
 template <typename T>
 int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f, bool x_zero) {
   if (C->desc.flags & SMG_FLAG_JACOBI) return vcycle_level_jacobi<T>(C, Ls, r, l, x, f, x_zero);

@@ -14,11 +14,14 @@
 //      pair) and the halo red of step s - 1.
 // Reds read their black neighbours from xin (the values before the sweep), so
 // the result is the red half-sweep followed by the black half-sweep, node for
-// node the arithmetic of halfsweep_node (smoother.h), the coarse correction
-// folded into the first post-smoothing sweep as there (the reds add the
-// interpolated correction of their black neighbours; an interpolation at load
-// time, carried with the black values, needed more registers than the wave
-// has and spilled: 1.78 against 1.07 ms per sweep at 511x511, N=256).  Faces, black values and
+// node the arithmetic of halfsweep_node (smoother.h).  The coarse correction
+// ahead of post-smoothing is a separate pass over the black nodes only
+// (k_prolong_black below; the reds never read the old red values): folded into
+// the sweep as in the half-sweeps, the reds' interpolation of their four black
+// neighbours re-read the coarse vector and cost 1.79 ms per sweep at 511x511,
+// N=256 FP64 against 0.90 ms for a plain sweep; the black pass plus a plain
+// sweep take about 1.2 ms, and 11 FP64 V-cycles to 1e-8 went from 90.4 to
+// 83.0 ms.  Faces, black values and
 // right-hand sides that two solves of the same wave need are kept in registers
 // between steps; what a wave shares with its neighbour pair is read by both
 // from memory at about the same time (neighbouring pairs run in the same
@@ -75,7 +78,6 @@ struct SweepPtrs {
   const T* __restrict__ xin;   // iterate before the sweep (unused with kZero)
   T* __restrict__ xout;        // iterate after the sweep
   const T* __restrict__ f;
-  const T* __restrict__ ec;    // coarse correction (kProlong)
 };
 
 // The node solve of eq. solution_reduced_system in two phases, arithmetic as
@@ -83,9 +85,8 @@ struct SweepPtrs {
 // b_P, b_Y, 1/a_j and this lane's part of the sum over samples from the faces,
 // the neighbour values (missing ones discarded by the boundary selects) and the
 // node's f; finish completes the sum over the 64 lanes and the update.  Two
-// independent nodes can then share the latency of their sums.  SRC: kPlain,
-// kZero (no neighbour terms), kProlong (neighbours plus the interpolated
-// correction, read from the coarse vector here).  cde: c_j, d_j, e_j in LDS.
+// independent nodes can then share the latency of their sums.  SRC: kPlain or
+// kZero (no neighbour terms).  cde: c_j, d_j, e_j in LDS.
 template <typename T, int JM>
 struct NodePrep {
   T bP[JM], bY[JM], ia[JM], cq[JM], eq[JM];
@@ -93,7 +94,7 @@ struct NodePrep {
 };
 
 template <typename T, int JM, int VW, int SRC>
-__device__ __forceinline__ void prep_node(const LevelArgs<T>& L, const SweepPtrs<T>& P, const T* cde, int xx,
+__device__ __forceinline__ void prep_node(const LevelArgs<T>& L, const T* cde, int xx,
                                           int k, int lane, const T (&kw)[JM], const T (&ke)[JM],
                                           const T (&ks)[JM], const T (&kn)[JM], const NodeYP<T, JM>& w,
                                           const NodeYP<T, JM>& e, const NodeYP<T, JM>& s,
@@ -101,9 +102,8 @@ __device__ __forceinline__ void prep_node(const LevelArgs<T>& L, const SweepPtrs
                                           NodePrep<T, JM>& o) {
   constexpr int NCH = JM / VW;
   const int n = L.n, N = L.N;
+  static_assert(SRC == kPlain || SRC == kZero, "one-launch sweep: plain or zero-start neighbours");
   const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
-  const int nc = (n - 1) / 2;
-  const size_t nnc = (size_t)nc * nc;
   o.num = T(0);
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
@@ -114,11 +114,6 @@ __device__ __forceinline__ void prep_node(const LevelArgs<T>& L, const SweepPtrs
     ldv<VW>(cde + j, cj);
     ldv<VW>(cde + N + j, dj);
     ldv<VW>(cde + 2 * N + j, ej);
-    T cwy[VW], cey[VW], csy[VW], cny[VW], cwp[VW], cep[VW], csp[VW], cnp[VW];
-    if constexpr (SRC == kProlong) {
-      prolong_nb<VW>(P.ec, nc, N, j, xx, k, cwy, cey, csy, cny);
-      prolong_nb<VW>(P.ec + (size_t)(N + 1) * nnc, nc, N, j, xx, k, cwp, cep, csp, cnp);
-    }
 #pragma unroll
     for (int u = 0; u < VW; ++u) {
       const int q = c * VW + u;
@@ -130,10 +125,6 @@ __device__ __forceinline__ void prep_node(const LevelArgs<T>& L, const SweepPtrs
       if constexpr (SRC != kZero) {
         sy = nbsum(w.y[q], e.y[q], s.y[q], nb.y[q]);
         sp = nbsum(w.p[q], e.p[q], s.p[q], nb.p[q]);
-      }
-      if constexpr (SRC == kProlong) {
-        sy += nbsum(cwy[u], cey[u], csy[u], cny[u]);
-        sp += nbsum(cwp[u], cep[u], csp[u], cnp[u]);
       }
       const T a = (kw[q] + ke[q]) + (ks[q] + kn[q]);
       const T ai = T(1) / a;
@@ -170,6 +161,50 @@ __device__ __forceinline__ void st_ypu(T* __restrict__ v, size_t nn, int N, size
   stn<T, JM, VW>(v + node * N, N, lane, o.y);
   stn<T, JM, VW>(v + (size_t)(N + 1) * nn + node * N, N, lane, o.p);
   if (lane == 0) v[(size_t)N * nn + node] = u;
+}
+
+// x += P e_c at the black nodes (x + k odd) only, Y and P blocks: the coarse
+// correction of Alg. 1 ahead of a one-launch post-smoothing sweep.  The sweep's
+// reds read only black neighbours, its blacks only the new reds, and no solve
+// reads a node's own old value or any u, so the red values and U block of x
+// after the correction are never used.  A black node lies on a coarse edge:
+// (P e)(x, k) is the mean of the two coarse nodes at its ends (zero outside the
+// coarse grid).  One wave per black node, 64 lanes, JM samples per lane.
+template <typename T, int JM, int VW>
+__global__ __launch_bounds__(kBlock) void k_prolong_black(int n, int N, const T* __restrict__ ec,
+                                                          T* __restrict__ x) {
+  constexpr int kWaves = kBlock / 64;
+  const int nc = (n - 1) / 2;
+  const size_t nn = (size_t)n * n, nnc = (size_t)nc * nc;
+  const int nblack = (int)(nn / 2), nb = (nblack + kWaves - 1) / kWaves;
+  const int slot = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, nb) * kWaves + (int)threadIdx.x / 64);
+  const int lane = threadIdx.x & 63;
+  if (slot >= nblack) return;
+  // rows 2m and 2m+1 hold n blacks: (n-1)/2 at odd x in row 2m, (n+1)/2 at even x in row 2m+1
+  const int m = slot / n, rem = slot - m * n, h = (n - 1) / 2;
+  const bool krow_even = rem < h;
+  const int k = krow_even ? 2 * m : 2 * m + 1, xx = krow_even ? 2 * rem + 1 : 2 * (rem - h);
+  // the two coarse ends: along the row (x even, k odd) or along the column (x odd, k even)
+  int X0, K0, X1, K1;
+  if (krow_even) { X0 = X1 = (xx - 1) / 2; K0 = k / 2 - 1; K1 = k / 2; }
+  else { K0 = K1 = (k - 1) / 2; X0 = xx / 2 - 1; X1 = xx / 2; }
+  const bool in0 = X0 >= 0 && K0 >= 0, in1 = X1 < nc && K1 < nc;
+  const size_t c0 = in0 ? (size_t)K0 * nc + X0 : 0, c1 = in1 ? (size_t)K1 * nc + X1 : 0;
+  const size_t node = (size_t)k * n + xx;
+  T ey0[JM], ey1[JM], ep0[JM], ep1[JM], y[JM], p[JM];
+  ldn<T, JM, VW>(ec + c0 * N, N, lane, ey0);
+  ldn<T, JM, VW>(ec + c1 * N, N, lane, ey1);
+  ldn<T, JM, VW>(ec + (size_t)(N + 1) * nnc + c0 * N, N, lane, ep0);
+  ldn<T, JM, VW>(ec + (size_t)(N + 1) * nnc + c1 * N, N, lane, ep1);
+  ldn<T, JM, VW>(x + node * N, N, lane, y);
+  ldn<T, JM, VW>(x + (size_t)(N + 1) * nn + node * N, N, lane, p);
+#pragma unroll
+  for (int q = 0; q < JM; ++q) {
+    y[q] += T(0.5) * ((in0 ? ey0[q] : T(0)) + (in1 ? ey1[q] : T(0)));
+    p[q] += T(0.5) * ((in0 ? ep0[q] : T(0)) + (in1 ? ep1[q] : T(0)));
+  }
+  stn<T, JM, VW>(x + node * N, N, lane, y);
+  stn<T, JM, VW>(x + (size_t)(N + 1) * nn + node * N, N, lane, p);
 }
 
 // Pair-walking waves: kBlock / 64 consecutive pairs of one row segment per
@@ -271,11 +306,11 @@ void k_sweep_fused(LevelArgs<T> L, SweepPtrs<T> P, int seg_rows) {
     // ---- 1+2. halo red (xh, s) and own red (xr, s), their sums together
     NodePrep<T, JM> ph, pr;
     if (odd) {
-      prep_node<T, JM, VW, SRC>(L, P, cde, xh, s, lane, Fh, F0, ksh, knh, vo, obIn, vs, vn, fyh, fph, ph);
-      prep_node<T, JM, VW, SRC>(L, P, cde, xr, s, lane, F1, F2, kys0, kyn0, obIn, vq, obS, obN, fyr, fpr, pr);
+      prep_node<T, JM, VW, SRC>(L, cde, xh, s, lane, Fh, F0, ksh, knh, vo, obIn, vs, vn, fyh, fph, ph);
+      prep_node<T, JM, VW, SRC>(L, cde, xr, s, lane, F1, F2, kys0, kyn0, obIn, vq, obS, obN, fyr, fpr, pr);
     } else {
-      prep_node<T, JM, VW, SRC>(L, P, cde, xh, s, lane, F2, Fh, ksh, knh, obIn, vo, vs, vn, fyh, fph, ph);
-      prep_node<T, JM, VW, SRC>(L, P, cde, xr, s, lane, F0, F1, kys0, kyn0, vq, obIn, obS, obN, fyr, fpr, pr);
+      prep_node<T, JM, VW, SRC>(L, cde, xh, s, lane, F2, Fh, ksh, knh, obIn, vo, vs, vn, fyh, fph, ph);
+      prep_node<T, JM, VW, SRC>(L, cde, xr, s, lane, F0, F1, kys0, kyn0, vq, obIn, obS, obN, fyr, fpr, pr);
     }
 #pragma unroll
     for (int q = 0; q < JM; ++q) asm volatile("" ::"v"(ph.eq[q]), "v"(pr.eq[q]));
@@ -294,10 +329,10 @@ void k_sweep_fused(LevelArgs<T> L, SweepPtrs<T> P, int seg_rows) {
     if (blk) {
       NodePrep<T, JM> pb;
       if (odd)
-        prep_node<T, JM, VW, kPlain>(L, P, cde, xr, s - 1, lane, kxin1, kxh1, kyn2, kys0, R1, H1, R2, R0, fyb, fpb,
+        prep_node<T, JM, VW, kPlain>(L, cde, xr, s - 1, lane, kxin1, kxh1, kyn2, kys0, R1, H1, R2, R0, fyb, fpb,
                                      pb);
       else
-        prep_node<T, JM, VW, kPlain>(L, P, cde, xr, s - 1, lane, kxh1, kxin1, kyn2, kys0, H1, R1, R2, R0, fyb, fpb,
+        prep_node<T, JM, VW, kPlain>(L, cde, xr, s - 1, lane, kxh1, kxin1, kyn2, kys0, H1, R1, R2, R0, fyb, fpb,
                                      pb);
 #pragma unroll
       for (int q = 0; q < JM; ++q) asm volatile("" ::"v"(pb.eq[q]));
