@@ -83,7 +83,8 @@ def time_halfsweep(ctx, x, f, stream, launches, fp32=False):
 
 def halfsweep_counter_run(ctx, x, f, n, N):
     """20 finest-level sweeps (one launch each where the level takes the
-    one-launch sweep, else 40 half-sweeps), then five 1 GiB device copies (the
+    one-launch sweep, else 40 half-sweeps), finest-level residuals and
+    residual + restrictions, 2 V-cycles, then five 1 GiB device copies (the
     calibration of the traffic counters)."""
     import torch
     xb = torch.empty_like(x)
@@ -94,6 +95,16 @@ def halfsweep_counter_run(ctx, x, f, n, N):
         else:
             ctx.smooth(0, 0, x, f)
             ctx.smooth(0, 1, x, f)
+    # the other finest-level passes of a cycle: 5 operator residuals (r written,
+    # norms), 5 fused residual + restrictions, then 2 V-cycles (zero-start and
+    # plain sweeps, the black-node prolongation, every coarser level)
+    r = torch.empty_like(x)
+    coarse = torch.empty(ctx.vlen(1), dtype=torch.float64, device=x.device)
+    for _ in range(5):
+        ctx.residual(x, f, r, norms=True)
+    for _ in range(5):
+        ctx.residual_restrict(0, x, f, coarse)
+    ctx.vcycle(x, f, 2)
     a = torch.ones(1 << 27, dtype=torch.float64, device=x.device)   # 1 GiB
     b = torch.empty_like(a)
     for _ in range(5):
@@ -653,7 +664,7 @@ def roofline_sweep(ctx, f, n, N, dev, launches, traffic_kind):
     one = ctx.sweep(0, xa, xb, f)
     if one:
         us = time_sweep(ctx, xa, xb, f, ctx.stream, launches)
-        algo, kernel = sweep_bytes(n, N, 8), "k_sweep_fused<double,4,1,kPlain> finest level (red+black sweep)"
+        algo, kernel = sweep_bytes(n, N, 8), "k_sweep_fused<double,4,2,kPlain> finest level (red+black sweep)"
     else:
         us = time_halfsweep(ctx, xa, f, ctx.stream, launches)
         algo, kernel = sweep_bytes(n, N, 8) / 2, "k_halfsweep<double,64,4> finest level"

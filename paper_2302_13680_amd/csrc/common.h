@@ -113,13 +113,18 @@ __device__ __forceinline__ int group_slot(int b) {
 }
 
 // VW consecutive samples as one access (VW = 2: an 8-byte float2 or a 16-byte
-// double2; the address is a multiple of VW elements from a 256-byte aligned base).
+// double2; VW = 4: a 16-byte float4; the address is a multiple of VW elements
+// from a 256-byte aligned base).
 template <int VW, typename T>
 __device__ __forceinline__ void ldv(const T* __restrict__ p, T (&v)[VW]) {
   if constexpr (VW == 1) {
     v[0] = *p;
+  } else if constexpr (VW == 4) {
+    static_assert(std::is_same<T, float>::value, "four samples per access: FP32 only");
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
   } else {
-    static_assert(VW == 2, "one or two samples per access");
+    static_assert(VW == 2, "one, two or four samples per access");
     using V2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
     const V2 t = *reinterpret_cast<const V2*>(p);
     v[0] = t.x;
@@ -130,6 +135,9 @@ template <int VW, typename T>
 __device__ __forceinline__ void stv(T* __restrict__ p, const T (&v)[VW]) {
   if constexpr (VW == 1) {
     *p = v[0];
+  } else if constexpr (VW == 4) {
+    static_assert(std::is_same<T, float>::value, "four samples per access: FP32 only");
+    *reinterpret_cast<float4*>(p) = float4{v[0], v[1], v[2], v[3]};
   } else {
     using V2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
     V2 t;
@@ -137,6 +145,14 @@ __device__ __forceinline__ void stv(T* __restrict__ p, const T (&v)[VW]) {
     t.y = v[1];
     *reinterpret_cast<V2*>(p) = t;
   }
+}
+
+// stv with the nontemporal hint, for level vectors no cache will hold until
+// they are read again (one access per element: 4- or 8-byte stores).
+template <int VW, typename T>
+__device__ __forceinline__ void stv_nt(T* __restrict__ p, const T (&v)[VW]) {
+#pragma unroll
+  for (int u = 0; u < VW; ++u) __builtin_nontemporal_store(v[u], p + u);
 }
 
 // Move a value between lanes of a row of 16 lanes with DPP (CTRL: 0xB1 = xor 1

@@ -89,8 +89,8 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
       }
     }
     if (act && out) {
-      stv<VW>(out + base, ry);
-      stv<VW>(out + (size_t)(N + 1) * nn + base, rp);
+      stv_nt<VW>(out + base, ry);
+      stv_nt<VW>(out + (size_t)(N + 1) * nn + base, rp);
     }
   }
   dsum = group_sum_w(dsum, W);

@@ -510,6 +510,26 @@ int resident_waves(const void* fn) {
   return cus * per * (kBlock / 64);
 }
 
+// Samples per access of the one-launch sweep and the black prolongation: FP32
+// as the half-sweeps take them (vw); FP64 two samples (one 16-byte access)
+// wherever N is even and a lane holds two or more samples.  On 511x511,
+// N = 256, 16-byte accesses took the FP64 operator residual from 937 to 742 us.
+template <typename T, int JM, typename F>
+void sweep_vw_dispatch(int vw, int N, F&& fn) {
+  if constexpr (std::is_same<T, double>::value && JM >= 2 && JM % 2 == 0) {
+    if (N % 2 == 0) { fn(IC<2>{}); return; }
+    fn(IC<1>{});
+  } else {
+    if constexpr (JM == 4) {
+      if (N % 4 == 0) { fn(IC<4>{}); return; }
+    }
+    if constexpr (JM % 2 == 0) {
+      if (vw == 2) { fn(IC<2>{}); return; }
+    }
+    fn(IC<1>{});
+  }
+}
+
 // One whole red+black sweep, xin -> xout (must not alias); src: kPlain or
 // kZero (xin taken as zero, not read).
 template <typename T>
@@ -520,16 +540,18 @@ int sweep_one_launch(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const
   bool launched = false;
   lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
-    constexpr int VW = halfsweep_vw(decltype(Vc)::value, JM);
     if constexpr (W == 64 && JM <= 4) {
-      auto go = [&](auto kern) {
-        static const int resident = resident_waves(reinterpret_cast<const void*>(kern));
-        const int rows = sweep_rows_for(L.n, C->desc.sweep_rows, resident);
-        const int nb = npg * ((L.n + rows - 1) / rows);
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, C->stream, a, P, rows);
-      };
-      if (src == kZero) go(k_sweep_fused<T, JM, VW, kZero>);
-      else go(k_sweep_fused<T, JM, VW, kPlain>);
+      sweep_vw_dispatch<T, JM>(halfsweep_vw(decltype(Vc)::value, JM), C->N, [&](auto Vk) {
+        constexpr int VW = decltype(Vk)::value;
+        auto go = [&](auto kern) {
+          static const int resident = resident_waves(reinterpret_cast<const void*>(kern));
+          const int rows = sweep_rows_for(L.n, C->desc.sweep_rows, resident);
+          const int nb = npg * ((L.n + rows - 1) / rows);
+          hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, C->stream, a, P, rows);
+        };
+        if (src == kZero) go(k_sweep_fused<T, JM, VW, kZero>);
+        else go(k_sweep_fused<T, JM, VW, kPlain>);
+      });
       launched = true;
     }
   });
@@ -548,10 +570,12 @@ int prolong_black(smg_ctx* C, const Level<T>& L, T* x, const T* ec) {
   bool launched = false;
   lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
-    constexpr int VW = halfsweep_vw(decltype(Vc)::value, JM);
     if constexpr (W == 64 && JM <= 4) {
       const int nblack = L.n * L.n / 2, nb = (nblack + kBlock / 64 - 1) / (kBlock / 64);
-      hipLaunchKernelGGL((k_prolong_black<T, JM, VW>), dim3(nb), dim3(kBlock), 0, C->stream, L.n, C->N, ec, x);
+      sweep_vw_dispatch<T, JM>(halfsweep_vw(decltype(Vc)::value, JM), C->N, [&](auto Vk) {
+        hipLaunchKernelGGL((k_prolong_black<T, JM, decltype(Vk)::value>), dim3(nb), dim3(kBlock), 0, C->stream, L.n,
+                           C->N, ec, x);
+      });
       launched = true;
     }
   });
@@ -732,6 +756,14 @@ int residual_into(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* o
     const int per = kBlock / W;
     const int nb = (int)((nn + per - 1) / per);
     mask_dispatch(C->masked, [&](auto Mc) {
+      // FP64 with an even N of 128..512: 16-byte accesses (two samples per lane and access)
+      if constexpr (std::is_same<TX, double>::value && W == 64 && VW == 1 && JM >= 2 && JM <= 8) {
+        if (C->N % 2 == 0 && C->N > 64 * (JM - 1)) {
+          hipLaunchKernelGGL((k_residual<T, TX, TO, 64, (JM + 1) / 2 * 2, 2, decltype(Mc)::value>), dim3(nb),
+                             dim3(kBlock), 0, C->stream, args(L, C->N, C->desc.strip), x, f, out, mode, partials);
+          return;
+        }
+      }
       hipLaunchKernelGGL((k_residual<T, TX, TO, W, JM, VW, decltype(Mc)::value>), dim3(nb), dim3(kBlock), 0,
                          C->stream, args(L, C->N, C->desc.strip), x, f, out, mode, partials);
     });

@@ -57,7 +57,7 @@ __device__ __forceinline__ void stn(T* __restrict__ p, int N, int lane, const T 
       T t[VW];
 #pragma unroll
       for (int u = 0; u < VW; ++u) t[u] = v[c * VW + u];
-      stv<VW>(p + j0, t);
+      stv_nt<VW>(p + j0, t);
     }
   }
 }
