@@ -112,11 +112,13 @@ __device__ __forceinline__ void residual_node(const LevelArgs<T>& L, const TX* _
 // of W lanes for one node; the neighbours' x + d are formed on the fly with the
 // same FP64 addition their own groups store, so no group reads x_next.  acc as
 // in residual_node.  x_next must not alias x.
-template <int JM, bool MK = true>
+template <int JM, int VW = 1, bool MK = true>
 __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, const double* __restrict__ x,
                                                   const float* __restrict__ d, double* __restrict__ xn,
                                                   const double* __restrict__ f, float* __restrict__ out,
                                                   int slot, int lane, int W, double (&acc)[4]) {
+  static_assert(JM % VW == 0, "whole chunks per lane");
+  constexpr int NCH = JM / VW;
   const int n = L.n, N = L.N;
   const size_t nn = (size_t)n * n, rowN = (size_t)n * N;
   int xx, k;
@@ -130,36 +132,61 @@ __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, co
   const bool hw = xx > 0, he = xx < n - 1, hs = k > 0, hn = k < n - 1;
   const ptrdiff_t ow = hw ? -(ptrdiff_t)N : 0, oe = he ? (ptrdiff_t)N : 0;
   const ptrdiff_t os = hs ? -(ptrdiff_t)rowN : 0, on = hn ? (ptrdiff_t)rowN : 0;
-  auto yv = [&](size_t i) { return x[i] + (double)d[i]; };
-  auto pv = [&](size_t i) { return x[oP + i] + (double)d[oP + i]; };
+  // x + d of VW samples at element offset i of the Y (o = 0) or P (o = oP) block
+  auto xd = [&](size_t i, double (&v)[VW]) {
+    double xv[VW];
+    float dv[VW];
+    ldv<VW>(x + i, xv);
+    ldv<VW>(d + i, dv);
+#pragma unroll
+    for (int q = 0; q < VW; ++q) v[q] = xv[q] + (double)dv[q];
+  };
   double dsum = 0;
 #pragma unroll
-  for (int q = 0; q < JM; ++q) {
-    const int j0 = lane + q * W;
+  for (int c = 0; c < NCH; ++c) {
+    const int j0 = VW * (lane + c * W);
     const bool act = j0 < N;
-    const int j = act ? j0 : N - 1;
-    const double kw = L.kx[kxb + j], ke = L.kx[kxb + N + j];
-    const double ks = L.ky[kyb + j], kn = L.ky[kyb + rowN + j];
+    const int j = act ? j0 : N - VW;
+    double kw[VW], ke[VW], ks[VW], kn[VW], cj[VW], dj[VW], ej[VW], fy[VW], fp[VW];
+    ldv<VW>(L.kx + kxb + j, kw);
+    ldv<VW>(L.kx + kxb + N + j, ke);
+    ldv<VW>(L.ky + kyb + j, ks);
+    ldv<VW>(L.ky + kyb + rowN + j, kn);
+    ldv<VW>(L.c + j, cj);
+    ldv<VW>(L.d + j, dj);
+    ldv<VW>(L.e + j, ej);
     const size_t base = node * N + j;
-    const double y0 = yv(base), p0 = pv(base);
-    auto nbsum = [&](double vw, double ve, double vs, double vn) {
-      return ((hw ? kw * vw : 0.0) + (he ? ke * ve : 0.0)) + ((hs ? ks * vs : 0.0) + (hn ? kn * vn : 0.0));
-    };
-    const double sy = nbsum(yv(base + ow), yv(base + oe), yv(base + os), yv(base + on));
-    const double sp = nbsum(pv(base + ow), pv(base + oe), pv(base + os), pv(base + on));
-    const double a = (kw + ke) + (ks + kn);
-    const double fy = f[base], fp = f[oP + base];
-    const double rY = node_live(mf) ? fy - (L.c[j] * y0 + (a * p0 - sp)) : 0.0;   // zero rows outside
-    const double rP = node_live(mf) ? fp - ((a * y0 - sy) + (mf.e * L.e[j]) * u) : 0.0;
-    dsum += act ? (mf.d * L.d[j]) * p0 : 0.0;
+    double y0[VW], p0[VW], yw[VW], ye[VW], ys[VW], yn[VW], pw[VW], pe[VW], ps[VW], pn[VW];
+    xd(base, y0); xd(oP + base, p0);
+    xd(base + ow, yw); xd(base + oe, ye); xd(base + os, ys); xd(base + on, yn);
+    xd(oP + base + ow, pw); xd(oP + base + oe, pe); xd(oP + base + os, ps); xd(oP + base + on, pn);
+    ldv<VW>(f + base, fy);
+    ldv<VW>(f + oP + base, fp);
+    float ry[VW], rp[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) {
+      auto nbsum = [&](double vw, double ve, double vs, double vn) {
+        return ((hw ? kw[q] * vw : 0.0) + (he ? ke[q] * ve : 0.0)) + ((hs ? ks[q] * vs : 0.0) + (hn ? kn[q] * vn : 0.0));
+      };
+      const double sy = nbsum(yw[q], ye[q], ys[q], yn[q]);
+      const double sp = nbsum(pw[q], pe[q], ps[q], pn[q]);
+      const double a = (kw[q] + ke[q]) + (ks[q] + kn[q]);
+      const double rY = node_live(mf) ? fy[q] - (cj[q] * y0[q] + (a * p0[q] - sp)) : 0.0;   // zero rows outside
+      const double rP = node_live(mf) ? fp[q] - ((a * y0[q] - sy) + (mf.e * ej[q]) * u) : 0.0;
+      dsum += act ? (mf.d * dj[q]) * p0[q] : 0.0;
+      ry[q] = (float)rY;
+      rp[q] = (float)rP;
+      if (act) {
+        acc[0] += rY * rY;
+        acc[2] += rP * rP;
+        acc[3] += fy[q] * fy[q] + fp[q] * fp[q];
+      }
+    }
     if (act) {
-      xn[base] = y0;
-      xn[oP + base] = p0;
-      out[base] = (float)rY;
-      out[oP + base] = (float)rP;
-      acc[0] += rY * rY;
-      acc[2] += rP * rP;
-      acc[3] += fy * fy + fp * fp;
+      stv_nt<VW>(xn + base, y0);
+      stv_nt<VW>(xn + oP + base, p0);
+      stv_nt<VW>(out + base, ry);
+      stv_nt<VW>(out + oP + base, rp);
     }
   }
   dsum = group_sum_w(dsum, W);
@@ -173,7 +200,7 @@ __device__ __forceinline__ void residual_add_node(const LevelArgs<double>& L, co
   }
 }
 
-template <int W, int JM, bool MK>
+template <int W, int JM, int VW, bool MK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, JM >= 4 ? 3 : 8)))
 void k_residual_add(LevelArgs<double> L, const double* __restrict__ x, const float* __restrict__ d,
                     double* __restrict__ xn, const double* __restrict__ f, float* __restrict__ out,
@@ -182,7 +209,7 @@ void k_residual_add(LevelArgs<double> L, const double* __restrict__ x, const flo
   const int lane = threadIdx.x & (W - 1);
   const int slot = group_slot<W>(b);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (slot < L.n * L.n) residual_add_node<JM, MK>(L, x, d, xn, f, out, slot, lane, W, acc);
+  if (slot < L.n * L.n) residual_add_node<JM, VW, MK>(L, x, d, xn, f, out, slot, lane, W, acc);
   block_sum<4>(acc);
   if (threadIdx.x == 0) {
 #pragma unroll

@@ -130,7 +130,9 @@ void lane_dispatch(int precision, int N, F&& fn) {
 // widths while one chunk of VW samples per lane covers N (up to 64 lanes), then
 // groups of 128 or 256 lanes (several waves) so that every lane still handles
 // one chunk: with all ~90 loads of a chunk in flight at once, a second chunk per
-// lane would need more registers than two waves per SIMD leave.
+// lane would need more registers than two waves per SIMD leave.  (FP64 in
+// 16-byte accesses, 128 lanes of two samples at N = 256, was slower at 511x511:
+// 1.20 against 1.01 ms for the finest level.)
 template <bool kVec2, typename F>
 void rr_dispatch(int precision, int N, F&& fn) {
   const bool v2 = kVec2 && vec2_ctx(precision, N);
@@ -756,9 +758,10 @@ int residual_into(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* o
     const int per = kBlock / W;
     const int nb = (int)((nn + per - 1) / per);
     mask_dispatch(C->masked, [&](auto Mc) {
-      // FP64 with an even N of 128..512: 16-byte accesses (two samples per lane and access)
-      if constexpr (std::is_same<TX, double>::value && W == 64 && VW == 1 && JM >= 2 && JM <= 8) {
-        if (C->N % 2 == 0 && C->N > 64 * (JM - 1)) {
+      // FP64 faces with an even N of 65..512: two samples per lane and access
+      // (16-byte FP64, 8-byte FP32 iterates)
+      if constexpr (std::is_same<T, double>::value && W == 64 && VW == 1 && JM >= 2 && JM <= 8) {
+        if (C->N % 2 == 0) {
           hipLaunchKernelGGL((k_residual<T, TX, TO, 64, (JM + 1) / 2 * 2, 2, decltype(Mc)::value>), dim3(nb),
                              dim3(kBlock), 0, C->stream, args(L, C->N, C->desc.strip), x, f, out, mode, partials);
           return;
@@ -796,7 +799,15 @@ int residual_add(smg_ctx* C, const double* x, const float* d, double* xn, const 
     const int per = kBlock / W;
     const int nb = (int)((nn + per - 1) / per);
     mask_dispatch(C->masked, [&](auto Mc) {
-      hipLaunchKernelGGL((k_residual_add<W, JM, decltype(Mc)::value>), dim3(nb), dim3(kBlock), 0, C->stream,
+      // two samples per access (16-byte FP64, 8-byte FP32) where N is even
+      if constexpr (W == 64 && JM % 2 == 0) {
+        if (C->N % 2 == 0) {
+          hipLaunchKernelGGL((k_residual_add<W, JM, 2, decltype(Mc)::value>), dim3(nb), dim3(kBlock), 0, C->stream,
+                             args(L, C->N, C->desc.strip), x, d, xn, f, out, C->partials);
+          return;
+        }
+      }
+      hipLaunchKernelGGL((k_residual_add<W, JM, 1, decltype(Mc)::value>), dim3(nb), dim3(kBlock), 0, C->stream,
                          args(L, C->N, C->desc.strip), x, d, xn, f, out, C->partials);
     });
     if (nb > kNormStageMin) {
