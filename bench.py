@@ -25,6 +25,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -775,11 +776,11 @@ def main():
                     help="run only the 511x511, N=256 mixed-precision section (for profiling)")
     ap.add_argument("--cvar-only", action="store_true",
                     help="run only the risk-averse solver at 705 nodes, N=2000, lambda 0.95 (for profiling)")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune_lanes.json"))
+    ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "smg_autotune_lanes.json"))
     ap.add_argument("--counters", nargs="?", const="medium", choices=["medium", "large"],
-                    help="launch only 20 finest-level FP64 sweeps of the 255x255, N=64 (medium) or "
-                         "511x511, N=256 (large) workload and a 1 GiB device copy (5x), for "
-                         "hardware-counter passes")
+                    help="launch only the finest-level FP64 passes of the 255x255, N=64 (medium) or "
+                         "511x511, N=256 (large) workload (20 sweeps, 5 residuals, 5 residual + "
+                         "restrictions, 2 V-cycles) and a 1 GiB device copy (5x), for hardware-counter passes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
