@@ -1,0 +1,183 @@
+// rrwalk.h -- the residual of a level restricted to the next coarser one, in
+// column walks (gfx950): coarse = R (f - S x), R = P^T full weighting.
+//
+// The per-coarse-node form (k_residual_restrict, transfer.h) loads the 5x5 fine
+// window of every coarse node; neighbouring windows overlap, so each fine value
+// is requested about five times and, at 511x511 with N = 256, 1.26x the
+// algorithmic bytes reach HBM.  Here a wavefront owns coarse column X, i.e. fine
+// columns 2X, 2X+1, 2X+2, over a segment of coarse rows, and walks the fine rows
+// upwards one at a time.  At fine row r it forms the Y and P residual rows of its
+// three fine nodes (eq. (2)'s block rows with the neighbours of the previous and
+// next rows), weights them across the columns by (1/2, 1, 1/2) into h(r), and
+// adds h(r) to the coarse row it belongs to: coarse row K gathers
+// h(2K)/2 + h(2K+1) + h(2K+2)/2.  The fine rows r-1 and r of its own columns, and
+// the S faces of row r, stay in registers from the previous step, so a step
+// loads the next row of x, the two side neighbours, the row's faces and
+// right-hand sides once.  The U row uses
+//   sum_f w_f r_U(f) = sum_f w_f (f_U(f) - g u(f)) - sum_j d_j sum_f w_f p_j(f),
+// one sum over samples per coarse node.  Column 2X + 2 is formed by this wave and
+// by the wave of column X + 1 (at about the same time, from L2).  No node
+// factors and no domain (distributed control on the square); 64 lanes per node.
+#pragma once
+#include "sweep.h"
+
+namespace smg {
+
+template <typename T, int JM, int VW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_rr_walk(LevelArgs<T> L, const T* __restrict__ x, const T* __restrict__ f, T* __restrict__ coarse,
+               int seg) {
+  constexpr int kWaves = kBlock / 64;
+  const int n = L.n, N = L.N;
+  const int nc = (n - 1) / 2;
+  __shared__ T cde[3 * 64 * JM];
+  for (int j = threadIdx.x; j < N; j += kBlock) {
+    cde[j] = L.c[j];
+    cde[N + j] = L.d[j];
+    cde[2 * N + j] = L.e[j];
+  }
+  __syncthreads();
+  const size_t nn = (size_t)n * n, nnc = (size_t)nc * nc;
+  const int npg = (nc + kWaves - 1) / kWaves, nseg = (nc + seg - 1) / seg;
+  const int t = xcd_remap(blockIdx.x, npg * nseg);
+  const int g = t / npg, pg = t - g * npg;
+  const int X = __builtin_amdgcn_readfirstlane(pg * kWaves + (int)threadIdx.x / 64);
+  const int lane = threadIdx.x & 63;
+  if (X >= nc) return;   // whole waves; no barriers below
+  const int K0 = g * seg, K1 = min(nc, K0 + seg);
+  if (K0 >= K1) return;
+  const int c0 = 2 * X;                       // columns c0, c0 + 1, c0 + 2
+  auto cl = [&](int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); };
+  auto nd = [&](int col, int row) { return (size_t)cl(row, n - 1) * n + cl(col, n - 1); };
+  auto kxp = [&](int row, int fc) { return L.kx + ((size_t)cl(row, n - 1) * (n + 1) + cl(fc, n)) * N; };
+  auto kyp = [&](int fr, int col) { return L.ky + ((size_t)cl(fr, n) * n + cl(col, n - 1)) * N; };
+  const T* __restrict__ fY = f;
+  const T* __restrict__ fU = f + (size_t)N * nn;
+  const T* __restrict__ fP = f + (size_t)(N + 1) * nn;
+  const T* __restrict__ U = x + (size_t)N * nn;
+  const bool hw0 = c0 > 0, he2 = c0 + 2 < n - 1;   // W of column c0, E of column c0 + 2
+  auto st_cached = [&](T* p, const T (&v)[JM]) {
+#pragma unroll
+    for (int c = 0; c < JM / VW; ++c) {
+      const int j0 = VW * (lane + c * 64);
+      if (j0 < N) {
+        T t2[VW];
+#pragma unroll
+        for (int u = 0; u < VW; ++u) t2[u] = v[c * VW + u];
+        stv<VW>(p + j0, t2);
+      }
+    }
+  };
+
+  // carried: x of rows r-1 and r (own columns), S faces of row r
+  NodeYP<T, JM> xp[3], xc[3];
+  T ks[3][JM];
+  const int r0 = 2 * K0, r1 = 2 * K1;          // fine rows r0..r1
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ld_yp<T, JM, VW>(x, nn, N, nd(c0 + c, r0 - 1), lane, xp[c]);
+    ld_yp<T, JM, VW>(x, nn, N, nd(c0 + c, r0), lane, xc[c]);
+    ldn<T, JM, VW>(kyp(r0, c0 + c), N, lane, ks[c]);
+  }
+  // coarse row being gathered: Y and P rows, the weighted p for the U row, and
+  // the weighted f_U - g u
+  T aY[JM], aP[JM], aQ[JM];
+  T aU = T(0);
+#pragma unroll
+  for (int q = 0; q < JM; ++q) aY[q] = aP[q] = aQ[q] = T(0);
+  for (int r = r0; r <= r1; ++r) {
+    const bool hs = r > 0, hn = r < n - 1;
+    // ---- loads of the step
+    NodeYP<T, JM> xn[3], sw, se;
+    T kxv[4][JM], kn[3][JM], fyv[3][JM], fpv[3][JM];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ld_yp<T, JM, VW>(x, nn, N, nd(c0 + c, r + 1), lane, xn[c]);
+    ld_yp<T, JM, VW>(x, nn, N, nd(c0 - 1, r), lane, sw);
+    ld_yp<T, JM, VW>(x, nn, N, nd(c0 + 3, r), lane, se);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ldn<T, JM, VW>(kxp(r, c0 + c), N, lane, kxv[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      ldn<T, JM, VW>(kyp(r + 1, c0 + c), N, lane, kn[c]);
+      ldn<T, JM, VW>(fY + nd(c0 + c, r) * N, N, lane, fyv[c]);
+      ldn<T, JM, VW>(fP + nd(c0 + c, r) * N, N, lane, fpv[c]);
+    }
+    T uu[3], fu[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uu[c] = U[nd(c0 + c, r)];
+      fu[c] = fU[nd(c0 + c, r)];
+    }
+    // ---- residual rows of the three nodes of row r, weighted across columns
+    T hY[JM], hP[JM], hQ[JM];
+#pragma unroll
+    for (int q = 0; q < JM; ++q) {
+      const int j = VW * (lane + (q / VW) * 64) + q % VW;
+      const T cj = cde[j < N ? j : N - 1], ej = cde[2 * N + (j < N ? j : N - 1)];
+      T sY = T(0), sP = T(0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool hw = c > 0 || hw0, he = c < 2 || he2;
+        const T kw = kxv[c][q], ke = kxv[c + 1][q], kS = ks[c][q], kN = kn[c][q];
+        const T yW = c == 0 ? sw.y[q] : xc[c - 1].y[q], yE = c == 2 ? se.y[q] : xc[c + 1].y[q];
+        const T pW = c == 0 ? sw.p[q] : xc[c - 1].p[q], pE = c == 2 ? se.p[q] : xc[c + 1].p[q];
+        auto nbsum = [&](T vw, T ve, T vs, T vn) -> T {
+          return ((hw ? kw * vw : T(0)) + (he ? ke * ve : T(0))) + ((hs ? kS * vs : T(0)) + (hn ? kN * vn : T(0)));
+        };
+        const T sy = nbsum(yW, yE, xp[c].y[q], xn[c].y[q]);
+        const T sp = nbsum(pW, pE, xp[c].p[q], xn[c].p[q]);
+        const T a = (kw + ke) + (kS + kN);
+        const T yq = xc[c].y[q], pq = xc[c].p[q];
+        const T rY = fyv[c][q] - (cj * yq + (a * pq - sp));
+        const T rP = fpv[c][q] - ((a * yq - sy) + ej * uu[c]);
+        const T w = c == 1 ? T(1) : T(0.5);
+        sY += w * rY;
+        sP += w * rP;
+      }
+      hY[q] = sY;
+      hP[q] = sP;
+      hQ[q] = (T(0.5) * xc[0].p[q] + xc[1].p[q]) + T(0.5) * xc[2].p[q];
+    }
+    const T hU = (T(0.5) * (fu[0] - L.g * uu[0]) + (fu[1] - L.g * uu[1])) + T(0.5) * (fu[2] - L.g * uu[2]);
+    // ---- gather into the coarse rows: row r = 2K + 1 is the middle of coarse
+    //      row K, an even row ends coarse row r/2 - 1 and starts row r/2
+    if (r & 1) {
+#pragma unroll
+      for (int q = 0; q < JM; ++q) { aY[q] += hY[q]; aP[q] += hP[q]; aQ[q] += hQ[q]; }
+      aU += hU;
+    } else {
+      if (r > r0) {   // coarse row K = r/2 - 1 complete
+        const int K = r / 2 - 1;
+        T dl = T(0);
+#pragma unroll
+        for (int q = 0; q < JM; ++q) {
+          aY[q] += T(0.5) * hY[q];
+          aP[q] += T(0.5) * hP[q];
+          aQ[q] += T(0.5) * hQ[q];
+          const int j = VW * (lane + (q / VW) * 64) + q % VW;
+          dl += j < N ? cde[N + j] * aQ[q] : T(0);
+        }
+        aU += T(0.5) * hU;
+        const size_t cn = (size_t)K * nc + X;
+        st_cached(coarse + cn * N, aY);   // read by the next level right away
+        st_cached(coarse + (size_t)(N + 1) * nnc + cn * N, aP);
+        const T D = group_sum<64>(dl);
+        if (lane == 0) coarse[(size_t)N * nnc + cn] = aU - D;
+      }
+      if (r < r1) {   // start coarse row r/2
+#pragma unroll
+        for (int q = 0; q < JM; ++q) { aY[q] = T(0.5) * hY[q]; aP[q] = T(0.5) * hP[q]; aQ[q] = T(0.5) * hQ[q]; }
+        aU = T(0.5) * hU;
+      }
+    }
+    // ---- shift the carried rows
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xp[c] = xc[c];
+      xc[c] = xn[c];
+      cpy(ks[c], kn[c]);
+    }
+  }
+}
+
+}  // namespace smg

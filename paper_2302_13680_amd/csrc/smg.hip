@@ -20,6 +20,7 @@
 #include "../../include/smg.h"
 #include "kernels.h"
 #include "sweep.h"
+#include "rrwalk.h"
 
 using namespace smg;
 
@@ -835,9 +836,39 @@ int restrict_to(smg_ctx* C, int nf, const T* fine, T* coarse) {
 }
 
 // coarse = R (f - S x) in one pass (the fine residual is never stored).
+// The column-walk form (k_rr_walk) where the level's sweeps run in one launch:
+// 64 lanes per node, at most four samples per lane, no node factors or domain.
+template <typename T>
+bool rr_walk(smg_ctx* C, const Level<T>& L, const T* x, const T* f, T* coarse) {
+  if (C->masked || C->domain || !one_launch_desc(C->desc, L.n) || L.n < 3) return false;
+  const int nc = (L.n - 1) / 2;
+  const LevelArgs<T> a = args(L, C->N, C->desc.strip);
+  bool launched = false;
+  lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    if constexpr (W == 64 && JM <= 4) {
+      sweep_vw_dispatch<T, JM>(halfsweep_vw(decltype(Vc)::value, JM), C->N, [&](auto Vk) {
+        constexpr int VW = decltype(Vk)::value;
+        auto kern = k_rr_walk<T, JM, VW>;
+        static const int resident = resident_waves(reinterpret_cast<const void*>(kern));
+        const int nseg = std::max(1, resident / nc), seg = (nc + nseg - 1) / nseg;
+        const int npg = (nc + kBlock / 64 - 1) / (kBlock / 64);
+        const int nb = npg * ((nc + seg - 1) / seg);
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, C->stream, a, x, f, coarse, seg);
+      });
+      launched = true;
+    }
+  });
+  return launched;
+}
+
 template <typename T>
 int residual_restrict(smg_ctx* C, const Level<T>& L, const T* x, const T* f, T* coarse) {
   const int nc = (L.n - 1) / 2;
+  if (rr_walk<T>(C, L, x, f, coarse)) {
+    LAUNCH_CHECK();
+    return SMG_OK;
+  }
   const LevelArgs<T> a = args(L, C->N, C->desc.strip);
   rr_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value, VW = decltype(Vc)::value;

@@ -57,6 +57,26 @@ def test_sweep_equals_two_halfsweeps_and_oracle(B, O, n, N, rows):
     assert_blocks(got, xo, n, N, 1e-13, "oracle")
 
 
+@pytest.mark.parametrize("n,N", [(63, 256), (63, 200), (31, 193), (127, 100), (15, 130)])
+def test_column_walk_residual_restrict_against_oracle(B, O, n, N):
+    """Where the sweeps run in one launch the V-cycle's residual + restriction
+    walks columns (k_rr_walk): every level against the oracle's residual then
+    full weighting, per block, with random x and f (even, odd and ragged N;
+    the short levels give one coarse row per segment)."""
+    p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=3 * n + N)
+    o = O.Oracle(p)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0, sweep_rows=4)
+    rng = np.random.default_rng(n + N)
+    for l in range(o.nlev - 1):
+        nl, nc = o.levels_n[l], o.levels_n[l + 1]
+        x = rng.standard_normal((2 * N + 1) * nl * nl)
+        f = rng.standard_normal(x.size)
+        cd = torch.empty((2 * N + 1) * nc * nc, dtype=torch.float64, device="cuda")
+        ctx.residual_restrict(l, dev(paper_to_node(x, nl, N)), dev(paper_to_node(f, nl, N)), cd)
+        ref = O.restrict(nl, N, o.residual(x, f, l))
+        assert_blocks(node_to_paper(host(cd), nc, N), ref, nc, N, 1e-14, f"level {l}")
+
+
 def test_sweep_refuses_aliasing_and_reports_the_fallback(B):
     p = inputs.make_problem(63, 64, 1e-4, M=6, sigma=0.5, decay=True, seed=3)
     ctx, f = B.context_from_problem(p, gmres_restart=0)
