@@ -130,6 +130,8 @@ struct ArnSlots {
 };
 
 // partials[b][slot], slots: [0,KM) R_i, [KM,2KM) B_i, then c, d, e (ArnSlots).
+// Pairs of entries per access (16 bytes; the basis stride ldv is even), the odd
+// last entry of an odd len by the first thread.
 template <int KM>
 __global__ __launch_bounds__(kBlock) void k_arnoldi_dots(size_t len, const double* __restrict__ V, size_t ldv,
                                                          int k, const double* __restrict__ w,
@@ -139,11 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_arnoldi_dots(size_t len, const doubl
 #pragma unroll
   for (int i = 0; i < S::kCount; ++i) acc[i] = 0.0;
   const double* __restrict__ vk = V + (size_t)k * ldv;
-  for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < len; t += (size_t)gridDim.x * kBlock) {
-    double vv[KM];
-#pragma unroll
-    for (int i = 0; i < KM; ++i) vv[i] = i < k ? V[(size_t)i * ldv + t] : 0.0;
-    const double v = vk[t], wv = w[t];
+  auto add = [&](const double (&vv)[KM], double v, double wv) {
 #pragma unroll
     for (int i = 0; i < KM; ++i) {
       acc[i] += vv[i] * v;
@@ -152,6 +150,26 @@ __global__ __launch_bounds__(kBlock) void k_arnoldi_dots(size_t len, const doubl
     acc[S::kC] += v * v;
     acc[S::kD] += v * wv;
     acc[S::kE] += wv * wv;
+  };
+  const size_t np = len / 2;
+  for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < np; t += (size_t)gridDim.x * kBlock) {
+    double2 vv2[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i)
+      vv2[i] = i < k ? *reinterpret_cast<const double2*>(V + (size_t)i * ldv + 2 * t) : double2{0.0, 0.0};
+    const double2 v2 = *reinterpret_cast<const double2*>(vk + 2 * t);
+    const double2 w2 = *reinterpret_cast<const double2*>(w + 2 * t);
+    double va[KM], vb[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) { va[i] = vv2[i].x; vb[i] = vv2[i].y; }
+    add(va, v2.x, w2.x);
+    add(vb, v2.y, w2.y);
+  }
+  if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double vv[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) vv[i] = i < k ? V[(size_t)i * ldv + len - 1] : 0.0;
+    add(vv, vk[len - 1], w[len - 1]);
   }
   __shared__ double red[kBlock / 64][S::kCount];
   const int lane = threadIdx.x & 63, wvi = threadIdx.x >> 6;
@@ -196,21 +214,36 @@ struct ArnCoef {
 
 // The update pass V_{k+1} = (w - sum_{i<=k} g_i V_i) * inv_rho (KM >= k + 1).  If
 // norm_partials is not null, partials[b] = block sum of the squared entries of
-// the unscaled vector.
+// the unscaled vector.  Pairs of entries per access, as k_arnoldi_dots.
 template <int KM>
 __global__ __launch_bounds__(kBlock) void k_arnoldi_update(size_t len, double* __restrict__ V, size_t ldv, int k,
                                                            const double* __restrict__ w, ArnCoef cf,
                                                            double* __restrict__ norm_partials) {
   double* __restrict__ vn = V + (size_t)(k + 1) * ldv;
   double acc[1] = {0.0};
-  for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < len; t += (size_t)gridDim.x * kBlock) {
-    double vv[KM];
+  const size_t np = len / 2;
+  for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < np; t += (size_t)gridDim.x * kBlock) {
+    double2 vv2[KM];
 #pragma unroll
-    for (int i = 0; i < KM; ++i) vv[i] = i <= k ? V[(size_t)i * ldv + t] : 0.0;
-    double ws = w[t];
+    for (int i = 0; i < KM; ++i)
+      vv2[i] = i <= k ? *reinterpret_cast<const double2*>(V + (size_t)i * ldv + 2 * t) : double2{0.0, 0.0};
+    const double2 w2 = *reinterpret_cast<const double2*>(w + 2 * t);
+    double wa = w2.x, wb = w2.y;
 #pragma unroll
-    for (int i = 0; i < KM; ++i) ws -= cf.g[i] * vv[i];
-    vn[t] = ws * cf.inv_rho;
+    for (int i = 0; i < KM; ++i) {
+      wa -= cf.g[i] * vv2[i].x;
+      wb -= cf.g[i] * vv2[i].y;
+    }
+    __builtin_nontemporal_store(wa * cf.inv_rho, vn + 2 * t);
+    __builtin_nontemporal_store(wb * cf.inv_rho, vn + 2 * t + 1);
+    acc[0] += wa * wa;
+    acc[0] += wb * wb;
+  }
+  if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double ws = w[len - 1];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) ws -= cf.g[i] * (i <= k ? V[(size_t)i * ldv + len - 1] : 0.0);
+    vn[len - 1] = ws * cf.inv_rho;
     acc[0] += ws * ws;
   }
   if (norm_partials) {
@@ -223,16 +256,40 @@ struct BasisCoef {
   double y[kMaxBasis];
 };
 
-// x += sum_i y_i Z_i
+// x += sum_i y_i Z_i, pairs of entries per access (ldz even) where x is 16-byte
+// aligned, else one entry per access.
 template <typename TZ, int KM>
 __global__ __launch_bounds__(kBlock) void k_basis_axpy(size_t len, double* __restrict__ x,
                                                        const TZ* __restrict__ Z, size_t ldz, int nz, BasisCoef cf) {
-  for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < len; t += (size_t)gridDim.x * kBlock) {
-    double s = x[t];
+  using Z2 = typename std::conditional<std::is_same<TZ, float>::value, float2, double2>::type;
+  if (reinterpret_cast<uintptr_t>(x) & 15) {
+    for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < len; t += (size_t)gridDim.x * kBlock) {
+      double s = x[t];
+#pragma unroll
+      for (int i = 0; i < KM; ++i)
+        if (i < nz) s += cf.y[i] * (double)Z[(size_t)i * ldz + t];
+      x[t] = s;
+    }
+    return;
+  }
+  const size_t np = len / 2;
+  for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < np; t += (size_t)gridDim.x * kBlock) {
+    double2 s = *reinterpret_cast<const double2*>(x + 2 * t);
 #pragma unroll
     for (int i = 0; i < KM; ++i)
-      if (i < nz) s += cf.y[i] * (double)Z[(size_t)i * ldz + t];
-    x[t] = s;
+      if (i < nz) {
+        const Z2 z = *reinterpret_cast<const Z2*>(Z + (size_t)i * ldz + 2 * t);
+        s.x += cf.y[i] * (double)z.x;
+        s.y += cf.y[i] * (double)z.y;
+      }
+    *reinterpret_cast<double2*>(x + 2 * t) = s;
+  }
+  if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = x[len - 1];
+#pragma unroll
+    for (int i = 0; i < KM; ++i)
+      if (i < nz) s += cf.y[i] * (double)Z[(size_t)i * ldz + len - 1];
+    x[len - 1] = s;
   }
 }
 

@@ -230,9 +230,10 @@ struct smg_ctx {
   double* mdp = nullptr;       // [kPartials][kArnSlots] partials of the Krylov reductions
   double* hdev = nullptr;      // [3][kMaxBasis+1]
   int* flag = nullptr;
-  double* V = nullptr;         // [(m+1)][len0] Krylov basis
-  double* Z64 = nullptr;       // [m][len0] preconditioned basis (FP64 cycle)
-  float* Z32 = nullptr;        // [m][len0] preconditioned basis (FP32 cycle)
+  double* V = nullptr;         // [(m+1)][ldk] Krylov basis
+  double* Z64 = nullptr;       // [m][ldk] preconditioned basis (FP64 cycle)
+  float* Z32 = nullptr;        // [m][ldk] preconditioned basis (FP32 cycle)
+  size_t ldk = 0;              // basis stride: len0 rounded up to 64 (16-byte aligned pairs)
   double* w = nullptr;         // [len0]
   double* rr = nullptr;        // [len0]
   size_t len0 = 0;
@@ -350,8 +351,9 @@ size_t plan(const smg_desc& d, smg_ctx* C, void* base) {
   C->rr = cv.take<double>(len0);
   const int mr = d.gmres_restart;
   if (mr > 0) {
-    C->V = cv.take<double>(len0 * (mr + 1));
-    if (f32) C->Z32 = cv.take<float>(len0 * mr); else C->Z64 = cv.take<double>(len0 * mr);
+    C->ldk = (len0 + 63) & ~(size_t)63;
+    C->V = cv.take<double>(C->ldk * (mr + 1));
+    if (f32) C->Z32 = cv.take<float>(C->ldk * mr); else C->Z64 = cv.take<double>(C->ldk * mr);
   }
   if (d.flags & SMG_FLAG_SSN) {
     const size_t nn = (size_t)d.n * d.n;
@@ -1193,14 +1195,14 @@ void stats_norms(smg_stats* st, const double* h, double fn) {
 //   Z_k = Vcycle(0, V_k);  w = S Z_k.
 int precond_and_apply(smg_ctx* C, int k) {
   const size_t len = C->len0;
-  double* vk = C->V + (size_t)k * len;
+  double* vk = C->V + (size_t)k * C->ldk;
   if (C->desc.precision == SMG_F64) {
-    double* zk = C->Z64 + (size_t)k * len;
+    double* zk = C->Z64 + (size_t)k * C->ldk;
     TRY(run_cycle<double>(C, zk, vk, true));
     TRY((residual<double, double, double>(C, C->L64[0], zk, (const double*)nullptr, C->w, 1, false)));
     TRY(lowrank_add(C, zk, C->w, 1.0));
   } else {
-    float* zk = C->Z32 + (size_t)k * len;
+    float* zk = C->Z32 + (size_t)k * C->ldk;
     TRY((convert<double, float>(C, vk, C->L32[0].f, len)));
     TRY(run_cycle<float>(C, zk, C->L32[0].f, true));
     TRY((residual<double, float, double>(C, C->L64[0], zk, (const float*)nullptr, C->w, 1, false)));
@@ -1274,7 +1276,7 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
     km_dispatch(k, [&](auto Kc) {
       constexpr int KM = decltype(Kc)::value;
       hipLaunchKernelGGL((k_arnoldi_dots<KM>), dim3(kPartials), dim3(kBlock), 0, C->stream, len,
-                         (const double*)C->V, len, k, (const double*)C->w, C->mdp);
+                         (const double*)C->V, C->ldk, k, (const double*)C->w, C->mdp);
     });
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_partials_finalize, dim3(nslots), dim3(kBlock), 0, C->stream, (const double*)C->mdp,
@@ -1345,8 +1347,8 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
       cf.inv_rho = 1.0;
       km_dispatch(k + 1, [&](auto Kc) {
         constexpr int KM = decltype(Kc)::value;
-        hipLaunchKernelGGL((k_arnoldi_update<KM>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, C->V, len, k,
-                           (const double*)C->w, cf, C->mdp);
+        hipLaunchKernelGGL((k_arnoldi_update<KM>), dim3(kPartials), dim3(kBlock), 0, C->stream, len, C->V, C->ldk,
+                           k, (const double*)C->w, cf, C->mdp);
       });
       LAUNCH_CHECK();
       hipLaunchKernelGGL(k_partials_finalize, dim3(1), dim3(kBlock), 0, C->stream, (const double*)C->mdp, kPartials,
@@ -1369,8 +1371,8 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
       cf.inv_rho = 1.0 / hn;
       km_dispatch(k + 1, [&](auto Kc) {
         constexpr int KM = decltype(Kc)::value;
-        hipLaunchKernelGGL((k_arnoldi_update<KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, C->V, len,
-                           k, (const double*)C->w, cf, (double*)nullptr);
+        hipLaunchKernelGGL((k_arnoldi_update<KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, C->V,
+                           C->ldk, k, (const double*)C->w, cf, (double*)nullptr);
       });
       LAUNCH_CHECK();
       rho = hn;
@@ -1387,10 +1389,10 @@ int gmres_cycle(smg_ctx* C, double* x, double beta, int m, double target, int bu
       constexpr int KM = decltype(Kc)::value;
       if (C->desc.precision == SMG_F64)
         hipLaunchKernelGGL((k_basis_axpy<double, KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x,
-                           (const double*)C->Z64, len, kend, y);
+                           (const double*)C->Z64, C->ldk, kend, y);
       else
         hipLaunchKernelGGL((k_basis_axpy<float, KM>), dim3(grid_for(len)), dim3(kBlock), 0, C->stream, len, x,
-                           (const float*)C->Z32, len, kend, y);
+                           (const float*)C->Z32, C->ldk, kend, y);
     });
     LAUNCH_CHECK();
   }

@@ -84,16 +84,21 @@ def test_lowrank_operator_and_gmres(B, cv, N):
     assert rel(node_to_paper(host(Sv), n, N), c.o.apply(v)) <= 1e-14
 
 
-def same_inner_counts(gpu, ref, cap=50):
+def same_inner_counts(gpu, ref, stalled=None, cap=50):
     """The Newton count of every evaluation of h(t) agrees within one (15% on
     long, backtracking evaluations, whose halvings rounding can shift), except
-    where either side ended at the cap: there the start sat within 1/tol of the
-    rounding floor (the printed rule's relative part out of reach), and whether
-    a rounding dip meets it first differs between the two arithmetics."""
+    where the start sat within 1/tol of the rounding floor, so that the printed
+    rule's relative part is out of reach (Section 6's inner rule as read in the
+    design notes): such an evaluation ends at the cap, or where the oracle marks
+    it stalled (no halving decreases ||F_1|| any more, ||F_1|| <= tol).  Its
+    count is the number of backtracked steps that still shave a rounding error
+    off ||F_1||, which differs between any two arithmetics (the oracle alone
+    gives 10 and 16 for the same evaluation on two hosts)."""
     assert len(gpu) == len(ref), (gpu, ref)
-    for a, b in zip(gpu, ref):
-        if a < cap and b < cap:
-            assert abs(a - b) <= max(1, 0.15 * max(a, b)), (gpu, ref)
+    stalled = stalled if stalled is not None else [False] * len(ref)
+    for a, b, st in zip(gpu, ref, stalled):
+        if a < cap and b < cap and not st:
+            assert abs(a - b) <= max(1, 0.15 * max(a, b)), (gpu, ref, stalled)
 
 
 @pytest.mark.parametrize("lam,eps,N", [(0.5, 0.05, 8), (0.9, 0.01, 40)])
@@ -110,7 +115,7 @@ def test_cvar_solve_matches_the_oracle(B, cv, lam, eps, N):
     rc, st = ctx.cvar_solve(x, f, dev(c.yd.reshape(p.n, p.n)), c.zeta, lam, eps, c.mass)
     assert rc == B.SMG_OK, st
     assert st["outer"] == ref["outer"], (st, ref["outer"])
-    same_inner_counts(st["inner_counts"], ref["inner_counts"])
+    same_inner_counts(st["inner_counts"], ref["inner_counts"], ref["inner_stalled"])
     assert sum(st["inner_counts"]) == st["inner_total"]
     assert st["inner_capped"] == sum(1 for k in st["inner_counts"] if k >= 50)
     assert abs(st["t"] - ref["t"]) <= 1e-7 * max(1.0, abs(ref["t"]))
@@ -135,7 +140,7 @@ def test_named_inner_variants_match_the_oracle(B, cv, rule, backtrack):
     rc, st = ctx.cvar_solve(x, f, dev(c.yd.reshape(p.n, p.n)), c.zeta, lam, eps, c.mass, inner_rule=rule,
                             inner_backtrack=backtrack)
     assert rc == B.SMG_OK and st["outer"] == ref["outer"]
-    same_inner_counts(st["inner_counts"], ref["inner_counts"])
+    same_inner_counts(st["inner_counts"], ref["inner_counts"], ref["inner_stalled"])
     assert abs(st["t"] - ref["t"]) <= 1e-7 * max(1.0, abs(ref["t"]))
     u = c.blocks(node_to_paper(host(x), p.n, p.N))[1]
     assert np.abs(u - ref["u"]).max() <= 1e-6 * np.abs(ref["u"]).max()
@@ -158,7 +163,7 @@ def test_cvar_on_the_square_with_collocation_weights(B, cv):
         rc, st = ctx.cvar_solve(x, f, dev(c.yd.reshape(p.n, p.n)), c.zeta, lam, eps, c.mass)
         assert rc == B.SMG_OK
         assert st["outer"] == ref["outer"]
-        same_inner_counts(st["inner_counts"], ref["inner_counts"])
+        same_inner_counts(st["inner_counts"], ref["inner_counts"], ref["inner_stalled"])
         if lam == 0.0:
             assert st["outer"] == 0 and st["t"] == 0.0
         assert abs(st["t"] - ref["t"]) <= 1e-7 * max(1.0, abs(ref["t"]))
