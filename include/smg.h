@@ -475,8 +475,9 @@ int smg_cvar_solve(smg_ctx *ctx, double *x, const double *f, const double *yd, d
 
 /* ------------------------------------------------------------------ batches
  * Many independent problem instances (different n, N and blocks) solved
- * together.  The instances are grouped by finest grid size and the groups run
- * one after another (smallest first) on the contexts' stream, so small
+ * together.  The smallest instances (a correction cycle touching at most 16 MB)
+ * form one group, the others one group per finest grid size, and the groups
+ * run one after another (smallest first) on the contexts' stream, so small
  * instances retire early.  Within a group every refinement step of all unretired
  * instances -- FP64 residual r_i = f_i - S_i x_i, convergence check, one
  * correction V-cycle from zero in the contexts' precision (red-black collective

@@ -2645,7 +2645,8 @@ extern "C" {
 
 }  // extern "C"
 
-// A batch: its instances in groups of one finest grid size, smallest first;
+// A batch: its instances in groups (the smallest instances, then one finest grid
+// size per group), smallest first;
 // every group is a lockstep batch of its own (BatchGroup) and the groups run one
 // after another on the contexts' stream.  Small instances then retire after
 // steps of their own size, not steps as long as the largest instance's.
@@ -2700,20 +2701,25 @@ double instance_bytes(const smg_ctx* C) {
   return b + 8.0 * 3.0 * (double)C->len0;
 }
 
-// Groups of instances: one per finest grid size, in order of the bytes a
-// correction cycle of their instances touches (smallest first), instances in
-// input order.  Measured on 64 uneven instances (n 63..255, N 16..128): one
-// group per grid size retires the 63x63 instances after 4.5 ms instead of the
-// whole batch's 100 ms at 2% less throughput than one lockstep group; groups
-// packed to fit the Infinity Cache lost a quarter of the throughput (the 255x255
-// instances exceed the cache alone, and small groups leave the GPU idle on the
-// coarse levels).
+// Groups of instances: the smallest instances (a correction cycle that touches
+// at most kFastLaneBytes: their steps run at the launch-latency floor) in one
+// group of their own, the others one group per finest grid size; groups in order
+// of the bytes a correction cycle of their largest instance touches (smallest
+// first), instances in input order.  Measured on 64 uneven instances (n 63..255,
+// N 16..128), retirement of the 63x63, N=16 instances / solves per second:
+// this grouping 2.1 ms / 618; one group per grid size 4.5 ms / 626; one group
+// per (n, N) 1.7 ms / 574; the small instances then all others in one lockstep
+// group 2.1 ms / 630 (but the 127x127 instances retire with the 255x255 ones,
+// at 92 ms instead of 20); all in one lockstep group 79 ms / 642; groups packed
+// to fit the Infinity Cache lost a quarter of the throughput.
+constexpr double kFastLaneBytes = 16e6;
+
 std::vector<std::vector<int>> group_members(smg_ctx* const* ctxs, int count) {
   std::vector<int> ns;
   std::vector<double> cost;
   std::vector<std::vector<int>> g;
   for (int i = 0; i < count; ++i) {
-    const int n = ctxs[i]->desc.n;
+    const int n = instance_bytes(ctxs[i]) <= kFastLaneBytes ? 0 : ctxs[i]->desc.n;   // group key
     size_t k = 0;
     while (k < ns.size() && ns[k] != n) ++k;
     if (k == ns.size()) { ns.push_back(n); g.emplace_back(); cost.push_back(0.0); }
