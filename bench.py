@@ -363,14 +363,17 @@ def paper_tables(dev):
     control on the square (N_h = 961).  Defaults of the sub-tables: nu 1e-4,
     sigma^2 0.5, L^2 0.5 with M = 3 and 5^3 collocation nodes, 31x31 (three
     levels); the Monte Carlo sub-tables take sigma^2 1.5, L^2 0.1, M = 15.
-    Counts beside the printed ones."""
+    The linear-quadratic systems keep the printed rows of eq.
+    full_space_optimality_system (rows="paper"), whose residual the printed
+    stopping rule measures; the L^1 run the rescaled adjoint its Newton system
+    is written in.  Counts beside the printed ones."""
     import numpy as np
     import torch
     from paper_2302_13680_amd import binding, inputs
 
-    def problem(n=31, q=5, nu=1e-4, sigma2=0.5, L2=0.5, M=3, mc=None, **kw):
+    def problem(n=31, q=5, nu=1e-4, sigma2=0.5, L2=0.5, M=3, mc=None, rows="paper", **kw):
         common = dict(sigma=float(np.sqrt(sigma2)), decay=True, yd=inputs.paper_target(n), f=0.0,
-                      field="gaussian", corr_len2=L2)
+                      field="gaussian", corr_len2=L2, rows=rows)
         if mc:
             return inputs.make_problem(n, mc, nu, M=M, seed=17, **common, **kw)
         return inputs.collocation_problem(n, q, nu, M=M, **common, **kw)
@@ -397,7 +400,8 @@ def paper_tables(dev):
         return res
 
     out = {"field": "Gaussian covariance (eq. log_normal)", "smoother": "collective Jacobi theta 1/2, V(2,2)",
-           "tol": 1e-9, "format": "[V-cycles, GMRES] (this build) beside [printed]"}
+           "tol": 1e-9, "rows": "as printed (eq. full_space_optimality_system)",
+           "format": "[V-cycles, GMRES] (this build) beside [printed]"}
     L = dict(domain="lshape")
     t1 = {}
     t1["nu"] = [{"nu": nu, "counts": counts(problem(nu=nu, **L)), "paper": pr}
@@ -419,7 +423,7 @@ def paper_tables(dev):
     out["local_square"] = t2
 
     def bproblem(n=63, q=5, nu=1e-4, sigma2=0.5, L2=0.5, M=3, mc=None):
-        common = dict(sigma=float(np.sqrt(sigma2)), decay=True, field="gaussian", corr_len2=L2)
+        common = dict(sigma=float(np.sqrt(sigma2)), decay=True, field="gaussian", corr_len2=L2, rows="paper")
         if mc:
             return inputs.boundary_control_problem(n, mc, nu, M=M, seed=17, **common)
         return inputs.boundary_collocation_problem(n, q, nu, M=M, **common)
@@ -436,7 +440,7 @@ def paper_tables(dev):
     t3["N_monte_carlo"] = [{"N": N, "counts": counts(bproblem(mc=N, sigma2=1.5, L2=0.1, M=15)), "paper": pr}
                            for N, pr in ((100, [18, 15]), (1000, [19, 16]), (2000, [20, 16]))]
     out["boundary_control"] = t3
-    p = problem(**L)
+    p = problem(rows="scaled", **L)
     ctx, f = binding.context_from_problem(p, device=dev, gmres_restart=30, theta=0.5, flags=binding.SMG_FLAG_JACOBI,
                                           ssn=True)
     x = torch.zeros(p.dof, dtype=torch.float64, device=dev)

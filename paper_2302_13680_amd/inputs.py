@@ -172,7 +172,7 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
                  f: float = 1.0, xi: np.ndarray | None = None,
                  kappa_const: float | None = None, weights: np.ndarray | None = None,
                  control_region: tuple | None = None, field: str = "sine",
-                 corr_len2: float = 0.5, domain: str = "square") -> Problem:
+                 corr_len2: float = 0.5, domain: str = "square", rows: str = "scaled") -> Problem:
     """Build one seeded instance.
 
     ``decay=False`` gives amplitudes a_m = sigma (the 31x31, N=8 case, four modes
@@ -189,6 +189,13 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
     ``control_region = (x0, x1, y0, y1)`` restricts the control to the nodes in
     the closed rectangle [x0, x1] x [y0, y1] (local control; the mask of the
     node entries of D_j and E_j); None lets it act everywhere.
+    ``rows``: "scaled" (default) carries the adjoint rescaled by the weights
+    (p~_j = zeta_j p_j, Y rows times zeta_j: C_j = zeta_j h^2, D_j = -h^2, the
+    symmetric form); "paper" keeps the rows as printed in eq.
+    full_space_optimality_system (C_j = M = h^2 I, D_j = -zeta_j h^2 I,
+    f_Y,j = h^2 y_d).  The two give the same iterates of the collective smoother
+    and of the multigrid hierarchy (a node-block scaling), but a residual norm,
+    and so a stopping test or a GMRES minimization, weighted differently.
     """
     h = 1.0 / (n + 1)
     if xi is None:
@@ -227,11 +234,18 @@ def make_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 4, sigma: float =
     zeta = np.full(N, 1.0 / N) if weights is None else np.asarray(weights, dtype=np.float64)
     if zeta.shape != (N,) or not np.all(zeta > 0):
         raise ValueError("weights must be N positive numbers")
-    c = zeta * h * h
-    d = np.full(N, -h * h)
+    if rows == "scaled":
+        c = zeta * h * h
+        d = np.full(N, -h * h)
+        fY = (zeta * h * h)[:, None, None] * ydv[None]
+    elif rows == "paper":
+        c = np.full(N, h * h)
+        d = -zeta * h * h
+        fY = np.repeat((h * h * ydv)[None], N, axis=0)
+    else:
+        raise ValueError(rows)
     e = np.full(N, -h * h)
     g = nu * h * h
-    fY = (zeta * h * h)[:, None, None] * ydv[None]
     fU = np.zeros((n, n))
     fP = np.full((N, n, n), h * h * f)
     dom = None
@@ -273,7 +287,7 @@ def paper_target(n: int) -> np.ndarray:
 def boundary_control_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 3, sigma: float = 0.5,
                              decay: bool = True, seed: int = 0, field: str = "sine", corr_len2: float = 0.5,
                              weights: np.ndarray | None = None, xi: np.ndarray | None = None,
-                             f: float = 0.0) -> Problem:
+                             f: float = 0.0, rows: str = "scaled") -> Problem:
     """Neumann boundary control on Gamma = (0,1) x {0} of the unit square (the
     paper's boundary-control table), Dirichlet on the rest of the boundary.
 
@@ -291,7 +305,8 @@ def boundary_control_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 3, si
     of a line, meta["control_growth"]) while C_j grows x4; kappa, y_d (the paper's target) and f taken at (x, |y|).  The
     coefficient models are those of ``make_problem`` evaluated at physical
     points; the solution's U block on the mirror row is the boundary control, its
-    Y and P blocks above it (and on it) the state and the adjoint."""
+    Y and P blocks above it (and on it) the state and the adjoint.  ``rows`` as
+    in ``make_problem`` ("paper": C_j = h^2 I, D_j = -2 zeta_j h I, f_Y = h^2 y_d)."""
     if n < 3 or (n + 1) % 4:
         raise ValueError("n + 1 must be a multiple of 4")
     H = 2.0 / (n + 1)                                   # physical spacing
@@ -324,11 +339,18 @@ def boundary_control_problem(n: int, N: int, nu: float = 1e-4, *, M: int = 3, si
     dom = (XX < 0.5 - 1e-12).astype(np.float64)         # x < 1
     ctrl = np.zeros((n, n))
     ctrl[mid, :] = dom[mid, :]
-    c = zeta * H * H
-    d = np.full(N, -2.0 * H)
+    if rows == "scaled":
+        c = zeta * H * H
+        d = np.full(N, -2.0 * H)
+        fY = (zeta * H * H)[:, None, None] * (ydv * dom)[None]
+    elif rows == "paper":
+        c = np.full(N, H * H)
+        d = -2.0 * H * zeta
+        fY = np.repeat((H * H * ydv * dom)[None], N, axis=0)
+    else:
+        raise ValueError(rows)
     e = np.full(N, -2.0 * H)
     g = 2.0 * nu * H
-    fY = (zeta * H * H)[:, None, None] * (ydv * dom)[None]
     fU = np.zeros((n, n))
     fP = np.full((N, n, n), H * H * f) * dom[None]
     return Problem(n=n, N=N, nu=nu, kx=np.ascontiguousarray(kx), ky=np.ascontiguousarray(ky), c=c, d=d, e=e, g=g,

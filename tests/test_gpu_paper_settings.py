@@ -22,16 +22,19 @@ def B():
     return binding
 
 
-def paper_problem(nu, region=None):
+def paper_problem(nu, region=None, rows="scaled", domain="square"):
     return inputs.collocation_problem(31, 5, nu, M=3, sigma=float(np.sqrt(0.5)), decay=True,
                                       yd=inputs.paper_target(31), f=0.0, field="gaussian", corr_len2=0.5,
-                                      control_region=region)
+                                      control_region=region, rows=rows, domain=domain)
 
 
-@pytest.mark.parametrize("region", [None, (0.25, 0.75, 0.25, 0.75)])
-def test_paper_setting_counts(B, region):
+@pytest.mark.parametrize("region,rows,domain", [(None, "scaled", "square"), ((0.25, 0.75, 0.25, 0.75), "scaled", "square"),
+                                                (None, "paper", "lshape"), ((0.25, 0.75, 0.25, 0.75), "paper", "square")])
+def test_paper_setting_counts(B, region, rows, domain):
+    """Both row scalings (the printed rows of eq. full_space_optimality_system
+    and the symmetrized form) on the square and on the L-shape."""
     from oracle.oracle import Oracle
-    p = paper_problem(1e-4, region)
+    p = paper_problem(1e-4, region, rows, domain)
     o = Oracle(p, smoother="jacobi", theta=0.5)
     fp = p.rhs_paper()
     ctx, f = B.context_from_problem(p, gmres_restart=30, theta=0.5, flags=B.SMG_FLAG_JACOBI)
