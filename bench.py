@@ -778,6 +778,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="the headline workload only")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the 511x511, N=256 mixed-precision section (for profiling)")
+    ap.add_argument("--medium-gmres-only", action="store_true",
+                    help="run only 4 FP64 GMRES(30) solves of the 255x255, N=64 instance (for tracing)")
     ap.add_argument("--cvar-only", action="store_true",
                     help="run only the risk-averse solver at 705 nodes, N=2000, lambda 0.95 (for profiling)")
     ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "smg_autotune_lanes.json"))
@@ -806,6 +808,16 @@ def main():
     if args.large_only:
         large, _, _, _ = large_mixed_section(dev)
         emit({"large_mixed": large})
+        return
+    if args.medium_gmres_only:
+        prob = inputs.medium_fp64()
+        ctx, f = binding.context_from_problem(prob, device=dev, gmres_restart=30)
+        x = torch.zeros(prob.dof, dtype=torch.float64, device=dev)
+        timed_solve(ctx, x, f, binding.SMG_GMRES, 1e-8)             # warm-up (graph capture)
+        runs = [timed_solve(ctx, x, f, binding.SMG_GMRES, 1e-8) for _ in range(3)]
+        emit({"medium_gmres": {"workload": "255x255, N=64, FP64 GMRES(30) + V(2,2) to 1e-8",
+                               "time_ms": [round(t, 3) for t, _ in runs],
+                               "iterations": runs[-1][1]["iterations"]}})
         return
     if args.counters:
         prob = inputs.large_mixed() if args.counters == "large" else inputs.medium_fp64()
