@@ -127,7 +127,8 @@ __global__ __launch_bounds__(64) void kb_coarse2(const BTask<T>* __restrict__ ta
 }
 
 // FP64 outer residual, rounded into t.out; per-block squared norms into partials.
-template <typename TO, int JM>
+// VW samples per access (2: every instance's N even).
+template <typename TO, int JM, int VW>
 __global__ __launch_bounds__(kBlock) void kb_outer_residual(const BOuterTask<TO>* __restrict__ tasks, int ntasks,
                                                             const int* __restrict__ done,
                                                             const int* __restrict__ iters,
@@ -145,12 +146,12 @@ __global__ __launch_bounds__(kBlock) void kb_outer_residual(const BOuterTask<TO>
       if (c > 0) {
         double* cur = (c & 1) ? t.w : t.x;
         const double* prev = (c & 1) ? t.x : t.w;
-        residual_add_node<JM>(t.L, prev, t.d, cur, t.f, t.out, slot, lane, W, acc);
+        residual_add_node<JM, VW>(t.L, prev, t.d, cur, t.f, t.out, slot, lane, W, acc);
       } else {
-        residual_node<double, double, TO, JM>(t.L, t.x, t.f, t.out, 0, slot, lane, W, acc);
+        residual_node<double, double, TO, JM, VW>(t.L, t.x, t.f, t.out, 0, slot, lane, W, acc);
       }
     } else {
-      residual_node<double, double, TO, JM>(t.L, t.x, t.f, t.out, 0, slot, lane, W, acc);
+      residual_node<double, double, TO, JM, VW>(t.L, t.x, t.f, t.out, 0, slot, lane, W, acc);
     }
   }
   double r3[3] = {acc[0], acc[1], acc[2]};

@@ -1664,9 +1664,14 @@ int batch_launch_step(BatchGroup* B, hipStream_t s, double tol, int maxit) {
       case kbOuter:
         jm_dispatch(B->jm, [&](auto Jc) {
           constexpr int JM = decltype(Jc)::value;
-          hipLaunchKernelGGL((kb_outer_residual<T, JM>), dim3(nbk), dim3(kBlock), 0, s,
-                             (const BOuterTask<T>*)tasks, nt, (const int*)B->done, (const int*)B->iters,
-                             B->partials);
+          auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(nbk), dim3(kBlock), 0, s, (const BOuterTask<T>*)tasks, nt,
+                               (const int*)B->done, (const int*)B->iters, B->partials);
+          };
+          if constexpr (JM % 2 == 0) {
+            if (B->vw == 2) { go(kb_outer_residual<T, JM, 2>); return; }   // two samples per access
+          }
+          go(kb_outer_residual<T, JM, 1>);
         });
         break;
       case kbCheck:

@@ -66,7 +66,11 @@ def test_batch_against_oracle(B, O, precision):
 
 def test_batch_equals_single_instance_refinement(B):
     """With the default lane widths the batched kernels run the same per-node
-    code as the single-instance FP32 refinement: identical iterates."""
+    arithmetic as the single-instance FP32 refinement: the same refinement
+    counts and iterates equal to rounding.  (The FP64 refinement residual takes
+    two samples per access in the batch wherever every N is even, and the
+    single-instance kernel only with 64 lanes per node, so for small N the sum
+    over samples in the control row runs in another order: 2.6e-14 observed.)"""
     probs = _problems()
     ctxs, xs, fs, singles = [], [], [], []
     for p in probs:
@@ -85,7 +89,7 @@ def test_batch_equals_single_instance_refinement(B):
         assert rc1 == B.SMG_OK
         assert st1["iterations"] == st["iterations"]
         rel = (torch.linalg.norm(x1 - xb) / torch.linalg.norm(x1)).item()
-        assert rel <= 1e-14, (p.n, p.N, rel)
+        assert rel <= 1e-13, (p.n, p.N, rel)
 
 
 def test_autotuned_lanes(B, O, tmp_path):
