@@ -50,6 +50,34 @@ def test_paper_setting_counts(B, region, rows, domain):
         assert np.linalg.norm(o.residual(xg, fp)) <= 1.01e-9 * np.linalg.norm(fp)
 
 
+def test_local_control_by_galerkin_node_factors(B):
+    """Local control on [0.25, 0.75]^2 as node factors of D_j and E_j coarsened by
+    full weighting (the row-lumped Galerkin product), printed rows: the GPU's
+    counts equal the oracle's (within one) and the solutions meet 1e-9 in the
+    oracle's residual."""
+    from oracle.oracle import Oracle
+    p = paper_problem(1e-4, None, "paper", "square")
+    t = (np.arange(p.n) + 1.0) / (p.n + 1)
+    X, Y = np.meshgrid(t, t)
+    m = ((X >= 0.25 - 1e-12) & (X <= 0.75 + 1e-12) & (Y >= 0.25 - 1e-12) & (Y <= 0.75 + 1e-12)).astype(np.float64)
+    o = Oracle(p, smoother="jacobi", theta=0.5)
+    o.set_masks(m, m, coarsen="full")
+    fp = p.rhs_paper()
+    ctx, f = B.context_from_problem(p, gmres_restart=30, theta=0.5, flags=B.SMG_FLAG_JACOBI)
+    md = torch.tensor(m, dtype=torch.float64, device="cuda")
+    ctx.set_node_factors(md, md, B.SMG_COARSEN_FULL)
+    for method, solve in ((B.SMG_VCYCLE, lambda: o.solve_vcycle(fp, tol=1e-9, maxit=300)),
+                          (B.SMG_GMRES, lambda: o.gmres(fp, tol=1e-9))):
+        x = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+        rc, st = ctx.solve(x, f, method, rtol=1e-9, maxit=300)
+        assert rc == B.SMG_OK
+        _, its, _ = solve()
+        assert abs(st["iterations"] - its) <= 1, (method, st["iterations"], its)
+        torch.cuda.synchronize()
+        xg = node_to_paper(x.cpu().numpy(), p.n, p.N)
+        assert np.linalg.norm(o.residual(xg, fp)) <= 1.01e-9 * np.linalg.norm(fp)
+
+
 def test_paper_l1_setting(B):
     from oracle import ssn
     p = paper_problem(1e-4)
