@@ -122,8 +122,10 @@ typedef struct {
                                  is set, with theta = 1, no node factors and no domain, a whole
                                  red+black sweep is one launch out of place between the level
                                  iterate and a second buffer, reading every face coefficient
-                                 once; both compute the same iteration (the same arithmetic per
-                                 node) */
+                                 once, the coarse correction ahead of post-smoothing is a pass
+                                 over the black nodes only, and the residual is restricted in
+                                 column walks; both compute the same iteration (the same
+                                 arithmetic per node, up to the order of the restriction's sums) */
 
 typedef struct {
   const double *kx;   /* device, [n][n+1][N] */
