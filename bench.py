@@ -282,7 +282,7 @@ def learned_section(dev, n_train=2000, n_test=200, epochs=20):
     """Warm start on 127x127, N=128 (nu log-uniform in [1e-5, 1e-3], y_d random
     sums of three sine products): 2000 multigrid solves as training data, the
     network trained on the GPU by the library's kernels, 200 held-out seeds,
-    judged after one V-cycle against the zero start's first-cycle residual."""
+    checked after one V-cycle against the zero start's first-cycle residual."""
     import numpy as np
     import torch
     from paper_2302_13680_amd import binding, learn
@@ -355,7 +355,7 @@ def ssn_section(dev, n, N, args):
 
 
 def paper_tables(dev):
-    """The settings of the paper's iteration-count tables on this build's grids
+    """The settings of the paper's iteration-count tables on this library's grids
     (finite differences; the paper: P1 elements): the Gaussian-covariance field
     of eq. log_normal, y_d = exp(y^2) sin(2 pi x) sin(2 pi y), no source, damped
     collective Jacobi (theta 1/2) V(2,2), tolerance 1e-9.  Distributed control
@@ -401,7 +401,7 @@ def paper_tables(dev):
 
     out = {"field": "Gaussian covariance (eq. log_normal)", "smoother": "collective Jacobi theta 1/2, V(2,2)",
            "tol": 1e-9, "rows": "as printed (eq. full_space_optimality_system)",
-           "format": "[V-cycles, GMRES] (this build) beside [printed]"}
+           "format": "[V-cycles, GMRES] (this library) beside [printed]"}
     L = dict(domain="lshape")
     t1 = {}
     t1["nu"] = [{"nu": nu, "counts": counts(problem(nu=nu, **L)), "paper": pr}
@@ -598,7 +598,7 @@ def cvar_tables(dev):
            "inner_rule": "printed: max(||F_1||/||F_1(x^0)||, ||F_1||) <= 1e-8, Newton steps backtracking on "
                          "||F_1||, at most 50; inner_stalled counts evaluations that ended at the rounding floor "
                          "(no decrease with ||F_1|| <= 1e-8), inner_capped those that ended at the cap",
-           "format": "[outer, inner Newton, mean GMRES] (this build) beside [outer, inner, mean V-cycles, mean GMRES]"}
+           "format": "[outer, inner Newton, mean GMRES] (this library) beside [outer, inner, mean V-cycles, mean GMRES]"}
     out["mesh"] = []
     for n, nh, pr in ((15, 161, [5, 62, 23.0, 13.9]), (31, 705, [6, 79, 28.0, 15.5]), (63, 2945, [6, 79, 26.2, 14.8])):
         _, _, r = run(problem(n=n), 0.9, 1e-2)
@@ -812,7 +812,7 @@ def main():
                          "restrictions, 2 V-cycles) and a 1 GiB device copy (5x), for hardware-counter passes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
+        print(json.dumps({"error": "this library runs on one GPU only; multi-GPU sharding is a design "
                                    "note, not an implemented path", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

@@ -10,10 +10,10 @@ Training: mean squared error of the per-channel standardized fields over the
 interior nodes, Adam, mini-batches, every step in smg_net_train_step.
 Evaluation: for held-out seeds, V-cycles and wall time to 1e-8 from the zero
 start and from the lifted prediction x0 (smg_net_lift), inference at batch 1.
-The zero start judges the warm start after one V-cycle: the warm solve goes on
+The warm start is checked against the zero start after one V-cycle: the warm solve goes on
 from V(x0) when ||f - S V(x0)|| <= rho0 ||f||, where rho0 is the relative
 residual one V-cycle from zero leaves (the median over the training solves);
-otherwise it falls back to the zero-start solve (the judging cycle is counted).
+otherwise it falls back to the zero-start solve (the checking cycle is counted).
 """
 from __future__ import annotations
 
@@ -171,7 +171,7 @@ def predict(net, feats):
 def evaluate(net, seeds, norm, n=127, N=128, device="cuda", rtol=1e-8, rho0=None):
     """Warm start against zero start on held-out seeds, inference at batch 1 (a
     batch-1 copy of the trained network).  rho0: the zero start's relative
-    residual after one V-cycle (median over the training solves; None: judge by
+    residual after one V-cycle (median over the training solves; None: check
     ||f - S x0|| <= ||f|| before any cycle).  Returns per-seed records."""
     import torch
     H = grid_for(n)
@@ -198,7 +198,7 @@ def evaluate(net, seeds, norm, n=127, N=128, device="cuda", rtol=1e-8, rho0=None
         fnorm = float(torch.linalg.norm(inst.f))
         k = inst.nu / N                      # mean(p) = nu/N times the third field
         lift_norm = norm[:2] + [norm[2] * k] + norm[3:5] + [norm[5] * k]
-        # warm start: features -> network -> lift -> one V-cycle -> judge -> solve
+        # warm start: features -> network -> lift -> one V-cycle -> check -> solve
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         binding.net_features(inst.ctx, inst.f, H, feat[0])
@@ -209,14 +209,14 @@ def evaluate(net, seeds, norm, n=127, N=128, device="cuda", rtol=1e-8, rho0=None
         rn0 = inst.ctx.residual(x, inst.f, r, norms=True)
         if rho0 is None:
             fell_back = not (rn0[0] <= fnorm)
-            judge_cycles = 0
+            check_cycles = 0
             rel1 = None
         else:
             inst.ctx.vcycle(x, inst.f, 1)
             rn1 = inst.ctx.residual(x, inst.f, r, norms=True)
             rel1 = rn1[0] / fnorm
             fell_back = not (rel1 <= rho0)
-            judge_cycles = 1
+            check_cycles = 1
         if fell_back:
             x.zero_()
         rc, st = inst.ctx.solve(x, inst.f, binding.SMG_VCYCLE, rtol=rtol, maxit=100, history=0)
@@ -236,7 +236,7 @@ def evaluate(net, seeds, norm, n=127, N=128, device="cuda", rtol=1e-8, rho0=None
         torch.cuda.synchronize()
         t_lifted = 1e3 * (time.perf_counter() - t1)
         recs.append(dict(seed=s, nu=inst.nu, zero_cycles=st0["iterations"], zero_ms=t_zero,
-                         warm_cycles=st["iterations"] + judge_cycles, warm_ms=t_warm, fell_back=fell_back,
+                         warm_cycles=st["iterations"] + check_cycles, warm_ms=t_warm, fell_back=fell_back,
                          warm_cycles_no_fallback=st2["iterations"], warm_ms_no_fallback=t_inf + t_lifted,
                          inference_ms=t_inf, pred_rel_err=err, mean_pred_rel_err=err_mean,
                          x0_relres=rn0[0] / fnorm, relres_after_one_cycle=rel1, rho0=rho0,

@@ -143,12 +143,12 @@ def test_warm_start_gain_small(B):
             assert r["warm_cycles"] == r["zero_cycles"]
 
 
-def test_warm_start_on_the_learned_workload_judged_after_one_cycle(B):
+def test_warm_start_on_the_learned_workload_checked_after_one_cycle(B):
     """127x127, N = 128 (the learned workload's grid and samples), trained on 400
-    multigrid solves, 24 held-out seeds, the zero start judging the warm start
+    multigrid solves, 24 held-out seeds, the zero start checking the warm start
     after one V-cycle (||f - S V(x0)|| against the median relative residual one
     cycle from zero leaves on the training solves): the warm start is kept on
-    most seeds and, counting the judging cycle, needs fewer V-cycles than the
+    most seeds and, counting the checking cycle, needs fewer V-cycles than the
     zero start; every solve converges.  Wall time (inference at batch 1
     included) is reported, not asserted: the broadcast lift cannot carry the
     per-sample part of the state, so the warm start saves well under one cycle
