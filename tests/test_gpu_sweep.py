@@ -107,12 +107,15 @@ def test_fp32_sweep_equals_two_halfsweeps(B, O, n, N):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_vcycles_with_and_without_one_launch_sweeps(B, O, precision):
-    """255x255, N = 64 with 32-row segments: levels 255, 127, 63 and below sweep
-    in one launch (zero start on the coarse levels, prolongation folded into the
-    first post sweep); iterates equal those of the half-sweep cycle and the
-    oracle's."""
-    p = inputs.make_problem(255, 64, 1e-4, M=6, sigma=0.5, decay=True, seed=21)
+@pytest.mark.parametrize("n,N", [(255, 64), (127, 200), (127, 193)])
+def test_vcycles_with_and_without_one_launch_sweeps(B, O, precision, n, N):
+    """32-row segments: every level sweeps in one launch (zero start on the
+    coarse levels, the coarse correction added at the black nodes ahead of
+    post-smoothing, the residual restricted in column walks); iterates equal
+    those of the half-sweep cycle and the oracle's.  N = 64: one sample per
+    lane; 200: four per lane in pairs (16-byte FP64 accesses) with a ragged
+    tail; 193: four per lane one at a time."""
+    p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=21)
     o = O.Oracle(p)
     fp = p.rhs_paper()
     c1, f = B.context_from_problem(p, gmres_restart=0, precision=precision, sweep_rows=32)
