@@ -1,6 +1,7 @@
 """The 511x511, N=256 workload at full size, in the launch configuration the
 solver runs: FP64 V-cycle iterates against the oracle in every block (Y, U, P),
-the FP32-refined solution checked by the oracle's own FP64 residual, and its
+the FP32-refined solution and the benchmarked FP64 GMRES(30) solution checked by
+the oracle's own FP64 residual, and the refined solution's
 per-field error against the oracle's FP64 solution.
 
 The oracle takes ~2-5 s per V-cycle at this size on the GPU host's cores.
@@ -77,3 +78,24 @@ def test_large_fp32_refinement_meets_oracle_residual(B, problem):
     assert hist[-1] <= 7e-11, hist[-5:]
     e = assert_blocks(xg, x_ref, p.n, p.N, 1e-7)
     print("511x511 FP32-refined per-field error vs the FP64 oracle:", e, flush=True)
+
+
+def test_large_gmres_meets_oracle_residual(B, problem):
+    """The benchmarked configuration itself: FP64 GMRES(30) right-preconditioned
+    by one V(2,2) from zero to 1e-8, the solution checked by the oracle's own FP64
+    residual, in total and per block row."""
+    p, o = problem
+    ctx, f = B.context_from_problem(p, gmres_restart=30)
+    x = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    rc, st = ctx.solve(x, f, B.SMG_GMRES, rtol=1e-8, maxit=60, history=0)
+    assert rc == B.SMG_OK, st
+    assert 5 <= st["iterations"] <= 15, st
+    torch.cuda.synchronize()
+    fp = p.rhs_paper()
+    xg = node_to_paper(x.cpu().numpy(), p.n, p.N)
+    r = o.residual(xg, fp)
+    nf = np.linalg.norm(fp)
+    assert np.linalg.norm(r) <= 1.01e-8 * nf
+    n2, N = p.n * p.n, p.N
+    for blk in (r[:N * n2], r[N * n2:(N + 1) * n2], r[(N + 1) * n2:]):
+        assert np.linalg.norm(blk) <= 1.01e-8 * nf
