@@ -181,3 +181,146 @@ void k_rr_walk(LevelArgs<T> L, const T* __restrict__ x, const T* __restrict__ f,
 }
 
 }  // namespace smg
+
+namespace smg {
+
+// One FP32-refinement update fused with the next residual, in column walks:
+// x_next = x + d (d: the FP32 correction of the cycle) and out = f - S x_next
+// rounded to FP32, the arithmetic of residual_add_node (residual.h) per node.
+// The per-node form reads x and d of all four neighbours of every node (about
+// five times each overall); here a wavefront owns one column c over a segment of
+// rows and walks it upwards, keeping x + d of rows r-1 and r and the S face of
+// row r in registers, so a step loads x and d of (c, r+1) and of the two side
+// neighbours once.  Per-block squared norms {r_Y, r_U, r_P, f} into partials
+// (every wave of a block takes part in the final block sum).  No node factors,
+// no domain; 64 lanes per node.
+template <int JM, int VW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_residual_add_walk(LevelArgs<double> L, const double* __restrict__ x, const float* __restrict__ d,
+                         double* __restrict__ xn, const double* __restrict__ f, float* __restrict__ out,
+                         double* __restrict__ partials, int seg) {
+  constexpr int kWaves = kBlock / 64;
+  const int n = L.n, N = L.N;
+  __shared__ double cde[3 * 64 * JM];
+  for (int j = threadIdx.x; j < N; j += kBlock) {
+    cde[j] = L.c[j];
+    cde[N + j] = L.d[j];
+    cde[2 * N + j] = L.e[j];
+  }
+  __syncthreads();
+  const size_t nn = (size_t)n * n;
+  const size_t oU = (size_t)N * nn, oP = (size_t)(N + 1) * nn;
+  const int npg = (n + kWaves - 1) / kWaves, nseg = (n + seg - 1) / seg;
+  const int t = xcd_remap(blockIdx.x, npg * nseg);
+  const int g = t / npg, pg = t - g * npg;
+  const int c = __builtin_amdgcn_readfirstlane(pg * kWaves + (int)threadIdx.x / 64);
+  const int lane = threadIdx.x & 63;
+  const int r0 = g * seg, r1 = min(n, r0 + seg);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (c < n && r0 < r1) {
+    auto cl = [&](int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); };
+    auto nd = [&](int col, int row) { return (size_t)cl(row, n - 1) * n + cl(col, n - 1); };
+    // x + d of VW samples per access, both fields of node k
+    auto xd = [&](size_t k, NodeYP<double, JM>& o) {
+#pragma unroll
+      for (int ch = 0; ch < JM / VW; ++ch) {
+        const int j0 = VW * (lane + ch * 64);
+        const int j = j0 < N ? j0 : N - VW;
+        double xv[VW], xw[VW];
+        float dv[VW], dw[VW];
+        ldv<VW>(x + k * N + j, xv);
+        ldv<VW>(d + k * N + j, dv);
+        ldv<VW>(x + oP + k * N + j, xw);
+        ldv<VW>(d + oP + k * N + j, dw);
+#pragma unroll
+        for (int u = 0; u < VW; ++u) {
+          o.y[ch * VW + u] = xv[u] + (double)dv[u];
+          o.p[ch * VW + u] = xw[u] + (double)dw[u];
+        }
+      }
+    };
+    const bool hw = c > 0, he = c < n - 1;
+    NodeYP<double, JM> xp, xc;
+    double ks[JM];
+    xd(nd(c, r0 - 1), xp);
+    xd(nd(c, r0), xc);
+    ldn<double, JM, VW>(L.ky + ((size_t)r0 * n + c) * N, N, lane, ks);
+    for (int r = r0; r < r1; ++r) {
+      const bool hs = r > 0, hn = r < n - 1;
+      const size_t node = (size_t)r * n + c;
+      NodeYP<double, JM> xq, xw, xe;
+      double kw[JM], ke[JM], kn[JM], fy[JM], fp[JM];
+      xd(nd(c, r + 1), xq);
+      xd(nd(c - 1, r), xw);
+      xd(nd(c + 1, r), xe);
+      ldn<double, JM, VW>(L.kx + ((size_t)r * (n + 1) + c) * N, N, lane, kw);
+      ldn<double, JM, VW>(L.kx + ((size_t)r * (n + 1) + c + 1) * N, N, lane, ke);
+      ldn<double, JM, VW>(L.ky + ((size_t)(r + 1) * n + c) * N, N, lane, kn);
+      ldn<double, JM, VW>(f + node * N, N, lane, fy);
+      ldn<double, JM, VW>(f + oP + node * N, N, lane, fp);
+      const double u = x[oU + node] + (double)d[oU + node];
+      double dsum = 0.0;
+      float ry[JM], rp[JM];
+#pragma unroll
+      for (int q = 0; q < JM; ++q) {
+        const int j = VW * (lane + (q / VW) * 64) + q % VW;
+        const bool act = j < N;
+        const int jj = act ? j : N - 1;
+        auto nbsum = [&](double vw, double ve, double vs, double vn) {
+          return ((hw ? kw[q] * vw : 0.0) + (he ? ke[q] * ve : 0.0)) + ((hs ? ks[q] * vs : 0.0) + (hn ? kn[q] * vn : 0.0));
+        };
+        const double sy = nbsum(xw.y[q], xe.y[q], xp.y[q], xq.y[q]);
+        const double sp = nbsum(xw.p[q], xe.p[q], xp.p[q], xq.p[q]);
+        const double a = (kw[q] + ke[q]) + (ks[q] + kn[q]);
+        const double rY = fy[q] - (cde[jj] * xc.y[q] + (a * xc.p[q] - sp));
+        const double rP = fp[q] - ((a * xc.y[q] - sy) + cde[2 * N + jj] * u);
+        dsum += act ? cde[N + jj] * xc.p[q] : 0.0;
+        ry[q] = (float)rY;
+        rp[q] = (float)rP;
+        if (act) {
+          acc[0] += rY * rY;
+          acc[2] += rP * rP;
+          acc[3] += fy[q] * fy[q] + fp[q] * fp[q];
+        }
+      }
+#pragma unroll
+      for (int ch = 0; ch < JM / VW; ++ch) {
+        const int j0 = VW * (lane + ch * 64);
+        if (j0 < N) {
+          double ty[VW], tp[VW];
+          float sy2[VW], sp2[VW];
+#pragma unroll
+          for (int u2 = 0; u2 < VW; ++u2) {
+            ty[u2] = xc.y[ch * VW + u2];
+            tp[u2] = xc.p[ch * VW + u2];
+            sy2[u2] = ry[ch * VW + u2];
+            sp2[u2] = rp[ch * VW + u2];
+          }
+          stv_nt<VW>(xn + node * N + j0, ty);
+          stv_nt<VW>(xn + oP + node * N + j0, tp);
+          stv_nt<VW>(out + node * N + j0, sy2);
+          stv_nt<VW>(out + oP + node * N + j0, sp2);
+        }
+      }
+      const double D = group_sum<64>(dsum);
+      if (lane == 0) {
+        const double fu = f[oU + node];
+        const double rU = fu - (L.g * u + D);
+        xn[oU + node] = u;
+        out[oU + node] = (float)rU;
+        acc[1] += rU * rU;
+        acc[3] += fu * fu;
+      }
+      xp = xc;
+      xc = xq;
+      cpy(ks, kn);
+    }
+  }
+  block_sum<4>(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) partials[4 * (size_t)blockIdx.x + i] = acc[i];
+  }
+}
+
+}  // namespace smg

@@ -797,11 +797,28 @@ int residual(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, i
 int residual_add(smg_ctx* C, const double* x, const float* d, double* xn, const double* f, float* out) {
   const Level<double>& L = C->L64[0];
   const size_t nn = (size_t)L.n * L.n;
+  // column walks (k_residual_add_walk) on a level that streams from HBM
+  const bool walk = !C->masked && !C->domain && one_launch_desc(C->desc, L.n);
   lane_dispatch<false>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
     const int per = kBlock / W;
-    const int nb = (int)((nn + per - 1) / per);
-    mask_dispatch(C->masked, [&](auto Mc) {
+    int nb = (int)((nn + per - 1) / per);
+    bool walked = false;
+    if constexpr (W == 64 && JM <= 4) {
+      if (walk) {
+        auto go = [&](auto kern) {
+          static const int resident = resident_waves(reinterpret_cast<const void*>(kern));
+          const int nseg = std::max(1, resident / L.n), seg = (L.n + nseg - 1) / nseg;
+          nb = ((L.n + kBlock / 64 - 1) / (kBlock / 64)) * ((L.n + seg - 1) / seg);
+          hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N, C->desc.strip), x, d, xn, f,
+                             out, C->partials, seg);
+        };
+        if (JM % 2 == 0 && C->N % 2 == 0) go(k_residual_add_walk<JM, (JM % 2 == 0 ? 2 : 1)>);
+        else go(k_residual_add_walk<JM, 1>);
+        walked = true;
+      }
+    }
+    if (!walked) mask_dispatch(C->masked, [&](auto Mc) {
       // two samples per access (16-byte FP64, 8-byte FP32) where N is even
       if constexpr (W == 64 && JM % 2 == 0) {
         if (C->N % 2 == 0) {

@@ -152,3 +152,27 @@ def test_large_level_takes_the_one_launch_sweep_by_default(B):
     assert not c2.sweep(0, xin, b, f)
     rel = (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
     assert rel <= 1e-15, rel
+
+
+@pytest.mark.parametrize("N", [200, 193])
+def test_fp32_refinement_with_column_walks(B, O, N):
+    """FP32 cycles in FP64 refinement where the refinement residual runs in column
+    walks (k_residual_add_walk, forced here by a segment length): the solution meets
+    1e-10 in the oracle's FP64 residual, in total and per block row, with the
+    oracle's refinement count within one."""
+    p = inputs.make_problem(127, N, 1e-4, M=6, sigma=0.5, decay=True, seed=5)
+    o = O.Oracle(p)
+    ctx, f = B.context_from_problem(p, gmres_restart=0, precision=B.SMG_F32, sweep_rows=8)
+    x = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    rc, st = ctx.solve(x, f, B.SMG_VCYCLE, rtol=1e-10, maxit=60)
+    assert rc == B.SMG_OK, st
+    fp = p.rhs_paper()
+    xg = node_to_paper(host(x), p.n, p.N)
+    r = o.residual(xg, fp)
+    nf = np.linalg.norm(fp)
+    nn = p.n * p.n
+    assert np.linalg.norm(r) <= 1e-10 * nf
+    for blk in (r[:N * nn], r[N * nn:(N + 1) * nn], r[(N + 1) * nn:]):
+        assert np.linalg.norm(blk) <= 1e-10 * nf
+    _, its, _, _ = o.solve_ir(fp, tol=1e-10, m=0)
+    assert abs(st["iterations"] - its) <= 1, (st["iterations"], its)
