@@ -117,7 +117,7 @@ typedef struct {
                                  rank-one vectors z_j and per-sample arrays); FP64 contexts only */
 #define SMG_FLAG_HALFSWEEPS 32 /* smooth with one launch per colour on every level.  By default,
                                  on levels whose two half-sweeps move at least 512 MB with
-                                 129..256 samples (four per lane), and on every level with 33..256
+                                 65..256 samples (two to four per lane), and on every level with 33..256
                                  samples (64 lanes per node; FP32 pairs: 65..256) when sweep_rows
                                  is set, with theta = 1, no node factors and no domain, a whole
                                  red+black sweep is one launch out of place between the level

@@ -171,13 +171,15 @@ void smoother_layout(int precision, int N, int* W, int* JM) {
 // Where a sweep runs as one launch (k_sweep_fused).  The one-launch sweep reads
 // every face once but recomputes the reds at the pair borders and walks each
 // column in serial steps of one memory round trip each, so it needs enough work
-// per step (four samples per lane, N = 129..256) and a level that streams from
-// HBM.  Measured (one-launch against two half-sweeps, us): 511x511, N=256 FP64
-// 890 / 1080, FP32 440 / 517; 255x255, N=256 FP64 247-270 / 272-278, FP32
-// 123 / 139; but 255x255, N=128 FP64 141 / 141 (two samples per lane), 511x511,
-// N=64 FP64 329 / 282 (one), and 255x255, N=64 FP64 59 / 54 (cache resident).
+// per step (two or more samples per lane, N = 65..256) and a level that streams
+// from HBM.  Measured (one-launch against two half-sweeps, us, 16-byte FP64
+// pairs): 511x511, N=256 FP64 788 / 1225, FP32 428 / 518; N=192 (three samples
+// per lane, one per access) 255x255 FP64 213 / 323, FP32 107 / 151; N=128
+// 511x511 FP64 450 / 755, FP32 323 / 397, 255x255 FP64 128 / 198; but with one
+// sample per lane (N = 64) 511x511 FP64 384 / 393, and 255x255, N=64 FP64 59 /
+// 54 (cache resident).
 constexpr double kOneLaunchMinBytes = 512e6;
-constexpr int kOneLaunchJM = 4;
+constexpr int kOneLaunchMinJM = 2;
 
 // Levels of this descriptor whose sweeps can run as one launch (the context's
 // node factors and domain are checked at run time).
@@ -189,7 +191,7 @@ bool one_launch_desc(const smg_desc& d, int n) {
   int W = 0, JM = 0;
   smoother_layout(d.precision, d.nsamples, &W, &JM);
   if (W != 64 || JM > 4) return false;
-  return d.sweep_rows > 0 || JM == kOneLaunchJM;
+  return d.sweep_rows > 0 || JM >= kOneLaunchMinJM;
 }
 
 int count_levels(int n, int nc) {

@@ -138,10 +138,12 @@ def test_vcycles_with_and_without_one_launch_sweeps(B, O, precision, n, N):
         print("cycle", k, "one-launch vs half-sweeps", e1, "vs oracle", e2, flush=True)
 
 
-def test_large_level_takes_the_one_launch_sweep_by_default(B):
-    """511x511, N = 256 (a level that streams from HBM): the default context sweeps
-    in one launch, SMG_FLAG_HALFSWEEPS does not, and both give the same sweep."""
-    p = inputs.large_mixed()
+@pytest.mark.parametrize("N", [256, 128])
+def test_large_level_takes_the_one_launch_sweep_by_default(B, N):
+    """511x511, N = 256 or 128 (levels that stream from HBM; four or two samples
+    per lane): the default context sweeps in one launch, SMG_FLAG_HALFSWEEPS does
+    not, and both give the same sweep."""
+    p = inputs.large_mixed() if N == 256 else inputs.make_problem(511, N, 1e-4, M=6, sigma=1.0, decay=True, seed=2)
     ctx, f = B.context_from_problem(p, gmres_restart=0)
     xin = torch.rand(p.dof, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
     a = torch.empty_like(xin)
