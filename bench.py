@@ -85,8 +85,9 @@ def time_halfsweep(ctx, x, f, stream, launches, fp32=False):
 def halfsweep_counter_run(ctx, x, f, n, N):
     """20 finest-level sweeps (one launch each where the level takes the
     one-launch sweep, else 40 half-sweeps), finest-level residuals and
-    residual + restrictions, 2 V-cycles, then five 1 GiB device copies (the
-    calibration of the traffic counters)."""
+    residual + restrictions (from f, then from the last sweep's change of the
+    black nodes), 2 V-cycles, then five 1 GiB device copies (the calibration of
+    the traffic counters)."""
     import torch
     xb = torch.empty_like(x)
     one = ctx.sweep(0, x, xb, f)
@@ -97,7 +98,7 @@ def halfsweep_counter_run(ctx, x, f, n, N):
             ctx.smooth(0, 0, x, f)
             ctx.smooth(0, 1, x, f)
     # the other finest-level passes of a cycle: 5 operator residuals (r written,
-    # norms), 5 fused residual + restrictions, then 2 V-cycles (zero-start and
+    # norms), 5 + 5 fused residual + restrictions, then 2 V-cycles (zero-start and
     # plain sweeps, the black-node prolongation, every coarser level)
     r = torch.empty_like(x)
     coarse = torch.empty(ctx.vlen(1), dtype=torch.float64, device=x.device)
@@ -105,6 +106,9 @@ def halfsweep_counter_run(ctx, x, f, n, N):
         ctx.residual(x, f, r, norms=True)
     for _ in range(5):
         ctx.residual_restrict(0, x, f, coarse)
+    if one:   # x is the last sweep of xb: the restriction from the blacks' change
+        for _ in range(5):
+            ctx.residual_restrict_after_sweep(0, xb, x, f, coarse)
     ctx.vcycle(x, f, 2)
     a = torch.ones(1 << 27, dtype=torch.float64, device=x.device)   # 1 GiB
     b = torch.empty_like(a)

@@ -290,6 +290,21 @@ int smg_jacobi(smg_ctx *ctx, int level, const double *x, double *xout, const dou
  * SMG_EINVAL if `level` has no coarser level. */
 int smg_residual_restrict(smg_ctx *ctx, int level, const double *x, const double *f, double *coarse);
 
+/* The same restriction right after a sweep (Alg. 1's residual following the
+ * pre-smoothing, Section 3 with collective Gauss-Seidel): xnew must be one
+ * smg_sweep of xold with right-hand side f (theta = 1); xold, xnew, f: FP64
+ * device vectors of level `level` (xold and xnew distinct), coarse: level + 1.
+ * Each node solve makes its own block row exact for the values it read, so the
+ * black rows and every U row of f - S xnew vanish and a red row is the coupling
+ * through its four faces to the blacks' change xnew - xold; where the column
+ * walk applies (the one-launch sweep's levels, see SMG_FLAG_HALFSWEEPS) coarse
+ * is formed from that change without reading f and *from_change (may be NULL)
+ * is set to 1; otherwise it is smg_residual_restrict(xnew, f) and 0.  Equal to
+ * R (f - S xnew) up to the rounding of the node solves.  SMG_EINVAL as
+ * smg_residual_restrict, or for xold == xnew. */
+int smg_residual_restrict_after_sweep(smg_ctx *ctx, int level, const double *xold, const double *xnew,
+                                      const double *f, double *coarse, int *from_change);
+
 /* fine += P coarse (bilinear interpolation; Alg. 1 coarse correction).  The U
  * block is prolongated into the control space only: fine nodes whose factors
  * of D_j and E_j are both zero (no control there, e.g. outside a local control

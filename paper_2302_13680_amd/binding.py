@@ -31,7 +31,7 @@ EXPORTED = [
     "smg_workspace_bytes", "smg_setup", "smg_destroy", "smg_strerror", "smg_last_error",
     "smg_num_levels", "smg_level_n", "smg_apply", "smg_residual", "smg_residual_static", "smg_smooth", "smg_smooth32", "smg_sweep",
     "smg_sweep32", "smg_stream_copy", "smg_restrict",
-    "smg_residual_restrict", "smg_jacobi", "smg_prolong_add", "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond",
+    "smg_residual_restrict", "smg_residual_restrict_after_sweep", "smg_jacobi", "smg_prolong_add", "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond",
     "smg_solve", "smg_batch_workspace_bytes", "smg_batch_setup", "smg_batch_solve", "smg_batch_destroy",
     "smg_batch_last_error", "smg_tune_lanes", "smg_net_param_count", "smg_net_workspace_bytes",
     "smg_net_setup", "smg_net_destroy", "smg_net_last_error", "smg_net_set_params", "smg_net_get_params",
@@ -146,6 +146,7 @@ def load(path: str = LIB_PATH):
     L.smg_stream_copy.restype = i
     L.smg_restrict.argtypes = [vp, i, vp, vp]
     L.smg_residual_restrict.argtypes = [vp, i, vp, vp, vp]
+    L.smg_residual_restrict_after_sweep.argtypes = [vp, i, vp, vp, vp, vp, C.POINTER(i)]
     L.smg_jacobi.argtypes = [vp, i, vp, vp, vp]
     L.smg_prolong_add.argtypes = [vp, i, vp, vp]
     L.smg_coarse_solve.argtypes = [vp, vp, vp]
@@ -199,7 +200,8 @@ def load(path: str = LIB_PATH):
                                  C.POINTER(CvarStats)]
     for name in ["smg_set_sample_weights", "smg_set_lowrank", "smg_cvar_solve"]:
         getattr(L, name).restype = i
-    for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_stream_copy", "smg_restrict", "smg_residual_restrict", "smg_jacobi", "smg_prolong_add",
+    for name in ["smg_apply", "smg_residual", "smg_smooth", "smg_smooth32", "smg_stream_copy", "smg_restrict", "smg_residual_restrict",
+                 "smg_residual_restrict_after_sweep", "smg_jacobi", "smg_prolong_add",
                  "smg_coarse_solve", "smg_level_faces", "smg_vcycle", "smg_gmres_precond", "smg_solve",
                  "smg_num_levels", "smg_level_n"]:
         getattr(L, name).restype = i
@@ -331,6 +333,14 @@ class Context:
 
     def residual_restrict(self, level, x, f, coarse):
         return self._check(self.L.smg_residual_restrict(self.ctx, level, _ptr(x), _ptr(f), _ptr(coarse)))
+
+    def residual_restrict_after_sweep(self, level, xold, xnew, f, coarse):
+        """coarse = R (f - S xnew) for xnew one sweep of xold; returns True where it
+        was formed from the blacks' change (f not read)."""
+        fc = C.c_int(0)
+        self._check(self.L.smg_residual_restrict_after_sweep(self.ctx, level, _ptr(xold), _ptr(xnew), _ptr(f),
+                                                             _ptr(coarse), C.byref(fc)))
+        return bool(fc.value)
 
     def prolong_add(self, level, coarse, fine):
         return self._check(self.L.smg_prolong_add(self.ctx, level, _ptr(coarse), _ptr(fine)))

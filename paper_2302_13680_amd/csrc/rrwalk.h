@@ -180,6 +180,155 @@ void k_rr_walk(LevelArgs<T> L, const T* __restrict__ x, const T* __restrict__ f,
   }
 }
 
+// The same restriction right after a Gauss-Seidel sweep xold -> xnew (theta = 1,
+// red then black), from the black nodes' change alone.  Every node solve makes
+// its own block row of eq. (2) exact for the neighbour values it read: a black
+// node read the final reds, so its residual is zero; a red node read the old
+// blacks, so its residual is what the blacks' change adds to the coupling
+// terms, r_Y = sum_nb k (p_new - p_old)_nb and r_P = sum_nb k (y_new - y_old)_nb
+// over its four faces; and the U row couples no neighbours, so it is zero at
+// every node.  The result equals R (f - S xnew) up to the rounding of the node
+// solves, without reading f, u or the red values: 2 words per node-sample of
+// faces and 2 of black values (old and new) instead of 6.  Full weighting then
+// takes the centre of each 3 x 3 fine window (weight 1) and its four corners
+// (1/4), the red ones.  A wave owns coarse column X, walks fine rows two at a
+// time (an odd row: the centre red 2X+1; an even row: the corner reds 2X and
+// 2X+2) and keeps the black changes of the last two rows in registers.
+template <typename T, int JM, int VW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_rr_gs_walk(LevelArgs<T> L, const T* __restrict__ xold, const T* __restrict__ xnew, T* __restrict__ coarse,
+                  int seg) {
+  constexpr int kWaves = kBlock / 64;
+  const int n = L.n, N = L.N;
+  const int nc = (n - 1) / 2;
+  const size_t nn = (size_t)n * n, nnc = (size_t)nc * nc;
+  const int npg = (nc + kWaves - 1) / kWaves, nseg = (nc + seg - 1) / seg;
+  const int t = xcd_remap(blockIdx.x, npg * nseg);
+  const int g = t / npg, pg = t - g * npg;
+  const int X = __builtin_amdgcn_readfirstlane(pg * kWaves + (int)threadIdx.x / 64);
+  const int lane = threadIdx.x & 63;
+  if (X >= nc) return;   // whole waves; no barriers in this kernel
+  const int K0 = g * seg, K1 = min(nc, K0 + seg);
+  if (K0 >= K1) return;
+  const int c0 = 2 * X;                       // fine columns c0, c0 + 1, c0 + 2
+  auto cl = [&](int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); };
+  auto nd = [&](int col, int row) { return (size_t)cl(row, n - 1) * n + cl(col, n - 1); };
+  auto kxp = [&](int row, int fc) { return L.kx + ((size_t)cl(row, n - 1) * (n + 1) + cl(fc, n)) * N; };
+  auto kyp = [&](int fr, int col) { return L.ky + ((size_t)cl(fr, n) * n + cl(col, n - 1)) * N; };
+  // new minus old y and p of a node (indices clamped; off-grid ones are never used)
+  auto dl = [&](int col, int row, NodeYP<T, JM>& o) {
+    NodeYP<T, JM> a;
+    ld_yp<T, JM, VW>(xnew, nn, N, nd(col, row), lane, o);
+    ld_yp<T, JM, VW>(xold, nn, N, nd(col, row), lane, a);
+#pragma unroll
+    for (int q = 0; q < JM; ++q) {
+      o.y[q] -= a.y[q];
+      o.p[q] -= a.p[q];
+    }
+  };
+  // residual of the red node (xx, r) from its neighbours' changes
+  auto red = [&](int xx, int r, const T (&kw)[JM], const T (&ke)[JM], const T (&kS)[JM], const T (&kN)[JM],
+                 const NodeYP<T, JM>& w, const NodeYP<T, JM>& e, const NodeYP<T, JM>& so,
+                 const NodeYP<T, JM>& no, T (&rY)[JM], T (&rP)[JM]) {
+    const bool hw = xx > 0, he = xx < n - 1, hs = r > 0, hn = r < n - 1;
+#pragma unroll
+    for (int q = 0; q < JM; ++q) {
+      auto nbsum = [&](T vw, T ve, T vs, T vn) -> T {
+        return ((hw ? kw[q] * vw : T(0)) + (he ? ke[q] * ve : T(0))) + ((hs ? kS[q] * vs : T(0)) + (hn ? kN[q] * vn : T(0)));
+      };
+      rY[q] = nbsum(w.p[q], e.p[q], so.p[q], no.p[q]);
+      rP[q] = nbsum(w.y[q], e.y[q], so.y[q], no.y[q]);
+    }
+  };
+  // even row r: the corner reds c0 and c0 + 2, weighted 1/2 across the columns;
+  // E: black changes of row r at c0 - 1, c0 + 1, c0 + 3; Os, On: rows r - 1 and
+  // r + 1 at c0, c0 + 2
+  auto even_row = [&](int r, const NodeYP<T, JM> (&E)[3], const NodeYP<T, JM> (&Os)[2],
+                      const NodeYP<T, JM> (&On)[2], T (&hY)[JM], T (&hP)[JM]) {
+    T k0[JM], k1[JM], k2[JM], k3[JM], s0[JM], n0[JM], s2[JM], n2[JM];
+    ldn<T, JM, VW>(kxp(r, c0), N, lane, k0);
+    ldn<T, JM, VW>(kxp(r, c0 + 1), N, lane, k1);
+    ldn<T, JM, VW>(kxp(r, c0 + 2), N, lane, k2);
+    ldn<T, JM, VW>(kxp(r, c0 + 3), N, lane, k3);
+    ldn<T, JM, VW>(kyp(r, c0), N, lane, s0);
+    ldn<T, JM, VW>(kyp(r + 1, c0), N, lane, n0);
+    ldn<T, JM, VW>(kyp(r, c0 + 2), N, lane, s2);
+    ldn<T, JM, VW>(kyp(r + 1, c0 + 2), N, lane, n2);
+    T uY[JM], uP[JM], vY[JM], vP[JM];
+    red(c0, r, k0, k1, s0, n0, E[0], E[1], Os[0], On[0], uY, uP);
+    red(c0 + 2, r, k2, k3, s2, n2, E[1], E[2], Os[1], On[1], vY, vP);
+#pragma unroll
+    for (int q = 0; q < JM; ++q) {
+      hY[q] = T(0.5) * uY[q] + T(0.5) * vY[q];
+      hP[q] = T(0.5) * uP[q] + T(0.5) * vP[q];
+    }
+  };
+  auto st_cached = [&](T* p, const T (&v)[JM]) {
+#pragma unroll
+    for (int c = 0; c < JM / VW; ++c) {
+      const int j0 = VW * (lane + c * 64);
+      if (j0 < N) {
+        T t2[VW];
+#pragma unroll
+        for (int u = 0; u < VW; ++u) t2[u] = v[c * VW + u];
+        stv<VW>(p + j0, t2);
+      }
+    }
+  };
+
+  // the first even row 2 K0 starts coarse row K0 with weight 1/2
+  NodeYP<T, JM> Ec[3], Oc[2], Op[2];
+  const int rb = 2 * K0;
+  dl(c0, rb - 1, Op[0]);
+  dl(c0 + 2, rb - 1, Op[1]);
+  dl(c0 - 1, rb, Ec[0]);
+  dl(c0 + 1, rb, Ec[1]);
+  dl(c0 + 3, rb, Ec[2]);
+  dl(c0, rb + 1, Oc[0]);
+  dl(c0 + 2, rb + 1, Oc[1]);
+  T aY[JM], aP[JM];
+  {
+    T hY[JM], hP[JM];
+    even_row(rb, Ec, Op, Oc, hY, hP);
+#pragma unroll
+    for (int q = 0; q < JM; ++q) { aY[q] = T(0.5) * hY[q]; aP[q] = T(0.5) * hP[q]; }
+  }
+  for (int K = K0; K < K1; ++K) {
+    const int ro = 2 * K + 1, re = 2 * K + 2;   // the centre row, then the even row ending K
+    NodeYP<T, JM> En[3], On[2];
+    dl(c0 - 1, re, En[0]);
+    dl(c0 + 1, re, En[1]);
+    dl(c0 + 3, re, En[2]);
+    dl(c0, re + 1, On[0]);
+    dl(c0 + 2, re + 1, On[1]);
+    // centre red (c0 + 1, ro): W, E the blacks of row ro, S, N column c0 + 1 of rows ro -/+ 1
+    {
+      T kw[JM], ke[JM], kS[JM], kN[JM], rY[JM], rP[JM];
+      ldn<T, JM, VW>(kxp(ro, c0 + 1), N, lane, kw);
+      ldn<T, JM, VW>(kxp(ro, c0 + 2), N, lane, ke);
+      ldn<T, JM, VW>(kyp(ro, c0 + 1), N, lane, kS);
+      ldn<T, JM, VW>(kyp(ro + 1, c0 + 1), N, lane, kN);
+      red(c0 + 1, ro, kw, ke, kS, kN, Oc[0], Oc[1], Ec[1], En[1], rY, rP);
+#pragma unroll
+      for (int q = 0; q < JM; ++q) { aY[q] += rY[q]; aP[q] += rP[q]; }
+    }
+    T hY[JM], hP[JM];
+    even_row(re, En, Oc, On, hY, hP);
+#pragma unroll
+    for (int q = 0; q < JM; ++q) { aY[q] += T(0.5) * hY[q]; aP[q] += T(0.5) * hP[q]; }
+    const size_t cn = (size_t)K * nc + X;
+    st_cached(coarse + cn * N, aY);   // read by the next level right away
+    st_cached(coarse + (size_t)(N + 1) * nnc + cn * N, aP);
+    if (lane == 0) coarse[(size_t)N * nnc + cn] = T(0);
+#pragma unroll
+    for (int q = 0; q < JM; ++q) { aY[q] = T(0.5) * hY[q]; aP[q] = T(0.5) * hP[q]; }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Ec[c] = En[c];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) Oc[c] = On[c];
+  }
+}
+
 }  // namespace smg
 
 namespace smg {

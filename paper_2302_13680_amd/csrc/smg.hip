@@ -883,6 +883,33 @@ bool rr_walk(smg_ctx* C, const Level<T>& L, const T* x, const T* f, T* coarse) {
   return launched;
 }
 
+// coarse = R (f - S xnew) where xnew is one Gauss-Seidel sweep of xold (theta =
+// 1, same f), from the blacks' change (k_rr_gs_walk) on the levels the column
+// walk takes; false elsewhere (the caller then forms the residual from f).
+template <typename T>
+bool rr_gs_walk(smg_ctx* C, const Level<T>& L, const T* xold, const T* xnew, T* coarse) {
+  if (C->desc.theta != 1.0 || C->masked || C->domain || !one_launch_desc(C->desc, L.n) || L.n < 3) return false;
+  const int nc = (L.n - 1) / 2;
+  const LevelArgs<T> a = args(L, C->N, C->desc.strip);
+  bool launched = false;
+  lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
+    constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value;
+    if constexpr (W == 64 && JM <= 4) {
+      sweep_vw_dispatch<T, JM>(halfsweep_vw(decltype(Vc)::value, JM), C->N, [&](auto Vk) {
+        constexpr int VW = decltype(Vk)::value;
+        auto kern = k_rr_gs_walk<T, JM, VW>;
+        static const int resident = resident_waves(reinterpret_cast<const void*>(kern));
+        const int nseg = std::max(1, resident / nc), seg = (nc + nseg - 1) / nseg;
+        const int npg = (nc + kBlock / 64 - 1) / (kBlock / 64);
+        const int nb = npg * ((nc + seg - 1) / seg);
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, C->stream, a, xold, xnew, coarse, seg);
+      });
+      launched = true;
+    }
+  });
+  return launched;
+}
+
 template <typename T>
 int residual_restrict(smg_ctx* C, const Level<T>& L, const T* x, const T* f, T* coarse) {
   const int nc = (L.n - 1) / 2;
@@ -1023,7 +1050,9 @@ int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f, bool x
     // whole sweeps in one launch each (k_sweep_fused), the same iteration
     TRY(sweeps_one_launch<T>(C, L, x, alt, f, C->desc.pre, x_zero ? kZero : kPlain, nullptr));
     Level<T>& Lc = Ls[l + 1];
-    TRY(residual_restrict<T>(C, L, x, f, Lc.f));
+    // two or more sweeps end with one from alt into x: restrict from the blacks' change
+    if (C->desc.pre >= 2 && rr_gs_walk<T>(C, L, alt, x, Lc.f)) LAUNCH_CHECK();
+    else TRY(residual_restrict<T>(C, L, x, f, Lc.f));
     TRY(vcycle_level<T>(C, Ls, r, l + 1, Lc.x, Lc.f, true));
     return sweeps_one_launch<T>(C, L, x, alt, f, C->desc.post, kProlong, Lc.x);
   }
@@ -2076,6 +2105,19 @@ int smg_residual_restrict(smg_ctx* C, int level, const double* x, const double* 
   if (!C || !x || !f || !coarse) return SMG_EINVAL;
   TRY(check_level(C, level, 1));
   return residual_restrict<double>(C, C->L64[level], x, f, coarse);
+}
+
+int smg_residual_restrict_after_sweep(smg_ctx* C, int level, const double* xold, const double* xnew,
+                                      const double* f, double* coarse, int* from_change) {
+  if (!C || !xold || !xnew || !f || !coarse || xold == xnew) return SMG_EINVAL;
+  TRY(check_level(C, level, 1));
+  const bool walk = rr_gs_walk<double>(C, C->L64[level], xold, xnew, coarse);
+  if (from_change) *from_change = walk ? 1 : 0;
+  if (walk) {
+    LAUNCH_CHECK();
+    return SMG_OK;
+  }
+  return residual_restrict<double>(C, C->L64[level], xnew, f, coarse);
 }
 
 int smg_jacobi(smg_ctx* C, int level, const double* x, double* xout, const double* f) {

@@ -7,7 +7,7 @@ import pytest
 
 from paper_2302_13680_amd import inputs
 from paper_2302_13680_amd.inputs import node_to_paper, paper_to_node
-from parity_util import assert_blocks
+from parity_util import assert_blocks, block_rel
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -75,6 +75,64 @@ def test_column_walk_residual_restrict_against_oracle(B, O, n, N):
         ctx.residual_restrict(l, dev(paper_to_node(x, nl, N)), dev(paper_to_node(f, nl, N)), cd)
         ref = O.restrict(nl, N, o.residual(x, f, l))
         assert_blocks(node_to_paper(host(cd), nc, N), ref, nc, N, 1e-14, f"level {l}")
+
+
+@pytest.mark.parametrize("n,N", [(63, 256), (63, 200), (31, 193), (127, 100), (15, 130), (63, 64)])
+def test_restriction_after_sweep_from_the_black_change(B, O, n, N):
+    """Where the column walk applies, the restriction after a sweep x0 -> x1
+    (k_rr_gs_walk: from the blacks' change, f not read) against the oracle's
+    R (f - S x1) on every level, x1 the oracle's own sweep of random x0: Y and P
+    blocks on their own scale; the U block exactly zero on the GPU and at the
+    rounding level in the oracle.  N = 64: one sample per lane; 100, 200, 256:
+    two per access; 130, 193: one at a time with a ragged tail."""
+    p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=5 * n + N)
+    o = O.Oracle(p)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0, sweep_rows=4)
+    rng = np.random.default_rng(n * N)
+    for l in range(o.nlev - 1):
+        nl, nc = o.levels_n[l], o.levels_n[l + 1]
+        x0 = rng.standard_normal(o.vlen(l))
+        f = rng.standard_normal(o.vlen(l))
+        x1 = o.halfsweep(o.halfsweep(x0, f, 0, l), f, 1, l)
+        cd = torch.full((o.vlen(l + 1),), np.nan, dtype=torch.float64, device="cuda")
+        walk = ctx.residual_restrict_after_sweep(l, dev(paper_to_node(x0, nl, N)), dev(paper_to_node(x1, nl, N)),
+                                                 dev(paper_to_node(f, nl, N)), cd)
+        assert walk, l
+        got = node_to_paper(host(cd), nc, N)
+        ref = O.restrict(nl, N, o.residual(x1, f, l))
+        e = block_rel(got, ref, nc, N)
+        print("level", l, e, flush=True)
+        assert e["y"] <= 1e-12 and e["p"] <= 1e-12, (l, e)
+        ncn = nc * nc
+        assert np.all(got[N * ncn:(N + 1) * ncn] == 0.0)
+        assert np.linalg.norm(ref[N * ncn:(N + 1) * ncn]) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_restriction_after_sweep_without_the_walk_reads_f(B, O):
+    """63 x 63, N = 64 without a forced segment length: no column walk, so the
+    entry point forms R (f - S x1) from f (the plain fused pass)."""
+    n, N = 63, 64
+    p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=9)
+    o = O.Oracle(p)
+    ctx, _ = B.context_from_problem(p, gmres_restart=0)
+    rng = np.random.default_rng(9)
+    x0 = rng.standard_normal(o.vlen())
+    f = rng.standard_normal(o.vlen())
+    x1 = o.halfsweep(o.halfsweep(x0, f, 0), f, 1)
+    nc = o.levels_n[1]
+    cd = torch.empty(o.vlen(1), dtype=torch.float64, device="cuda")
+    assert not ctx.residual_restrict_after_sweep(0, dev(paper_to_node(x0, n, N)), dev(paper_to_node(x1, n, N)),
+                                                 dev(paper_to_node(f, n, N)), cd)
+    got, ref = node_to_paper(host(cd), nc, N), o.residual_restrict(x1, f)
+    e = block_rel(got, ref, nc, N)
+    assert e["y"] <= 1e-13 and e["p"] <= 1e-13, e
+    # after a sweep the U rows vanish: both sides leave only rounding there
+    ncn = nc * nc
+    for v in (got, ref):
+        assert np.linalg.norm(v[N * ncn:(N + 1) * ncn]) <= 1e-12 * np.linalg.norm(ref)
+    xa = dev(paper_to_node(x0, n, N))
+    with pytest.raises(B.SmgError):                       # xold and xnew the same vector
+        ctx.residual_restrict_after_sweep(0, xa, xa, dev(paper_to_node(f, n, N)), cd)
 
 
 def test_sweep_refuses_aliasing_and_reports_the_fallback(B):
