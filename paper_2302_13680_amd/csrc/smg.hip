@@ -538,9 +538,10 @@ void sweep_vw_dispatch(int vw, int N, F&& fn) {
 }
 
 // One whole red+black sweep, xin -> xout (must not alias); src: kPlain or
-// kZero (xin taken as zero, not read).
+// kZero (xin taken as zero, not read); all = false: only the blacks' y and p
+// of xout are written (the rest of xout keeps what it held).
 template <typename T>
-int sweep_one_launch(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const T* f, int src) {
+int sweep_one_launch(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const T* f, int src, bool all = true) {
   const LevelArgs<T> a = args(L, C->N, C->desc.strip);
   const SweepPtrs<T> P{xin, xout, f};
   const int npair = (L.n + 1) / 2, npg = (npair + kBlock / 64 - 1) / (kBlock / 64);
@@ -556,8 +557,13 @@ int sweep_one_launch(smg_ctx* C, const Level<T>& L, const T* xin, T* xout, const
           const int nb = npg * ((L.n + rows - 1) / rows);
           hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, C->stream, a, P, rows);
         };
-        if (src == kZero) go(k_sweep_fused<T, JM, VW, kZero>);
-        else go(k_sweep_fused<T, JM, VW, kPlain>);
+        if (src == kZero) {
+          if (all) go(k_sweep_fused<T, JM, VW, kZero, true>);
+          else go(k_sweep_fused<T, JM, VW, kZero, false>);
+        } else {
+          if (all) go(k_sweep_fused<T, JM, VW, kPlain, true>);
+          else go(k_sweep_fused<T, JM, VW, kPlain, false>);
+        }
       });
       launched = true;
     }
@@ -598,10 +604,13 @@ int prolong_black(smg_ctx* C, const Level<T>& L, T* x, const T* ec) {
 // neighbour source src (kProlong: x + P ec): one launch per sweep between x and
 // alt (an even number, ending in x), an odd count starting with one sweep in
 // place by half-sweeps; with kProlong and an even count the correction is added
-// at the black nodes first (the only old values a sweep reads).
+// at the black nodes first (the only old values a sweep reads).  The one-launch
+// sweeps write the blacks' y and p only, except the last one when last_all: the
+// red values and u of a sweep are read by nothing but a consumer of the whole
+// vector.
 template <typename T>
 int sweeps_one_launch(smg_ctx* C, const Level<T>& L, T* x, T* alt, const T* f, int count, int src,
-                      const T* ec) {
+                      const T* ec, bool last_all) {
   int s = 0;
   if (count & 1) {
     TRY(halfsweep<T>(C, L, x, f, 0, src, ec));
@@ -614,8 +623,8 @@ int sweeps_one_launch(smg_ctx* C, const Level<T>& L, T* x, T* alt, const T* f, i
     src = kPlain;
   }
   for (; s < count; s += 2, src = kPlain) {
-    TRY(sweep_one_launch<T>(C, L, x, alt, f, src));
-    TRY(sweep_one_launch<T>(C, L, alt, x, f, kPlain));
+    TRY(sweep_one_launch<T>(C, L, x, alt, f, src, false));
+    TRY(sweep_one_launch<T>(C, L, alt, x, f, kPlain, last_all && s + 2 >= count));
   }
   return SMG_OK;
 }
@@ -1048,13 +1057,23 @@ int vcycle_level(smg_ctx* C, Level<T>* Ls, T* r, int l, T* x, const T* f, bool x
   T* alt = l == 0 ? r : L.xa;
   if (fused && one_launch<T>(C, L, alt) && C->desc.pre > 0 && C->desc.post > 0) {
     // whole sweeps in one launch each (k_sweep_fused), the same iteration
-    TRY(sweeps_one_launch<T>(C, L, x, alt, f, C->desc.pre, x_zero ? kZero : kPlain, nullptr));
+    // two or more pre-smoothing sweeps end with one from alt into x and the
+    // residual is restricted from the blacks' change, which reads no red value
+    // and no u: then no pre-smoothing sweep writes them
+    const bool gs_rr = C->desc.pre >= 2;
+    TRY(sweeps_one_launch<T>(C, L, x, alt, f, C->desc.pre, x_zero ? kZero : kPlain, nullptr, !gs_rr));
     Level<T>& Lc = Ls[l + 1];
-    // two or more sweeps end with one from alt into x: restrict from the blacks' change
-    if (C->desc.pre >= 2 && rr_gs_walk<T>(C, L, alt, x, Lc.f)) LAUNCH_CHECK();
-    else TRY(residual_restrict<T>(C, L, x, f, Lc.f));
+    if (gs_rr) {
+      if (!rr_gs_walk<T>(C, L, alt, x, Lc.f)) {
+        C->err = "restriction after a sweep: layout without 64 lanes per node";
+        return SMG_EINVAL;
+      }
+      LAUNCH_CHECK();
+    } else {
+      TRY(residual_restrict<T>(C, L, x, f, Lc.f));
+    }
     TRY(vcycle_level<T>(C, Ls, r, l + 1, Lc.x, Lc.f, true));
-    return sweeps_one_launch<T>(C, L, x, alt, f, C->desc.post, kProlong, Lc.x);
+    return sweeps_one_launch<T>(C, L, x, alt, f, C->desc.post, kProlong, Lc.x, true);
   }
   int s0 = 0;
   if (x_zero) {

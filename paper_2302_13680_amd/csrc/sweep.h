@@ -210,8 +210,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong_black(int n, int N, const T*
 // Pair-walking waves: kBlock / 64 consecutive pairs of one row segment per
 // workgroup; blocks remapped so that each XCD takes contiguous segments.  Every
 // load of a step is issued before its arithmetic (one memory round trip per
-// step); c_j, d_j, e_j sit in LDS.
-template <typename T, int JM, int VW, int SRC>
+// step); c_j, d_j, e_j sit in LDS.  ALL = false writes the blacks' y and p only:
+// no solve reads a red value, a u or a node's own old value, so only the last
+// sweep before a consumer of the whole vector needs to store them (the others
+// feed the next sweep, the restriction from the blacks' change and the black
+// prolongation): 7 words per node-sample instead of 8.
+template <typename T, int JM, int VW, int SRC, bool ALL = true>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void k_sweep_fused(LevelArgs<T> L, SweepPtrs<T> P, int seg_rows) {
   constexpr int kWaves = kBlock / 64;
@@ -323,7 +327,9 @@ void k_sweep_fused(LevelArgs<T> L, SweepPtrs<T> P, int seg_rows) {
 #pragma unroll
       for (int q = 0; q < JM; ++q) H0.y[q] = H0.p[q] = T(0);
     }
-    if (red_ok && s >= r0 && s < r1) st_ypu<T, JM, VW>(P.xout, nn, N, (size_t)s * n + xr, lane, R0, uR);
+    if constexpr (ALL) {
+      if (red_ok && s >= r0 && s < r1) st_ypu<T, JM, VW>(P.xout, nn, N, (size_t)s * n + xr, lane, R0, uR);
+    }
     // ---- 3. own black (xr, s-1): W/E = pair partner (R1) and halo (H1) of step
     //         s-1, S = own red of step s-2 (R2), N = own red of step s (R0)
     if (blk) {
@@ -339,7 +345,13 @@ void k_sweep_fused(LevelArgs<T> L, SweepPtrs<T> P, int seg_rows) {
       NodeYP<T, JM> Bv;
       T uB;
       finish_node<T, JM>(pb, group_sum<64>(pb.num), fub, gdb, Bv, uB);
-      st_ypu<T, JM, VW>(P.xout, nn, N, (size_t)(s - 1) * n + xr, lane, Bv, uB);
+      if constexpr (ALL) {
+        st_ypu<T, JM, VW>(P.xout, nn, N, (size_t)(s - 1) * n + xr, lane, Bv, uB);
+      } else {
+        const size_t node = (size_t)(s - 1) * n + xr;
+        stn<T, JM, VW>(P.xout + node * N, N, lane, Bv.y);
+        stn<T, JM, VW>(P.xout + (size_t)(N + 1) * nn + node * N, N, lane, Bv.p);
+      }
     }
     // ---- shift the carried values to step s+1
     R2 = R1; R1 = R0; H1 = H0;
