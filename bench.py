@@ -696,7 +696,8 @@ def roofline_sweep(ctx, f, n, N, dev, launches, traffic_kind):
     if one:
         us = time_sweep(ctx, xa, xb, f, ctx.stream, launches)
         algo = sweep_bytes(n, N, 8)
-        kernel = f"k_sweep_fused<double,4,{2 if N % 2 == 0 else 1},kPlain> finest level (red+black sweep)"
+        kernel = (f"k_sweep_fused<double,4,{2 if N % 2 == 0 else 1},kPlain,all> finest level "
+                  "(red+black sweep, every field written)")
     else:
         us = time_halfsweep(ctx, xa, f, ctx.stream, launches)
         algo, kernel = sweep_bytes(n, N, 8) / 2, "k_halfsweep<double,64,4> finest level"
