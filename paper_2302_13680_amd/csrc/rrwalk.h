@@ -473,3 +473,142 @@ void k_residual_add_walk(LevelArgs<double> L, const double* __restrict__ x, cons
 }
 
 }  // namespace smg
+
+namespace smg {
+
+// The residual or operator application of residual_node (residual.h), out =
+// f - S x (mode 0) or S x (mode 1) with the same arithmetic per node, in column
+// walks: the per-node form reads x of all four neighbours of every node (about
+// five times each overall); here a wavefront owns one column c over a segment of
+// rows and walks it upwards, keeping x of rows r-1 and r and the S face of row r
+// in registers, so a step loads x of (c, r+1) and of the two side neighbours
+// (shared with the neighbouring columns' waves, from L2), the row's faces and
+// right-hand sides once.  FP64 faces, x and f in TX, out in TO (may be null);
+// per-block squared norms {r_Y, r_U, r_P, f} into partials when given (every
+// wave of a block takes part in the final block sum).  No node factors, no
+// domain; 64 lanes per node.
+template <typename TX, typename TO, int JM, int VW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_residual_walk(LevelArgs<double> L, const TX* __restrict__ x, const TX* __restrict__ f, TO* __restrict__ out,
+                     int mode, double* __restrict__ partials, int seg) {
+  constexpr int kWaves = kBlock / 64;
+  const int n = L.n, N = L.N;
+  __shared__ double cde[3 * 64 * JM];
+  for (int j = threadIdx.x; j < N; j += kBlock) {
+    cde[j] = L.c[j];
+    cde[N + j] = L.d[j];
+    cde[2 * N + j] = L.e[j];
+  }
+  __syncthreads();
+  const size_t nn = (size_t)n * n;
+  const size_t oU = (size_t)N * nn, oP = (size_t)(N + 1) * nn;
+  const int npg = (n + kWaves - 1) / kWaves, nseg = (n + seg - 1) / seg;
+  const int t = xcd_remap(blockIdx.x, npg * nseg);
+  const int g = t / npg, pg = t - g * npg;
+  const int c = __builtin_amdgcn_readfirstlane(pg * kWaves + (int)threadIdx.x / 64);
+  const int lane = threadIdx.x & 63;
+  const int r0 = g * seg, r1 = min(n, r0 + seg);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (c < n && r0 < r1) {
+    auto cl = [&](int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); };
+    auto nd = [&](int col, int row) { return (size_t)cl(row, n - 1) * n + cl(col, n - 1); };
+    // both fields of node k, VW samples per access, widened to FP64
+    auto ldx = [&](size_t k, NodeYP<double, JM>& o) {
+#pragma unroll
+      for (int ch = 0; ch < JM / VW; ++ch) {
+        const int j0 = VW * (lane + ch * 64);
+        const int j = j0 < N ? j0 : N - VW;
+        TX yv[VW], pv[VW];
+        ldv<VW>(x + k * N + j, yv);
+        ldv<VW>(x + oP + k * N + j, pv);
+#pragma unroll
+        for (int u = 0; u < VW; ++u) {
+          o.y[ch * VW + u] = (double)yv[u];
+          o.p[ch * VW + u] = (double)pv[u];
+        }
+      }
+    };
+    const bool hw = c > 0, he = c < n - 1;
+    NodeYP<double, JM> xp, xc;
+    double ks[JM];
+    ldx(nd(c, r0 - 1), xp);
+    ldx(nd(c, r0), xc);
+    ldn<double, JM, VW>(L.ky + ((size_t)r0 * n + c) * N, N, lane, ks);
+    for (int r = r0; r < r1; ++r) {
+      const bool hs = r > 0, hn = r < n - 1;
+      const size_t node = (size_t)r * n + c;
+      NodeYP<double, JM> xq, xw, xe;
+      double kw[JM], ke[JM], kn[JM];
+      TX fy[JM], fp[JM];
+      ldx(nd(c, r + 1), xq);
+      ldx(nd(c - 1, r), xw);
+      ldx(nd(c + 1, r), xe);
+      ldn<double, JM, VW>(L.kx + ((size_t)r * (n + 1) + c) * N, N, lane, kw);
+      ldn<double, JM, VW>(L.kx + ((size_t)r * (n + 1) + c + 1) * N, N, lane, ke);
+      ldn<double, JM, VW>(L.ky + ((size_t)(r + 1) * n + c) * N, N, lane, kn);
+      if (mode == 0) {
+        ldn<TX, JM, VW>(f + node * N, N, lane, fy);
+        ldn<TX, JM, VW>(f + oP + node * N, N, lane, fp);
+      }
+      const double u = (double)x[oU + node];
+      double dsum = 0.0;
+      TO ry[JM], rp[JM];
+#pragma unroll
+      for (int q = 0; q < JM; ++q) {
+        const int j = VW * (lane + (q / VW) * 64) + q % VW;
+        const bool act = j < N;
+        const int jj = act ? j : N - 1;
+        auto nbsum = [&](double vw, double ve, double vs, double vn) {
+          return ((hw ? kw[q] * vw : 0.0) + (he ? ke[q] * ve : 0.0)) + ((hs ? ks[q] * vs : 0.0) + (hn ? kn[q] * vn : 0.0));
+        };
+        const double sy = nbsum(xw.y[q], xe.y[q], xp.y[q], xq.y[q]);
+        const double sp = nbsum(xw.p[q], xe.p[q], xp.p[q], xq.p[q]);
+        const double a = (kw[q] + ke[q]) + (ks[q] + kn[q]);
+        double rY = cde[jj] * xc.y[q] + (a * xc.p[q] - sp);
+        double rP = (a * xc.y[q] - sy) + cde[2 * N + jj] * u;
+        dsum += act ? cde[N + jj] * xc.p[q] : 0.0;
+        double ff = 0.0;
+        if (mode == 0) {
+          const double fyq = (double)fy[q], fpq = (double)fp[q];
+          rY = fyq - rY;
+          rP = fpq - rP;
+          ff = fyq * fyq + fpq * fpq;
+        }
+        ry[q] = (TO)rY;
+        rp[q] = (TO)rP;
+        if (act) {
+          acc[0] += rY * rY;
+          acc[2] += rP * rP;
+          acc[3] += ff;
+        }
+      }
+      if (out) {
+        stn<TO, JM, VW>(out + node * N, N, lane, ry);
+        stn<TO, JM, VW>(out + oP + node * N, N, lane, rp);
+      }
+      const double D = group_sum<64>(dsum);
+      if (lane == 0) {
+        double rU = L.g * u + D;
+        if (mode == 0) {
+          const double fu = (double)f[oU + node];
+          rU = fu - rU;
+          acc[3] += fu * fu;
+        }
+        if (out) out[oU + node] = (TO)rU;
+        acc[1] += rU * rU;
+      }
+      xp = xc;
+      xc = xq;
+      cpy(ks, kn);
+    }
+  }
+  if (partials) {
+    block_sum<4>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) partials[4 * (size_t)blockIdx.x + i] = acc[i];
+    }
+  }
+}
+
+}  // namespace smg

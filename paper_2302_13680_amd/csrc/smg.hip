@@ -767,11 +767,28 @@ template <typename T, typename TX, typename TO>
 int residual_into(smg_ctx* C, const Level<T>& L, const TX* x, const TX* f, TO* out, int mode, double* partials,
                   double* partials2, double* norms) {
   const size_t nn = (size_t)L.n * L.n;
+  // column walks (k_residual_walk) on an FP64-face level that streams from HBM
+  const bool walk = std::is_same<T, double>::value && !C->masked && !C->domain && one_launch_desc(C->desc, L.n);
   lane_dispatch<std::is_same<T, float>::value>(C->desc.precision, C->N, [&](auto Wc, auto Jc, auto Vc) {
     constexpr int W = decltype(Wc)::value, JM = decltype(Jc)::value, VW = decltype(Vc)::value;
     const int per = kBlock / W;
-    const int nb = (int)((nn + per - 1) / per);
-    mask_dispatch(C->masked, [&](auto Mc) {
+    int nb = (int)((nn + per - 1) / per);
+    bool walked = false;
+    if constexpr (std::is_same<T, double>::value && W == 64 && JM <= 4) {
+      if (walk) {
+        auto go = [&](auto kern) {
+          static const int resident = resident_waves(reinterpret_cast<const void*>(kern));
+          const int nseg = std::max(1, resident / L.n), seg = (L.n + nseg - 1) / nseg;
+          nb = ((L.n + kBlock / 64 - 1) / (kBlock / 64)) * ((L.n + seg - 1) / seg);
+          hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, C->stream, args(L, C->N, C->desc.strip), x, f, out,
+                             mode, partials, seg);
+        };
+        if (JM % 2 == 0 && C->N % 2 == 0) go(k_residual_walk<TX, TO, JM, (JM % 2 == 0 ? 2 : 1)>);
+        else go(k_residual_walk<TX, TO, JM, 1>);
+        walked = true;
+      }
+    }
+    if (!walked) mask_dispatch(C->masked, [&](auto Mc) {
       // FP64 faces with an even N of 65..512: two samples per lane and access
       // (16-byte FP64, 8-byte FP32 iterates)
       if constexpr (std::is_same<T, double>::value && W == 64 && VW == 1 && JM >= 2 && JM <= 8) {

@@ -135,6 +135,53 @@ def test_restriction_after_sweep_without_the_walk_reads_f(B, O):
         ctx.residual_restrict_after_sweep(0, xa, xa, dev(paper_to_node(f, n, N)), cd)
 
 
+@pytest.mark.parametrize("n,N", [(63, 256), (63, 200), (31, 193), (127, 100), (63, 64), (15, 130)])
+def test_column_walk_residual_and_apply_equal_the_per_node_form(B, O, n, N):
+    """On one-launch levels the finest residual and operator application run in
+    column walks (k_residual_walk): with the per-node arithmetic, so the vectors
+    equal those of the per-node kernel bit for bit (a context without forced
+    segments at these sizes), the block norms to the summation order, and the
+    oracle's residual per block.  Even, odd and ragged N."""
+    p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=7 * n + N)
+    o = O.Oracle(p)
+    cw, _ = B.context_from_problem(p, gmres_restart=0, sweep_rows=4)
+    cn, _ = B.context_from_problem(p, gmres_restart=0)
+    rng = np.random.default_rng(3 * n + N)
+    x = rng.standard_normal(o.vlen())
+    f = rng.standard_normal(o.vlen())
+    xd, fd = dev(paper_to_node(x, n, N)), dev(paper_to_node(f, n, N))
+    a1, a2 = torch.empty_like(xd), torch.empty_like(xd)
+    cw.apply(xd, a1)
+    cn.apply(xd, a2)
+    assert torch.equal(a1, a2)
+    r1, r2 = torch.empty_like(xd), torch.empty_like(xd)
+    h1 = cw.residual(xd, fd, r1, norms=True)
+    h2 = cn.residual(xd, fd, r2, norms=True)
+    assert torch.equal(r1, r2)
+    np.testing.assert_allclose(h1, h2, rtol=1e-13)
+    assert_blocks(node_to_paper(host(r1), n, N), o.residual(x, f), n, N, 1e-14, "oracle residual")
+    assert_blocks(node_to_paper(host(a1), n, N), o.apply(x), n, N, 1e-14, "oracle apply")
+
+
+@pytest.mark.parametrize("N", [200, 193])
+def test_fp32_fgmres_with_column_walks(B, O, N):
+    """FGMRES(30) around FP32 cycles where the operator application on FP32
+    preconditioned vectors runs in column walks (forced by a segment length):
+    the solution meets 1e-10 in the oracle's FP64 residual, with the oracle's
+    refinement count within one."""
+    p = inputs.make_problem(127, N, 1e-4, M=6, sigma=0.5, decay=True, seed=6)
+    o = O.Oracle(p)
+    ctx, f = B.context_from_problem(p, gmres_restart=30, precision=B.SMG_F32, sweep_rows=8)
+    x = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    rc, st = ctx.solve(x, f, B.SMG_GMRES, rtol=1e-10, maxit=60)
+    assert rc == B.SMG_OK, st
+    fp = p.rhs_paper()
+    r = o.residual(node_to_paper(host(x), p.n, p.N), fp)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(fp)
+    _, its, _, _ = o.solve_ir(fp, tol=1e-10, m=30)
+    assert abs(st["iterations"] - its) <= 1, (st["iterations"], its)
+
+
 def test_sweep_refuses_aliasing_and_reports_the_fallback(B):
     p = inputs.make_problem(63, 64, 1e-4, M=6, sigma=0.5, decay=True, seed=3)
     ctx, f = B.context_from_problem(p, gmres_restart=0)
