@@ -123,9 +123,15 @@ typedef struct {
                                  red+black sweep is one launch out of place between the level
                                  iterate and a second buffer, reading every face coefficient
                                  once, the coarse correction ahead of post-smoothing is a pass
-                                 over the black nodes only, and the residual is restricted in
-                                 column walks; both compute the same iteration (the same
-                                 arithmetic per node, up to the order of the restriction's sums) */
+                                 over the black nodes only, the residual after two or more
+                                 pre-smoothing sweeps is restricted from the black nodes' change
+                                 in the last one (see smg_residual_restrict_after_sweep), every
+                                 sweep but the last post-smoothing one stores the black nodes'
+                                 y and p only (no later step reads the rest), and the finest
+                                 residual and operator application run in column walks; both
+                                 compute the same iteration (the same arithmetic per node, up to
+                                 the order of the restriction's sums and the rounding of the
+                                 node solves in the restricted residual) */
 
 typedef struct {
   const double *kx;   /* device, [n][n+1][N] */
