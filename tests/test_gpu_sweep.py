@@ -77,14 +77,15 @@ def test_column_walk_residual_restrict_against_oracle(B, O, n, N):
         assert_blocks(node_to_paper(host(cd), nc, N), ref, nc, N, 1e-14, f"level {l}")
 
 
-@pytest.mark.parametrize("n,N", [(63, 256), (63, 200), (31, 193), (127, 100), (15, 130), (63, 64)])
+@pytest.mark.parametrize("n,N", [(63, 256), (63, 200), (31, 193), (127, 100), (15, 130), (63, 64), (31, 65),
+                                 (15, 255), (31, 129)])
 def test_restriction_after_sweep_from_the_black_change(B, O, n, N):
     """Where the column walk applies, the restriction after a sweep x0 -> x1
     (k_rr_gs_walk: from the blacks' change, f not read) against the oracle's
     R (f - S x1) on every level, x1 the oracle's own sweep of random x0: Y and P
     blocks on their own scale; the U block exactly zero on the GPU and at the
     rounding level in the oracle.  N = 64: one sample per lane; 100, 200, 256:
-    two per access; 130, 193: one at a time with a ragged tail."""
+    two per access; 65, 129, 130, 193, 255: one at a time with a ragged tail."""
     p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=5 * n + N)
     o = O.Oracle(p)
     ctx, _ = B.context_from_problem(p, gmres_restart=0, sweep_rows=4)
@@ -135,7 +136,8 @@ def test_restriction_after_sweep_without_the_walk_reads_f(B, O):
         ctx.residual_restrict_after_sweep(0, xa, xa, dev(paper_to_node(f, n, N)), cd)
 
 
-@pytest.mark.parametrize("n,N", [(63, 256), (63, 200), (31, 193), (127, 100), (63, 64), (15, 130)])
+@pytest.mark.parametrize("n,N", [(63, 256), (63, 200), (31, 193), (127, 100), (63, 64), (15, 130), (31, 65),
+                                 (15, 255), (31, 129)])
 def test_column_walk_residual_and_apply_equal_the_per_node_form(B, O, n, N):
     """On one-launch levels the finest residual and operator application run in
     column walks (k_residual_walk): with the per-node arithmetic, so the vectors
