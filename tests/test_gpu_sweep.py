@@ -245,6 +245,31 @@ def test_vcycles_with_and_without_one_launch_sweeps(B, O, precision, n, N):
         print("cycle", k, "one-launch vs half-sweeps", e1, "vs oracle", e2, flush=True)
 
 
+@pytest.mark.parametrize("pre,post", [(1, 1), (3, 3), (1, 2), (3, 1), (2, 3)])
+def test_vcycles_with_odd_smoothing_counts(B, O, pre, post):
+    """Odd numbers of sweeps on one-launch levels: the first sweep then runs as two
+    half-sweeps in place and the rest in one-launch pairs (blacks-only stores but
+    for the cycle's last sweep, the restriction from the blacks' change only after
+    two or more pre-smoothing sweeps); iterates against the half-sweep cycle and
+    the oracle with the same counts, every cycle, per block."""
+    n, N = 127, 200
+    p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=31)
+    o = O.Oracle(p, pre=pre, post=post)
+    fp = p.rhs_paper()
+    c1, f = B.context_from_problem(p, gmres_restart=0, pre=pre, post=post, sweep_rows=16)
+    c2, _ = B.context_from_problem(p, gmres_restart=0, pre=pre, post=post, flags=B.SMG_FLAG_HALFSWEEPS)
+    x1 = torch.zeros(p.dof, dtype=torch.float64, device="cuda")
+    x2 = torch.zeros_like(x1)
+    xo = np.zeros(o.vlen())
+    for k in range(2):
+        c1.vcycle(x1, f, 1)
+        c2.vcycle(x2, f, 1)
+        xo = o.vcycle(xo, fp, 1)
+        g1 = node_to_paper(host(x1), n, N)
+        assert_blocks(g1, node_to_paper(host(x2), n, N), n, N, 1e-13, ("half-sweeps", k))
+        assert_blocks(g1, xo, n, N, 1e-12, ("oracle", k))
+
+
 @pytest.mark.parametrize("N", [256, 128])
 def test_large_level_takes_the_one_launch_sweep_by_default(B, N):
     """511x511, N = 256 or 128 (levels that stream from HBM; four or two samples
