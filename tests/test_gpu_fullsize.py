@@ -54,6 +54,23 @@ def test_large_vcycle_iterates_against_oracle(B, problem):
         assert_blocks(node_to_paper(xd.cpu().numpy(), p.n, p.N), x_o, p.n, p.N, 1e-12)
 
 
+def test_large_fp32_vcycle_iterate_against_oracle(B, problem):
+    """One FP32 V-cycle from zero at full size (one-launch sweeps with blacks-only
+    stores, the restriction from the blacks' change, half-sweeps below) against the
+    oracle's FP32 cycle, per block: two FP32 evaluations in different orders agree
+    to FP32 rounding (measured 2-5e-7 per block; the bound leaves room for the P
+    block's cancellation, which can amplify it towards 1e-5)."""
+    p, o = problem
+    ctx, f = B.context_from_problem(p, gmres_restart=0, precision=B.SMG_F32)
+    fp = p.rhs_paper()
+    xd = torch.zeros(o.vlen(), dtype=torch.float64, device="cuda")
+    ctx.vcycle(xd, f, 1)
+    torch.cuda.synchronize()
+    x_o = o.vcycle32(np.zeros(o.vlen()), fp, 1)
+    e = assert_blocks(node_to_paper(xd.cpu().numpy(), p.n, p.N), x_o, p.n, p.N, 1e-5)
+    print("511x511 FP32 cycle vs the FP32 oracle:", e, flush=True)
+
+
 def test_large_fp32_refinement_meets_oracle_residual(B, problem):
     p, o = problem
     ctx, f = B.context_from_problem(p, gmres_restart=0, precision=B.SMG_F32)
