@@ -201,7 +201,10 @@ class Oracle:
 
     def __del__(self):
         if getattr(self, "ctx", None):
-            _load().or_destroy(self.ctx)
+            try:
+                _load().or_destroy(self.ctx)
+            except TypeError:   # interpreter shutdown: the module's globals are gone
+                pass
             self.ctx = None
 
     def vlen(self, l: int = 0) -> int:
