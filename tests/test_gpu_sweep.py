@@ -184,6 +184,32 @@ def test_fp32_fgmres_with_column_walks(B, O, N):
     assert abs(st["iterations"] - its) <= 1, (st["iterations"], its)
 
 
+@pytest.mark.parametrize("case", ["local control", "theta 1/2"])
+def test_restriction_after_sweep_falls_back_where_the_identity_is_not_used(B, O, case):
+    """With node factors (control on a subregion) or theta != 1 the entry point
+    forms R (f - S xnew) from f (the black-change form needs plain Gauss-Seidel
+    rows without factors): it reports so, even with forced segments, and matches
+    the oracle's fused residual + restriction for any xnew."""
+    n, N = 63, 200
+    if case == "local control":
+        p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=41,
+                                control_region=(0.25, 0.75, 0.25, 0.75))
+        ctx, _ = B.context_from_problem(p, gmres_restart=0, sweep_rows=8)
+    else:
+        p = inputs.make_problem(n, N, 1e-4, M=6, sigma=0.5, decay=True, seed=42)
+        ctx, _ = B.context_from_problem(p, gmres_restart=0, sweep_rows=8, theta=0.5)
+    o = O.Oracle(p)
+    rng = np.random.default_rng(43)
+    x0 = rng.standard_normal(o.vlen())
+    x1 = rng.standard_normal(o.vlen())
+    f = rng.standard_normal(o.vlen())
+    nc = o.levels_n[1]
+    cd = torch.empty(o.vlen(1), dtype=torch.float64, device="cuda")
+    assert not ctx.residual_restrict_after_sweep(0, dev(paper_to_node(x0, n, N)), dev(paper_to_node(x1, n, N)),
+                                                 dev(paper_to_node(f, n, N)), cd)
+    assert_blocks(node_to_paper(host(cd), nc, N), o.residual_restrict(x1, f), nc, N, 1e-13, case)
+
+
 def test_sweep_refuses_aliasing_and_reports_the_fallback(B):
     p = inputs.make_problem(63, 64, 1e-4, M=6, sigma=0.5, decay=True, seed=3)
     ctx, f = B.context_from_problem(p, gmres_restart=0)
